@@ -1,0 +1,630 @@
+/*
+ * Plain serial FP64 reference ("oracle") of the parallel VC-SGC transmutation
+ * Monte Carlo and EAM molecular dynamics of Sadigh et al. (arXiv:1012.5082).
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the product path.  It shares no
+ * code with the HIP library.  Compiled with -O2 -ffp-contract=off so that every
+ * expression below is evaluated exactly as written (no fused multiply-add).
+ *
+ * Every floating-point expression is written in the order stated in its
+ * comment; the reading of the paper that each step follows is cited there.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_KB 8.617333262e-5      /* Boltzmann constant, eV/K */
+#define OR_ACC 9.648533212e-3     /* (eV/Angstrom)/u -> Angstrom/fs^2 */
+#define OR_TIE 1e-9               /* near-tie margin |ln u + x| */
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10: ten rounds of two 64x64->128 multiplies and a Feistel-like  */
+/* mix; the key is bumped by the Weyl constants between rounds.              */
+/* ------------------------------------------------------------------------ */
+static const uint64_t PH_M0 = 0xD2E7470EE14C6C93ULL;
+static const uint64_t PH_M1 = 0xCA5A826395121157ULL;
+static const uint64_t PH_W0 = 0x9E3779B97F4A7C15ULL;
+static const uint64_t PH_W1 = 0xBB67AE8584CAA73BULL;
+
+void or_philox4x64_10(const uint64_t key[2], const uint64_t ctr[4], uint64_t out[4]) {
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += PH_W0;
+      k1 += PH_W1;
+    }
+    unsigned __int128 p0 = (unsigned __int128)PH_M0 * c0;
+    unsigned __int128 p1 = (unsigned __int128)PH_M1 * c2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* floor(w * m / 2^64): a uniform index in [0, m) from a 64-bit word. */
+static uint64_t or_index(uint64_t w, uint64_t m) {
+  return (uint64_t)(((unsigned __int128)w * m) >> 64);
+}
+
+/* (w >> 11 + 1/2) 2^-53: a uniform double strictly inside (0, 1). */
+static double or_unit(uint64_t w) {
+  return ((double)(w >> 11) + 0.5) * 0x1p-53;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour lists                                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t j, code;
+  double r, dx, dy, dz;
+} nent;
+
+static int cmp_nent(const void *a, const void *b) {
+  const nent *u = (const nent *)a, *v = (const nent *)b;
+  if (u->j != v->j) return u->j < v->j ? -1 : 1;
+  if (u->code != v->code) return u->code < v->code ? -1 : 1;
+  return 0;
+}
+
+/* Minimum-image separation along one periodic axis. */
+static double or_mimage(double d, double L) {
+  double h = 0.5 * L;
+  if (d > h) return d - L;
+  if (d < -h) return d + L;
+  return d;
+}
+
+typedef struct {
+  nent *e;
+  int64_t n, cap;
+} nbuf;
+
+static void nbuf_push(nbuf *b, nent v) {
+  if (b->n == b->cap) {
+    b->cap = b->cap ? 2 * b->cap : 64;
+    b->e = (nent *)realloc(b->e, (size_t)b->cap * sizeof(nent));
+  }
+  b->e[b->n++] = v;
+}
+
+/* Separation r = sqrt((dx^2 + dy^2) + dz^2); a pair is a neighbour iff r < cutoff. */
+static int or_try_pair(nbuf *row, int32_t j, int32_t code, double dx, double dy, double dz,
+                       double cutoff) {
+  double r = sqrt((dx * dx + dy * dy) + dz * dz);
+  if (r < cutoff) {
+    nent v = {j, code, r, dx, dy, dz};
+    nbuf_push(row, v);
+    return 1;
+  }
+  return 0;
+}
+
+int64_t or_neighbors(int64_t n, const double *x, const double *y, const double *z,
+                     const double box[3], double cutoff, int mode, int64_t cap,
+                     int64_t *start, int32_t *nj, double *nr,
+                     double *ndx, double *ndy, double *ndz) {
+  double Lmin = box[0];
+  if (box[1] < Lmin) Lmin = box[1];
+  if (box[2] < Lmin) Lmin = box[2];
+  if (!(Lmin > cutoff)) return -1;
+  if (mode == 0) mode = (Lmin >= 3.0 * cutoff) ? 3 : (Lmin >= 2.0 * cutoff ? 1 : 2);
+  if (mode == 1 && !(Lmin >= 2.0 * cutoff)) return -1;
+  if (mode == 3 && !(Lmin >= 3.0 * cutoff)) return -1;
+
+  /* mode 3: candidates from the 27 surrounding bins of edge >= cutoff */
+  int nb[3] = {1, 1, 1};
+  int32_t *bin_start = NULL, *bin_atoms = NULL, *bin_of = NULL;
+  if (mode == 3) {
+    for (int d = 0; d < 3; ++d) nb[d] = (int)(box[d] / cutoff);
+    int64_t nbins = (int64_t)nb[0] * nb[1] * nb[2];
+    bin_start = (int32_t *)calloc((size_t)nbins + 1, sizeof(int32_t));
+    bin_atoms = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    bin_of = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) {
+      const double *u[3] = {x, y, z};
+      int b[3];
+      for (int d = 0; d < 3; ++d) {
+        b[d] = (int)(u[d][i] / (box[d] / nb[d]));
+        if (b[d] < 0) b[d] = 0;
+        if (b[d] >= nb[d]) b[d] = nb[d] - 1;
+      }
+      bin_of[i] = b[0] + nb[0] * (b[1] + nb[1] * b[2]);
+      bin_start[bin_of[i] + 1]++;
+    }
+    for (int64_t c = 0; c < nbins; ++c) bin_start[c + 1] += bin_start[c];
+    int32_t *fill = (int32_t *)malloc((size_t)nbins * sizeof(int32_t));
+    memcpy(fill, bin_start, (size_t)nbins * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) bin_atoms[fill[bin_of[i]]++] = (int32_t)i;
+    free(fill);
+  }
+
+  nbuf row = {0, 0, 0};
+  int64_t total = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    row.n = 0;
+    if (mode == 1) {
+      for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        or_try_pair(&row, (int32_t)j, 13, or_mimage(x[j] - x[i], box[0]),
+                    or_mimage(y[j] - y[i], box[1]), or_mimage(z[j] - z[i], box[2]), cutoff);
+      }
+    } else if (mode == 2) {
+      for (int64_t j = 0; j < n; ++j) {
+        for (int sz = -1; sz <= 1; ++sz)
+          for (int sy = -1; sy <= 1; ++sy)
+            for (int sx = -1; sx <= 1; ++sx) {
+              if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
+              int code = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
+              or_try_pair(&row, (int32_t)j, code, (x[j] - x[i]) + sx * box[0],
+                          (y[j] - y[i]) + sy * box[1], (z[j] - z[i]) + sz * box[2], cutoff);
+            }
+      }
+    } else {
+      int b = bin_of[i];
+      int bx = b % nb[0], by = (b / nb[0]) % nb[1], bz = b / (nb[0] * nb[1]);
+      for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+          for (int ox = -1; ox <= 1; ++ox) {
+            int cx = (bx + ox + nb[0]) % nb[0];
+            int cy = (by + oy + nb[1]) % nb[1];
+            int cz = (bz + oz + nb[2]) % nb[2];
+            int c = cx + nb[0] * (cy + nb[1] * cz);
+            for (int32_t k = bin_start[c]; k < bin_start[c + 1]; ++k) {
+              int32_t j = bin_atoms[k];
+              if (j == i) continue;
+              or_try_pair(&row, j, 13, or_mimage(x[j] - x[i], box[0]),
+                          or_mimage(y[j] - y[i], box[1]), or_mimage(z[j] - z[i], box[2]),
+                          cutoff);
+            }
+          }
+    }
+    qsort(row.e, (size_t)row.n, sizeof(nent), cmp_nent);
+    if (start) start[i] = total;
+    for (int64_t k = 0; k < row.n; ++k, ++total) {
+      if (total < cap) {
+        nj[total] = row.e[k].j;
+        nr[total] = row.e[k].r;
+        if (ndx) ndx[total] = row.e[k].dx;
+        if (ndy) ndy[total] = row.e[k].dy;
+        if (ndz) ndz[total] = row.e[k].dz;
+      }
+    }
+  }
+  if (start) start[n] = total;
+  free(row.e);
+  free(bin_start);
+  free(bin_atoms);
+  free(bin_of);
+  return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Potential (Finnis-Sinclair form; species 0 = A, 1 = B)                    */
+/* ------------------------------------------------------------------------ */
+static double or_eps(const or_pot *p, int a, int b) {
+  int s = a + b;
+  return s == 0 ? p->eps_aa : (s == 1 ? p->eps_ab : p->eps_bb);
+}
+
+/* phi_XY(r) = (eps_XY (rc - r)^2) (c0 + c1 r) */
+static double or_phi(const or_pot *p, int a, int b, double r) {
+  double d = p->rc - r;
+  return or_eps(p, a, b) * (d * d) * (p->c0 + p->c1 * r);
+}
+
+/* phi'_XY(r) = eps_XY ((-2 (rc - r)) (c0 + c1 r) + c1 (rc - r)^2) */
+static double or_dphi(const or_pot *p, int a, int b, double r) {
+  double d = p->rc - r;
+  return or_eps(p, a, b) * (-2.0 * d * (p->c0 + p->c1 * r) + p->c1 * (d * d));
+}
+
+/* f_X(r) = t_X (rc - r)^2 */
+static double or_f(const or_pot *p, int a, double r) {
+  double d = p->rc - r;
+  return (a ? p->t_b : p->t_a) * (d * d);
+}
+
+/* f'_X(r) = (-2 t_X) (rc - r) */
+static double or_df(const or_pot *p, int a, double r) {
+  double d = p->rc - r;
+  return -2.0 * (a ? p->t_b : p->t_a) * d;
+}
+
+/* F_X(rho) = -A_X sqrt(max(rho, 0)) */
+static double or_embed(const or_pot *p, int a, double rho) {
+  double A = a ? p->a_b : p->a_a;
+  return -A * sqrt(rho > 0.0 ? rho : 0.0);
+}
+
+/* F'_X(rho) = -A_X / (2 sqrt(rho)), and 0 at rho = 0 */
+static double or_dembed(const or_pot *p, int a, double rho) {
+  double A = a ? p->a_b : p->a_a;
+  return rho > 0.0 ? -A / (2.0 * sqrt(rho)) : 0.0;
+}
+
+/* rho_i = sum_j f_{s_j}(r_ij), in neighbour order. */
+void or_density(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
+                const uint8_t *species, const or_pot *p, double *rho) {
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t e = start[i]; e < start[i + 1]; ++e)
+      if (nr[e] < p->rc) s += or_f(p, species[nj[e]], nr[e]);
+    rho[i] = s;
+  }
+}
+
+/* E_i = F_{s_i}(rho_i) + (1/2) sum_j phi_{s_i s_j}(r_ij); U = sum_i E_i. */
+void or_energy_atoms(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
+                     const uint8_t *species, const or_pot *p, const double *rho, double *e) {
+  for (int64_t i = 0; i < n; ++i) {
+    double ps = 0.0;
+    for (int64_t k = start[i]; k < start[i + 1]; ++k)
+      if (nr[k] < p->rc) ps += or_phi(p, species[i], species[nj[k]], nr[k]);
+    e[i] = or_embed(p, species[i], rho[i]) + 0.5 * ps;
+  }
+}
+
+double or_energy_total(int64_t n, const double *e) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += e[i];
+  return s;
+}
+
+/* F_i = -dU/dx_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i) / r */
+void or_forces(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
+               const double *ndx, const double *ndy, const double *ndz,
+               const uint8_t *species, const or_pot *p, const double *rho,
+               double *fx, double *fy, double *fz) {
+  double *fp = (double *)malloc((size_t)n * sizeof(double));
+  for (int64_t i = 0; i < n; ++i) fp[i] = or_dembed(p, species[i], rho[i]);
+  for (int64_t i = 0; i < n; ++i) {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    int si = species[i];
+    for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+      double r = nr[e];
+      if (!(r < p->rc)) continue;
+      int32_t j = nj[e];
+      int sj = species[j];
+      double s = or_dphi(p, si, sj, r) + fp[i] * or_df(p, sj, r) + fp[j] * or_df(p, si, r);
+      double coef = s / r;
+      ax += coef * ndx[e];
+      ay += coef * ndy[e];
+      az += coef * ndz[e];
+    }
+    fx[i] = ax;
+    fy[i] = ay;
+    fz[i] = az;
+  }
+  free(fp);
+}
+
+/*
+ * Energy change of the transmutation s_i -> 1 - s_i (Sec. II.A, the
+ * definition of Delta U), written locally for an EAM potential:
+ *   dU = [F_{s'}(rho_i) - F_s(rho_i)]                              own embedding
+ *      + sum_j [phi_{s' s_j}(r_ij) - phi_{s s_j}(r_ij)]            pair terms
+ *      + sum_j [F_{s_j}(rho_j + delta_j) - F_{s_j}(rho_j)]         neighbours' embedding
+ * with delta_j = sum over the images of i near j of [f_{s'}(r) - f_s(r)]
+ * (one image per neighbour unless the box is smaller than twice the cutoff).
+ * Evaluated as (own + pair) + emb, each sum in neighbour order.
+ */
+double or_delta_u(int64_t i, const int64_t *start, const int32_t *nj, const double *nr,
+                  const uint8_t *species, const double *rho, const or_pot *p) {
+  int s = species[i], s1 = 1 - s;
+  double own = or_embed(p, s1, rho[i]) - or_embed(p, s, rho[i]);
+  double pair = 0.0, emb = 0.0;
+  for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+    if (!(nr[e] < p->rc)) continue;
+    int sj = species[nj[e]];
+    pair += or_phi(p, s1, sj, nr[e]) - or_phi(p, s, sj, nr[e]);
+  }
+  for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+    if (e > start[i] && nj[e] == nj[e - 1]) continue;  /* images already aggregated */
+    int32_t j = nj[e];
+    double delta = 0.0;
+    int any = 0;
+    for (int64_t e2 = e; e2 < start[i + 1] && nj[e2] == j; ++e2) {
+      if (!(nr[e2] < p->rc)) continue;
+      delta += or_f(p, s1, nr[e2]) - or_f(p, s, nr[e2]);
+      any = 1;
+    }
+    if (!any) continue;
+    int sj = species[j];
+    emb += or_embed(p, sj, rho[j] + delta) - or_embed(p, sj, rho[j]);
+  }
+  return own + pair + emb;
+}
+
+/* Commit of a transmutation at i: rho_j += delta_j for every neighbour, then flip. */
+static void or_commit(int64_t i, const int64_t *start, const int32_t *nj, const double *nr,
+                      uint8_t *species, double *rho, const or_pot *p) {
+  int s = species[i], s1 = 1 - s;
+  for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+    if (e > start[i] && nj[e] == nj[e - 1]) continue;
+    int32_t j = nj[e];
+    double delta = 0.0;
+    int any = 0;
+    for (int64_t e2 = e; e2 < start[i + 1] && nj[e2] == j; ++e2) {
+      if (!(nr[e2] < p->rc)) continue;
+      delta += or_f(p, s1, nr[e2]) - or_f(p, s, nr[e2]);
+      any = 1;
+    }
+    if (any) rho[j] = rho[j] + delta;
+  }
+  species[i] = (uint8_t)s1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cells (Sec. III.A): the box is cut into an even number of cells of edge   */
+/* >= r_dep per dimension; cells whose index parities agree form one of      */
+/* eight colours, and same-colour cells are a full cell edge apart, so       */
+/* trial sites chosen in them do not interact (octant scheme, Fig. 5).       */
+/* ------------------------------------------------------------------------ */
+int or_cell_grid(const double box[3], double r_dep, int32_t nc[3]) {
+  for (int d = 0; d < 3; ++d) {
+    nc[d] = 2 * (int32_t)floor(box[d] / (2.0 * r_dep));
+    if (nc[d] < 2) return -1;
+  }
+  return 0;
+}
+
+static int or_over(const double *over, int64_t n_over, int64_t w, int64_t s, int64_t cell,
+                   int *dec) {
+  for (int64_t k = 0; k < n_over; ++k) {
+    const double *o = over + 4 * k;
+    if ((int64_t)o[0] == w && (int64_t)o[1] == s && (int64_t)o[2] == cell) {
+      *dec = o[3] != 0.0;
+      return 1;
+    }
+  }
+  return 0;
+}
+
+/*
+ * Parallel VC-SGC Monte Carlo sweeps (Sec. III.B.2).
+ *
+ * Ensemble: pi(sigma) ~ exp[-beta (U + phi n + (kappa/N) n^2)], kappa per site,
+ * phi = dmu0 - 2 kappa cbar (Eq. pi_vcsgc with kappa_paper = kappa/N).
+ *
+ * A sweep has S = 8 ceil(N / N_cells) stages (one MC cycle = N trials, Sec. IV.B).
+ * In each stage s of sweep w:
+ *   1. colour k = top 3 bits of Philox(key, (w, s, 0, 0)).w0  (shared random
+ *      choice of the independent domain set, Sec. III.A);
+ *   2. every cell c of colour k with m_c > 0 sites, in ascending c, draws
+ *      Philox(key, (w, s, c, 1)): site = its floor(w0 m_c / 2^64)-th atom in
+ *      ascending index, u = unit(w1); the local test of Eq. trans_vcsgc_par1
+ *      accepts iff ln u < -beta (dU_i + dmu0 dn_i), dn_i = 1 - 2 s_i;
+ *   3. with dn_tot the sum over locally accepted moves, the composite move is
+ *      accepted iff ln u_g < -beta (kappa/N) dn_tot (dn_tot + 2 (n - N cbar)),
+ *      u_g = unit(Philox(key, (w, s, 0, 0)).w1) (Eq. trans_vcsgc_par2 with the
+ *      sign of the (c - c0) term that makes the product of the two factors
+ *      equal the full VC-SGC weight ratio);
+ *   4. if accepted every locally accepted flip is committed (rho cache updated).
+ * key = (seed, replica).
+ */
+int or_sweep(int64_t n, const double *x, const double *y, const double *z, const double box[3],
+             const int64_t *start, const int32_t *nj, const double *nr,
+             uint8_t *species, double *rho, int64_t *n_b, const or_pot *p,
+             const or_sweep_args *a, double *vx, double *vy, double *vz,
+             double *tlog, int64_t tcap, int64_t *tn,
+             double *slog, int64_t scap, int64_t *sn,
+             const double *over, int64_t n_over, or_stats *st) {
+  if (n < 1 || !(a->temp > 0.0) || !(a->kappa >= 0.0)) return -1;
+  int32_t nc[3] = {1, 1, 1};
+  int64_t ncells = 1;
+  if (!a->one_cell) {
+    if (or_cell_grid(box, a->r_dep, nc)) return -2;
+    ncells = (int64_t)nc[0] * nc[1] * nc[2];
+  }
+  /* counting sort of sites into cells; ascending index inside each cell */
+  int32_t *cstart = (int32_t *)calloc((size_t)ncells + 1, sizeof(int32_t));
+  int32_t *catoms = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *cof = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *ccol = (int32_t *)malloc((size_t)ncells * sizeof(int32_t));
+  for (int64_t i = 0; i < n; ++i) {
+    if (a->one_cell) {
+      cof[i] = 0;
+    } else {
+      const double *u[3] = {x, y, z};
+      int b[3];
+      for (int d = 0; d < 3; ++d) {
+        b[d] = (int)(u[d][i] / (box[d] / nc[d]));
+        if (b[d] < 0) b[d] = 0;
+        if (b[d] >= nc[d]) b[d] = nc[d] - 1;
+      }
+      cof[i] = b[0] + nc[0] * (b[1] + nc[1] * b[2]);
+    }
+    cstart[cof[i] + 1]++;
+  }
+  for (int64_t c = 0; c < ncells; ++c) cstart[c + 1] += cstart[c];
+  {
+    int32_t *fill = (int32_t *)malloc((size_t)ncells * sizeof(int32_t));
+    memcpy(fill, cstart, (size_t)ncells * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) catoms[fill[cof[i]]++] = (int32_t)i;
+    free(fill);
+  }
+  for (int64_t c = 0; c < ncells; ++c) {
+    int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((int64_t)nc[0] * nc[1]));
+    ccol[c] = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
+  }
+  int64_t S = a->one_cell ? n : 8 * ((n + ncells - 1) / ncells);
+
+  double beta = 1.0 / (OR_KB * a->temp);
+  double kN = a->kappa / (double)n;
+  uint64_t key[2] = {a->seed, a->replica};
+  int32_t *rec = (int32_t *)malloc((size_t)ncells * sizeof(int32_t));
+  memset(st, 0, sizeof(*st));
+  int64_t ntl = 0, nsl = 0;
+
+  for (int64_t w = a->w0; w < a->w0 + a->n_sweeps; ++w) {
+    for (int64_t s = 0; s < S; ++s) {
+      uint64_t ctr[4] = {(uint64_t)w, (uint64_t)s, 0, 0}, g[4];
+      or_philox4x64_10(key, ctr, g);
+      int colour = (int)(g[0] >> 61);
+      int64_t nrec = 0, dn_tot = 0;
+      for (int64_t c = 0; c < ncells; ++c) {
+        if (!a->one_cell && ccol[c] != colour) continue;
+        int64_t m = cstart[c + 1] - cstart[c];
+        if (m == 0) continue;
+        uint64_t tc[4] = {(uint64_t)w, (uint64_t)s, (uint64_t)c, 1}, t[4];
+        or_philox4x64_10(key, tc, t);
+        int64_t i = catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m)];
+        double u = or_unit(t[1]);
+        double du = or_delta_u(i, start, nj, nr, species, rho, p);
+        int dn = 1 - 2 * (int)species[i];
+        double xl = beta * (du + a->dmu0 * (double)dn);
+        double lnu = log(u);
+        double margin = lnu + xl;
+        int acc = lnu < -xl;
+        if (fabs(margin) < OR_TIE) {
+          st->near_ties++;
+          int dec;
+          if (over && or_over(over, n_over, w, s, c, &dec)) acc = dec;
+        }
+        st->trials++;
+        if (acc) {
+          st->local_accepts++;
+          rec[nrec++] = (int32_t)i;
+          dn_tot += dn;
+        }
+        if (tlog && ntl < tcap) {
+          double *L = tlog + 8 * ntl;
+          L[0] = (double)w; L[1] = (double)s; L[2] = (double)c; L[3] = (double)i;
+          L[4] = (double)dn; L[5] = (double)acc; L[6] = du; L[7] = margin;
+        }
+        ntl++;
+      }
+      st->stages++;
+      int gacc = -1;
+      double xg = 0.0, mg = 0.0;
+      if (nrec > 0) {
+        double tt = (double)*n_b - (double)n * a->cbar;
+        double dnd = (double)dn_tot;
+        xg = beta * kN * dnd * (dnd + 2.0 * tt);
+        double lnug = log(or_unit(g[1]));
+        mg = lnug + xg;
+        gacc = lnug < -xg;
+        if (fabs(mg) < OR_TIE) {
+          st->near_ties++;
+          int dec;
+          if (over && or_over(over, n_over, w, s, -1, &dec)) gacc = dec;
+        }
+        if (gacc) {
+          for (int64_t k = 0; k < nrec; ++k) {
+            int64_t i = rec[k];
+            int s0 = species[i];
+            or_commit(i, start, nj, nr, species, rho, p);
+            if (vx) {
+              double m0 = s0 ? a->mass_b : a->mass_a, m1 = s0 ? a->mass_a : a->mass_b;
+              double f = sqrt(m0 / m1);
+              vx[i] = vx[i] * f;
+              vy[i] = vy[i] * f;
+              vz[i] = vz[i] * f;
+            }
+          }
+          *n_b += dn_tot;
+          st->flips += nrec;
+          st->stage_accepts++;
+        }
+      }
+      if (slog && nsl < scap) {
+        double *L = slog + 8 * nsl;
+        L[0] = (double)w; L[1] = (double)s; L[2] = (double)colour; L[3] = (double)dn_tot;
+        L[4] = (double)nrec; L[5] = (double)gacc; L[6] = xg; L[7] = mg;
+      }
+      nsl++;
+    }
+    st->sum_n += (double)*n_b;
+    st->sum_n2 += (double)*n_b * (double)*n_b;
+  }
+  st->n_final = *n_b;
+  if (tn) *tn = ntl;
+  if (sn) *sn = nsl;
+  free(rec);
+  free(cstart);
+  free(catoms);
+  free(cof);
+  free(ccol);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Velocity Verlet MD with EAM forces (Sec. IV.A hybrid scheme, NVE)         */
+/* ------------------------------------------------------------------------ */
+static double or_wrap(double u, double L) {
+  if (u < 0.0) u += L;
+  if (u >= L) u -= L;
+  return u;
+}
+
+static int or_eval_forces(int64_t n, const double *x, const double *y, const double *z,
+                          const uint8_t *species, const double box[3], const or_pot *p,
+                          double *fx, double *fy, double *fz, double *rho) {
+  int64_t cap = 32 * n + 64;
+  for (;;) {
+    int64_t *start = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *nj = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
+    double *nr = (double *)malloc((size_t)cap * sizeof(double));
+    double *dx = (double *)malloc((size_t)cap * sizeof(double));
+    double *dy = (double *)malloc((size_t)cap * sizeof(double));
+    double *dz = (double *)malloc((size_t)cap * sizeof(double));
+    int64_t tot = or_neighbors(n, x, y, z, box, p->rc, 0, cap, start, nj, nr, dx, dy, dz);
+    if (tot < 0) {
+      free(start); free(nj); free(nr); free(dx); free(dy); free(dz);
+      return -1;
+    }
+    if (tot <= cap) {
+      or_density(n, start, nj, nr, species, p, rho);
+      or_forces(n, start, nj, nr, dx, dy, dz, species, p, rho, fx, fy, fz);
+      free(start); free(nj); free(nr); free(dx); free(dy); free(dz);
+      return 0;
+    }
+    free(start); free(nj); free(nr); free(dx); free(dy); free(dz);
+    cap = tot;
+  }
+}
+
+/*
+ * Per step, per atom, with a = F (ACC / m):
+ *   v = v + (dt/2) a;  x = wrap(x + dt v);  forces at the new positions;  v = v + (dt/2) a.
+ */
+int or_md(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+          const uint8_t *species, const double box[3], const or_pot *p,
+          double mass_a, double mass_b, double dt, int64_t n_steps,
+          double *fx, double *fy, double *fz, double *rho) {
+  double cm[2] = {OR_ACC / mass_a, OR_ACC / mass_b};
+  double hdt = 0.5 * dt;
+  if (or_eval_forces(n, x, y, z, species, box, p, fx, fy, fz, rho)) return -1;
+  for (int64_t step = 0; step < n_steps; ++step) {
+    for (int64_t i = 0; i < n; ++i) {
+      double c = cm[species[i]];
+      vx[i] = vx[i] + hdt * (fx[i] * c);
+      vy[i] = vy[i] + hdt * (fy[i] * c);
+      vz[i] = vz[i] + hdt * (fz[i] * c);
+      x[i] = or_wrap(x[i] + dt * vx[i], box[0]);
+      y[i] = or_wrap(y[i] + dt * vy[i], box[1]);
+      z[i] = or_wrap(z[i] + dt * vz[i], box[2]);
+    }
+    if (or_eval_forces(n, x, y, z, species, box, p, fx, fy, fz, rho)) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+      double c = cm[species[i]];
+      vx[i] = vx[i] + hdt * (fx[i] * c);
+      vy[i] = vy[i] + hdt * (fy[i] * c);
+      vz[i] = vz[i] + hdt * (fz[i] * c);
+    }
+  }
+  return 0;
+}

@@ -1,0 +1,96 @@
+/*
+ * Plain serial FP64 reference ("oracle") of the parallel VC-SGC transmutation
+ * Monte Carlo and EAM molecular dynamics of Sadigh et al., "A scalable parallel
+ * Monte Carlo algorithm for atomistic simulations of precipitation in alloys".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+ * this code; only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code with the HIP library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (see oracle/build_oracle.py).
+ */
+#ifndef VCSGC_ORACLE_H
+#define VCSGC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Analytic Finnis-Sinclair EAM: phi_XY = eps_XY (rc-r)^2 (c0 + c1 r),
+ * f_X = t_X (rc-r)^2, F_X(rho) = -A_X sqrt(rho); zero for r >= rc. */
+typedef struct {
+  double rc, c0, c1, eps_aa, eps_ab, eps_bb, t_a, t_b, a_a, a_b;
+} or_pot;
+
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void or_philox4x64_10(const uint64_t key[2], const uint64_t ctr[4], uint64_t out[4]);
+
+/* All pairs (j, image) with r < cutoff, rows in ascending (j, image) order.
+ * mode 0: automatic; 1: brute force, minimum image; 2: brute force image sum.
+ * Requires every box edge > cutoff (image sum) or >= 2*cutoff (minimum image).
+ * Returns the number of entries; if it exceeds cap nothing past cap is written.
+ * Returns -1 on an invalid box. */
+int64_t or_neighbors(int64_t n, const double *x, const double *y, const double *z,
+                     const double box[3], double cutoff, int mode, int64_t cap,
+                     int64_t *start, int32_t *nj, double *nr,
+                     double *ndx, double *ndy, double *ndz);
+
+void or_density(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
+                const uint8_t *species, const or_pot *p, double *rho);
+void or_energy_atoms(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
+                     const uint8_t *species, const or_pot *p, const double *rho, double *e);
+double or_energy_total(int64_t n, const double *e);
+void or_forces(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
+               const double *ndx, const double *ndy, const double *ndz,
+               const uint8_t *species, const or_pot *p, const double *rho,
+               double *fx, double *fy, double *fz);
+double or_delta_u(int64_t i, const int64_t *start, const int32_t *nj, const double *nr,
+                  const uint8_t *species, const double *rho, const or_pot *p);
+
+/* Link cells for the sweep: 2*floor(L/(2 r_dep)) cells per dimension. */
+int or_cell_grid(const double box[3], double r_dep, int32_t nc[3]);
+
+typedef struct {
+  double dmu0;      /* eV: Delta mu_0 = phi + 2 kappa c0 (local factor) */
+  double kappa;     /* eV per site (ensemble weight exp[-beta kappa n^2 / N]) */
+  double cbar;      /* c0 of the global factor */
+  double temp;      /* K */
+  uint64_t seed, replica;
+  int64_t w0, n_sweeps;
+  double r_dep;     /* independence distance: cell edge >= r_dep */
+  int32_t one_cell; /* serial mode: one cell holding every site, N stages per sweep */
+  double mass_a, mass_b; /* for velocity rescaling on transmutation */
+} or_sweep_args;
+
+typedef struct {
+  int64_t trials, local_accepts, stages, stage_accepts, flips, near_ties, n_final;
+  double sum_n, sum_n2;
+} or_stats;
+
+/* One pass of n_sweeps sweeps.  species, rho and n (count of species 1)
+ * are updated in place.  vx/vy/vz may be NULL.
+ * tlog: trial log, 8 doubles per trial (w, s, cell, site, dn, acc, dU, margin),
+ * slog: stage log, 8 doubles per stage (w, s, colour, dn_tot, nrec, acc, xg, margin),
+ * over: near-tie decisions to adopt, 4 doubles each (w, s, cell or -1, decision).
+ * Returns 0, or a negative code on invalid input. */
+int or_sweep(int64_t n, const double *x, const double *y, const double *z, const double box[3],
+             const int64_t *start, const int32_t *nj, const double *nr,
+             uint8_t *species, double *rho, int64_t *n_b, const or_pot *p,
+             const or_sweep_args *a, double *vx, double *vy, double *vz,
+             double *tlog, int64_t tcap, int64_t *tn,
+             double *slog, int64_t scap, int64_t *sn,
+             const double *over, int64_t n_over, or_stats *st);
+
+/* Velocity Verlet, n_steps steps of dt (fs).  Forces are evaluated at the
+ * incoming positions first; on return fx/fy/fz and rho hold the values at the
+ * final positions. */
+int or_md(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+          const uint8_t *species, const double box[3], const or_pot *p,
+          double mass_a, double mass_b, double dt, int64_t n_steps,
+          double *fx, double *fy, double *fz, double *rho);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,258 @@
+"""ctypes wrapper of the plain serial FP64 oracle (oracle/oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product path.  The oracle
+shares no code with the HIP library; both sides only share the seeded input
+generators.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+# VCSGC_ORACLE_LIB points the tests at another build of oracle.c (used by
+# tests/mutation_check.py to confirm that planted mistakes are caught).
+LIB_PATH = os.environ.get("VCSGC_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
+SRC = os.path.join(_HERE, "oracle.c")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no contraction into fused multiply-adds)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Pot(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("rc", "c0", "c1", "eps_aa", "eps_ab", "eps_bb", "t_a", "t_b", "a_a", "a_b")]
+
+
+class SweepArgs(C.Structure):
+    _fields_ = [("dmu0", C.c_double), ("kappa", C.c_double), ("cbar", C.c_double),
+                ("temp", C.c_double), ("seed", C.c_uint64), ("replica", C.c_uint64),
+                ("w0", C.c_int64), ("n_sweeps", C.c_int64), ("r_dep", C.c_double),
+                ("one_cell", C.c_int32), ("mass_a", C.c_double), ("mass_b", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("trials", C.c_int64), ("local_accepts", C.c_int64), ("stages", C.c_int64),
+                ("stage_accepts", C.c_int64), ("flips", C.c_int64), ("near_ties", C.c_int64),
+                ("n_final", C.c_int64), ("sum_n", C.c_double), ("sum_n2", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.c_void_p
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=False)
+        L = C.CDLL(LIB_PATH)
+        L.or_philox4x64_10.argtypes = [_P, _P, _P]
+        L.or_neighbors.restype = C.c_int64
+        L.or_neighbors.argtypes = [C.c_int64, _P, _P, _P, _P, C.c_double, C.c_int, C.c_int64,
+                                   _P, _P, _P, _P, _P, _P]
+        L.or_density.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P]
+        L.or_energy_atoms.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P]
+        L.or_energy_total.restype = C.c_double
+        L.or_energy_total.argtypes = [C.c_int64, _P]
+        L.or_forces.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.or_delta_u.restype = C.c_double
+        L.or_delta_u.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P]
+        L.or_cell_grid.restype = C.c_int
+        L.or_cell_grid.argtypes = [_P, C.c_double, _P]
+        L.or_sweep.restype = C.c_int
+        L.or_sweep.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                               _P, _P, _P, _P, C.c_int64, _P, _P, C.c_int64, _P, _P,
+                               C.c_int64, _P]
+        L.or_md.restype = C.c_int
+        L.or_md.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
+                            C.c_double, C.c_double, C.c_int64, _P, _P, _P, _P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def pot_struct(pot) -> Pot:
+    return Pot(*pot.as_tuple())
+
+
+def philox(key, ctr) -> np.ndarray:
+    k = np.asarray(key, dtype=np.uint64)
+    c = np.asarray(ctr, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().or_philox4x64_10(_p(k), _p(c), _p(out))
+    return out
+
+
+class NeighborList:
+    """CSR neighbour list: row i is entries start[i]:start[i+1] (j, r, dx, dy, dz)."""
+
+    def __init__(self, start, j, r, dx, dy, dz):
+        self.start, self.j, self.r, self.dx, self.dy, self.dz = start, j, r, dx, dy, dz
+
+    @property
+    def n(self):
+        return self.start.size - 1
+
+    def row(self, i):
+        return self.j[self.start[i]:self.start[i + 1]]
+
+
+def neighbors(x, y, z, box, cutoff, mode: int = 0) -> NeighborList:
+    x, y, z, box = _f64(x), _f64(y), _f64(z), _f64(box)
+    n = x.size
+    cap = 24 * n + 64
+    while True:
+        start = np.zeros(n + 1, dtype=np.int64)
+        j = np.zeros(cap, dtype=np.int32)
+        r, dx, dy, dz = (np.zeros(cap) for _ in range(4))
+        tot = lib().or_neighbors(n, _p(x), _p(y), _p(z), _p(box), float(cutoff), int(mode), cap,
+                                 _p(start), _p(j), _p(r), _p(dx), _p(dy), _p(dz))
+        if tot < 0:
+            raise ValueError("box too small for the requested neighbour mode")
+        if tot <= cap:
+            return NeighborList(start, j[:tot].copy(), r[:tot].copy(), dx[:tot].copy(),
+                                dy[:tot].copy(), dz[:tot].copy())
+        cap = int(tot)
+
+
+def density(nl: NeighborList, species, pot) -> np.ndarray:
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    rho = np.zeros(nl.n)
+    P = pot_struct(pot)
+    lib().or_density(nl.n, _p(nl.start), _p(nl.j), _p(nl.r), _p(sp), C.byref(P), _p(rho))
+    return rho
+
+
+def energy_atoms(nl: NeighborList, species, pot, rho=None) -> np.ndarray:
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    if rho is None:
+        rho = density(nl, sp, pot)
+    e = np.zeros(nl.n)
+    P = pot_struct(pot)
+    lib().or_energy_atoms(nl.n, _p(nl.start), _p(nl.j), _p(nl.r), _p(sp), C.byref(P),
+                          _p(_f64(rho)), _p(e))
+    return e
+
+
+def energy_total(e) -> float:
+    e = _f64(e)
+    return lib().or_energy_total(e.size, _p(e))
+
+
+def forces(nl: NeighborList, species, pot, rho=None):
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    if rho is None:
+        rho = density(nl, sp, pot)
+    fx, fy, fz = np.zeros(nl.n), np.zeros(nl.n), np.zeros(nl.n)
+    P = pot_struct(pot)
+    lib().or_forces(nl.n, _p(nl.start), _p(nl.j), _p(nl.r), _p(nl.dx), _p(nl.dy), _p(nl.dz),
+                    _p(sp), C.byref(P), _p(_f64(rho)), _p(fx), _p(fy), _p(fz))
+    return fx, fy, fz
+
+
+def delta_u(nl: NeighborList, i, species, rho, pot) -> float:
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    P = pot_struct(pot)
+    return lib().or_delta_u(int(i), _p(nl.start), _p(nl.j), _p(nl.r), _p(sp), _p(_f64(rho)),
+                            C.byref(P))
+
+
+def cell_grid(box, r_dep):
+    box = _f64(box)
+    nc = np.zeros(3, dtype=np.int32)
+    if lib().or_cell_grid(_p(box), float(r_dep), _p(nc)):
+        raise ValueError("box too small for two cells of edge r_dep")
+    return nc
+
+
+class SweepState:
+    """Mutable chain state of the oracle (species, rho cache, n, sweep counter)."""
+
+    def __init__(self, x, y, z, box, species, pot, nl: NeighborList | None = None,
+                 vx=None, vy=None, vz=None):
+        self.x, self.y, self.z, self.box = _f64(x), _f64(y), _f64(z), _f64(box)
+        self.pot = pot
+        self.species = np.array(species, dtype=np.uint8)
+        self.nl = nl if nl is not None else neighbors(self.x, self.y, self.z, self.box, pot.rc)
+        self.rho = density(self.nl, self.species, pot)
+        self.n_b = np.array([int(self.species.sum())], dtype=np.int64)
+        self.w = 0
+        self.vx = None if vx is None else _f64(vx).copy()
+        self.vy = None if vy is None else _f64(vy).copy()
+        self.vz = None if vz is None else _f64(vz).copy()
+
+    @property
+    def n(self):
+        return self.x.size
+
+
+def sweep(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, replica=0, r_dep=None,
+          one_cell=False, log_trials=0, log_stages=0, overrides=None,
+          mass_a=55.845, mass_b=63.546):
+    """Run n_sweeps sweeps from the state's sweep counter; returns (stats, tlog, slog)."""
+    L = lib()
+    if r_dep is None:
+        r_dep = 2.0 * st.pot.rc
+    a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
+                  int(st.w), int(n_sweeps), float(r_dep), int(bool(one_cell)),
+                  float(mass_a), float(mass_b))
+    tlog = np.zeros((max(log_trials, 0), 8)) if log_trials else None
+    slog = np.zeros((max(log_stages, 0), 8)) if log_stages else None
+    tn = np.zeros(1, dtype=np.int64)
+    sn = np.zeros(1, dtype=np.int64)
+    ov = None if overrides is None or len(overrides) == 0 else _f64(overrides)
+    nov = 0 if ov is None else ov.shape[0]
+    s = Stats()
+    P = pot_struct(st.pot)
+    rc = L.or_sweep(st.n, _p(st.x), _p(st.y), _p(st.z), _p(st.box), _p(st.nl.start),
+                    _p(st.nl.j), _p(st.nl.r), _p(st.species), _p(st.rho), _p(st.n_b),
+                    C.byref(P), C.byref(a), _p(st.vx), _p(st.vy), _p(st.vz),
+                    _p(tlog), int(log_trials), _p(tn), _p(slog), int(log_stages), _p(sn),
+                    _p(ov), int(nov), C.byref(s))
+    if rc != 0:
+        raise ValueError(f"or_sweep failed ({rc})")
+    st.w += int(n_sweeps)
+    if tlog is not None:
+        tlog = tlog[:min(int(tn[0]), log_trials)]
+    if slog is not None:
+        slog = slog[:min(int(sn[0]), log_stages)]
+    return s.as_dict(), tlog, slog
+
+
+def md(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, mass_a=55.845, mass_b=63.546):
+    """Velocity Verlet; returns new arrays (x, y, z, vx, vy, vz, fx, fy, fz, rho)."""
+    x, y, z = _f64(x).copy(), _f64(y).copy(), _f64(z).copy()
+    vx, vy, vz = _f64(vx).copy(), _f64(vy).copy(), _f64(vz).copy()
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    n = x.size
+    fx, fy, fz, rho = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    P = pot_struct(pot)
+    rc = lib().or_md(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(sp), _p(_f64(box)),
+                     C.byref(P), float(mass_a), float(mass_b), float(dt), int(n_steps),
+                     _p(fx), _p(fy), _p(fz), _p(rho))
+    if rc != 0:
+        raise ValueError("or_md failed")
+    return x, y, z, vx, vy, vz, fx, fy, fz, rho

@@ -1,0 +1,81 @@
+"""Plant plausible mistakes in a copy of the oracle and confirm that the CPU
+pin tests catch every one of them.
+
+Run:  python tests/mutation_check.py      (CPU only; a few minutes)
+
+Each mutation edits one expression of oracle/oracle.c in a temporary copy,
+builds it, and runs the oracle pin tests against that build through
+VCSGC_ORACLE_LIB.  A mutation that no test catches is reported and the
+script exits non-zero.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTATIONS = [
+    ("half pair energy dropped", "e[i] = or_embed(p, species[i], rho[i]) + 0.5 * ps;",
+     "e[i] = or_embed(p, species[i], rho[i]) + ps;"),
+    ("global factor sign", "xg = beta * kN * dnd * (dnd + 2.0 * tt);",
+     "xg = beta * kN * dnd * (dnd - 2.0 * tt);"),
+    ("global factor 2 dropped", "xg = beta * kN * dnd * (dnd + 2.0 * tt);",
+     "xg = beta * kN * dnd * (dnd + tt);"),
+    ("kappa not per site", "double kN = a->kappa / (double)n;", "double kN = a->kappa;"),
+    ("neighbour embedding dropped", "  return own + pair + emb;", "  return own + pair;"),
+    ("pair uses own species for j", "    int sj = species[nj[e]];\n    pair +=",
+     "    int sj = species[i];\n    pair +="),
+    ("rho commit sign", "if (any) rho[j] = rho[j] + delta;", "if (any) rho[j] = rho[j] - delta;"),
+    ("local chemical term sign", "double xl = beta * (du + a->dmu0 * (double)dn);",
+     "double xl = beta * (du - a->dmu0 * (double)dn);"),
+    ("force density derivative swapped",
+     "fp[i] * or_df(p, sj, r) + fp[j] * or_df(p, si, r)",
+     "fp[i] * or_df(p, si, r) + fp[j] * or_df(p, sj, r)"),
+    ("force direction", "double coef = s / r;", "double coef = -s / r;"),
+    ("embedding derivative factor", "return rho > 0.0 ? -A / (2.0 * sqrt(rho)) : 0.0;",
+     "return rho > 0.0 ? -A / sqrt(rho) : 0.0;"),
+    ("philox key bump", "      k1 += PH_W1;", "      k1 += PH_W0;"),
+    ("density uses own species", "s += or_f(p, species[nj[e]], nr[e]);", "s += or_f(p, species[i], nr[e]);"),
+    ("neighbour cutoff inclusive of far pairs", "  if (r < cutoff) {", "  if (r < cutoff + 0.5) {"),
+    ("site drawn from wrong word", "catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m)]",
+     "catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m) / 2]"),
+    ("commit skips flip", "  species[i] = (uint8_t)s1;\n}", "  species[i] = (uint8_t)s;\n}"),
+]
+
+TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_eam.py",
+         "tests/test_oracle_ensemble.py", "tests/test_oracle_md.py"]
+
+
+def main():
+    src = open(SRC).read()
+    missed = []
+    with tempfile.TemporaryDirectory() as td:
+        for name, old, new in MUTATIONS:
+            if src.count(old) != 1:
+                print(f"[skip] {name}: pattern not unique/found")
+                missed.append(name)
+                continue
+            mut = os.path.join(td, "oracle.c")
+            open(mut, "w").write(src.replace(old, new))
+            lib = os.path.join(td, "liboracle_mut.so")
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                                   "-std=c11", "-I", os.path.join(ROOT, "oracle"), "-o", lib,
+                                   mut, "-lm"])
+            env = dict(os.environ, VCSGC_ORACLE_LIB=lib)
+            r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                                *TESTS], cwd=ROOT, env=env, capture_output=True, text=True,
+                               timeout=900)
+            caught = r.returncode != 0
+            print(f"[{'caught' if caught else 'MISSED'}] {name}")
+            if not caught:
+                missed.append(name)
+    if missed:
+        print("uncaught:", missed)
+        sys.exit(1)
+    print("all mutations caught")
+
+
+if __name__ == "__main__":
+    main()
