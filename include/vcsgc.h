@@ -1,0 +1,180 @@
+/*
+ * vcsgc.h -- C ABI of the MI355X (gfx950) implementation of parallel
+ * variance-constrained semi-grandcanonical (VC-SGC) transmutation Monte Carlo
+ * with an embedded-atom (EAM) potential, interleaved with velocity-Verlet MD
+ * (Sadigh, Erhart, Stukowski, Caro, Martinez, Zepeda-Ruiz, "A scalable parallel
+ * Monte Carlo algorithm for atomistic simulations of precipitation in alloys").
+ *
+ * Conventions
+ *  - Every call except vcsgc_last_error returns a vcsgc_status (0 = OK, < 0 =
+ *    error).  No exception crosses the ABI.  On an argument error nothing is
+ *    modified.  A device error is sticky: later calls on the context return
+ *    VCSGC_E_STATE; vcsgc_last_error gives the message.
+ *  - Pointers in vcsgc_system are DEVICE pointers owned by the caller.  They
+ *    are borrowed for the lifetime of the context and must not be written by
+ *    the caller while a call is in flight.  Library scratch (cells, neighbour
+ *    lists, density cache, stage records, counters) is owned by the context
+ *    and released by vcsgc_destroy.
+ *  - All work is ordered on the stream given at creation and is asynchronous,
+ *    except calls that return host values (statistics, energies, counts),
+ *    which synchronize that stream.
+ *  - Species: 0 = A, 1 = B ("spin 1" of Sec. II; c = n_B / N).  Positions are
+ *    Cartesian in an orthorhombic periodic box and must lie in [0, L).
+ *  - Units: Angstrom, eV, fs, atomic mass units, K.
+ */
+#ifndef VCSGC_H
+#define VCSGC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vcsgc_ctx vcsgc_ctx; /* opaque, library-owned */
+
+typedef enum {
+  VCSGC_OK = 0,
+  VCSGC_E_INVALID_ARG = -1,
+  VCSGC_E_BOX_TOO_SMALL = -2,
+  VCSGC_E_OUT_OF_MEMORY = -3,
+  VCSGC_E_DEVICE = -4,
+  VCSGC_E_STATE = -5,
+  VCSGC_E_NO_SURROGATE = -6,
+  VCSGC_E_OVERFLOW = -8
+} vcsgc_status;
+
+/* Analytic Finnis-Sinclair EAM (zero for r >= rc):
+ *   pair      phi_XY(r) = eps_XY (rc - r)^2 (c0 + c1 r)
+ *   density   f_X(r)    = t_X (rc - r)^2
+ *   embedding F_X(rho)  = -A_X sqrt(rho)
+ * mass_a / mass_b are the species masses for MD (u). */
+typedef struct {
+  double rc, c0, c1, eps_aa, eps_ab, eps_bb, t_a, t_b, a_a, a_b, mass_a, mass_b;
+} vcsgc_eam_fs;
+
+typedef struct {
+  int64_t n_atoms;  /* N >= 2 */
+  double box[3];    /* orthorhombic periodic box edges, Angstrom */
+  double *x, *y, *z;    /* positions in [0, L), device, N each */
+  double *vx, *vy, *vz; /* velocities (A/fs), device; NULL => MC-only context */
+  double *fx, *fy, *fz; /* forces (eV/A), device; NULL allowed for MC-only */
+  uint8_t *species;     /* device, N entries in {0, 1} */
+  vcsgc_eam_fs pot;
+  double skin;   /* MD neighbour-list skin (A), >= 0; typical 0.3 */
+  double r_dep;  /* independence distance for the cell colouring; 0 => 2 rc */
+  uint32_t flags;        /* reserved, 0 */
+} vcsgc_system;
+
+/* Per-call statistics (host struct). */
+typedef struct {
+  int64_t trials;         /* local trials made (sites drawn in non-empty active cells) */
+  int64_t local_accepts;  /* trials passing the local factor */
+  int64_t stages;         /* stages run */
+  int64_t stage_accepts;  /* stages whose composite move passed the global factor */
+  int64_t flips;          /* transmutations committed */
+  int64_t near_ties;      /* decisions with |ln u + x| < 1e-9 */
+  int64_t n_final;        /* n_B after the call */
+  double sum_n, sum_n2;   /* sum over sweeps of n_B and n_B^2 after each sweep */
+} vcsgc_stats;
+
+typedef struct {
+  uint64_t sweeps_done; /* cumulative sweep counter w (Philox counter word 0) */
+  int64_t n_b;          /* current number of B atoms */
+} vcsgc_state;
+
+typedef struct {
+  int32_t n_cells[3];   /* link cells per dimension (even, edge >= r_dep) */
+  int64_t stages_per_sweep; /* S = 8 ceil(N / N_cells) */
+  int32_t kmax;         /* neighbour-list row capacity */
+  int32_t mc_kmax_used; /* largest row of the r < rc list */
+} vcsgc_info;
+
+/* Create a context for one system.  Validates the arguments and the input
+ * arrays (positions inside the box, species in {0, 1}), bins the sites into
+ * link cells of edge >= r_dep (an even number per dimension), builds the
+ * r < rc neighbour list and the density cache rho_i = sum_j f_{s_j}(r_ij).
+ * Sec. III.A: the independent-domain decomposition with R_c = 2 rc for a
+ * many-body potential.  Errors: VCSGC_E_INVALID_ARG, VCSGC_E_BOX_TOO_SMALL
+ * (fewer than two cells of edge r_dep in some dimension),
+ * VCSGC_E_OUT_OF_MEMORY, VCSGC_E_OVERFLOW (a site with more than kmax
+ * neighbours), VCSGC_E_DEVICE.  *out is set only on success. */
+vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx **out);
+
+/* Release a context and its scratch (synchronizes its stream). NULL is a no-op. */
+vcsgc_status vcsgc_destroy(vcsgc_ctx *ctx);
+
+/* Run n_sweeps sweeps of the parallel VC-SGC Monte Carlo of Sec. III.B.2 on
+ * the species array.  Ensemble (Eq. pi_vcsgc, kappa per site):
+ *   pi(sigma) ~ exp[-beta (U + phi n + (kappa/N) n^2)],  phi = dmu0 - 2 kappa cbar.
+ * A sweep has S = 8 ceil(N/N_cells) stages (one MC cycle = N trials, Sec.
+ * IV.B).  In each stage a colour is drawn (one of the eight independent
+ * domain sets, Sec. III.A) and every non-empty cell of that colour makes one
+ * trial at a uniformly drawn site, accepted locally with
+ *   min{1, exp[-beta (dU_i + dmu0 dn_i)]}            (Eq. trans_vcsgc_par1);
+ * the composite move is then accepted with
+ *   min{1, exp[-beta (kappa/N) dn_tot (dn_tot + 2 (n - N cbar))]}
+ * (Eq. trans_vcsgc_par2, the sign under which the two factors multiply to the
+ * ensemble's weight ratio) and committed, updating the density cache.
+ * Random numbers are Philox4x64-10 keyed (seed, 0) with counters
+ * (w, s, 0, 0) for the stage and (w, s, cell, 1) for a trial, w the
+ * cumulative sweep counter, so sweep(a) followed by sweep(b) equals
+ * sweep(a + b).  kappa = 0 is plain SGC.  With velocities present a
+ * transmuted atom's velocity is scaled by sqrt(m_old / m_new).
+ * dmu0 in eV, kappa in eV per site (>= 0), cbar in [0, 1], T_K > 0,
+ * n_sweeps >= 0.  out (host, may be NULL) receives the statistics of this call. */
+vcsgc_status vcsgc_sweep(vcsgc_ctx *ctx, double dmu0, double kappa, double cbar, double T_K,
+                         int64_t n_sweeps, uint64_t seed, vcsgc_stats *out);
+
+/* Fresh EAM evaluation at the current positions and species: rho, per-atom
+ * energies E_i = F_{s_i}(rho_i) + 1/2 sum_j phi(r_ij) and, if want_forces,
+ * forces F_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i)/r
+ * written to sys.fx/fy/fz (which must then be non-NULL).  energy_eV (host,
+ * may be NULL) receives U = sum_i E_i from a fixed-shape reduction tree. */
+vcsgc_status eam_energy_forces(vcsgc_ctx *ctx, double *energy_eV, int want_forces);
+
+/* n_steps velocity-Verlet steps of dt_fs with EAM forces (NVE; the MD half of
+ * the hybrid MD/MC scheme of Sec. IV.A).  Forces are evaluated at the incoming
+ * positions first; per step: v += dt/2 a, x += dt v (wrapped), forces,
+ * v += dt/2 a, with a = F * 9.648533212e-3 / m.  The r < rc + skin list is
+ * rebuilt whenever an atom has moved more than skin/2 since the last build.
+ * Requires velocities and forces in the system.  On return the density cache
+ * matches the final positions. */
+vcsgc_status md_verlet_step(vcsgc_ctx *ctx, double dt_fs, int64_t n_steps);
+
+/* Message of the last error on this context (or of the last failed create when
+ * ctx is NULL).  The string is owned by the library. */
+const char *vcsgc_last_error(const vcsgc_ctx *ctx);
+
+/* Parity logging.  While enabled, every trial appends 8 doubles
+ * (w, s, cell, site, dn, local_accept, dU, ln u + x) to tlog and every stage
+ * appends (w, s, colour, dn_tot, n_records, global_accept or -1, x_g,
+ * ln u_g + x_g) to slog, in completion order, until the capacities (in
+ * records) are reached.  Buffers are caller-owned device memory.  Passing
+ * NULL buffers disables logging and resets the counters. */
+vcsgc_status vcsgc_set_log(vcsgc_ctx *ctx, double *tlog_dev, int64_t tcap, double *slog_dev,
+                           int64_t scap);
+/* Number of records written so far (may exceed the capacity). */
+vcsgc_status vcsgc_log_counts(vcsgc_ctx *ctx, int64_t *n_trials, int64_t *n_stages);
+
+/* Chain state for checkpoint/resume: the cumulative sweep counter and n_B.
+ * set_state only moves the counter (n_B is recomputed from the species). */
+vcsgc_status vcsgc_get_state(vcsgc_ctx *ctx, vcsgc_state *out);
+vcsgc_status vcsgc_set_state(vcsgc_ctx *ctx, const vcsgc_state *in);
+
+/* Copy the density cache (N doubles) into a caller device buffer. */
+vcsgc_status vcsgc_copy_rho(vcsgc_ctx *ctx, double *rho_dev);
+/* Per-atom energies at the current state (fresh density) into a device buffer. */
+vcsgc_status vcsgc_atom_energies(vcsgc_ctx *ctx, double *e_dev);
+/* Geometry of the context. */
+vcsgc_status vcsgc_get_info(vcsgc_ctx *ctx, vcsgc_info *out);
+
+/* Diagnostics: out[i] = sqrt(in[i]) in FP64 on the device, n >= 0. */
+vcsgc_status vcsgc_selftest_sqrt(const double *in_dev, double *out_dev, int64_t n,
+                                 hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VCSGC_H */

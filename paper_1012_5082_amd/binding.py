@@ -1,0 +1,270 @@
+"""ctypes binding of libvcsgc.so (the C ABI of include/vcsgc.h).
+
+Argument marshalling only: every step of the sweep, the EAM evaluation and the
+MD runs in the library's HIP kernels.  PyTorch supplies device memory and the
+HIP stream.  There is no fallback: if the library is missing or no GPU is
+present, constructing a context raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvcsgc.so")
+
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BOX_TOO_SMALL", -3: "OUT_OF_MEMORY", -4: "DEVICE",
+          -5: "STATE", -6: "NO_SURROGATE", -8: "OVERFLOW"}
+
+
+class VcsgcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vcsgc error {code} ({STATUS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class EamFS(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("rc", "c0", "c1", "eps_aa", "eps_ab", "eps_bb", "t_a",
+                                          "t_b", "a_a", "a_b", "mass_a", "mass_b")]
+
+
+class System(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("box", C.c_double * 3),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
+                ("fx", C.c_void_p), ("fy", C.c_void_p), ("fz", C.c_void_p),
+                ("species", C.c_void_p), ("pot", EamFS), ("skin", C.c_double),
+                ("r_dep", C.c_double), ("flags", C.c_uint32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("trials", C.c_int64), ("local_accepts", C.c_int64), ("stages", C.c_int64),
+                ("stage_accepts", C.c_int64), ("flips", C.c_int64), ("near_ties", C.c_int64),
+                ("n_final", C.c_int64), ("sum_n", C.c_double), ("sum_n2", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class State(C.Structure):
+    _fields_ = [("sweeps_done", C.c_uint64), ("n_b", C.c_int64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_cells", C.c_int32 * 3), ("stages_per_sweep", C.c_int64), ("kmax", C.c_int32),
+                ("mc_kmax_used", C.c_int32)]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Load libvcsgc.so (after torch, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (binds the process to torch's HIP runtime first)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        L.vcsgc_create.restype = st
+        L.vcsgc_create.argtypes = [C.POINTER(System), _P, C.POINTER(_P)]
+        L.vcsgc_destroy.restype = st
+        L.vcsgc_destroy.argtypes = [_P]
+        L.vcsgc_sweep.restype = st
+        L.vcsgc_sweep.argtypes = [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64,
+                                  C.c_uint64, C.POINTER(Stats)]
+        L.eam_energy_forces.restype = st
+        L.eam_energy_forces.argtypes = [_P, C.POINTER(C.c_double), C.c_int]
+        L.md_verlet_step.restype = st
+        L.md_verlet_step.argtypes = [_P, C.c_double, C.c_int64]
+        L.vcsgc_last_error.restype = C.c_char_p
+        L.vcsgc_last_error.argtypes = [_P]
+        L.vcsgc_set_log.restype = st
+        L.vcsgc_set_log.argtypes = [_P, _P, C.c_int64, _P, C.c_int64]
+        L.vcsgc_log_counts.restype = st
+        L.vcsgc_log_counts.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.vcsgc_get_state.restype = st
+        L.vcsgc_get_state.argtypes = [_P, C.POINTER(State)]
+        L.vcsgc_set_state.restype = st
+        L.vcsgc_set_state.argtypes = [_P, C.POINTER(State)]
+        L.vcsgc_copy_rho.restype = st
+        L.vcsgc_copy_rho.argtypes = [_P, _P]
+        L.vcsgc_atom_energies.restype = st
+        L.vcsgc_atom_energies.argtypes = [_P, _P]
+        L.vcsgc_get_info.restype = st
+        L.vcsgc_get_info.argtypes = [_P, C.POINTER(Info)]
+        L.vcsgc_selftest_sqrt.restype = st
+        L.vcsgc_selftest_sqrt.argtypes = [_P, _P, C.c_int64, _P]
+        _lib = L
+    return _lib
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(a, dtype, device):
+    import torch
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=dtype)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+    return t.contiguous()
+
+
+def pot_struct(pot, mass_a=55.845, mass_b=63.546) -> EamFS:
+    return EamFS(*pot.as_tuple(), mass_a, mass_b)
+
+
+def selftest_sqrt(x):
+    """Device FP64 sqrt of a CUDA float64 tensor (diagnostic)."""
+    import torch
+    out = torch.empty_like(x)
+    rc = lib().vcsgc_selftest_sqrt(_P(x.data_ptr()), _P(out.data_ptr()), x.numel(),
+                                   _stream_handle())
+    if rc:
+        raise VcsgcError(rc, "selftest_sqrt")
+    torch.cuda.synchronize()
+    return out
+
+
+class VCSGC:
+    """One system on the GPU.  Arrays are torch CUDA tensors owned by this
+    object (copied from numpy inputs) and borrowed by the library context."""
+
+    def __init__(self, x, y, z, box, species, pot, vx=None, vy=None, vz=None, forces=False,
+                 skin=0.3, r_dep=0.0, mass_a=55.845, mass_b=63.546, device="cuda", stream=None):
+        import torch
+        L = lib()
+        self.device = torch.device(device)
+        f64 = torch.float64
+        self.x, self.y, self.z = (_dev(a, f64, self.device) for a in (x, y, z))
+        self.species = _dev(species, torch.uint8, self.device)
+        self.n = self.x.numel()
+        self.box = np.asarray(box, dtype=np.float64)
+        self.pot = pot
+        self.vx = self.vy = self.vz = None
+        if vx is not None:
+            self.vx, self.vy, self.vz = (_dev(a, f64, self.device) for a in (vx, vy, vz))
+        self.fx = self.fy = self.fz = None
+        if forces or vx is not None:
+            self.fx, self.fy, self.fz = (torch.zeros(self.n, dtype=f64, device=self.device)
+                                         for _ in range(3))
+        self.stream = stream
+        sysd = System()
+        sysd.n_atoms = self.n
+        sysd.box = (C.c_double * 3)(*self.box.tolist())
+        ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        sysd.x, sysd.y, sysd.z = ptr(self.x), ptr(self.y), ptr(self.z)
+        sysd.vx, sysd.vy, sysd.vz = ptr(self.vx), ptr(self.vy), ptr(self.vz)
+        sysd.fx, sysd.fy, sysd.fz = ptr(self.fx), ptr(self.fy), ptr(self.fz)
+        sysd.species = ptr(self.species)
+        sysd.pot = pot_struct(pot, mass_a, mass_b)
+        sysd.skin = float(skin)
+        sysd.r_dep = float(r_dep)
+        sysd.flags = 0
+        self._sys = sysd
+        h = _P()
+        rc = L.vcsgc_create(C.byref(sysd), _stream_handle(stream), C.byref(h))
+        if rc:
+            raise VcsgcError(rc, L.vcsgc_last_error(None).decode())
+        self._h = h
+        self._logs = None
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vcsgc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().vcsgc_last_error(self._h)
+            raise VcsgcError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    # -- calls --------------------------------------------------------------
+    def sweep(self, dmu0, kappa, cbar, T, n_sweeps, seed, stats=True):
+        s = Stats()
+        self._check(lib().vcsgc_sweep(self._h, float(dmu0), float(kappa), float(cbar), float(T),
+                                      int(n_sweeps), int(seed), C.byref(s) if stats else None),
+                    "sweep")
+        return s.as_dict() if stats else None
+
+    def energy(self, forces=False):
+        e = C.c_double()
+        self._check(lib().eam_energy_forces(self._h, C.byref(e), int(bool(forces))), "energy")
+        return e.value
+
+    def compute_forces(self):
+        self._check(lib().eam_energy_forces(self._h, None, 1), "forces")
+
+    def md(self, dt, n_steps):
+        self._check(lib().md_verlet_step(self._h, float(dt), int(n_steps)), "md")
+
+    def enable_log(self, trial_cap, stage_cap):
+        import torch
+        t = torch.zeros((max(trial_cap, 1), 8), dtype=torch.float64, device=self.device)
+        s = torch.zeros((max(stage_cap, 1), 8), dtype=torch.float64, device=self.device)
+        self._logs = (t, s, trial_cap, stage_cap)
+        self._check(lib().vcsgc_set_log(self._h, _P(t.data_ptr()), int(trial_cap),
+                                        _P(s.data_ptr()), int(stage_cap)), "set_log")
+
+    def disable_log(self):
+        self._check(lib().vcsgc_set_log(self._h, None, 0, None, 0), "set_log")
+        self._logs = None
+
+    def logs(self):
+        """(trial log, stage log) as numpy arrays, rows sorted by (w, s, cell)."""
+        import torch
+        nt, ns = C.c_int64(), C.c_int64()
+        self._check(lib().vcsgc_log_counts(self._h, C.byref(nt), C.byref(ns)), "log_counts")
+        t, s, tc, sc = self._logs
+        torch.cuda.synchronize()
+        tl = t[:min(nt.value, tc)].cpu().numpy()
+        sl = s[:min(ns.value, sc)].cpu().numpy()
+        if tl.size:
+            tl = tl[np.lexsort((tl[:, 2], tl[:, 1], tl[:, 0]))]
+        if sl.size:
+            sl = sl[np.lexsort((sl[:, 1], sl[:, 0]))]
+        return tl, sl, nt.value, ns.value
+
+    def get_state(self):
+        st = State()
+        self._check(lib().vcsgc_get_state(self._h, C.byref(st)), "get_state")
+        return {"sweeps_done": st.sweeps_done, "n_b": st.n_b}
+
+    def set_state(self, sweeps_done):
+        st = State(int(sweeps_done), 0)
+        self._check(lib().vcsgc_set_state(self._h, C.byref(st)), "set_state")
+
+    def rho(self):
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self._check(lib().vcsgc_copy_rho(self._h, _P(out.data_ptr())), "copy_rho")
+        torch.cuda.synchronize()
+        return out
+
+    def atom_energies(self):
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self._check(lib().vcsgc_atom_energies(self._h, _P(out.data_ptr())), "atom_energies")
+        torch.cuda.synchronize()
+        return out
+
+    def info(self):
+        i = Info()
+        self._check(lib().vcsgc_get_info(self._h, C.byref(i)), "info")
+        return {"n_cells": list(i.n_cells), "stages_per_sweep": i.stages_per_sweep,
+                "kmax": i.kmax, "mc_kmax_used": i.mc_kmax_used}

@@ -1,0 +1,284 @@
+// Link cells and neighbour lists (Sec. III.A: cells of edge >= the
+// independence distance, an even number per dimension so that cells whose
+// index parities agree are a full cell edge apart), the density cache of the
+// sweep, input validation and a fixed-shape FP64 reduction.
+#include "common.hpp"
+
+namespace vc {
+
+// ----------------------------------------------------------------------------
+// validation: positions inside [0, L), species in {0, 1}
+// ----------------------------------------------------------------------------
+__global__ void k_validate(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                           const double *__restrict__ z, const uint8_t *__restrict__ sp, double L0,
+                           double L1, double L2, DevState *ds) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = x[i], b = y[i], c = z[i];
+  const bool ok = (a >= 0.0 && a < L0) && (b >= 0.0 && b < L1) && (c >= 0.0 && c < L2) &&
+                  sp[i] <= 1;
+  if (!ok) atomicOr(&ds->bad_input, 1);
+}
+
+hipError_t launch_validate(vcsgc_ctx *c) {
+  k_validate<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, c->sp, c->box[0],
+                                                      c->box[1], c->box[2], c->ds);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// binning: count, exclusive scan, scatter, then sort each cell ascending
+// ----------------------------------------------------------------------------
+struct Grid {
+  double L0, L1, L2;
+  int n0, n1, n2;
+};
+
+__device__ __forceinline__ int cell_of(const Grid &g, double a, double b, double c) {
+  const int cx = cell_coord(a, g.L0, g.n0);
+  const int cy = cell_coord(b, g.L1, g.n1);
+  const int cz = cell_coord(c, g.L2, g.n2);
+  return cx + g.n0 * (cy + g.n1 * cz);
+}
+
+__global__ void k_cell_count(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                             const double *__restrict__ z, Grid g, int32_t *count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&count[cell_of(g, x[i], y[i], z[i])], 1);
+}
+
+// exclusive scan of count[0..m) into start[0..m], one block of 1024 threads
+__global__ void __launch_bounds__(1024) k_scan(int64_t m, const int32_t *__restrict__ count,
+                                                int32_t *start, int32_t *fill) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (m + 1023) / 1024;
+  const int64_t lo = t * chunk, hi = lo + chunk < m ? lo + chunk : m;
+  int32_t s = 0;
+  for (int64_t k = lo; k < hi; ++k) s += count[k];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = part[t] - s;  // exclusive prefix of this chunk
+  for (int64_t k = lo; k < hi; ++k) {
+    start[k] = run;
+    fill[k] = run;
+    run += count[k];
+  }
+  if (t == 1023) start[m] = part[1023];
+}
+
+__global__ void k_cell_fill(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                            const double *__restrict__ z, Grid g, int32_t *fill, int32_t *atoms) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell_of(g, x[i], y[i], z[i]);
+  atoms[atomicAdd(&fill[c], 1)] = (int32_t)i;
+}
+
+// canonical order inside a cell: ascending site index
+__global__ void k_cell_sort(int64_t m, const int32_t *__restrict__ start, int32_t *atoms) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int32_t lo = start[c], hi = start[c + 1];
+  for (int32_t a = lo + 1; a < hi; ++a) {
+    const int32_t v = atoms[a];
+    int32_t b = a - 1;
+    while (b >= lo && atoms[b] > v) {
+      atoms[b + 1] = atoms[b];
+      --b;
+    }
+    atoms[b + 1] = v;
+  }
+}
+
+hipError_t launch_bin_cells(vcsgc_ctx *c) {
+  Grid g{c->box[0], c->box[1], c->box[2], c->nc[0], c->nc[1], c->nc[2]};
+  hipError_t e = hipMemsetAsync(c->cell_count, 0, sizeof(int32_t) * c->ncells, c->stream);
+  if (e != hipSuccess) return e;
+  k_cell_count<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, g, c->cell_count);
+  k_scan<<<1, 1024, 0, c->stream>>>(c->ncells, c->cell_count, c->cell_start, c->cell_fill);
+  k_cell_fill<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, g, c->cell_fill,
+                                                       c->cell_atoms);
+  k_cell_sort<<<grid_for(c->ncells), BLOCK, 0, c->stream>>>(c->ncells, c->cell_start,
+                                                            c->cell_atoms);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// neighbour lists from the cells.  Every pair with r < cutoff, r from the
+// minimum-image separation as sqrt((dx^2 + dy^2) + dz^2), rows sorted by
+// neighbour index.  Column-major rows: entry k of atom i at [k * n + i].
+// MC rows additionally store dd = (rc - r)^2 and g = c0 + c1 r.
+// ----------------------------------------------------------------------------
+template <bool MC>
+__global__ void k_build(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                        const double *__restrict__ z, Grid g,
+                        const int32_t *__restrict__ cstart, const int32_t *__restrict__ catoms,
+                        double cutoff, PotD p, int32_t *nj, double *ndd, double *ng,
+                        uint8_t *cnt, double *xr, double *yr, double *zr, DevState *ds) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i], zi = z[i];
+  const int cx = cell_coord(xi, g.L0, g.n0), cy = cell_coord(yi, g.L1, g.n1),
+            cz = cell_coord(zi, g.L2, g.n2);
+  // distinct neighbouring cells per axis (two cells per axis: both, once)
+  const int lo0 = g.n0 >= 3 ? -1 : 0, lo1 = g.n1 >= 3 ? -1 : 0, lo2 = g.n2 >= 3 ? -1 : 0;
+  const int hi0 = g.n0 >= 2 ? 1 : 0, hi1 = g.n1 >= 2 ? 1 : 0, hi2 = g.n2 >= 2 ? 1 : 0;
+  int count = 0;
+  for (int oz = lo2; oz <= hi2; ++oz) {
+    const int zz = (cz + oz + g.n2) % g.n2;
+    for (int oy = lo1; oy <= hi1; ++oy) {
+      const int yy = (cy + oy + g.n1) % g.n1;
+      for (int ox = lo0; ox <= hi0; ++ox) {
+        const int xx = (cx + ox + g.n0) % g.n0;
+        const int cc = xx + g.n0 * (yy + g.n1 * zz);
+        for (int32_t k = cstart[cc]; k < cstart[cc + 1]; ++k) {
+          const int32_t j = catoms[k];
+          if (j == i) continue;
+          const double dx = min_image(x[j] - xi, g.L0);
+          const double dy = min_image(y[j] - yi, g.L1);
+          const double dz = min_image(z[j] - zi, g.L2);
+          const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+          if (r < cutoff) {
+            if (count < KMAX) {
+              nj[(int64_t)count * n + i] = j;
+              if (MC) ndd[(int64_t)count * n + i] = r;
+            }
+            ++count;
+          }
+        }
+      }
+    }
+  }
+  if (count > KMAX) {
+    atomicOr(&ds->overflow, 1);
+    count = KMAX;
+  }
+  atomicMax(&ds->kmax_used, count);
+  // insertion sort of the row by neighbour index (r travels along for MC)
+  for (int a = 1; a < count; ++a) {
+    const int32_t v = nj[(int64_t)a * n + i];
+    const double rv = MC ? ndd[(int64_t)a * n + i] : 0.0;
+    int b = a - 1;
+    while (b >= 0 && nj[(int64_t)b * n + i] > v) {
+      nj[(int64_t)(b + 1) * n + i] = nj[(int64_t)b * n + i];
+      if (MC) ndd[(int64_t)(b + 1) * n + i] = ndd[(int64_t)b * n + i];
+      --b;
+    }
+    nj[(int64_t)(b + 1) * n + i] = v;
+    if (MC) ndd[(int64_t)(b + 1) * n + i] = rv;
+  }
+  if (MC) {
+    for (int a = 0; a < count; ++a) {
+      const double r = ndd[(int64_t)a * n + i];
+      const double d = p.rc - r;
+      ndd[(int64_t)a * n + i] = d * d;
+      ng[(int64_t)a * n + i] = p.c0 + p.c1 * r;
+    }
+  } else {
+    xr[i] = xi;
+    yr[i] = yi;
+    zr[i] = zi;
+  }
+  cnt[i] = (uint8_t)count;
+}
+
+hipError_t launch_build_mc_list(vcsgc_ctx *c) {
+  Grid g{c->box[0], c->box[1], c->box[2], c->nc[0], c->nc[1], c->nc[2]};
+  k_build<true><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+      c->n, c->x, c->y, c->z, g, c->cell_start, c->cell_atoms, c->pot.rc, c->pot, c->mc_j,
+      c->mc_dd, c->mc_g, c->mc_cnt, nullptr, nullptr, nullptr, c->ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_md_list(vcsgc_ctx *c) {
+  Grid g{c->box[0], c->box[1], c->box[2], c->nc[0], c->nc[1], c->nc[2]};
+  k_build<false><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+      c->n, c->x, c->y, c->z, g, c->cell_start, c->cell_atoms, c->pot.rc + c->skin, c->pot,
+      c->md_j, nullptr, nullptr, c->md_cnt, c->xr, c->yr, c->zr, c->ds);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// density cache: rho_i = sum_j t_{s_j} (rc - r_ij)^2, ascending j
+// ----------------------------------------------------------------------------
+__global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
+                             const double *__restrict__ ndd, const uint8_t *__restrict__ cnt,
+                             const uint8_t *__restrict__ sp, PotD p, double *rho) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  const int m = cnt[i];
+  for (int k = 0; k < m; ++k) {
+    const int32_t j = nj[(int64_t)k * n + i];
+    s += p.t[sp[j]] * ndd[(int64_t)k * n + i];
+  }
+  rho[i] = s;
+}
+
+hipError_t launch_density_mc(vcsgc_ctx *c) {
+  k_density_mc<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->mc_j, c->mc_dd, c->mc_cnt, c->sp,
+                                                        c->pot, c->rho);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// fixed-shape reduction: 256-wide blocks summed by a fixed binary tree, then
+// the block sums by the same scheme in one block (deterministic for given n)
+// ----------------------------------------------------------------------------
+__global__ void k_reduce_blocks(int64_t n, const double *__restrict__ v, double *out) {
+  __shared__ double s[BLOCK];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + t;
+  s[t] = i < n ? v[i] : 0.0;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if (t < h) s[t] = s[t] + s[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[blockIdx.x] = s[0];
+}
+
+__global__ void k_reduce_final(int64_t m, const double *__restrict__ part, double *out) {
+  __shared__ double s[BLOCK];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t k = t; k < m; k += BLOCK) acc = acc + part[k];
+  s[t] = acc;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if (t < h) s[t] = s[t] + s[t + h];
+    __syncthreads();
+  }
+  if (t == 0) *out = s[0];
+}
+
+hipError_t launch_reduce_sum(vcsgc_ctx *c, const double *v, int64_t n, double *out_dev) {
+  const int nb = grid_for(n);
+  k_reduce_blocks<<<nb, BLOCK, 0, c->stream>>>(n, v, c->red);
+  k_reduce_final<<<1, BLOCK, 0, c->stream>>>(nb, c->red, out_dev);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// diagnostics
+// ----------------------------------------------------------------------------
+__global__ void k_sqrt(int64_t n, const double *__restrict__ in, double *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = sqrt(in[i]);
+}
+
+hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_sqrt<<<grid_for(n), BLOCK, 0, s>>>(n, in, out);
+  return hipGetLastError();
+}
+
+}  // namespace vc

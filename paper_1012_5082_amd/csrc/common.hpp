@@ -1,0 +1,194 @@
+// Shared declarations of the HIP library: context, device helpers (Philox,
+// Finnis-Sinclair EAM), launch helpers.  gfx950 only.
+//
+// Floating-point policy: every FP64 expression is evaluated exactly in the
+// order written (the library is compiled with -ffp-contract=off), sums over
+// neighbours run in ascending neighbour index, and no floating-point atomics
+// are used, so results are reproducible bit for bit run to run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "vcsgc.h"
+
+namespace vc {
+
+constexpr double KB = 8.617333262e-5;   // eV/K
+constexpr double ACC = 9.648533212e-3;  // (eV/A)/u -> A/fs^2
+constexpr double TIE = 1e-9;            // near-tie margin on |ln u + x|
+constexpr int KMAX = 32;                // neighbour-list row capacity
+constexpr int BLOCK = 256;
+
+// Potential in device-friendly form; eps is indexed by s_i + s_j.
+struct PotD {
+  double rc, c0, c1;
+  double eps[3];
+  double t[2];
+  double A[2];
+  double cm[2];    // ACC / mass
+  double mass[2];  // u
+};
+
+// Device-resident counters and chain scalars of one context.
+struct DevState {
+  unsigned long long trials, local_acc, stages, stage_acc, flips, near_ties;
+  long long n_b[2];             // n_B, ping-pong by stage parity within a call
+  long long n_b_cur;            // n_B after the last committed stage
+  long long dn[2];              // per-stage sum of dn over local accepts
+  unsigned long long nrec[2];   // per-stage count of local accepts
+  double sum_n, sum_n2;
+  unsigned long long tlog_n, slog_n;
+  int overflow;   // a neighbour row exceeded KMAX
+  int bad_input;  // position outside the box / species not in {0,1}
+  int rebuild;    // MD: an atom moved more than skin/2
+  int kmax_used;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
+// multiplies words 0 and 2 by the two round constants (full 128-bit
+// products), swaps and xors the high halves with words 1/3 and the key; the
+// key advances by the two Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ U4 philox(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1,
+                                     uint64_t c2, uint64_t c3) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t a = hi1 ^ c1 ^ k0, b = hi0 ^ c3 ^ k1;
+    c0 = a;
+    c1 = lo1;
+    c2 = b;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  U4 o;
+  o.v[0] = c0;
+  o.v[1] = c1;
+  o.v[2] = c2;
+  o.v[3] = c3;
+  return o;
+}
+
+// uniform double in (0,1): ((w >> 11) + 1/2) 2^-53
+__device__ __forceinline__ double unit_open(uint64_t w) {
+  return ((double)(w >> 11) + 0.5) * 0x1p-53;
+}
+
+// uniform index in [0, m): floor(w m / 2^64)
+__device__ __forceinline__ uint32_t draw_index(uint64_t w, uint32_t m) {
+  return (uint32_t)__umul64hi(w, (uint64_t)m);
+}
+
+// ---------------------------------------------------------------------------
+// Finnis-Sinclair EAM pieces.  With d = rc - r, dd = d*d, g = c0 + c1 r:
+//   phi_XY = (eps_XY dd) g,  f_X = t_X dd,  F_X(rho) = -A_X sqrt(max(rho,0)).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double embed(const PotD &p, int s, double rho) {
+  return -p.A[s] * sqrt(rho > 0.0 ? rho : 0.0);
+}
+
+__device__ __forceinline__ double dembed(const PotD &p, int s, double rho) {
+  return rho > 0.0 ? -p.A[s] / (2.0 * sqrt(rho)) : 0.0;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) {
+  const double h = 0.5 * L;
+  if (d > h) return d - L;
+  if (d < -h) return d + L;
+  return d;
+}
+
+__device__ __forceinline__ double wrap_box(double u, double L) {
+  if (u < 0.0) u += L;
+  if (u >= L) u -= L;
+  return u;
+}
+
+// cell coordinate along one axis: (int)(u / (L / nc)), clamped
+__device__ __forceinline__ int cell_coord(double u, double L, int nc) {
+  int c = (int)(u / (L / (double)nc));
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+inline int grid_for(int64_t n, int block = BLOCK) {
+  int64_t g = (n + block - 1) / block;
+  return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace vc
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct vcsgc_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int64_t n = 0;
+  double box[3] = {0, 0, 0};
+  double *x = nullptr, *y = nullptr, *z = nullptr;
+  double *vx = nullptr, *vy = nullptr, *vz = nullptr;
+  double *fx = nullptr, *fy = nullptr, *fz = nullptr;
+  uint8_t *sp = nullptr;
+  vc::PotD pot{};
+  double skin = 0.3, r_dep = 7.2;
+
+  // link cells (edge >= r_dep, even count per dimension)
+  int nc[3] = {0, 0, 0};
+  int64_t ncells = 0, S = 0;
+  int32_t *cell_count = nullptr, *cell_start = nullptr, *cell_atoms = nullptr,
+          *cell_fill = nullptr;
+
+  // r < rc list, column-major rows [k * n + i]: neighbour, (rc-r)^2, c0 + c1 r
+  int32_t *mc_j = nullptr;
+  double *mc_dd = nullptr, *mc_g = nullptr;
+  uint8_t *mc_cnt = nullptr;
+  // r < rc + skin list for MD, and positions at its build
+  int32_t *md_j = nullptr;
+  uint8_t *md_cnt = nullptr;
+  double *xr = nullptr, *yr = nullptr, *zr = nullptr;
+
+  double *rho = nullptr;                        // density cache of the sweep
+  double *rho_f = nullptr, *fp = nullptr;        // fresh density and F' (energy, MD)
+  double *eatom = nullptr, *red = nullptr;
+  int32_t *rec = nullptr;  // per active cell: locally accepted site or -1
+  vc::DevState *ds = nullptr;
+
+  bool mc_valid = false, md_valid = false;
+  uint64_t w = 0;  // sweep counter
+  int kmax_used = 0;
+
+  double *tlog = nullptr, *slog = nullptr;
+  int64_t tcap = 0, scap = 0;
+
+  std::string err;
+  bool sticky = false;
+};
+
+// internal host entry points implemented across the .hip files
+namespace vc {
+hipError_t launch_bin_cells(vcsgc_ctx *c);
+hipError_t launch_build_mc_list(vcsgc_ctx *c);
+hipError_t launch_build_md_list(vcsgc_ctx *c);
+hipError_t launch_density_mc(vcsgc_ctx *c);
+hipError_t launch_energy(vcsgc_ctx *c);  // fresh rho (MD list) + per-atom energies
+hipError_t launch_forces(vcsgc_ctx *c);  // fresh rho, F', forces (MD list)
+hipError_t launch_validate(vcsgc_ctx *c);
+hipError_t launch_reduce_sum(vcsgc_ctx *c, const double *v, int64_t n, double *out_dev);
+hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
+                         int64_t n_sweeps, uint64_t seed);
+hipError_t launch_kick_drift(vcsgc_ctx *c, double dt);
+hipError_t launch_kick(vcsgc_ctx *c, double dt);
+hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
+}  // namespace vc

@@ -1,0 +1,283 @@
+// Parallel VC-SGC sweep (Sec. III.B.2), one stage at a time:
+//   k_trial  : every cell of the stage's colour draws a site, computes the
+//              transmutation energy dU from the density cache and applies
+//              the local factor min{1, exp[-beta (dU + dmu0 dn)]}
+//              (Eq. trans_vcsgc_par1); the block sums of dn over local
+//              accepts go to a per-stage accumulator;
+//   k_commit : every thread evaluates the same global factor
+//              min{1, exp[-beta (kappa/N) dn_tot (dn_tot + 2 (n - N cbar))]}
+//              (Eq. trans_vcsgc_par2) and, if it passes, commits the flips of
+//              its cell: species, density cache rho_j += delta_j of every
+//              neighbour, and the velocity rescaling.
+// Cells of one colour are at least one cell edge (>= 2 rc) apart, so their
+// energy changes are independent and every rho_j has at most one writer per
+// stage.
+#include "common.hpp"
+
+namespace vc {
+
+struct SweepArgs {
+  int64_t n;
+  int n0, n1, n2;
+  int64_t ncpc;  // cells per colour
+  int64_t S;
+  double beta, dmu0, kN, ncbar;
+  uint64_t seed, replica;
+  PotD p;
+  const int32_t *cstart, *catoms;
+  const int32_t *nj;
+  const double *ndd, *ng;
+  const uint8_t *cnt;
+  uint8_t *sp;
+  double *rho;
+  double *vx, *vy, *vz;
+  int32_t *rec;
+  DevState *ds;
+  double *tlog;
+  int64_t tcap;
+  double *slog;
+  int64_t scap;
+};
+
+// dU of s_i -> 1 - s_i:
+//   (F_{s'}(rho_i) - F_s(rho_i)) + sum_j [(eps_{s's_j} dd) g - (eps_{s s_j} dd) g]
+//   + sum_j [F_{s_j}(rho_j + (t_{s'} dd - t_s dd)) - F_{s_j}(rho_j)]
+__device__ __forceinline__ double delta_u(const SweepArgs &a, int64_t i) {
+  const int s = a.sp[i], s1 = 1 - s;
+  const double ri = a.rho[i];
+  const double own = embed(a.p, s1, ri) - embed(a.p, s, ri);
+  const int m = a.cnt[i];
+  double pair = 0.0, emb = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const int64_t e = (int64_t)k * a.n + i;
+    const int32_t j = a.nj[e];
+    const int sj = a.sp[j];
+    const double dd = a.ndd[e], g = a.ng[e];
+    pair += a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
+  }
+  for (int k = 0; k < m; ++k) {
+    const int64_t e = (int64_t)k * a.n + i;
+    const int32_t j = a.nj[e];
+    const int sj = a.sp[j];
+    const double dd = a.ndd[e];
+    const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
+    const double rj = a.rho[j];
+    emb += embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
+  }
+  return own + pair + emb;
+}
+
+__device__ __forceinline__ int64_t colour_cell(const SweepArgs &a, int colour, int64_t t) {
+  const int hx = a.n0 >> 1, hy = a.n1 >> 1;
+  const int64_t ia = t % hx, ib = (t / hx) % hy, ic = t / ((int64_t)hx * hy);
+  const int64_t cx = 2 * ia + (colour & 1), cy = 2 * ib + ((colour >> 1) & 1),
+                cz = 2 * ic + ((colour >> 2) & 1);
+  return cx + (int64_t)a.n0 * (cy + (int64_t)a.n1 * cz);
+}
+
+__device__ __forceinline__ long long block_sum(long long v, long long *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if (t < h) sh[t] += sh[t + h];
+    __syncthreads();
+  }
+  const long long r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_init(DevState *ds) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ds->n_b[0] = ds->n_b_cur;
+    ds->dn[0] = 0;
+    ds->nrec[0] = 0;
+    ds->trials = ds->local_acc = ds->stages = ds->stage_acc = ds->flips = ds->near_ties = 0;
+    ds->sum_n = 0.0;
+    ds->sum_n2 = 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w, int64_t s, int par) {
+  __shared__ long long sh[BLOCK];
+  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+  const int colour = (int)(g.v[0] >> 61);
+  long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
+  if (t < a.ncpc) {
+    const int64_t cell = colour_cell(a, colour, t);
+    const int32_t st = a.cstart[cell];
+    const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
+    int32_t site = -1;
+    if (m > 0) {
+      const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
+      const int64_t i = a.catoms[st + draw_index(r.v[0], m)];
+      const double u = unit_open(r.v[1]);
+      const double du = delta_u(a, i);
+      const int dn = 1 - 2 * (int)a.sp[i];
+      const double xl = a.beta * (du + a.dmu0 * (double)dn);
+      const double lnu = log(u);
+      const double margin = lnu + xl;
+      const bool ok = lnu < -xl;
+      valid = 1;
+      tie = fabs(margin) < TIE;
+      if (ok) {
+        acc = 1;
+        dn_acc = dn;
+        site = (int32_t)i;
+      }
+      if (a.tlog) {
+        const unsigned long long idx = atomicAdd(&a.ds->tlog_n, 1ull);
+        if ((int64_t)idx < a.tcap) {
+          double *L = a.tlog + 8 * idx;
+          L[0] = (double)w;
+          L[1] = (double)s;
+          L[2] = (double)cell;
+          L[3] = (double)i;
+          L[4] = (double)dn;
+          L[5] = ok ? 1.0 : 0.0;
+          L[6] = du;
+          L[7] = margin;
+        }
+      }
+    }
+    a.rec[t] = site;
+  }
+  const long long bv = block_sum(valid, sh);
+  const long long ba = block_sum(acc, sh);
+  const long long bd = block_sum(dn_acc, sh);
+  const long long bt = block_sum(tie, sh);
+  if (threadIdx.x == 0) {
+    if (bv) atomicAdd(&a.ds->trials, (unsigned long long)bv);
+    if (ba) {
+      atomicAdd(&a.ds->local_acc, (unsigned long long)ba);
+      atomicAdd(&a.ds->nrec[par], (unsigned long long)ba);
+      atomicAdd((unsigned long long *)&a.ds->dn[par], (unsigned long long)bd);
+    }
+    if (bt) atomicAdd(&a.ds->near_ties, (unsigned long long)bt);
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64_t s, int par,
+                                                  int last) {
+  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const unsigned long long nrec = a.ds->nrec[par];
+  const long long dn_tot = a.ds->dn[par];
+  const long long nb = a.ds->n_b[par];
+  int gacc = -1;
+  double xg = 0.0, mg = 0.0;
+  if (nrec > 0) {
+    const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+    const double tt = (double)nb - a.ncbar;
+    const double dnd = (double)dn_tot;
+    xg = a.beta * a.kN * dnd * (dnd + 2.0 * tt);
+    const double lnug = log(unit_open(g.v[1]));
+    mg = lnug + xg;
+    gacc = lnug < -xg ? 1 : 0;
+  }
+  if (gacc == 1 && t < a.ncpc) {
+    const int32_t i = a.rec[t];
+    if (i >= 0) {
+      const int s0 = a.sp[i], s1 = 1 - s0;
+      const int m = a.cnt[i];
+      for (int k = 0; k < m; ++k) {
+        const int64_t e = (int64_t)k * a.n + i;
+        const int32_t j = a.nj[e];
+        const double dd = a.ndd[e];
+        const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
+        a.rho[j] = a.rho[j] + delta;
+      }
+      a.sp[i] = (uint8_t)s1;
+      if (a.vx) {
+        const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
+        a.vx[i] = a.vx[i] * f;
+        a.vy[i] = a.vy[i] * f;
+        a.vz[i] = a.vz[i] * f;
+      }
+    }
+  }
+  if (t == 0) {
+    const long long nb_new = nb + (gacc == 1 ? dn_tot : 0);
+    DevState *ds = a.ds;
+    ds->n_b[par ^ 1] = nb_new;
+    ds->n_b_cur = nb_new;
+    ds->dn[par ^ 1] = 0;
+    ds->nrec[par ^ 1] = 0;
+    ds->stages += 1;
+    if (gacc == 1) {
+      ds->stage_acc += 1;
+      ds->flips += nrec;
+    }
+    if (nrec > 0 && fabs(mg) < TIE) ds->near_ties += 1;
+    if (last) {
+      ds->sum_n += (double)nb_new;
+      ds->sum_n2 += (double)nb_new * (double)nb_new;
+    }
+    if (a.slog) {
+      const unsigned long long idx = ds->slog_n++;
+      if ((int64_t)idx < a.scap) {
+        double *L = a.slog + 8 * idx;
+        L[0] = (double)w;
+        L[1] = (double)s;
+        L[2] = (double)(int)(philox(a.seed, a.replica, w, (uint64_t)s, 0, 0).v[0] >> 61);
+        L[3] = (double)dn_tot;
+        L[4] = (double)nrec;
+        L[5] = (double)gacc;
+        L[6] = xg;
+        L[7] = mg;
+      }
+    }
+  }
+}
+
+hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
+                         int64_t n_sweeps, uint64_t seed) {
+  SweepArgs a;
+  a.n = c->n;
+  a.n0 = c->nc[0];
+  a.n1 = c->nc[1];
+  a.n2 = c->nc[2];
+  a.ncpc = c->ncells / 8;
+  a.S = c->S;
+  a.beta = 1.0 / (KB * T);
+  a.dmu0 = dmu0;
+  a.kN = kappa / (double)c->n;
+  a.ncbar = (double)c->n * cbar;
+  a.seed = seed;
+  a.replica = 0;
+  a.p = c->pot;
+  a.cstart = c->cell_start;
+  a.catoms = c->cell_atoms;
+  a.nj = c->mc_j;
+  a.ndd = c->mc_dd;
+  a.ng = c->mc_g;
+  a.cnt = c->mc_cnt;
+  a.sp = c->sp;
+  a.rho = c->rho;
+  a.vx = c->vx;
+  a.vy = c->vy;
+  a.vz = c->vz;
+  a.rec = c->rec;
+  a.ds = c->ds;
+  a.tlog = c->tlog;
+  a.tcap = c->tcap;
+  a.slog = c->slog;
+  a.scap = c->scap;
+  k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
+  const int gb = grid_for(a.ncpc);
+  int64_t q = 0;
+  for (int64_t sw = 0; sw < n_sweeps; ++sw) {
+    const uint64_t w = c->w + (uint64_t)sw;
+    for (int64_t s = 0; s < c->S; ++s, ++q) {
+      const int par = (int)(q & 1);
+      k_trial<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
+      k_commit<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par, s == c->S - 1);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vc

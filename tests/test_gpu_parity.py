@@ -1,0 +1,246 @@
+"""GPU (HIP, through the C ABI) against the oracle on identical seeded inputs.
+
+Bar: integer state (species, n_B, site choices, decisions, counters) bit
+for bit; FP64 dU within 1e-12 relative, forces within 1e-10 relative of the
+sum of term magnitudes, energies/densities/positions bit for bit where the
+arithmetic is the same (both sides evaluate the same expressions in the same
+order without contraction); decisions may differ only at near ties
+(|ln u + x| < 1e-9), where the oracle adopts the GPU's decision.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1012_5082_amd import inputs as I
+from paper_1012_5082_amd import workloads as W
+from parity_utils import compare_logs, gpu_context, oracle_state, tie_overrides
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_device_sqrt_correctly_rounded(torch_cuda):
+    torch = torch_cuda
+    from paper_1012_5082_amd.binding import selftest_sqrt
+    rng = np.random.default_rng(1)
+    bits = rng.integers(0, 0x7FEFFFFFFFFFFFFF, size=4_000_000, dtype=np.int64)
+    vals = np.concatenate([bits.view(np.float64),
+                           rng.uniform(0.0, 40.0, 2_000_000),
+                           rng.uniform(0.0, 1e-3, 500_000),
+                           np.array([0.0, 1.0, 2.0, 4.0, 13.134408449586, 5e-324, 1e300])])
+    x = torch.tensor(vals, dtype=torch.float64, device="cuda")
+    got = selftest_sqrt(x).cpu().numpy()
+    assert np.array_equal(got.view(np.int64), np.sqrt(vals).view(np.int64))
+
+
+def test_create_rejects_bad_input(torch_cuda):
+    from paper_1012_5082_amd.binding import VCSGC, VcsgcError
+    pot = I.params("FS-P1")
+    x, y, z, box = I.bcc(10, 10, 10)
+    sp = np.zeros(x.size, np.uint8)
+    xb = x.copy()
+    xb[5] = box[0] + 1.0
+    with pytest.raises(VcsgcError) as e:
+        VCSGC(xb, y, z, box, sp, pot)
+    assert e.value.code == -1
+    sp2 = sp.copy()
+    sp2[3] = 2
+    with pytest.raises(VcsgcError) as e:
+        VCSGC(x, y, z, box, sp2, pot)
+    assert e.value.code == -1
+    xs, ys, zs, bs = I.bcc(4, 4, 4)
+    with pytest.raises(VcsgcError) as e:
+        VCSGC(xs, ys, zs, bs, np.zeros(xs.size, np.uint8), pot)
+    assert e.value.code == -2
+    g = VCSGC(x, y, z, box, sp, pot)
+    with pytest.raises(VcsgcError) as e:
+        g.sweep(0.0, -1.0, 0.05, 600.0, 1, 1)
+    assert e.value.code == -1
+    with pytest.raises(VcsgcError):
+        g.md(1.0, 1)   # MC-only context
+    g.close()
+
+
+def _eam_parity(O, d, pot):
+    g = gpu_context(d, pot, forces=True)
+    st = oracle_state(O, d, pot)
+    rho_g = g.rho().cpu().numpy()
+    assert np.array_equal(rho_g, st.rho)
+    e_o = O.energy_atoms(st.nl, st.species, pot, st.rho)
+    e_g = g.atom_energies().cpu().numpy()
+    assert np.array_equal(e_g, e_o)
+    U = g.energy(forces=True)
+    assert abs(U - math.fsum(e_o)) <= 1e-12 * abs(U)
+    fo = O.forces(st.nl, st.species, pot, st.rho)
+    for a, b in zip((g.fx, g.fy, g.fz), fo):
+        a = a.cpu().numpy()
+        assert np.array_equal(a, b)
+    g.close()
+
+
+def test_eam_parity_c1_thermal(torch_cuda, oracle_mod):
+    d = W.c1(c_init=0.3)
+    d["x"], d["y"], d["z"] = I.thermalize(d["x"], d["y"], d["z"], d["box"], 0.05, 5)
+    _eam_parity(oracle_mod, d, I.params("FS-P1"))
+
+
+def test_eam_parity_c2(torch_cuda, oracle_mod):
+    _eam_parity(oracle_mod, W.c2(cbar=0.10), I.params("FS-P1"))
+
+
+def _sweep_parity(O, d, pot, n_sweeps, kappa=None, cbar=None, log=True, chunks=None):
+    kappa = d["kappa"] if kappa is None else kappa
+    cbar = d["cbar"] if cbar is None else cbar
+    args = (d["dmu0"], kappa, cbar, d["T"])
+    g = gpu_context(d, pot)
+    info = g.info()
+    S = info["stages_per_sweep"]
+    ncpc = int(np.prod(info["n_cells"])) // 8
+    st0 = oracle_state(O, d, pot)
+    if log:
+        g.enable_log(n_sweeps * S * ncpc, n_sweeps * S)
+    chunks = chunks or [n_sweeps]
+    gs = None
+    for k in chunks:
+        s = g.sweep(*args, k, d["seed"])
+        gs = s if gs is None else {key: gs[key] + s[key] if key not in ("n_final",) else s[key]
+                                   for key in s}
+    sp_g = g.species.cpu().numpy()
+    rho_g = g.rho().cpu().numpy()
+    res = {}
+    tl_g = sl_g = None
+    if log:
+        tl_g, sl_g, nt, ns = g.logs()
+        assert nt == tl_g.shape[0] and ns == sl_g.shape[0]
+    over = tie_overrides(tl_g, sl_g) if log else None
+    so, tl_o, sl_o = O.sweep(st0, *args, n_sweeps, d["seed"], log_trials=10 ** 8 if log else 0,
+                             log_stages=10 ** 8 if log else 0, overrides=over)
+    if log:
+        res = compare_logs(tl_g, sl_g, tl_o, sl_o)
+    for k in ("trials", "local_accepts", "stages", "stage_accepts", "flips", "n_final"):
+        assert gs[k] == so[k], (k, gs[k], so[k])
+    assert gs["sum_n"] == so["sum_n"] and gs["sum_n2"] == so["sum_n2"]
+    assert np.array_equal(sp_g, st0.species)
+    assert np.array_equal(rho_g, st0.rho)
+    g.close()
+    res.update(gs)
+    return res
+
+
+@pytest.mark.parametrize("kappa", [1000.0, 10.0, 0.0])
+def test_sweep_parity_c1(torch_cuda, oracle_mod, kappa):
+    d = W.c1()
+    r = _sweep_parity(oracle_mod, d, I.params("FS-P1"), 100, kappa=kappa)
+    assert r["trials"] == 100 * 2000
+    if kappa <= 10.0:
+        assert r["flips"] > 0
+
+
+@pytest.mark.parametrize("cbar", [0.02, 0.05, 0.10])
+def test_sweep_parity_c2(torch_cuda, oracle_mod, cbar):
+    d = W.c2(cbar=cbar)
+    r = _sweep_parity(oracle_mod, d, I.params("FS-P1"), 10)
+    assert r["flips"] > 0
+
+
+def test_sweep_chunking_and_determinism(torch_cuda, oracle_mod):
+    d = W.c2(cbar=0.05)
+    pot = I.params("FS-P1")
+    _sweep_parity(oracle_mod, d, pot, 6, log=False, chunks=[2, 1, 3])
+    a = gpu_context(d, pot)
+    b = gpu_context(d, pot)
+    a.sweep(d["dmu0"], d["kappa"], d["cbar"], d["T"], 5, 9)
+    b.sweep(d["dmu0"], d["kappa"], d["cbar"], d["T"], 5, 9)
+    assert np.array_equal(a.species.cpu().numpy(), b.species.cpu().numpy())
+    assert np.array_equal(a.rho().cpu().numpy(), b.rho().cpu().numpy())
+    a.close()
+    b.close()
+
+
+def _md_system(n=10, T=700.0, seed=31, c=0.05):
+    x, y, z, box = I.bcc(n, n, n)
+    x, y, z = I.thermalize(x, y, z, box, 0.05, seed)
+    sp = I.initial_species(x.size, c, seed + 1)
+    vx, vy, vz = I.mb_velocities(sp, T, seed + 2)
+    return dict(x=x, y=y, z=z, box=box, species=sp, vx=vx, vy=vy, vz=vz, T=T, kappa=1000.0,
+                cbar=c, dmu0=W.dmu_s(T, c), seed=4001)
+
+
+def test_md_parity(torch_cuda, oracle_mod):
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = _md_system()
+    g = gpu_context(d, pot, velocities=True)
+    g.md(1.0, 40)
+    out = O.md(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"], d["species"], d["box"], pot,
+               1.0, 40)
+    names = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz")
+    for nm, want in zip(names, out[:9]):
+        got = getattr(g, nm).cpu().numpy()
+        assert np.array_equal(got, want), nm
+    g.close()
+
+
+def test_hybrid_cycle_parity(torch_cuda, oracle_mod):
+    """[1 sweep; 20 MD steps] x 3 with velocity rescaling on transmutation."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = _md_system(n=16, c=0.1, seed=41)
+    g = gpu_context(d, pot, velocities=True)
+    x, y, z = d["x"], d["y"], d["z"]
+    vx, vy, vz = d["vx"], d["vy"], d["vz"]
+    sp = d["species"]
+    w = 0
+    for cyc in range(3):
+        g.sweep(d["dmu0"], 1.0, d["cbar"], d["T"], 1, d["seed"])
+        st = O.SweepState(x, y, z, d["box"], sp, pot, vx=vx, vy=vy, vz=vz)
+        st.w = w
+        O.sweep(st, d["dmu0"], 1.0, d["cbar"], d["T"], 1, d["seed"])
+        w += 1
+        sp = st.species
+        g.md(1.0, 20)
+        x, y, z, vx, vy, vz, *_ = O.md(x, y, z, st.vx, st.vy, st.vz, sp, d["box"], pot, 1.0, 20)
+    assert np.array_equal(g.species.cpu().numpy(), sp)
+    for nm, want in zip(("x", "y", "z", "vx", "vy", "vz"), (x, y, z, vx, vy, vz)):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), want), nm
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def c3_data():
+    return W.c3()
+
+
+def test_full_size_c3_sweep_and_md(torch_cuda, oracle_mod, c3_data):
+    """The 1.96M-site polycrystal: one full sweep (species and density cache
+    bit for bit, every counter equal) and two MD steps (positions and
+    velocities bit for bit)."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = c3_data
+    g = gpu_context(d, pot, velocities=True)
+    s = g.sweep(d["dmu0"], d["kappa"], d["cbar"], d["T"], 1, d["seed"])
+    st = oracle_state(O, d, pot, velocities=True)
+    so, _, _ = O.sweep(st, d["dmu0"], d["kappa"], d["cbar"], d["T"], 1, d["seed"])
+    for k in ("trials", "local_accepts", "stages", "stage_accepts", "flips", "n_final"):
+        assert s[k] == so[k], k
+    assert s["trials"] >= 0.9 * x_size(d)
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    g.md(1.0, 2)
+    out = O.md(d["x"], d["y"], d["z"], st.vx, st.vy, st.vz, st.species, d["box"], pot, 1.0, 2)
+    for nm, want in zip(("x", "y", "z", "vx", "vy", "vz"), out[:6]):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), want), nm
+    g.close()
+
+
+def x_size(d):
+    return d["x"].size
