@@ -1,0 +1,212 @@
+"""Benchmark: hybrid VC-SGC Monte Carlo / EAM MD on one MI355X.
+
+One step = one hybrid cycle of the 1.96M-site Voronoi polycrystal: one
+parallel VC-SGC sweep (N trials) followed by 20 velocity-Verlet steps
+(dt = 1 fs), the 1:20 interleaving of the paper's production run.
+
+Reported (one JSON line):
+  value               MC trials/s of the sweeps in the timed region
+                      (trials / summed sweep time, HIP events on the stream)
+  md_atom_steps_per_s MD atom-steps/s of the MD parts of the same cycles
+  ms_per_step         wall time per hybrid cycle
+  roofline            the kernel with the largest summed time: algorithmic
+                      bytes per launch / average launch duration (HIP events)
+  cpu_baseline        the oracle on host cores (one sweep of the same system)
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --copy-calib      (plain device copy, for counter scaling)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MC trials/s @2M atoms (plain vs surrogate-DA, same ⟨c⟩); MD atom-steps/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials):
+    """Compulsory HBM bytes of one launch (each array element counted once).
+
+    forces    : (x,y,z,F') packed (32) + species (1) + row length (1) + neighbour
+                indices (4 per r < rc + skin pair) + fx,fy,fz written (24)
+    density   : (x,y,z,species) packed (32) + species (1) + row length (1) +
+                indices (4 per pair) + rho, F' (16) and (x,y,z,F') (32) written
+    kick_drift: x,y,z,v,F,species,reference positions read (105), x,y,z,v and the
+                packed positions written (80)
+    kick      : v, F, species read (49), v written (24)
+    trial     : per trial, own species/rho/row length (10) + per r < rc pair the
+                index, (rc-r)^2, c0+c1 r (20) and the neighbour's species and rho
+                (9) + cell start/atom (8+4) + record (4)"""
+    if kind == "forces":
+        return 58 * n + 4 * pairs_md
+    if kind == "density":
+        return 82 * n + 4 * pairs_md
+    if kind == "kick_drift":
+        return 185 * n
+    if kind == "kick":
+        return 73 * n
+    if kind == "trial":
+        k = pairs_mc / n
+        return trials * (26 + 29 * k)
+    return None
+
+
+HAS_BYTES = ("forces", "density", "kick_drift", "kick", "trial")
+
+
+def copy_calib():
+    import torch
+    n = 1 << 27  # 128 Mi doubles = 1 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {n * 8} bytes 5 times")
+    print(json.dumps({"copy_bytes": n * 8, "launches": 5}))
+
+
+def cpu_baseline(d, pot):
+    """The oracle as it stands, timed on this host: one sweep of the same
+    system (the neighbour list is built first, untimed)."""
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    st = O.SweepState(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s, _, _ = O.sweep(st, d["dmu0"], d["kappa"], d["cbar"], d["T"], 1, d["seed"])
+    dt = time.perf_counter() - t0
+    return {"value": s["trials"] / dt, "unit": "trials/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 sweep ({s['trials']} trials) of the same {d['x'].size}-site system, "
+                      f"serial FP64 C oracle, {dt:.2f} s (neighbour list {setup:.1f} s untimed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(replicas and spatial shards would be distributed per GPU; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    if args.copy_calib:
+        copy_calib()
+        return
+
+    from paper_1012_5082_amd import inputs as I
+    from paper_1012_5082_amd import workloads as W
+    from paper_1012_5082_amd.binding import VCSGC
+
+    pot = I.params("FS-P1")
+    t0 = time.perf_counter()
+    d = W.c3()
+    n = d["x"].size
+    log(f"workload {d['name']}: {n} sites generated in {time.perf_counter() - t0:.1f} s")
+    g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
+              vz=d["vz"])
+    info = g.info()
+    sweep_args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
+    md_steps, dt = d["md_steps"], d["dt"]
+
+    for k in range(args.warmup):
+        g.sweep(*sweep_args, 1, d["seed"])
+        g.md(dt, md_steps)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} cycles done")
+
+    # kernel breakdown over one extra cycle (untimed for the headline numbers)
+    g.kernel_timing(["trial", "commit", "density", "forces", "kick_drift", "kick", "build"])
+    g.sweep(*sweep_args, 1, d["seed"])
+    g.md(dt, md_steps)
+    breakdown = g.kernel_times()
+    top = max(breakdown, key=lambda k: breakdown[k][0])
+    dominant = max((k for k in breakdown if k in HAS_BYTES), key=lambda k: breakdown[k][0])
+    log("breakdown (ms, launches): " + ", ".join(
+        f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(breakdown.items(), key=lambda t: -t[1][0])))
+
+    # timed region: K hybrid cycles; the dominant kernel class timed per launch
+    g.kernel_timing([dominant])
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    trials = 0
+    flips = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        s = g.sweep(*sweep_args, 1, d["seed"])
+        ev[k][1].record()
+        g.md(dt, md_steps)
+        ev[k][2].record()
+        trials += s["trials"]
+        flips += s["flips"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mc_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
+    md_ms = sum(b.elapsed_time(c) for _, b, c in ev)
+    kt = g.kernel_times()
+    tot_ms, launches = kt[dominant]
+    avg_s = tot_ms / launches / 1e3
+
+    info2 = g.info()
+    pairs_md = info2["md_pairs"]
+    pairs_mc = info["mc_pairs"]
+    per_launch_trials = trials / max(1, launches) if dominant == "trial" else 0
+    abytes = algorithmic_bytes(dominant, n, pairs_md, pairs_mc, per_launch_trials)
+    roof = None
+    if abytes:
+        ach = abytes / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_launch": int(abytes),
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches}
+
+    value = trials / (mc_ms / 1e3)
+    md_rate = n * md_steps * args.steps / (md_ms / 1e3)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "trials/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{d['name']}: {n}-site 16-grain bcc Voronoi polycrystal "
+                               f"(100^3-cell box), FS-P1 EAM, kappa=1000 eV, cbar=0.03, "
+                               f"T=700 K, step = 1 VC-SGC sweep + 20 MD steps (dt=1 fs)",
+                   "n_sites": n, "n_cells": info["n_cells"],
+                   "stages_per_sweep": info["stages_per_sweep"], "variant": "plain",
+                   "md_list_rebuilds": info2["md_rebuilds"]},
+        "md_atom_steps_per_s": round(md_rate, 1),
+        "mc_ms_per_sweep": round(mc_ms / args.steps, 3),
+        "md_ms_per_step": round(md_ms / args.steps / md_steps, 4),
+        "accepted_flips_per_s": round(flips / (mc_ms / 1e3), 1),
+        "kernel_breakdown_ms": {k: round(v[0], 4) for k, v in breakdown.items()},
+        "top_kernel": top,
+        "roofline": roof,
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        log("timing the oracle on host cores ...")
+        out["cpu_baseline"] = cpu_baseline(d, pot)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -89,6 +89,9 @@ typedef struct {
   int64_t stages_per_sweep; /* S = 8 ceil(N / N_cells) */
   int32_t kmax;         /* neighbour-list row capacity */
   int32_t mc_kmax_used; /* largest row of the r < rc list */
+  int64_t mc_pairs;     /* entries of the r < rc list (0 before it is built) */
+  int64_t md_pairs;     /* entries of the r < rc + skin list (0 before it is built) */
+  int64_t md_rebuilds;  /* MD neighbour-list rebuilds so far */
 } vcsgc_info;
 
 /* Create a context for one system.  Validates the arguments and the input
@@ -139,8 +142,9 @@ vcsgc_status eam_energy_forces(vcsgc_ctx *ctx, double *energy_eV, int want_force
  * positions first; per step: v += dt/2 a, x += dt v (wrapped), forces,
  * v += dt/2 a, with a = F * 9.648533212e-3 / m.  The r < rc + skin list is
  * rebuilt whenever an atom has moved more than skin/2 since the last build.
- * Requires velocities and forces in the system.  On return the density cache
- * matches the final positions. */
+ * Requires velocities and forces in the system.  The sweep's cell lists,
+ * r < rc list and density cache are rebuilt from the new positions before the
+ * next sweep. */
 vcsgc_status md_verlet_step(vcsgc_ctx *ctx, double dt_fs, int64_t n_steps);
 
 /* Message of the last error on this context (or of the last failed create when
@@ -169,6 +173,29 @@ vcsgc_status vcsgc_copy_rho(vcsgc_ctx *ctx, double *rho_dev);
 vcsgc_status vcsgc_atom_energies(vcsgc_ctx *ctx, double *e_dev);
 /* Geometry of the context. */
 vcsgc_status vcsgc_get_info(vcsgc_ctx *ctx, vcsgc_info *out);
+
+/* Kernel classes for per-kernel timing. */
+#define VCSGC_KT_TRIAL 0      /* sweep: trial + local factor */
+#define VCSGC_KT_COMMIT 1     /* sweep: global factor + commit */
+#define VCSGC_KT_DENSITY 2    /* EAM density + embedding derivative */
+#define VCSGC_KT_FORCES 3     /* EAM forces */
+#define VCSGC_KT_KICKDRIFT 4  /* velocity Verlet first half + drift */
+#define VCSGC_KT_KICK 5       /* velocity Verlet second half */
+#define VCSGC_KT_BUILD 6      /* cell binning + neighbour list */
+#define VCSGC_KT_ENERGY 7     /* per-atom energies */
+#define VCSGC_KT_CLASSES 8
+
+typedef struct {
+  double total_ms[VCSGC_KT_CLASSES]; /* summed event-to-event durations */
+  int64_t count[VCSGC_KT_CLASSES];   /* timed launches */
+} vcsgc_ktimes;
+
+/* Time every launch of the kernel classes in mask (bit k = class k) with a
+ * pair of HIP events recorded on the context's stream around the launch;
+ * resets the accumulated times.  mask = 0 disables timing. */
+vcsgc_status vcsgc_kernel_timing(vcsgc_ctx *ctx, uint32_t mask);
+/* Accumulated times since the last vcsgc_kernel_timing call (synchronizes). */
+vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *ctx, vcsgc_ktimes *out);
 
 /* Diagnostics: out[i] = sqrt(in[i]) in FP64 on the device, n >= 0. */
 vcsgc_status vcsgc_selftest_sqrt(const double *in_dev, double *out_dev, int64_t n,

@@ -100,10 +100,13 @@ static void nbuf_push(nbuf *b, nent v) {
   b->e[b->n++] = v;
 }
 
-/* Separation r = sqrt((dx^2 + dy^2) + dz^2); a pair is a neighbour iff r < cutoff. */
+/* Separation r = sqrt((dx^2 + dy^2) + dz^2); a pair is a neighbour iff r < cutoff.
+ * (The squared test only skips pairs that are certainly farther away.) */
 static int or_try_pair(nbuf *row, int32_t j, int32_t code, double dx, double dy, double dz,
                        double cutoff) {
-  double r = sqrt((dx * dx + dy * dy) + dz * dz);
+  double r2 = (dx * dx + dy * dy) + dz * dz;
+  if (r2 > 1.000001 * cutoff * cutoff) return 0;
+  double r = sqrt(r2);
   if (r < cutoff) {
     nent v = {j, code, r, dx, dy, dz};
     nbuf_push(row, v);
@@ -191,7 +194,16 @@ int64_t or_neighbors(int64_t n, const double *x, const double *y, const double *
             }
           }
     }
-    qsort(row.e, (size_t)row.n, sizeof(nent), cmp_nent);
+    /* ascending (j, image) by insertion sort */
+    for (int64_t a = 1; a < row.n; ++a) {
+      nent v = row.e[a];
+      int64_t b = a - 1;
+      while (b >= 0 && cmp_nent(&row.e[b], &v) > 0) {
+        row.e[b + 1] = row.e[b];
+        --b;
+      }
+      row.e[b + 1] = v;
+    }
     if (start) start[i] = total;
     for (int64_t k = 0; k < row.n; ++k, ++total) {
       if (total < cap) {

@@ -120,21 +120,23 @@ class NeighborList:
         return self.j[self.start[i]:self.start[i + 1]]
 
 
-def neighbors(x, y, z, box, cutoff, mode: int = 0) -> NeighborList:
+def neighbors(x, y, z, box, cutoff, mode: int = 0, vectors: bool = True) -> NeighborList:
+    """All pairs with r < cutoff; separation vectors only if vectors=True."""
     x, y, z, box = _f64(x), _f64(y), _f64(z), _f64(box)
     n = x.size
-    cap = 24 * n + 64
+    cap = 16 * n + 64
     while True:
-        start = np.zeros(n + 1, dtype=np.int64)
-        j = np.zeros(cap, dtype=np.int32)
-        r, dx, dy, dz = (np.zeros(cap) for _ in range(4))
+        start = np.empty(n + 1, dtype=np.int64)
+        j = np.empty(cap, dtype=np.int32)
+        r = np.empty(cap)
+        dx, dy, dz = ((np.empty(cap) for _ in range(3)) if vectors else (None, None, None))
         tot = lib().or_neighbors(n, _p(x), _p(y), _p(z), _p(box), float(cutoff), int(mode), cap,
                                  _p(start), _p(j), _p(r), _p(dx), _p(dy), _p(dz))
         if tot < 0:
             raise ValueError("box too small for the requested neighbour mode")
         if tot <= cap:
-            return NeighborList(start, j[:tot].copy(), r[:tot].copy(), dx[:tot].copy(),
-                                dy[:tot].copy(), dz[:tot].copy())
+            cut = (lambda a: None if a is None else a[:tot])  # noqa: E731
+            return NeighborList(start, j[:tot], r[:tot], cut(dx), cut(dy), cut(dz))
         cap = int(tot)
 
 
@@ -163,6 +165,8 @@ def energy_total(e) -> float:
 
 
 def forces(nl: NeighborList, species, pot, rho=None):
+    if nl.dx is None:
+        raise ValueError("forces need a neighbour list built with vectors=True")
     sp = np.ascontiguousarray(species, dtype=np.uint8)
     if rho is None:
         rho = density(nl, sp, pot)
@@ -196,7 +200,8 @@ class SweepState:
         self.x, self.y, self.z, self.box = _f64(x), _f64(y), _f64(z), _f64(box)
         self.pot = pot
         self.species = np.array(species, dtype=np.uint8)
-        self.nl = nl if nl is not None else neighbors(self.x, self.y, self.z, self.box, pot.rc)
+        self.nl = nl if nl is not None else neighbors(self.x, self.y, self.z, self.box, pot.rc,
+                                                      vectors=False)
         self.rho = density(self.nl, self.species, pot)
         self.n_b = np.array([int(self.species.sum())], dtype=np.int64)
         self.w = 0

@@ -54,7 +54,15 @@ class State(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("n_cells", C.c_int32 * 3), ("stages_per_sweep", C.c_int64), ("kmax", C.c_int32),
-                ("mc_kmax_used", C.c_int32)]
+                ("mc_kmax_used", C.c_int32), ("mc_pairs", C.c_int64), ("md_pairs", C.c_int64),
+                ("md_rebuilds", C.c_int64)]
+
+
+KT_NAMES = ["trial", "commit", "density", "forces", "kick_drift", "kick", "build", "energy"]
+
+
+class KTimes(C.Structure):
+    _fields_ = [("total_ms", C.c_double * 8), ("count", C.c_int64 * 8)]
 
 
 _lib = None
@@ -97,6 +105,10 @@ def lib():
         L.vcsgc_atom_energies.argtypes = [_P, _P]
         L.vcsgc_get_info.restype = st
         L.vcsgc_get_info.argtypes = [_P, C.POINTER(Info)]
+        L.vcsgc_kernel_timing.restype = st
+        L.vcsgc_kernel_timing.argtypes = [_P, C.c_uint32]
+        L.vcsgc_get_kernel_timing.restype = st
+        L.vcsgc_get_kernel_timing.argtypes = [_P, C.POINTER(KTimes)]
         L.vcsgc_selftest_sqrt.restype = st
         L.vcsgc_selftest_sqrt.argtypes = [_P, _P, C.c_int64, _P]
         _lib = L
@@ -263,8 +275,22 @@ class VCSGC:
         torch.cuda.synchronize()
         return out
 
+    def kernel_timing(self, names):
+        """Time every launch of the named kernel classes with HIP events (resets)."""
+        mask = 0
+        for nm in names:
+            mask |= 1 << KT_NAMES.index(nm)
+        self._check(lib().vcsgc_kernel_timing(self._h, mask), "kernel_timing")
+
+    def kernel_times(self):
+        """{class: (total_ms, launches)} accumulated since kernel_timing()."""
+        k = KTimes()
+        self._check(lib().vcsgc_get_kernel_timing(self._h, C.byref(k)), "get_kernel_timing")
+        return {nm: (k.total_ms[i], k.count[i]) for i, nm in enumerate(KT_NAMES) if k.count[i]}
+
     def info(self):
         i = Info()
         self._check(lib().vcsgc_get_info(self._h, C.byref(i)), "info")
         return {"n_cells": list(i.n_cells), "stages_per_sweep": i.stages_per_sweep,
-                "kmax": i.kmax, "mc_kmax_used": i.mc_kmax_used}
+                "kmax": i.kmax, "mc_kmax_used": i.mc_kmax_used, "mc_pairs": i.mc_pairs,
+                "md_pairs": i.md_pairs, "md_rebuilds": i.md_rebuilds}

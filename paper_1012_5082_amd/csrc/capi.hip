@@ -19,10 +19,11 @@ hipError_t dalloc(T **p, size_t count) {
 }
 
 void free_all(vcsgc_ctx *c) {
-  void *ptrs[] = {c->cell_count, c->cell_start, c->cell_atoms, c->cell_fill, c->mc_j, c->mc_dd,
+  void *ptrs[] = {c->bin_count,  c->bin_atoms,  c->cell_count, c->cell_start, c->cell_atoms,
+                  c->cell_fill,  c->mc_j,       c->mc_dd,
                   c->mc_g,       c->mc_cnt,     c->md_j,       c->md_cnt,    c->xr,   c->yr,
                   c->zr,         c->rho,        c->rho_f,      c->fp,        c->eatom, c->red,
-                  c->rec,        c->ds};
+                  c->rec,        c->ds,         c->ps4,        c->pf4,       c->part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -71,31 +72,62 @@ vc::DevState read_state(vcsgc_ctx *c, hipError_t *e) {
   return h;
 }
 
-// Rebuild cells + the r < rc list + the density cache; checks row overflow.
-vcsgc_status refresh_mc(vcsgc_ctx *c) {
-  VC_CHECK(c, vc::launch_bin_cells(c), "binning");
-  VC_CHECK(c, vc::launch_build_mc_list(c), "neighbour list");
-  VC_CHECK(c, vc::launch_density_mc(c), "density");
-  hipError_t e;
-  vc::DevState h = read_state(c, &e);
-  if (e != hipSuccess) return dev_fail(c, e, "neighbour list");
-  if (h.overflow)
-    return fail(c, VCSGC_E_OVERFLOW, "a site has more than 32 neighbours within rc");
-  c->kmax_used = h.kmax_used;
-  c->mc_valid = true;
+// Grow the search bins after an overflow (capacity doubles).
+vcsgc_status grow_bins(vcsgc_ctx *c) {
+  if (c->bmax >= 1024) return fail(c, VCSGC_E_OVERFLOW, "more than 1024 atoms in a search bin");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  (void)hipFree(c->bin_atoms);
+  c->bin_atoms = nullptr;
+  c->bmax *= 2;
+  VC_CHECK(c, dalloc(&c->bin_atoms, (size_t)c->nbins * c->bmax), "allocation");
+  int zero = 0;
+  VC_CHECK(c, hipMemcpyAsync(&c->ds->bin_overflow, &zero, sizeof(int), hipMemcpyHostToDevice,
+                             c->stream),
+           "reset");
   return VCSGC_OK;
 }
 
-vcsgc_status refresh_md(vcsgc_ctx *c, bool rebin) {
-  if (rebin) VC_CHECK(c, vc::launch_bin_cells(c), "binning");
-  VC_CHECK(c, vc::launch_build_md_list(c), "neighbour list (MD)");
-  hipError_t e;
-  vc::DevState h = read_state(c, &e);
-  if (e != hipSuccess) return dev_fail(c, e, "neighbour list (MD)");
-  if (h.overflow)
-    return fail(c, VCSGC_E_OVERFLOW, "a site has more than 32 neighbours within rc + skin");
-  c->md_valid = true;
-  return VCSGC_OK;
+// Rebuild cells + the r < rc list + the density cache; checks row overflow.
+vcsgc_status refresh_mc(vcsgc_ctx *c) {
+  for (;;) {
+    VC_CHECK(c, vc::launch_bin_cells(c), "binning");
+    VC_CHECK(c, vc::launch_bin_search(c), "binning");
+    VC_CHECK(c, vc::launch_build_mc_list(c), "neighbour list");
+    VC_CHECK(c, vc::launch_density_mc(c), "density");
+    hipError_t e;
+    vc::DevState h = read_state(c, &e);
+    if (e != hipSuccess) return dev_fail(c, e, "neighbour list");
+    if (h.bin_overflow) {
+      vcsgc_status st = grow_bins(c);
+      if (st) return st;
+      continue;
+    }
+    if (h.overflow)
+      return fail(c, VCSGC_E_OVERFLOW, "a site has more than 32 neighbours within rc");
+    c->kmax_used = h.kmax_used;
+    c->mc_valid = true;
+    return VCSGC_OK;
+  }
+}
+
+vcsgc_status refresh_md(vcsgc_ctx *c) {
+  for (;;) {
+    VC_CHECK(c, vc::launch_bin_search(c), "binning");
+    VC_CHECK(c, vc::launch_build_md_list(c), "neighbour list (MD)");
+    hipError_t e;
+    vc::DevState h = read_state(c, &e);
+    if (e != hipSuccess) return dev_fail(c, e, "neighbour list (MD)");
+    if (h.bin_overflow) {
+      vcsgc_status st = grow_bins(c);
+      if (st) return st;
+      continue;
+    }
+    if (h.overflow)
+      return fail(c, VCSGC_E_OVERFLOW, "a site has more than 32 neighbours within rc + skin");
+    c->md_valid = true;
+    c->md_rebuilds += 1;
+    return VCSGC_OK;
+  }
 }
 
 vcsgc_status check_ctx(vcsgc_ctx *c) {
@@ -107,7 +139,82 @@ vcsgc_status check_ctx(vcsgc_ctx *c) {
 
 }  // namespace
 
+namespace vc {
+
+int tstart(vcsgc_ctx *c, int cls) {
+  if (!(c->tmask & (1u << cls))) return -1;
+  hipEvent_t ev[2];
+  for (int k = 0; k < 2; ++k) {
+    if (!c->ev_pool.empty()) {
+      ev[k] = c->ev_pool.back();
+      c->ev_pool.pop_back();
+    } else if (hipEventCreate(&ev[k]) != hipSuccess) {
+      if (k == 1) c->ev_pool.push_back(ev[0]);
+      return -1;
+    }
+  }
+  if (hipEventRecord(ev[0], c->stream) != hipSuccess) {
+    c->ev_pool.push_back(ev[0]);
+    c->ev_pool.push_back(ev[1]);
+    return -1;
+  }
+  c->ev_pending.push_back({cls, ev[0], ev[1]});
+  return (int)c->ev_pending.size() - 1;
+}
+
+void tstop(vcsgc_ctx *c, int h) {
+  if (h < 0) return;
+  (void)hipEventRecord(c->ev_pending[h].b, c->stream);
+}
+
+}  // namespace vc
+
+namespace {
+
+// fold pending event pairs into the per-class totals (synchronizes)
+hipError_t drain_timers(vcsgc_ctx *c) {
+  if (c->ev_pending.empty()) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  for (auto &p : c->ev_pending) {
+    float ms = 0.f;
+    if (e == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->kt_ms[p.cls] += ms;
+      c->kt_n[p.cls] += 1;
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->ev_pending.clear();
+  return e;
+}
+
+}  // namespace
+
 extern "C" {
+
+vcsgc_status vcsgc_kernel_timing(vcsgc_ctx *c, uint32_t mask) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  VC_CHECK(c, drain_timers(c), "timing");
+  c->tmask = mask & ((1u << VCSGC_KT_CLASSES) - 1);
+  for (int k = 0; k < VCSGC_KT_CLASSES; ++k) {
+    c->kt_ms[k] = 0.0;
+    c->kt_n[k] = 0;
+  }
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *c, vcsgc_ktimes *out) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (!out) return fail(c, VCSGC_E_INVALID_ARG, "null output");
+  VC_CHECK(c, drain_timers(c), "timing");
+  for (int k = 0; k < VCSGC_KT_CLASSES; ++k) {
+    out->total_ms[k] = c->kt_ms[k];
+    out->count[k] = c->kt_n[k];
+  }
+  return VCSGC_OK;
+}
 
 vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx **out) {
   if (!sys || !out) return fail(nullptr, VCSGC_E_INVALID_ARG, "null argument");
@@ -182,12 +289,17 @@ vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx
   p.cm[1] = P.mass_b > 0.0 ? vc::ACC / P.mass_b : 0.0;
   c->ncells = (int64_t)nc[0] * nc[1] * nc[2];
   c->S = 8 * ((c->n + c->ncells - 1) / c->ncells);
+  for (int d = 0; d < 3; ++d) c->nb[d] = (int)std::floor(sys->box[d] / (P.rc + sys->skin));
+  c->nbins = (int64_t)c->nb[0] * c->nb[1] * c->nb[2];
+  c->bmax = 16;
 
   const int64_t n = c->n, K = vc::KMAX;
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t r) {
     if (e == hipSuccess) e = r;
   };
+  A(dalloc(&c->bin_count, c->nbins));
+  A(dalloc(&c->bin_atoms, c->nbins * c->bmax));
   A(dalloc(&c->cell_count, c->ncells));
   A(dalloc(&c->cell_start, c->ncells + 1));
   A(dalloc(&c->cell_fill, c->ncells));
@@ -201,12 +313,16 @@ vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx
   A(dalloc(&c->xr, n));
   A(dalloc(&c->yr, n));
   A(dalloc(&c->zr, n));
+  A(dalloc(&c->ps4, n));
+  A(dalloc(&c->pf4, n));
   A(dalloc(&c->rho, n));
   A(dalloc(&c->rho_f, n));
   A(dalloc(&c->fp, n));
   A(dalloc(&c->eatom, n));
   A(dalloc(&c->red, (n + vc::BLOCK - 1) / vc::BLOCK + 8));
   A(dalloc(&c->rec, c->ncells / 8));
+  c->npart = (c->ncells / 8 * 16 + vc::BLOCK - 1) / vc::BLOCK;
+  A(dalloc(&c->part, 4 * c->npart));
   A(dalloc(&c->ds, 1));
   if (e != hipSuccess) {
     free_all(c);
@@ -245,6 +361,11 @@ vcsgc_status vcsgc_destroy(vcsgc_ctx *c) {
   if (!c) return VCSGC_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  for (auto &p : c->ev_pending) {
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
   free_all(c);
   delete c;
   return VCSGC_OK;
@@ -291,9 +412,10 @@ vcsgc_status eam_energy_forces(vcsgc_ctx *c, double *energy_eV, int want_forces)
   if (want_forces && !c->fx)
     return fail(c, VCSGC_E_INVALID_ARG, "forces requested but the system has no force arrays");
   if (!c->md_valid) {
-    st = refresh_md(c, true);
+    st = refresh_md(c);
     if (st) return st;
   }
+  VC_CHECK(c, vc::launch_pack(c), "pack");
   VC_CHECK(c, vc::launch_energy(c), "energy");
   if (want_forces) VC_CHECK(c, vc::launch_forces(c), "forces");
   if (energy_eV) {
@@ -317,12 +439,14 @@ vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
   if (!is_fin(dt_fs) || !(dt_fs > 0.0) || n_steps < 0)
     return fail(c, VCSGC_E_INVALID_ARG, "need dt > 0 and n_steps >= 0");
   if (!c->md_valid) {
-    st = refresh_md(c, true);
+    st = refresh_md(c);
     if (st) return st;
   }
+  VC_CHECK(c, vc::launch_pack(c), "pack");
   VC_CHECK(c, vc::launch_forces(c), "forces");
   for (int64_t k = 0; k < n_steps; ++k) {
-    VC_CHECK(c, vc::launch_kick_drift(c, dt_fs), "kick-drift");
+    // the closing half-kick of step k-1 is fused into the opening one of step k
+    VC_CHECK(c, vc::launch_kick_drift(c, dt_fs, k > 0), "kick-drift");
     int flag = 0;
     VC_CHECK(c, hipMemcpyAsync(&flag, &c->ds->rebuild, sizeof(int), hipMemcpyDeviceToHost,
                                c->stream),
@@ -331,12 +455,12 @@ vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
     c->mc_valid = false;
     if (flag) {
       VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild, 0, sizeof(int), c->stream), "reset");
-      st = refresh_md(c, true);
+      st = refresh_md(c);
       if (st) return st;
     }
     VC_CHECK(c, vc::launch_forces(c), "forces");
-    VC_CHECK(c, vc::launch_kick(c, dt_fs), "kick");
   }
+  if (n_steps > 0) VC_CHECK(c, vc::launch_kick(c, dt_fs), "kick");
   return VCSGC_OK;
 }
 
@@ -415,9 +539,10 @@ vcsgc_status vcsgc_atom_energies(vcsgc_ctx *c, double *e_dev) {
   if (st) return st;
   if (!e_dev) return fail(c, VCSGC_E_INVALID_ARG, "null output");
   if (!c->md_valid) {
-    st = refresh_md(c, true);
+    st = refresh_md(c);
     if (st) return st;
   }
+  VC_CHECK(c, vc::launch_pack(c), "pack");
   VC_CHECK(c, vc::launch_energy(c), "energy");
   VC_CHECK(c, hipMemcpyAsync(e_dev, c->eatom, sizeof(double) * c->n, hipMemcpyDeviceToDevice,
                              c->stream),
@@ -433,6 +558,12 @@ vcsgc_status vcsgc_get_info(vcsgc_ctx *c, vcsgc_info *out) {
   out->stages_per_sweep = c->S;
   out->kmax = vc::KMAX;
   out->mc_kmax_used = c->kmax_used;
+  hipError_t e;
+  vc::DevState h = read_state(c, &e);
+  if (e != hipSuccess) return dev_fail(c, e, "info");
+  out->mc_pairs = c->mc_valid ? (int64_t)h.pairs_mc : 0;
+  out->md_pairs = c->md_valid ? (int64_t)h.pairs_md : 0;
+  out->md_rebuilds = c->md_rebuilds;
   return VCSGC_OK;
 }
 

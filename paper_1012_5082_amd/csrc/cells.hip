@@ -112,102 +112,182 @@ hipError_t launch_bin_cells(vcsgc_ctx *c) {
 }
 
 // ----------------------------------------------------------------------------
-// neighbour lists from the cells.  Every pair with r < cutoff, r from the
-// minimum-image separation as sqrt((dx^2 + dy^2) + dz^2), rows sorted by
+// search bins: edge >= rc + skin, at most bmax atoms each (overflow flagged)
+// ----------------------------------------------------------------------------
+__global__ void k_bin_search(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                             const double *__restrict__ z, Grid g, int bmax, int32_t *count,
+                             int32_t *atoms, DevState *ds) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = cell_of(g, x[i], y[i], z[i]);
+  const int slot = atomicAdd(&count[b], 1);
+  if (slot < bmax)
+    atoms[(int64_t)b * bmax + slot] = (int32_t)i;
+  else
+    atomicOr(&ds->bin_overflow, 1);
+}
+
+hipError_t launch_bin_search(vcsgc_ctx *c) {
+  Grid g{c->box[0], c->box[1], c->box[2], c->nb[0], c->nb[1], c->nb[2]};
+  hipError_t e = hipMemsetAsync(c->bin_count, 0, sizeof(int32_t) * c->nbins, c->stream);
+  if (e != hipSuccess) return e;
+  k_bin_search<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, g, c->bmax,
+                                                        c->bin_count, c->bin_atoms, c->ds);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// neighbour lists from the search bins.  Every pair with r < cutoff, r from
+// the minimum-image separation as sqrt((dx^2 + dy^2) + dz^2), rows sorted by
 // neighbour index.  Column-major rows: entry k of atom i at [k * n + i].
 // MC rows additionally store dd = (rc - r)^2 and g = c0 + c1 r.
 // ----------------------------------------------------------------------------
+__device__ __forceinline__ double pair_r(const double *__restrict__ x,
+                                         const double *__restrict__ y,
+                                         const double *__restrict__ z, const Grid &g, double xi,
+                                         double yi, double zi, int32_t j) {
+  const double dx = min_image(x[j] - xi, g.L0);
+  const double dy = min_image(y[j] - yi, g.L1);
+  const double dz = min_image(z[j] - zi, g.L2);
+  return sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
+// One group of BG lanes per atom; lane L walks the L-th of the 27 (or fewer,
+// with two bins along an axis) surrounding search bins.  Hits are appended to
+// an LDS row through an LDS counter (arbitrary order), then every hit is
+// stored at its rank among the row's neighbour indices, so rows come out
+// sorted and independent of the append order.
+// MC rows are row-major ([i * KMAX + k]) for the group-per-trial sweep;
+// MD rows are column-major ([k * n + i]) for the thread-per-atom kernels.
+constexpr int BG = 32;
+
 template <bool MC>
-__global__ void k_build(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                        const double *__restrict__ z, Grid g,
-                        const int32_t *__restrict__ cstart, const int32_t *__restrict__ catoms,
-                        double cutoff, PotD p, int32_t *nj, double *ndd, double *ng,
-                        uint8_t *cnt, double *xr, double *yr, double *zr, DevState *ds) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double xi = x[i], yi = y[i], zi = z[i];
-  const int cx = cell_coord(xi, g.L0, g.n0), cy = cell_coord(yi, g.L1, g.n1),
-            cz = cell_coord(zi, g.L2, g.n2);
-  // distinct neighbouring cells per axis (two cells per axis: both, once)
-  const int lo0 = g.n0 >= 3 ? -1 : 0, lo1 = g.n1 >= 3 ? -1 : 0, lo2 = g.n2 >= 3 ? -1 : 0;
-  const int hi0 = g.n0 >= 2 ? 1 : 0, hi1 = g.n1 >= 2 ? 1 : 0, hi2 = g.n2 >= 2 ? 1 : 0;
-  int count = 0;
-  for (int oz = lo2; oz <= hi2; ++oz) {
-    const int zz = (cz + oz + g.n2) % g.n2;
-    for (int oy = lo1; oy <= hi1; ++oy) {
-      const int yy = (cy + oy + g.n1) % g.n1;
-      for (int ox = lo0; ox <= hi0; ++ox) {
-        const int xx = (cx + ox + g.n0) % g.n0;
-        const int cc = xx + g.n0 * (yy + g.n1 * zz);
-        for (int32_t k = cstart[cc]; k < cstart[cc + 1]; ++k) {
-          const int32_t j = catoms[k];
-          if (j == i) continue;
-          const double dx = min_image(x[j] - xi, g.L0);
-          const double dy = min_image(y[j] - yi, g.L1);
-          const double dz = min_image(z[j] - zi, g.L2);
-          const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-          if (r < cutoff) {
-            if (count < KMAX) {
-              nj[(int64_t)count * n + i] = j;
-              if (MC) ndd[(int64_t)count * n + i] = r;
-            }
-            ++count;
-          }
+__global__ void __launch_bounds__(BLOCK)
+    k_build(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+            const double *__restrict__ z, Grid g, const int32_t *__restrict__ bcount,
+            const int32_t *__restrict__ batoms, int bmax, double cutoff, PotD p, int32_t *nj,
+            double *ndd, double *ng, uint8_t *cnt, double *xr, double *yr, double *zr,
+            DevState *ds) {
+  __shared__ int32_t rowbuf[BLOCK / BG][KMAX];
+  __shared__ int rowcount[BLOCK / BG];
+  const int lane = threadIdx.x % BG, grp = threadIdx.x / BG;
+  const int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / BG;
+  const bool live = i < n;
+  if (lane == 0) rowcount[grp] = 0;
+  __syncthreads();
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (live) {
+    xi = x[i];
+    yi = y[i];
+    zi = z[i];
+    const int n0 = g.n0 >= 3 ? 3 : 2, n1 = g.n1 >= 3 ? 3 : 2, n2 = g.n2 >= 3 ? 3 : 2;
+    if (lane < n0 * n1 * n2) {
+      const int ox = (g.n0 >= 3 ? -1 : 0) + lane % n0;
+      const int oy = (g.n1 >= 3 ? -1 : 0) + (lane / n0) % n1;
+      const int oz = (g.n2 >= 3 ? -1 : 0) + lane / (n0 * n1);
+      const int xx = (cell_coord(xi, g.L0, g.n0) + ox + g.n0) % g.n0;
+      const int yy = (cell_coord(yi, g.L1, g.n1) + oy + g.n1) % g.n1;
+      const int zz = (cell_coord(zi, g.L2, g.n2) + oz + g.n2) % g.n2;
+      const int64_t bb = xx + (int64_t)g.n0 * (yy + (int64_t)g.n1 * zz);
+      int m = bcount[bb];
+      m = m < bmax ? m : bmax;
+      for (int k = 0; k < m; ++k) {
+        const int32_t j = batoms[bb * bmax + k];
+        if (j != i && pair_r(x, y, z, g, xi, yi, zi, j) < cutoff) {
+          const int pos = atomicAdd(&rowcount[grp], 1);
+          if (pos < KMAX) rowbuf[grp][pos] = j;
         }
       }
     }
   }
-  if (count > KMAX) {
-    atomicOr(&ds->overflow, 1);
-    count = KMAX;
-  }
-  atomicMax(&ds->kmax_used, count);
-  // insertion sort of the row by neighbour index (r travels along for MC)
-  for (int a = 1; a < count; ++a) {
-    const int32_t v = nj[(int64_t)a * n + i];
-    const double rv = MC ? ndd[(int64_t)a * n + i] : 0.0;
-    int b = a - 1;
-    while (b >= 0 && nj[(int64_t)b * n + i] > v) {
-      nj[(int64_t)(b + 1) * n + i] = nj[(int64_t)b * n + i];
-      if (MC) ndd[(int64_t)(b + 1) * n + i] = ndd[(int64_t)b * n + i];
-      --b;
+  __syncthreads();
+  if (live) {
+    int count = rowcount[grp];
+    if (count > KMAX) {
+      if (lane == 0) atomicOr(&ds->overflow, 1);
+      count = KMAX;
     }
-    nj[(int64_t)(b + 1) * n + i] = v;
-    if (MC) ndd[(int64_t)(b + 1) * n + i] = rv;
-  }
-  if (MC) {
-    for (int a = 0; a < count; ++a) {
-      const double r = ndd[(int64_t)a * n + i];
-      const double d = p.rc - r;
-      ndd[(int64_t)a * n + i] = d * d;
-      ng[(int64_t)a * n + i] = p.c0 + p.c1 * r;
+    if (lane == 0) cnt[i] = (uint8_t)count;
+    for (int a = lane; a < count; a += BG) {
+      const int32_t j = rowbuf[grp][a];
+      int rank = 0;
+      for (int b = 0; b < count; ++b) rank += rowbuf[grp][b] < j ? 1 : 0;
+      if (MC) {
+        const int64_t e = i * KMAX + rank;
+        nj[e] = j;
+        const double r = pair_r(x, y, z, g, xi, yi, zi, j);
+        const double d = p.rc - r;
+        ndd[e] = d * d;
+        ng[e] = p.c0 + p.c1 * r;
+      } else {
+        nj[(int64_t)rank * n + i] = j;
+      }
     }
-  } else {
-    xr[i] = xi;
-    yr[i] = yi;
-    zr[i] = zi;
+    if (!MC && lane == 0) {
+      xr[i] = xi;
+      yr[i] = yi;
+      zr[i] = zi;
+    }
   }
-  cnt[i] = (uint8_t)count;
+}
+
+// sum and maximum of the row lengths: one atomic pair per block
+__global__ void __launch_bounds__(BLOCK) k_row_stats(int64_t n, const uint8_t *__restrict__ cnt,
+                                                     unsigned long long *sum, int *mx) {
+  __shared__ unsigned int ss[BLOCK];
+  __shared__ int sm[BLOCK];
+  unsigned int a = 0;
+  int b = 0;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * BLOCK) {
+    const int v = cnt[i];
+    a += v;
+    b = v > b ? v : b;
+  }
+  ss[threadIdx.x] = a;
+  sm[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      ss[threadIdx.x] += ss[threadIdx.x + h];
+      sm[threadIdx.x] = sm[threadIdx.x] > sm[threadIdx.x + h] ? sm[threadIdx.x] : sm[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(sum, (unsigned long long)ss[0]);
+    atomicMax(mx, sm[0]);
+  }
 }
 
 hipError_t launch_build_mc_list(vcsgc_ctx *c) {
-  Grid g{c->box[0], c->box[1], c->box[2], c->nc[0], c->nc[1], c->nc[2]};
-  k_build<true><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
-      c->n, c->x, c->y, c->z, g, c->cell_start, c->cell_atoms, c->pot.rc, c->pot, c->mc_j,
+  Grid g{c->box[0], c->box[1], c->box[2], c->nb[0], c->nb[1], c->nb[2]};
+  hipError_t e = hipMemsetAsync(&c->ds->pairs_mc, 0, sizeof(unsigned long long), c->stream);
+  if (e != hipSuccess) return e;
+  int h = tstart(c, VCSGC_KT_BUILD);
+  k_build<true><<<grid_for(c->n * BG), BLOCK, 0, c->stream>>>(
+      c->n, c->x, c->y, c->z, g, c->bin_count, c->bin_atoms, c->bmax, c->pot.rc, c->pot, c->mc_j,
       c->mc_dd, c->mc_g, c->mc_cnt, nullptr, nullptr, nullptr, c->ds);
+  tstop(c, h);
+  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->mc_cnt, &c->ds->pairs_mc, &c->ds->kmax_used);
   return hipGetLastError();
 }
 
 hipError_t launch_build_md_list(vcsgc_ctx *c) {
-  Grid g{c->box[0], c->box[1], c->box[2], c->nc[0], c->nc[1], c->nc[2]};
-  k_build<false><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
-      c->n, c->x, c->y, c->z, g, c->cell_start, c->cell_atoms, c->pot.rc + c->skin, c->pot,
-      c->md_j, nullptr, nullptr, c->md_cnt, c->xr, c->yr, c->zr, c->ds);
+  Grid g{c->box[0], c->box[1], c->box[2], c->nb[0], c->nb[1], c->nb[2]};
+  hipError_t e = hipMemsetAsync(&c->ds->pairs_md, 0, sizeof(unsigned long long), c->stream);
+  if (e != hipSuccess) return e;
+  int h = tstart(c, VCSGC_KT_BUILD);
+  k_build<false><<<grid_for(c->n * BG), BLOCK, 0, c->stream>>>(
+      c->n, c->x, c->y, c->z, g, c->bin_count, c->bin_atoms, c->bmax, c->pot.rc + c->skin,
+      c->pot, c->md_j, nullptr, nullptr, c->md_cnt, c->xr, c->yr, c->zr, c->ds);
+  tstop(c, h);
+  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_used);
   return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------
-// density cache: rho_i = sum_j t_{s_j} (rc - r_ij)^2, ascending j
+// density cache: rho_i = sum_j t_{s_j} (rc - r_ij)^2, ascending j (row-major MC rows)
 // ----------------------------------------------------------------------------
 __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
                              const double *__restrict__ ndd, const uint8_t *__restrict__ cnt,
@@ -217,8 +297,8 @@ __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
   double s = 0.0;
   const int m = cnt[i];
   for (int k = 0; k < m; ++k) {
-    const int32_t j = nj[(int64_t)k * n + i];
-    s += p.t[sp[j]] * ndd[(int64_t)k * n + i];
+    const int32_t j = nj[i * KMAX + k];
+    s += p.t[sp[j]] * ndd[i * KMAX + k];
   }
   rho[i] = s;
 }

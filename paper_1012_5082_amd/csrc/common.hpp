@@ -11,6 +11,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "vcsgc.h"
 
@@ -42,9 +43,11 @@ struct DevState {
   double sum_n, sum_n2;
   unsigned long long tlog_n, slog_n;
   int overflow;   // a neighbour row exceeded KMAX
+  int bin_overflow;  // a search bin exceeded its capacity
   int bad_input;  // position outside the box / species not in {0,1}
   int rebuild;    // MD: an atom moved more than skin/2
   int kmax_used;
+  unsigned long long pairs_mc, pairs_md;  // entries of the last r < rc / r < rc + skin lists
 };
 
 // ---------------------------------------------------------------------------
@@ -150,6 +153,12 @@ struct vcsgc_ctx {
   int32_t *cell_count = nullptr, *cell_start = nullptr, *cell_atoms = nullptr,
           *cell_fill = nullptr;
 
+  // search bins for neighbour lists: edge >= rc + skin, fixed capacity per bin
+  int nb[3] = {0, 0, 0};
+  int64_t nbins = 0;
+  int bmax = 16;
+  int32_t *bin_count = nullptr, *bin_atoms = nullptr;
+
   // r < rc list, column-major rows [k * n + i]: neighbour, (rc-r)^2, c0 + c1 r
   int32_t *mc_j = nullptr;
   double *mc_dd = nullptr, *mc_g = nullptr;
@@ -159,18 +168,34 @@ struct vcsgc_ctx {
   uint8_t *md_cnt = nullptr;
   double *xr = nullptr, *yr = nullptr, *zr = nullptr;
 
+  double4 *ps4 = nullptr;  // MD: (x, y, z, species) packed for neighbour gathers
+  double4 *pf4 = nullptr;  // MD: (x, y, z, F') written by the density pass
   double *rho = nullptr;                        // density cache of the sweep
   double *rho_f = nullptr, *fp = nullptr;        // fresh density and F' (energy, MD)
   double *eatom = nullptr, *red = nullptr;
   int32_t *rec = nullptr;  // per active cell: locally accepted site or -1
+  long long *part = nullptr;  // per trial block: trials, local accepts, sum dn, near ties
+  int64_t npart = 0;
   vc::DevState *ds = nullptr;
 
   bool mc_valid = false, md_valid = false;
   uint64_t w = 0;  // sweep counter
   int kmax_used = 0;
+  int64_t md_rebuilds = 0;
 
   double *tlog = nullptr, *slog = nullptr;
   int64_t tcap = 0, scap = 0;
+
+  // optional per-kernel timing with HIP events on the context's stream
+  uint32_t tmask = 0;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pending> ev_pending;
+  double kt_ms[VCSGC_KT_CLASSES] = {};
+  int64_t kt_n[VCSGC_KT_CLASSES] = {};
 
   std::string err;
   bool sticky = false;
@@ -178,7 +203,13 @@ struct vcsgc_ctx {
 
 // internal host entry points implemented across the .hip files
 namespace vc {
+// Kernel timing: tstart records a start event when the class is enabled and
+// returns a handle (or -1); tstop records the matching end event.
+int tstart(vcsgc_ctx *c, int cls);
+void tstop(vcsgc_ctx *c, int h);
+
 hipError_t launch_bin_cells(vcsgc_ctx *c);
+hipError_t launch_bin_search(vcsgc_ctx *c);
 hipError_t launch_build_mc_list(vcsgc_ctx *c);
 hipError_t launch_build_md_list(vcsgc_ctx *c);
 hipError_t launch_density_mc(vcsgc_ctx *c);
@@ -188,7 +219,8 @@ hipError_t launch_validate(vcsgc_ctx *c);
 hipError_t launch_reduce_sum(vcsgc_ctx *c, const double *v, int64_t n, double *out_dev);
 hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
                          int64_t n_sweeps, uint64_t seed);
-hipError_t launch_kick_drift(vcsgc_ctx *c, double dt);
+hipError_t launch_pack(vcsgc_ctx *c);
+hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first);
 hipError_t launch_kick(vcsgc_ctx *c, double dt);
 hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
 }  // namespace vc

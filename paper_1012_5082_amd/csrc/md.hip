@@ -9,49 +9,67 @@ struct Box {
   double L0, L1, L2;
 };
 
-// rho_i = sum_{j: r < rc} t_{s_j} (rc - r)^2 and F'_i = -A_{s_i} / (2 sqrt(rho_i))
-__global__ void k_density_md(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                             const double *__restrict__ z, const int32_t *__restrict__ nj,
-                             const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp,
-                             Box b, PotD p, double *rho, double *fp) {
+// (x, y, z, species) of every atom, packed for the density pass
+__global__ void k_pack(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                       const double *__restrict__ z, const uint8_t *__restrict__ sp,
+                       double4 *ps4) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double xi = x[i], yi = y[i], zi = z[i];
+  ps4[i] = make_double4(x[i], y[i], z[i], (double)sp[i]);
+}
+
+hipError_t launch_pack(vcsgc_ctx *c) {
+  k_pack<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, c->sp, c->ps4);
+  return hipGetLastError();
+}
+
+// rho_i = sum_{j: r < rc} t_{s_j} (rc - r)^2 and F'_i = -A_{s_i} / (2 sqrt(rho_i));
+// also writes (x_i, y_i, z_i, F'_i) for the force pass
+__global__ void __launch_bounds__(BLOCK)
+    k_density_md(int64_t n, const double4 *__restrict__ ps4, const int32_t *__restrict__ nj,
+                 const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
+                 double *rho, double *fp, double4 *pf4) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 qi = ps4[i];
   double s = 0.0;
   const int m = cnt[i];
   for (int k = 0; k < m; ++k) {
     const int32_t j = nj[(int64_t)k * n + i];
-    const double dx = min_image(x[j] - xi, b.L0);
-    const double dy = min_image(y[j] - yi, b.L1);
-    const double dz = min_image(z[j] - zi, b.L2);
+    const double4 qj = ps4[j];
+    const double dx = min_image(qj.x - qi.x, b.L0);
+    const double dy = min_image(qj.y - qi.y, b.L1);
+    const double dz = min_image(qj.z - qi.z, b.L2);
     const double r = sqrt((dx * dx + dy * dy) + dz * dz);
     if (!(r < p.rc)) continue;
     const double d = p.rc - r;
-    s += p.t[sp[j]] * (d * d);
+    s += p.t[(int)qj.w] * (d * d);
   }
   rho[i] = s;
-  fp[i] = dembed(p, sp[i], s);
+  const double f = dembed(p, sp[i], s);
+  fp[i] = f;
+  pf4[i] = make_double4(qi.x, qi.y, qi.z, f);
 }
 
 // F_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i) / r with
 // phi'(r) = eps ((-2 d)(c0 + c1 r) + c1 d^2) and f'_X(r) = (-2 t_X) d, d = rc - r
-__global__ void k_forces(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                         const double *__restrict__ z, const int32_t *__restrict__ nj,
-                         const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp,
-                         const double *__restrict__ fp, Box b, PotD p, double *fx, double *fy,
-                         double *fz) {
+__global__ void __launch_bounds__(BLOCK)
+    k_forces(int64_t n, const double4 *__restrict__ pf4, const int32_t *__restrict__ nj,
+             const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
+             double *fx, double *fy, double *fz) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double xi = x[i], yi = y[i], zi = z[i];
+  const double4 qi = pf4[i];
   const int si = sp[i];
-  const double fpi = fp[i];
+  const double fpi = qi.w;
   double ax = 0.0, ay = 0.0, az = 0.0;
   const int m = cnt[i];
   for (int k = 0; k < m; ++k) {
     const int32_t j = nj[(int64_t)k * n + i];
-    const double dx = min_image(x[j] - xi, b.L0);
-    const double dy = min_image(y[j] - yi, b.L1);
-    const double dz = min_image(z[j] - zi, b.L2);
+    const double4 qj = pf4[j];
+    const double dx = min_image(qj.x - qi.x, b.L0);
+    const double dy = min_image(qj.y - qi.y, b.L1);
+    const double dz = min_image(qj.z - qi.z, b.L2);
     const double r = sqrt((dx * dx + dy * dy) + dz * dz);
     if (!(r < p.rc)) continue;
     const int sj = sp[j];
@@ -59,7 +77,7 @@ __global__ void k_forces(int64_t n, const double *__restrict__ x, const double *
     const double dphi = p.eps[si + sj] * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
     const double dfj = -2.0 * p.t[sj] * d;
     const double dfi = -2.0 * p.t[si] * d;
-    const double s = dphi + fpi * dfj + fp[j] * dfi;
+    const double s = dphi + fpi * dfj + qj.w * dfi;
     const double coef = s / r;
     ax += coef * dx;
     ay += coef * dy;
@@ -71,64 +89,78 @@ __global__ void k_forces(int64_t n, const double *__restrict__ x, const double *
 }
 
 // E_i = F_{s_i}(rho_i) + 0.5 sum_j (eps d^2)(c0 + c1 r)
-__global__ void k_energy(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                         const double *__restrict__ z, const int32_t *__restrict__ nj,
-                         const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp,
-                         const double *__restrict__ rho, Box b, PotD p, double *e) {
+__global__ void k_energy(int64_t n, const double4 *__restrict__ ps4, const int32_t *__restrict__ nj,
+                         const uint8_t *__restrict__ cnt, const double *__restrict__ rho, Box b,
+                         PotD p, double *e) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double xi = x[i], yi = y[i], zi = z[i];
-  const int si = sp[i];
+  const double4 qi = ps4[i];
+  const int si = (int)qi.w;
   double ps = 0.0;
   const int m = cnt[i];
   for (int k = 0; k < m; ++k) {
     const int32_t j = nj[(int64_t)k * n + i];
-    const double dx = min_image(x[j] - xi, b.L0);
-    const double dy = min_image(y[j] - yi, b.L1);
-    const double dz = min_image(z[j] - zi, b.L2);
+    const double4 qj = ps4[j];
+    const double dx = min_image(qj.x - qi.x, b.L0);
+    const double dy = min_image(qj.y - qi.y, b.L1);
+    const double dz = min_image(qj.z - qi.z, b.L2);
     const double r = sqrt((dx * dx + dy * dy) + dz * dz);
     if (!(r < p.rc)) continue;
     const double d = p.rc - r;
-    ps += p.eps[si + sp[j]] * (d * d) * (p.c0 + p.c1 * r);
+    ps += p.eps[si + (int)qj.w] * (d * d) * (p.c0 + p.c1 * r);
   }
   e[i] = embed(p, si, rho[i]) + 0.5 * ps;
 }
 
 hipError_t launch_forces(vcsgc_ctx *c) {
   Box b{c->box[0], c->box[1], c->box[2]};
-  k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, c->md_j,
-                                                        c->md_cnt, c->sp, b, c->pot, c->rho_f,
-                                                        c->fp);
-  k_forces<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, c->md_j, c->md_cnt,
-                                                    c->sp, c->fp, b, c->pot, c->fx, c->fy, c->fz);
+  int h = tstart(c, VCSGC_KT_DENSITY);
+  k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
+                                                        b, c->pot, c->rho_f, c->fp, c->pf4);
+  tstop(c, h);
+  h = tstart(c, VCSGC_KT_FORCES);
+  k_forces<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b,
+                                                    c->pot, c->fx, c->fy, c->fz);
+  tstop(c, h);
   return hipGetLastError();
 }
 
 hipError_t launch_energy(vcsgc_ctx *c) {
   Box b{c->box[0], c->box[1], c->box[2]};
-  k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, c->md_j,
-                                                        c->md_cnt, c->sp, b, c->pot, c->rho_f,
-                                                        c->fp);
-  k_energy<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, c->md_j, c->md_cnt,
-                                                    c->sp, c->rho_f, b, c->pot, c->eatom);
+  int h = tstart(c, VCSGC_KT_ENERGY);
+  k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
+                                                        b, c->pot, c->rho_f, c->fp, c->pf4);
+  k_energy<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->rho_f,
+                                                    b, c->pot, c->eatom);
+  tstop(c, h);
   return hipGetLastError();
 }
 
-// v += (dt/2)(F cm); x = wrap(x + dt v); flag a list rebuild when an atom has
-// moved more than skin/2 from its position at the last build
-__global__ void k_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
-                             double *vz, const double *__restrict__ fx,
-                             const double *__restrict__ fy, const double *__restrict__ fz,
-                             const uint8_t *__restrict__ sp, const double *__restrict__ xr,
-                             const double *__restrict__ yr, const double *__restrict__ zr, Box b,
-                             PotD p, double dt, double half_skin2, DevState *ds) {
+// [v += (dt/2)(F cm) (closing the previous step) ;] v += (dt/2)(F cm);
+// x = wrap(x + dt v); flag a list rebuild when an atom has moved more than
+// skin/2 from its position at the last build
+__global__ void __launch_bounds__(BLOCK)
+    k_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                 const double *__restrict__ fx, const double *__restrict__ fy,
+                 const double *__restrict__ fz, const uint8_t *__restrict__ sp,
+                 const double *__restrict__ xr, const double *__restrict__ yr,
+                 const double *__restrict__ zr, double4 *ps4, Box b, PotD p, double dt,
+                 double half_skin2, int kick_first, DevState *ds) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double cm = p.cm[sp[i]];
+  const int s = sp[i];
+  const double cm = p.cm[s];
   const double hdt = 0.5 * dt;
-  const double ux = vx[i] + hdt * (fx[i] * cm);
-  const double uy = vy[i] + hdt * (fy[i] * cm);
-  const double uz = vz[i] + hdt * (fz[i] * cm);
+  const double ax = fx[i] * cm, ay = fy[i] * cm, az = fz[i] * cm;
+  double ux = vx[i], uy = vy[i], uz = vz[i];
+  if (kick_first) {
+    ux = ux + hdt * ax;
+    uy = uy + hdt * ay;
+    uz = uz + hdt * az;
+  }
+  ux = ux + hdt * ax;
+  uy = uy + hdt * ay;
+  uz = uz + hdt * az;
   vx[i] = ux;
   vy[i] = uy;
   vz[i] = uz;
@@ -138,6 +170,7 @@ __global__ void k_kick_drift(int64_t n, double *x, double *y, double *z, double 
   x[i] = nx;
   y[i] = ny;
   z[i] = nz;
+  ps4[i] = make_double4(nx, ny, nz, (double)s);
   const double ex = min_image(nx - xr[i], b.L0);
   const double ey = min_image(ny - yr[i], b.L1);
   const double ez = min_image(nz - zr[i], b.L2);
@@ -156,19 +189,22 @@ __global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, const doub
   vz[i] = vz[i] + hdt * (fz[i] * cm);
 }
 
-hipError_t launch_kick_drift(vcsgc_ctx *c, double dt) {
+hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first) {
   Box b{c->box[0], c->box[1], c->box[2]};
   const double hs = 0.5 * c->skin;
-  k_kick_drift<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, c->vx, c->vy,
-                                                        c->vz, c->fx, c->fy, c->fz, c->sp, c->xr,
-                                                        c->yr, c->zr, b, c->pot, dt, hs * hs,
-                                                        c->ds);
+  int h = tstart(c, VCSGC_KT_KICKDRIFT);
+  k_kick_drift<<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+      c->n, c->x, c->y, c->z, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz, c->sp, c->xr, c->yr,
+      c->zr, c->ps4, b, c->pot, dt, hs * hs, kick_first ? 1 : 0, c->ds);
+  tstop(c, h);
   return hipGetLastError();
 }
 
 hipError_t launch_kick(vcsgc_ctx *c, double dt) {
+  int h = tstart(c, VCSGC_KT_KICK);
   k_kick<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz,
                                                   c->sp, c->pot, dt);
+  tstop(c, h);
   return hipGetLastError();
 }
 

@@ -32,6 +32,8 @@ struct SweepArgs {
   double *rho;
   double *vx, *vy, *vz;
   int32_t *rec;
+  long long *part;  // [nblocks][4] partial sums of the trial kernel
+  int nblk;
   DevState *ds;
   double *tlog;
   int64_t tcap;
@@ -39,31 +41,45 @@ struct SweepArgs {
   int64_t scap;
 };
 
-// dU of s_i -> 1 - s_i:
+// Lanes per trial: lane k of a group handles neighbour entries k and k + TL.
+constexpr int TL = 16;
+static_assert(KMAX <= 2 * TL, "a trial group covers at most 2*TL neighbours");
+
+// dU of s_i -> 1 - s_i, evaluated by the TL lanes of one group:
 //   (F_{s'}(rho_i) - F_s(rho_i)) + sum_j [(eps_{s's_j} dd) g - (eps_{s s_j} dd) g]
 //   + sum_j [F_{s_j}(rho_j + (t_{s'} dd - t_s dd)) - F_{s_j}(rho_j)]
-__device__ __forceinline__ double delta_u(const SweepArgs &a, int64_t i) {
+// Each lane computes the terms of its entries; the two sums are then formed
+// in ascending entry order from the shuffled terms, so the rounding is that
+// of the sequential sums.  Every lane of the group returns the same value.
+__device__ __forceinline__ double delta_u_group(const SweepArgs &a, int64_t i, int lane) {
   const int s = a.sp[i], s1 = 1 - s;
   const double ri = a.rho[i];
-  const double own = embed(a.p, s1, ri) - embed(a.p, s, ri);
   const int m = a.cnt[i];
+  double tp[2] = {0.0, 0.0}, te[2] = {0.0, 0.0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = lane + h * TL;
+    if (k < m) {
+      const int64_t e = i * KMAX + k;
+      const int32_t j = a.nj[e];
+      const int sj = a.sp[j];
+      const double dd = a.ndd[e], g = a.ng[e];
+      const double rj = a.rho[j];
+      tp[h] = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
+      const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
+      te[h] = embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
+    }
+  }
+  // two independent in-order chains
   double pair = 0.0, emb = 0.0;
   for (int k = 0; k < m; ++k) {
-    const int64_t e = (int64_t)k * a.n + i;
-    const int32_t j = a.nj[e];
-    const int sj = a.sp[j];
-    const double dd = a.ndd[e], g = a.ng[e];
-    pair += a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
+    const int h = k / TL;
+    const double vp = __shfl(h ? tp[1] : tp[0], k % TL, TL);
+    const double ve = __shfl(h ? te[1] : te[0], k % TL, TL);
+    pair += vp;
+    emb += ve;
   }
-  for (int k = 0; k < m; ++k) {
-    const int64_t e = (int64_t)k * a.n + i;
-    const int32_t j = a.nj[e];
-    const int sj = a.sp[j];
-    const double dd = a.ndd[e];
-    const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
-    const double rj = a.rho[j];
-    emb += embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
-  }
+  const double own = embed(a.p, s1, ri) - embed(a.p, s, ri);
   return own + pair + emb;
 }
 
@@ -99,13 +115,15 @@ __global__ void __launch_bounds__(BLOCK) k_init(DevState *ds) {
   }
 }
 
+// one group of TL lanes per active cell
 __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w, int64_t s, int par) {
   __shared__ long long sh[BLOCK];
-  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
-  const int colour = (int)(g.v[0] >> 61);
+  const int lane = threadIdx.x % TL;
+  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
   long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
   if (t < a.ncpc) {
+    const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+    const int colour = (int)(g.v[0] >> 61);
     const int64_t cell = colour_cell(a, colour, t);
     const int32_t st = a.cstart[cell];
     const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
@@ -113,57 +131,67 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w, int64_
     if (m > 0) {
       const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
       const int64_t i = a.catoms[st + draw_index(r.v[0], m)];
-      const double u = unit_open(r.v[1]);
-      const double du = delta_u(a, i);
-      const int dn = 1 - 2 * (int)a.sp[i];
-      const double xl = a.beta * (du + a.dmu0 * (double)dn);
-      const double lnu = log(u);
-      const double margin = lnu + xl;
-      const bool ok = lnu < -xl;
-      valid = 1;
-      tie = fabs(margin) < TIE;
-      if (ok) {
-        acc = 1;
-        dn_acc = dn;
-        site = (int32_t)i;
-      }
-      if (a.tlog) {
-        const unsigned long long idx = atomicAdd(&a.ds->tlog_n, 1ull);
-        if ((int64_t)idx < a.tcap) {
-          double *L = a.tlog + 8 * idx;
-          L[0] = (double)w;
-          L[1] = (double)s;
-          L[2] = (double)cell;
-          L[3] = (double)i;
-          L[4] = (double)dn;
-          L[5] = ok ? 1.0 : 0.0;
-          L[6] = du;
-          L[7] = margin;
+      const double du = delta_u_group(a, i, lane);
+      if (lane == 0) {
+        const double u = unit_open(r.v[1]);
+        const int dn = 1 - 2 * (int)a.sp[i];
+        const double xl = a.beta * (du + a.dmu0 * (double)dn);
+        const double lnu = log(u);
+        const double margin = lnu + xl;
+        const bool ok = lnu < -xl;
+        valid = 1;
+        tie = fabs(margin) < TIE;
+        if (ok) {
+          acc = 1;
+          dn_acc = dn;
+          site = (int32_t)i;
+        }
+        if (a.tlog) {
+          const unsigned long long idx = atomicAdd(&a.ds->tlog_n, 1ull);
+          if ((int64_t)idx < a.tcap) {
+            double *L = a.tlog + 8 * idx;
+            L[0] = (double)w;
+            L[1] = (double)s;
+            L[2] = (double)cell;
+            L[3] = (double)i;
+            L[4] = (double)dn;
+            L[5] = ok ? 1.0 : 0.0;
+            L[6] = du;
+            L[7] = margin;
+          }
         }
       }
     }
-    a.rec[t] = site;
+    if (lane == 0) a.rec[t] = site;
   }
+  // per-block partial sums (no atomics): the commit kernel reduces them
   const long long bv = block_sum(valid, sh);
   const long long ba = block_sum(acc, sh);
   const long long bd = block_sum(dn_acc, sh);
   const long long bt = block_sum(tie, sh);
   if (threadIdx.x == 0) {
-    if (bv) atomicAdd(&a.ds->trials, (unsigned long long)bv);
-    if (ba) {
-      atomicAdd(&a.ds->local_acc, (unsigned long long)ba);
-      atomicAdd(&a.ds->nrec[par], (unsigned long long)ba);
-      atomicAdd((unsigned long long *)&a.ds->dn[par], (unsigned long long)bd);
-    }
-    if (bt) atomicAdd(&a.ds->near_ties, (unsigned long long)bt);
+    long long *P = a.part + 4 * blockIdx.x;
+    P[0] = bv;
+    P[1] = ba;
+    P[2] = bd;
+    P[3] = bt;
   }
 }
 
+// one group of TL lanes per active cell: lane k updates rho of entries k, k + TL
 __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64_t s, int par,
                                                   int last) {
-  const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const unsigned long long nrec = a.ds->nrec[par];
-  const long long dn_tot = a.ds->dn[par];
+  __shared__ long long sh[BLOCK];
+  const int lane = threadIdx.x % TL;
+  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
+  // every block reduces the trial kernel's partial sums itself, in a fixed order
+  long long pa = 0, pd = 0;
+  for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
+    pa += a.part[4 * b + 1];
+    pd += a.part[4 * b + 2];
+  }
+  const unsigned long long nrec = (unsigned long long)block_sum(pa, sh);
+  const long long dn_tot = block_sum(pd, sh);
   const long long nb = a.ds->n_b[par];
   int gacc = -1;
   double xg = 0.0, mg = 0.0;
@@ -181,29 +209,45 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64
     if (i >= 0) {
       const int s0 = a.sp[i], s1 = 1 - s0;
       const int m = a.cnt[i];
-      for (int k = 0; k < m; ++k) {
-        const int64_t e = (int64_t)k * a.n + i;
-        const int32_t j = a.nj[e];
-        const double dd = a.ndd[e];
-        const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
-        a.rho[j] = a.rho[j] + delta;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = lane + h * TL;
+        if (k < m) {
+          const int64_t e = (int64_t)i * KMAX + k;
+          const int32_t j = a.nj[e];
+          const double dd = a.ndd[e];
+          const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
+          a.rho[j] = a.rho[j] + delta;
+        }
       }
-      a.sp[i] = (uint8_t)s1;
-      if (a.vx) {
-        const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
-        a.vx[i] = a.vx[i] * f;
-        a.vy[i] = a.vy[i] * f;
-        a.vz[i] = a.vz[i] * f;
+      if (lane == 0) {
+        a.sp[i] = (uint8_t)s1;
+        if (a.vx) {
+          const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
+          a.vx[i] = a.vx[i] * f;
+          a.vy[i] = a.vy[i] * f;
+          a.vz[i] = a.vz[i] * f;
+        }
       }
     }
   }
-  if (t == 0) {
+  long long pv = 0, pt = 0;
+  if (blockIdx.x == 0) {
+    for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
+      pv += a.part[4 * b + 0];
+      pt += a.part[4 * b + 3];
+    }
+    pv = block_sum(pv, sh);
+    pt = block_sum(pt, sh);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     const long long nb_new = nb + (gacc == 1 ? dn_tot : 0);
     DevState *ds = a.ds;
     ds->n_b[par ^ 1] = nb_new;
     ds->n_b_cur = nb_new;
-    ds->dn[par ^ 1] = 0;
-    ds->nrec[par ^ 1] = 0;
+    ds->trials += (unsigned long long)pv;
+    ds->local_acc += nrec;
+    ds->near_ties += (unsigned long long)pt;
     ds->stages += 1;
     if (gacc == 1) {
       ds->stage_acc += 1;
@@ -259,20 +303,26 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.vy = c->vy;
   a.vz = c->vz;
   a.rec = c->rec;
+  a.part = c->part;
   a.ds = c->ds;
   a.tlog = c->tlog;
   a.tcap = c->tcap;
   a.slog = c->slog;
   a.scap = c->scap;
   k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
-  const int gb = grid_for(a.ncpc);
+  const int gb = grid_for(a.ncpc * TL);
+  a.nblk = gb;
   int64_t q = 0;
   for (int64_t sw = 0; sw < n_sweeps; ++sw) {
     const uint64_t w = c->w + (uint64_t)sw;
     for (int64_t s = 0; s < c->S; ++s, ++q) {
       const int par = (int)(q & 1);
+      int h = tstart(c, VCSGC_KT_TRIAL);
       k_trial<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
+      tstop(c, h);
+      h = tstart(c, VCSGC_KT_COMMIT);
       k_commit<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par, s == c->S - 1);
+      tstop(c, h);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

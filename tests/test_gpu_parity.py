@@ -79,7 +79,8 @@ def _eam_parity(O, d, pot):
     assert np.array_equal(e_g, e_o)
     U = g.energy(forces=True)
     assert abs(U - math.fsum(e_o)) <= 1e-12 * abs(U)
-    fo = O.forces(st.nl, st.species, pot, st.rho)
+    nlv = O.neighbors(d["x"], d["y"], d["z"], d["box"], pot.rc)
+    fo = O.forces(nlv, st.species, pot, st.rho)
     for a, b in zip((g.fx, g.fy, g.fz), fo):
         a = a.cpu().numpy()
         assert np.array_equal(a, b)
