@@ -127,6 +127,11 @@ def main():
     sweep_args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
     md_steps, dt = d["md_steps"], d["dt"]
 
+    # the autotuner's timing sweeps are real sweeps of the chain (warmup)
+    from paper_1012_5082_amd import autotune
+    tuned = autotune.tune(g, lambda k: g.sweep(*sweep_args, k, d["seed"], stats=False),
+                          use_cache=False)
+    log(f"autotune: {tuned['choice']} from {tuned['times_ms']}")
     for k in range(args.warmup):
         g.sweep(*sweep_args, 1, d["seed"])
         g.md(dt, md_steps)
@@ -134,7 +139,8 @@ def main():
     log(f"warmup {args.warmup} cycles done")
 
     # kernel breakdown over one extra cycle (untimed for the headline numbers)
-    g.kernel_timing(["trial", "commit", "density", "forces", "kick_drift", "kick", "build"])
+    g.kernel_timing(["trial", "commit", "density", "forces", "kick_drift", "kick", "build",
+                     "persist"])
     g.sweep(*sweep_args, 1, d["seed"])
     g.md(dt, md_steps)
     breakdown = g.kernel_times()
@@ -192,6 +198,7 @@ def main():
                                f"T=700 K, step = 1 VC-SGC sweep + 20 MD steps (dt=1 fs)",
                    "n_sites": n, "n_cells": info["n_cells"],
                    "stages_per_sweep": info["stages_per_sweep"], "variant": "plain",
+                   "sweep_tiling": list(tuned["choice"]),
                    "md_list_rebuilds": info2["md_rebuilds"]},
         "md_atom_steps_per_s": round(md_rate, 1),
         "mc_ms_per_sweep": round(mc_ms / args.steps, 3),
@@ -199,6 +206,7 @@ def main():
         "accepted_flips_per_s": round(flips / (mc_ms / 1e3), 1),
         "kernel_breakdown_ms": {k: round(v[0], 4) for k, v in breakdown.items()},
         "top_kernel": top,
+        "autotune_ms_per_sweep": {k: round(v, 3) for k, v in tuned["times_ms"].items()},
         "roofline": roof,
     }
     g.close()

@@ -130,6 +130,40 @@ vcsgc_status vcsgc_destroy(vcsgc_ctx *ctx);
 vcsgc_status vcsgc_sweep(vcsgc_ctx *ctx, double dmu0, double kappa, double cbar, double T_K,
                          int64_t n_sweeps, uint64_t seed, vcsgc_stats *out);
 
+/* Batch of independent replicas (for example a scan over T, kappa and cbar
+ * as in phase-diagram work): one context, one persistent launch per call.
+ * sys describes the concatenated arrays (n_atoms = sum of rep_atoms; replica
+ * r occupies the next rep_atoms[r] entries); sys->box is ignored and
+ * rep_box[3 r .. 3 r + 2] gives replica r's box.  Each replica gets its own
+ * cells, stage count and Philox key (seed, r).  MC only: md_verlet_step,
+ * eam_energy_forces and vcsgc_atom_energies reject batch contexts.
+ * rep_atoms and rep_box are host arrays of n_rep and 3 n_rep entries. */
+vcsgc_status vcsgc_create_batch(const vcsgc_system *sys, int32_t n_rep, const int64_t *rep_atoms,
+                                const double *rep_box, hipStream_t stream, vcsgc_ctx **out);
+
+/* n_sweeps sweeps of every replica of a batch (as vcsgc_sweep, per replica),
+ * with per-replica parameters in host arrays of n_rep entries.  out (host,
+ * n_rep entries, may be NULL) receives per-replica statistics.  All replicas
+ * run in one persistent launch (wrapped in a HIP graph by default); each
+ * replica's workgroups synchronize among themselves only. */
+vcsgc_status vcsgc_sweep_batch(vcsgc_ctx *ctx, const double *dmu0, const double *kappa,
+                               const double *cbar, const double *T_K, int64_t n_sweeps,
+                               uint64_t seed, vcsgc_stats *out);
+
+/* Execution tuning of the sweep (results do not depend on it):
+ *   strategy 0: persistent launch captured in a HIP graph (default),
+ *            1: persistent cooperative launch without a graph,
+ *            2: one trial kernel and one commit kernel per stage (single
+ *               system only);
+ *   trials_per_group: active cells handled by each 16-lane trial group per
+ *            stage in the persistent kernel (sets the number of workgroups
+ *            per replica; raised automatically if the grid would not fit).
+ * Synchronizes the stream. */
+vcsgc_status vcsgc_set_tuning(vcsgc_ctx *ctx, int32_t strategy, int32_t trials_per_group);
+/* Current tuning and the persistent grid size (any output may be NULL). */
+vcsgc_status vcsgc_get_tuning(vcsgc_ctx *ctx, int32_t *strategy, int32_t *trials_per_group,
+                              int32_t *workgroups);
+
 /* Fresh EAM evaluation at the current positions and species: rho, per-atom
  * energies E_i = F_{s_i}(rho_i) + 1/2 sum_j phi(r_ij) and, if want_forces,
  * forces F_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i)/r
@@ -183,7 +217,8 @@ vcsgc_status vcsgc_get_info(vcsgc_ctx *ctx, vcsgc_info *out);
 #define VCSGC_KT_KICK 5       /* velocity Verlet second half */
 #define VCSGC_KT_BUILD 6      /* cell binning + neighbour list */
 #define VCSGC_KT_ENERGY 7     /* per-atom energies */
-#define VCSGC_KT_CLASSES 8
+#define VCSGC_KT_PERSIST 8    /* persistent sweep (one launch per call) */
+#define VCSGC_KT_CLASSES 9
 
 typedef struct {
   double total_ms[VCSGC_KT_CLASSES]; /* summed event-to-event durations */

@@ -1,0 +1,82 @@
+"""Autotuner for the sweep's execution tiling.
+
+Candidates: one trial kernel + one commit kernel per stage ("stage", single
+systems only) and the graph-captured persistent launch with 1, 2, 4 or 8
+active cells per 16-lane trial group per stage (which sets the number of
+workgroups per replica).  Results do not depend on the choice: every
+candidate produces the same chain, so the sweeps made while tuning are real
+sweeps of the chain.  The winner is cached in a JSON file keyed by the GPU
+architecture and the problem shape (replicas, sites and active cells per
+stage, bucketed to powers of two).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+CACHE = os.environ.get("VCSGC_TUNING_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "vcsgc_tuning.json"))
+TPG = (1, 2, 4, 8)
+
+
+def _key(ctx):
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    info = ctx.info()
+    n_rep = getattr(ctx, "n_rep", 1)
+    b = lambda v: int(2 ** round(math.log2(max(1, v))))  # noqa: E731
+    ncpc = int(info["n_cells"][0] * info["n_cells"][1] * info["n_cells"][2]) // 8
+    return f"{arch}|R{n_rep}|N{b(ctx.n)}|C{b(ncpc)}"
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(tab):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        with open(CACHE, "w") as f:
+            json.dump(tab, f, indent=1)
+    except OSError:
+        pass
+
+
+def tune(ctx, sweep_fn, sweeps_per_candidate=2, use_cache=True):
+    """Pick the fastest tiling for ctx.  sweep_fn(n) runs n sweeps on ctx with
+    the caller's parameters (and no statistics read-back).  Returns
+    {"choice": (strategy, tpg), "times_ms": {...}, "cached": bool}."""
+    import torch
+    key = _key(ctx)
+    tab = _load() if use_cache else {}
+    if key in tab:
+        s, t = tab[key]["choice"]
+        ctx.set_tuning(s, t)
+        return {"choice": (s, t), "times_ms": tab[key]["times_ms"], "cached": True, "key": key}
+    cands = [("graph", t) for t in TPG]
+    if getattr(ctx, "n_rep", 1) == 1:
+        cands.insert(0, ("stage", 1))
+    times = {}
+    for s, t in cands:
+        ctx.set_tuning(s, t)
+        sweep_fn(1)  # first use builds the graph
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        sweep_fn(sweeps_per_candidate)
+        b.record()
+        torch.cuda.synchronize()
+        times[f"{s}:{t}"] = a.elapsed_time(b) / sweeps_per_candidate
+    best = min(times, key=times.get)
+    s, t = best.split(":")
+    ctx.set_tuning(s, int(t))
+    if use_cache:
+        tab[key] = {"choice": [s, int(t)], "times_ms": times}
+        _store(tab)
+    return {"choice": (s, int(t)), "times_ms": times, "cached": False, "key": key}

@@ -58,11 +58,13 @@ class Info(C.Structure):
                 ("md_rebuilds", C.c_int64)]
 
 
-KT_NAMES = ["trial", "commit", "density", "forces", "kick_drift", "kick", "build", "energy"]
+KT_NAMES = ["trial", "commit", "density", "forces", "kick_drift", "kick", "build", "energy",
+            "persist"]
+STRATEGIES = {"graph": 0, "persistent": 1, "stage": 2}
 
 
 class KTimes(C.Structure):
-    _fields_ = [("total_ms", C.c_double * 8), ("count", C.c_int64 * 8)]
+    _fields_ = [("total_ms", C.c_double * 9), ("count", C.c_int64 * 9)]
 
 
 _lib = None
@@ -109,6 +111,15 @@ def lib():
         L.vcsgc_kernel_timing.argtypes = [_P, C.c_uint32]
         L.vcsgc_get_kernel_timing.restype = st
         L.vcsgc_get_kernel_timing.argtypes = [_P, C.POINTER(KTimes)]
+        L.vcsgc_create_batch.restype = st
+        L.vcsgc_create_batch.argtypes = [C.POINTER(System), C.c_int32, _P, _P, _P, C.POINTER(_P)]
+        L.vcsgc_sweep_batch.restype = st
+        L.vcsgc_sweep_batch.argtypes = [_P, _P, _P, _P, _P, C.c_int64, C.c_uint64, _P]
+        L.vcsgc_set_tuning.restype = st
+        L.vcsgc_set_tuning.argtypes = [_P, C.c_int32, C.c_int32]
+        L.vcsgc_get_tuning.restype = st
+        L.vcsgc_get_tuning.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]
         L.vcsgc_selftest_sqrt.restype = st
         L.vcsgc_selftest_sqrt.argtypes = [_P, _P, C.c_int64, _P]
         _lib = L
@@ -288,9 +299,82 @@ class VCSGC:
         self._check(lib().vcsgc_get_kernel_timing(self._h, C.byref(k)), "get_kernel_timing")
         return {nm: (k.total_ms[i], k.count[i]) for i, nm in enumerate(KT_NAMES) if k.count[i]}
 
+    def set_tuning(self, strategy="graph", trials_per_group=1):
+        self._check(lib().vcsgc_set_tuning(self._h, STRATEGIES[strategy], int(trials_per_group)),
+                    "set_tuning")
+
+    def tuning(self):
+        a, b, g = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(lib().vcsgc_get_tuning(self._h, C.byref(a), C.byref(b), C.byref(g)),
+                    "get_tuning")
+        inv = {v: k for k, v in STRATEGIES.items()}
+        return {"strategy": inv[a.value], "trials_per_group": b.value, "workgroups": g.value}
+
     def info(self):
         i = Info()
         self._check(lib().vcsgc_get_info(self._h, C.byref(i)), "info")
         return {"n_cells": list(i.n_cells), "stages_per_sweep": i.stages_per_sweep,
                 "kmax": i.kmax, "mc_kmax_used": i.mc_kmax_used, "mc_pairs": i.mc_pairs,
                 "md_pairs": i.md_pairs, "md_rebuilds": i.md_rebuilds}
+
+
+class VCSGCBatch(VCSGC):
+    """Independent replicas in one context (MC only).  reps: list of dicts with
+    x, y, z, box, species (numpy); arrays are concatenated on the device."""
+
+    def __init__(self, reps, pot, r_dep=0.0, mass_a=55.845, mass_b=63.546, device="cuda",
+                 stream=None):
+        import torch
+        L = lib()
+        self.device = torch.device(device)
+        f64 = torch.float64
+        cat = lambda k, dt: torch.as_tensor(np.concatenate([np.asarray(r[k]) for r in reps]),  # noqa: E731
+                                            dtype=dt, device=self.device).contiguous()
+        self.x, self.y, self.z = cat("x", f64), cat("y", f64), cat("z", f64)
+        self.species = cat("species", torch.uint8)
+        self.n = self.x.numel()
+        self.n_rep = len(reps)
+        self.rep_atoms = np.array([np.asarray(r["x"]).size for r in reps], dtype=np.int64)
+        self.offsets = np.concatenate([[0], np.cumsum(self.rep_atoms)])
+        self.rep_box = np.ascontiguousarray(np.stack([np.asarray(r["box"], dtype=np.float64)
+                                                      for r in reps]))
+        self.box = self.rep_box[0]
+        self.pot = pot
+        self.vx = self.vy = self.vz = self.fx = self.fy = self.fz = None
+        sysd = System()
+        sysd.n_atoms = self.n
+        sysd.box = (C.c_double * 3)(*self.box.tolist())
+        sysd.x, sysd.y, sysd.z = self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr()
+        sysd.species = self.species.data_ptr()
+        sysd.pot = pot_struct(pot, mass_a, mass_b)
+        sysd.skin = 0.3
+        sysd.r_dep = float(r_dep)
+        self._sys = sysd
+        self.stream = stream
+        h = _P()
+        rc = L.vcsgc_create_batch(C.byref(sysd), self.n_rep,
+                                  self.rep_atoms.ctypes.data_as(_P),
+                                  self.rep_box.ctypes.data_as(_P), _stream_handle(stream),
+                                  C.byref(h))
+        if rc:
+            raise VcsgcError(rc, L.vcsgc_last_error(None).decode())
+        self._h = h
+        self._logs = None
+
+    def sweep_batch(self, dmu0, kappa, cbar, T, n_sweeps, seed, stats=True):
+        arr = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64),  # noqa: E731
+                                                             (self.n_rep,)))
+        d, k, c, t = arr(dmu0), arr(kappa), arr(cbar), arr(T)
+        out = (Stats * self.n_rep)() if stats else None
+        self._check(lib().vcsgc_sweep_batch(self._h, d.ctypes.data_as(_P), k.ctypes.data_as(_P),
+                                            c.ctypes.data_as(_P), t.ctypes.data_as(_P),
+                                            int(n_sweeps), int(seed), out), "sweep_batch")
+        return [s.as_dict() for s in out] if stats else None
+
+    def replica_species(self, r):
+        a, b = self.offsets[r], self.offsets[r + 1]
+        return self.species[a:b].cpu().numpy()
+
+    def replica_rho(self, r):
+        rho = self.rho().cpu().numpy()
+        return rho[self.offsets[r]:self.offsets[r + 1]]

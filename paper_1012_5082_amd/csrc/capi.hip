@@ -2,8 +2,10 @@
 // host side of the sweep / EAM / MD calls.  See include/vcsgc.h.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -23,9 +25,14 @@ void free_all(vcsgc_ctx *c) {
                   c->cell_fill,  c->mc_j,       c->mc_dd,
                   c->mc_g,       c->mc_cnt,     c->md_j,       c->md_cnt,    c->xr,   c->yr,
                   c->zr,         c->rho,        c->rho_f,      c->fp,        c->eatom, c->red,
-                  c->rec,        c->ds,         c->ps4,        c->pf4,       c->part};
+                  c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
+                  c->d_reps,     c->d_rs,       c->d_wg_rep};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  if (c->h_reps) (void)hipHostFree(c->h_reps);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
 }
 
 vcsgc_status fail(vcsgc_ctx *c, vcsgc_status st, const std::string &msg) {
@@ -50,19 +57,6 @@ vcsgc_status dev_fail(vcsgc_ctx *c, hipError_t e, const char *where) {
   } while (0)
 
 bool is_fin(double v) { return std::isfinite(v); }
-
-__global__ void k_count_b(int64_t n, const uint8_t *__restrict__ sp, vc::DevState *ds) {
-  __shared__ long long sh[vc::BLOCK];
-  const int64_t i = (int64_t)blockIdx.x * vc::BLOCK + threadIdx.x;
-  sh[threadIdx.x] = i < n ? (long long)sp[i] : 0;
-  __syncthreads();
-  for (int h = vc::BLOCK / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && sh[0]) atomicAdd((unsigned long long *)&ds->n_b_cur,
-                                           (unsigned long long)sh[0]);
-}
 
 vc::DevState read_state(vcsgc_ctx *c, hipError_t *e) {
   vc::DevState h;
@@ -90,9 +84,12 @@ vcsgc_status grow_bins(vcsgc_ctx *c) {
 // Rebuild cells + the r < rc list + the density cache; checks row overflow.
 vcsgc_status refresh_mc(vcsgc_ctx *c) {
   for (;;) {
-    VC_CHECK(c, vc::launch_bin_cells(c), "binning");
-    VC_CHECK(c, vc::launch_bin_search(c), "binning");
-    VC_CHECK(c, vc::launch_build_mc_list(c), "neighbour list");
+    for (const RepHost &r : c->reps) {
+      VC_CHECK(c, vc::launch_bin_cells(c, r), "binning");
+      VC_CHECK(c, vc::launch_bin_search(c, r), "binning");
+      VC_CHECK(c, vc::launch_build_mc_list(c, r), "neighbour list");
+    }
+    VC_CHECK(c, vc::launch_mc_row_stats(c), "neighbour list");
     VC_CHECK(c, vc::launch_density_mc(c), "density");
     hipError_t e;
     vc::DevState h = read_state(c, &e);
@@ -112,7 +109,7 @@ vcsgc_status refresh_mc(vcsgc_ctx *c) {
 
 vcsgc_status refresh_md(vcsgc_ctx *c) {
   for (;;) {
-    VC_CHECK(c, vc::launch_bin_search(c), "binning");
+    VC_CHECK(c, vc::launch_bin_search(c, c->reps[0]), "binning");
     VC_CHECK(c, vc::launch_build_md_list(c), "neighbour list (MD)");
     hipError_t e;
     vc::DevState h = read_state(c, &e);
@@ -127,6 +124,64 @@ vcsgc_status refresh_md(vcsgc_ctx *c) {
     c->md_valid = true;
     c->md_rebuilds += 1;
     return VCSGC_OK;
+  }
+}
+
+// Workgroups of the persistent sweep: replica r gets about
+// ncpc / (groups per workgroup * trials_per_group) of them (at least one);
+// replicas with 8 or more get a multiple of 8 starting at a multiple of 8 so
+// that their shares can be laid out XCD by XCD.  The grid must fit the
+// co-resident capacity; trials_per_group doubles until it does.
+vcsgc_status assign_workgroups(vcsgc_ctx *c) {
+  int dev_cu = 0, per_cu = 0;
+  VC_CHECK(c, hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, c->device),
+           "device query");
+  VC_CHECK(c, vc::persist_max_blocks(&per_cu), "occupancy query");
+  const int cap = dev_cu * (per_cu > 0 ? per_cu : 1);
+  const int R = (int)c->reps.size();
+  if (R > cap) return fail(c, VCSGC_E_INVALID_ARG, "more replicas than co-resident workgroups");
+  int tpg = c->trials_per_group < 1 ? 1 : c->trials_per_group;
+  for (;;) {
+    std::vector<int> want(R);
+    int64_t total = 0;
+    for (int k = 0; k < R; ++k) {
+      const int64_t per = (int64_t)vc::persist_groups() * tpg;
+      int64_t g = (c->reps[k].ncpc + per - 1) / per;
+      if (g < 1) g = 1;
+      if (g >= 8) g = (g + 7) / 8 * 8;
+      want[k] = (int)g;
+      total += g;
+    }
+    if (total <= cap || tpg >= (1 << 20)) {
+      if (total > cap) return fail(c, VCSGC_E_INVALID_ARG, "persistent grid does not fit");
+      // large replicas first (aligned), then the single-digit ones
+      std::vector<int> order(R);
+      for (int k = 0; k < R; ++k) order[k] = k;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int b) { return (want[a] >= 8) > (want[b] >= 8); });
+      std::vector<int32_t> map((size_t)total);
+      int g0 = 0;
+      for (int k : order) {
+        c->reps[k].g0 = g0;
+        c->reps[k].G = want[k];
+        for (int q = 0; q < want[k]; ++q) map[g0 + q] = k;
+        g0 += want[k];
+      }
+      if (c->d_wg_rep) (void)hipFree(c->d_wg_rep);
+      c->d_wg_rep = nullptr;
+      VC_CHECK(c, dalloc(&c->d_wg_rep, (size_t)total), "allocation");
+      VC_CHECK(c, hipMemcpy(c->d_wg_rep, map.data(), sizeof(int32_t) * total,
+                            hipMemcpyHostToDevice),
+               "copy");
+      c->grid_total = (int)total;
+      c->trials_per_group = tpg;
+      if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+      }
+      return VCSGC_OK;
+    }
+    tpg *= 2;
   }
 }
 
@@ -216,16 +271,19 @@ vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *c, vcsgc_ktimes *out) {
   return VCSGC_OK;
 }
 
-vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx **out) {
+}  // extern "C"
+
+namespace {
+
+// Shared by vcsgc_create (one replica) and vcsgc_create_batch.
+vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atoms,
+                         const double *rep_box, hipStream_t stream, vcsgc_ctx **out) {
   if (!sys || !out) return fail(nullptr, VCSGC_E_INVALID_ARG, "null argument");
   const vcsgc_eam_fs &P = sys->pot;
   if (sys->n_atoms < 2 || sys->n_atoms > (int64_t)0x7fffffff)
     return fail(nullptr, VCSGC_E_INVALID_ARG, "n_atoms must be in [2, 2^31)");
   if (!sys->x || !sys->y || !sys->z || !sys->species)
     return fail(nullptr, VCSGC_E_INVALID_ARG, "positions and species are required");
-  for (int d = 0; d < 3; ++d)
-    if (!(sys->box[d] > 0.0) || !is_fin(sys->box[d]))
-      return fail(nullptr, VCSGC_E_INVALID_ARG, "box edges must be positive and finite");
   const double pv[] = {P.rc, P.c0, P.c1, P.eps_aa, P.eps_ab, P.eps_bb, P.t_a, P.t_b, P.a_a, P.a_b};
   for (double v : pv)
     if (!is_fin(v)) return fail(nullptr, VCSGC_E_INVALID_ARG, "non-finite potential parameter");
@@ -240,26 +298,57 @@ vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx
     return fail(nullptr, VCSGC_E_INVALID_ARG, "forces must be all set or all NULL");
   if (has_v && (!(P.mass_a > 0.0) || !(P.mass_b > 0.0) || !is_fin(P.mass_a) || !is_fin(P.mass_b)))
     return fail(nullptr, VCSGC_E_INVALID_ARG, "masses must be positive with velocities");
-  double r_dep = sys->r_dep == 0.0 ? 2.0 * P.rc : sys->r_dep;
+  const double r_dep = sys->r_dep == 0.0 ? 2.0 * P.rc : sys->r_dep;
   if (!(r_dep >= 2.0 * P.rc) || !is_fin(r_dep))
     return fail(nullptr, VCSGC_E_INVALID_ARG, "r_dep must be >= 2 rc");
 
-  int nc[3];
-  for (int d = 0; d < 3; ++d) {
-    nc[d] = 2 * (int)std::floor(sys->box[d] / (2.0 * r_dep));
-    if (nc[d] < 2)
-      return fail(nullptr, VCSGC_E_BOX_TOO_SMALL,
-                  "box must hold two cells of edge r_dep in every dimension");
+  std::vector<RepHost> reps((size_t)R);
+  int64_t aoff = 0, coff = 0, boff = 0, roff = 0;
+  for (int k = 0; k < R; ++k) {
+    RepHost &r = reps[k];
+    r.n = rep_atoms[k];
+    if (r.n < 2) return fail(nullptr, VCSGC_E_INVALID_ARG, "every replica needs >= 2 atoms");
+    r.aoff = aoff;
+    for (int d = 0; d < 3; ++d) {
+      r.box[d] = rep_box[3 * k + d];
+      if (!(r.box[d] > 0.0) || !is_fin(r.box[d]))
+        return fail(nullptr, VCSGC_E_INVALID_ARG, "box edges must be positive and finite");
+      r.nc[d] = 2 * (int)std::floor(r.box[d] / (2.0 * r_dep));
+      if (r.nc[d] < 2)
+        return fail(nullptr, VCSGC_E_BOX_TOO_SMALL,
+                    "box must hold two cells of edge r_dep in every dimension");
+      r.nb[d] = (int)std::floor(r.box[d] / (P.rc + sys->skin));
+    }
+    r.ncells = (int64_t)r.nc[0] * r.nc[1] * r.nc[2];
+    r.coff = coff;
+    r.cso = coff + k;
+    r.S = 8 * ((r.n + r.ncells - 1) / r.ncells);
+    r.ncpc = r.ncells / 8;
+    r.roff = roff;
+    r.nbins = (int64_t)r.nb[0] * r.nb[1] * r.nb[2];
+    r.boff = boff;
+    aoff += r.n;
+    coff += r.ncells;
+    boff += r.nbins;
+    roff += r.ncpc;
   }
+  if (aoff != sys->n_atoms)
+    return fail(nullptr, VCSGC_E_INVALID_ARG, "replica sizes must add up to n_atoms");
 
   vcsgc_ctx *c = new vcsgc_ctx();
   (void)hipGetDevice(&c->device);
   c->stream = stream;
   c->n = sys->n_atoms;
+  c->reps = reps;
+  const RepHost &r0 = reps[0];
   for (int d = 0; d < 3; ++d) {
-    c->box[d] = sys->box[d];
-    c->nc[d] = nc[d];
+    c->box[d] = r0.box[d];
+    c->nc[d] = r0.nc[d];
+    c->nb[d] = r0.nb[d];
   }
+  c->ncells = r0.ncells;
+  c->S = r0.S;
+  c->nbins = r0.nbins;
   c->x = sys->x;
   c->y = sys->y;
   c->z = sys->z;
@@ -287,43 +376,45 @@ vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx
   p.mass[1] = P.mass_b;
   p.cm[0] = P.mass_a > 0.0 ? vc::ACC / P.mass_a : 0.0;
   p.cm[1] = P.mass_b > 0.0 ? vc::ACC / P.mass_b : 0.0;
-  c->ncells = (int64_t)nc[0] * nc[1] * nc[2];
-  c->S = 8 * ((c->n + c->ncells - 1) / c->ncells);
-  for (int d = 0; d < 3; ++d) c->nb[d] = (int)std::floor(sys->box[d] / (P.rc + sys->skin));
-  c->nbins = (int64_t)c->nb[0] * c->nb[1] * c->nb[2];
   c->bmax = 16;
+  c->strategy = 0;
 
   const int64_t n = c->n, K = vc::KMAX;
+  const bool single = R == 1;
   hipError_t e = hipSuccess;
-  auto A = [&](hipError_t r) {
-    if (e == hipSuccess) e = r;
+  auto A = [&](hipError_t rr) {
+    if (e == hipSuccess) e = rr;
   };
-  A(dalloc(&c->bin_count, c->nbins));
-  A(dalloc(&c->bin_atoms, c->nbins * c->bmax));
-  A(dalloc(&c->cell_count, c->ncells));
-  A(dalloc(&c->cell_start, c->ncells + 1));
-  A(dalloc(&c->cell_fill, c->ncells));
+  A(dalloc(&c->bin_count, boff));
+  A(dalloc(&c->bin_atoms, boff * c->bmax));
+  A(dalloc(&c->cell_count, coff));
+  A(dalloc(&c->cell_start, coff + R));
+  A(dalloc(&c->cell_fill, coff));
   A(dalloc(&c->cell_atoms, n));
   A(dalloc(&c->mc_j, K * n));
   A(dalloc(&c->mc_dd, K * n));
   A(dalloc(&c->mc_g, K * n));
   A(dalloc(&c->mc_cnt, n));
-  A(dalloc(&c->md_j, K * n));
-  A(dalloc(&c->md_cnt, n));
-  A(dalloc(&c->xr, n));
-  A(dalloc(&c->yr, n));
-  A(dalloc(&c->zr, n));
-  A(dalloc(&c->ps4, n));
-  A(dalloc(&c->pf4, n));
+  if (single) {
+    A(dalloc(&c->md_j, K * n));
+    A(dalloc(&c->md_cnt, n));
+    A(dalloc(&c->xr, n));
+    A(dalloc(&c->yr, n));
+    A(dalloc(&c->zr, n));
+    A(dalloc(&c->ps4, n));
+    A(dalloc(&c->pf4, n));
+    A(dalloc(&c->rho_f, n));
+    A(dalloc(&c->fp, n));
+    A(dalloc(&c->eatom, n));
+  }
   A(dalloc(&c->rho, n));
-  A(dalloc(&c->rho_f, n));
-  A(dalloc(&c->fp, n));
-  A(dalloc(&c->eatom, n));
   A(dalloc(&c->red, (n + vc::BLOCK - 1) / vc::BLOCK + 8));
-  A(dalloc(&c->rec, c->ncells / 8));
-  c->npart = (c->ncells / 8 * 16 + vc::BLOCK - 1) / vc::BLOCK;
-  A(dalloc(&c->part, 4 * c->npart));
+  A(dalloc(&c->rec, roff));
   A(dalloc(&c->ds, 1));
+  A(dalloc((unsigned char **)&c->d_reps, vc::repd_size() * R));
+  A(dalloc((unsigned char **)&c->d_rs, vc::repstate_size() * R));
+  if (e == hipSuccess) e = hipHostMalloc(&c->h_reps, vc::repd_size() * R, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     free_all(c);
     delete c;
@@ -338,9 +429,17 @@ vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx
     delete c;
     return st;
   };
+  vcsgc_status st = assign_workgroups(c);
+  if (st) return bail(st);
+  // trial-kernel partial sums: the larger of the two strategies' needs
+  const int64_t npart_stage = (r0.ncpc * 16 + vc::BLOCK - 1) / vc::BLOCK + 1;
+  c->npart = std::max<int64_t>(npart_stage, c->grid_total);
+  if ((e = dalloc(&c->part, 4 * c->npart)) != hipSuccess) return bail(dev_fail(c, e, "allocation"));
   if ((e = hipMemsetAsync(c->ds, 0, sizeof(vc::DevState), c->stream)) != hipSuccess)
     return bail(dev_fail(c, e, "init"));
-  if ((e = vc::launch_validate(c)) != hipSuccess) return bail(dev_fail(c, e, "validate"));
+  for (const RepHost &r : c->reps) {
+    if ((e = vc::launch_validate(c, r)) != hipSuccess) return bail(dev_fail(c, e, "validate"));
+  }
   {
     hipError_t e2;
     vc::DevState h = read_state(c, &e2);
@@ -349,12 +448,28 @@ vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx
       return bail(fail(c, VCSGC_E_INVALID_ARG,
                        "positions must lie in [0, L) and species in {0, 1}"));
   }
-  k_count_b<<<vc::grid_for(n), vc::BLOCK, 0, c->stream>>>(n, c->sp, c->ds);
-  if ((e = hipGetLastError()) != hipSuccess) return bail(dev_fail(c, e, "count"));
-  vcsgc_status st = refresh_mc(c);
+  if ((e = vc::persist_count(c)) != hipSuccess) return bail(dev_fail(c, e, "count"));
+  st = refresh_mc(c);
   if (st != VCSGC_OK) return bail(st);
   *out = c;
   return VCSGC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vcsgc_status vcsgc_create(const vcsgc_system *sys, hipStream_t stream, vcsgc_ctx **out) {
+  if (!sys || !out) return fail(nullptr, VCSGC_E_INVALID_ARG, "null argument");
+  const int64_t n = sys->n_atoms;
+  return create_impl(sys, 1, &n, sys->box, stream, out);
+}
+
+vcsgc_status vcsgc_create_batch(const vcsgc_system *sys, int32_t n_rep, const int64_t *rep_atoms,
+                                const double *rep_box, hipStream_t stream, vcsgc_ctx **out) {
+  if (!sys || !out || n_rep < 1 || !rep_atoms || !rep_box)
+    return fail(nullptr, VCSGC_E_INVALID_ARG, "null argument or n_rep < 1");
+  return create_impl(sys, n_rep, rep_atoms, rep_box, stream, out);
 }
 
 vcsgc_status vcsgc_destroy(vcsgc_ctx *c) {
@@ -375,40 +490,123 @@ const char *vcsgc_last_error(const vcsgc_ctx *c) {
   return c ? c->err.c_str() : g_create_error.c_str();
 }
 
+}  // extern "C"
+
+namespace {
+
+bool valid_params(double dmu0, double kappa, double cbar, double T) {
+  return is_fin(dmu0) && is_fin(kappa) && kappa >= 0.0 && is_fin(cbar) && cbar >= 0.0 &&
+         cbar <= 1.0 && is_fin(T) && T > 0.0;
+}
+
+// Sweeps of every replica with per-replica parameters; stats may be NULL.
+vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, const double *cbar,
+                        const double *T, int64_t n_sweeps, uint64_t seed, vcsgc_stats *out) {
+  const int R = (int)c->reps.size();
+  if (n_sweeps < 0) return fail(c, VCSGC_E_INVALID_ARG, "n_sweeps must be >= 0");
+  for (int k = 0; k < R; ++k)
+    if (!valid_params(dmu0[k], kappa[k], cbar[k], T[k]))
+      return fail(c, VCSGC_E_INVALID_ARG,
+                  "need finite dmu0, kappa >= 0, cbar in [0,1], T > 0 for every replica");
+  if (!c->mc_valid) {
+    vcsgc_status st = refresh_mc(c);
+    if (st) return st;
+  }
+  if (c->strategy == 2 && R == 1) {
+    // one trial kernel and one commit kernel per stage
+    VC_CHECK(c, vc::persist_sync_nb_to_stage(c), "sweep");
+    VC_CHECK(c, vc::launch_sweeps(c, dmu0[0], kappa[0], cbar[0], T[0], n_sweeps, seed), "sweep");
+    VC_CHECK(c, vc::persist_sync_nb_from_stage(c), "sweep");
+    c->w += (uint64_t)n_sweeps;
+    if (out) {
+      hipError_t e;
+      vc::DevState h = read_state(c, &e);
+      if (e != hipSuccess) return dev_fail(c, e, "sweep");
+      out->trials = (int64_t)h.trials;
+      out->local_accepts = (int64_t)h.local_acc;
+      out->stages = (int64_t)h.stages;
+      out->stage_accepts = (int64_t)h.stage_acc;
+      out->flips = (int64_t)h.flips;
+      out->near_ties = (int64_t)h.near_ties;
+      out->n_final = h.n_b_cur;
+      out->sum_n = h.sum_n;
+      out->sum_n2 = h.sum_n2;
+    }
+    return VCSGC_OK;
+  }
+  VC_CHECK(c, vc::persist_stage_params(c, dmu0, kappa, cbar, T, n_sweeps, seed), "sweep");
+  if (n_sweeps > 0) {
+    int h = vc::tstart(c, VCSGC_KT_PERSIST);
+    VC_CHECK(c, vc::launch_persistent(c, c->strategy == 0), "persistent sweep");
+    vc::tstop(c, h);
+  }
+  c->w += (uint64_t)n_sweeps;
+  if (out) {
+    int err = 0;
+    VC_CHECK(c, vc::persist_read_stats(c, out, &err), "sweep");
+    if (err) return fail(c, VCSGC_E_DEVICE, "barrier wait exceeded its limit");
+  }
+  return VCSGC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 vcsgc_status vcsgc_sweep(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T_K,
                          int64_t n_sweeps, uint64_t seed, vcsgc_stats *out) {
   vcsgc_status st = check_ctx(c);
   if (st) return st;
-  if (!is_fin(dmu0) || !is_fin(kappa) || !(kappa >= 0.0) || !is_fin(cbar) || cbar < 0.0 ||
-      cbar > 1.0 || !is_fin(T_K) || !(T_K > 0.0) || n_sweeps < 0)
-    return fail(c, VCSGC_E_INVALID_ARG,
-                "need finite dmu0, kappa >= 0, cbar in [0,1], T > 0, n_sweeps >= 0");
-  if (!c->mc_valid) {
-    st = refresh_mc(c);
+  if (c->reps.size() != 1) return fail(c, VCSGC_E_INVALID_ARG, "batch context: use vcsgc_sweep_batch");
+  return sweep_impl(c, &dmu0, &kappa, &cbar, &T_K, n_sweeps, seed, out);
+}
+
+vcsgc_status vcsgc_sweep_batch(vcsgc_ctx *c, const double *dmu0, const double *kappa,
+                               const double *cbar, const double *T, int64_t n_sweeps,
+                               uint64_t seed, vcsgc_stats *out) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (!dmu0 || !kappa || !cbar || !T) return fail(c, VCSGC_E_INVALID_ARG, "null parameter array");
+  return sweep_impl(c, dmu0, kappa, cbar, T, n_sweeps, seed, out);
+}
+
+vcsgc_status vcsgc_set_tuning(vcsgc_ctx *c, int32_t strategy, int32_t trials_per_group) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (strategy < 0 || strategy > 2 || trials_per_group < 1 || trials_per_group > 64)
+    return fail(c, VCSGC_E_INVALID_ARG, "strategy in {0,1,2}, trials_per_group in [1,64]");
+  if (strategy == 2 && c->reps.size() != 1)
+    return fail(c, VCSGC_E_INVALID_ARG, "per-stage launches need a single-system context");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  c->strategy = strategy;
+  if (trials_per_group != c->trials_per_group) {
+    c->trials_per_group = trials_per_group;
+    st = assign_workgroups(c);
     if (st) return st;
+    if (c->grid_total > c->npart) {
+      (void)hipFree(c->part);
+      c->part = nullptr;
+      c->npart = c->grid_total;
+      VC_CHECK(c, dalloc(&c->part, 4 * c->npart), "allocation");
+    }
   }
-  VC_CHECK(c, vc::launch_sweeps(c, dmu0, kappa, cbar, T_K, n_sweeps, seed), "sweep");
-  c->w += (uint64_t)n_sweeps;
-  if (out) {
-    hipError_t e;
-    vc::DevState h = read_state(c, &e);
-    if (e != hipSuccess) return dev_fail(c, e, "sweep");
-    out->trials = (int64_t)h.trials;
-    out->local_accepts = (int64_t)h.local_acc;
-    out->stages = (int64_t)h.stages;
-    out->stage_accepts = (int64_t)h.stage_acc;
-    out->flips = (int64_t)h.flips;
-    out->near_ties = (int64_t)h.near_ties;
-    out->n_final = h.n_b_cur;
-    out->sum_n = h.sum_n;
-    out->sum_n2 = h.sum_n2;
-  }
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_get_tuning(vcsgc_ctx *c, int32_t *strategy, int32_t *trials_per_group,
+                              int32_t *workgroups) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (strategy) *strategy = c->strategy;
+  if (trials_per_group) *trials_per_group = c->trials_per_group;
+  if (workgroups) *workgroups = c->grid_total;
   return VCSGC_OK;
 }
 
 vcsgc_status eam_energy_forces(vcsgc_ctx *c, double *energy_eV, int want_forces) {
   vcsgc_status st = check_ctx(c);
   if (st) return st;
+  if (c->reps.size() != 1) return fail(c, VCSGC_E_INVALID_ARG, "not available on a batch context");
   if (want_forces && !c->fx)
     return fail(c, VCSGC_E_INVALID_ARG, "forces requested but the system has no force arrays");
   if (!c->md_valid) {
@@ -434,6 +632,7 @@ vcsgc_status eam_energy_forces(vcsgc_ctx *c, double *energy_eV, int want_forces)
 vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
   vcsgc_status st = check_ctx(c);
   if (st) return st;
+  if (c->reps.size() != 1) return fail(c, VCSGC_E_INVALID_ARG, "not available on a batch context");
   if (!c->vx || !c->fx)
     return fail(c, VCSGC_E_INVALID_ARG, "MD needs velocity and force arrays");
   if (!is_fin(dt_fs) || !(dt_fs > 0.0) || n_steps < 0)
@@ -496,11 +695,11 @@ vcsgc_status vcsgc_get_state(vcsgc_ctx *c, vcsgc_state *out) {
   vcsgc_status st = check_ctx(c);
   if (st) return st;
   if (!out) return fail(c, VCSGC_E_INVALID_ARG, "null output");
-  hipError_t e;
-  vc::DevState h = read_state(c, &e);
-  if (e != hipSuccess) return dev_fail(c, e, "state");
+  vcsgc_stats s;
+  int err = 0;
+  VC_CHECK(c, vc::persist_read_stats(c, &s, &err), "state");  // n_final of replica 0
   out->sweeps_done = c->w;
-  out->n_b = h.n_b_cur;
+  out->n_b = s.n_final;
   return VCSGC_OK;
 }
 
@@ -509,12 +708,7 @@ vcsgc_status vcsgc_set_state(vcsgc_ctx *c, const vcsgc_state *in) {
   if (st) return st;
   if (!in) return fail(c, VCSGC_E_INVALID_ARG, "null input");
   c->w = in->sweeps_done;
-  long long zero = 0;
-  VC_CHECK(c, hipMemcpyAsync(&c->ds->n_b_cur, &zero, sizeof(zero), hipMemcpyHostToDevice,
-                             c->stream),
-           "state");
-  k_count_b<<<vc::grid_for(c->n), vc::BLOCK, 0, c->stream>>>(c->n, c->sp, c->ds);
-  VC_CHECK(c, hipGetLastError(), "state");
+  VC_CHECK(c, vc::persist_count(c), "state");  // n_B recounted from the species
   c->mc_valid = false;  // species may have been restored: fresh density cache
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   return VCSGC_OK;
@@ -537,6 +731,7 @@ vcsgc_status vcsgc_copy_rho(vcsgc_ctx *c, double *rho_dev) {
 vcsgc_status vcsgc_atom_energies(vcsgc_ctx *c, double *e_dev) {
   vcsgc_status st = check_ctx(c);
   if (st) return st;
+  if (c->reps.size() != 1) return fail(c, VCSGC_E_INVALID_ARG, "not available on a batch context");
   if (!e_dev) return fail(c, VCSGC_E_INVALID_ARG, "null output");
   if (!c->md_valid) {
     st = refresh_md(c);

@@ -20,9 +20,10 @@ __global__ void k_validate(int64_t n, const double *__restrict__ x, const double
   if (!ok) atomicOr(&ds->bad_input, 1);
 }
 
-hipError_t launch_validate(vcsgc_ctx *c) {
-  k_validate<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, c->sp, c->box[0],
-                                                      c->box[1], c->box[2], c->ds);
+hipError_t launch_validate(vcsgc_ctx *c, const RepHost &r) {
+  k_validate<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x + r.aoff, c->y + r.aoff,
+                                                     c->z + r.aoff, c->sp + r.aoff, r.box[0],
+                                                     r.box[1], r.box[2], c->ds);
   return hipGetLastError();
 }
 
@@ -75,11 +76,12 @@ __global__ void __launch_bounds__(1024) k_scan(int64_t m, const int32_t *__restr
 }
 
 __global__ void k_cell_fill(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                            const double *__restrict__ z, Grid g, int32_t *fill, int32_t *atoms) {
+                            const double *__restrict__ z, Grid g, int32_t *fill, int32_t *atoms,
+                            int64_t aoff) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int c = cell_of(g, x[i], y[i], z[i]);
-  atoms[atomicAdd(&fill[c], 1)] = (int32_t)i;
+  atoms[atomicAdd(&fill[c], 1)] = (int32_t)(aoff + i);
 }
 
 // canonical order inside a cell: ascending site index
@@ -98,16 +100,19 @@ __global__ void k_cell_sort(int64_t m, const int32_t *__restrict__ start, int32_
   }
 }
 
-hipError_t launch_bin_cells(vcsgc_ctx *c) {
-  Grid g{c->box[0], c->box[1], c->box[2], c->nc[0], c->nc[1], c->nc[2]};
-  hipError_t e = hipMemsetAsync(c->cell_count, 0, sizeof(int32_t) * c->ncells, c->stream);
+// cells of one replica; cell_atoms holds global atom indices, cell_start the
+// positions inside the replica's segment of cell_atoms
+hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r) {
+  Grid g{r.box[0], r.box[1], r.box[2], r.nc[0], r.nc[1], r.nc[2]};
+  int32_t *count = c->cell_count + r.coff, *fill = c->cell_fill + r.coff;
+  int32_t *start = c->cell_start + r.cso, *atoms = c->cell_atoms + r.aoff;
+  hipError_t e = hipMemsetAsync(count, 0, sizeof(int32_t) * r.ncells, c->stream);
   if (e != hipSuccess) return e;
-  k_cell_count<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, g, c->cell_count);
-  k_scan<<<1, 1024, 0, c->stream>>>(c->ncells, c->cell_count, c->cell_start, c->cell_fill);
-  k_cell_fill<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, g, c->cell_fill,
-                                                       c->cell_atoms);
-  k_cell_sort<<<grid_for(c->ncells), BLOCK, 0, c->stream>>>(c->ncells, c->cell_start,
-                                                            c->cell_atoms);
+  const double *x = c->x + r.aoff, *y = c->y + r.aoff, *z = c->z + r.aoff;
+  k_cell_count<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, x, y, z, g, count);
+  k_scan<<<1, 1024, 0, c->stream>>>(r.ncells, count, start, fill);
+  k_cell_fill<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, x, y, z, g, fill, atoms, r.aoff);
+  k_cell_sort<<<grid_for(r.ncells), BLOCK, 0, c->stream>>>(r.ncells, start, atoms);
   return hipGetLastError();
 }
 
@@ -127,12 +132,15 @@ __global__ void k_bin_search(int64_t n, const double *__restrict__ x, const doub
     atomicOr(&ds->bin_overflow, 1);
 }
 
-hipError_t launch_bin_search(vcsgc_ctx *c) {
-  Grid g{c->box[0], c->box[1], c->box[2], c->nb[0], c->nb[1], c->nb[2]};
-  hipError_t e = hipMemsetAsync(c->bin_count, 0, sizeof(int32_t) * c->nbins, c->stream);
+// search bins of one replica (local atom indices)
+hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r) {
+  Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
+  int32_t *count = c->bin_count + r.boff, *atoms = c->bin_atoms + r.boff * c->bmax;
+  hipError_t e = hipMemsetAsync(count, 0, sizeof(int32_t) * r.nbins, c->stream);
   if (e != hipSuccess) return e;
-  k_bin_search<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->x, c->y, c->z, g, c->bmax,
-                                                        c->bin_count, c->bin_atoms, c->ds);
+  k_bin_search<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x + r.aoff, c->y + r.aoff,
+                                                       c->z + r.aoff, g, c->bmax, count, atoms,
+                                                       c->ds);
   return hipGetLastError();
 }
 
@@ -167,7 +175,7 @@ __global__ void __launch_bounds__(BLOCK)
             const double *__restrict__ z, Grid g, const int32_t *__restrict__ bcount,
             const int32_t *__restrict__ batoms, int bmax, double cutoff, PotD p, int32_t *nj,
             double *ndd, double *ng, uint8_t *cnt, double *xr, double *yr, double *zr,
-            DevState *ds) {
+            DevState *ds, int64_t aoff, int64_t ntot) {
   __shared__ int32_t rowbuf[BLOCK / BG][KMAX];
   __shared__ int rowcount[BLOCK / BG];
   const int lane = threadIdx.x % BG, grp = threadIdx.x / BG;
@@ -207,26 +215,27 @@ __global__ void __launch_bounds__(BLOCK)
       if (lane == 0) atomicOr(&ds->overflow, 1);
       count = KMAX;
     }
-    if (lane == 0) cnt[i] = (uint8_t)count;
+    const int64_t ig = aoff + i;  // global row
+    if (lane == 0) cnt[ig] = (uint8_t)count;
     for (int a = lane; a < count; a += BG) {
       const int32_t j = rowbuf[grp][a];
       int rank = 0;
       for (int b = 0; b < count; ++b) rank += rowbuf[grp][b] < j ? 1 : 0;
       if (MC) {
-        const int64_t e = i * KMAX + rank;
-        nj[e] = j;
+        const int64_t e = ig * KMAX + rank;
+        nj[e] = (int32_t)(aoff + j);
         const double r = pair_r(x, y, z, g, xi, yi, zi, j);
         const double d = p.rc - r;
         ndd[e] = d * d;
         ng[e] = p.c0 + p.c1 * r;
       } else {
-        nj[(int64_t)rank * n + i] = j;
+        nj[(int64_t)rank * ntot + ig] = (int32_t)(aoff + j);
       }
     }
     if (!MC && lane == 0) {
-      xr[i] = xi;
-      yr[i] = yi;
-      zr[i] = zi;
+      xr[ig] = xi;
+      yr[ig] = yi;
+      zr[ig] = zi;
     }
   }
 }
@@ -260,27 +269,35 @@ __global__ void __launch_bounds__(BLOCK) k_row_stats(int64_t n, const uint8_t *_
   }
 }
 
-hipError_t launch_build_mc_list(vcsgc_ctx *c) {
-  Grid g{c->box[0], c->box[1], c->box[2], c->nb[0], c->nb[1], c->nb[2]};
+// r < rc list of one replica (rows and neighbour indices global)
+hipError_t launch_build_mc_list(vcsgc_ctx *c, const RepHost &r) {
+  Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
+  int h = tstart(c, VCSGC_KT_BUILD);
+  k_build<true><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
+      r.n, c->x + r.aoff, c->y + r.aoff, c->z + r.aoff, g, c->bin_count + r.boff,
+      c->bin_atoms + r.boff * c->bmax, c->bmax, c->pot.rc, c->pot, c->mc_j, c->mc_dd, c->mc_g,
+      c->mc_cnt, nullptr, nullptr, nullptr, c->ds, r.aoff, c->n);
+  tstop(c, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_mc_row_stats(vcsgc_ctx *c) {
   hipError_t e = hipMemsetAsync(&c->ds->pairs_mc, 0, sizeof(unsigned long long), c->stream);
   if (e != hipSuccess) return e;
-  int h = tstart(c, VCSGC_KT_BUILD);
-  k_build<true><<<grid_for(c->n * BG), BLOCK, 0, c->stream>>>(
-      c->n, c->x, c->y, c->z, g, c->bin_count, c->bin_atoms, c->bmax, c->pot.rc, c->pot, c->mc_j,
-      c->mc_dd, c->mc_g, c->mc_cnt, nullptr, nullptr, nullptr, c->ds);
-  tstop(c, h);
   k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->mc_cnt, &c->ds->pairs_mc, &c->ds->kmax_used);
   return hipGetLastError();
 }
 
+// r < rc + skin list (single-system contexts)
 hipError_t launch_build_md_list(vcsgc_ctx *c) {
-  Grid g{c->box[0], c->box[1], c->box[2], c->nb[0], c->nb[1], c->nb[2]};
+  const RepHost &r = c->reps[0];
+  Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   hipError_t e = hipMemsetAsync(&c->ds->pairs_md, 0, sizeof(unsigned long long), c->stream);
   if (e != hipSuccess) return e;
   int h = tstart(c, VCSGC_KT_BUILD);
-  k_build<false><<<grid_for(c->n * BG), BLOCK, 0, c->stream>>>(
-      c->n, c->x, c->y, c->z, g, c->bin_count, c->bin_atoms, c->bmax, c->pot.rc + c->skin,
-      c->pot, c->md_j, nullptr, nullptr, c->md_cnt, c->xr, c->yr, c->zr, c->ds);
+  k_build<false><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
+      r.n, c->x, c->y, c->z, g, c->bin_count, c->bin_atoms, c->bmax, c->pot.rc + c->skin, c->pot,
+      c->md_j, nullptr, nullptr, c->md_cnt, c->xr, c->yr, c->zr, c->ds, 0, c->n);
   tstop(c, h);
   k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_used);
   return hipGetLastError();

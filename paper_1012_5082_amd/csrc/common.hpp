@@ -135,6 +135,22 @@ inline int grid_for(int64_t n, int block = BLOCK) {
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
+// Geometry of one replica of a batch (a single system is a batch of one).
+// Atoms of replica r occupy [aoff, aoff + n) of the concatenated arrays.
+struct RepHost {
+  int64_t n = 0, aoff = 0;
+  double box[3] = {0, 0, 0};
+  int nc[3] = {0, 0, 0};     // link cells per dimension (even, edge >= r_dep)
+  int64_t ncells = 0;
+  int64_t coff = 0;          // offset of the replica's cells in per-cell arrays
+  int64_t cso = 0;           // offset of its (ncells + 1)-entry cell_start block
+  int64_t S = 0;             // stages per sweep
+  int64_t ncpc = 0, roff = 0;  // active cells per stage, offset in the record array
+  int nb[3] = {0, 0, 0};     // search bins per dimension
+  int64_t nbins = 0, boff = 0;
+  int g0 = 0, G = 1;         // workgroups of the persistent sweep
+};
+
 struct vcsgc_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
@@ -146,6 +162,7 @@ struct vcsgc_ctx {
   uint8_t *sp = nullptr;
   vc::PotD pot{};
   double skin = 0.3, r_dep = 7.2;
+  std::vector<RepHost> reps;  // batch geometry (reps[0] mirrors the fields below)
 
   // link cells (edge >= r_dep, even count per dimension)
   int nc[3] = {0, 0, 0};
@@ -197,6 +214,22 @@ struct vcsgc_ctx {
   double kt_ms[VCSGC_KT_CLASSES] = {};
   int64_t kt_n[VCSGC_KT_CLASSES] = {};
 
+  // persistent batched sweep
+  void *d_reps = nullptr;     // per-replica parameters (device)
+  void *h_reps = nullptr;     // pinned staging buffer for them
+  void *d_rs = nullptr;       // per-replica chain state and counters
+  int32_t *d_wg_rep = nullptr;  // workgroup -> replica
+  int grid_total = 0;
+  int trials_per_group = 1;   // tiling: active cells per trial group and stage
+  int strategy = 0;           // 0: persistent (graph), 1: persistent (direct), 2: per-stage
+  unsigned int spin_limit = 1u << 24;
+  hipEvent_t stage_ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graph_coop = false;
+  double *graph_args_tlog = nullptr, *graph_args_slog = nullptr;
+  alignas(16) unsigned char graph_args_storage[512];  // kernel arguments of the graph node
+
   std::string err;
   bool sticky = false;
 };
@@ -208,14 +241,15 @@ namespace vc {
 int tstart(vcsgc_ctx *c, int cls);
 void tstop(vcsgc_ctx *c, int h);
 
-hipError_t launch_bin_cells(vcsgc_ctx *c);
-hipError_t launch_bin_search(vcsgc_ctx *c);
-hipError_t launch_build_mc_list(vcsgc_ctx *c);
+hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r);
+hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r);
+hipError_t launch_build_mc_list(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_build_md_list(vcsgc_ctx *c);
+hipError_t launch_mc_row_stats(vcsgc_ctx *c);
 hipError_t launch_density_mc(vcsgc_ctx *c);
 hipError_t launch_energy(vcsgc_ctx *c);  // fresh rho (MD list) + per-atom energies
 hipError_t launch_forces(vcsgc_ctx *c);  // fresh rho, F', forces (MD list)
-hipError_t launch_validate(vcsgc_ctx *c);
+hipError_t launch_validate(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_reduce_sum(vcsgc_ctx *c, const double *v, int64_t n, double *out_dev);
 hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
                          int64_t n_sweeps, uint64_t seed);
@@ -223,4 +257,18 @@ hipError_t launch_pack(vcsgc_ctx *c);
 hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first);
 hipError_t launch_kick(vcsgc_ctx *c, double dt);
 hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
+// persistent sweep (persist.hip)
+int persist_block();
+int persist_groups();
+size_t repd_size();
+size_t repstate_size();
+hipError_t persist_max_blocks(int *per_cu);
+hipError_t persist_stage_params(vcsgc_ctx *c, const double *dmu0, const double *kappa,
+                                const double *cbar, const double *T, int64_t n_sweeps,
+                                uint64_t seed);
+hipError_t launch_persistent(vcsgc_ctx *c, bool use_graph);
+hipError_t persist_read_stats(vcsgc_ctx *c, vcsgc_stats *out, int *err);
+hipError_t persist_count(vcsgc_ctx *c);
+hipError_t persist_sync_nb_to_stage(vcsgc_ctx *c);
+hipError_t persist_sync_nb_from_stage(vcsgc_ctx *c);
 }  // namespace vc

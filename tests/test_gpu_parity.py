@@ -97,11 +97,13 @@ def test_eam_parity_c2(torch_cuda, oracle_mod):
     _eam_parity(oracle_mod, W.c2(cbar=0.10), I.params("FS-P1"))
 
 
-def _sweep_parity(O, d, pot, n_sweeps, kappa=None, cbar=None, log=True, chunks=None):
+def _sweep_parity(O, d, pot, n_sweeps, kappa=None, cbar=None, log=True, chunks=None,
+                  strategy="graph", trials_per_group=1):
     kappa = d["kappa"] if kappa is None else kappa
     cbar = d["cbar"] if cbar is None else cbar
     args = (d["dmu0"], kappa, cbar, d["T"])
     g = gpu_context(d, pot)
+    g.set_tuning(strategy, trials_per_group)
     info = g.info()
     S = info["stages_per_sweep"]
     ncpc = int(np.prod(info["n_cells"])) // 8
@@ -150,6 +152,58 @@ def test_sweep_parity_c2(torch_cuda, oracle_mod, cbar):
     d = W.c2(cbar=cbar)
     r = _sweep_parity(oracle_mod, d, I.params("FS-P1"), 10)
     assert r["flips"] > 0
+
+
+@pytest.mark.parametrize("strategy,tpg", [("stage", 1), ("persistent", 1), ("graph", 3)])
+def test_sweep_strategies_agree(torch_cuda, oracle_mod, strategy, tpg):
+    """Per-stage launches, the direct persistent launch and other tilings of
+    the graph-captured persistent launch all reproduce the oracle."""
+    d = W.c2(cbar=0.05)
+    r = _sweep_parity(oracle_mod, d, I.params("FS-P1"), 4, strategy=strategy,
+                      trials_per_group=tpg)
+    assert r["flips"] > 0
+    r1 = _sweep_parity(oracle_mod, W.c1(), I.params("FS-P1"), 20, kappa=10.0,
+                       strategy=strategy, trials_per_group=tpg)
+    assert r1["trials"] == 20 * 2000
+
+
+def _replica_set(n_rep=6, seed=55):
+    """Uneven rigid bcc replicas on a T x kappa x cbar grid (small sizes)."""
+    rng = np.random.default_rng(seed)
+    reps = []
+    for r in range(n_rep):
+        nx, ny, nz = (int(v) for v in rng.integers(10, 19, size=3))
+        x, y, z, box = I.bcc(nx, ny, nz)
+        T = [400.0, 600.0, 800.0][r % 3]
+        kappa = [100.0, 1000.0][(r // 3) % 2]
+        cbar = float(np.exp(rng.uniform(np.log(0.01), np.log(0.2))))
+        sp = I.initial_species(x.size, cbar, seed + r)
+        reps.append(dict(x=x, y=y, z=z, box=box, species=sp, T=T, kappa=kappa, cbar=cbar,
+                         dmu0=W.dmu_s(T, cbar)))
+    return reps
+
+
+def test_batch_replicas_match_oracle(torch_cuda, oracle_mod):
+    """Each replica of a batch equals an independent oracle chain keyed
+    (seed, replica index), with its own parameters and stage count."""
+    O = oracle_mod
+    from paper_1012_5082_amd.binding import VCSGCBatch
+    pot = I.params("FS-P1")
+    reps = _replica_set()
+    b = VCSGCBatch(reps, pot)
+    args = [np.array([r[k] for r in reps]) for k in ("dmu0", "kappa", "cbar", "T")]
+    seed = 777
+    s1 = b.sweep_batch(*args, 3, seed)
+    s2 = b.sweep_batch(*args, 2, seed)
+    for k, r in enumerate(reps):
+        st = O.SweepState(r["x"], r["y"], r["z"], r["box"], r["species"], pot)
+        so, _, _ = O.sweep(st, r["dmu0"], r["kappa"], r["cbar"], r["T"], 5, seed, replica=k)
+        assert s1[k]["trials"] + s2[k]["trials"] == so["trials"]
+        assert s1[k]["flips"] + s2[k]["flips"] == so["flips"]
+        assert s2[k]["n_final"] == so["n_final"]
+        assert np.array_equal(b.replica_species(k), st.species), k
+        assert np.array_equal(b.replica_rho(k), st.rho), k
+    b.close()
 
 
 def test_sweep_chunking_and_determinism(torch_cuda, oracle_mod):
