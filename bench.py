@@ -92,6 +92,165 @@ def cpu_baseline(d, pot):
                       f"serial FP64 C oracle, {dt:.2f} s (neighbour list {setup:.1f} s untimed)"}
 
 
+def _timed(fn):
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    out = fn()
+    b.record()
+    torch.cuda.synchronize()
+    return out, a.elapsed_time(b) / 1e3
+
+
+def bench_replicas(args):
+    """64 rigid bcc replicas of uneven size on a T x kappa x cbar grid, all in
+    one graph-captured persistent launch per call; tiling from the autotuner."""
+    import numpy as np
+    from paper_1012_5082_amd import autotune
+    from paper_1012_5082_amd import inputs as I
+    from paper_1012_5082_amd import workloads as W
+    from paper_1012_5082_amd.binding import VCSGCBatch
+    pot = I.params("FS-P1")
+    reps = []
+    for r in W.c4_replicas():
+        x, y, z, box = I.bcc(r["nx"], r["ny"], r["nz"])
+        reps.append(dict(x=x, y=y, z=z, box=box,
+                         species=I.initial_species(x.size, r["cbar"], r["seed"]), **r))
+    b = VCSGCBatch(reps, pot)
+    par = [np.array([r[k] for r in reps]) for k in ("dmu0", "kappa", "cbar", "T")]
+    seed = 4004
+    tuned = autotune.tune(b, lambda k: b.sweep_batch(*par, k, seed, stats=False), use_cache=False)
+    log(f"c4 autotune {tuned['choice']} {tuned['times_ms']}")
+    n_sw = args.sweeps or 500
+    stats, dt = _timed(lambda: b.sweep_batch(*par, n_sw, seed))
+    trials = sum(s["trials"] for s in stats)
+    flips = sum(s["flips"] for s in stats)
+    sizes = [int(np.asarray(r["x"]).size) for r in reps]
+    cmean = [s["sum_n"] / n_sw / n for s, n in zip(stats, sizes)]
+    out = {"metric": "MC trials/s, 64 replicas in one launch", "value": round(trials / dt, 1),
+           "unit": "trials/s", "workload": "c4-replicas64", "n_replicas": len(reps),
+           "sites_total": int(sum(sizes)), "sites_min": min(sizes), "sites_max": max(sizes),
+           "sweeps": n_sw, "seconds": round(dt, 4), "flips_per_s": round(flips / dt, 1),
+           "tiling": list(tuned["choice"]), "workgroups": b.tuning()["workgroups"],
+           "autotune_ms_per_sweep": {k: round(v, 3) for k, v in tuned["times_ms"].items()},
+           "mean_c_first8": [round(c, 5) for c in cmean[:8]],
+           "cbar_first8": [round(float(r["cbar"]), 5) for r in reps[:8]]}
+    b.close()
+    return out
+
+
+def _blocked(series, nb=10):
+    import numpy as np
+    a = np.asarray(series, dtype=np.float64)
+    m = a.size // nb
+    bm = a[: m * nb].reshape(nb, m).mean(axis=1)
+    return float(bm.mean()), float(bm.std(ddof=1) / np.sqrt(nb))
+
+
+def bench_surrogate(args):
+    """Surrogate delayed acceptance on the 1.96M-site polycrystal.
+
+    1. training samples: (descriptor, exact dU) of every 128th trial of plain
+       sweeps of the 40^3 thermal bcc system at cbar = 0.02, 0.05, 0.10
+       (about 10^6 pairs);
+    2. hand-written training (BF16 MFMA forward/backward, Adam);
+    3. the polycrystal (cells of edge >= 8.01 A, the descriptor's dependence
+       range) is first relaxed by plain sweeps; from that state a plain and a
+       delayed-acceptance chain run with identical parameters: trials/s,
+       exact-accepted moves/s, pre-rejection rate, and <c>, <E> (energy every
+       10 sweeps, outside the timed sweeps) with blocked errors."""
+    import numpy as np
+    import torch
+    from paper_1012_5082_amd import inputs as I
+    from paper_1012_5082_amd import workloads as W
+    from paper_1012_5082_amd.binding import VCSGC, Mlp
+    pot = I.params("FS-P1")
+    descs, des = [], []
+    t0 = time.perf_counter()
+    for cb in (0.02, 0.05, 0.10):
+        d = W.c2(cbar=cb)
+        g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, descriptor=True)
+        g.sweep(d["dmu0"], d["kappa"], cb, d["T"], 20, d["seed"])
+        g.enable_sample_log(340000, 128)
+        g.sweep(d["dmu0"], d["kappa"], cb, d["T"], 345, d["seed"])
+        a, e = g.samples()
+        descs.append(a.clone())
+        des.append(e.clone())
+        g.close()
+    desc = torch.cat(descs)[:1000000].contiguous()
+    dE = torch.cat(des)[:1000000].contiguous()
+    t_log = time.perf_counter() - t0
+    log(f"c5: {desc.shape[0]} training samples in {t_log:.1f} s")
+    net = Mlp(seed=7)
+    net.fit_normalization(desc, dE)
+    rep, t_train = _timed(lambda: net.train(desc, dE, epochs=10, batch=4096, lr=2e-3, seed=11))
+    log(f"c5: trained {rep} in {t_train:.1f} s")
+
+    d = W.c3(with_velocities=False)
+    n = d["x"].size
+    r_dep = 8.01
+    sp = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
+    plain = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, descriptor=True,
+                  r_dep=r_dep)
+    plain.set_tuning("stage", 1)
+    n_relax = 100
+    plain.sweep(*sp, n_relax, d["seed"])
+    # held-out accuracy on the polycrystal itself
+    plain.enable_sample_log(200000, 97)
+    plain.sweep(*sp, 2, d["seed"] + 1)
+    hd, he = plain.samples()
+    pred = net.forward(hd.contiguous())
+    rmse = float(torch.sqrt(torch.mean((pred - he) ** 2)))
+    std_e = float(torch.std(he))
+    plain.disable_sample_log()
+    da = VCSGC(d["x"], d["y"], d["z"], d["box"], plain.species.cpu().numpy(), pot,
+               descriptor=True, r_dep=r_dep)
+    da.set_surrogate("mlp", net)
+    n_blocks = max(1, (args.sweeps or 400) // 10)
+    res = {}
+    for name, g, seed in (("plain", plain, 5005), ("da", da, 5005)):
+        g.sweep(*sp, 2, seed + 999)  # warmup
+        cs, es, trials, flips, pass1, secs = [], [], 0, 0, 0, 0.0
+        for k in range(n_blocks):
+            s, dt = _timed(lambda: g.sweep(*sp, 10, seed))
+            secs += dt
+            trials += s["trials"]
+            flips += s["flips"]
+            pass1 += s["stage1_pass"]
+            cs.append(s["sum_n"] / 10 / n)
+            es.append(g.energy() / n)
+        cm, ce = _blocked(cs)
+        em, ee = _blocked(es)
+        res[name] = {"trials_per_s": round(trials / secs, 1),
+                     "exact_accepted_per_s": round(flips / secs, 1),
+                     "ms_per_sweep": round(secs / (10 * n_blocks) * 1e3, 3),
+                     "pre_rejection_rate": (round(1.0 - pass1 / trials, 5) if name == "da"
+                                            else 0.0),
+                     "mean_c": cm, "mean_c_err": ce, "mean_E_per_atom": em, "mean_E_err": ee}
+        log(f"c5 {name}: {res[name]}")
+    z = {}
+    for key, err in (("mean_c", "mean_c_err"), ("mean_E_per_atom", "mean_E_err")):
+        z[key] = abs(res["plain"][key] - res["da"][key]) / max(
+            1e-30, float(np.hypot(res["plain"][err], res["da"][err])))
+    out = {"metric": "MC trials/s @2M atoms, plain vs surrogate-DA (same <c>, <E>)",
+           "value": res["da"]["trials_per_s"], "unit": "trials/s", "workload": "c5-surrogate-da",
+           "n_sites": n, "r_dep": r_dep, "relax_sweeps": n_relax, "sweeps_each": 10 * n_blocks,
+           "plain": res["plain"], "da": res["da"],
+           "speedup_trials": round(res["da"]["trials_per_s"] / res["plain"]["trials_per_s"], 3),
+           "z_c": round(z["mean_c"], 3), "z_E": round(z["mean_E_per_atom"], 3),
+           "surrogate": {"train_samples": int(desc.shape[0]), "log_seconds": round(t_log, 2),
+                         "train_seconds": round(t_train, 2),
+                         "loss_first": rep["loss_first"], "loss_last": rep["loss_last"],
+                         "steps": rep["steps"], "heldout_rmse_eV": rmse,
+                         "heldout_dE_std_eV": std_e, "heldout_samples": int(hd.shape[0])}}
+    plain.close()
+    da.close()
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +258,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
+                    help="c3: hybrid cycle (default line); c4: replica batch; c5: surrogate DA")
+    ap.add_argument("--sweeps", type=int, default=0, help="c4/c5: timed sweeps")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -110,6 +272,13 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calib:
         copy_calib()
+        return
+
+    if args.workload == "c4":
+        print(json.dumps(bench_replicas(args)), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(bench_surrogate(args)), flush=True)
         return
 
     from paper_1012_5082_amd import inputs as I

@@ -33,6 +33,10 @@ extern "C" {
 #endif
 
 typedef struct vcsgc_ctx vcsgc_ctx; /* opaque, library-owned */
+typedef struct vcsgc_mlp vcsgc_mlp; /* opaque surrogate network, library-owned */
+
+/* vcsgc_system.flags */
+#define VCSGC_FLAG_DESCRIPTOR 1u /* keep the r < 4.41 A descriptor list (surrogate, sample log) */
 
 typedef enum {
   VCSGC_OK = 0,
@@ -64,7 +68,7 @@ typedef struct {
   vcsgc_eam_fs pot;
   double skin;   /* MD neighbour-list skin (A), >= 0; typical 0.3 */
   double r_dep;  /* independence distance for the cell colouring; 0 => 2 rc */
-  uint32_t flags;        /* reserved, 0 */
+  uint32_t flags;        /* VCSGC_FLAG_* */
 } vcsgc_system;
 
 /* Per-call statistics (host struct). */
@@ -77,6 +81,7 @@ typedef struct {
   int64_t near_ties;      /* decisions with |ln u + x| < 1e-9 */
   int64_t n_final;        /* n_B after the call */
   double sum_n, sum_n2;   /* sum over sweeps of n_B and n_B^2 after each sweep */
+  int64_t stage1_pass;    /* trials passing the surrogate stage (= trials without one) */
 } vcsgc_stats;
 
 typedef struct {
@@ -231,6 +236,73 @@ typedef struct {
 vcsgc_status vcsgc_kernel_timing(vcsgc_ctx *ctx, uint32_t mask);
 /* Accumulated times since the last vcsgc_kernel_timing call (synchronizes). */
 vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *ctx, vcsgc_ktimes *out);
+
+/* ---- surrogate delayed acceptance -------------------------------------
+ * A small network (10 -> 64 -> 64 -> 1, SiLU; BF16 weights and activations
+ * on the MFMA units, FP32 accumulation) predicts the transmutation energy
+ * change from a local descriptor of the site:
+ *   [s_i, nB1, nB2, nB3, n1, n2, n3, rho1, rho2, rho3]
+ * (species of the site; B and total neighbour counts and mean neighbour
+ * density in the shells r < 2.68, [2.68, 3.46), [3.46, 4.41) A).  It is used
+ * only as the first stage of a delayed-acceptance test (Christen and Fox):
+ * the exact FP64 energy change decides every accepted move, so the sampled
+ * ensemble is that of vcsgc_sweep.  Contexts need VCSGC_FLAG_DESCRIPTOR. */
+
+typedef struct {
+  int64_t epochs;   /* passes over the samples */
+  int64_t batch;    /* minibatch size (samples drawn with replacement) */
+  double lr, beta1, beta2, eps; /* Adam */
+  uint64_t seed;    /* minibatch draws */
+} vcsgc_train_cfg;
+
+typedef struct {
+  double loss_first, loss_last; /* mean squared error of the normalized output */
+  int64_t steps;
+} vcsgc_train_report;
+
+/* New network with random FP32 weights (seed) on the calling device. */
+vcsgc_status vcsgc_mlp_create(uint64_t seed, hipStream_t stream, vcsgc_mlp **out);
+vcsgc_status vcsgc_mlp_destroy(vcsgc_mlp *m);
+/* Host copies of the 4929 parameters (w1[64][10], b1[64], w2[64][64], b2[64],
+ * w3[64], b3) and of the normalization (mu[10], sd[10], out_mu, out_sd). */
+vcsgc_status vcsgc_mlp_set_params(vcsgc_mlp *m, const float *params, const float *mu,
+                                  const float *sd, float out_mu, float out_sd);
+vcsgc_status vcsgc_mlp_get_params(vcsgc_mlp *m, float *params, float *mu, float *sd,
+                                  float *out_mu, float *out_sd);
+/* Input and output normalization from n samples (device arrays
+ * desc[n][10] FP64, dE[n] eV): per-column mean and standard deviation. */
+vcsgc_status vcsgc_mlp_fit_normalization(vcsgc_mlp *m, const double *desc_dev,
+                                         const double *dE_dev, int64_t n);
+/* Train on n device samples (Adam on FP32 master weights, mean squared error
+ * of the normalized output); report may be NULL. */
+vcsgc_status vcsgc_mlp_train(vcsgc_mlp *m, const double *desc_dev, const double *dE_dev,
+                             int64_t n, const vcsgc_train_cfg *cfg, vcsgc_train_report *report);
+/* dE_dev[k] = network(desc_dev[k]) in eV for n samples. */
+vcsgc_status vcsgc_mlp_forward(vcsgc_mlp *m, const double *desc_dev, int64_t n, double *dE_dev);
+/* Gradient of the loss over all n samples (host, 4929 floats) and the loss. */
+vcsgc_status vcsgc_mlp_grad(vcsgc_mlp *m, const double *desc_dev, const double *dE_dev, int64_t n,
+                            float *grad_host, double *loss);
+
+/* Record (descriptor, exact dU) of every stride-th trial of later sweeps into
+ * caller device buffers desc_dev[cap][10], dE_dev[cap] (training samples);
+ * NULL buffers stop recording.  Needs VCSGC_FLAG_DESCRIPTOR. */
+vcsgc_status vcsgc_set_sample_log(vcsgc_ctx *ctx, double *desc_dev, double *dE_dev, int64_t cap,
+                                  int64_t stride);
+vcsgc_status vcsgc_sample_count(vcsgc_ctx *ctx, int64_t *n_logged);
+
+/* Surrogate stage for later sweeps: mode 0 plain, 1 the network m, 2 perfect
+ * surrogate (dE = exact dU; equals the plain chain), 3 zero surrogate.  Mode 1
+ * needs VCSGC_FLAG_DESCRIPTOR and r_dep >= 4.41 + rc (the descriptor reads
+ * densities that depend on species up to that distance).  The network must
+ * outlive its use.  Delayed acceptance runs with per-stage launches. */
+vcsgc_status vcsgc_set_surrogate(vcsgc_ctx *ctx, const vcsgc_mlp *m, int32_t mode);
+/* While enabled, every delayed-acceptance trial appends (w, s, cell, dE_f,
+ * dE_r or NaN) to a caller device buffer of cap rows. */
+vcsgc_status vcsgc_set_surrogate_log(vcsgc_ctx *ctx, double *log_dev, int64_t cap);
+/* Descriptors (out_dev[n][10]) of the given sites at the current state, or of
+ * the states with each site flipped (flip != 0).  Diagnostics. */
+vcsgc_status vcsgc_descriptors(vcsgc_ctx *ctx, const int32_t *sites_dev, int64_t n, int32_t flip,
+                               double *out_dev);
 
 /* Diagnostics: out[i] = sqrt(in[i]) in FP64 on the device, n >= 0. */
 vcsgc_status vcsgc_selftest_sqrt(const double *in_dev, double *out_dev, int64_t n,

@@ -427,13 +427,19 @@ static int or_over(const double *over, int64_t n_over, int64_t w, int64_t s, int
  *   4. if accepted every locally accepted flip is committed (rho cache updated).
  * key = (seed, replica).
  */
-int or_sweep(int64_t n, const double *x, const double *y, const double *z, const double box[3],
-             const int64_t *start, const int32_t *nj, const double *nr,
-             uint8_t *species, double *rho, int64_t *n_b, const or_pot *p,
-             const or_sweep_args *a, double *vx, double *vy, double *vz,
-             double *tlog, int64_t tcap, int64_t *tn,
-             double *slog, int64_t scap, int64_t *sn,
-             const double *over, int64_t n_over, or_stats *st) {
+static int or_da_local(const or_da *da, int64_t w, int64_t s, int64_t c, int64_t i,
+                       const int64_t *start, const int32_t *nj, const double *nr,
+                       const uint8_t *species, const double *rho, const or_pot *p,
+                       double beta, double dmu0, const uint64_t t[4], double *du_out,
+                       double *margin_out, int *pass1, int *status);
+
+static int sweep_core(int64_t n, const double *x, const double *y, const double *z,
+                      const double box[3], const int64_t *start, const int32_t *nj,
+                      const double *nr, uint8_t *species, double *rho, int64_t *n_b,
+                      const or_pot *p, const or_sweep_args *a, double *vx, double *vy,
+                      double *vz, double *tlog, int64_t tcap, int64_t *tn, double *slog,
+                      int64_t scap, int64_t *sn, const double *over, int64_t n_over,
+                      or_stats *st, or_da *da) {
   if (n < 1 || !(a->temp > 0.0) || !(a->kappa >= 0.0)) return -1;
   int32_t nc[3] = {1, 1, 1};
   int64_t ncells = 1;
@@ -494,17 +500,31 @@ int or_sweep(int64_t n, const double *x, const double *y, const double *z, const
         uint64_t tc[4] = {(uint64_t)w, (uint64_t)s, (uint64_t)c, 1}, t[4];
         or_philox4x64_10(key, tc, t);
         int64_t i = catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m)];
-        double u = or_unit(t[1]);
-        double du = or_delta_u(i, start, nj, nr, species, rho, p);
         int dn = 1 - 2 * (int)species[i];
-        double xl = beta * (du + a->dmu0 * (double)dn);
-        double lnu = log(u);
-        double margin = lnu + xl;
-        int acc = lnu < -xl;
-        if (fabs(margin) < OR_TIE) {
-          st->near_ties++;
-          int dec;
-          if (over && or_over(over, n_over, w, s, c, &dec)) acc = dec;
+        double du, margin;
+        int acc;
+        if (da && da->mode != OR_DA_OFF) {
+          int pass1 = 0, status = 0;
+          acc = or_da_local(da, w, s, c, i, start, nj, nr, species, rho, p, beta, a->dmu0, t,
+                            &du, &margin, &pass1, &status);
+          if (status) {
+            free(rec); free(cstart); free(catoms); free(cof); free(ccol);
+            return status;
+          }
+          if (pass1) da->stage1_pass++;
+          if (fabs(margin) < OR_TIE) st->near_ties++;
+        } else {
+          double u = or_unit(t[1]);
+          du = or_delta_u(i, start, nj, nr, species, rho, p);
+          double xl = beta * (du + a->dmu0 * (double)dn);
+          double lnu = log(u);
+          margin = lnu + xl;
+          acc = lnu < -xl;
+          if (fabs(margin) < OR_TIE) {
+            st->near_ties++;
+            int dec;
+            if (over && or_over(over, n_over, w, s, c, &dec)) acc = dec;
+          }
         }
         st->trials++;
         if (acc) {
@@ -571,6 +591,239 @@ int or_sweep(int64_t n, const double *x, const double *y, const double *z, const
   free(cof);
   free(ccol);
   return 0;
+}
+
+int or_sweep(int64_t n, const double *x, const double *y, const double *z, const double box[3],
+             const int64_t *start, const int32_t *nj, const double *nr,
+             uint8_t *species, double *rho, int64_t *n_b, const or_pot *p,
+             const or_sweep_args *a, double *vx, double *vy, double *vz,
+             double *tlog, int64_t tcap, int64_t *tn,
+             double *slog, int64_t scap, int64_t *sn,
+             const double *over, int64_t n_over, or_stats *st) {
+  return sweep_core(n, x, y, z, box, start, nj, nr, species, rho, n_b, p, a, vx, vy, vz, tlog,
+                    tcap, tn, slog, scap, sn, over, n_over, st, NULL);
+}
+
+int or_sweep_da(int64_t n, const double *x, const double *y, const double *z, const double box[3],
+                const int64_t *start, const int32_t *nj, const double *nr,
+                uint8_t *species, double *rho, int64_t *n_b, const or_pot *p,
+                const or_sweep_args *a, or_da *da,
+                double *tlog, int64_t tcap, int64_t *tn,
+                double *slog, int64_t scap, int64_t *sn, or_stats *st) {
+  if (!da) return -1;
+  da->stage1_pass = 0;
+  return sweep_core(n, x, y, z, box, start, nj, nr, species, rho, n_b, p, a, NULL, NULL, NULL,
+                    tlog, tcap, tn, slog, scap, sn, NULL, 0, st, da);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Surrogate: descriptor, bfloat16 rounding, MLP, delayed acceptance         */
+/* ------------------------------------------------------------------------ */
+static int or_shell(double r) {
+  if (r < 2.68) return 0;
+  if (r < 3.46) return 1;
+  if (r < 4.41) return 2;
+  return -1;
+}
+
+void or_descriptor(int64_t i, const int64_t *start, const int32_t *nj, const double *nr,
+                   const uint8_t *species, const double *rho, const or_pot *p, int flip,
+                   double out[10]) {
+  int s = species[i], s1 = 1 - s;
+  double cnt[3] = {0.0, 0.0, 0.0}, cb[3] = {0.0, 0.0, 0.0}, rs[3] = {0.0, 0.0, 0.0};
+  for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+    int k = or_shell(nr[e]);
+    if (k < 0) continue;
+    int32_t j = nj[e];
+    double rj = rho[j];
+    if (flip) {
+      /* the density of j in the flipped state: the commit's aggregated shift */
+      int64_t e0 = e;
+      while (e0 > start[i] && nj[e0 - 1] == j) --e0;
+      double delta = 0.0;
+      int any = 0;
+      for (int64_t e2 = e0; e2 < start[i + 1] && nj[e2] == j; ++e2) {
+        if (!(nr[e2] < p->rc)) continue;
+        delta += or_f(p, s1, nr[e2]) - or_f(p, s, nr[e2]);
+        any = 1;
+      }
+      if (any) rj = rj + delta;
+    }
+    cnt[k] += 1.0;
+    cb[k] += (double)species[j];
+    rs[k] += rj;
+  }
+  out[0] = (double)(flip ? s1 : s);
+  for (int k = 0; k < 3; ++k) {
+    out[1 + k] = cb[k];
+    out[4 + k] = cnt[k];
+    out[7 + k] = cnt[k] > 0.0 ? rs[k] / cnt[k] : 0.0;
+  }
+}
+
+float or_bf16(float v) {
+  uint32_t b;
+  memcpy(&b, &v, sizeof(b));
+  b = b + 0x7FFFu + ((b >> 16) & 1u);
+  b &= 0xFFFF0000u;
+  float r;
+  memcpy(&r, &b, sizeof(r));
+  return r;
+}
+
+static double or_sig(double a) { return 1.0 / (1.0 + exp(-a)); }
+
+/* one sample: activations kept for the gradient */
+typedef struct {
+  double z[10], a1[64], h1[64], a2[64], h2[64], y;
+} or_act;
+
+static double or_w(float w, int bf16) { return bf16 ? (double)or_bf16(w) : (double)w; }
+
+static void or_mlp_one(const or_mlp *m, const double *d, int bf16, or_act *A) {
+  for (int k = 0; k < 10; ++k) {
+    float zk = (float)((d[k] - (double)m->mu[k]) / (double)m->sd[k]);
+    A->z[k] = bf16 ? (double)or_bf16(zk) : (double)zk;
+  }
+  for (int j = 0; j < 64; ++j) {
+    double acc = (double)m->b1[j];
+    for (int k = 0; k < 10; ++k) acc += or_w(m->w1[j * 10 + k], bf16) * A->z[k];
+    A->a1[j] = acc;
+    double h = acc * or_sig(acc);
+    A->h1[j] = bf16 ? (double)or_bf16((float)h) : h;
+  }
+  for (int j = 0; j < 64; ++j) {
+    double acc = (double)m->b2[j];
+    for (int k = 0; k < 64; ++k) acc += or_w(m->w2[j * 64 + k], bf16) * A->h1[k];
+    A->a2[j] = acc;
+    double h = acc * or_sig(acc);
+    A->h2[j] = bf16 ? (double)or_bf16((float)h) : h;
+  }
+  double y = (double)m->b3[0];
+  for (int k = 0; k < 64; ++k) y += or_w(m->w3[k], bf16) * A->h2[k];
+  A->y = y;
+}
+
+void or_mlp_forward(const or_mlp *m, int64_t n, const double *d, int bf16, double *y, double *dE) {
+  or_act A;
+  for (int64_t b = 0; b < n; ++b) {
+    or_mlp_one(m, d + 10 * b, bf16, &A);
+    if (y) y[b] = A.y;
+    if (dE) dE[b] = A.y * (double)m->out_sd + (double)m->out_mu;
+  }
+}
+
+/* d SiLU / da = s (1 + a (1 - s)), s = sigmoid(a) */
+static double or_dsilu(double a) {
+  double sg = or_sig(a);
+  return sg * (1.0 + a * (1.0 - sg));
+}
+
+static double or_bfd(double v, int bf16) { return bf16 ? (double)or_bf16((float)v) : v; }
+
+double or_mlp_grad(const or_mlp *m, int64_t n, const double *d, const double *t, int bf16,
+                   double *grad) {
+  double *gw1 = grad, *gb1 = grad + 640, *gw2 = grad + 704, *gb2 = grad + 4800,
+         *gw3 = grad + 4864, *gb3 = grad + 4928;
+  memset(grad, 0, 4929 * sizeof(double));
+  double loss = 0.0;
+  or_act A;
+  for (int64_t b = 0; b < n; ++b) {
+    or_mlp_one(m, d + 10 * b, bf16, &A);
+    double tn = (t[b] - (double)m->out_mu) / (double)m->out_sd;
+    double r = A.y - tn;
+    loss += r * r;
+    double dy = 2.0 * r / (double)n;
+    gb3[0] += dy;
+    double da2[64], da1[64];
+    for (int k = 0; k < 64; ++k) {
+      gw3[k] += dy * A.h2[k];
+      double dh2 = dy * or_w(m->w3[k], bf16);
+      da2[k] = dh2 * or_dsilu(A.a2[k]);
+    }
+    for (int j = 0; j < 64; ++j) {
+      gb2[j] += da2[j];
+      double dq = or_bfd(da2[j], bf16);
+      for (int k = 0; k < 64; ++k) gw2[j * 64 + k] += dq * A.h1[k];
+    }
+    for (int k = 0; k < 64; ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < 64; ++j) acc += or_bfd(da2[j], bf16) * or_w(m->w2[j * 64 + k], bf16);
+      da1[k] = acc * or_dsilu(A.a1[k]);
+    }
+    for (int j = 0; j < 64; ++j) {
+      gb1[j] += da1[j];
+      double dq = or_bfd(da1[j], bf16);
+      for (int k = 0; k < 10; ++k) gw1[j * 10 + k] += dq * A.z[k];
+    }
+  }
+  return loss / (double)n;
+}
+
+static int or_table_find(const or_da *da, int64_t w, int64_t s, int64_t c, double *f, double *r) {
+  int64_t lo = 0, hi = da->n_table - 1;
+  while (lo <= hi) {
+    int64_t mid = (lo + hi) / 2;
+    const double *row = da->table + 5 * mid;
+    int64_t rw = (int64_t)row[0], rs = (int64_t)row[1], rc = (int64_t)row[2];
+    int cmp = rw != w ? (rw < w ? -1 : 1) : (rs != s ? (rs < s ? -1 : 1) : (rc != c ? (rc < c ? -1 : 1) : 0));
+    if (cmp == 0) {
+      *f = row[3];
+      *r = row[4];
+      return 1;
+    }
+    if (cmp < 0) lo = mid + 1; else hi = mid - 1;
+  }
+  return 0;
+}
+
+/* Delayed-acceptance local test (stage 1 with the surrogate, stage 2 exact). */
+static int or_da_local(const or_da *da, int64_t w, int64_t s, int64_t c, int64_t i,
+                       const int64_t *start, const int32_t *nj, const double *nr,
+                       const uint8_t *species, const double *rho, const or_pot *p,
+                       double beta, double dmu0, const uint64_t t[4], double *du_out,
+                       double *margin_out, int *pass1, int *status) {
+  int dn = 1 - 2 * (int)species[i];
+  double ef = 0.0, er = 0.0, du = NAN;
+  int have_du = 0;
+  *status = 0;
+  if (da->mode == OR_DA_TABLE) {
+    if (!or_table_find(da, w, s, c, &ef, &er)) {
+      *status = -3;
+      return 0;
+    }
+  } else if (da->mode == OR_DA_PERFECT) {
+    du = or_delta_u(i, start, nj, nr, species, rho, p);
+    have_du = 1;
+    ef = du;
+    er = -du;
+  } else if (da->mode == OR_DA_MLP) {
+    double dx[10], dy[10];
+    or_descriptor(i, da->dstart, da->dnj, da->dnr, species, rho, p, 0, dx);
+    or_descriptor(i, da->dstart, da->dnj, da->dnr, species, rho, p, 1, dy);
+    or_mlp_forward(da->mlp, 1, dx, 1, NULL, &ef);
+    or_mlp_forward(da->mlp, 1, dy, 1, NULL, &er);
+  }
+  /* stage 1: min{1, exp(-beta s_f)}, s_f = dE_f + dmu0 dn */
+  double sf = ef + dmu0 * (double)dn;
+  double x1 = beta * sf;
+  double lnu1 = log(or_unit(t[1]));
+  *pass1 = lnu1 < -x1;
+  if (!*pass1) {
+    *du_out = NAN;
+    *margin_out = lnu1 + x1;
+    return 0;
+  }
+  /* stage 2: exp(-beta (dU + dmu0 dn)) min{1, exp(-beta s_r)} / min{1, exp(-beta s_f)} */
+  if (!have_du) du = or_delta_u(i, start, nj, nr, species, rho, p);
+  double sr = er - dmu0 * (double)dn;
+  double xl = beta * (du + dmu0 * (double)dn);
+  double xr = -(beta * sr);
+  double l2 = (-xl + (xr < 0.0 ? xr : 0.0)) - (-x1 < 0.0 ? -x1 : 0.0);
+  double lnu2 = log(or_unit(t[2]));
+  *du_out = du;
+  *margin_out = lnu2 - l2;
+  return lnu2 < l2;
 }
 
 /* ------------------------------------------------------------------------ */

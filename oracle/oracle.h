@@ -82,6 +82,76 @@ int or_sweep(int64_t n, const double *x, const double *y, const double *z, const
              double *slog, int64_t scap, int64_t *sn,
              const double *over, int64_t n_over, or_stats *st);
 
+/* ---- surrogate delayed acceptance ------------------------------------ */
+
+/* Local descriptor of site i (10 values): [s_i, nB1, nB2, nB3, n1, n2, n3,
+ * rho1, rho2, rho3], shells r < 2.68, [2.68, 3.46), [3.46, 4.41) A; nBk / nk
+ * count B / all neighbours in shell k, rhok is the mean density of the
+ * shell's neighbours (0 for an empty shell).  The list (CSR) must hold every
+ * pair with r < 4.41.  With flip != 0 the descriptor is that of the state
+ * with s_i flipped: rho_j of every neighbour with r < rc is shifted by
+ * f_{s'}(r) - f_s(r) (summed over images). */
+void or_descriptor(int64_t i, const int64_t *start, const int32_t *nj, const double *nr,
+                   const uint8_t *species, const double *rho, const or_pot *p, int flip,
+                   double out[10]);
+
+/* Round a float to bfloat16 (round to nearest, ties to even), returned as a
+ * float holding the rounded value. */
+float or_bf16(float v);
+
+/* MLP 10 -> 64 -> 64 -> 1 with SiLU, parameters in FP32:
+ * w1[64*10], b1[64], w2[64*64], b2[64], w3[64], b3[1]; input normalization
+ * z_k = (float)((d_k - mu_k) / sd_k); output dE = y * out_sd + out_mu.
+ * With bf16 != 0 the operands of the products (z, weights, hidden
+ * activations) are rounded to bfloat16 as the device does; sums are FP64. */
+typedef struct {
+  const float *w1, *b1, *w2, *b2, *w3, *b3, *mu, *sd;
+  float out_mu, out_sd;
+} or_mlp;
+
+/* Forward for n samples of raw descriptors d[n*10] (FP64); y[n] (normalized
+ * output) and dE[n] (eV) may be NULL. */
+void or_mlp_forward(const or_mlp *m, int64_t n, const double *d, int bf16, double *y, double *dE);
+
+/* Mean squared error of the normalized output against (t - out_mu)/out_sd
+ * over n samples and its gradient (FP64) in the parameter order
+ * w1, b1, w2, b2, w3, b3 (4929 values). Returns the loss. */
+double or_mlp_grad(const or_mlp *m, int64_t n, const double *d, const double *t, int bf16,
+                   double *grad);
+
+/* Surrogate modes of the delayed-acceptance sweep. */
+#define OR_DA_OFF 0     /* plain sweep */
+#define OR_DA_TABLE 1   /* surrogate values taken from a table (w, s, cell, fwd, rev) */
+#define OR_DA_PERFECT 2 /* forward = exact dU, reverse = -dU */
+#define OR_DA_ZERO 3    /* forward = reverse = 0 */
+#define OR_DA_MLP 4     /* the MLP above on the descriptors (bf16 emulation) */
+
+typedef struct {
+  int mode;
+  const double *table; /* OR_DA_TABLE: n_table rows (w, s, cell, fwd, rev) sorted by (w, s, cell) */
+  int64_t n_table;
+  const or_mlp *mlp;   /* OR_DA_MLP */
+  const int64_t *dstart; /* descriptor list (r < 4.41), OR_DA_MLP */
+  const int32_t *dnj;
+  const double *dnr;
+  int64_t stage1_pass; /* out: trials passing the surrogate stage */
+} or_da;
+
+/* The same sweep with the delayed-acceptance local test (Christen & Fox):
+ * stage 1 accepts with min{1, exp(-beta (dE_f + dmu0 dn))} using u1 = unit(w1);
+ * a survivor is accepted with
+ *   min{1, exp(-beta (dU + dmu0 dn)) min{1, exp(-beta s_r)} / min{1, exp(-beta s_f)}},
+ * s_f = dE_f + dmu0 dn, s_r = dE_r - dmu0 dn, dE_r the surrogate value for
+ * the reverse move, using u2 = unit(w2); the global factor is unchanged.
+ * The trial log's dU column holds the exact dU for survivors and NaN for
+ * stage-1 rejections; its margin column the margin of the deciding test. */
+int or_sweep_da(int64_t n, const double *x, const double *y, const double *z, const double box[3],
+                const int64_t *start, const int32_t *nj, const double *nr,
+                uint8_t *species, double *rho, int64_t *n_b, const or_pot *p,
+                const or_sweep_args *a, or_da *da,
+                double *tlog, int64_t tcap, int64_t *tn,
+                double *slog, int64_t scap, int64_t *sn, or_stats *st);
+
 /* Velocity Verlet, n_steps steps of dt (fs).  Forces are evaluated at the
  * incoming positions first; on return fx/fy/fz and rho hold the values at the
  * final positions. */

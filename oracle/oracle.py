@@ -52,6 +52,22 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Mlp(C.Structure):
+    _fields_ = [("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p), ("b2", C.c_void_p),
+                ("w3", C.c_void_p), ("b3", C.c_void_p), ("mu", C.c_void_p), ("sd", C.c_void_p),
+                ("out_mu", C.c_float), ("out_sd", C.c_float)]
+
+
+class Da(C.Structure):
+    _fields_ = [("mode", C.c_int), ("table", C.c_void_p), ("n_table", C.c_int64),
+                ("mlp", C.c_void_p), ("dstart", C.c_void_p), ("dnj", C.c_void_p),
+                ("dnr", C.c_void_p), ("stage1_pass", C.c_int64)]
+
+
+DA_MODES = {"off": 0, "table": 1, "perfect": 2, "zero": 3, "mlp": 4}
+DESC_CUTOFF = 4.41
+N_PARAMS = 4929
+
 _P = C.c_void_p
 _lib = None
 
@@ -79,6 +95,15 @@ def lib():
         L.or_sweep.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                _P, _P, _P, _P, C.c_int64, _P, _P, C.c_int64, _P, _P,
                                C.c_int64, _P]
+        L.or_sweep_da.restype = C.c_int
+        L.or_sweep_da.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                  _P, _P, C.c_int64, _P, _P, C.c_int64, _P, _P]
+        L.or_descriptor.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, C.c_int, _P]
+        L.or_bf16.restype = C.c_float
+        L.or_bf16.argtypes = [C.c_float]
+        L.or_mlp_forward.argtypes = [_P, C.c_int64, _P, C.c_int, _P, _P]
+        L.or_mlp_grad.restype = C.c_double
+        L.or_mlp_grad.argtypes = [_P, C.c_int64, _P, _P, C.c_int, _P]
         L.or_md.restype = C.c_int
         L.or_md.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
                             C.c_double, C.c_double, C.c_int64, _P, _P, _P, _P]
@@ -261,3 +286,119 @@ def md(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, mass_a=55.845, mass_
     if rc != 0:
         raise ValueError("or_md failed")
     return x, y, z, vx, vy, vz, fx, fy, fz, rho
+
+
+# ---------------------------------------------------------------------------
+# surrogate
+# ---------------------------------------------------------------------------
+class MlpParams:
+    """FP32 parameters of the 10-64-64-1 SiLU network plus the input and
+    output normalization."""
+
+    def __init__(self, w1, b1, w2, b2, w3, b3, mu, sd, out_mu, out_sd):
+        f = lambda a, shape: np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(shape))  # noqa: E731
+        self.w1, self.b1 = f(w1, (64, 10)), f(b1, (64,))
+        self.w2, self.b2 = f(w2, (64, 64)), f(b2, (64,))
+        self.w3, self.b3 = f(w3, (64,)), f(b3, (1,))
+        self.mu, self.sd = f(mu, (10,)), f(sd, (10,))
+        self.out_mu, self.out_sd = float(np.float32(out_mu)), float(np.float32(out_sd))
+
+    @staticmethod
+    def random(seed=0, mu=None, sd=None, out_mu=0.0, out_sd=1.0, scale=1.0):
+        rng = np.random.default_rng(seed)
+        w1 = rng.normal(0, scale / np.sqrt(10), (64, 10))
+        w2 = rng.normal(0, scale / np.sqrt(64), (64, 64))
+        w3 = rng.normal(0, scale / np.sqrt(64), 64)
+        b1, b2, b3 = rng.normal(0, 0.1, 64), rng.normal(0, 0.1, 64), rng.normal(0, 0.1, 1)
+        mu = np.zeros(10) if mu is None else mu
+        sd = np.ones(10) if sd is None else sd
+        return MlpParams(w1, b1, w2, b2, w3, b3, mu, sd, out_mu, out_sd)
+
+    def flat(self):
+        return np.concatenate([self.w1.ravel(), self.b1, self.w2.ravel(), self.b2, self.w3,
+                               self.b3]).astype(np.float32)
+
+    @staticmethod
+    def from_flat(v, mu, sd, out_mu, out_sd):
+        v = np.asarray(v, dtype=np.float32)
+        return MlpParams(v[:640], v[640:704], v[704:4800], v[4800:4864], v[4864:4928],
+                         v[4928:4929], mu, sd, out_mu, out_sd)
+
+    def struct(self):
+        m = Mlp(*(a.ctypes.data_as(C.c_void_p) for a in
+                  (self.w1, self.b1, self.w2, self.b2, self.w3, self.b3, self.mu, self.sd)),
+                self.out_mu, self.out_sd)
+        m._keep = self
+        return m
+
+
+def bf16(v):
+    return lib().or_bf16(float(v))
+
+
+def descriptor(nl: NeighborList, i, species, rho, pot, flip=False):
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    out = np.zeros(10)
+    P = pot_struct(pot)
+    lib().or_descriptor(int(i), _p(nl.start), _p(nl.j), _p(nl.r), _p(sp), _p(_f64(rho)),
+                        C.byref(P), int(bool(flip)), _p(out))
+    return out
+
+
+def mlp_forward(m: MlpParams, d, bf16_emul=True):
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1, 10))
+    y, dE = np.zeros(d.shape[0]), np.zeros(d.shape[0])
+    ms = m.struct()
+    lib().or_mlp_forward(C.byref(ms), d.shape[0], _p(d), int(bool(bf16_emul)), _p(y), _p(dE))
+    return y, dE
+
+
+def mlp_grad(m: MlpParams, d, t, bf16_emul=False):
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1, 10))
+    t = _f64(t)
+    g = np.zeros(N_PARAMS)
+    ms = m.struct()
+    loss = lib().or_mlp_grad(C.byref(ms), d.shape[0], _p(d), _p(t), int(bool(bf16_emul)), _p(g))
+    return loss, g
+
+
+def sweep_da(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, mode, replica=0, r_dep=None,
+             one_cell=False, table=None, mlp: MlpParams | None = None,
+             desc_nl: NeighborList | None = None, log_trials=0, log_stages=0):
+    """Delayed-acceptance sweeps; returns (stats, stage-1 passes, tlog, slog)."""
+    L = lib()
+    if r_dep is None:
+        r_dep = 2.0 * st.pot.rc
+    a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
+                  int(st.w), int(n_sweeps), float(r_dep), int(bool(one_cell)), 55.845, 63.546)
+    da = Da()
+    da.mode = DA_MODES[mode]
+    keep = []
+    if table is not None:
+        tab = np.ascontiguousarray(np.asarray(table, dtype=np.float64).reshape(-1, 5))
+        tab = tab[np.lexsort((tab[:, 2], tab[:, 1], tab[:, 0]))]
+        keep.append(tab)
+        da.table, da.n_table = tab.ctypes.data_as(C.c_void_p), tab.shape[0]
+    if mlp is not None:
+        ms = mlp.struct()
+        keep.append(ms)
+        da.mlp = C.cast(C.pointer(ms), C.c_void_p)
+    if desc_nl is not None:
+        da.dstart, da.dnj, da.dnr = _p(desc_nl.start), _p(desc_nl.j), _p(desc_nl.r)
+    tlog = np.zeros((max(log_trials, 0), 8)) if log_trials else None
+    slog = np.zeros((max(log_stages, 0), 8)) if log_stages else None
+    tn, sn = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
+    s = Stats()
+    P = pot_struct(st.pot)
+    rc = L.or_sweep_da(st.n, _p(st.x), _p(st.y), _p(st.z), _p(st.box), _p(st.nl.start),
+                       _p(st.nl.j), _p(st.nl.r), _p(st.species), _p(st.rho), _p(st.n_b),
+                       C.byref(P), C.byref(a), C.byref(da), _p(tlog), int(log_trials), _p(tn),
+                       _p(slog), int(log_stages), _p(sn), C.byref(s))
+    if rc != 0:
+        raise ValueError(f"or_sweep_da failed ({rc})")
+    st.w += int(n_sweeps)
+    if tlog is not None:
+        tlog = tlog[:min(int(tn[0]), log_trials)]
+    if slog is not None:
+        slog = slog[:min(int(sn[0]), log_stages)]
+    return s.as_dict(), int(da.stage1_pass), tlog, slog

@@ -42,10 +42,26 @@ class System(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("trials", C.c_int64), ("local_accepts", C.c_int64), ("stages", C.c_int64),
                 ("stage_accepts", C.c_int64), ("flips", C.c_int64), ("near_ties", C.c_int64),
-                ("n_final", C.c_int64), ("sum_n", C.c_double), ("sum_n2", C.c_double)]
+                ("n_final", C.c_int64), ("sum_n", C.c_double), ("sum_n2", C.c_double),
+                ("stage1_pass", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int64), ("batch", C.c_int64), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class TrainReport(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("steps", C.c_int64)]
+
+
+FLAG_DESCRIPTOR = 1
+SURROGATE_MODES = {"off": 0, "mlp": 1, "perfect": 2, "zero": 3}
+N_PARAMS = 4929
 
 
 class State(C.Structure):
@@ -120,6 +136,34 @@ def lib():
         L.vcsgc_get_tuning.restype = st
         L.vcsgc_get_tuning.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32)]
+        L.vcsgc_mlp_create.restype = st
+        L.vcsgc_mlp_create.argtypes = [C.c_uint64, _P, C.POINTER(_P)]
+        L.vcsgc_mlp_destroy.restype = st
+        L.vcsgc_mlp_destroy.argtypes = [_P]
+        L.vcsgc_mlp_set_params.restype = st
+        L.vcsgc_mlp_set_params.argtypes = [_P, _P, _P, _P, C.c_float, C.c_float]
+        L.vcsgc_mlp_get_params.restype = st
+        L.vcsgc_mlp_get_params.argtypes = [_P, _P, _P, _P, C.POINTER(C.c_float),
+                                           C.POINTER(C.c_float)]
+        L.vcsgc_mlp_fit_normalization.restype = st
+        L.vcsgc_mlp_fit_normalization.argtypes = [_P, _P, _P, C.c_int64]
+        L.vcsgc_mlp_train.restype = st
+        L.vcsgc_mlp_train.argtypes = [_P, _P, _P, C.c_int64, C.POINTER(TrainCfg),
+                                      C.POINTER(TrainReport)]
+        L.vcsgc_mlp_forward.restype = st
+        L.vcsgc_mlp_forward.argtypes = [_P, _P, C.c_int64, _P]
+        L.vcsgc_mlp_grad.restype = st
+        L.vcsgc_mlp_grad.argtypes = [_P, _P, _P, C.c_int64, _P, C.POINTER(C.c_double)]
+        L.vcsgc_set_sample_log.restype = st
+        L.vcsgc_set_sample_log.argtypes = [_P, _P, _P, C.c_int64, C.c_int64]
+        L.vcsgc_sample_count.restype = st
+        L.vcsgc_sample_count.argtypes = [_P, C.POINTER(C.c_int64)]
+        L.vcsgc_set_surrogate.restype = st
+        L.vcsgc_set_surrogate.argtypes = [_P, _P, C.c_int32]
+        L.vcsgc_set_surrogate_log.restype = st
+        L.vcsgc_set_surrogate_log.argtypes = [_P, _P, C.c_int64]
+        L.vcsgc_descriptors.restype = st
+        L.vcsgc_descriptors.argtypes = [_P, _P, C.c_int64, C.c_int32, _P]
         L.vcsgc_selftest_sqrt.restype = st
         L.vcsgc_selftest_sqrt.argtypes = [_P, _P, C.c_int64, _P]
         _lib = L
@@ -162,7 +206,8 @@ class VCSGC:
     object (copied from numpy inputs) and borrowed by the library context."""
 
     def __init__(self, x, y, z, box, species, pot, vx=None, vy=None, vz=None, forces=False,
-                 skin=0.3, r_dep=0.0, mass_a=55.845, mass_b=63.546, device="cuda", stream=None):
+                 skin=0.3, r_dep=0.0, mass_a=55.845, mass_b=63.546, device="cuda", stream=None,
+                 descriptor=False):
         import torch
         L = lib()
         self.device = torch.device(device)
@@ -191,7 +236,7 @@ class VCSGC:
         sysd.pot = pot_struct(pot, mass_a, mass_b)
         sysd.skin = float(skin)
         sysd.r_dep = float(r_dep)
-        sysd.flags = 0
+        sysd.flags = FLAG_DESCRIPTOR if descriptor else 0
         self._sys = sysd
         h = _P()
         rc = L.vcsgc_create(C.byref(sysd), _stream_handle(stream), C.byref(h))
@@ -254,6 +299,7 @@ class VCSGC:
         nt, ns = C.c_int64(), C.c_int64()
         self._check(lib().vcsgc_log_counts(self._h, C.byref(nt), C.byref(ns)), "log_counts")
         t, s, tc, sc = self._logs
+        self._logs_n_trials = nt.value
         torch.cuda.synchronize()
         tl = t[:min(nt.value, tc)].cpu().numpy()
         sl = s[:min(ns.value, sc)].cpu().numpy()
@@ -309,6 +355,55 @@ class VCSGC:
                     "get_tuning")
         inv = {v: k for k, v in STRATEGIES.items()}
         return {"strategy": inv[a.value], "trials_per_group": b.value, "workgroups": g.value}
+
+    # -- surrogate ----------------------------------------------------------
+    def set_surrogate(self, mode="off", mlp=None):
+        self._mlp_ref = mlp
+        self._check(lib().vcsgc_set_surrogate(self._h, None if mlp is None else mlp._h,
+                                              SURROGATE_MODES[mode]), "set_surrogate")
+
+    def enable_surrogate_log(self, cap):
+        import torch
+        self._dalog = torch.zeros((max(cap, 1), 5), dtype=torch.float64, device=self.device)
+        self._dacap = cap
+        self._check(lib().vcsgc_set_surrogate_log(self._h, _P(self._dalog.data_ptr()), int(cap)),
+                    "set_surrogate_log")
+
+    def surrogate_log(self):
+        """(w, s, cell, dE_f, dE_r) rows sorted by (w, s, cell); call after logs()."""
+        import torch
+        torch.cuda.synchronize()
+        n = min(int(self._logs_n_trials), self._dacap)
+        a = self._dalog[:n].cpu().numpy()
+        return a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))] if n else a
+
+    def enable_sample_log(self, cap, stride):
+        import torch
+        self._smp_desc = torch.zeros((max(cap, 1), 10), dtype=torch.float64, device=self.device)
+        self._smp_de = torch.zeros(max(cap, 1), dtype=torch.float64, device=self.device)
+        self._smp_cap = cap
+        self._check(lib().vcsgc_set_sample_log(self._h, _P(self._smp_desc.data_ptr()),
+                                               _P(self._smp_de.data_ptr()), int(cap), int(stride)),
+                    "set_sample_log")
+
+    def disable_sample_log(self):
+        self._check(lib().vcsgc_set_sample_log(self._h, None, None, 0, 1), "set_sample_log")
+
+    def samples(self):
+        """(descriptors [n][10], dE [n]) recorded so far, as device tensors."""
+        n = C.c_int64()
+        self._check(lib().vcsgc_sample_count(self._h, C.byref(n)), "sample_count")
+        k = min(n.value, self._smp_cap)
+        return self._smp_desc[:k], self._smp_de[:k]
+
+    def descriptors(self, sites, flip=False):
+        import torch
+        s = torch.as_tensor(np.asarray(sites, dtype=np.int32), device=self.device)
+        out = torch.zeros((s.numel(), 10), dtype=torch.float64, device=self.device)
+        self._check(lib().vcsgc_descriptors(self._h, _P(s.data_ptr()), s.numel(), int(bool(flip)),
+                                            _P(out.data_ptr())), "descriptors")
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
 
     def info(self):
         i = Info()
@@ -378,3 +473,74 @@ class VCSGCBatch(VCSGC):
     def replica_rho(self, r):
         rho = self.rho().cpu().numpy()
         return rho[self.offsets[r]:self.offsets[r + 1]]
+
+
+class Mlp:
+    """Surrogate network handle (device parameters, training, inference)."""
+
+    def __init__(self, seed=0, stream=None):
+        h = _P()
+        rc = lib().vcsgc_mlp_create(int(seed), _stream_handle(stream), C.byref(h))
+        if rc:
+            raise VcsgcError(rc, "mlp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vcsgc_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc:
+            raise VcsgcError(rc, what)
+
+    def set_params(self, flat, mu, sd, out_mu, out_sd):
+        f = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32))  # noqa: E731
+        p, m, s = f(flat), f(mu), f(sd)
+        self._check(lib().vcsgc_mlp_set_params(self._h, p.ctypes.data_as(_P), m.ctypes.data_as(_P),
+                                               s.ctypes.data_as(_P), float(out_mu), float(out_sd)),
+                    "set_params")
+
+    def get_params(self):
+        p = np.zeros(N_PARAMS, dtype=np.float32)
+        mu = np.zeros(10, dtype=np.float32)
+        sd = np.zeros(10, dtype=np.float32)
+        om, osd = C.c_float(), C.c_float()
+        self._check(lib().vcsgc_mlp_get_params(self._h, p.ctypes.data_as(_P), mu.ctypes.data_as(_P),
+                                               sd.ctypes.data_as(_P), C.byref(om), C.byref(osd)),
+                    "get_params")
+        return p, mu, sd, om.value, osd.value
+
+    def fit_normalization(self, desc, dE):
+        self._check(lib().vcsgc_mlp_fit_normalization(self._h, _P(desc.data_ptr()),
+                                                      _P(dE.data_ptr()), desc.shape[0]),
+                    "fit_normalization")
+
+    def train(self, desc, dE, epochs=10, batch=4096, lr=1e-3, seed=0):
+        cfg = TrainCfg(int(epochs), int(batch), float(lr), 0.9, 0.999, 1e-8, int(seed))
+        rep = TrainReport()
+        self._check(lib().vcsgc_mlp_train(self._h, _P(desc.data_ptr()), _P(dE.data_ptr()),
+                                          desc.shape[0], C.byref(cfg), C.byref(rep)), "train")
+        return {"loss_first": rep.loss_first, "loss_last": rep.loss_last, "steps": rep.steps}
+
+    def forward(self, desc):
+        import torch
+        out = torch.zeros(desc.shape[0], dtype=torch.float64, device=desc.device)
+        self._check(lib().vcsgc_mlp_forward(self._h, _P(desc.data_ptr()), desc.shape[0],
+                                            _P(out.data_ptr())), "forward")
+        torch.cuda.synchronize()
+        return out
+
+    def grad(self, desc, dE):
+        g = np.zeros(N_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        self._check(lib().vcsgc_mlp_grad(self._h, _P(desc.data_ptr()), _P(dE.data_ptr()),
+                                         desc.shape[0], g.ctypes.data_as(_P), C.byref(loss)),
+                    "grad")
+        return loss.value, g

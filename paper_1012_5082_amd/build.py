@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvcsgc.so")
-SOURCES = ["capi.hip", "cells.hip", "sweep.hip", "md.hip", "persist.hip"]
+SOURCES = ["capi.hip", "cells.hip", "sweep.hip", "md.hip", "persist.hip", "surrogate.hip"]
 ARCH = "gfx950"
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -26,7 +26,8 @@ void free_all(vcsgc_ctx *c) {
                   c->mc_g,       c->mc_cnt,     c->md_j,       c->md_cnt,    c->xr,   c->yr,
                   c->zr,         c->rho,        c->rho_f,      c->fp,        c->eatom, c->red,
                   c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
-                  c->d_reps,     c->d_rs,       c->d_wg_rep};
+                  c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
+                  c->d_cnt};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -88,6 +89,7 @@ vcsgc_status refresh_mc(vcsgc_ctx *c) {
       VC_CHECK(c, vc::launch_bin_cells(c, r), "binning");
       VC_CHECK(c, vc::launch_bin_search(c, r), "binning");
       VC_CHECK(c, vc::launch_build_mc_list(c, r), "neighbour list");
+      if (c->desc) VC_CHECK(c, vc::launch_build_desc_list(c, r), "descriptor list");
     }
     VC_CHECK(c, vc::launch_mc_row_stats(c), "neighbour list");
     VC_CHECK(c, vc::launch_density_mc(c), "density");
@@ -317,7 +319,12 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
       if (r.nc[d] < 2)
         return fail(nullptr, VCSGC_E_BOX_TOO_SMALL,
                     "box must hold two cells of edge r_dep in every dimension");
-      r.nb[d] = (int)std::floor(r.box[d] / (P.rc + sys->skin));
+      const double bin_edge = (sys->flags & VCSGC_FLAG_DESCRIPTOR)
+                                  ? std::max(P.rc + sys->skin, vc::DESC_CUT)
+                                  : P.rc + sys->skin;
+      r.nb[d] = (int)std::floor(r.box[d] / bin_edge);
+      if (r.nb[d] < 2)
+        return fail(nullptr, VCSGC_E_BOX_TOO_SMALL, "box too small for the neighbour search");
     }
     r.ncells = (int64_t)r.nc[0] * r.nc[1] * r.nc[2];
     r.coff = coff;
@@ -378,6 +385,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   p.cm[1] = P.mass_b > 0.0 ? vc::ACC / P.mass_b : 0.0;
   c->bmax = 16;
   c->strategy = 0;
+  c->desc = (sys->flags & VCSGC_FLAG_DESCRIPTOR) != 0;
 
   const int64_t n = c->n, K = vc::KMAX;
   const bool single = R == 1;
@@ -407,6 +415,11 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->fp, n));
     A(dalloc(&c->eatom, n));
   }
+  if (c->desc) {
+    A(dalloc(&c->d_j, K * n));
+    A(dalloc(&c->d_r, K * n));
+    A(dalloc(&c->d_cnt, n));
+  }
   A(dalloc(&c->rho, n));
   A(dalloc(&c->red, (n + vc::BLOCK - 1) / vc::BLOCK + 8));
   A(dalloc(&c->rec, roff));
@@ -434,7 +447,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   // trial-kernel partial sums: the larger of the two strategies' needs
   const int64_t npart_stage = (r0.ncpc * 16 + vc::BLOCK - 1) / vc::BLOCK + 1;
   c->npart = std::max<int64_t>(npart_stage, c->grid_total);
-  if ((e = dalloc(&c->part, 4 * c->npart)) != hipSuccess) return bail(dev_fail(c, e, "allocation"));
+  if ((e = dalloc(&c->part, vc::NPART * c->npart)) != hipSuccess)
+    return bail(dev_fail(c, e, "allocation"));
   if ((e = hipMemsetAsync(c->ds, 0, sizeof(vc::DevState), c->stream)) != hipSuccess)
     return bail(dev_fail(c, e, "init"));
   for (const RepHost &r : c->reps) {
@@ -512,7 +526,8 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
     vcsgc_status st = refresh_mc(c);
     if (st) return st;
   }
-  if (c->strategy == 2 && R == 1) {
+  // delayed acceptance and the training-sample log run with per-stage launches
+  if ((c->strategy == 2 || c->da_mode || c->smp_cap > 0) && R == 1) {
     // one trial kernel and one commit kernel per stage
     VC_CHECK(c, vc::persist_sync_nb_to_stage(c), "sweep");
     VC_CHECK(c, vc::launch_sweeps(c, dmu0[0], kappa[0], cbar[0], T[0], n_sweeps, seed), "sweep");
@@ -531,6 +546,7 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
       out->n_final = h.n_b_cur;
       out->sum_n = h.sum_n;
       out->sum_n2 = h.sum_n2;
+      out->stage1_pass = (int64_t)h.stage1_pass;
     }
     return VCSGC_OK;
   }
@@ -587,7 +603,7 @@ vcsgc_status vcsgc_set_tuning(vcsgc_ctx *c, int32_t strategy, int32_t trials_per
       (void)hipFree(c->part);
       c->part = nullptr;
       c->npart = c->grid_total;
-      VC_CHECK(c, dalloc(&c->part, 4 * c->npart), "allocation");
+      VC_CHECK(c, dalloc(&c->part, vc::NPART * c->npart), "allocation");
     }
   }
   return VCSGC_OK;
@@ -759,6 +775,83 @@ vcsgc_status vcsgc_get_info(vcsgc_ctx *c, vcsgc_info *out) {
   out->mc_pairs = c->mc_valid ? (int64_t)h.pairs_mc : 0;
   out->md_pairs = c->md_valid ? (int64_t)h.pairs_md : 0;
   out->md_rebuilds = c->md_rebuilds;
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_set_sample_log(vcsgc_ctx *c, double *desc_dev, double *dE_dev, int64_t cap,
+                                  int64_t stride) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (desc_dev && (!c->desc || !dE_dev || cap < 0 || stride < 1))
+    return fail(c, VCSGC_E_INVALID_ARG,
+                "sample log needs VCSGC_FLAG_DESCRIPTOR, both buffers, cap >= 0, stride >= 1");
+  if (desc_dev && c->reps.size() != 1)
+    return fail(c, VCSGC_E_INVALID_ARG, "sample log needs a single-system context");
+  c->smp_desc = desc_dev;
+  c->smp_de = desc_dev ? dE_dev : nullptr;
+  c->smp_cap = desc_dev ? cap : 0;
+  c->smp_stride = stride < 1 ? 1 : stride;
+  const unsigned long long zero = 0;
+  VC_CHECK(c, hipMemcpyAsync(&c->ds->smp_n, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream),
+           "reset");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_sample_count(vcsgc_ctx *c, int64_t *n_logged) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (!n_logged) return fail(c, VCSGC_E_INVALID_ARG, "null output");
+  hipError_t e;
+  vc::DevState h = read_state(c, &e);
+  if (e != hipSuccess) return dev_fail(c, e, "sample count");
+  *n_logged = (int64_t)h.smp_n;
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_set_surrogate(vcsgc_ctx *c, const vcsgc_mlp *m, int32_t mode) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (mode < 0 || mode > 3) return fail(c, VCSGC_E_INVALID_ARG, "mode must be in [0, 3]");
+  if (mode != 0 && c->reps.size() != 1)
+    return fail(c, VCSGC_E_INVALID_ARG, "delayed acceptance needs a single-system context");
+  if (mode == 1) {
+    if (!m) return fail(c, VCSGC_E_NO_SURROGATE, "mode 1 needs a network");
+    if (!c->desc) return fail(c, VCSGC_E_INVALID_ARG, "mode 1 needs VCSGC_FLAG_DESCRIPTOR");
+    if (c->r_dep < vc::DESC_CUT + c->pot.rc)
+      return fail(c, VCSGC_E_INVALID_ARG, "mode 1 needs r_dep >= 4.41 + rc");
+  }
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  c->mlp = mode == 1 ? m : nullptr;
+  c->da_mode = mode;
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_set_surrogate_log(vcsgc_ctx *c, double *log_dev, int64_t cap) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (log_dev && cap < 0) return fail(c, VCSGC_E_INVALID_ARG, "negative capacity");
+  c->dalog = log_dev;
+  c->dacap = log_dev ? cap : 0;
+  const unsigned long long zero = 0;
+  VC_CHECK(c, hipMemcpyAsync(&c->ds->dalog_n, &zero, sizeof(zero), hipMemcpyHostToDevice,
+                             c->stream),
+           "reset");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_descriptors(vcsgc_ctx *c, const int32_t *sites_dev, int64_t n, int32_t flip,
+                               double *out_dev) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (!c->desc) return fail(c, VCSGC_E_INVALID_ARG, "needs VCSGC_FLAG_DESCRIPTOR");
+  if (n < 0 || (n > 0 && (!sites_dev || !out_dev))) return fail(c, VCSGC_E_INVALID_ARG, "bad arguments");
+  if (!c->mc_valid) {
+    st = refresh_mc(c);
+    if (st) return st;
+  }
+  VC_CHECK(c, vc::launch_descriptors(c, sites_dev, n, flip, out_dev), "descriptors");
   return VCSGC_OK;
 }
 

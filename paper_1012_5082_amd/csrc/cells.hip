@@ -169,7 +169,9 @@ __device__ __forceinline__ double pair_r(const double *__restrict__ x,
 // MD rows are column-major ([k * n + i]) for the thread-per-atom kernels.
 constexpr int BG = 32;
 
-template <bool MC>
+// MODE 0: MD rows (column-major indices), 1: MC rows (row-major, (rc-r)^2 and
+// c0 + c1 r), 2: descriptor rows (row-major, r)
+template <int MODE>
 __global__ void __launch_bounds__(BLOCK)
     k_build(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
             const double *__restrict__ z, Grid g, const int32_t *__restrict__ bcount,
@@ -221,18 +223,22 @@ __global__ void __launch_bounds__(BLOCK)
       const int32_t j = rowbuf[grp][a];
       int rank = 0;
       for (int b = 0; b < count; ++b) rank += rowbuf[grp][b] < j ? 1 : 0;
-      if (MC) {
+      if (MODE == 1) {
         const int64_t e = ig * KMAX + rank;
         nj[e] = (int32_t)(aoff + j);
         const double r = pair_r(x, y, z, g, xi, yi, zi, j);
         const double d = p.rc - r;
         ndd[e] = d * d;
         ng[e] = p.c0 + p.c1 * r;
+      } else if (MODE == 2) {
+        const int64_t e = ig * KMAX + rank;
+        nj[e] = (int32_t)(aoff + j);
+        ndd[e] = pair_r(x, y, z, g, xi, yi, zi, j);
       } else {
         nj[(int64_t)rank * ntot + ig] = (int32_t)(aoff + j);
       }
     }
-    if (!MC && lane == 0) {
+    if (MODE == 0 && lane == 0) {
       xr[ig] = xi;
       yr[ig] = yi;
       zr[ig] = zi;
@@ -273,11 +279,21 @@ __global__ void __launch_bounds__(BLOCK) k_row_stats(int64_t n, const uint8_t *_
 hipError_t launch_build_mc_list(vcsgc_ctx *c, const RepHost &r) {
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   int h = tstart(c, VCSGC_KT_BUILD);
-  k_build<true><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
+  k_build<1><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
       r.n, c->x + r.aoff, c->y + r.aoff, c->z + r.aoff, g, c->bin_count + r.boff,
       c->bin_atoms + r.boff * c->bmax, c->bmax, c->pot.rc, c->pot, c->mc_j, c->mc_dd, c->mc_g,
       c->mc_cnt, nullptr, nullptr, nullptr, c->ds, r.aoff, c->n);
   tstop(c, h);
+  return hipGetLastError();
+}
+
+// r < 4.41 A descriptor list of one replica (row-major, with distances)
+hipError_t launch_build_desc_list(vcsgc_ctx *c, const RepHost &r) {
+  Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
+  k_build<2><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
+      r.n, c->x + r.aoff, c->y + r.aoff, c->z + r.aoff, g, c->bin_count + r.boff,
+      c->bin_atoms + r.boff * c->bmax, c->bmax, DESC_CUT, c->pot, c->d_j, c->d_r, nullptr,
+      c->d_cnt, nullptr, nullptr, nullptr, c->ds, r.aoff, c->n);
   return hipGetLastError();
 }
 
@@ -295,7 +311,7 @@ hipError_t launch_build_md_list(vcsgc_ctx *c) {
   hipError_t e = hipMemsetAsync(&c->ds->pairs_md, 0, sizeof(unsigned long long), c->stream);
   if (e != hipSuccess) return e;
   int h = tstart(c, VCSGC_KT_BUILD);
-  k_build<false><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
+  k_build<0><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
       r.n, c->x, c->y, c->z, g, c->bin_count, c->bin_atoms, c->bmax, c->pot.rc + c->skin, c->pot,
       c->md_j, nullptr, nullptr, c->md_cnt, c->xr, c->yr, c->zr, c->ds, 0, c->n);
   tstop(c, h);

@@ -22,6 +22,8 @@ constexpr double ACC = 9.648533212e-3;  // (eV/A)/u -> A/fs^2
 constexpr double TIE = 1e-9;            // near-tie margin on |ln u + x|
 constexpr int KMAX = 32;                // neighbour-list row capacity
 constexpr int BLOCK = 256;
+constexpr double DESC_CUT = 4.41;  // outer edge of the third descriptor shell (A)
+constexpr int NPART = 5;           // trial-kernel partials: trials, accepts, sum dn, ties, stage-1 passes
 
 // Potential in device-friendly form; eps is indexed by s_i + s_j.
 struct PotD {
@@ -48,6 +50,8 @@ struct DevState {
   int rebuild;    // MD: an atom moved more than skin/2
   int kmax_used;
   unsigned long long pairs_mc, pairs_md;  // entries of the last r < rc / r < rc + skin lists
+  unsigned long long stage1_pass;         // trials passing the surrogate stage
+  unsigned long long smp_n, dalog_n;      // sample-log and surrogate-log records written
 };
 
 // ---------------------------------------------------------------------------
@@ -180,6 +184,18 @@ struct vcsgc_ctx {
   int32_t *mc_j = nullptr;
   double *mc_dd = nullptr, *mc_g = nullptr;
   uint8_t *mc_cnt = nullptr;
+  // r < 4.41 A descriptor list (row-major: neighbour, distance), when enabled
+  bool desc = false;
+  int32_t *d_j = nullptr;
+  double *d_r = nullptr;
+  uint8_t *d_cnt = nullptr;
+  // surrogate delayed acceptance and sample logging
+  const struct vcsgc_mlp *mlp = nullptr;
+  int da_mode = 0;  // 0 off, 1 network, 2 perfect, 3 zero
+  double *smp_desc = nullptr, *smp_de = nullptr;
+  int64_t smp_cap = 0, smp_stride = 1;
+  double *dalog = nullptr;
+  int64_t dacap = 0;
   // r < rc + skin list for MD, and positions at its build
   int32_t *md_j = nullptr;
   uint8_t *md_cnt = nullptr;
@@ -246,6 +262,9 @@ hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_build_mc_list(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_build_md_list(vcsgc_ctx *c);
 hipError_t launch_mc_row_stats(vcsgc_ctx *c);
+hipError_t launch_build_desc_list(vcsgc_ctx *c, const RepHost &r);
+hipError_t launch_descriptors(vcsgc_ctx *c, const int32_t *sites, int64_t n, int flip,
+                              double *out);
 hipError_t launch_density_mc(vcsgc_ctx *c);
 hipError_t launch_energy(vcsgc_ctx *c);  // fresh rho (MD list) + per-atom energies
 hipError_t launch_forces(vcsgc_ctx *c);  // fresh rho, F', forces (MD list)

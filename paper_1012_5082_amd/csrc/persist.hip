@@ -56,7 +56,7 @@ struct PersistArgs {
   double *rho;
   double *vx, *vy, *vz;
   int32_t *rec;
-  long long *part;  // [grid][4]
+  long long *part;  // [grid][NPART]
   PotD p;
   double *tlog;
   int64_t tcap;
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
       const long long bv = wg_sum(valid, sh), ba = wg_sum(acc, sh);
       const long long bd = wg_sum(dn_acc, sh), bt = wg_sum(tie, sh);
       if (threadIdx.x == 0) {
-        long long *P = a.part + 4 * (int64_t)g;
+        long long *P = a.part + NPART * (int64_t)g;
         P[0] = bv;
         P[1] = ba;
         P[2] = bd;
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
       // ---- global factor, identical in every workgroup of the replica
       long long pa = 0, pd = 0, pv = 0, pt = 0;
       for (int k = threadIdx.x; k < r.G; k += BLOCK) {
-        const long long *P = a.part + 4 * (int64_t)(r.g0 + k);
+        const long long *P = a.part + NPART * (int64_t)(r.g0 + k);
         pv += P[0];
         pa += P[1];
         pd += P[2];
@@ -501,6 +501,7 @@ hipError_t persist_read_stats(vcsgc_ctx *c, vcsgc_stats *out, int *err) {
     out[k].n_final = h[k].n_final;
     out[k].sum_n = h[k].sum_n;
     out[k].sum_n2 = h[k].sum_n2;
+    out[k].stage1_pass = (int64_t)h[k].trials;
   }
   return hipSuccess;
 }

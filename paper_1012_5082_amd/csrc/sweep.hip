@@ -12,7 +12,7 @@
 // Cells of one colour are at least one cell edge (>= 2 rc) apart, so their
 // energy changes are independent and every rho_j has at most one writer per
 // stage.
-#include "common.hpp"
+#include "mlp_device.hpp"
 
 namespace vc {
 
@@ -39,6 +39,17 @@ struct SweepArgs {
   int64_t tcap;
   double *slog;
   int64_t scap;
+  // descriptor list and surrogate
+  const int32_t *dj;
+  const double *dr;
+  const uint8_t *dcnt;
+  MlpDev md;
+  int da_mode;
+  double *dalog;
+  int64_t dacap;
+  // training-sample log: every stride-th trial's (descriptor, dU)
+  double *smp_desc, *smp_de;
+  int64_t smp_cap, smp_stride;
 };
 
 // Lanes per trial: lane k of a group handles neighbour entries k and k + TL.
@@ -83,6 +94,56 @@ __device__ __forceinline__ double delta_u_group(const SweepArgs &a, int64_t i, i
   return own + pair + emb;
 }
 
+// Descriptor of site i (or of the state with s_i flipped), by the TL lanes
+// of a group: [s_i, nB1, nB2, nB3, n1, n2, n3, rho1, rho2, rho3] over the
+// shells r < 2.68, [2.68, 3.46), [3.46, 4.41) A; the shell sums run in
+// ascending neighbour order.  In the flipped state every neighbour within rc
+// has rho_j + (t_{s'} - t_s)(rc - r)^2.  All lanes return the same values.
+__device__ __forceinline__ void descriptor_group(const SweepArgs &a, int64_t i, int lane,
+                                                 bool flip, double out[10]) {
+  const int s = a.sp[i], s1 = 1 - s;
+  const int m = a.dcnt[i];
+  int shl[2] = {-1, -1}, bj[2] = {0, 0};
+  double rj[2] = {0.0, 0.0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = lane + h * TL;
+    if (k < m) {
+      const int64_t e = i * KMAX + k;
+      const int32_t j = a.dj[e];
+      const double r = a.dr[e];
+      shl[h] = r < 2.68 ? 0 : (r < 3.46 ? 1 : (r < DESC_CUT ? 2 : -1));
+      bj[h] = a.sp[j];
+      double rho = a.rho[j];
+      if (flip && r < a.p.rc) {
+        const double d = a.p.rc - r;
+        const double dd = d * d;
+        rho = rho + (a.p.t[s1] * dd - a.p.t[s] * dd);
+      }
+      rj[h] = rho;
+    }
+  }
+  double cnt[3] = {0.0, 0.0, 0.0}, cb[3] = {0.0, 0.0, 0.0}, rs[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < m; ++k) {
+    const int h = k / TL;
+    const int sk = __shfl(h ? shl[1] : shl[0], k % TL, TL);
+    const int bk = __shfl(h ? bj[1] : bj[0], k % TL, TL);
+    const double rk = __shfl(h ? rj[1] : rj[0], k % TL, TL);
+    if (sk >= 0) {
+      cnt[sk] += 1.0;
+      cb[sk] += (double)bk;
+      rs[sk] += rk;
+    }
+  }
+  out[0] = (double)(flip ? s1 : s);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    out[1 + k] = cb[k];
+    out[4 + k] = cnt[k];
+    out[7 + k] = cnt[k] > 0.0 ? rs[k] / cnt[k] : 0.0;
+  }
+}
+
 __device__ __forceinline__ int64_t colour_cell(const SweepArgs &a, int colour, int64_t t) {
   const int hx = a.n0 >> 1, hy = a.n1 >> 1;
   const int64_t ia = t % hx, ib = (t / hx) % hy, ic = t / ((int64_t)hx * hy);
@@ -110,6 +171,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(DevState *ds) {
     ds->dn[0] = 0;
     ds->nrec[0] = 0;
     ds->trials = ds->local_acc = ds->stages = ds->stage_acc = ds->flips = ds->near_ties = 0;
+    ds->stage1_pass = 0;
     ds->sum_n = 0.0;
     ds->sum_n2 = 0.0;
   }
@@ -132,6 +194,17 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w, int64_
       const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
       const int64_t i = a.catoms[st + draw_index(r.v[0], m)];
       const double du = delta_u_group(a, i, lane);
+      if (a.smp_cap > 0 && ((int64_t)(w * (uint64_t)a.S + (uint64_t)s) * a.ncpc + t) % a.smp_stride == 0) {
+        double d[10];
+        descriptor_group(a, i, lane, false, d);
+        if (lane == 0) {
+          const unsigned long long idx = atomicAdd(&a.ds->smp_n, 1ull);
+          if ((int64_t)idx < a.smp_cap) {
+            for (int k = 0; k < 10; ++k) a.smp_desc[10 * idx + k] = d[k];
+            a.smp_de[idx] = du;
+          }
+        }
+      }
       if (lane == 0) {
         const double u = unit_open(r.v[1]);
         const int dn = 1 - 2 * (int)a.sp[i];
@@ -170,11 +243,144 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w, int64_
   const long long bd = block_sum(dn_acc, sh);
   const long long bt = block_sum(tie, sh);
   if (threadIdx.x == 0) {
-    long long *P = a.part + 4 * blockIdx.x;
+    long long *P = a.part + NPART * blockIdx.x;
     P[0] = bv;
     P[1] = ba;
     P[2] = bd;
     P[3] = bt;
+    P[4] = bv;  // no surrogate stage: every trial goes to the exact test
+  }
+}
+
+// Delayed acceptance (Christen and Fox), one group of TL lanes per active
+// cell and 16 cells per block:
+//   stage 1: surrogate dE_f of the move, accepted with min{1, exp(-beta s_f)},
+//            s_f = dE_f + dmu0 dn, using u1 = unit(w1) (the plain test's u);
+//   stage 2 (survivors): exact dU and the surrogate dE_r of the reverse move
+//            (descriptor of the proposed state), accepted with
+//            min{1, exp(-beta (dU + dmu0 dn)) min{1, exp(-beta s_r)} / min{1, exp(-beta s_f)}},
+//            s_r = dE_r - dmu0 dn, using u2 = unit(w2).
+// The network runs on the block's 16 descriptors at once (BF16 MFMA).
+// Surrogate modes: 1 network, 2 perfect (dE_f = dU, dE_r = -dU), 3 zero.
+__global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w, int64_t s, int par) {
+  __shared__ long long sh[BLOCK];
+  __shared__ __bf16 zs[16 * MLP_KP];
+  __shared__ __bf16 h1[16 * MLP_H], h2[16 * MLP_H];
+  __shared__ float yv[16];
+  const int lane = threadIdx.x % TL, grp = threadIdx.x / TL;
+  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
+  int64_t cell = -1, i = -1;
+  U4 r = {};
+  if (t < a.ncpc) {
+    const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+    cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+    const int32_t c0 = a.cstart[cell];
+    const uint32_t m = (uint32_t)(a.cstart[cell + 1] - c0);
+    if (m > 0) {
+      r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
+      i = a.catoms[c0 + draw_index(r.v[0], m)];
+    }
+  }
+  const bool has = i >= 0;
+  const int dn = has ? 1 - 2 * (int)a.sp[i] : 0;
+  double du = 0.0, ef = 0.0, er = 0.0;
+  bool have_du = false;
+  // ---- surrogate value of the forward move
+  if (a.da_mode == 1) {
+    double d[10];
+    if (has) descriptor_group(a, i, lane, false, d);
+    for (int k = lane; k < MLP_KP; k += TL)
+      zs[grp * MLP_KP + k] = (has && k < MLP_IN) ? mlp_input(a.md, k, d[k]) : to_bf16(0.0f);
+    __syncthreads();
+    mlp_block16(a.md, zs, h1, h2, yv);
+    ef = (double)(yv[grp] * a.md.out_sd + a.md.out_mu);
+  } else if (a.da_mode == 2 && has) {
+    du = delta_u_group(a, i, lane);
+    have_du = true;
+    ef = du;
+  }
+  // ---- stage 1 (every lane of the group evaluates the same test)
+  const double sf = ef + a.dmu0 * (double)dn;
+  const double x1 = a.beta * sf;
+  const double lnu1 = has ? log(unit_open(r.v[1])) : 0.0;
+  const bool pass1 = has && lnu1 < -x1;
+  // ---- stage 2 inputs for the survivors
+  if (pass1 && !have_du) du = delta_u_group(a, i, lane);
+  if (a.da_mode == 1) {
+    const int any = __syncthreads_or(pass1 ? 1 : 0);
+    if (any) {
+      double d[10];
+      if (pass1) descriptor_group(a, i, lane, true, d);
+      for (int k = lane; k < MLP_KP; k += TL)
+        zs[grp * MLP_KP + k] = (pass1 && k < MLP_IN) ? mlp_input(a.md, k, d[k]) : to_bf16(0.0f);
+      __syncthreads();
+      mlp_block16(a.md, zs, h1, h2, yv);
+      er = (double)(yv[grp] * a.md.out_sd + a.md.out_mu);
+    }
+  } else if (a.da_mode == 2) {
+    er = -du;
+  }
+  long long valid = 0, acc = 0, dn_acc = 0, tie = 0, p1 = 0;
+  if (lane == 0 && t < a.ncpc) {
+    int32_t site = -1;
+    if (has) {
+      bool ok = false;
+      double margin = lnu1 + x1;
+      if (pass1) {
+        const double sr = er - a.dmu0 * (double)dn;
+        const double xl = a.beta * (du + a.dmu0 * (double)dn);
+        const double xr = -(a.beta * sr);
+        const double l2 = (-xl + (xr < 0.0 ? xr : 0.0)) - (-x1 < 0.0 ? -x1 : 0.0);
+        const double lnu2 = log(unit_open(r.v[2]));
+        ok = lnu2 < l2;
+        margin = lnu2 - l2;
+      }
+      valid = 1;
+      p1 = pass1 ? 1 : 0;
+      tie = fabs(margin) < TIE;
+      if (ok) {
+        acc = 1;
+        dn_acc = dn;
+        site = (int32_t)i;
+      }
+      if (a.tlog) {
+        const unsigned long long idx = atomicAdd(&a.ds->tlog_n, 1ull);
+        if ((int64_t)idx < a.tcap) {
+          double *L = a.tlog + 8 * idx;
+          L[0] = (double)w;
+          L[1] = (double)s;
+          L[2] = (double)cell;
+          L[3] = (double)i;
+          L[4] = (double)dn;
+          L[5] = ok ? 1.0 : 0.0;
+          L[6] = pass1 ? du : __builtin_nan("");
+          L[7] = margin;
+        }
+      }
+      if (a.dalog) {
+        const unsigned long long idx = atomicAdd(&a.ds->dalog_n, 1ull);
+        if ((int64_t)idx < a.dacap) {
+          double *L = a.dalog + 5 * idx;
+          L[0] = (double)w;
+          L[1] = (double)s;
+          L[2] = (double)cell;
+          L[3] = ef;
+          L[4] = pass1 ? er : __builtin_nan("");
+        }
+      }
+    }
+    a.rec[t] = site;
+  }
+  const long long bv = block_sum(valid, sh), ba = block_sum(acc, sh);
+  const long long bd = block_sum(dn_acc, sh), bt = block_sum(tie, sh);
+  const long long b1 = block_sum(p1, sh);
+  if (threadIdx.x == 0) {
+    long long *P = a.part + NPART * blockIdx.x;
+    P[0] = bv;
+    P[1] = ba;
+    P[2] = bd;
+    P[3] = bt;
+    P[4] = b1;
   }
 }
 
@@ -187,8 +393,8 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64
   // every block reduces the trial kernel's partial sums itself, in a fixed order
   long long pa = 0, pd = 0;
   for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
-    pa += a.part[4 * b + 1];
-    pd += a.part[4 * b + 2];
+    pa += a.part[NPART * b + 1];
+    pd += a.part[NPART * b + 2];
   }
   const unsigned long long nrec = (unsigned long long)block_sum(pa, sh);
   const long long dn_tot = block_sum(pd, sh);
@@ -231,14 +437,16 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64
       }
     }
   }
-  long long pv = 0, pt = 0;
+  long long pv = 0, pt = 0, p1 = 0;
   if (blockIdx.x == 0) {
     for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
-      pv += a.part[4 * b + 0];
-      pt += a.part[4 * b + 3];
+      pv += a.part[NPART * b + 0];
+      pt += a.part[NPART * b + 3];
+      p1 += a.part[NPART * b + 4];
     }
     pv = block_sum(pv, sh);
     pt = block_sum(pt, sh);
+    p1 = block_sum(p1, sh);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const long long nb_new = nb + (gacc == 1 ? dn_tot : 0);
@@ -246,6 +454,7 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64
     ds->n_b[par ^ 1] = nb_new;
     ds->n_b_cur = nb_new;
     ds->trials += (unsigned long long)pv;
+    ds->stage1_pass += (unsigned long long)p1;
     ds->local_acc += nrec;
     ds->near_ties += (unsigned long long)pt;
     ds->stages += 1;
@@ -273,6 +482,39 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_descriptors(SweepArgs a, const int32_t *__restrict__ sites, int64_t n, int flip,
+                  double *out) {
+  const int lane = threadIdx.x % TL;
+  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
+  if (t >= n) return;  // whole group leaves together
+  const int32_t i = sites[t];
+  if (i < 0 || (int64_t)i >= a.n) {  // invalid site: NaN row
+    if (lane == 0)
+      for (int k = 0; k < 10; ++k) out[10 * t + k] = __builtin_nan("");
+    return;
+  }
+  double d[10];
+  descriptor_group(a, i, lane, flip != 0, d);
+  if (lane == 0)
+    for (int k = 0; k < 10; ++k) out[10 * t + k] = d[k];
+}
+
+hipError_t launch_descriptors(vcsgc_ctx *c, const int32_t *sites, int64_t n, int flip,
+                              double *out) {
+  SweepArgs a = {};
+  a.n = c->n;
+  a.p = c->pot;
+  a.sp = c->sp;
+  a.rho = c->rho;
+  a.dj = c->d_j;
+  a.dr = c->d_r;
+  a.dcnt = c->d_cnt;
+  if (n <= 0) return hipSuccess;
+  k_descriptors<<<grid_for(n * TL), BLOCK, 0, c->stream>>>(a, sites, n, flip, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
@@ -309,6 +551,17 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.tcap = c->tcap;
   a.slog = c->slog;
   a.scap = c->scap;
+  a.dj = c->d_j;
+  a.dr = c->d_r;
+  a.dcnt = c->d_cnt;
+  a.da_mode = c->da_mode;
+  if (c->mlp) a.md = mlp_dev(c->mlp);
+  a.dalog = c->dalog;
+  a.dacap = c->dacap;
+  a.smp_desc = c->smp_desc;
+  a.smp_de = c->smp_de;
+  a.smp_cap = c->smp_cap;
+  a.smp_stride = c->smp_stride < 1 ? 1 : c->smp_stride;
   k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
   const int gb = grid_for(a.ncpc * TL);
   a.nblk = gb;
@@ -318,7 +571,10 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
     for (int64_t s = 0; s < c->S; ++s, ++q) {
       const int par = (int)(q & 1);
       int h = tstart(c, VCSGC_KT_TRIAL);
-      k_trial<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
+      if (a.da_mode)
+        k_trial_da<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
+      else
+        k_trial<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
       tstop(c, h);
       h = tstart(c, VCSGC_KT_COMMIT);
       k_commit<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par, s == c->S - 1);

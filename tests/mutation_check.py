@@ -38,14 +38,24 @@ MUTATIONS = [
      "return rho > 0.0 ? -A / sqrt(rho) : 0.0;"),
     ("philox key bump", "      k1 += PH_W1;", "      k1 += PH_W0;"),
     ("density uses own species", "s += or_f(p, species[nj[e]], nr[e]);", "s += or_f(p, species[i], nr[e]);"),
-    ("neighbour cutoff inclusive of far pairs", "  if (r < cutoff) {", "  if (r < cutoff + 0.5) {"),
+    ("neighbour cutoff inclusive of far pairs",
+     "  if (r2 > 1.000001 * cutoff * cutoff) return 0;\n  double r = sqrt(r2);\n  if (r < cutoff) {",
+     "  double r = sqrt(r2);\n  if (r < cutoff + 0.5) {"),
     ("site drawn from wrong word", "catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m)]",
      "catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m) / 2]"),
     ("commit skips flip", "  species[i] = (uint8_t)s1;\n}", "  species[i] = (uint8_t)s;\n}"),
+    ("delayed acceptance without the reverse-move factor",
+     "double l2 = (-xl + (xr < 0.0 ? xr : 0.0)) - (-x1 < 0.0 ? -x1 : 0.0);",
+     "double l2 = -xl - (-x1 < 0.0 ? -x1 : 0.0);"),
+    ("flipped descriptor ignores the density shift", "      if (any) rj = rj + delta;\n    }\n    cnt[k]",
+     "      (void)any;\n    }\n    cnt[k]"),
+    ("MLP gradient skips the activation derivative", "      da2[k] = dh2 * or_dsilu(A.a2[k]);",
+     "      da2[k] = dh2;"),
 ]
 
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_eam.py",
-         "tests/test_oracle_ensemble.py", "tests/test_oracle_md.py"]
+         "tests/test_oracle_ensemble.py", "tests/test_oracle_md.py",
+         "tests/test_oracle_surrogate.py"]
 
 
 def main():

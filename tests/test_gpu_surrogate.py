@@ -1,0 +1,192 @@
+"""GPU surrogate pieces against the oracle.
+
+* network forward (BF16 MFMA, FP32 accumulation) vs the oracle's FP64
+  evaluation with BF16 rounding of the same operands;
+* gradients of the hand-written backward kernels vs the oracle's emulated
+  gradient, norm-wise per parameter tensor;
+* descriptors (current and flipped state) bit for bit;
+* delayed acceptance: a perfect surrogate reproduces the plain chain bit for
+  bit; with the network, the oracle replays the chain from the GPU's logged
+  surrogate values (compare mode) and must agree bit for bit;
+* sample logging and training on samples of the method itself.
+"""
+import numpy as np
+import pytest
+
+from paper_1012_5082_amd import inputs as I
+from paper_1012_5082_amd import workloads as W
+from parity_utils import compare_logs
+
+pytestmark = pytest.mark.gpu
+
+TENSORS = [("w1", 0, 640), ("b1", 640, 704), ("w2", 704, 4800), ("b2", 4800, 4864),
+           ("w3", 4864, 4928), ("b3", 4928, 4929)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _samples(n=512, seed=1):
+    rng = np.random.default_rng(seed)
+    d = np.column_stack([rng.integers(0, 2, n), rng.integers(0, 4, (n, 3)),
+                         rng.integers(6, 13, (n, 3)), rng.normal(13.0, 0.3, (n, 3))])
+    t = rng.normal(0.4, 0.2, n)
+    return d.astype(np.float64), t
+
+
+def _params(seed=3):
+    from oracle.oracle import MlpParams
+    mu = np.array([0.5, 1, 1, 1, 8, 6, 12, 13, 13, 13], dtype=np.float64)
+    sd = np.array([0.5, 1, 1, 1, 1, 1, 1, 0.5, 0.5, 0.5], dtype=np.float64)
+    return MlpParams.random(seed, mu=mu, sd=sd, out_mu=0.4, out_sd=0.2)
+
+
+def _gpu_mlp(m):
+    from paper_1012_5082_amd.binding import Mlp
+    g = Mlp(seed=0)
+    g.set_params(m.flat(), m.mu, m.sd, m.out_mu, m.out_sd)
+    return g
+
+
+def test_mlp_forward_matches_oracle(torch_cuda, oracle_mod):
+    torch = torch_cuda
+    m = _params()
+    d, _ = _samples(1000)
+    g = _gpu_mlp(m)
+    got = g.forward(torch.tensor(d, device="cuda")).cpu().numpy()
+    _, want = oracle_mod.mlp_forward(m, d, bf16_emul=True)
+    err = np.abs(got - want)
+    scale = np.abs(want).max() + m.out_sd
+    assert err.max() <= 5e-3 * scale, (err.max(), scale)
+    assert np.median(err) <= 5e-4 * scale, np.median(err)
+    g.close()
+
+
+def test_mlp_gradient_matches_oracle(torch_cuda, oracle_mod):
+    torch = torch_cuda
+    m = _params(5)
+    d, t = _samples(2048, seed=2)
+    g = _gpu_mlp(m)
+    loss_g, grad_g = g.grad(torch.tensor(d, device="cuda"), torch.tensor(t, device="cuda"))
+    loss_o, grad_o = oracle_mod.mlp_grad(m, d, t, bf16_emul=True)
+    assert abs(loss_g - loss_o) <= 1e-3 * loss_o
+    for name, a, b in TENSORS:
+        rel = np.linalg.norm(grad_g[a:b] - grad_o[a:b]) / np.linalg.norm(grad_o[a:b])
+        assert rel <= 1e-2, (name, rel)
+    g.close()
+
+
+def _c2_state(O, pot, sweeps=3, cbar=0.1, r_dep=0.0):
+    from paper_1012_5082_amd.binding import VCSGC
+    d = W.c2(cbar=cbar)
+    g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, descriptor=True, r_dep=r_dep)
+    if sweeps:
+        g.sweep(d["dmu0"], 5.0, cbar, d["T"], sweeps, 11)
+    return d, g
+
+
+def test_descriptors_match_oracle(torch_cuda, oracle_mod):
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d, g = _c2_state(O, pot)
+    sp = g.species.cpu().numpy()
+    rho = g.rho().cpu().numpy()
+    dnl = O.neighbors(d["x"], d["y"], d["z"], d["box"], O.DESC_CUTOFF, vectors=False)
+    sites = np.random.default_rng(0).choice(d["x"].size, 600, replace=False).astype(np.int32)
+    for flip in (False, True):
+        got = g.descriptors(sites, flip=flip)
+        want = np.stack([O.descriptor(dnl, i, sp, rho, pot, flip=flip) for i in sites])
+        assert np.array_equal(got, want), flip
+    g.close()
+
+
+def test_da_perfect_surrogate_equals_plain(torch_cuda, oracle_mod):
+    pot = I.params("FS-P1")
+    d = W.c2(cbar=0.05)
+    from paper_1012_5082_amd.binding import VCSGC
+    a = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
+    b = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
+    b.set_surrogate("perfect")
+    args = (d["dmu0"], 5.0, 0.05, d["T"], 5, d["seed"])
+    sa, sb = a.sweep(*args), b.sweep(*args)
+    for k in ("trials", "local_accepts", "stage_accepts", "flips", "n_final"):
+        assert sa[k] == sb[k], k
+    assert sb["stage1_pass"] == sa["local_accepts"]
+    assert np.array_equal(a.species.cpu().numpy(), b.species.cpu().numpy())
+    assert np.array_equal(a.rho().cpu().numpy(), b.rho().cpu().numpy())
+    a.close()
+    b.close()
+
+
+def test_da_network_chain_matches_oracle_replay(torch_cuda, oracle_mod):
+    """DA with the network: the oracle consumes the GPU's logged surrogate
+    values (forward and reverse) and must reproduce the whole chain."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    r_dep = 8.01
+    d, g = _c2_state(O, pot, sweeps=0, cbar=0.05, r_dep=r_dep)
+    m = _params(7)
+    m.out_mu, m.out_sd = float(np.float32(0.45)), float(np.float32(0.2))
+    net = _gpu_mlp(m)
+    g.set_surrogate("mlp", net)
+    info = g.info()
+    S, ncpc = info["stages_per_sweep"], int(np.prod(info["n_cells"])) // 8
+    n_sw = 3
+    g.enable_log(n_sw * S * ncpc, n_sw * S)
+    g.enable_surrogate_log(n_sw * S * ncpc)
+    args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
+    sg = g.sweep(*args, n_sw, d["seed"])
+    tl_g, sl_g, nt, ns = g.logs()
+    table = g.surrogate_log()
+    assert table.shape[0] == nt
+    assert 0 < sg["stage1_pass"] < sg["trials"]
+    st = O.SweepState(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
+    so, p1, tl_o, sl_o = O.sweep_da(st, *args, n_sw, d["seed"], "table", r_dep=r_dep, table=table,
+                                    log_trials=10 ** 8, log_stages=10 ** 8)
+    assert p1 == sg["stage1_pass"]
+    for k in ("trials", "local_accepts", "stage_accepts", "flips", "n_final"):
+        assert sg[k] == so[k], k
+    # dU is logged (and compared) for survivors only
+    keep = ~np.isnan(tl_o[:, 6])
+    assert np.array_equal(np.isnan(tl_g[:, 6]), ~keep)
+    compare_logs(tl_g[keep], sl_g, tl_o[keep], sl_o)
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    g.close()
+    net.close()
+
+
+def test_sample_log_and_training(torch_cuda, oracle_mod):
+    torch = torch_cuda
+    pot = I.params("FS-P1")
+    from paper_1012_5082_amd.binding import Mlp
+    d, g = _c2_state(oracle_mod, pot, sweeps=0, cbar=0.05)
+    g.enable_sample_log(200000, 7)
+    g.sweep(d["dmu0"], 5.0, 0.05, d["T"], 6, 3)
+    desc, dE = g.samples()
+    n = desc.shape[0]
+    assert n > 50000
+    D = desc.cpu().numpy()
+    assert np.all((D[:, 0] == 0) | (D[:, 0] == 1))
+    # thermal bcc (sigma 0.05 A): a few first/second-shell neighbours cross the
+    # 2.68 A edge, none crosses 3.46 A (0.6 A away from both shells)
+    assert np.all(D[:, 4] + D[:, 5] == 14)
+    assert np.median(D[:, 4]) == 8 and np.median(D[:, 5]) == 6
+    assert np.all(np.abs(D[:, 6] - 12) <= 2)
+    assert np.all(D[:, 1:4] <= D[:, 4:7])
+    E = dE.cpu().numpy()
+    assert np.all(np.isfinite(E)) and 0.2 < np.median(np.abs(E)) < 1.5
+    net = Mlp(seed=1)
+    net.fit_normalization(desc, dE)
+    rep = net.train(desc, dE, epochs=4, batch=4096, lr=2e-3, seed=5)
+    assert rep["loss_last"] < 0.5 * rep["loss_first"], rep
+    pred = net.forward(desc).cpu().numpy()
+    rmse = float(np.sqrt(np.mean((pred - E) ** 2)))
+    assert rmse < 0.5 * float(np.std(E)), (rmse, float(np.std(E)))
+    g.close()
+    net.close()
