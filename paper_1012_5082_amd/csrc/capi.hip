@@ -27,7 +27,7 @@ void free_all(vcsgc_ctx *c) {
                   c->zr,         c->rho,        c->rho_f,      c->fp,        c->eatom, c->red,
                   c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
                   c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
-                  c->d_cnt};
+                  c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -72,9 +72,13 @@ vcsgc_status grow_bins(vcsgc_ctx *c) {
   if (c->bmax >= 1024) return fail(c, VCSGC_E_OVERFLOW, "more than 1024 atoms in a search bin");
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   (void)hipFree(c->bin_atoms);
+  (void)hipFree(c->bin_pos);
   c->bin_atoms = nullptr;
+  c->bin_pos = nullptr;
   c->bmax *= 2;
-  VC_CHECK(c, dalloc(&c->bin_atoms, (size_t)c->nbins * c->bmax), "allocation");
+  VC_CHECK(c, dalloc(&c->bin_atoms, (size_t)c->nbins_total * c->bmax), "allocation");
+  if (c->reps.size() == 1)
+    VC_CHECK(c, dalloc(&c->bin_pos, (size_t)c->nbins_total * c->bmax), "allocation");
   int zero = 0;
   VC_CHECK(c, hipMemcpyAsync(&c->ds->bin_overflow, &zero, sizeof(int), hipMemcpyHostToDevice,
                              c->stream),
@@ -107,6 +111,28 @@ vcsgc_status refresh_mc(vcsgc_ctx *c) {
     c->mc_valid = true;
     return VCSGC_OK;
   }
+}
+
+// After MD the r < rc + skin list is valid for the current positions and
+// rho_f holds the current densities: the cells are re-binned, the r < rc rows
+// are filtered out of the MD rows and the density cache is a copy of rho_f
+// (both bitwise what a fresh build gives).  No row can overflow here.
+vcsgc_status refresh_mc_from_md(vcsgc_ctx *c) {
+  VC_CHECK(c, vc::launch_bin_cells(c, c->reps[0]), "binning");
+  VC_CHECK(c, vc::launch_mc_from_md(c), "neighbour list");
+  VC_CHECK(c, vc::launch_mc_row_stats(c), "neighbour list");
+  VC_CHECK(c, hipMemcpyAsync(c->rho, c->rho_f, sizeof(double) * c->n, hipMemcpyDeviceToDevice,
+                             c->stream),
+           "density");
+  c->mc_valid = true;
+  return VCSGC_OK;
+}
+
+vcsgc_status ensure_mc(vcsgc_ctx *c) {
+  if (c->mc_valid) return VCSGC_OK;
+  if (c->rho_f_fresh && c->md_valid && !c->desc && c->reps.size() == 1)
+    return refresh_mc_from_md(c);
+  return refresh_mc(c);
 }
 
 vcsgc_status refresh_md(vcsgc_ctx *c) {
@@ -356,6 +382,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   c->ncells = r0.ncells;
   c->S = r0.S;
   c->nbins = r0.nbins;
+  c->nbins_total = boff;
   c->x = sys->x;
   c->y = sys->y;
   c->z = sys->z;
@@ -395,10 +422,16 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   };
   A(dalloc(&c->bin_count, boff));
   A(dalloc(&c->bin_atoms, boff * c->bmax));
+  if (single) A(dalloc(&c->bin_pos, boff * c->bmax));
   A(dalloc(&c->cell_count, coff));
   A(dalloc(&c->cell_start, coff + R));
   A(dalloc(&c->cell_fill, coff));
   A(dalloc(&c->cell_atoms, n));
+  {
+    int64_t mx = 1;
+    for (const RepHost &r : c->reps) mx = std::max<int64_t>(mx, (r.ncells + 1023) / 1024);
+    A(dalloc(&c->scan_tmp, mx));
+  }
   A(dalloc(&c->mc_j, K * n));
   A(dalloc(&c->mc_dd, K * n));
   A(dalloc(&c->mc_g, K * n));
@@ -522,10 +555,11 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
     if (!valid_params(dmu0[k], kappa[k], cbar[k], T[k]))
       return fail(c, VCSGC_E_INVALID_ARG,
                   "need finite dmu0, kappa >= 0, cbar in [0,1], T > 0 for every replica");
-  if (!c->mc_valid) {
-    vcsgc_status st = refresh_mc(c);
+  {
+    vcsgc_status st = ensure_mc(c);
     if (st) return st;
   }
+  if (n_sweeps > 0) c->rho_f_fresh = false;
   // delayed acceptance and the training-sample log run with per-stage launches
   if ((c->strategy == 2 || c->da_mode || c->smp_cap > 0) && R == 1) {
     // one trial kernel and one commit kernel per stage
@@ -632,6 +666,7 @@ vcsgc_status eam_energy_forces(vcsgc_ctx *c, double *energy_eV, int want_forces)
   VC_CHECK(c, vc::launch_pack(c), "pack");
   VC_CHECK(c, vc::launch_energy(c), "energy");
   if (want_forces) VC_CHECK(c, vc::launch_forces(c), "forces");
+  c->rho_f_fresh = true;
   if (energy_eV) {
     VC_CHECK(c, vc::launch_reduce_sum(c, c->eatom, c->n, c->red + (c->n + vc::BLOCK - 1) / vc::BLOCK + 1),
              "reduce");
@@ -645,18 +680,13 @@ vcsgc_status eam_energy_forces(vcsgc_ctx *c, double *energy_eV, int want_forces)
   return VCSGC_OK;
 }
 
-vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
-  vcsgc_status st = check_ctx(c);
-  if (st) return st;
-  if (c->reps.size() != 1) return fail(c, VCSGC_E_INVALID_ARG, "not available on a batch context");
-  if (!c->vx || !c->fx)
-    return fail(c, VCSGC_E_INVALID_ARG, "MD needs velocity and force arrays");
-  if (!is_fin(dt_fs) || !(dt_fs > 0.0) || n_steps < 0)
-    return fail(c, VCSGC_E_INVALID_ARG, "need dt > 0 and n_steps >= 0");
-  if (!c->md_valid) {
-    st = refresh_md(c);
-    if (st) return st;
-  }
+}  // extern "C"
+
+namespace {
+
+// Steps with the rebuild decision taken on the host after every drift
+// (handles bin growth); used when the device path cannot be.
+vcsgc_status md_steps_host(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
   VC_CHECK(c, vc::launch_pack(c), "pack");
   VC_CHECK(c, vc::launch_forces(c), "forces");
   for (int64_t k = 0; k < n_steps; ++k) {
@@ -667,15 +697,83 @@ vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
                                c->stream),
              "copy");
     VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
-    c->mc_valid = false;
     if (flag) {
       VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild, 0, sizeof(int), c->stream), "reset");
-      st = refresh_md(c);
+      vcsgc_status st = refresh_md(c);
       if (st) return st;
     }
     VC_CHECK(c, vc::launch_forces(c), "forces");
   }
   if (n_steps > 0) VC_CHECK(c, vc::launch_kick(c, dt_fs), "kick");
+  return VCSGC_OK;
+}
+
+// Steps with the rebuild decided on the device (no host round trip per step).
+// State at entry is kept; if a bin or a row overflowed on the way, it is
+// restored and the steps are redone on the host-decided path.
+vcsgc_status md_steps_device(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
+  const size_t nb = sizeof(double) * (size_t)c->n;
+  if (!c->snap) VC_CHECK(c, dalloc(&c->snap, 6 * (size_t)c->n), "allocation");
+  double *state[6] = {c->x, c->y, c->z, c->vx, c->vy, c->vz};
+  for (int k = 0; k < 6; ++k)
+    VC_CHECK(c, hipMemcpyAsync(c->snap + k * c->n, state[k], nb, hipMemcpyDeviceToDevice,
+                               c->stream),
+             "snapshot");
+  VC_CHECK(c, hipMemsetAsync(&c->ds->md_rebuilds, 0, sizeof(unsigned long long), c->stream),
+           "reset");
+  VC_CHECK(c, vc::launch_pack(c), "pack");
+  VC_CHECK(c, vc::launch_forces(c), "forces");
+  for (int64_t k = 0; k < n_steps; ++k) {
+    VC_CHECK(c, vc::launch_kick_drift(c, dt_fs, k > 0), "kick-drift");
+    VC_CHECK(c, vc::launch_md_rebuild_cond(c), "neighbour list (MD)");
+    VC_CHECK(c, vc::launch_forces(c), "forces");
+  }
+  VC_CHECK(c, vc::launch_kick(c, dt_fs), "kick");
+  hipError_t e;
+  vc::DevState h = read_state(c, &e);
+  if (e != hipSuccess) return dev_fail(c, e, "MD");
+  c->md_rebuilds += (int64_t)h.md_rebuilds;
+  if (!h.bin_overflow && !h.overflow) return VCSGC_OK;
+  for (int k = 0; k < 6; ++k)
+    VC_CHECK(c, hipMemcpyAsync(state[k], c->snap + k * c->n, nb, hipMemcpyDeviceToDevice,
+                               c->stream),
+             "restore");
+  const int zero[2] = {0, 0};
+  VC_CHECK(c, hipMemcpyAsync(&c->ds->overflow, zero, 2 * sizeof(int), hipMemcpyHostToDevice,
+                             c->stream),
+           "reset");
+  VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild, 0, sizeof(int), c->stream), "reset");
+  if (h.bin_overflow) {
+    vcsgc_status st = grow_bins(c);
+    if (st) return st;
+  }
+  vcsgc_status st = refresh_md(c);
+  if (st) return st;
+  return md_steps_host(c, dt_fs, n_steps);
+}
+
+}  // namespace
+
+extern "C" {
+
+vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (c->reps.size() != 1) return fail(c, VCSGC_E_INVALID_ARG, "not available on a batch context");
+  if (!c->vx || !c->fx)
+    return fail(c, VCSGC_E_INVALID_ARG, "MD needs velocity and force arrays");
+  if (!is_fin(dt_fs) || !(dt_fs > 0.0) || n_steps < 0)
+    return fail(c, VCSGC_E_INVALID_ARG, "need dt > 0 and n_steps >= 0");
+  c->rho_f_fresh = false;
+  if (!c->md_valid) {
+    st = refresh_md(c);
+    if (st) return st;
+  }
+  if (n_steps > 0) c->mc_valid = false;
+  st = (n_steps > 0 && vc::md_rebuild_on_device(c)) ? md_steps_device(c, dt_fs, n_steps)
+                                                    : md_steps_host(c, dt_fs, n_steps);
+  if (st) return st;
+  c->rho_f_fresh = true;  // the last force pass ran at the final positions
   return VCSGC_OK;
 }
 
@@ -726,6 +824,7 @@ vcsgc_status vcsgc_set_state(vcsgc_ctx *c, const vcsgc_state *in) {
   c->w = in->sweeps_done;
   VC_CHECK(c, vc::persist_count(c), "state");  // n_B recounted from the species
   c->mc_valid = false;  // species may have been restored: fresh density cache
+  c->rho_f_fresh = false;
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   return VCSGC_OK;
 }
@@ -734,10 +833,8 @@ vcsgc_status vcsgc_copy_rho(vcsgc_ctx *c, double *rho_dev) {
   vcsgc_status st = check_ctx(c);
   if (st) return st;
   if (!rho_dev) return fail(c, VCSGC_E_INVALID_ARG, "null output");
-  if (!c->mc_valid) {
-    st = refresh_mc(c);
-    if (st) return st;
-  }
+  st = ensure_mc(c);
+  if (st) return st;
   VC_CHECK(c, hipMemcpyAsync(rho_dev, c->rho, sizeof(double) * c->n, hipMemcpyDeviceToDevice,
                              c->stream),
            "copy");
@@ -755,6 +852,7 @@ vcsgc_status vcsgc_atom_energies(vcsgc_ctx *c, double *e_dev) {
   }
   VC_CHECK(c, vc::launch_pack(c), "pack");
   VC_CHECK(c, vc::launch_energy(c), "energy");
+  c->rho_f_fresh = true;
   VC_CHECK(c, hipMemcpyAsync(e_dev, c->eatom, sizeof(double) * c->n, hipMemcpyDeviceToDevice,
                              c->stream),
            "copy");
@@ -768,10 +866,10 @@ vcsgc_status vcsgc_get_info(vcsgc_ctx *c, vcsgc_info *out) {
   for (int d = 0; d < 3; ++d) out->n_cells[d] = c->nc[d];
   out->stages_per_sweep = c->S;
   out->kmax = vc::KMAX;
-  out->mc_kmax_used = c->kmax_used;
   hipError_t e;
   vc::DevState h = read_state(c, &e);
   if (e != hipSuccess) return dev_fail(c, e, "info");
+  out->mc_kmax_used = c->mc_valid ? h.kmax_used : 0;
   out->mc_pairs = c->mc_valid ? (int64_t)h.pairs_mc : 0;
   out->md_pairs = c->md_valid ? (int64_t)h.pairs_md : 0;
   out->md_rebuilds = c->md_rebuilds;
@@ -847,10 +945,8 @@ vcsgc_status vcsgc_descriptors(vcsgc_ctx *c, const int32_t *sites_dev, int64_t n
   if (st) return st;
   if (!c->desc) return fail(c, VCSGC_E_INVALID_ARG, "needs VCSGC_FLAG_DESCRIPTOR");
   if (n < 0 || (n > 0 && (!sites_dev || !out_dev))) return fail(c, VCSGC_E_INVALID_ARG, "bad arguments");
-  if (!c->mc_valid) {
-    st = refresh_mc(c);
-    if (st) return st;
-  }
+  st = ensure_mc(c);
+  if (st) return st;
   VC_CHECK(c, vc::launch_descriptors(c, sites_dev, n, flip, out_dev), "descriptors");
   return VCSGC_OK;
 }

@@ -49,30 +49,67 @@ __global__ void k_cell_count(int64_t n, const double *__restrict__ x, const doub
   atomicAdd(&count[cell_of(g, x[i], y[i], z[i])], 1);
 }
 
-// exclusive scan of count[0..m) into start[0..m], one block of 1024 threads
-__global__ void __launch_bounds__(1024) k_scan(int64_t m, const int32_t *__restrict__ count,
-                                                int32_t *start, int32_t *fill) {
-  __shared__ int32_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t chunk = (m + 1023) / 1024;
-  const int64_t lo = t * chunk, hi = lo + chunk < m ? lo + chunk : m;
-  int32_t s = 0;
-  for (int64_t k = lo; k < hi; ++k) s += count[k];
-  part[t] = s;
+// exclusive scan of count[0..m) into start[0..m] (and a copy in fill):
+// chunks of SCAN_CHUNK values, first the chunk sums, then every chunk adds
+// the sums of the chunks before it to its own scan
+__global__ void __launch_bounds__(256) k_scan_sums(int64_t m, const int32_t *__restrict__ count,
+                                                   int32_t *bsum) {
+  __shared__ int32_t s[256];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+  int32_t v = 0;
+  for (int k = threadIdx.x; k < SCAN_CHUNK; k += 256)
+    if (base + k < m) v += count[base + k];
+  s[threadIdx.x] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int32_t v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
     __syncthreads();
   }
-  int32_t run = part[t] - s;  // exclusive prefix of this chunk
-  for (int64_t k = lo; k < hi; ++k) {
-    start[k] = run;
-    fill[k] = run;
-    run += count[k];
+  if (threadIdx.x == 0) bsum[blockIdx.x] = s[0];
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(int64_t m, const int32_t *__restrict__ count,
+                                                    const int32_t *__restrict__ bsum,
+                                                    int32_t *start, int32_t *fill) {
+  __shared__ int32_t s[256];
+  const int t = threadIdx.x;
+  // offset of this chunk
+  int32_t o = 0;
+  for (int k = t; k < (int)blockIdx.x; k += 256) o += bsum[k];
+  s[t] = o;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) s[t] += s[t + h];
+    __syncthreads();
   }
-  if (t == 1023) start[m] = part[1023];
+  const int32_t off = s[0];
+  __syncthreads();
+  // thread t owns values 4t .. 4t+3 of the chunk
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + 4 * t;
+  int32_t v[4], own = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = base + q < m ? count[base + q] : 0;
+    own += v[q];
+  }
+  s[t] = own;
+  __syncthreads();
+  for (int h = 1; h < 256; h <<= 1) {
+    const int32_t add = t >= h ? s[t - h] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  int32_t run = off + s[t] - own;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (base + q < m) {
+      start[base + q] = run;
+      fill[base + q] = run;
+    }
+    run += v[q];
+  }
+  if (blockIdx.x == gridDim.x - 1 && t == 255) start[m] = off + s[255];
 }
 
 __global__ void k_cell_fill(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
@@ -84,19 +121,39 @@ __global__ void k_cell_fill(int64_t n, const double *__restrict__ x, const doubl
   atoms[atomicAdd(&fill[c], 1)] = (int32_t)(aoff + i);
 }
 
-// canonical order inside a cell: ascending site index
-__global__ void k_cell_sort(int64_t m, const int32_t *__restrict__ start, int32_t *atoms) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= m) return;
+// canonical order inside a cell: ascending site index.  One wave per cell:
+// a rank sort in LDS (every index is distinct); cells larger than the LDS
+// buffer fall back to an insertion sort by one lane.
+constexpr int SORT_CAP = 2048;
+
+__global__ void __launch_bounds__(64) k_cell_sort(int64_t m, const int32_t *__restrict__ start,
+                                                  int32_t *atoms) {
+  __shared__ int32_t v[SORT_CAP];
+  const int64_t c = blockIdx.x;
   const int32_t lo = start[c], hi = start[c + 1];
-  for (int32_t a = lo + 1; a < hi; ++a) {
-    const int32_t v = atoms[a];
-    int32_t b = a - 1;
-    while (b >= lo && atoms[b] > v) {
-      atoms[b + 1] = atoms[b];
-      --b;
+  const int cnt = hi - lo;
+  if (cnt <= 1) return;
+  if (cnt > SORT_CAP) {
+    if (threadIdx.x == 0) {
+      for (int32_t a = lo + 1; a < hi; ++a) {
+        const int32_t x = atoms[a];
+        int32_t b = a - 1;
+        while (b >= lo && atoms[b] > x) {
+          atoms[b + 1] = atoms[b];
+          --b;
+        }
+        atoms[b + 1] = x;
+      }
     }
-    atoms[b + 1] = v;
+    return;
+  }
+  for (int e = threadIdx.x; e < cnt; e += 64) v[e] = atoms[lo + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < cnt; e += 64) {
+    const int32_t x = v[e];
+    int rank = 0;
+    for (int f = 0; f < cnt; ++f) rank += v[f] < x ? 1 : 0;
+    atoms[lo + rank] = x;
   }
 }
 
@@ -110,26 +167,34 @@ hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r) {
   if (e != hipSuccess) return e;
   const double *x = c->x + r.aoff, *y = c->y + r.aoff, *z = c->z + r.aoff;
   k_cell_count<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, x, y, z, g, count);
-  k_scan<<<1, 1024, 0, c->stream>>>(r.ncells, count, start, fill);
+  const int nchunk = (int)((r.ncells + SCAN_CHUNK - 1) / SCAN_CHUNK);
+  k_scan_sums<<<nchunk, 256, 0, c->stream>>>(r.ncells, count, c->scan_tmp);
+  k_scan_apply<<<nchunk, 256, 0, c->stream>>>(r.ncells, count, c->scan_tmp, start, fill);
   k_cell_fill<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, x, y, z, g, fill, atoms, r.aoff);
-  k_cell_sort<<<grid_for(r.ncells), BLOCK, 0, c->stream>>>(r.ncells, start, atoms);
+  k_cell_sort<<<(unsigned)r.ncells, 64, 0, c->stream>>>(r.ncells, start, atoms);
   return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------
 // search bins: edge >= rc + skin, at most bmax atoms each (overflow flagged)
 // ----------------------------------------------------------------------------
+// cond (may be NULL): run only when *cond != 0 (device-decided MD rebuild)
+// pos (may be NULL) receives (x, y, z, i) of the atom in its slot
 __global__ void k_bin_search(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ z, Grid g, int bmax, int32_t *count,
-                             int32_t *atoms, DevState *ds) {
+                             int32_t *atoms, double4 *pos, DevState *ds, const int *cond) {
+  if (cond && *cond == 0) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int b = cell_of(g, x[i], y[i], z[i]);
+  const double a = x[i], b2 = y[i], c2 = z[i];
+  const int b = cell_of(g, a, b2, c2);
   const int slot = atomicAdd(&count[b], 1);
-  if (slot < bmax)
+  if (slot < bmax) {
     atoms[(int64_t)b * bmax + slot] = (int32_t)i;
-  else
+    if (pos) pos[(int64_t)b * bmax + slot] = make_double4(a, b2, c2, (double)i);
+  } else {
     atomicOr(&ds->bin_overflow, 1);
+  }
 }
 
 // search bins of one replica (local atom indices)
@@ -140,8 +205,28 @@ hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r) {
   if (e != hipSuccess) return e;
   k_bin_search<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x + r.aoff, c->y + r.aoff,
                                                        c->z + r.aoff, g, c->bmax, count, atoms,
-                                                       c->ds);
+                                                       c->reps.size() == 1 ? c->bin_pos : nullptr,
+                                                       c->ds, nullptr);
   return hipGetLastError();
+}
+
+// clears the bin counts and the MD row statistics when a rebuild is pending
+__global__ void k_bins_clear_cond(int64_t nbins, int32_t *count, DevState *ds) {
+  if (ds->rebuild == 0) return;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) {
+    ds->pairs_md = 0ull;
+    ds->kmax_md = 0;
+  }
+  if (b < nbins) count[b] = 0;
+}
+
+// closes a pending rebuild: the list now matches the positions
+__global__ void k_rebuild_done(DevState *ds) {
+  if (threadIdx.x == 0 && ds->rebuild != 0) {
+    ds->rebuild = 0;
+    ds->md_rebuilds += 1ull;
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -181,7 +266,7 @@ __global__ void __launch_bounds__(BLOCK)
   __shared__ int32_t rowbuf[BLOCK / BG][KMAX];
   __shared__ int rowcount[BLOCK / BG];
   const int lane = threadIdx.x % BG, grp = threadIdx.x / BG;
-  const int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / BG;
+  const int64_t i = (xcd_block() * BLOCK + threadIdx.x) / BG;
   const bool live = i < n;
   if (lane == 0) rowcount[grp] = 0;
   __syncthreads();
@@ -248,7 +333,9 @@ __global__ void __launch_bounds__(BLOCK)
 
 // sum and maximum of the row lengths: one atomic pair per block
 __global__ void __launch_bounds__(BLOCK) k_row_stats(int64_t n, const uint8_t *__restrict__ cnt,
-                                                     unsigned long long *sum, int *mx) {
+                                                     unsigned long long *sum, int *mx,
+                                                     const int *cond) {
+  if (cond && *cond == 0) return;
   __shared__ unsigned int ss[BLOCK];
   __shared__ int sm[BLOCK];
   unsigned int a = 0;
@@ -299,9 +386,94 @@ hipError_t launch_build_desc_list(vcsgc_ctx *c, const RepHost &r) {
 
 hipError_t launch_mc_row_stats(vcsgc_ctx *c) {
   hipError_t e = hipMemsetAsync(&c->ds->pairs_mc, 0, sizeof(unsigned long long), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(&c->ds->kmax_used, 0, sizeof(int), c->stream);
   if (e != hipSuccess) return e;
-  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->mc_cnt, &c->ds->pairs_mc, &c->ds->kmax_used);
+  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->mc_cnt, &c->ds->pairs_mc, &c->ds->kmax_used,
+                                            nullptr);
   return hipGetLastError();
+}
+
+// r < rc + skin list, one lane per atom: the lane walks the surrounding
+// search bins through the packed (x, y, z, index) slots, appends hits to its
+// column-major row, then reloads the row into registers, sorts it by a fixed
+// bitonic network (ascending neighbour index) and writes it back.  The test
+// is r^2 < cut2: the list only has to hold every pair that can come within
+// rc before the next rebuild (its users test r < rc themselves).
+// cond (may be NULL): run only when *cond != 0.
+__global__ void __launch_bounds__(BLOCK)
+    k_build_md(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+               const double *__restrict__ z, Grid g, const int32_t *__restrict__ bcount,
+               const double4 *__restrict__ bpos, int bmax, double cut2, int32_t *nj, uint8_t *cnt,
+               double *xr, double *yr, double *zr, DevState *ds, const int *cond) {
+  if (cond && *cond == 0) return;
+  const int64_t i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i], zi = z[i];
+  const int bx = cell_coord(xi, g.L0, g.n0), by = cell_coord(yi, g.L1, g.n1),
+            bz = cell_coord(zi, g.L2, g.n2);
+  const int n0 = g.n0 >= 3 ? 3 : 2, n1 = g.n1 >= 3 ? 3 : 2, n2 = g.n2 >= 3 ? 3 : 2;
+  const int s0 = g.n0 >= 3 ? -1 : 0, s1 = g.n1 >= 3 ? -1 : 0, s2 = g.n2 >= 3 ? -1 : 0;
+  int c = 0;
+  for (int oz = 0; oz < n2; ++oz) {
+    const int zz = (bz + s2 + oz + g.n2) % g.n2;
+    for (int oy = 0; oy < n1; ++oy) {
+      const int yy = (by + s1 + oy + g.n1) % g.n1;
+      for (int ox = 0; ox < n0; ++ox) {
+        const int xx = (bx + s0 + ox + g.n0) % g.n0;
+        const int64_t nb = xx + (int64_t)g.n0 * (yy + (int64_t)g.n1 * zz);
+        const int m = min(bcount[nb], bmax);
+        const double4 *slot = bpos + nb * bmax;
+        for (int t = 0; t < m; t += 4) {
+          double4 q[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) q[u] = t + u < m ? slot[t + u] : make_double4(0, 0, 0, -1.0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int32_t j = (int32_t)q[u].w;
+            if (t + u < m && j != (int32_t)i) {
+              const double dx = min_image(q[u].x - xi, g.L0);
+              const double dy = min_image(q[u].y - yi, g.L1);
+              const double dz = min_image(q[u].z - zi, g.L2);
+              if ((dx * dx + dy * dy) + dz * dz < cut2) {
+                if (c < KMAX) nj[(int64_t)c * n + i] = j;
+                ++c;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  if (c > KMAX) {
+    atomicOr(&ds->overflow, 1);
+    c = KMAX;
+  }
+  int32_t v[KMAX];
+#pragma unroll
+  for (int u = 0; u < KMAX; ++u) v[u] = u < c ? nj[(int64_t)u * n + i] : INT32_MAX;
+#pragma unroll
+  for (int k = 2; k <= KMAX; k <<= 1) {
+#pragma unroll
+    for (int h = k >> 1; h > 0; h >>= 1) {
+#pragma unroll
+      for (int a = 0; a < KMAX; ++a) {
+        const int b = a ^ h;
+        if (b > a) {
+          const int32_t lo = min(v[a], v[b]), hi = max(v[a], v[b]);
+          const bool up = (a & k) == 0;
+          v[a] = up ? lo : hi;
+          v[b] = up ? hi : lo;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < KMAX; ++u)
+    if (u < c) nj[(int64_t)u * n + i] = v[u];
+  cnt[i] = (uint8_t)c;
+  xr[i] = xi;
+  yr[i] = yi;
+  zr[i] = zi;
 }
 
 // r < rc + skin list (single-system contexts)
@@ -309,15 +481,45 @@ hipError_t launch_build_md_list(vcsgc_ctx *c) {
   const RepHost &r = c->reps[0];
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   hipError_t e = hipMemsetAsync(&c->ds->pairs_md, 0, sizeof(unsigned long long), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(&c->ds->kmax_md, 0, sizeof(int), c->stream);
   if (e != hipSuccess) return e;
   int h = tstart(c, VCSGC_KT_BUILD);
-  k_build<0><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
-      r.n, c->x, c->y, c->z, g, c->bin_count, c->bin_atoms, c->bmax, c->pot.rc + c->skin, c->pot,
-      c->md_j, nullptr, nullptr, c->md_cnt, c->xr, c->yr, c->zr, c->ds, 0, c->n);
+  const double cut = c->pot.rc + c->skin;
+  k_build_md<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bin_count,
+                                                     c->bin_pos, c->bmax, cut * cut, c->md_j,
+                                                     c->md_cnt, c->xr, c->yr, c->zr, c->ds,
+                                                     nullptr);
   tstop(c, h);
-  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_used);
+  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_md,
+                                            nullptr);
   return hipGetLastError();
 }
+
+// MD list rebuild decided on the device: every kernel of the chain returns
+// at once unless the last drift raised ds->rebuild.
+// Overflows are flagged as in the host-decided path; the caller checks them
+// once at the end of its steps.
+hipError_t launch_md_rebuild_cond(vcsgc_ctx *c) {
+  const RepHost &r = c->reps[0];
+  Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
+  const int *cond = &c->ds->rebuild;
+  const double cut = c->pot.rc + c->skin;
+  int h = tstart(c, VCSGC_KT_BUILD);
+  k_bins_clear_cond<<<grid_for(r.nbins), BLOCK, 0, c->stream>>>(r.nbins, c->bin_count, c->ds);
+  k_bin_search<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bmax,
+                                                       c->bin_count, c->bin_atoms, c->bin_pos,
+                                                       c->ds, cond);
+  k_build_md<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bin_count,
+                                                     c->bin_pos, c->bmax, cut * cut, c->md_j,
+                                                     c->md_cnt, c->xr, c->yr, c->zr, c->ds, cond);
+  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_md,
+                                            cond);
+  k_rebuild_done<<<1, 64, 0, c->stream>>>(c->ds);
+  tstop(c, h);
+  return hipGetLastError();
+}
+
+bool md_rebuild_on_device(const vcsgc_ctx *c) { return c->bin_pos != nullptr; }
 
 // ----------------------------------------------------------------------------
 // density cache: rho_i = sum_j t_{s_j} (rc - r_ij)^2, ascending j (row-major MC rows)
@@ -325,7 +527,7 @@ hipError_t launch_build_md_list(vcsgc_ctx *c) {
 __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
                              const double *__restrict__ ndd, const uint8_t *__restrict__ cnt,
                              const uint8_t *__restrict__ sp, PotD p, double *rho) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
   const int m = cnt[i];
@@ -334,6 +536,61 @@ __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
     s += p.t[sp[j]] * ndd[i * KMAX + k];
   }
   rho[i] = s;
+}
+
+// The r < rc rows taken from a valid r < rc + skin list (MD rows, column-major,
+// ascending j): same entries, same order and the same dd, g values as a build
+// from the search bins, since r is evaluated by the same expression.  A group
+// of MFM_G lanes per atom: lane l tests entries l, l + MFM_G, ...; the hits of
+// a pass are placed by a ballot prefix count, so the row keeps the MD order
+// and the stores of a group are contiguous.
+constexpr int MFM_G = 16;
+
+__global__ void __launch_bounds__(BLOCK)
+    k_mc_from_md(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                 const double *__restrict__ z, Grid g, const int32_t *__restrict__ mdj,
+                 const uint8_t *__restrict__ mdcnt, PotD p, int32_t *nj, double *ndd, double *ng,
+                 uint8_t *cnt) {
+  const int64_t gid = xcd_block() * BLOCK + threadIdx.x;
+  const int64_t i = gid / MFM_G;
+  const int l = (int)(gid % MFM_G);
+  if (i >= n) return;  // whole groups leave together
+  const int wl = threadIdx.x & 63, gb = wl & ~(MFM_G - 1);
+  const double xi = x[i], yi = y[i], zi = z[i];
+  const int m = mdcnt[i];
+  int base = 0;
+  for (int k0 = 0; k0 < m; k0 += MFM_G) {
+    const int k = k0 + l;
+    bool hit = false;
+    int32_t j = 0;
+    double r = 0.0;
+    if (k < m) {
+      j = mdj[(int64_t)k * n + i];
+      r = pair_r(x, y, z, g, xi, yi, zi, j);
+      hit = r < p.rc;
+    }
+    const unsigned long long gm = (__ballot(hit) >> gb) & ((1ull << MFM_G) - 1ull);
+    if (hit) {
+      const int64_t e = i * KMAX + base + __popcll(gm & ((1ull << l) - 1ull));
+      nj[e] = j;
+      const double d = p.rc - r;
+      ndd[e] = d * d;
+      ng[e] = p.c0 + p.c1 * r;
+    }
+    base += __popcll(gm);
+  }
+  if (l == 0) cnt[i] = (uint8_t)base;
+}
+
+hipError_t launch_mc_from_md(vcsgc_ctx *c) {
+  const RepHost &r = c->reps[0];
+  Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
+  int h = tstart(c, VCSGC_KT_BUILD);
+  k_mc_from_md<<<grid_for(c->n * MFM_G), BLOCK, 0, c->stream>>>(
+      c->n, c->x, c->y, c->z, g, c->md_j, c->md_cnt, c->pot, c->mc_j, c->mc_dd, c->mc_g,
+      c->mc_cnt);
+  tstop(c, h);
+  return hipGetLastError();
 }
 
 hipError_t launch_density_mc(vcsgc_ctx *c) {

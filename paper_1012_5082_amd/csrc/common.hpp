@@ -48,10 +48,12 @@ struct DevState {
   int bin_overflow;  // a search bin exceeded its capacity
   int bad_input;  // position outside the box / species not in {0,1}
   int rebuild;    // MD: an atom moved more than skin/2
-  int kmax_used;
+  int kmax_used;  // longest row of the current r < rc list
+  int kmax_md;    // longest row of the current r < rc + skin list
   unsigned long long pairs_mc, pairs_md;  // entries of the last r < rc / r < rc + skin lists
   unsigned long long stage1_pass;         // trials passing the surrogate stage
   unsigned long long smp_n, dalog_n;      // sample-log and surrogate-log records written
+  unsigned long long md_rebuilds;         // MD list rebuilds taken on the device
 };
 
 // ---------------------------------------------------------------------------
@@ -129,6 +131,19 @@ __device__ __forceinline__ int cell_coord(double u, double L, int nc) {
   return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
+// Workgroups are dispatched to the eight XCDs round robin (workgroup b runs on
+// XCD b mod 8), and each XCD has its own L2.  For gather kernels whose
+// neighbouring atoms have neighbouring indices, this maps the launch so that
+// each XCD gets one contiguous eighth of the logical blocks: the data shared
+// by adjacent blocks then stays in one L2.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+constexpr int SCAN_CHUNK = 1024;  // values per block of the cell-count scan
+
 inline int grid_for(int64_t n, int block = BLOCK) {
   int64_t g = (n + block - 1) / block;
   return (int)(g < 1 ? 1 : g);
@@ -173,12 +188,16 @@ struct vcsgc_ctx {
   int64_t ncells = 0, S = 0;
   int32_t *cell_count = nullptr, *cell_start = nullptr, *cell_atoms = nullptr,
           *cell_fill = nullptr;
+  int32_t *scan_tmp = nullptr;  // chunk sums of the cell-count scan
+  double *snap = nullptr;       // x, y, z, vx, vy, vz at the start of an MD call (6 n)
 
   // search bins for neighbour lists: edge >= rc + skin, fixed capacity per bin
   int nb[3] = {0, 0, 0};
   int64_t nbins = 0;
   int bmax = 16;
   int32_t *bin_count = nullptr, *bin_atoms = nullptr;
+  double4 *bin_pos = nullptr;  // (x, y, z, index) per bin slot (single-system contexts)
+  int64_t nbins_total = 0;     // bins of all replicas
 
   // r < rc list, column-major rows [k * n + i]: neighbour, (rc-r)^2, c0 + c1 r
   int32_t *mc_j = nullptr;
@@ -212,6 +231,9 @@ struct vcsgc_ctx {
   vc::DevState *ds = nullptr;
 
   bool mc_valid = false, md_valid = false;
+  // rho_f holds the densities at the current positions and species (set by
+  // the MD and energy paths, cleared by anything that changes species)
+  bool rho_f_fresh = false;
   uint64_t w = 0;  // sweep counter
   int kmax_used = 0;
   int64_t md_rebuilds = 0;
@@ -261,11 +283,14 @@ hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_build_mc_list(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_build_md_list(vcsgc_ctx *c);
+hipError_t launch_md_rebuild_cond(vcsgc_ctx *c);
+bool md_rebuild_on_device(const vcsgc_ctx *c);
 hipError_t launch_mc_row_stats(vcsgc_ctx *c);
 hipError_t launch_build_desc_list(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_descriptors(vcsgc_ctx *c, const int32_t *sites, int64_t n, int flip,
                               double *out);
 hipError_t launch_density_mc(vcsgc_ctx *c);
+hipError_t launch_mc_from_md(vcsgc_ctx *c);
 hipError_t launch_energy(vcsgc_ctx *c);  // fresh rho (MD list) + per-atom energies
 hipError_t launch_forces(vcsgc_ctx *c);  // fresh rho, F', forces (MD list)
 hipError_t launch_validate(vcsgc_ctx *c, const RepHost &r);

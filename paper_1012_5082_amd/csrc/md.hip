@@ -9,6 +9,8 @@ struct Box {
   double L0, L1, L2;
 };
 
+constexpr int UNR = 4;  // neighbour gathers in flight per lane
+
 // (x, y, z, species) of every atom, packed for the density pass
 __global__ void k_pack(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                        const double *__restrict__ z, const uint8_t *__restrict__ sp,
@@ -29,21 +31,30 @@ __global__ void __launch_bounds__(BLOCK)
     k_density_md(int64_t n, const double4 *__restrict__ ps4, const int32_t *__restrict__ nj,
                  const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
                  double *rho, double *fp, double4 *pf4) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 qi = ps4[i];
   double s = 0.0;
   const int m = cnt[i];
-  for (int k = 0; k < m; ++k) {
-    const int32_t j = nj[(int64_t)k * n + i];
-    const double4 qj = ps4[j];
-    const double dx = min_image(qj.x - qi.x, b.L0);
-    const double dy = min_image(qj.y - qi.y, b.L1);
-    const double dz = min_image(qj.z - qi.z, b.L2);
-    const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-    if (!(r < p.rc)) continue;
-    const double d = p.rc - r;
-    s += p.t[(int)qj.w] * (d * d);
+  // UNR neighbours in flight: indices, then gathers, then the terms in order
+  for (int k = 0; k < m; k += UNR) {
+    int32_t j[UNR];
+    double4 q[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) j[u] = k + u < m ? nj[(int64_t)(k + u) * n + i] : (int32_t)i;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) q[u] = ps4[j[u]];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const double dx = min_image(q[u].x - qi.x, b.L0);
+      const double dy = min_image(q[u].y - qi.y, b.L1);
+      const double dz = min_image(q[u].z - qi.z, b.L2);
+      const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+      if (k + u < m && r < p.rc) {
+        const double d = p.rc - r;
+        s += p.t[(int)q[u].w] * (d * d);
+      }
+    }
   }
   rho[i] = s;
   const double f = dembed(p, sp[i], s);
@@ -57,31 +68,42 @@ __global__ void __launch_bounds__(BLOCK)
     k_forces(int64_t n, const double4 *__restrict__ pf4, const int32_t *__restrict__ nj,
              const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
              double *fx, double *fy, double *fz) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 qi = pf4[i];
   const int si = sp[i];
   const double fpi = qi.w;
   double ax = 0.0, ay = 0.0, az = 0.0;
   const int m = cnt[i];
-  for (int k = 0; k < m; ++k) {
-    const int32_t j = nj[(int64_t)k * n + i];
-    const double4 qj = pf4[j];
-    const double dx = min_image(qj.x - qi.x, b.L0);
-    const double dy = min_image(qj.y - qi.y, b.L1);
-    const double dz = min_image(qj.z - qi.z, b.L2);
-    const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-    if (!(r < p.rc)) continue;
-    const int sj = sp[j];
-    const double d = p.rc - r;
-    const double dphi = p.eps[si + sj] * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
-    const double dfj = -2.0 * p.t[sj] * d;
-    const double dfi = -2.0 * p.t[si] * d;
-    const double s = dphi + fpi * dfj + qj.w * dfi;
-    const double coef = s / r;
-    ax += coef * dx;
-    ay += coef * dy;
-    az += coef * dz;
+  for (int k = 0; k < m; k += UNR) {
+    int32_t j[UNR];
+    double4 q[UNR];
+    int sj[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) j[u] = k + u < m ? nj[(int64_t)(k + u) * n + i] : (int32_t)i;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      q[u] = pf4[j[u]];
+      sj[u] = sp[j[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const double dx = min_image(q[u].x - qi.x, b.L0);
+      const double dy = min_image(q[u].y - qi.y, b.L1);
+      const double dz = min_image(q[u].z - qi.z, b.L2);
+      const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+      if (k + u < m && r < p.rc) {
+        const double d = p.rc - r;
+        const double dphi = p.eps[si + sj[u]] * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
+        const double dfj = -2.0 * p.t[sj[u]] * d;
+        const double dfi = -2.0 * p.t[si] * d;
+        const double s = dphi + fpi * dfj + q[u].w * dfi;
+        const double coef = s / r;
+        ax += coef * dx;
+        ay += coef * dy;
+        az += coef * dz;
+      }
+    }
   }
   fx[i] = ax;
   fy[i] = ay;
@@ -92,7 +114,7 @@ __global__ void __launch_bounds__(BLOCK)
 __global__ void k_energy(int64_t n, const double4 *__restrict__ ps4, const int32_t *__restrict__ nj,
                          const uint8_t *__restrict__ cnt, const double *__restrict__ rho, Box b,
                          PotD p, double *e) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 qi = ps4[i];
   const int si = (int)qi.w;

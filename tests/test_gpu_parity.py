@@ -261,8 +261,14 @@ def test_hybrid_cycle_parity(torch_cuda, oracle_mod):
         O.sweep(st, d["dmu0"], 1.0, d["cbar"], d["T"], 1, d["seed"])
         w += 1
         sp = st.species
+        assert np.array_equal(g.rho().cpu().numpy(), st.rho)
         g.md(1.0, 20)
         x, y, z, vx, vy, vz, *_ = O.md(x, y, z, st.vx, st.vy, st.vz, sp, d["box"], pot, 1.0, 20)
+        # the sweep's lists and density cache after MD come from the MD list and
+        # the last MD density pass: equal to a fresh r < rc build at the new positions
+        nl = O.neighbors(x, y, z, d["box"], pot.rc, vectors=False)
+        assert np.array_equal(g.rho().cpu().numpy(), O.density(nl, sp, pot))
+        assert g.info()["mc_pairs"] == nl.j.size
     assert np.array_equal(g.species.cpu().numpy(), sp)
     for nm, want in zip(("x", "y", "z", "vx", "vy", "vz"), (x, y, z, vx, vy, vz)):
         assert np.array_equal(getattr(g, nm).cpu().numpy(), want), nm
