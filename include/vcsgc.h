@@ -228,12 +228,18 @@ vcsgc_status vcsgc_get_info(vcsgc_ctx *ctx, vcsgc_info *out);
 typedef struct {
   double total_ms[VCSGC_KT_CLASSES]; /* summed event-to-event durations */
   int64_t count[VCSGC_KT_CLASSES];   /* timed launches */
+  int64_t launches[VCSGC_KT_CLASSES]; /* all launches of the class (timed or not) */
 } vcsgc_ktimes;
 
 /* Time every launch of the kernel classes in mask (bit k = class k) with a
  * pair of HIP events recorded on the context's stream around the launch;
  * resets the accumulated times.  mask = 0 disables timing. */
 vcsgc_status vcsgc_kernel_timing(vcsgc_ctx *ctx, uint32_t mask);
+/* As vcsgc_kernel_timing, but only one launch in `every` (>= 1) of each
+ * class is timed (launch index mod every == 0 since this call), for classes
+ * launched hundreds of times per call where the event pairs themselves would
+ * add host work; count then holds the timed launches. */
+vcsgc_status vcsgc_kernel_timing_sampled(vcsgc_ctx *ctx, uint32_t mask, int32_t every);
 /* Accumulated times since the last vcsgc_kernel_timing call (synchronizes). */
 vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *ctx, vcsgc_ktimes *out);
 

@@ -80,7 +80,8 @@ STRATEGIES = {"graph": 0, "persistent": 1, "stage": 2}
 
 
 class KTimes(C.Structure):
-    _fields_ = [("total_ms", C.c_double * 9), ("count", C.c_int64 * 9)]
+    _fields_ = [("total_ms", C.c_double * 9), ("count", C.c_int64 * 9),
+                ("launches", C.c_int64 * 9)]
 
 
 _lib = None
@@ -125,6 +126,8 @@ def lib():
         L.vcsgc_get_info.argtypes = [_P, C.POINTER(Info)]
         L.vcsgc_kernel_timing.restype = st
         L.vcsgc_kernel_timing.argtypes = [_P, C.c_uint32]
+        L.vcsgc_kernel_timing_sampled.restype = st
+        L.vcsgc_kernel_timing_sampled.argtypes = [_P, C.c_uint32, C.c_int32]
         L.vcsgc_get_kernel_timing.restype = st
         L.vcsgc_get_kernel_timing.argtypes = [_P, C.POINTER(KTimes)]
         L.vcsgc_create_batch.restype = st
@@ -332,18 +335,21 @@ class VCSGC:
         torch.cuda.synchronize()
         return out
 
-    def kernel_timing(self, names):
-        """Time every launch of the named kernel classes with HIP events (resets)."""
+    def kernel_timing(self, names, every=1):
+        """Time the launches of the named kernel classes with HIP events (resets);
+        with every > 1 only one launch in `every` of each class is timed."""
         mask = 0
         for nm in names:
             mask |= 1 << KT_NAMES.index(nm)
-        self._check(lib().vcsgc_kernel_timing(self._h, mask), "kernel_timing")
+        self._check(lib().vcsgc_kernel_timing_sampled(self._h, mask, int(every)),
+                    "kernel_timing")
 
     def kernel_times(self):
-        """{class: (total_ms, launches)} accumulated since kernel_timing()."""
+        """{class: (total_ms, timed launches, all launches)} since kernel_timing()."""
         k = KTimes()
         self._check(lib().vcsgc_get_kernel_timing(self._h, C.byref(k)), "get_kernel_timing")
-        return {nm: (k.total_ms[i], k.count[i]) for i, nm in enumerate(KT_NAMES) if k.count[i]}
+        return {nm: (k.total_ms[i], k.count[i], k.launches[i]) for i, nm in enumerate(KT_NAMES)
+                if k.count[i]}
 
     def set_tuning(self, strategy="graph", trials_per_group=1):
         self._check(lib().vcsgc_set_tuning(self._h, STRATEGIES[strategy], int(trials_per_group)),

@@ -27,13 +27,15 @@ void free_all(vcsgc_ctx *c) {
                   c->zr,         c->rho,        c->rho_f,      c->fp,        c->eatom, c->red,
                   c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
                   c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
-                  c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos};
+                  c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos,
+                  c->md_tmp,     c->md_tcnt,    c->sites};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
+  vc::free_stage_graph(c);
 }
 
 vcsgc_status fail(vcsgc_ctx *c, vcsgc_status st, const std::string &msg) {
@@ -226,6 +228,7 @@ namespace vc {
 
 int tstart(vcsgc_ctx *c, int cls) {
   if (!(c->tmask & (1u << cls))) return -1;
+  if (c->kt_seen[cls]++ % c->t_every != 0) return -1;
   hipEvent_t ev[2];
   for (int k = 0; k < 2; ++k) {
     if (!c->ev_pool.empty()) {
@@ -275,16 +278,23 @@ hipError_t drain_timers(vcsgc_ctx *c) {
 
 extern "C" {
 
-vcsgc_status vcsgc_kernel_timing(vcsgc_ctx *c, uint32_t mask) {
+vcsgc_status vcsgc_kernel_timing_sampled(vcsgc_ctx *c, uint32_t mask, int32_t every) {
   vcsgc_status st = check_ctx(c);
   if (st) return st;
+  if (every < 1) return fail(c, VCSGC_E_INVALID_ARG, "every must be >= 1");
   VC_CHECK(c, drain_timers(c), "timing");
   c->tmask = mask & ((1u << VCSGC_KT_CLASSES) - 1);
+  c->t_every = every;
   for (int k = 0; k < VCSGC_KT_CLASSES; ++k) {
     c->kt_ms[k] = 0.0;
     c->kt_n[k] = 0;
+    c->kt_seen[k] = 0;
   }
   return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_kernel_timing(vcsgc_ctx *c, uint32_t mask) {
+  return vcsgc_kernel_timing_sampled(c, mask, 1);
 }
 
 vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *c, vcsgc_ktimes *out) {
@@ -295,6 +305,7 @@ vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *c, vcsgc_ktimes *out) {
   for (int k = 0; k < VCSGC_KT_CLASSES; ++k) {
     out->total_ms[k] = c->kt_ms[k];
     out->count[k] = c->kt_n[k];
+    out->launches[k] = c->kt_seen[k];
   }
   return VCSGC_OK;
 }
@@ -422,14 +433,20 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   };
   A(dalloc(&c->bin_count, boff));
   A(dalloc(&c->bin_atoms, boff * c->bmax));
-  if (single) A(dalloc(&c->bin_pos, boff * c->bmax));
+  if (single) {
+    A(dalloc(&c->bin_pos, boff * c->bmax));
+    A(dalloc(&c->md_tmp, K * n));
+    A(dalloc(&c->md_tcnt, n));
+    A(dalloc(&c->sites, reps[0].S * reps[0].ncpc));
+  }
   A(dalloc(&c->cell_count, coff));
   A(dalloc(&c->cell_start, coff + R));
   A(dalloc(&c->cell_fill, coff));
   A(dalloc(&c->cell_atoms, n));
   {
     int64_t mx = 1;
-    for (const RepHost &r : c->reps) mx = std::max<int64_t>(mx, (r.ncells + 1023) / 1024);
+    for (const RepHost &r : c->reps)
+      mx = std::max<int64_t>(mx, (std::max(r.ncells, r.nbins) + vc::SCAN_CHUNK - 1) / vc::SCAN_CHUNK);
     A(dalloc(&c->scan_tmp, mx));
   }
   A(dalloc(&c->mc_j, K * n));
@@ -483,6 +500,11 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   if ((e = dalloc(&c->part, vc::NPART * c->npart)) != hipSuccess)
     return bail(dev_fail(c, e, "allocation"));
   if ((e = hipMemsetAsync(c->ds, 0, sizeof(vc::DevState), c->stream)) != hipSuccess)
+    return bail(dev_fail(c, e, "init"));
+  // rows of the MD build always hold valid indices (empty until built)
+  if (c->md_tcnt &&
+      ((e = hipMemsetAsync(c->md_tcnt, 0, sizeof(int32_t) * n, c->stream)) != hipSuccess ||
+       (e = hipMemsetAsync(c->md_tmp, 0, sizeof(int32_t) * vc::KMAX * n, c->stream)) != hipSuccess))
     return bail(dev_fail(c, e, "init"));
   for (const RepHost &r : c->reps) {
     if ((e = vc::launch_validate(c, r)) != hipSuccess) return bail(dev_fail(c, e, "validate"));
@@ -634,6 +656,7 @@ vcsgc_status vcsgc_set_tuning(vcsgc_ctx *c, int32_t strategy, int32_t trials_per
     st = assign_workgroups(c);
     if (st) return st;
     if (c->grid_total > c->npart) {
+      vc::free_stage_graph(c);  // its nodes hold the old buffer
       (void)hipFree(c->part);
       c->part = nullptr;
       c->npart = c->grid_total;

@@ -52,13 +52,16 @@ __global__ void k_cell_count(int64_t n, const double *__restrict__ x, const doub
 // exclusive scan of count[0..m) into start[0..m] (and a copy in fill):
 // chunks of SCAN_CHUNK values, first the chunk sums, then every chunk adds
 // the sums of the chunks before it to its own scan
+// Values are clamped to cap; fill may be NULL; cond (may be NULL): run only
+// when *cond != 0.
 __global__ void __launch_bounds__(256) k_scan_sums(int64_t m, const int32_t *__restrict__ count,
-                                                   int32_t *bsum) {
+                                                   int32_t *bsum, int cap, const int *cond) {
+  if (cond && *cond == 0) return;
   __shared__ int32_t s[256];
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
   int32_t v = 0;
   for (int k = threadIdx.x; k < SCAN_CHUNK; k += 256)
-    if (base + k < m) v += count[base + k];
+    if (base + k < m) v += min(count[base + k], cap);
   s[threadIdx.x] = v;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -70,7 +73,9 @@ __global__ void __launch_bounds__(256) k_scan_sums(int64_t m, const int32_t *__r
 
 __global__ void __launch_bounds__(256) k_scan_apply(int64_t m, const int32_t *__restrict__ count,
                                                     const int32_t *__restrict__ bsum,
-                                                    int32_t *start, int32_t *fill) {
+                                                    int32_t *start, int32_t *fill, int cap,
+                                                    const int *cond) {
+  if (cond && *cond == 0) return;
   __shared__ int32_t s[256];
   const int t = threadIdx.x;
   // offset of this chunk
@@ -89,7 +94,7 @@ __global__ void __launch_bounds__(256) k_scan_apply(int64_t m, const int32_t *__
   int32_t v[4], own = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    v[q] = base + q < m ? count[base + q] : 0;
+    v[q] = base + q < m ? min(count[base + q], cap) : 0;
     own += v[q];
   }
   s[t] = own;
@@ -105,7 +110,7 @@ __global__ void __launch_bounds__(256) k_scan_apply(int64_t m, const int32_t *__
   for (int q = 0; q < 4; ++q) {
     if (base + q < m) {
       start[base + q] = run;
-      fill[base + q] = run;
+      if (fill) fill[base + q] = run;
     }
     run += v[q];
   }
@@ -168,8 +173,9 @@ hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r) {
   const double *x = c->x + r.aoff, *y = c->y + r.aoff, *z = c->z + r.aoff;
   k_cell_count<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, x, y, z, g, count);
   const int nchunk = (int)((r.ncells + SCAN_CHUNK - 1) / SCAN_CHUNK);
-  k_scan_sums<<<nchunk, 256, 0, c->stream>>>(r.ncells, count, c->scan_tmp);
-  k_scan_apply<<<nchunk, 256, 0, c->stream>>>(r.ncells, count, c->scan_tmp, start, fill);
+  k_scan_sums<<<nchunk, 256, 0, c->stream>>>(r.ncells, count, c->scan_tmp, INT32_MAX, nullptr);
+  k_scan_apply<<<nchunk, 256, 0, c->stream>>>(r.ncells, count, c->scan_tmp, start, fill,
+                                              INT32_MAX, nullptr);
   k_cell_fill<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, x, y, z, g, fill, atoms, r.aoff);
   k_cell_sort<<<(unsigned)r.ncells, 64, 0, c->stream>>>(r.ncells, start, atoms);
   return hipGetLastError();
@@ -393,8 +399,9 @@ hipError_t launch_mc_row_stats(vcsgc_ctx *c) {
   return hipGetLastError();
 }
 
-// r < rc + skin list, one lane per atom: the lane walks the surrounding
-// search bins through the packed (x, y, z, index) slots, appends hits to its
+// r < rc + skin list, one lane per atom (used when some axis has fewer than
+// four search bins): the lane walks the surrounding search bins through the
+// packed (x, y, z, index) slots, appends hits to its
 // column-major row, then reloads the row into registers, sorts it by a fixed
 // bitonic network (ascending neighbour index) and writes it back.  The test
 // is r^2 < cut2: the list only has to hold every pair that can come within
@@ -476,6 +483,197 @@ __global__ void __launch_bounds__(BLOCK)
   zr[i] = zi;
 }
 
+// r < rc + skin list by super-bins of 2 x 2 x 2 search bins (every axis needs
+// at least four bins).  A block stages the 4 x 4 x 4 bins around its
+// super-bin in LDS once (positions relative to the super-bin origin, in
+// float, periodic images resolved), then four lanes per own atom test the
+// atom's 27 neighbouring bins from LDS and append hits to an LDS row.  The
+// float test uses cut2f = (cut + 1e-3)^2, a superset of r < cut (coordinates
+// are below 20 A, so the float error is below 1e-5 A); users of the list test
+// r < rc in FP64 themselves.  Rows go out unsorted, row-major, to tmp; the
+// finishing kernel sorts them and writes the column-major list.
+// Dynamic LDS: 64 * bmax float4.
+constexpr int SB_OWN = 64;  // own atoms per pass (four lanes each)
+
+__global__ void __launch_bounds__(BLOCK)
+    k_build_md_sb(Grid g, int nsx, int nsy, const int32_t *__restrict__ bcount,
+                  const double4 *__restrict__ bpos, int bmax, float cut2f, int32_t *tmp,
+                  int32_t *tcnt, const int *cond) {
+  if (cond && *cond == 0) return;
+  extern __shared__ float4 cand[];
+  __shared__ int cnt[64], off[65], gbin[64];
+  __shared__ double shx[64], shy[64], shz[64];
+  __shared__ int rowlen[SB_OWN];
+  __shared__ int32_t hit[SB_OWN * KMAX];
+  __shared__ int own_bins[8], n_own_bins;
+  const int tid = threadIdx.x;
+  const int64_t sb = xcd_block();
+  const int sx = (int)(sb % nsx), sy = (int)((sb / nsx) % nsy), sz = (int)(sb / ((int64_t)nsx * nsy));
+  const double bw0 = g.L0 / g.n0, bw1 = g.L1 / g.n1, bw2 = g.L2 / g.n2;
+  // origin of the super-bin
+  const double o0 = (2 * sx) * bw0, o1 = (2 * sy) * bw1, o2 = (2 * sz) * bw2;
+  if (tid < 64) {
+    const int ux = tid & 3, uy = (tid >> 2) & 3, uz = tid >> 4;
+    int gx = 2 * sx - 1 + ux, gy = 2 * sy - 1 + uy, gz = 2 * sz - 1 + uz;
+    double hx = 0.0, hy = 0.0, hz = 0.0;  // image shift
+    if (gx < 0) { gx += g.n0; hx = -g.L0; } else if (gx >= g.n0) { gx -= g.n0; hx = g.L0; }
+    if (gy < 0) { gy += g.n1; hy = -g.L1; } else if (gy >= g.n1) { gy -= g.n1; hy = g.L1; }
+    if (gz < 0) { gz += g.n2; hz = -g.L2; } else if (gz >= g.n2) { gz -= g.n2; hz = g.L2; }
+    const int b = gx + g.n0 * (gy + g.n1 * gz);
+    gbin[tid] = b;
+    shx[tid] = hx;
+    shy[tid] = hy;
+    shz[tid] = hz;
+    cnt[tid] = min(bcount[b], bmax);
+  }
+  if (tid == 0) {
+    // own bins: local coordinates 1..2 that exist on the grid
+    int k = 0;
+    for (int uz = 1; uz <= 2; ++uz)
+      for (int uy = 1; uy <= 2; ++uy)
+        for (int ux = 1; ux <= 2; ++ux)
+          if (2 * sx + ux - 1 < g.n0 && 2 * sy + uy - 1 < g.n1 && 2 * sz + uz - 1 < g.n2)
+            own_bins[k++] = ux + 4 * (uy + 4 * uz);
+    n_own_bins = k;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    off[0] = 0;
+    for (int u = 0; u < 64; ++u) off[u + 1] = off[u] + cnt[u];
+  }
+  __syncthreads();
+  // stage every slot of the 64 bins: (x, y, z) relative to the origin, index in w
+  for (int q = tid; q < 64 * bmax; q += BLOCK) {
+    const int u = q / bmax, t = q - u * bmax;
+    if (t < cnt[u]) {
+      const double4 p = bpos[(int64_t)gbin[u] * bmax + t];
+      cand[off[u] + t] = make_float4((float)(p.x + shx[u] - o0), (float)(p.y + shy[u] - o1),
+                                     (float)(p.z + shz[u] - o2), __int_as_float((int32_t)p.w));
+    }
+  }
+  int n_own = 0;
+  for (int k = 0; k < n_own_bins; ++k) n_own += cnt[own_bins[k]];
+  __syncthreads();
+  for (int base = 0; base < n_own; base += SB_OWN) {
+    const int a = tid >> 2, l = tid & 3;
+    // own atom base + a: its bin and staged index
+    int ob = -1, si = -1;
+    {
+      int q = base + a;
+      for (int k = 0; k < n_own_bins && q >= 0; ++k) {
+        const int u = own_bins[k];
+        if (q < cnt[u]) {
+          ob = u;
+          si = off[u] + q;
+          q = -1;
+        } else {
+          q -= cnt[u];
+        }
+      }
+    }
+    if (l == 0) rowlen[a] = 0;
+    __syncthreads();
+    if (si >= 0) {
+      const float4 me = cand[si];
+      const int lx = ob & 3, ly = (ob >> 2) & 3, lz = ob >> 4;
+      int phase = l;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int u0 = (lx - 1) + 4 * ((ly + dy) + 4 * (lz + dz));
+          const int a0 = off[u0], len = off[u0 + 3] - a0;
+          int t = phase;
+          for (; t < len; t += 4) {
+            const int ci = a0 + t;
+            if (ci == si) continue;
+            const float4 c = cand[ci];
+            const float dx = c.x - me.x, dyy = c.y - me.y, dzz = c.z - me.z;
+            if (dx * dx + dyy * dyy + dzz * dzz < cut2f) {
+              const int pos = atomicAdd(&rowlen[a], 1);
+              if (pos < KMAX) hit[a * KMAX + pos] = __float_as_int(c.w);
+            }
+          }
+          phase = t - len;
+        }
+    }
+    __syncthreads();
+    if (si >= 0) {
+      const int32_t i = __float_as_int(cand[si].w);
+      const int len = rowlen[a];
+      const int c = len < KMAX ? len : KMAX;
+      for (int k = l; k < c; k += 4) tmp[(int64_t)i * KMAX + k] = hit[a * KMAX + k];
+      if (l == 0) tcnt[i] = len;
+    }
+    __syncthreads();
+  }
+}
+
+// Sorts the rows of tmp (row-major, unsorted, tcnt entries) by a fixed
+// bitonic network, writes them column-major, and keeps the positions of this
+// build.  One lane per atom.
+__global__ void __launch_bounds__(BLOCK)
+    k_md_rows_finish(int64_t n, const int32_t *__restrict__ tmp, const int32_t *__restrict__ tcnt,
+                     const double *__restrict__ x, const double *__restrict__ y,
+                     const double *__restrict__ z, int32_t *nj, uint8_t *cnt, double *xr,
+                     double *yr, double *zr, DevState *ds, const int *cond) {
+  if (cond && *cond == 0) return;
+  const int64_t i = xcd_block() * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  int c = tcnt[i];
+  if (c > KMAX) {
+    atomicOr(&ds->overflow, 1);
+    c = KMAX;
+  }
+  int32_t v[KMAX];
+#pragma unroll
+  for (int u = 0; u < KMAX; ++u) v[u] = u < c ? tmp[i * KMAX + u] : INT32_MAX;
+#pragma unroll
+  for (int k = 2; k <= KMAX; k <<= 1) {
+#pragma unroll
+    for (int h = k >> 1; h > 0; h >>= 1) {
+#pragma unroll
+      for (int a = 0; a < KMAX; ++a) {
+        const int b = a ^ h;
+        if (b > a) {
+          const int32_t lo = min(v[a], v[b]), hi = max(v[a], v[b]);
+          const bool up = (a & k) == 0;
+          v[a] = up ? lo : hi;
+          v[b] = up ? hi : lo;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < KMAX; ++u)
+    if (u < c) nj[(int64_t)u * n + i] = v[u];
+  cnt[i] = (uint8_t)c;
+  xr[i] = x[i];
+  yr[i] = y[i];
+  zr[i] = z[i];
+}
+
+// the list build from filled search bins (super-bins when every axis has at
+// least four bins and the staged bins fit in LDS, else one lane per atom)
+hipError_t launch_md_build_chain(vcsgc_ctx *c, const Grid &g, const int *cond) {
+  const RepHost &r = c->reps[0];
+  const double cut = c->pot.rc + c->skin;
+  if (g.n0 >= 4 && g.n1 >= 4 && g.n2 >= 4 && c->bmax <= 32) {
+    const int nsx = (g.n0 + 1) / 2, nsy = (g.n1 + 1) / 2, nsz = (g.n2 + 1) / 2;
+    const float cf = (float)(cut + 1e-3);
+    const size_t lds = sizeof(float4) * 64 * (size_t)c->bmax;
+    k_build_md_sb<<<(unsigned)((int64_t)nsx * nsy * nsz), BLOCK, lds, c->stream>>>(
+        g, nsx, nsy, c->bin_count, c->bin_pos, c->bmax, cf * cf, c->md_tmp, c->md_tcnt, cond);
+    k_md_rows_finish<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->md_tmp, c->md_tcnt, c->x,
+                                                              c->y, c->z, c->md_j, c->md_cnt,
+                                                              c->xr, c->yr, c->zr, c->ds, cond);
+  } else {
+    k_build_md<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bin_count,
+                                                       c->bin_pos, c->bmax, cut * cut, c->md_j,
+                                                       c->md_cnt, c->xr, c->yr, c->zr, c->ds,
+                                                       cond);
+  }
+  return hipGetLastError();
+}
+
 // r < rc + skin list (single-system contexts)
 hipError_t launch_build_md_list(vcsgc_ctx *c) {
   const RepHost &r = c->reps[0];
@@ -484,12 +682,9 @@ hipError_t launch_build_md_list(vcsgc_ctx *c) {
   if (e == hipSuccess) e = hipMemsetAsync(&c->ds->kmax_md, 0, sizeof(int), c->stream);
   if (e != hipSuccess) return e;
   int h = tstart(c, VCSGC_KT_BUILD);
-  const double cut = c->pot.rc + c->skin;
-  k_build_md<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bin_count,
-                                                     c->bin_pos, c->bmax, cut * cut, c->md_j,
-                                                     c->md_cnt, c->xr, c->yr, c->zr, c->ds,
-                                                     nullptr);
+  e = launch_md_build_chain(c, g, nullptr);
   tstop(c, h);
+  if (e != hipSuccess) return e;
   k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_md,
                                             nullptr);
   return hipGetLastError();
@@ -503,15 +698,13 @@ hipError_t launch_md_rebuild_cond(vcsgc_ctx *c) {
   const RepHost &r = c->reps[0];
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   const int *cond = &c->ds->rebuild;
-  const double cut = c->pot.rc + c->skin;
   int h = tstart(c, VCSGC_KT_BUILD);
   k_bins_clear_cond<<<grid_for(r.nbins), BLOCK, 0, c->stream>>>(r.nbins, c->bin_count, c->ds);
   k_bin_search<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bmax,
                                                        c->bin_count, c->bin_atoms, c->bin_pos,
                                                        c->ds, cond);
-  k_build_md<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bin_count,
-                                                     c->bin_pos, c->bmax, cut * cut, c->md_j,
-                                                     c->md_cnt, c->xr, c->yr, c->zr, c->ds, cond);
+  hipError_t e = launch_md_build_chain(c, g, cond);
+  if (e != hipSuccess) return e;
   k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_md,
                                             cond);
   k_rebuild_done<<<1, 64, 0, c->stream>>>(c->ds);
@@ -540,15 +733,15 @@ __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
 
 // The r < rc rows taken from a valid r < rc + skin list (MD rows, column-major,
 // ascending j): same entries, same order and the same dd, g values as a build
-// from the search bins, since r is evaluated by the same expression.  A group
+// from the search bins, since r is evaluated by the same expression (the
+// packed positions are current whenever the MD list and its densities are).  A group
 // of MFM_G lanes per atom: lane l tests entries l, l + MFM_G, ...; the hits of
 // a pass are placed by a ballot prefix count, so the row keeps the MD order
 // and the stores of a group are contiguous.
 constexpr int MFM_G = 16;
 
 __global__ void __launch_bounds__(BLOCK)
-    k_mc_from_md(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                 const double *__restrict__ z, Grid g, const int32_t *__restrict__ mdj,
+    k_mc_from_md(int64_t n, const double4 *__restrict__ ps4, Grid g, const int32_t *__restrict__ mdj,
                  const uint8_t *__restrict__ mdcnt, PotD p, int32_t *nj, double *ndd, double *ng,
                  uint8_t *cnt) {
   const int64_t gid = xcd_block() * BLOCK + threadIdx.x;
@@ -556,7 +749,7 @@ __global__ void __launch_bounds__(BLOCK)
   const int l = (int)(gid % MFM_G);
   if (i >= n) return;  // whole groups leave together
   const int wl = threadIdx.x & 63, gb = wl & ~(MFM_G - 1);
-  const double xi = x[i], yi = y[i], zi = z[i];
+  const double4 qi = ps4[i];
   const int m = mdcnt[i];
   int base = 0;
   for (int k0 = 0; k0 < m; k0 += MFM_G) {
@@ -566,7 +759,11 @@ __global__ void __launch_bounds__(BLOCK)
     double r = 0.0;
     if (k < m) {
       j = mdj[(int64_t)k * n + i];
-      r = pair_r(x, y, z, g, xi, yi, zi, j);
+      const double4 qj = ps4[j];
+      const double dx = min_image(qj.x - qi.x, g.L0);
+      const double dy = min_image(qj.y - qi.y, g.L1);
+      const double dz = min_image(qj.z - qi.z, g.L2);
+      r = sqrt((dx * dx + dy * dy) + dz * dz);
       hit = r < p.rc;
     }
     const unsigned long long gm = (__ballot(hit) >> gb) & ((1ull << MFM_G) - 1ull);
@@ -587,7 +784,7 @@ hipError_t launch_mc_from_md(vcsgc_ctx *c) {
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   int h = tstart(c, VCSGC_KT_BUILD);
   k_mc_from_md<<<grid_for(c->n * MFM_G), BLOCK, 0, c->stream>>>(
-      c->n, c->x, c->y, c->z, g, c->md_j, c->md_cnt, c->pot, c->mc_j, c->mc_dd, c->mc_g,
+      c->n, c->ps4, g, c->md_j, c->md_cnt, c->pot, c->mc_j, c->mc_dd, c->mc_g,
       c->mc_cnt);
   tstop(c, h);
   return hipGetLastError();

@@ -54,6 +54,7 @@ struct DevState {
   unsigned long long stage1_pass;         // trials passing the surrogate stage
   unsigned long long smp_n, dalog_n;      // sample-log and surrogate-log records written
   unsigned long long md_rebuilds;         // MD list rebuilds taken on the device
+  unsigned long long wcur;                // sweep counter of a graph-replayed sweep
 };
 
 // ---------------------------------------------------------------------------
@@ -197,6 +198,9 @@ struct vcsgc_ctx {
   int bmax = 16;
   int32_t *bin_count = nullptr, *bin_atoms = nullptr;
   double4 *bin_pos = nullptr;  // (x, y, z, index) per bin slot (single-system contexts)
+  int32_t *md_tmp = nullptr, *md_tcnt = nullptr;  // unsorted MD rows (row-major) and lengths
+  int32_t *sites = nullptr;  // trial sites of one sweep, S x (cells / 8) (single-system)
+  void *stage_graph = nullptr;  // per-stage sweep replayed as a HIP graph (sweep.hip)
   int64_t nbins_total = 0;     // bins of all replicas
 
   // r < rc list, column-major rows [k * n + i]: neighbour, (rc-r)^2, c0 + c1 r
@@ -243,6 +247,8 @@ struct vcsgc_ctx {
 
   // optional per-kernel timing with HIP events on the context's stream
   uint32_t tmask = 0;
+  int32_t t_every = 1;                          // time one launch in t_every
+  int64_t kt_seen[VCSGC_KT_CLASSES] = {};       // launches per class since enabling
   struct Pending {
     int cls;
     hipEvent_t a, b;
@@ -291,6 +297,7 @@ hipError_t launch_descriptors(vcsgc_ctx *c, const int32_t *sites, int64_t n, int
                               double *out);
 hipError_t launch_density_mc(vcsgc_ctx *c);
 hipError_t launch_mc_from_md(vcsgc_ctx *c);
+void free_stage_graph(vcsgc_ctx *c);
 hipError_t launch_energy(vcsgc_ctx *c);  // fresh rho (MD list) + per-atom energies
 hipError_t launch_forces(vcsgc_ctx *c);  // fresh rho, F', forces (MD list)
 hipError_t launch_validate(vcsgc_ctx *c, const RepHost &r);

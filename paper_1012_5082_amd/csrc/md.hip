@@ -9,6 +9,7 @@ struct Box {
   double L0, L1, L2;
 };
 
+constexpr int IB = 16;  // neighbour indices loaded per round
 constexpr int UNR = 4;  // neighbour gathers in flight per lane
 
 // (x, y, z, species) of every atom, packed for the density pass
@@ -25,8 +26,43 @@ hipError_t launch_pack(vcsgc_ctx *c) {
   return hipGetLastError();
 }
 
-// rho_i = sum_{j: r < rc} t_{s_j} (rc - r)^2 and F'_i = -A_{s_i} / (2 sqrt(rho_i));
-// also writes (x_i, y_i, z_i, F'_i) for the force pass
+// rho_i = sum_{j: r < rc} t_{s_j} (rc - r)^2 over the row of i, in entry
+// order: the indices of up to IB entries in one round, then the gathers UNR
+// at a time
+__device__ __forceinline__ double density_row(int64_t n, int64_t i, int m, const double4 &qi,
+                                              const double4 *__restrict__ ps4,
+                                              const int32_t *__restrict__ nj, const Box &b,
+                                              const PotD &p) {
+  const double t0 = p.t[0], t1 = p.t[1];
+  double s = 0.0;
+  for (int k0 = 0; k0 < m; k0 += IB) {
+    int32_t jb[IB];
+#pragma unroll
+    for (int u = 0; u < IB; ++u) jb[u] = k0 + u < m ? nj[(int64_t)(k0 + u) * n + i] : (int32_t)i;
+#pragma unroll
+    for (int g = 0; g < IB; g += UNR) {
+      if (k0 + g >= m) break;
+      double4 q[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) q[u] = ps4[jb[g + u]];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const double dx = min_image(q[u].x - qi.x, b.L0);
+        const double dy = min_image(q[u].y - qi.y, b.L1);
+        const double dz = min_image(q[u].z - qi.z, b.L2);
+        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+        if (k0 + g + u < m && r < p.rc) {
+          const double d = p.rc - r;
+          s += (q[u].w != 0.0 ? t1 : t0) * (d * d);
+        }
+      }
+    }
+  }
+  return s;
+}
+
+// rho_i and F'_i = -A_{s_i} / (2 sqrt(rho_i)); also writes (x_i, y_i, z_i,
+// F'_i) for the force pass
 __global__ void __launch_bounds__(BLOCK)
     k_density_md(int64_t n, const double4 *__restrict__ ps4, const int32_t *__restrict__ nj,
                  const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
@@ -34,28 +70,8 @@ __global__ void __launch_bounds__(BLOCK)
   const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 qi = ps4[i];
-  double s = 0.0;
   const int m = cnt[i];
-  // UNR neighbours in flight: indices, then gathers, then the terms in order
-  for (int k = 0; k < m; k += UNR) {
-    int32_t j[UNR];
-    double4 q[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) j[u] = k + u < m ? nj[(int64_t)(k + u) * n + i] : (int32_t)i;
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) q[u] = ps4[j[u]];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const double dx = min_image(q[u].x - qi.x, b.L0);
-      const double dy = min_image(q[u].y - qi.y, b.L1);
-      const double dz = min_image(q[u].z - qi.z, b.L2);
-      const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-      if (k + u < m && r < p.rc) {
-        const double d = p.rc - r;
-        s += p.t[(int)q[u].w] * (d * d);
-      }
-    }
-  }
+  const double s = density_row(n, i, m, qi, ps4, nj, b, p);
   rho[i] = s;
   const double f = dembed(p, sp[i], s);
   fp[i] = f;
@@ -63,7 +79,52 @@ __global__ void __launch_bounds__(BLOCK)
 }
 
 // F_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i) / r with
-// phi'(r) = eps ((-2 d)(c0 + c1 r) + c1 d^2) and f'_X(r) = (-2 t_X) d, d = rc - r
+// phi'(r) = eps ((-2 d)(c0 + c1 r) + c1 d^2) and f'_X(r) = (-2 t_X) d, d = rc - r,
+// summed in entry order
+__device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, const double4 &qi,
+                                          const double4 *__restrict__ pf4,
+                                          const int32_t *__restrict__ nj,
+                                          const uint8_t *__restrict__ sp, const Box &b,
+                                          const PotD &p, double &ax, double &ay, double &az) {
+  const double fpi = qi.w;
+  const double e0 = p.eps[si], e1 = p.eps[si + 1], t0 = p.t[0], t1 = p.t[1], ti = p.t[si];
+  for (int k0 = 0; k0 < m; k0 += IB) {
+    int32_t jb[IB];
+#pragma unroll
+    for (int u = 0; u < IB; ++u) jb[u] = k0 + u < m ? nj[(int64_t)(k0 + u) * n + i] : (int32_t)i;
+#pragma unroll
+    for (int g = 0; g < IB; g += UNR) {
+      if (k0 + g >= m) break;
+      double4 q[UNR];
+      int sj[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        q[u] = pf4[jb[g + u]];
+        sj[u] = sp[jb[g + u]];
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const double dx = min_image(q[u].x - qi.x, b.L0);
+        const double dy = min_image(q[u].y - qi.y, b.L1);
+        const double dz = min_image(q[u].z - qi.z, b.L2);
+        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+        if (k0 + g + u < m && r < p.rc) {
+          const double d = p.rc - r;
+          const double eps = sj[u] ? e1 : e0, tj = sj[u] ? t1 : t0;
+          const double dphi = eps * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
+          const double dfj = -2.0 * tj * d;
+          const double dfi = -2.0 * ti * d;
+          const double s = dphi + fpi * dfj + q[u].w * dfi;
+          const double coef = s / r;
+          ax += coef * dx;
+          ay += coef * dy;
+          az += coef * dz;
+        }
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(BLOCK)
     k_forces(int64_t n, const double4 *__restrict__ pf4, const int32_t *__restrict__ nj,
              const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
@@ -72,39 +133,9 @@ __global__ void __launch_bounds__(BLOCK)
   if (i >= n) return;
   const double4 qi = pf4[i];
   const int si = sp[i];
-  const double fpi = qi.w;
-  double ax = 0.0, ay = 0.0, az = 0.0;
   const int m = cnt[i];
-  for (int k = 0; k < m; k += UNR) {
-    int32_t j[UNR];
-    double4 q[UNR];
-    int sj[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) j[u] = k + u < m ? nj[(int64_t)(k + u) * n + i] : (int32_t)i;
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      q[u] = pf4[j[u]];
-      sj[u] = sp[j[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const double dx = min_image(q[u].x - qi.x, b.L0);
-      const double dy = min_image(q[u].y - qi.y, b.L1);
-      const double dz = min_image(q[u].z - qi.z, b.L2);
-      const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-      if (k + u < m && r < p.rc) {
-        const double d = p.rc - r;
-        const double dphi = p.eps[si + sj[u]] * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
-        const double dfj = -2.0 * p.t[sj[u]] * d;
-        const double dfi = -2.0 * p.t[si] * d;
-        const double s = dphi + fpi * dfj + q[u].w * dfi;
-        const double coef = s / r;
-        ax += coef * dx;
-        ay += coef * dy;
-        az += coef * dz;
-      }
-    }
-  }
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  force_row(n, i, m, si, qi, pf4, nj, sp, b, p, ax, ay, az);
   fx[i] = ax;
   fy[i] = ay;
   fz[i] = az;

@@ -50,7 +50,16 @@ struct SweepArgs {
   // training-sample log: every stride-th trial's (descriptor, dU)
   double *smp_desc, *smp_de;
   int64_t smp_cap, smp_stride;
+  // sites of every stage of the current sweep, [s][t] (-1: empty cell)
+  int32_t *sites;
+  // graph replay: the sweep counter is read from here instead of the
+  // kernel argument (advanced by k_next_sweep at the end of each sweep)
+  const unsigned long long *wdev;
 };
+
+__device__ __forceinline__ uint64_t sweep_of(const SweepArgs &a, uint64_t w) {
+  return a.wdev ? (uint64_t)*a.wdev : w;
+}
 
 // Lanes per trial: lane k of a group handles neighbour entries k and k + TL.
 constexpr int TL = 16;
@@ -152,17 +161,28 @@ __device__ __forceinline__ int64_t colour_cell(const SweepArgs &a, int colour, i
   return cx + (int64_t)a.n0 * (cy + (int64_t)a.n1 * cz);
 }
 
-__device__ __forceinline__ long long block_sum(long long v, long long *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+// Sums of N integer values over the block (exact, so the order is free):
+// butterfly inside each wave, then the per-wave totals through LDS.  sh
+// needs N * (BLOCK / 64) entries; contains two barriers, so every thread of
+// the block must call it.
+template <int N>
+__device__ __forceinline__ void block_sums(long long (&v)[N], long long *sh) {
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[wv * N + k] = v[k];
   __syncthreads();
-  for (int h = BLOCK / 2; h > 0; h >>= 1) {
-    if (t < h) sh[t] += sh[t + h];
-    __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    long long t = 0;
+    for (int q = 0; q < BLOCK / 64; ++q) t += sh[q * N + k];
+    v[k] = t;
   }
-  const long long r = sh[0];
   __syncthreads();
-  return r;
 }
 
 __global__ void __launch_bounds__(BLOCK) k_init(DevState *ds) {
@@ -177,22 +197,50 @@ __global__ void __launch_bounds__(BLOCK) k_init(DevState *ds) {
   }
 }
 
+__global__ void k_set_sweep(DevState *ds, unsigned long long w) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ds->wcur = w;
+}
+
+__global__ void k_next_sweep(DevState *ds) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ds->wcur += 1ull;
+}
+
+// The trial sites of a whole sweep: for stage s and active cell t, the site
+// drawn from the cell's atoms (the draws the trial kernel would make), or -1
+// for an empty cell.  The cell lists do not change during a sweep.
+__global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
+  const uint64_t w = sweep_of(a, w_arg);
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (q >= a.S * a.ncpc) return;
+  const int64_t s = q / a.ncpc, t = q - s * a.ncpc;
+  const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+  const int64_t cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+  const int32_t st = a.cstart[cell];
+  const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
+  int32_t site = -1;
+  if (m > 0) {
+    const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
+    site = a.catoms[st + draw_index(r.v[0], m)];
+  }
+  a.sites[q] = site;
+}
+
 // one group of TL lanes per active cell
-__global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w, int64_t s, int par) {
+__global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, int64_t s, int par) {
+  const uint64_t w = sweep_of(a, w_arg);
   __shared__ long long sh[BLOCK];
   const int lane = threadIdx.x % TL;
   const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
   long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
   if (t < a.ncpc) {
+    const int32_t si = a.sites[s * a.ncpc + t];
     const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
     const int colour = (int)(g.v[0] >> 61);
     const int64_t cell = colour_cell(a, colour, t);
-    const int32_t st = a.cstart[cell];
-    const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
     int32_t site = -1;
-    if (m > 0) {
+    if (si >= 0) {
       const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
-      const int64_t i = a.catoms[st + draw_index(r.v[0], m)];
+      const int64_t i = si;
       const double du = delta_u_group(a, i, lane);
       if (a.smp_cap > 0 && ((int64_t)(w * (uint64_t)a.S + (uint64_t)s) * a.ncpc + t) % a.smp_stride == 0) {
         double d[10];
@@ -238,17 +286,15 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w, int64_
     if (lane == 0) a.rec[t] = site;
   }
   // per-block partial sums (no atomics): the commit kernel reduces them
-  const long long bv = block_sum(valid, sh);
-  const long long ba = block_sum(acc, sh);
-  const long long bd = block_sum(dn_acc, sh);
-  const long long bt = block_sum(tie, sh);
+  long long v4[4] = {valid, acc, dn_acc, tie};
+  block_sums<4>(v4, sh);
   if (threadIdx.x == 0) {
     long long *P = a.part + NPART * blockIdx.x;
-    P[0] = bv;
-    P[1] = ba;
-    P[2] = bd;
-    P[3] = bt;
-    P[4] = bv;  // no surrogate stage: every trial goes to the exact test
+    P[0] = v4[0];
+    P[1] = v4[1];
+    P[2] = v4[2];
+    P[3] = v4[3];
+    P[4] = v4[0];  // no surrogate stage: every trial goes to the exact test
   }
 }
 
@@ -371,33 +417,54 @@ __global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w, int
     }
     a.rec[t] = site;
   }
-  const long long bv = block_sum(valid, sh), ba = block_sum(acc, sh);
-  const long long bd = block_sum(dn_acc, sh), bt = block_sum(tie, sh);
-  const long long b1 = block_sum(p1, sh);
+  long long v5[5] = {valid, acc, dn_acc, tie, p1};
+  block_sums<5>(v5, sh);
   if (threadIdx.x == 0) {
     long long *P = a.part + NPART * blockIdx.x;
-    P[0] = bv;
-    P[1] = ba;
-    P[2] = bd;
-    P[3] = bt;
-    P[4] = b1;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) P[k] = v5[k];
   }
 }
 
 // one group of TL lanes per active cell: lane k updates rho of entries k, k + TL
-__global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64_t s, int par,
+__global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, int64_t s, int par,
                                                   int last) {
+  const uint64_t w = sweep_of(a, w_arg);
   __shared__ long long sh[BLOCK];
   const int lane = threadIdx.x % TL;
   const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
+  // the group's record and its row are read before the decision, so that
+  // these loads overlap the reduction below
+  int32_t i = -1;
+  int s0 = 0, m = 0;
+  int32_t jr[2] = {0, 0};
+  double ddr[2] = {0.0, 0.0};
+  if (t < a.ncpc) {
+    i = a.rec[t];
+    if (i >= 0) {
+      s0 = a.sp[i];
+      m = a.cnt[i];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = lane + h * TL;
+        if (k < m) {
+          const int64_t e = (int64_t)i * KMAX + k;
+          jr[h] = a.nj[e];
+          ddr[h] = a.ndd[e];
+        }
+      }
+    }
+  }
   // every block reduces the trial kernel's partial sums itself, in a fixed order
   long long pa = 0, pd = 0;
   for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
     pa += a.part[NPART * b + 1];
     pd += a.part[NPART * b + 2];
   }
-  const unsigned long long nrec = (unsigned long long)block_sum(pa, sh);
-  const long long dn_tot = block_sum(pd, sh);
+  long long v2[2] = {pa, pd};
+  block_sums<2>(v2, sh);
+  const unsigned long long nrec = (unsigned long long)v2[0];
+  const long long dn_tot = v2[1];
   const long long nb = a.ds->n_b[par];
   int gacc = -1;
   double xg = 0.0, mg = 0.0;
@@ -410,30 +477,24 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64
     mg = lnug + xg;
     gacc = lnug < -xg ? 1 : 0;
   }
-  if (gacc == 1 && t < a.ncpc) {
-    const int32_t i = a.rec[t];
-    if (i >= 0) {
-      const int s0 = a.sp[i], s1 = 1 - s0;
-      const int m = a.cnt[i];
+  if (gacc == 1 && i >= 0) {
+    const int s1 = 1 - s0;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int k = lane + h * TL;
-        if (k < m) {
-          const int64_t e = (int64_t)i * KMAX + k;
-          const int32_t j = a.nj[e];
-          const double dd = a.ndd[e];
-          const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
-          a.rho[j] = a.rho[j] + delta;
-        }
+    for (int h = 0; h < 2; ++h) {
+      const int k = lane + h * TL;
+      if (k < m) {
+        const double dd = ddr[h];
+        const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
+        a.rho[jr[h]] = a.rho[jr[h]] + delta;
       }
-      if (lane == 0) {
-        a.sp[i] = (uint8_t)s1;
-        if (a.vx) {
-          const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
-          a.vx[i] = a.vx[i] * f;
-          a.vy[i] = a.vy[i] * f;
-          a.vz[i] = a.vz[i] * f;
-        }
+    }
+    if (lane == 0) {
+      a.sp[i] = (uint8_t)s1;
+      if (a.vx) {
+        const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
+        a.vx[i] = a.vx[i] * f;
+        a.vy[i] = a.vy[i] * f;
+        a.vz[i] = a.vz[i] * f;
       }
     }
   }
@@ -444,9 +505,11 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w, int64
       pt += a.part[NPART * b + 3];
       p1 += a.part[NPART * b + 4];
     }
-    pv = block_sum(pv, sh);
-    pt = block_sum(pt, sh);
-    p1 = block_sum(p1, sh);
+    long long v3[3] = {pv, pt, p1};
+    block_sums<3>(v3, sh);
+    pv = v3[0];
+    pt = v3[1];
+    p1 = v3[2];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const long long nb_new = nb + (gacc == 1 ? dn_tot : 0);
@@ -517,6 +580,103 @@ hipError_t launch_descriptors(vcsgc_ctx *c, const int32_t *sites, int64_t n, int
   return hipGetLastError();
 }
 
+// Arguments of the kernel nodes of the per-stage sweep graph (kept with the
+// context while the graph lives).
+struct StageNodeArgs {
+  SweepArgs a;
+  uint64_t w;
+  int64_t s;
+  int par, last;
+};
+
+struct StageGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<StageNodeArgs> args;
+  double key[4] = {0, 0, 0, 0};
+  uint64_t seed = 0;
+};
+
+void free_stage_graph(vcsgc_ctx *c) {
+  StageGraph *g = (StageGraph *)c->stage_graph;
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  c->stage_graph = nullptr;
+}
+
+// One sweep as a graph: the site table, then trial and commit of every stage,
+// then the sweep counter advance.  Physical parameters and the seed are baked
+// in (the graph is rebuilt when they change); the sweep counter is read from
+// device memory.
+static hipError_t build_stage_graph(vcsgc_ctx *c, const SweepArgs &a0, double dmu0, double kappa,
+                                    double cbar, double T, uint64_t seed) {
+  free_stage_graph(c);
+  StageGraph *g = new StageGraph();
+  c->stage_graph = g;
+  g->key[0] = dmu0;
+  g->key[1] = kappa;
+  g->key[2] = cbar;
+  g->key[3] = T;
+  g->seed = seed;
+  hipError_t e = hipGraphCreate(&g->graph, 0);
+  if (e != hipSuccess) return e;
+  const int64_t S = c->S;
+  g->args.resize((size_t)(2 * S + 1));
+  SweepArgs a = a0;
+  a.wdev = &c->ds->wcur;
+  const unsigned gb = (unsigned)grid_for(a.ncpc * TL);
+  hipGraphNode_t prev = nullptr;
+  auto add = [&](void *fn, unsigned grid, void **params) -> hipError_t {
+    hipKernelNodeParams kp = {};
+    kp.func = fn;
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(BLOCK);
+    kp.kernelParams = params;
+    hipGraphNode_t node;
+    hipError_t e2 = hipGraphAddKernelNode(&node, g->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e2 == hipSuccess) prev = node;
+    return e2;
+  };
+  StageNodeArgs &sa = g->args[0];
+  sa.a = a;
+  sa.w = 0;
+  void *sp_[] = {&sa.a, &sa.w};
+  e = add((void *)k_sites, (unsigned)grid_for(a.S * a.ncpc), sp_);
+  if (e != hipSuccess) return e;
+  for (int64_t s = 0; s < S; ++s) {
+    StageNodeArgs &t = g->args[(size_t)(1 + 2 * s)];
+    t.a = a;
+    t.w = 0;
+    t.s = s;
+    t.par = (int)(s & 1);
+    t.last = 0;
+    void *tp[] = {&t.a, &t.w, &t.s, &t.par};
+    e = add((void *)k_trial, gb, tp);
+    if (e != hipSuccess) return e;
+    StageNodeArgs &u = g->args[(size_t)(2 + 2 * s)];
+    u = t;
+    u.last = s == S - 1 ? 1 : 0;
+    void *up[] = {&u.a, &u.w, &u.s, &u.par, &u.last};
+    e = add((void *)k_commit, gb, up);
+    if (e != hipSuccess) return e;
+  }
+  DevState *ds = c->ds;
+  void *np[] = {&ds};
+  {
+    hipKernelNodeParams kp = {};
+    kp.func = (void *)k_next_sweep;
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.kernelParams = np;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, g->graph, &prev, 1, &kp);
+    if (e != hipSuccess) return e;
+  }
+  return hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+}
+
 hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
                          int64_t n_sweeps, uint64_t seed) {
   SweepArgs a;
@@ -562,12 +722,38 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.smp_de = c->smp_de;
   a.smp_cap = c->smp_cap;
   a.smp_stride = c->smp_stride < 1 ? 1 : c->smp_stride;
-  k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
+  a.sites = c->sites;
+  a.wdev = nullptr;
   const int gb = grid_for(a.ncpc * TL);
   a.nblk = gb;
+  k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
+  // plain sweeps with no logs and no per-kernel timing replay a graph of one
+  // sweep (no host work per stage); everything else launches stage by stage
+  const bool per_kernel_timing = (c->tmask & ((1u << VCSGC_KT_TRIAL) | (1u << VCSGC_KT_COMMIT))) != 0;
+  if (!a.da_mode && !a.tlog && !a.slog && a.smp_cap == 0 && !per_kernel_timing && n_sweeps > 0) {
+    StageGraph *g = (StageGraph *)c->stage_graph;
+    if (!g || !g->exec || g->key[0] != dmu0 || g->key[1] != kappa || g->key[2] != cbar ||
+        g->key[3] != T || g->seed != seed) {
+      hipError_t e = build_stage_graph(c, a, dmu0, kappa, cbar, T, seed);
+      if (e != hipSuccess) {
+        free_stage_graph(c);
+        return e;
+      }
+      g = (StageGraph *)c->stage_graph;
+    }
+    k_set_sweep<<<1, 64, 0, c->stream>>>(c->ds, (unsigned long long)c->w);
+    int h = tstart(c, VCSGC_KT_PERSIST);
+    for (int64_t sw = 0; sw < n_sweeps; ++sw) {
+      hipError_t e = hipGraphLaunch(g->exec, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    tstop(c, h);
+    return hipGetLastError();
+  }
   int64_t q = 0;
   for (int64_t sw = 0; sw < n_sweeps; ++sw) {
     const uint64_t w = c->w + (uint64_t)sw;
+    if (!a.da_mode) k_sites<<<grid_for(a.S * a.ncpc), BLOCK, 0, c->stream>>>(a, w);
     for (int64_t s = 0; s < c->S; ++s, ++q) {
       const int par = (int)(q & 1);
       int h = tstart(c, VCSGC_KT_TRIAL);

@@ -220,6 +220,30 @@ def test_sweep_chunking_and_determinism(torch_cuda, oracle_mod):
     b.close()
 
 
+def test_stage_graph_replay(torch_cuda, oracle_mod):
+    """Per-stage sweeps without logs run as a replayed graph of one sweep
+    (sweep counter on the device, rebuilt when the parameters change): the
+    chain equals the oracle's across calls, chunks and parameter changes."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = W.c2(cbar=0.05)
+    _sweep_parity(O, d, pot, 6, log=False, chunks=[2, 1, 3], strategy="stage")
+    g = gpu_context(d, pot)
+    g.set_tuning("stage", 1)
+    st = oracle_state(O, d, pot)
+    plan = [((d["dmu0"], d["kappa"], 0.05, d["T"]), 2), ((d["dmu0"] + 0.02, 10.0, 0.04, 650.0), 3),
+            ((d["dmu0"], d["kappa"], 0.05, d["T"]), 1)]
+    for args, k in plan:
+        sg = g.sweep(*args, k, d["seed"])
+        so, _, _ = O.sweep(st, *args, k, d["seed"])
+        for key in ("trials", "local_accepts", "stage_accepts", "flips", "n_final"):
+            assert sg[key] == so[key], key
+        assert sg["sum_n"] == so["sum_n"]
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    g.close()
+
+
 def _md_system(n=10, T=700.0, seed=31, c=0.05):
     x, y, z, box = I.bcc(n, n, n)
     x, y, z = I.thermalize(x, y, z, box, 0.05, seed)
