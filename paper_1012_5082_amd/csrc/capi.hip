@@ -28,7 +28,7 @@ void free_all(vcsgc_ctx *c) {
                   c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
                   c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
                   c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos,
-                  c->md_tmp,     c->md_tcnt,    c->sites};
+                  c->md_tmp,     c->md_tcnt,    c->sites,      c->site_lnu};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -229,12 +229,14 @@ namespace vc {
 int tstart(vcsgc_ctx *c, int cls) {
   if (!(c->tmask & (1u << cls))) return -1;
   if (c->kt_seen[cls]++ % c->t_every != 0) return -1;
+  // timing-only events: no system-scope fence when recorded (the stream is
+  // synchronized before the times are read)
   hipEvent_t ev[2];
   for (int k = 0; k < 2; ++k) {
     if (!c->ev_pool.empty()) {
       ev[k] = c->ev_pool.back();
       c->ev_pool.pop_back();
-    } else if (hipEventCreate(&ev[k]) != hipSuccess) {
+    } else if (hipEventCreateWithFlags(&ev[k], hipEventDisableSystemFence) != hipSuccess) {
       if (k == 1) c->ev_pool.push_back(ev[0]);
       return -1;
     }
@@ -438,6 +440,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->md_tmp, K * n));
     A(dalloc(&c->md_tcnt, n));
     A(dalloc(&c->sites, reps[0].S * reps[0].ncpc));
+    A(dalloc(&c->site_lnu, reps[0].S * reps[0].ncpc));
   }
   A(dalloc(&c->cell_count, coff));
   A(dalloc(&c->cell_start, coff + R));

@@ -200,6 +200,7 @@ struct vcsgc_ctx {
   double4 *bin_pos = nullptr;  // (x, y, z, index) per bin slot (single-system contexts)
   int32_t *md_tmp = nullptr, *md_tcnt = nullptr;  // unsorted MD rows (row-major) and lengths
   int32_t *sites = nullptr;  // trial sites of one sweep, S x (cells / 8) (single-system)
+  double *site_lnu = nullptr;  // ln u of those trials
   void *stage_graph = nullptr;  // per-stage sweep replayed as a HIP graph (sweep.hip)
   int64_t nbins_total = 0;     // bins of all replicas
 

@@ -50,8 +50,10 @@ struct SweepArgs {
   // training-sample log: every stride-th trial's (descriptor, dU)
   double *smp_desc, *smp_de;
   int64_t smp_cap, smp_stride;
-  // sites of every stage of the current sweep, [s][t] (-1: empty cell)
+  // sites of every stage of the current sweep, [s][t] (-1: empty cell), and
+  // ln u of their local tests
   int32_t *sites;
+  double *site_lnu;
   // graph replay: the sweep counter is read from here instead of the
   // kernel argument (advanced by k_next_sweep at the end of each sweep)
   const unsigned long long *wdev;
@@ -205,9 +207,10 @@ __global__ void k_next_sweep(DevState *ds) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ds->wcur += 1ull;
 }
 
-// The trial sites of a whole sweep: for stage s and active cell t, the site
-// drawn from the cell's atoms (the draws the trial kernel would make), or -1
-// for an empty cell.  The cell lists do not change during a sweep.
+// The trials of a whole sweep: for stage s and active cell t, the site drawn
+// from the cell's atoms, or -1 for an empty cell, and ln u of the trial's
+// local test (the same draws, in the same precision, as a per-trial
+// evaluation).  The cell lists do not change during a sweep.
 __global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
   const uint64_t w = sweep_of(a, w_arg);
   const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -218,11 +221,14 @@ __global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
   const int32_t st = a.cstart[cell];
   const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
   int32_t site = -1;
+  double lnu = 0.0;
   if (m > 0) {
     const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
     site = a.catoms[st + draw_index(r.v[0], m)];
+    lnu = log(unit_open(r.v[1]));
   }
   a.sites[q] = site;
+  a.site_lnu[q] = lnu;
 }
 
 // one group of TL lanes per active cell
@@ -234,12 +240,9 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, in
   long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
   if (t < a.ncpc) {
     const int32_t si = a.sites[s * a.ncpc + t];
-    const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
-    const int colour = (int)(g.v[0] >> 61);
-    const int64_t cell = colour_cell(a, colour, t);
+    const double lnu = a.site_lnu[s * a.ncpc + t];
     int32_t site = -1;
     if (si >= 0) {
-      const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
       const int64_t i = si;
       const double du = delta_u_group(a, i, lane);
       if (a.smp_cap > 0 && ((int64_t)(w * (uint64_t)a.S + (uint64_t)s) * a.ncpc + t) % a.smp_stride == 0) {
@@ -254,10 +257,8 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, in
         }
       }
       if (lane == 0) {
-        const double u = unit_open(r.v[1]);
         const int dn = 1 - 2 * (int)a.sp[i];
         const double xl = a.beta * (du + a.dmu0 * (double)dn);
-        const double lnu = log(u);
         const double margin = lnu + xl;
         const bool ok = lnu < -xl;
         valid = 1;
@@ -270,10 +271,11 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, in
         if (a.tlog) {
           const unsigned long long idx = atomicAdd(&a.ds->tlog_n, 1ull);
           if ((int64_t)idx < a.tcap) {
+            const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
             double *L = a.tlog + 8 * idx;
             L[0] = (double)w;
             L[1] = (double)s;
-            L[2] = (double)cell;
+            L[2] = (double)colour_cell(a, (int)(g.v[0] >> 61), t);
             L[3] = (double)i;
             L[4] = (double)dn;
             L[5] = ok ? 1.0 : 0.0;
@@ -723,6 +725,7 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.smp_cap = c->smp_cap;
   a.smp_stride = c->smp_stride < 1 ? 1 : c->smp_stride;
   a.sites = c->sites;
+  a.site_lnu = c->site_lnu;
   a.wdev = nullptr;
   const int gb = grid_for(a.ncpc * TL);
   a.nblk = gb;
