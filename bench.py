@@ -295,6 +295,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
                     help="c3: hybrid cycle (default line); c4: replica batch; c5: surrogate DA")
     ap.add_argument("--sweeps", type=int, default=0, help="c4/c5: timed sweeps")
+    ap.add_argument("--local-steps", type=int, default=1,
+                    help="c3: trials per active cell per stage (1 = the plain scheme)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -326,14 +328,22 @@ def main():
     log(f"workload {d['name']}: {n} sites generated in {time.perf_counter() - t0:.1f} s")
     g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
               vz=d["vz"])
+    if args.local_steps > 1:
+        g.set_local_steps(args.local_steps)
     info = g.info()
     sweep_args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
     md_steps, dt = d["md_steps"], d["dt"]
 
-    # the autotuner's timing sweeps are real sweeps of the chain (warmup)
-    from paper_1012_5082_amd import autotune
-    tuned = autotune.tune(g, lambda k: g.sweep(*sweep_args, k, d["seed"], stats=False),
-                          use_cache=False)
+    # the autotuner's timing sweeps are real sweeps of the chain (warmup);
+    # local chains always run stage by stage
+    if args.local_steps > 1:
+        g.set_tuning("stage", 1)
+        g.sweep(*sweep_args, 2, d["seed"], stats=False)
+        tuned = {"choice": ("stage", 1), "times_ms": {}}
+    else:
+        from paper_1012_5082_amd import autotune
+        tuned = autotune.tune(g, lambda k: g.sweep(*sweep_args, k, d["seed"], stats=False),
+                              use_cache=False)
     log(f"autotune: {tuned['choice']} from {tuned['times_ms']}")
     for k in range(args.warmup):
         g.sweep(*sweep_args, 1, d["seed"])
@@ -362,7 +372,7 @@ def main():
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     trials = 0
-    flips = 0
+    flips = stages = stage_acc = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -373,6 +383,8 @@ def main():
         ev[k][2].record()
         trials += s["trials"]
         flips += s["flips"]
+        stages += s["stages"]
+        stage_acc += s["stage_accepts"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     mc_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
@@ -406,13 +418,16 @@ def main():
                                f"(100^3-cell box), FS-P1 EAM, kappa=1000 eV, cbar=0.03, "
                                f"T=700 K, step = 1 VC-SGC sweep + 20 MD steps (dt=1 fs)",
                    "n_sites": n, "n_cells": info["n_cells"],
-                   "stages_per_sweep": info["stages_per_sweep"], "variant": "plain",
+                   "stages_per_sweep": info["stages_per_sweep"],
+                   "variant": ("plain" if args.local_steps == 1
+                               else f"local chains of {args.local_steps} trials per cell"),
                    "sweep_tiling": list(tuned["choice"]),
                    "md_list_rebuilds": info2["md_rebuilds"]},
         "md_atom_steps_per_s": round(md_rate, 1),
         "mc_ms_per_sweep": round(mc_ms / args.steps, 3),
         "md_ms_per_step": round(md_ms / args.steps / md_steps, 4),
         "accepted_flips_per_s": round(flips / (mc_ms / 1e3), 1),
+        "stage_acceptance": round(stage_acc / max(1, stages), 4),
         "kernel_breakdown_ms": {k: round(v[0], 4) for k, v in breakdown.items()},
         "top_kernel": top,
         "autotune_ms_per_sweep": {k: round(v, 3) for k, v in tuned["times_ms"].items()},

@@ -135,6 +135,18 @@ vcsgc_status vcsgc_destroy(vcsgc_ctx *ctx);
 vcsgc_status vcsgc_sweep(vcsgc_ctx *ctx, double dmu0, double kappa, double cbar, double T_K,
                          int64_t n_sweeps, uint64_t seed, vcsgc_stats *out);
 
+/* Local chains (single-system contexts): every active cell makes k trials
+ * per stage (1 <= k <= 64; default 1, the scheme of Sec. III.B), each on the
+ * state left by the previous ones, with site and uniform from Philox counters
+ * (w, s, cell, 1 + q), q = 0..k-1.  A locally accepted trial is applied at
+ * once; the global factor of Eq. trans_vcsgc_par2 on the net change of n
+ * keeps or undoes the stage as a whole (the local chain is reversible with
+ * respect to the semi-grand-canonical weight at dmu0, so the product with the
+ * global factor samples the same VC-SGC ensemble).  A sweep then has
+ * 8 ceil(ceil(N / N_cells) / k) stages.  Such sweeps use per-stage launches;
+ * delayed acceptance and the sample log need k = 1.  Applies to later calls. */
+vcsgc_status vcsgc_set_local_steps(vcsgc_ctx *ctx, int32_t k);
+
 /* Batch of independent replicas (for example a scan over T, kappa and cbar
  * as in phase-diagram work): one context, one persistent launch per call.
  * sys describes the concatenated arrays (n_atoms = sum of rep_atoms; replica

@@ -433,6 +433,101 @@ static int or_da_local(const or_da *da, int64_t w, int64_t s, int64_t c, int64_t
                        double beta, double dmu0, const uint64_t t[4], double *du_out,
                        double *margin_out, int *pass1, int *status);
 
+/* Undo log of the tentative flips of one stage (local chains of k > 1
+ * steps): the values a flip overwrites, restored in reverse order when the
+ * global factor rejects the stage. */
+typedef struct {
+  int64_t idx;
+  int kind; /* 0: rho[idx], 1: species[idx], 2: velocity of idx */
+  double v[3];
+} or_undo;
+
+typedef struct {
+  or_undo *e;
+  int64_t n, cap;
+} or_undo_log;
+
+static void undo_push(or_undo_log *u, int64_t idx, int kind, double a, double b, double c) {
+  if (u->n == u->cap) {
+    u->cap = u->cap ? 2 * u->cap : 1024;
+    u->e = (or_undo *)realloc(u->e, (size_t)u->cap * sizeof(or_undo));
+  }
+  or_undo *x = &u->e[u->n++];
+  x->idx = idx;
+  x->kind = kind;
+  x->v[0] = a;
+  x->v[1] = b;
+  x->v[2] = c;
+}
+
+/* Flip at i applied in place with its undo records (the same arithmetic as
+ * or_commit). */
+static void or_apply_logged(int64_t i, const int64_t *start, const int32_t *nj, const double *nr,
+                            uint8_t *species, double *rho, const or_pot *p, double *vx,
+                            double *vy, double *vz, double mass_a, double mass_b,
+                            or_undo_log *u) {
+  for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+    if (e > start[i] && nj[e] == nj[e - 1]) continue;
+    if (!(nr[e] < p->rc)) {
+      int any = 0;
+      for (int64_t e2 = e; e2 < start[i + 1] && nj[e2] == nj[e]; ++e2) any |= nr[e2] < p->rc;
+      if (!any) continue;
+    }
+    undo_push(u, nj[e], 0, rho[nj[e]], 0.0, 0.0);
+  }
+  int s0 = species[i];
+  undo_push(u, i, 1, (double)s0, 0.0, 0.0);
+  or_commit(i, start, nj, nr, species, rho, p);
+  if (vx) {
+    undo_push(u, i, 2, vx[i], vy[i], vz[i]);
+    double m0 = s0 ? mass_b : mass_a, m1 = s0 ? mass_a : mass_b;
+    double f = sqrt(m0 / m1);
+    vx[i] = vx[i] * f;
+    vy[i] = vy[i] * f;
+    vz[i] = vz[i] * f;
+  }
+}
+
+static void undo_all(or_undo_log *u, uint8_t *species, double *rho, double *vx, double *vy,
+                     double *vz) {
+  for (int64_t k = u->n - 1; k >= 0; --k) {
+    const or_undo *x = &u->e[k];
+    if (x->kind == 0) rho[x->idx] = x->v[0];
+    else if (x->kind == 1) species[x->idx] = (uint8_t)x->v[0];
+    else {
+      vx[x->idx] = x->v[0];
+      vy[x->idx] = x->v[1];
+      vz[x->idx] = x->v[2];
+    }
+  }
+  u->n = 0;
+}
+
+/* The local test of Eq. trans_vcsgc_par1 for site i of trial block t:
+ * accept iff ln u < -beta (dU_i + dmu0 dn_i), u = unit(t[1]).  Returns the
+ * decision; dU, dn and the margin ln u + beta (dU + dmu0 dn) go out. */
+static int or_local_test(int64_t i, const uint64_t t[4], const int64_t *start,
+                         const int32_t *nj, const double *nr, const uint8_t *species,
+                         const double *rho, const or_pot *p, double beta, double dmu0,
+                         double *du_out, int *dn_out, double *margin_out) {
+  int dn = 1 - 2 * (int)species[i];
+  double u = or_unit(t[1]);
+  double du = or_delta_u(i, start, nj, nr, species, rho, p);
+  double xl = beta * (du + dmu0 * (double)dn);
+  double lnu = log(u);
+  *du_out = du;
+  *dn_out = dn;
+  *margin_out = lnu + xl;
+  return lnu < -xl;
+}
+
+/* Site of a trial: the floor(w0 m / 2^64)-th of the cell's m atoms. */
+static int64_t or_site(const uint64_t t[4], const int32_t *cstart, const int32_t *catoms,
+                       int64_t c) {
+  int64_t m = cstart[c + 1] - cstart[c];
+  return catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m)];
+}
+
 static int sweep_core(int64_t n, const double *x, const double *y, const double *z,
                       const double box[3], const int64_t *start, const int32_t *nj,
                       const double *nr, uint8_t *species, double *rho, int64_t *n_b,
@@ -440,6 +535,8 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
                       double *vz, double *tlog, int64_t tcap, int64_t *tn, double *slog,
                       int64_t scap, int64_t *sn, const double *over, int64_t n_over,
                       or_stats *st, or_da *da) {
+  const int64_t K = a->local_steps > 1 ? a->local_steps : 1;
+  if (K > 1 && da && da->mode != OR_DA_OFF) return -3; /* delayed acceptance: one step only */
   if (n < 1 || !(a->temp > 0.0) || !(a->kappa >= 0.0)) return -1;
   int32_t nc[3] = {1, 1, 1};
   int64_t ncells = 1;
@@ -478,12 +575,13 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
     int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((int64_t)nc[0] * nc[1]));
     ccol[c] = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
   }
-  int64_t S = a->one_cell ? n : 8 * ((n + ncells - 1) / ncells);
+  int64_t S = a->one_cell ? (n + K - 1) / K : 8 * ((((n + ncells - 1) / ncells) + K - 1) / K);
 
   double beta = 1.0 / (OR_KB * a->temp);
   double kN = a->kappa / (double)n;
   uint64_t key[2] = {a->seed, a->replica};
   int32_t *rec = (int32_t *)malloc((size_t)ncells * sizeof(int32_t));
+  or_undo_log ulog = {NULL, 0, 0};
   memset(st, 0, sizeof(*st));
   int64_t ntl = 0, nsl = 0;
 
@@ -493,13 +591,50 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
       or_philox4x64_10(key, ctr, g);
       int colour = (int)(g[0] >> 61);
       int64_t nrec = 0, dn_tot = 0;
-      for (int64_t c = 0; c < ncells; ++c) {
+      if (K > 1) {
+        /* local chains: every step on the state left by the previous one;
+         * accepted flips are applied at once and logged for undoing */
+        for (int64_t c = 0; c < ncells; ++c) {
+          if (!a->one_cell && ccol[c] != colour) continue;
+          int64_t m = cstart[c + 1] - cstart[c];
+          if (m == 0) continue;
+          for (int64_t q = 0; q < K; ++q) {
+            uint64_t tc[4] = {(uint64_t)w, (uint64_t)s, (uint64_t)c, (uint64_t)(1 + q)}, t[4];
+            or_philox4x64_10(key, tc, t);
+            int64_t i = or_site(t, cstart, catoms, c);
+            int dn;
+            double du, margin;
+            int acc = or_local_test(i, t, start, nj, nr, species, rho, p, beta, a->dmu0, &du, &dn,
+                                    &margin);
+            if (fabs(margin) < OR_TIE) {
+              st->near_ties++;
+              int dec;
+              if (over && or_over(over, n_over, w, s, c * K + q, &dec)) acc = dec;
+            }
+            st->trials++;
+            if (acc) {
+              st->local_accepts++;
+              nrec++;
+              dn_tot += dn;
+              or_apply_logged(i, start, nj, nr, species, rho, p, vx, vy, vz, a->mass_a,
+                              a->mass_b, &ulog);
+            }
+            if (tlog && ntl < tcap) {
+              double *L = tlog + 8 * ntl;
+              L[0] = (double)w; L[1] = (double)s; L[2] = (double)(c * K + q); L[3] = (double)i;
+              L[4] = (double)dn; L[5] = (double)acc; L[6] = du; L[7] = margin;
+            }
+            ntl++;
+          }
+        }
+      }
+      for (int64_t c = 0; c < ncells && K == 1; ++c) {
         if (!a->one_cell && ccol[c] != colour) continue;
         int64_t m = cstart[c + 1] - cstart[c];
         if (m == 0) continue;
         uint64_t tc[4] = {(uint64_t)w, (uint64_t)s, (uint64_t)c, 1}, t[4];
         or_philox4x64_10(key, tc, t);
-        int64_t i = catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m)];
+        int64_t i = or_site(t, cstart, catoms, c);
         int dn = 1 - 2 * (int)species[i];
         double du, margin;
         int acc;
@@ -514,12 +649,8 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
           if (pass1) da->stage1_pass++;
           if (fabs(margin) < OR_TIE) st->near_ties++;
         } else {
-          double u = or_unit(t[1]);
-          du = or_delta_u(i, start, nj, nr, species, rho, p);
-          double xl = beta * (du + a->dmu0 * (double)dn);
-          double lnu = log(u);
-          margin = lnu + xl;
-          acc = lnu < -xl;
+          acc = or_local_test(i, t, start, nj, nr, species, rho, p, beta, a->dmu0, &du, &dn,
+                              &margin);
           if (fabs(margin) < OR_TIE) {
             st->near_ties++;
             int dec;
@@ -554,7 +685,15 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
           int dec;
           if (over && or_over(over, n_over, w, s, -1, &dec)) gacc = dec;
         }
-        if (gacc) {
+        if (K > 1) {
+          if (gacc) ulog.n = 0; /* the tentative flips stay */
+          else undo_all(&ulog, species, rho, vx, vy, vz);
+          if (gacc) {
+            *n_b += dn_tot;
+            st->flips += nrec;
+            st->stage_accepts++;
+          }
+        } else if (gacc) {
           for (int64_t k = 0; k < nrec; ++k) {
             int64_t i = rec[k];
             int s0 = species[i];
@@ -585,6 +724,7 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
   st->n_final = *n_b;
   if (tn) *tn = ntl;
   if (sn) *sn = nsl;
+  free(ulog.e);
   free(rec);
   free(cstart);
   free(catoms);

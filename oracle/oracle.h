@@ -61,6 +61,7 @@ typedef struct {
   double r_dep;     /* independence distance: cell edge >= r_dep */
   int32_t one_cell; /* serial mode: one cell holding every site, N stages per sweep */
   double mass_a, mass_b; /* for velocity rescaling on transmutation */
+  int32_t local_steps;   /* trials per active cell per stage (0 or 1: one) */
 } or_sweep_args;
 
 typedef struct {
@@ -70,6 +71,13 @@ typedef struct {
 
 /* One pass of n_sweeps sweeps.  species, rho and n (count of species 1)
  * are updated in place.  vx/vy/vz may be NULL.
+ * With local_steps = k > 1 every active cell runs a local Metropolis chain
+ * of k trials per stage (each on the state left by the previous one, sites
+ * and uniforms from Philox(key, (w, s, cell, 1 + q)), q = 0..k-1); the
+ * composite move of the stage is the product of these chains and is kept or
+ * undone as a whole by the global factor on its net dn_tot.  A sweep then has
+ * 8 ceil(ceil(N / N_cells) / k) stages (ceil(N / k) in one-cell mode).  In the
+ * trial log and the overrides the cell field holds cell * k + q.
  * tlog: trial log, 8 doubles per trial (w, s, cell, site, dn, acc, dU, margin),
  * slog: stage log, 8 doubles per stage (w, s, colour, dn_tot, nrec, acc, xg, margin),
  * over: near-tie decisions to adopt, 4 doubles each (w, s, cell or -1, decision).

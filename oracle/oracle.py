@@ -40,7 +40,8 @@ class SweepArgs(C.Structure):
     _fields_ = [("dmu0", C.c_double), ("kappa", C.c_double), ("cbar", C.c_double),
                 ("temp", C.c_double), ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("w0", C.c_int64), ("n_sweeps", C.c_int64), ("r_dep", C.c_double),
-                ("one_cell", C.c_int32), ("mass_a", C.c_double), ("mass_b", C.c_double)]
+                ("one_cell", C.c_int32), ("mass_a", C.c_double), ("mass_b", C.c_double),
+                ("local_steps", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -241,14 +242,15 @@ class SweepState:
 
 def sweep(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, replica=0, r_dep=None,
           one_cell=False, log_trials=0, log_stages=0, overrides=None,
-          mass_a=55.845, mass_b=63.546):
-    """Run n_sweeps sweeps from the state's sweep counter; returns (stats, tlog, slog)."""
+          mass_a=55.845, mass_b=63.546, local_steps=1):
+    """Run n_sweeps sweeps from the state's sweep counter; returns (stats, tlog, slog).
+    local_steps = k: k trials per active cell per stage (exact local chains)."""
     L = lib()
     if r_dep is None:
         r_dep = 2.0 * st.pot.rc
     a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
                   int(st.w), int(n_sweeps), float(r_dep), int(bool(one_cell)),
-                  float(mass_a), float(mass_b))
+                  float(mass_a), float(mass_b), int(local_steps))
     tlog = np.zeros((max(log_trials, 0), 8)) if log_trials else None
     slog = np.zeros((max(log_stages, 0), 8)) if log_stages else None
     tn = np.zeros(1, dtype=np.int64)

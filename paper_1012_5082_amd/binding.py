@@ -126,6 +126,8 @@ def lib():
         L.vcsgc_get_info.argtypes = [_P, C.POINTER(Info)]
         L.vcsgc_kernel_timing.restype = st
         L.vcsgc_kernel_timing.argtypes = [_P, C.c_uint32]
+        L.vcsgc_set_local_steps.restype = st
+        L.vcsgc_set_local_steps.argtypes = [_P, C.c_int32]
         L.vcsgc_kernel_timing_sampled.restype = st
         L.vcsgc_kernel_timing_sampled.argtypes = [_P, C.c_uint32, C.c_int32]
         L.vcsgc_get_kernel_timing.restype = st
@@ -354,6 +356,10 @@ class VCSGC:
     def set_tuning(self, strategy="graph", trials_per_group=1):
         self._check(lib().vcsgc_set_tuning(self._h, STRATEGIES[strategy], int(trials_per_group)),
                     "set_tuning")
+
+    def set_local_steps(self, k):
+        """Trials per active cell per stage (local chains; 1 = the plain scheme)."""
+        self._check(lib().vcsgc_set_local_steps(self._h, int(k)), "set_local_steps")
 
     def tuning(self):
         a, b, g = C.c_int32(), C.c_int32(), C.c_int32()

@@ -28,7 +28,8 @@ void free_all(vcsgc_ctx *c) {
                   c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
                   c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
                   c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos,
-                  c->md_tmp,     c->md_tcnt,    c->sites,      c->site_lnu};
+                  c->md_tmp,     c->md_tcnt,    c->sites,      c->site_lnu,
+                  c->u_site,     c->u_j,        c->u_rho,      c->u_v};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -585,8 +586,12 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
     if (st) return st;
   }
   if (n_sweeps > 0) c->rho_f_fresh = false;
-  // delayed acceptance and the training-sample log run with per-stage launches
-  if ((c->strategy == 2 || c->da_mode || c->smp_cap > 0) && R == 1) {
+  if (c->local_steps > 1 && (c->da_mode || c->smp_cap > 0))
+    return fail(c, VCSGC_E_INVALID_ARG,
+                "delayed acceptance and the sample log need one trial per cell per stage");
+  // delayed acceptance, the training-sample log and local chains run with
+  // per-stage launches
+  if ((c->strategy == 2 || c->da_mode || c->smp_cap > 0 || c->local_steps > 1) && R == 1) {
     // one trial kernel and one commit kernel per stage
     VC_CHECK(c, vc::persist_sync_nb_to_stage(c), "sweep");
     VC_CHECK(c, vc::launch_sweeps(c, dmu0[0], kappa[0], cbar[0], T[0], n_sweeps, seed), "sweep");
@@ -665,6 +670,33 @@ vcsgc_status vcsgc_set_tuning(vcsgc_ctx *c, int32_t strategy, int32_t trials_per
       c->npart = c->grid_total;
       VC_CHECK(c, dalloc(&c->part, vc::NPART * c->npart), "allocation");
     }
+  }
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_set_local_steps(vcsgc_ctx *c, int32_t k) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (c->reps.size() != 1) return fail(c, VCSGC_E_INVALID_ARG, "local chains need a single system");
+  if (k < 1 || k > 64) return fail(c, VCSGC_E_INVALID_ARG, "local chain length in [1, 64]");
+  if (k == c->local_steps) return VCSGC_OK;
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  vc::free_stage_graph(c);  // its nodes hold the old buffers
+  void *old[] = {c->sites, c->site_lnu, c->u_site, c->u_j, c->u_rho, c->u_v};
+  for (void *p : old)
+    if (p) (void)hipFree(p);
+  c->sites = c->u_site = c->u_j = nullptr;
+  c->site_lnu = c->u_rho = c->u_v = nullptr;
+  c->local_steps = k;
+  const int64_t ncpc = c->ncells / 8, K = k;
+  const int64_t tab = vc::stages_per_sweep(c) * ncpc * K;
+  VC_CHECK(c, dalloc(&c->sites, tab), "allocation");
+  VC_CHECK(c, dalloc(&c->site_lnu, tab), "allocation");
+  if (K > 1) {
+    VC_CHECK(c, dalloc(&c->u_site, ncpc * K), "allocation");
+    VC_CHECK(c, dalloc(&c->u_j, ncpc * K * vc::KMAX), "allocation");
+    VC_CHECK(c, dalloc(&c->u_rho, ncpc * K * vc::KMAX), "allocation");
+    VC_CHECK(c, dalloc(&c->u_v, ncpc * K * 3), "allocation");
   }
   return VCSGC_OK;
 }
@@ -890,7 +922,7 @@ vcsgc_status vcsgc_get_info(vcsgc_ctx *c, vcsgc_info *out) {
   if (st) return st;
   if (!out) return fail(c, VCSGC_E_INVALID_ARG, "null output");
   for (int d = 0; d < 3; ++d) out->n_cells[d] = c->nc[d];
-  out->stages_per_sweep = c->S;
+  out->stages_per_sweep = c->reps.size() == 1 ? vc::stages_per_sweep(c) : c->S;
   out->kmax = vc::KMAX;
   hipError_t e;
   vc::DevState h = read_state(c, &e);

@@ -201,6 +201,9 @@ struct vcsgc_ctx {
   int32_t *md_tmp = nullptr, *md_tcnt = nullptr;  // unsorted MD rows (row-major) and lengths
   int32_t *sites = nullptr;  // trial sites of one sweep, S x (cells / 8) (single-system)
   double *site_lnu = nullptr;  // ln u of those trials
+  int local_steps = 1;          // trials per active cell per stage (local chain length)
+  int32_t *u_site = nullptr, *u_j = nullptr;  // undo log of a stage of local chains
+  double *u_rho = nullptr, *u_v = nullptr;
   void *stage_graph = nullptr;  // per-stage sweep replayed as a HIP graph (sweep.hip)
   int64_t nbins_total = 0;     // bins of all replicas
 
@@ -285,6 +288,13 @@ namespace vc {
 // returns a handle (or -1); tstop records the matching end event.
 int tstart(vcsgc_ctx *c, int cls);
 void tstop(vcsgc_ctx *c, int h);
+
+// Stages per sweep of a single-system context: 8 ceil(ceil(N / N_cells) / k)
+// for local chains of k trials (8 ceil(N / N_cells) for k = 1).
+inline int64_t stages_per_sweep(const vcsgc_ctx *c) {
+  const int64_t m = (c->n + c->ncells - 1) / c->ncells;
+  return 8 * ((m + c->local_steps - 1) / c->local_steps);
+}
 
 hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r);

@@ -57,6 +57,12 @@ struct SweepArgs {
   // graph replay: the sweep counter is read from here instead of the
   // kernel argument (advanced by k_next_sweep at the end of each sweep)
   const unsigned long long *wdev;
+  // local chains of K > 1 trials per active cell per stage: per (cell, step)
+  // the site flipped (-1: none), the old velocity, and per neighbour entry
+  // the index and old density, to undo a rejected stage
+  int K;
+  int32_t *u_site, *u_j;
+  double *u_rho, *u_v;
 };
 
 __device__ __forceinline__ uint64_t sweep_of(const SweepArgs &a, uint64_t w) {
@@ -220,15 +226,18 @@ __global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
   const int64_t cell = colour_cell(a, (int)(g.v[0] >> 61), t);
   const int32_t st = a.cstart[cell];
   const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
-  int32_t site = -1;
-  double lnu = 0.0;
-  if (m > 0) {
-    const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
-    site = a.catoms[st + draw_index(r.v[0], m)];
-    lnu = log(unit_open(r.v[1]));
+  // trial k of the cell's chain: Philox(key, (w, s, cell, 1 + k))
+  for (int k = 0; k < a.K; ++k) {
+    int32_t site = -1;
+    double lnu = 0.0;
+    if (m > 0) {
+      const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1 + (uint64_t)k);
+      site = a.catoms[st + draw_index(r.v[0], m)];
+      lnu = log(unit_open(r.v[1]));
+    }
+    a.sites[q * a.K + k] = site;
+    a.site_lnu[q * a.K + k] = lnu;
   }
-  a.sites[q] = site;
-  a.site_lnu[q] = lnu;
 }
 
 // one group of TL lanes per active cell
@@ -297,6 +306,104 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, in
     P[2] = v4[2];
     P[3] = v4[3];
     P[4] = v4[0];  // no surrogate stage: every trial goes to the exact test
+  }
+}
+
+// Local chains (K > 1): the TL lanes of a group run the K trials of their
+// cell in order, each on the state left by the previous ones.  An accepted
+// trial is applied at once (densities of the neighbours, species, velocity),
+// with the overwritten values kept in the undo log; the block synchronizes
+// between trials so that every lane sees the group's updates.  Chains of
+// different active cells touch disjoint atoms (same-colour cells are a cell
+// edge >= 2 rc apart), so they run side by side.
+__global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_arg, int64_t s,
+                                                       int par) {
+  const uint64_t w = sweep_of(a, w_arg);
+  __shared__ long long sh[BLOCK];
+  const int lane = threadIdx.x % TL;
+  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
+  const bool live = t < a.ncpc;
+  long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
+  for (int k = 0; k < a.K; ++k) {
+    const int64_t q = (s * a.ncpc + t) * a.K + k;  // the sweep's table
+    const int64_t uq = t * a.K + k;                // this stage's undo log
+    const int32_t si = live ? a.sites[q] : -1;
+    int32_t flipped = -1;
+    if (si >= 0) {
+      const int64_t i = si;
+      const double lnu = a.site_lnu[q];
+      const double du = delta_u_group(a, i, lane);
+      const int s0 = a.sp[i];
+      const int dn = 1 - 2 * s0;
+      const double xl = a.beta * (du + a.dmu0 * (double)dn);
+      const double margin = lnu + xl;
+      const bool ok = lnu < -xl;  // the same on every lane of the group
+      if (lane == 0) {
+        valid += 1;
+        tie += fabs(margin) < TIE ? 1 : 0;
+        if (ok) {
+          acc += 1;
+          dn_acc += dn;
+        }
+        if (a.tlog) {
+          const unsigned long long idx = atomicAdd(&a.ds->tlog_n, 1ull);
+          if ((int64_t)idx < a.tcap) {
+            const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+            double *L = a.tlog + 8 * idx;
+            L[0] = (double)w;
+            L[1] = (double)s;
+            L[2] = (double)(colour_cell(a, (int)(g.v[0] >> 61), t) * a.K + k);
+            L[3] = (double)i;
+            L[4] = (double)dn;
+            L[5] = ok ? 1.0 : 0.0;
+            L[6] = du;
+            L[7] = margin;
+          }
+        }
+      }
+      if (ok) {
+        const int s1 = 1 - s0;
+        const int m = a.cnt[i];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int e = lane + h * TL;
+          if (e < m) {
+            const int64_t ee = i * KMAX + e;
+            const int32_t j = a.nj[ee];
+            const double dd = a.ndd[ee];
+            const double old = a.rho[j];
+            a.u_j[uq * KMAX + e] = j;
+            a.u_rho[uq * KMAX + e] = old;
+            a.rho[j] = old + (a.p.t[s1] * dd - a.p.t[s0] * dd);
+          }
+        }
+        if (lane == 0) {
+          a.sp[i] = (uint8_t)s1;
+          if (a.vx) {
+            const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
+            a.u_v[3 * uq + 0] = a.vx[i];
+            a.u_v[3 * uq + 1] = a.vy[i];
+            a.u_v[3 * uq + 2] = a.vz[i];
+            a.vx[i] = a.vx[i] * f;
+            a.vy[i] = a.vy[i] * f;
+            a.vz[i] = a.vz[i] * f;
+          }
+        }
+        flipped = si;
+      }
+    }
+    if (live && lane == 0) a.u_site[uq] = flipped;
+    __syncthreads();  // the group's updates are seen by its next trial
+  }
+  long long v4[4] = {valid, acc, dn_acc, tie};
+  block_sums<4>(v4, sh);
+  if (threadIdx.x == 0) {
+    long long *P = a.part + NPART * blockIdx.x;
+    P[0] = v4[0];
+    P[1] = v4[1];
+    P[2] = v4[2];
+    P[3] = v4[3];
+    P[4] = v4[0];
   }
 }
 
@@ -428,36 +535,18 @@ __global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w, int
   }
 }
 
-// one group of TL lanes per active cell: lane k updates rho of entries k, k + TL
-__global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, int64_t s, int par,
-                                                  int last) {
-  const uint64_t w = sweep_of(a, w_arg);
-  __shared__ long long sh[BLOCK];
-  const int lane = threadIdx.x % TL;
-  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
-  // the group's record and its row are read before the decision, so that
-  // these loads overlap the reduction below
-  int32_t i = -1;
-  int s0 = 0, m = 0;
-  int32_t jr[2] = {0, 0};
-  double ddr[2] = {0.0, 0.0};
-  if (t < a.ncpc) {
-    i = a.rec[t];
-    if (i >= 0) {
-      s0 = a.sp[i];
-      m = a.cnt[i];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int k = lane + h * TL;
-        if (k < m) {
-          const int64_t e = (int64_t)i * KMAX + k;
-          jr[h] = a.nj[e];
-          ddr[h] = a.ndd[e];
-        }
-      }
-    }
-  }
-  // every block reduces the trial kernel's partial sums itself, in a fixed order
+// The global test of a stage (Eq. trans_vcsgc_par2): every block reduces the
+// trial kernel's partial sums itself, in a fixed order.  Returns 1 (accept),
+// 0 (reject) or -1 (nothing to decide).  Must be called by the whole block.
+struct StageDecision {
+  unsigned long long nrec;
+  long long dn_tot, nb;
+  double xg, mg;
+  int gacc;
+};
+
+__device__ __forceinline__ StageDecision stage_decision(const SweepArgs &a, uint64_t w, int64_t s,
+                                                        int par, long long *sh) {
   long long pa = 0, pd = 0;
   for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
     pa += a.part[NPART * b + 1];
@@ -465,41 +554,33 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, i
   }
   long long v2[2] = {pa, pd};
   block_sums<2>(v2, sh);
-  const unsigned long long nrec = (unsigned long long)v2[0];
-  const long long dn_tot = v2[1];
-  const long long nb = a.ds->n_b[par];
-  int gacc = -1;
-  double xg = 0.0, mg = 0.0;
-  if (nrec > 0) {
+  StageDecision d;
+  d.nrec = (unsigned long long)v2[0];
+  d.dn_tot = v2[1];
+  d.nb = a.ds->n_b[par];
+  d.gacc = -1;
+  d.xg = 0.0;
+  d.mg = 0.0;
+  if (d.nrec > 0) {
     const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
-    const double tt = (double)nb - a.ncbar;
-    const double dnd = (double)dn_tot;
-    xg = a.beta * a.kN * dnd * (dnd + 2.0 * tt);
+    const double tt = (double)d.nb - a.ncbar;
+    const double dnd = (double)d.dn_tot;
+    d.xg = a.beta * a.kN * dnd * (dnd + 2.0 * tt);
     const double lnug = log(unit_open(g.v[1]));
-    mg = lnug + xg;
-    gacc = lnug < -xg ? 1 : 0;
+    d.mg = lnug + d.xg;
+    d.gacc = lnug < -d.xg ? 1 : 0;
   }
-  if (gacc == 1 && i >= 0) {
-    const int s1 = 1 - s0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = lane + h * TL;
-      if (k < m) {
-        const double dd = ddr[h];
-        const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
-        a.rho[jr[h]] = a.rho[jr[h]] + delta;
-      }
-    }
-    if (lane == 0) {
-      a.sp[i] = (uint8_t)s1;
-      if (a.vx) {
-        const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
-        a.vx[i] = a.vx[i] * f;
-        a.vy[i] = a.vy[i] * f;
-        a.vz[i] = a.vz[i] * f;
-      }
-    }
-  }
+  return d;
+}
+
+// Statistics and the stage log after the decision (block 0; the whole block
+// calls it).
+__device__ __forceinline__ void stage_stats(const SweepArgs &a, uint64_t w, int64_t s, int par,
+                                            int last, const StageDecision &dc, long long *sh) {
+  const int gacc = dc.gacc;
+  const unsigned long long nrec = dc.nrec;
+  const long long dn_tot = dc.dn_tot, nb = dc.nb;
+  const double xg = dc.xg, mg = dc.mg;
   long long pv = 0, pt = 0, p1 = 0;
   if (blockIdx.x == 0) {
     for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
@@ -547,6 +628,97 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, i
       }
     }
   }
+}
+
+
+// one group of TL lanes per active cell: lane k updates rho of entries k, k + TL
+__global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, int64_t s, int par,
+                                                  int last) {
+  const uint64_t w = sweep_of(a, w_arg);
+  __shared__ long long sh[BLOCK];
+  const int lane = threadIdx.x % TL;
+  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
+  // the group's record and its row are read before the decision, so that
+  // these loads overlap the reduction below
+  int32_t i = -1;
+  int s0 = 0, m = 0;
+  int32_t jr[2] = {0, 0};
+  double ddr[2] = {0.0, 0.0};
+  if (t < a.ncpc) {
+    i = a.rec[t];
+    if (i >= 0) {
+      s0 = a.sp[i];
+      m = a.cnt[i];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = lane + h * TL;
+        if (k < m) {
+          const int64_t e = (int64_t)i * KMAX + k;
+          jr[h] = a.nj[e];
+          ddr[h] = a.ndd[e];
+        }
+      }
+    }
+  }
+  const StageDecision dc = stage_decision(a, w, s, par, sh);
+  const int gacc = dc.gacc;
+  if (gacc == 1 && i >= 0) {
+    const int s1 = 1 - s0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = lane + h * TL;
+      if (k < m) {
+        const double dd = ddr[h];
+        const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
+        a.rho[jr[h]] = a.rho[jr[h]] + delta;
+      }
+    }
+    if (lane == 0) {
+      a.sp[i] = (uint8_t)s1;
+      if (a.vx) {
+        const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
+        a.vx[i] = a.vx[i] * f;
+        a.vy[i] = a.vy[i] * f;
+        a.vz[i] = a.vz[i] * f;
+      }
+    }
+  }
+  stage_stats(a, w, s, par, last, dc, sh);
+}
+
+// Global test of a stage of local chains: a rejected stage is undone, each
+// group restoring its cell's accepted trials in reverse order.
+__global__ void __launch_bounds__(BLOCK) k_commit_chain(SweepArgs a, uint64_t w_arg, int64_t s,
+                                                        int par, int last) {
+  const uint64_t w = sweep_of(a, w_arg);
+  __shared__ long long sh[BLOCK];
+  const int lane = threadIdx.x % TL;
+  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
+  const StageDecision dc = stage_decision(a, w, s, par, sh);
+  if (dc.gacc == 0) {  // uniform over the grid
+    for (int k = a.K - 1; k >= 0; --k) {
+      const int64_t uq = t * a.K + k;
+      const int32_t i = t < a.ncpc ? a.u_site[uq] : -1;
+      if (i >= 0) {
+        const int m = a.cnt[i];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int e = lane + h * TL;
+          if (e < m) a.rho[a.u_j[uq * KMAX + e]] = a.u_rho[uq * KMAX + e];
+        }
+        if (lane == 0) {
+          a.sp[i] = (uint8_t)(1 - a.sp[i]);
+          if (a.vx) {
+            a.vx[i] = a.u_v[3 * uq + 0];
+            a.vy[i] = a.u_v[3 * uq + 1];
+            a.vz[i] = a.u_v[3 * uq + 2];
+          }
+        }
+      }
+      __syncthreads();  // later trials are undone before earlier ones
+    }
+  }
+  stage_stats(a, w, s, par, last, dc, sh);
 }
 
 __global__ void __launch_bounds__(BLOCK)
@@ -597,6 +769,7 @@ struct StageGraph {
   std::vector<StageNodeArgs> args;
   double key[4] = {0, 0, 0, 0};
   uint64_t seed = 0;
+  int K = 1;
 };
 
 void free_stage_graph(vcsgc_ctx *c) {
@@ -613,7 +786,8 @@ void free_stage_graph(vcsgc_ctx *c) {
 // in (the graph is rebuilt when they change); the sweep counter is read from
 // device memory.
 static hipError_t build_stage_graph(vcsgc_ctx *c, const SweepArgs &a0, double dmu0, double kappa,
-                                    double cbar, double T, uint64_t seed) {
+                                    double cbar, double T, uint64_t seed, void *f_trial,
+                                    void *f_commit) {
   free_stage_graph(c);
   StageGraph *g = new StageGraph();
   c->stage_graph = g;
@@ -622,9 +796,10 @@ static hipError_t build_stage_graph(vcsgc_ctx *c, const SweepArgs &a0, double dm
   g->key[2] = cbar;
   g->key[3] = T;
   g->seed = seed;
+  g->K = a0.K;
   hipError_t e = hipGraphCreate(&g->graph, 0);
   if (e != hipSuccess) return e;
-  const int64_t S = c->S;
+  const int64_t S = a0.S;
   g->args.resize((size_t)(2 * S + 1));
   SweepArgs a = a0;
   a.wdev = &c->ds->wcur;
@@ -655,13 +830,13 @@ static hipError_t build_stage_graph(vcsgc_ctx *c, const SweepArgs &a0, double dm
     t.par = (int)(s & 1);
     t.last = 0;
     void *tp[] = {&t.a, &t.w, &t.s, &t.par};
-    e = add((void *)k_trial, gb, tp);
+    e = add(f_trial, gb, tp);
     if (e != hipSuccess) return e;
     StageNodeArgs &u = g->args[(size_t)(2 + 2 * s)];
     u = t;
     u.last = s == S - 1 ? 1 : 0;
     void *up[] = {&u.a, &u.w, &u.s, &u.par, &u.last};
-    e = add((void *)k_commit, gb, up);
+    e = add(f_commit, gb, up);
     if (e != hipSuccess) return e;
   }
   DevState *ds = c->ds;
@@ -687,7 +862,8 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.n1 = c->nc[1];
   a.n2 = c->nc[2];
   a.ncpc = c->ncells / 8;
-  a.S = c->S;
+  a.K = c->local_steps;
+  a.S = stages_per_sweep(c);
   a.beta = 1.0 / (KB * T);
   a.dmu0 = dmu0;
   a.kN = kappa / (double)c->n;
@@ -727,6 +903,12 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.sites = c->sites;
   a.site_lnu = c->site_lnu;
   a.wdev = nullptr;
+  a.u_site = c->u_site;
+  a.u_j = c->u_j;
+  a.u_rho = c->u_rho;
+  a.u_v = c->u_v;
+  void *f_trial = a.K > 1 ? (void *)k_trial_chain : (void *)k_trial;
+  void *f_commit = a.K > 1 ? (void *)k_commit_chain : (void *)k_commit;
   const int gb = grid_for(a.ncpc * TL);
   a.nblk = gb;
   k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
@@ -736,8 +918,8 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   if (!a.da_mode && !a.tlog && !a.slog && a.smp_cap == 0 && !per_kernel_timing && n_sweeps > 0) {
     StageGraph *g = (StageGraph *)c->stage_graph;
     if (!g || !g->exec || g->key[0] != dmu0 || g->key[1] != kappa || g->key[2] != cbar ||
-        g->key[3] != T || g->seed != seed) {
-      hipError_t e = build_stage_graph(c, a, dmu0, kappa, cbar, T, seed);
+        g->key[3] != T || g->seed != seed || g->K != a.K) {
+      hipError_t e = build_stage_graph(c, a, dmu0, kappa, cbar, T, seed, f_trial, f_commit);
       if (e != hipSuccess) {
         free_stage_graph(c);
         return e;
@@ -757,16 +939,21 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   for (int64_t sw = 0; sw < n_sweeps; ++sw) {
     const uint64_t w = c->w + (uint64_t)sw;
     if (!a.da_mode) k_sites<<<grid_for(a.S * a.ncpc), BLOCK, 0, c->stream>>>(a, w);
-    for (int64_t s = 0; s < c->S; ++s, ++q) {
+    for (int64_t s = 0; s < a.S; ++s, ++q) {
       const int par = (int)(q & 1);
       int h = tstart(c, VCSGC_KT_TRIAL);
       if (a.da_mode)
         k_trial_da<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
+      else if (a.K > 1)
+        k_trial_chain<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
       else
         k_trial<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
       tstop(c, h);
       h = tstart(c, VCSGC_KT_COMMIT);
-      k_commit<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par, s == c->S - 1);
+      if (a.K > 1)
+        k_commit_chain<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par, s == a.S - 1);
+      else
+        k_commit<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par, s == a.S - 1);
       tstop(c, h);
     }
     hipError_t e = hipGetLastError();

@@ -22,3 +22,22 @@ def oracle_mod():
     if not os.path.exists(O.LIB_PATH):
         O.build(force=False)
     return O
+
+
+@pytest.fixture(scope="session")
+def enum16(oracle_mod):
+    """16-site bcc cell (2 x 2 x 2 conventional cells, periodic image sums):
+    the FS-P1 energy of all 2^16 species assignments."""
+    import numpy as np
+    from paper_1012_5082_amd import inputs as I
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    x, y, z, box = I.bcc(2, 2, 2)
+    nl = O.neighbors(x, y, z, box, pot.rc)
+    N = 16
+    U = np.zeros(2 ** N)
+    for s in range(2 ** N):
+        sp = np.array([(s >> k) & 1 for k in range(N)], np.uint8)
+        U[s] = O.energy_total(O.energy_atoms(nl, sp, pot))
+    nb = np.array([bin(s).count("1") for s in range(2 ** N)])
+    return dict(x=x, y=y, z=z, box=box, nl=nl, U=U, nb=nb, pot=pot, N=N)

@@ -28,8 +28,8 @@ MUTATIONS = [
     ("pair uses own species for j", "    int sj = species[nj[e]];\n    pair +=",
      "    int sj = species[i];\n    pair +="),
     ("rho commit sign", "if (any) rho[j] = rho[j] + delta;", "if (any) rho[j] = rho[j] - delta;"),
-    ("local chemical term sign", "double xl = beta * (du + a->dmu0 * (double)dn);",
-     "double xl = beta * (du - a->dmu0 * (double)dn);"),
+    ("local chemical term sign", "  double xl = beta * (du + dmu0 * (double)dn);\n  double lnu = log(u);",
+     "  double xl = beta * (du - dmu0 * (double)dn);\n  double lnu = log(u);"),
     ("force density derivative swapped",
      "fp[i] * or_df(p, sj, r) + fp[j] * or_df(p, si, r)",
      "fp[i] * or_df(p, si, r) + fp[j] * or_df(p, sj, r)"),
@@ -43,6 +43,10 @@ MUTATIONS = [
      "  double r = sqrt(r2);\n  if (r < cutoff + 0.5) {"),
     ("site drawn from wrong word", "catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m)]",
      "catoms[cstart[c] + (int64_t)or_index(t[0], (uint64_t)m) / 2]"),
+    ("local chain keeps rejected stages", "          else undo_all(&ulog, species, rho, vx, vy, vz);",
+     "          else ulog.n = 0;"),
+    ("local chain counts only the last step", "              nrec++;\n              dn_tot += dn;",
+     "              nrec++;\n              dn_tot = dn;"),
     ("commit skips flip", "  species[i] = (uint8_t)s1;\n}", "  species[i] = (uint8_t)s;\n}"),
     ("delayed acceptance without the reverse-move factor",
      "double l2 = (-xl + (xr < 0.0 ? xr : 0.0)) - (-x1 < 0.0 ? -x1 : 0.0);",
@@ -55,7 +59,7 @@ MUTATIONS = [
 
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_eam.py",
          "tests/test_oracle_ensemble.py", "tests/test_oracle_md.py",
-         "tests/test_oracle_surrogate.py"]
+         "tests/test_oracle_surrogate.py", "tests/test_oracle_localchain.py"]
 
 
 def main():

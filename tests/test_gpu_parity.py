@@ -244,6 +244,62 @@ def test_stage_graph_replay(torch_cuda, oracle_mod):
     g.close()
 
 
+@pytest.mark.parametrize("k", [2, 5])
+def test_local_chain_parity(torch_cuda, oracle_mod, k):
+    """k trials per active cell per stage: every trial (its dU, decision and
+    margin), every stage and the final state equal the oracle's."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = W.c2(cbar=0.05)
+    args = (d["dmu0"], 5.0, d["cbar"], d["T"])
+    g = gpu_context(d, pot)
+    g.set_local_steps(k)
+    info = g.info()
+    S = info["stages_per_sweep"]
+    ncpc = int(np.prod(info["n_cells"])) // 8
+    n_sw = 3
+    g.enable_log(n_sw * S * ncpc * k, n_sw * S)
+    sg = g.sweep(*args, n_sw, d["seed"])
+    tl_g, sl_g, nt, ns = g.logs()
+    st = oracle_state(O, d, pot)
+    so, tl_o, sl_o = O.sweep(st, *args, n_sw, d["seed"], log_trials=10 ** 8, log_stages=10 ** 8,
+                             overrides=tie_overrides(tl_g, sl_g), local_steps=k)
+    compare_logs(tl_g, sl_g, tl_o, sl_o)
+    for key in ("trials", "local_accepts", "stages", "stage_accepts", "flips", "n_final"):
+        assert sg[key] == so[key], key
+    assert 0 < sg["stage_accepts"] < sg["stages"]
+    assert sg["local_accepts"] > sg["flips"]  # some stages were undone
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    # the same chain without logs (replayed graph), from a fresh context
+    g2 = gpu_context(d, pot)
+    g2.set_tuning("stage", 1)
+    g2.set_local_steps(k)
+    s2 = g2.sweep(*args, n_sw, d["seed"])
+    assert s2["flips"] == so["flips"] and s2["n_final"] == so["n_final"]
+    assert np.array_equal(g2.species.cpu().numpy(), st.species)
+    g.close()
+    g2.close()
+
+
+def test_local_chain_undo_restores_velocities(torch_cuda, oracle_mod):
+    """With velocities, trials of undone stages restore them exactly."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = _md_system(n=16, c=0.1, seed=43)
+    g = gpu_context(d, pot, velocities=True)
+    g.set_local_steps(3)
+    sg = g.sweep(d["dmu0"], 1.0, d["cbar"], d["T"], 2, d["seed"])
+    st = O.SweepState(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
+                      vz=d["vz"])
+    so, _, _ = O.sweep(st, d["dmu0"], 1.0, d["cbar"], d["T"], 2, d["seed"], local_steps=3)
+    assert sg["flips"] == so["flips"] and sg["stage_accepts"] < sg["stages"]
+    for nm in ("vx", "vy", "vz"):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), getattr(st, nm)), nm
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    g.close()
+
+
 def _md_system(n=10, T=700.0, seed=31, c=0.05):
     x, y, z, box = I.bcc(n, n, n)
     x, y, z = I.thermalize(x, y, z, box, 0.05, seed)

@@ -98,21 +98,6 @@ def test_indep_poisson_binomial(oracle_mod):
     assert abs(ns.var() / v - 1.0) < 0.25
 
 
-@pytest.fixture(scope="module")
-def enum16(oracle_mod):
-    O = oracle_mod
-    pot = I.params("FS-P1")
-    x, y, z, box = I.bcc(2, 2, 2)
-    nl = O.neighbors(x, y, z, box, pot.rc)
-    N = 16
-    U = np.zeros(2 ** N)
-    for s in range(2 ** N):
-        sp = np.array([(s >> k) & 1 for k in range(N)], np.uint8)
-        U[s] = O.energy_total(O.energy_atoms(nl, sp, pot))
-    nb = np.array([bin(s).count("1") for s in range(2 ** N)])
-    return dict(x=x, y=y, z=z, box=box, nl=nl, U=U, nb=nb, pot=pot, N=N)
-
-
 E16 = dict(T=600.0, kappa=0.5, cbar=0.25, dmu0=-0.3)
 
 
