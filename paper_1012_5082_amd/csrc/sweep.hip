@@ -161,6 +161,80 @@ __device__ __forceinline__ void descriptor_group(const SweepArgs &a, int64_t i, 
   }
 }
 
+// Forward and flipped descriptors of site i and dU of its transmutation from
+// one gather of the r < 4.41 A list, by the TL lanes of a group.  The shell
+// sums are those of descriptor_group; dU is formed from the entries with
+// r < rc exactly as delta_u_group forms it from the r < rc list (the same
+// entries in the same order, the same (rc - r)^2 and c0 + c1 r from the same
+// r), so both give the same value.  All lanes return the same values.
+__device__ __forceinline__ void desc_du_group(const SweepArgs &a, int64_t i, int lane,
+                                              double fwd[10], double flp[10], double &du) {
+  const int s = a.sp[i], s1 = 1 - s;
+  const double ri = a.rho[i];
+  const int m = a.dcnt[i];
+  int code[2] = {0, 0};  // shell + 1 (0: outside), B flag << 2, r < rc flag << 3
+  double rj[2] = {0.0, 0.0}, rjf[2] = {0.0, 0.0}, tp[2] = {0.0, 0.0}, te[2] = {0.0, 0.0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = lane + h * TL;
+    if (k < m) {
+      const int64_t e = i * KMAX + k;
+      const int32_t j = a.dj[e];
+      const double r = a.dr[e];
+      const int shl = r < 2.68 ? 0 : (r < 3.46 ? 1 : (r < DESC_CUT ? 2 : -1));
+      const int sj = a.sp[j];
+      const double rho = a.rho[j];
+      rj[h] = rho;
+      rjf[h] = rho;
+      int in = 0;
+      if (r < a.p.rc) {
+        const double d = a.p.rc - r;
+        const double dd = d * d;
+        const double g = a.p.c0 + a.p.c1 * r;
+        const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
+        rjf[h] = rho + delta;
+        tp[h] = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
+        te[h] = embed(a.p, sj, rho + delta) - embed(a.p, sj, rho);
+        in = 1;
+      }
+      code[h] = (shl + 1) | (sj << 2) | (in << 3);
+    }
+  }
+  double cnt[3] = {0.0, 0.0, 0.0}, cb[3] = {0.0, 0.0, 0.0};
+  double rs[3] = {0.0, 0.0, 0.0}, rsf[3] = {0.0, 0.0, 0.0};
+  double pair = 0.0, emb = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const int h = k / TL, src = k % TL;
+    const int ck = __shfl(h ? code[1] : code[0], src, TL);
+    const double rk = __shfl(h ? rj[1] : rj[0], src, TL);
+    const double rkf = __shfl(h ? rjf[1] : rjf[0], src, TL);
+    const double vp = __shfl(h ? tp[1] : tp[0], src, TL);
+    const double ve = __shfl(h ? te[1] : te[0], src, TL);
+    const int sk = (ck & 3) - 1;
+    if (sk >= 0) {
+      cnt[sk] += 1.0;
+      cb[sk] += (double)((ck >> 2) & 1);
+      rs[sk] += rk;
+      rsf[sk] += rkf;
+    }
+    if (ck & 8) {
+      pair += vp;
+      emb += ve;
+    }
+  }
+  fwd[0] = (double)s;
+  flp[0] = (double)s1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    fwd[1 + k] = flp[1 + k] = cb[k];
+    fwd[4 + k] = flp[4 + k] = cnt[k];
+    fwd[7 + k] = cnt[k] > 0.0 ? rs[k] / cnt[k] : 0.0;
+    flp[7 + k] = cnt[k] > 0.0 ? rsf[k] / cnt[k] : 0.0;
+  }
+  const double own = embed(a.p, s1, ri) - embed(a.p, s, ri);
+  du = own + pair + emb;
+}
+
 __device__ __forceinline__ int64_t colour_cell(const SweepArgs &a, int colour, int64_t t) {
   const int hx = a.n0 >> 1, hy = a.n1 >> 1;
   const int64_t ia = t % hx, ib = (t / hx) % hy, ic = t / ((int64_t)hx * hy);
@@ -417,63 +491,71 @@ __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_a
 //            s_r = dE_r - dmu0 dn, using u2 = unit(w2).
 // The network runs on the block's 16 descriptors at once (BF16 MFMA).
 // Surrogate modes: 1 network, 2 perfect (dE_f = dU, dE_r = -dU), 3 zero.
-__global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w, int64_t s, int par) {
+__global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w_arg, int64_t s,
+                                                    int par) {
+  const uint64_t w = sweep_of(a, w_arg);
   __shared__ long long sh[BLOCK];
   __shared__ __bf16 zs[16 * MLP_KP];
   __shared__ __bf16 h1[16 * MLP_H], h2[16 * MLP_H];
   __shared__ float yv[16];
   const int lane = threadIdx.x % TL, grp = threadIdx.x / TL;
   const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
-  int64_t cell = -1, i = -1;
-  U4 r = {};
-  if (t < a.ncpc) {
-    const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
-    cell = colour_cell(a, (int)(g.v[0] >> 61), t);
-    const int32_t c0 = a.cstart[cell];
-    const uint32_t m = (uint32_t)(a.cstart[cell + 1] - c0);
-    if (m > 0) {
-      r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
-      i = a.catoms[c0 + draw_index(r.v[0], m)];
-    }
-  }
+  // site and ln u1 from the sweep's table (the plain test's draws)
+  const int64_t i = t < a.ncpc ? a.sites[s * a.ncpc + t] : -1;
+  const double lnu1 = t < a.ncpc ? a.site_lnu[s * a.ncpc + t] : 0.0;
   const bool has = i >= 0;
   const int dn = has ? 1 - 2 * (int)a.sp[i] : 0;
+  // one gather gives the forward and flipped descriptors and the exact dU
+  // (contexts without the descriptor list: dU from the r < rc list)
   double du = 0.0, ef = 0.0, er = 0.0;
-  bool have_du = false;
+  double dfw[10] = {}, dfl[10] = {};
+  if (has) {
+    if (a.dj)
+      desc_du_group(a, i, lane, dfw, dfl, du);
+    else
+      du = delta_u_group(a, i, lane);
+  }
   // ---- surrogate value of the forward move
   if (a.da_mode == 1) {
-    double d[10];
-    if (has) descriptor_group(a, i, lane, false, d);
-    for (int k = lane; k < MLP_KP; k += TL)
-      zs[grp * MLP_KP + k] = (has && k < MLP_IN) ? mlp_input(a.md, k, d[k]) : to_bf16(0.0f);
+    for (int k = lane; k < MLP_KP; k += TL) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < MLP_IN; ++q) v = q == k ? dfw[q] : v;  // static indices
+      zs[grp * MLP_KP + k] = (has && k < MLP_IN) ? mlp_input(a.md, k, v) : to_bf16(0.0f);
+    }
     __syncthreads();
     mlp_block16(a.md, zs, h1, h2, yv);
     ef = (double)(yv[grp] * a.md.out_sd + a.md.out_mu);
-  } else if (a.da_mode == 2 && has) {
-    du = delta_u_group(a, i, lane);
-    have_du = true;
+  } else if (a.da_mode == 2) {
     ef = du;
   }
   // ---- stage 1 (every lane of the group evaluates the same test)
   const double sf = ef + a.dmu0 * (double)dn;
   const double x1 = a.beta * sf;
-  const double lnu1 = has ? log(unit_open(r.v[1])) : 0.0;
   const bool pass1 = has && lnu1 < -x1;
-  // ---- stage 2 inputs for the survivors
-  if (pass1 && !have_du) du = delta_u_group(a, i, lane);
+  // ---- surrogate value of the reverse move for the survivors
   if (a.da_mode == 1) {
     const int any = __syncthreads_or(pass1 ? 1 : 0);
     if (any) {
-      double d[10];
-      if (pass1) descriptor_group(a, i, lane, true, d);
-      for (int k = lane; k < MLP_KP; k += TL)
-        zs[grp * MLP_KP + k] = (pass1 && k < MLP_IN) ? mlp_input(a.md, k, d[k]) : to_bf16(0.0f);
+      for (int k = lane; k < MLP_KP; k += TL) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < MLP_IN; ++q) v = q == k ? dfl[q] : v;
+        zs[grp * MLP_KP + k] = (pass1 && k < MLP_IN) ? mlp_input(a.md, k, v) : to_bf16(0.0f);
+      }
       __syncthreads();
       mlp_block16(a.md, zs, h1, h2, yv);
       er = (double)(yv[grp] * a.md.out_sd + a.md.out_mu);
     }
   } else if (a.da_mode == 2) {
     er = -du;
+  }
+  int64_t cell = -1;
+  U4 r = {};
+  if (has && (pass1 || a.tlog || a.dalog)) {
+    const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+    cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+    r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
   }
   long long valid = 0, acc = 0, dn_acc = 0, tie = 0, p1 = 0;
   if (lane == 0 && t < a.ncpc) {
@@ -938,7 +1020,7 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   int64_t q = 0;
   for (int64_t sw = 0; sw < n_sweeps; ++sw) {
     const uint64_t w = c->w + (uint64_t)sw;
-    if (!a.da_mode) k_sites<<<grid_for(a.S * a.ncpc), BLOCK, 0, c->stream>>>(a, w);
+    k_sites<<<grid_for(a.S * a.ncpc), BLOCK, 0, c->stream>>>(a, w);
     for (int64_t s = 0; s < a.S; ++s, ++q) {
       const int par = (int)(q & 1);
       int h = tstart(c, VCSGC_KT_TRIAL);

@@ -105,12 +105,20 @@ def test_descriptors_match_oracle(torch_cuda, oracle_mod):
     g.close()
 
 
-def test_da_perfect_surrogate_equals_plain(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("desc", [False, True])
+def test_da_perfect_surrogate_equals_plain(torch_cuda, oracle_mod, desc):
+    """With the exact dU as surrogate the chain is the plain one, bit for bit;
+    with the descriptor list present dU comes from that list's r < rc
+    entries instead of the r < rc list, and must be the same number."""
     pot = I.params("FS-P1")
     d = W.c2(cbar=0.05)
     from paper_1012_5082_amd.binding import VCSGC
     a = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
-    b = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
+    b = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, descriptor=desc,
+              r_dep=8.01 if desc else 0.0)
+    if desc:
+        a.close()
+        a = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, r_dep=8.01)
     b.set_surrogate("perfect")
     args = (d["dmu0"], 5.0, 0.05, d["T"], 5, d["seed"])
     sa, sb = a.sweep(*args), b.sweep(*args)
