@@ -145,6 +145,30 @@ __device__ __forceinline__ int64_t xcd_block() {
 
 constexpr int SCAN_CHUNK = 1024;  // values per block of the cell-count scan
 
+// Sums of N integer values over the block (exact, so the order is free):
+// butterfly inside each wave, then the per-wave totals through LDS.  sh
+// needs N * (BLOCK / 64) entries; contains two barriers, so every thread of
+// the block must call it.
+template <int N>
+__device__ __forceinline__ void block_sums(long long (&v)[N], long long *sh) {
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[wv * N + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    long long t = 0;
+    for (int q = 0; q < BLOCK / 64; ++q) t += sh[q * N + k];
+    v[k] = t;
+  }
+  __syncthreads();
+}
+
 inline int grid_for(int64_t n, int block = BLOCK) {
   int64_t g = (n + block - 1) / block;
   return (int)(g < 1 ? 1 : g);

@@ -66,19 +66,6 @@ struct PersistArgs {
   unsigned int spin_limit;
 };
 
-__device__ __forceinline__ long long wg_sum(long long v, long long *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int h = BLOCK / 2; h > 0; h >>= 1) {
-    if (t < h) sh[t] += sh[t + h];
-    __syncthreads();
-  }
-  const long long r = sh[0];
-  __syncthreads();
-  return r;
-}
-
 // Barrier of the G workgroups of one replica on a monotonically increasing
 // counter; returns false if the wait timed out.
 __device__ __forceinline__ bool rep_barrier(RepState *st, int G, unsigned int target,
@@ -221,14 +208,14 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
         }
         if (lane == 0) rec[t] = site;
       }
-      const long long bv = wg_sum(valid, sh), ba = wg_sum(acc, sh);
-      const long long bd = wg_sum(dn_acc, sh), bt = wg_sum(tie, sh);
+      long long v4[4] = {valid, acc, dn_acc, tie};
+      block_sums<4>(v4, sh);
       if (threadIdx.x == 0) {
         long long *P = a.part + NPART * (int64_t)g;
-        P[0] = bv;
-        P[1] = ba;
-        P[2] = bd;
-        P[3] = bt;
+        P[0] = v4[0];
+        P[1] = v4[1];
+        P[2] = v4[2];
+        P[3] = v4[3];
       }
       nbar += 1;
       if (!rep_barrier(st, r.G, nbar * (unsigned)r.G, a.spin_limit, &bflag)) return;
@@ -241,7 +228,9 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
         pd += P[2];
         pt += P[3];
       }
-      const long long nrec = wg_sum(pa, sh), dn_tot = wg_sum(pd, sh);
+      long long r4[4] = {pa, pd, pv, pt};
+      block_sums<4>(r4, sh);
+      const long long nrec = r4[0], dn_tot = r4[1];
       const long long nb = st->n_b[par];
       int gacc = -1;
       double xg = 0.0, mg = 0.0;
@@ -282,7 +271,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
           }
         }
       }
-      const long long sv = wg_sum(pv, sh), stt = wg_sum(pt, sh);
+      const long long sv = r4[2], stt = r4[3];
       if (q == 0 && threadIdx.x == 0) {
         const long long nb_new = nb + (gacc == 1 ? dn_tot : 0);
         st->n_b[par ^ 1] = nb_new;

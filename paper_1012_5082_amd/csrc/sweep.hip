@@ -243,30 +243,6 @@ __device__ __forceinline__ int64_t colour_cell(const SweepArgs &a, int colour, i
   return cx + (int64_t)a.n0 * (cy + (int64_t)a.n1 * cz);
 }
 
-// Sums of N integer values over the block (exact, so the order is free):
-// butterfly inside each wave, then the per-wave totals through LDS.  sh
-// needs N * (BLOCK / 64) entries; contains two barriers, so every thread of
-// the block must call it.
-template <int N>
-__device__ __forceinline__ void block_sums(long long (&v)[N], long long *sh) {
-#pragma unroll
-  for (int k = 0; k < N; ++k)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int k = 0; k < N; ++k) sh[wv * N + k] = v[k];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    long long t = 0;
-    for (int q = 0; q < BLOCK / 64; ++q) t += sh[q * N + k];
-    v[k] = t;
-  }
-  __syncthreads();
-}
-
 __global__ void __launch_bounds__(BLOCK) k_init(DevState *ds) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ds->n_b[0] = ds->n_b_cur;
