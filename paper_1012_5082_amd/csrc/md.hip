@@ -12,6 +12,15 @@ struct Box {
 constexpr int IB = 16;  // neighbour indices loaded per round
 constexpr int UNR = 4;  // neighbour gathers in flight per lane
 
+// Minimum image without branches: both shifted values are formed and one is
+// selected (the same number min_image returns), so the pair bodies below
+// are straight-line code the compiler can interleave.
+__device__ __forceinline__ double min_image_sel(double d, double L) {
+  const double h = 0.5 * L;
+  const double lo = d + L, hi = d - L;
+  return d > h ? hi : (d < -h ? lo : d);
+}
+
 // (x, y, z, species) of every atom, packed for the density pass
 __global__ void k_pack(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                        const double *__restrict__ z, const uint8_t *__restrict__ sp,
@@ -47,14 +56,14 @@ __device__ __forceinline__ double density_row(int64_t n, int64_t i, int m, const
       for (int u = 0; u < UNR; ++u) q[u] = ps4[jb[g + u]];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const double dx = min_image(q[u].x - qi.x, b.L0);
-        const double dy = min_image(q[u].y - qi.y, b.L1);
-        const double dz = min_image(q[u].z - qi.z, b.L2);
+        const double dx = min_image_sel(q[u].x - qi.x, b.L0);
+        const double dy = min_image_sel(q[u].y - qi.y, b.L1);
+        const double dz = min_image_sel(q[u].z - qi.z, b.L2);
         const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-        if (k0 + g + u < m && r < p.rc) {
-          const double d = p.rc - r;
-          s += (q[u].w != 0.0 ? t1 : t0) * (d * d);
-        }
+        const double d = p.rc - r;
+        const double term = (q[u].w != 0.0 ? t1 : t0) * (d * d);
+        // a skipped pair adds +0.0: s is never -0.0, so s + 0.0 == s
+        s += (k0 + g + u < m && r < p.rc) ? term : 0.0;
       }
     }
   }
@@ -104,22 +113,22 @@ __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, c
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const double dx = min_image(q[u].x - qi.x, b.L0);
-        const double dy = min_image(q[u].y - qi.y, b.L1);
-        const double dz = min_image(q[u].z - qi.z, b.L2);
+        const double dx = min_image_sel(q[u].x - qi.x, b.L0);
+        const double dy = min_image_sel(q[u].y - qi.y, b.L1);
+        const double dz = min_image_sel(q[u].z - qi.z, b.L2);
         const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-        if (k0 + g + u < m && r < p.rc) {
-          const double d = p.rc - r;
-          const double eps = sj[u] ? e1 : e0, tj = sj[u] ? t1 : t0;
-          const double dphi = eps * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
-          const double dfj = -2.0 * tj * d;
-          const double dfi = -2.0 * ti * d;
-          const double s = dphi + fpi * dfj + q[u].w * dfi;
-          const double coef = s / r;
-          ax += coef * dx;
-          ay += coef * dy;
-          az += coef * dz;
-        }
+        const double d = p.rc - r;
+        const double eps = sj[u] ? e1 : e0, tj = sj[u] ? t1 : t0;
+        const double dphi = eps * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
+        const double dfj = -2.0 * tj * d;
+        const double dfi = -2.0 * ti * d;
+        const double s = dphi + fpi * dfj + q[u].w * dfi;
+        const double coef = s / r;
+        // a skipped pair adds +0.0 (the sums are never -0.0, so unchanged)
+        const bool in = k0 + g + u < m && r < p.rc;
+        ax += in ? coef * dx : 0.0;
+        ay += in ? coef * dy : 0.0;
+        az += in ? coef * dz : 0.0;
       }
     }
   }
