@@ -29,7 +29,8 @@ void free_all(vcsgc_ctx *c) {
                   c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
                   c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos,
                   c->md_tmp,     c->md_tcnt,    c->sites,      c->site_lnu,
-                  c->u_site,     c->u_j,        c->u_rho,      c->u_v};
+                  c->u_site,     c->u_j,        c->u_rho,      c->u_v,
+                  c->stage_lnug};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -442,6 +443,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->md_tcnt, n));
     A(dalloc(&c->sites, reps[0].S * reps[0].ncpc));
     A(dalloc(&c->site_lnu, reps[0].S * reps[0].ncpc));
+    A(dalloc(&c->stage_lnug, reps[0].S));
   }
   A(dalloc(&c->cell_count, coff));
   A(dalloc(&c->cell_start, coff + R));
@@ -682,16 +684,17 @@ vcsgc_status vcsgc_set_local_steps(vcsgc_ctx *c, int32_t k) {
   if (k == c->local_steps) return VCSGC_OK;
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   vc::free_stage_graph(c);  // its nodes hold the old buffers
-  void *old[] = {c->sites, c->site_lnu, c->u_site, c->u_j, c->u_rho, c->u_v};
+  void *old[] = {c->sites, c->site_lnu, c->stage_lnug, c->u_site, c->u_j, c->u_rho, c->u_v};
   for (void *p : old)
     if (p) (void)hipFree(p);
   c->sites = c->u_site = c->u_j = nullptr;
-  c->site_lnu = c->u_rho = c->u_v = nullptr;
+  c->site_lnu = c->stage_lnug = c->u_rho = c->u_v = nullptr;
   c->local_steps = k;
   const int64_t ncpc = c->ncells / 8, K = k;
   const int64_t tab = vc::stages_per_sweep(c) * ncpc * K;
   VC_CHECK(c, dalloc(&c->sites, tab), "allocation");
   VC_CHECK(c, dalloc(&c->site_lnu, tab), "allocation");
+  VC_CHECK(c, dalloc(&c->stage_lnug, vc::stages_per_sweep(c)), "allocation");
   if (K > 1) {
     VC_CHECK(c, dalloc(&c->u_site, ncpc * K), "allocation");
     VC_CHECK(c, dalloc(&c->u_j, ncpc * K * vc::KMAX), "allocation");

@@ -42,11 +42,31 @@ __device__ __forceinline__ int cell_of(const Grid &g, double a, double b, double
   return cx + g.n0 * (cy + g.n1 * cz);
 }
 
+// atomicAdd(&counter[key], 1) for every active lane, with one atomic per
+// distinct key in the wave (neighbouring atoms mostly share a cell); returns
+// the lane's old value plus its rank among the lanes with the same key
+__device__ __forceinline__ int32_t wave_add_one(int32_t *counter, int key) {
+  const int lane = __lane_id();
+  unsigned long long todo = __ballot(1);
+  int32_t slot = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lkey = __shfl(key, leader);
+    const unsigned long long same = __ballot(key == lkey) & todo;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(&counter[lkey], (int32_t)__popcll(same));
+    base = __shfl(base, leader);
+    if (same & (1ull << lane)) slot = base + (int32_t)__popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  return slot;
+}
+
 __global__ void k_cell_count(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ z, Grid g, int32_t *count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  atomicAdd(&count[cell_of(g, x[i], y[i], z[i])], 1);
+  (void)wave_add_one(count, cell_of(g, x[i], y[i], z[i]));
 }
 
 // exclusive scan of count[0..m) into start[0..m] (and a copy in fill):
@@ -123,7 +143,7 @@ __global__ void k_cell_fill(int64_t n, const double *__restrict__ x, const doubl
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int c = cell_of(g, x[i], y[i], z[i]);
-  atoms[atomicAdd(&fill[c], 1)] = (int32_t)(aoff + i);
+  atoms[wave_add_one(fill, c)] = (int32_t)(aoff + i);
 }
 
 // canonical order inside a cell: ascending site index.  One wave per cell:
@@ -255,20 +275,17 @@ __device__ __forceinline__ double pair_r(const double *__restrict__ x,
 // with two bins along an axis) surrounding search bins.  Hits are appended to
 // an LDS row through an LDS counter (arbitrary order), then every hit is
 // stored at its rank among the row's neighbour indices, so rows come out
-// sorted and independent of the append order.
-// MC rows are row-major ([i * KMAX + k]) for the group-per-trial sweep;
-// MD rows are column-major ([k * n + i]) for the thread-per-atom kernels.
+// sorted and independent of the append order.  Rows are row-major
+// ([i * KMAX + k]) for the group-per-trial sweep kernels.
 constexpr int BG = 32;
 
-// MODE 0: MD rows (column-major indices), 1: MC rows (row-major, (rc-r)^2 and
-// c0 + c1 r), 2: descriptor rows (row-major, r)
+// MODE 1: MC rows ((rc - r)^2 and c0 + c1 r), 2: descriptor rows (r)
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK)
     k_build(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
             const double *__restrict__ z, Grid g, const int32_t *__restrict__ bcount,
             const int32_t *__restrict__ batoms, int bmax, double cutoff, PotD p, int32_t *nj,
-            double *ndd, double *ng, uint8_t *cnt, double *xr, double *yr, double *zr,
-            DevState *ds, int64_t aoff, int64_t ntot) {
+            double *ndd, double *ng, uint8_t *cnt, DevState *ds, int64_t aoff) {
   __shared__ int32_t rowbuf[BLOCK / BG][KMAX];
   __shared__ int rowcount[BLOCK / BG];
   const int lane = threadIdx.x % BG, grp = threadIdx.x / BG;
@@ -314,25 +331,16 @@ __global__ void __launch_bounds__(BLOCK)
       const int32_t j = rowbuf[grp][a];
       int rank = 0;
       for (int b = 0; b < count; ++b) rank += rowbuf[grp][b] < j ? 1 : 0;
+      const int64_t e = ig * KMAX + rank;
+      nj[e] = (int32_t)(aoff + j);
+      const double r = pair_r(x, y, z, g, xi, yi, zi, j);
       if (MODE == 1) {
-        const int64_t e = ig * KMAX + rank;
-        nj[e] = (int32_t)(aoff + j);
-        const double r = pair_r(x, y, z, g, xi, yi, zi, j);
         const double d = p.rc - r;
         ndd[e] = d * d;
         ng[e] = p.c0 + p.c1 * r;
-      } else if (MODE == 2) {
-        const int64_t e = ig * KMAX + rank;
-        nj[e] = (int32_t)(aoff + j);
-        ndd[e] = pair_r(x, y, z, g, xi, yi, zi, j);
       } else {
-        nj[(int64_t)rank * ntot + ig] = (int32_t)(aoff + j);
+        ndd[e] = r;
       }
-    }
-    if (MODE == 0 && lane == 0) {
-      xr[ig] = xi;
-      yr[ig] = yi;
-      zr[ig] = zi;
     }
   }
 }
@@ -375,7 +383,7 @@ hipError_t launch_build_mc_list(vcsgc_ctx *c, const RepHost &r) {
   k_build<1><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
       r.n, c->x + r.aoff, c->y + r.aoff, c->z + r.aoff, g, c->bin_count + r.boff,
       c->bin_atoms + r.boff * c->bmax, c->bmax, c->pot.rc, c->pot, c->mc_j, c->mc_dd, c->mc_g,
-      c->mc_cnt, nullptr, nullptr, nullptr, c->ds, r.aoff, c->n);
+      c->mc_cnt, c->ds, r.aoff);
   tstop(c, h);
   return hipGetLastError();
 }
@@ -386,7 +394,7 @@ hipError_t launch_build_desc_list(vcsgc_ctx *c, const RepHost &r) {
   k_build<2><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
       r.n, c->x + r.aoff, c->y + r.aoff, c->z + r.aoff, g, c->bin_count + r.boff,
       c->bin_atoms + r.boff * c->bmax, c->bmax, DESC_CUT, c->pot, c->d_j, c->d_r, nullptr,
-      c->d_cnt, nullptr, nullptr, nullptr, c->ds, r.aoff, c->n);
+      c->d_cnt, c->ds, r.aoff);
   return hipGetLastError();
 }
 

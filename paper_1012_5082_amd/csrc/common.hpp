@@ -225,6 +225,7 @@ struct vcsgc_ctx {
   int32_t *md_tmp = nullptr, *md_tcnt = nullptr;  // unsorted MD rows (row-major) and lengths
   int32_t *sites = nullptr;  // trial sites of one sweep, S x (cells / 8) (single-system)
   double *site_lnu = nullptr;  // ln u of those trials
+  double *stage_lnug = nullptr;  // ln u_g of the sweep's stages
   int local_steps = 1;          // trials per active cell per stage (local chain length)
   int32_t *u_site = nullptr, *u_j = nullptr;  // undo log of a stage of local chains
   double *u_rho = nullptr, *u_v = nullptr;

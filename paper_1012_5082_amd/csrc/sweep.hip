@@ -54,6 +54,7 @@ struct SweepArgs {
   // ln u of their local tests
   int32_t *sites;
   double *site_lnu;
+  double *stage_lnug;  // ln u_g of every stage's global test
   // graph replay: the sweep counter is read from here instead of the
   // kernel argument (advanced by k_next_sweep at the end of each sweep)
   const unsigned long long *wdev;
@@ -273,6 +274,7 @@ __global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
   if (q >= a.S * a.ncpc) return;
   const int64_t s = q / a.ncpc, t = q - s * a.ncpc;
   const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+  if (t == 0) a.stage_lnug[s] = log(unit_open(g.v[1]));
   const int64_t cell = colour_cell(a, (int)(g.v[0] >> 61), t);
   const int32_t st = a.cstart[cell];
   const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
@@ -605,6 +607,7 @@ struct StageDecision {
 
 __device__ __forceinline__ StageDecision stage_decision(const SweepArgs &a, uint64_t w, int64_t s,
                                                         int par, long long *sh) {
+  const double lnug = a.stage_lnug[s];  // issued before the reduction
   long long pa = 0, pd = 0;
   for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
     pa += a.part[NPART * b + 1];
@@ -620,11 +623,9 @@ __device__ __forceinline__ StageDecision stage_decision(const SweepArgs &a, uint
   d.xg = 0.0;
   d.mg = 0.0;
   if (d.nrec > 0) {
-    const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
     const double tt = (double)d.nb - a.ncbar;
     const double dnd = (double)d.dn_tot;
     d.xg = a.beta * a.kN * dnd * (dnd + 2.0 * tt);
-    const double lnug = log(unit_open(g.v[1]));
     d.mg = lnug + d.xg;
     d.gacc = lnug < -d.xg ? 1 : 0;
   }
@@ -960,6 +961,7 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.smp_stride = c->smp_stride < 1 ? 1 : c->smp_stride;
   a.sites = c->sites;
   a.site_lnu = c->site_lnu;
+  a.stage_lnug = c->stage_lnug;
   a.wdev = nullptr;
   a.u_site = c->u_site;
   a.u_j = c->u_j;
