@@ -47,7 +47,11 @@ def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials):
     kick      : v, F, species read (49), v written (24)
     trial     : per trial, own species/rho/row length (10) + per r < rc pair the
                 index, (rc-r)^2, c0+c1 r (20) and the neighbour's species and rho
-                (9) + cell start/atom (8+4) + record (4)"""
+                (9) + cell start/atom (8+4) + record (4)
+    stage     : the trial bytes above with the site and ln u read from the site
+                table (4+8 in place of the cell start/atom), plus per active cell
+                the next sweep's draw: cell start/atom read (8+4), site and ln u
+                written (4+8); `trials` is then (trials, active cells) per launch"""
     if kind == "forces":
         return 58 * n + 4 * pairs_md
     if kind == "density":
@@ -59,10 +63,14 @@ def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials):
     if kind == "trial":
         k = pairs_mc / n
         return trials * (26 + 29 * k)
+    if kind == "stage":
+        k = pairs_mc / n
+        nt, ncells = trials
+        return nt * (26 + 29 * k) + ncells * 24
     return None
 
 
-HAS_BYTES = ("forces", "density", "kick_drift", "kick", "trial")
+HAS_BYTES = ("forces", "density", "kick_drift", "kick", "trial", "stage")
 SAMPLE = 8  # sweep-kernel launches per timed launch
 
 # kernel class -> (kernel symbol, source file, profile summary holding its
@@ -72,6 +80,7 @@ TRAFFIC = {
     "density": ("k_density_md", "paper_1012_5082_amd/csrc/md.hip",
                 "profiles/k_density_md_c3_traffic.md"),
     "trial": ("k_trial", "paper_1012_5082_amd/csrc/sweep.hip", "profiles/k_trial_c3_traffic.md"),
+    "stage": ("k_stage", "paper_1012_5082_amd/csrc/sweep.hip", "profiles/k_stage_c3_traffic.md"),
 }
 
 
@@ -355,8 +364,8 @@ def main():
     # every class sampled one launch in SAMPLE (an event pair per launch costs
     # host time next to the ~10 us sweep kernels); the per-cycle time of a
     # class is its mean timed launch times all its launches
-    g.kernel_timing(["trial", "commit", "density", "forces", "kick_drift", "kick", "build",
-                     "persist"], every=SAMPLE)
+    g.kernel_timing(["trial", "commit", "stage", "density", "forces", "kick_drift", "kick",
+                     "build", "persist"], every=SAMPLE)
     g.sweep(*sweep_args, 1, d["seed"])
     g.md(dt, md_steps)
     kt0 = g.kernel_times()
@@ -368,7 +377,7 @@ def main():
 
     # timed region: K hybrid cycles; the dominant kernel class timed per launch
     # (one launch in SAMPLE for the per-stage sweep kernels)
-    g.kernel_timing([dominant], every=SAMPLE if dominant in ("trial", "commit") else 1)
+    g.kernel_timing([dominant], every=SAMPLE if dominant in ("trial", "commit", "stage") else 1)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     trials = 0
@@ -397,6 +406,10 @@ def main():
     pairs_md = info2["md_pairs"]
     pairs_mc = info["mc_pairs"]
     per_launch_trials = trials / max(1, all_launches) if dominant == "trial" else 0
+    if dominant == "stage":
+        nc = info["n_cells"]
+        ncpc = nc[0] * nc[1] * nc[2] // 8
+        per_launch_trials = (trials / max(1, all_launches), stages * ncpc / max(1, all_launches))
     abytes = algorithmic_bytes(dominant, n, pairs_md, pairs_mc, per_launch_trials)
     roof = None
     if abytes:

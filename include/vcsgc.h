@@ -235,7 +235,9 @@ vcsgc_status vcsgc_get_info(vcsgc_ctx *ctx, vcsgc_info *out);
 #define VCSGC_KT_BUILD 6      /* cell binning + neighbour list */
 #define VCSGC_KT_ENERGY 7     /* per-atom energies */
 #define VCSGC_KT_PERSIST 8    /* persistent sweep (one launch per call) */
-#define VCSGC_KT_CLASSES 9
+#define VCSGC_KT_STAGE 9      /* sweep: fused stage kernel (global factor of one stage,
+                                 then, unless it accepts, the trials of the next) */
+#define VCSGC_KT_CLASSES 10
 
 typedef struct {
   double total_ms[VCSGC_KT_CLASSES]; /* summed event-to-event durations */

@@ -75,13 +75,13 @@ class Info(C.Structure):
 
 
 KT_NAMES = ["trial", "commit", "density", "forces", "kick_drift", "kick", "build", "energy",
-            "persist"]
+            "persist", "stage"]
 STRATEGIES = {"graph": 0, "persistent": 1, "stage": 2}
 
 
 class KTimes(C.Structure):
-    _fields_ = [("total_ms", C.c_double * 9), ("count", C.c_int64 * 9),
-                ("launches", C.c_int64 * 9)]
+    _fields_ = [("total_ms", C.c_double * len(KT_NAMES)), ("count", C.c_int64 * len(KT_NAMES)),
+                ("launches", C.c_int64 * len(KT_NAMES))]
 
 
 _lib = None

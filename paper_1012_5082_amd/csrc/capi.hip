@@ -30,14 +30,17 @@ void free_all(vcsgc_ctx *c) {
                   c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos,
                   c->md_tmp,     c->md_tcnt,    c->sites,      c->site_lnu,
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
-                  c->stage_lnug};
+                  c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnug,   c->m_rec,
+                  c->m_part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
+  if (c->h_pipe) (void)hipHostFree(c->h_pipe);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
   vc::free_stage_graph(c);
+  vc::free_pipe_graph(c);
 }
 
 vcsgc_status fail(vcsgc_ctx *c, vcsgc_status st, const std::string &msg) {
@@ -444,6 +447,15 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->sites, reps[0].S * reps[0].ncpc));
     A(dalloc(&c->site_lnu, reps[0].S * reps[0].ncpc));
     A(dalloc(&c->stage_lnug, reps[0].S));
+    // fused stage pipeline: two sweeps of site tables, two stages of records
+    // and trial-block sums
+    const int64_t S1 = reps[0].S, nc1 = reps[0].ncpc;
+    A(dalloc(&c->m_sites, 2 * S1 * nc1));
+    A(dalloc(&c->m_lnu, 2 * S1 * nc1));
+    A(dalloc(&c->m_lnug, 2 * S1));
+    A(dalloc(&c->m_rec, 2 * nc1));
+    A(dalloc(&c->m_part, 2 * vc::NPART * (int64_t)vc::grid_for(nc1 * 16)));
+    A(hipHostMalloc((void **)&c->h_pipe, sizeof(vc::StageProgress), hipHostMallocDefault));
   }
   A(dalloc(&c->cell_count, coff));
   A(dalloc(&c->cell_start, coff + R));

@@ -35,6 +35,23 @@ struct PotD {
   double mass[2];  // u
 };
 
+// Progress of the fused stage pipeline of one call: stage s of sweep w and
+// what its next kernel does with it.  Kept twice, indexed by the parity of
+// the launch: a kernel reads one copy and its block 0 writes the other.
+enum : int { SM_TRIAL = 0, SM_DECIDE = 1, SM_DONE = 2 };
+struct StageMachine {
+  unsigned long long w;  // sweep of the stage
+  long long s;           // stage within the sweep
+  long long nb;          // n_B before the global test of stage (w, s)
+  int phase;             // SM_TRIAL: its trials are next; SM_DECIDE: its global test is next
+  int pad;
+};
+struct StageProgress {
+  StageMachine sm[2];
+  unsigned long long w_end;    // first sweep past the end of the call
+  unsigned long long used;     // pipeline kernels that did work in the call
+};
+
 // Device-resident counters and chain scalars of one context.
 struct DevState {
   unsigned long long trials, local_acc, stages, stage_acc, flips, near_ties;
@@ -55,6 +72,7 @@ struct DevState {
   unsigned long long smp_n, dalog_n;      // sample-log and surrogate-log records written
   unsigned long long md_rebuilds;         // MD list rebuilds taken on the device
   unsigned long long wcur;                // sweep counter of a graph-replayed sweep
+  StageProgress pipe;                     // fused stage pipeline of the current call
 };
 
 // ---------------------------------------------------------------------------
@@ -259,6 +277,16 @@ struct vcsgc_ctx {
   double *rho_f = nullptr, *fp = nullptr;        // fresh density and F' (energy, MD)
   double *eatom = nullptr, *red = nullptr;
   int32_t *rec = nullptr;  // per active cell: locally accepted site or -1
+  // fused stage pipeline (single system, one trial per cell and stage): site
+  // tables of two sweeps [w & 1][s][t], ln u of their local tests and of the
+  // stages' global tests, and records and trial-block sums of two stages
+  int32_t *m_sites = nullptr;
+  double *m_lnu = nullptr, *m_lnug = nullptr;
+  int32_t *m_rec = nullptr;
+  long long *m_part = nullptr;
+  vc::StageProgress *h_pipe = nullptr;  // pinned copy of the pipeline's progress
+  double m_acc_rate = 0.05;             // accepted stages per stage, last call
+  void *pipe_graph = nullptr;           // graphs of pipeline kernels
   long long *part = nullptr;  // per trial block: trials, local accepts, sum dn, near ties
   int64_t npart = 0;
   vc::DevState *ds = nullptr;
@@ -334,6 +362,7 @@ hipError_t launch_descriptors(vcsgc_ctx *c, const int32_t *sites, int64_t n, int
 hipError_t launch_density_mc(vcsgc_ctx *c);
 hipError_t launch_mc_from_md(vcsgc_ctx *c);
 void free_stage_graph(vcsgc_ctx *c);
+void free_pipe_graph(vcsgc_ctx *c);
 hipError_t launch_energy(vcsgc_ctx *c);  // fresh rho (MD list) + per-atom energies
 hipError_t launch_forces(vcsgc_ctx *c);  // fresh rho, F', forces (MD list)
 hipError_t launch_validate(vcsgc_ctx *c, const RepHost &r);

@@ -113,22 +113,24 @@ __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, c
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const double dx = min_image_sel(q[u].x - qi.x, b.L0);
-        const double dy = min_image_sel(q[u].y - qi.y, b.L1);
-        const double dz = min_image_sel(q[u].z - qi.z, b.L2);
+        const double dx = min_image(q[u].x - qi.x, b.L0);
+        const double dy = min_image(q[u].y - qi.y, b.L1);
+        const double dz = min_image(q[u].z - qi.z, b.L2);
         const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-        const double d = p.rc - r;
-        const double eps = sj[u] ? e1 : e0, tj = sj[u] ? t1 : t0;
-        const double dphi = eps * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
-        const double dfj = -2.0 * tj * d;
-        const double dfi = -2.0 * ti * d;
-        const double s = dphi + fpi * dfj + q[u].w * dfi;
-        const double coef = s / r;
-        // a skipped pair adds +0.0 (the sums are never -0.0, so unchanged)
-        const bool in = k0 + g + u < m && r < p.rc;
-        ax += in ? coef * dx : 0.0;
-        ay += in ? coef * dy : 0.0;
-        az += in ? coef * dz : 0.0;
+        // branch kept here: the select form evaluates the FP64 division for
+        // every list entry and measured slower than this one
+        if (k0 + g + u < m && r < p.rc) {
+          const double d = p.rc - r;
+          const double eps = sj[u] ? e1 : e0, tj = sj[u] ? t1 : t0;
+          const double dphi = eps * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
+          const double dfj = -2.0 * tj * d;
+          const double dfi = -2.0 * ti * d;
+          const double s = dphi + fpi * dfj + q[u].w * dfi;
+          const double coef = s / r;
+          ax += coef * dx;
+          ay += coef * dy;
+          az += coef * dz;
+        }
       }
     }
   }

@@ -12,6 +12,8 @@
 // Cells of one colour are at least one cell edge (>= 2 rc) apart, so their
 // energy changes are independent and every rho_j has at most one writer per
 // stage.
+#include <cmath>
+
 #include "mlp_device.hpp"
 
 namespace vc {
@@ -74,26 +76,62 @@ __device__ __forceinline__ uint64_t sweep_of(const SweepArgs &a, uint64_t w) {
 constexpr int TL = 16;
 static_assert(KMAX <= 2 * TL, "a trial group covers at most 2*TL neighbours");
 
+// What one lane of a trial group reads for the trial at site i: the site's
+// species, density and row length, and its neighbour entries k = lane and
+// k = lane + TL with their species and densities.  Entry k = lane always lies
+// inside the KMAX-entry row, so the row reads are issued together with those
+// of the site (unused entries beyond the row length are never dereferenced).
+struct TrialIn {
+  int s, m;
+  double ri;
+  int32_t j[2];
+  double dd[2], g[2], rj[2];
+  int sj[2];
+};
+
+__device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int lane, TrialIn &v) {
+  v.s = a.sp[i];
+  v.ri = a.rho[i];
+  v.m = a.cnt[i];
+  const int64_t e0 = i * KMAX + lane;
+  v.j[0] = a.nj[e0];
+  v.dd[0] = a.ndd[e0];
+  v.g[0] = a.ng[e0];
+  v.j[1] = 0;
+  v.dd[1] = v.g[1] = 0.0;
+  v.sj[0] = v.sj[1] = 0;
+  v.rj[0] = v.rj[1] = 0.0;
+  if (lane + TL < v.m) {
+    const int64_t e1 = e0 + TL;
+    v.j[1] = a.nj[e1];
+    v.dd[1] = a.ndd[e1];
+    v.g[1] = a.ng[e1];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (lane + h * TL < v.m) {
+      v.sj[h] = a.sp[v.j[h]];
+      v.rj[h] = a.rho[v.j[h]];
+    }
+}
+
 // dU of s_i -> 1 - s_i, evaluated by the TL lanes of one group:
 //   (F_{s'}(rho_i) - F_s(rho_i)) + sum_j [(eps_{s's_j} dd) g - (eps_{s s_j} dd) g]
 //   + sum_j [F_{s_j}(rho_j + (t_{s'} dd - t_s dd)) - F_{s_j}(rho_j)]
 // Each lane computes the terms of its entries; the two sums are then formed
 // in ascending entry order from the shuffled terms, so the rounding is that
 // of the sequential sums.  Every lane of the group returns the same value.
-__device__ __forceinline__ double delta_u_group(const SweepArgs &a, int64_t i, int lane) {
-  const int s = a.sp[i], s1 = 1 - s;
-  const double ri = a.rho[i];
-  const int m = a.cnt[i];
+__device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialIn &v, int lane) {
+  const int s = v.s, s1 = 1 - s;
+  const int m = v.m;
   double tp[2] = {0.0, 0.0}, te[2] = {0.0, 0.0};
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int k = lane + h * TL;
     if (k < m) {
-      const int64_t e = i * KMAX + k;
-      const int32_t j = a.nj[e];
-      const int sj = a.sp[j];
-      const double dd = a.ndd[e], g = a.ng[e];
-      const double rj = a.rho[j];
+      const int sj = v.sj[h];
+      const double dd = v.dd[h], g = v.g[h];
+      const double rj = v.rj[h];
       tp[h] = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
       const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
       te[h] = embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
@@ -108,8 +146,14 @@ __device__ __forceinline__ double delta_u_group(const SweepArgs &a, int64_t i, i
     pair += vp;
     emb += ve;
   }
-  const double own = embed(a.p, s1, ri) - embed(a.p, s, ri);
+  const double own = embed(a.p, s1, v.ri) - embed(a.p, s, v.ri);
   return own + pair + emb;
+}
+
+__device__ __forceinline__ double delta_u_group(const SweepArgs &a, int64_t i, int lane) {
+  TrialIn v;
+  load_trial(a, i, lane, v);
+  return delta_u_of(a, v, lane);
 }
 
 // Descriptor of site i (or of the state with s_i flipped), by the TL lanes
@@ -780,6 +824,297 @@ __global__ void __launch_bounds__(BLOCK) k_commit_chain(SweepArgs a, uint64_t w_
   stage_stats(a, w, s, par, last, dc, sh);
 }
 
+// ---------------------------------------------------------------------------
+// Fused stage pipeline (one trial per active cell and stage).  A stage whose
+// global test fails leaves the state untouched, so the trials of the next
+// stage can be evaluated by the same kernel that evaluates the global test;
+// only an accepted stage, whose flips must be visible to every block first,
+// costs a kernel of its own for the next stage's trials.  Each kernel reads
+// the pipeline state left by block 0 of the kernel before it:
+//   SM_TRIAL  (w, s): trials of (w, s)                         -> SM_DECIDE (w, s)
+//   SM_DECIDE (w, s): global test of (w, s); accepted: commit  -> SM_TRIAL next
+//                                  otherwise: trials of next   -> SM_DECIDE next
+// and the stage after the last one of the call leads to SM_DONE (kernels
+// launched beyond that do nothing).  The draws are those of the per-stage
+// path, so both give the same chain.  The site table of sweep w + 1, stage s
+// is drawn by extra blocks of the kernel that tests (w, s): every stage's
+// sites are drawn once, after the entries they replace (sweep w - 1) were
+// last read and before the trials that read them.
+// ---------------------------------------------------------------------------
+
+// Site of active cell t in stage s of sweep w and ln u of its local test
+// (the draws of k_sites for one trial per cell); t == 0 also writes ln u_g.
+__device__ __forceinline__ void draw_site(const SweepArgs &a, uint64_t w, int64_t s, int64_t t,
+                                          int32_t *sites, double *lnus, double *lnug) {
+  const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+  if (t == 0) *lnug = log(unit_open(g.v[1]));
+  const int64_t cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+  const int32_t st = a.cstart[cell];
+  const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
+  int32_t site = -1;
+  double lnu = 0.0;
+  if (m > 0) {
+    const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
+    site = a.catoms[st + draw_index(r.v[0], m)];
+    lnu = log(unit_open(r.v[1]));
+  }
+  sites[t] = site;
+  lnus[t] = lnu;
+}
+
+// The whole site table of sweep w (into its half of the two-sweep ring).
+__global__ void __launch_bounds__(BLOCK) k_sites_ring(SweepArgs a, uint64_t w) {
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (q >= a.S * a.ncpc) return;
+  const int64_t s = q / a.ncpc, t = q - s * a.ncpc;
+  const int64_t row = (int64_t)(w & 1) * a.S + s;
+  draw_site(a, w, s, t, a.sites + row * a.ncpc, a.site_lnu + row * a.ncpc, a.stage_lnug + row);
+}
+
+__global__ void k_pipe_init(DevState *ds, unsigned long long w0, unsigned long long w_end) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    StageMachine m;
+    m.w = w0;
+    m.s = 0;
+    m.nb = ds->n_b_cur;
+    m.phase = w0 < w_end ? SM_TRIAL : SM_DONE;
+    m.pad = 0;
+    ds->pipe.sm[0] = m;
+    ds->pipe.sm[1] = m;
+    ds->pipe.w_end = w_end;
+    ds->pipe.used = 0;
+  }
+}
+
+// Local tests of stage (w, s) from the loaded trial data: the record of the
+// group's cell, the trial log, and the block's partial sums into part.
+__device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t w, int64_t s,
+                                                   int64_t t, int lane, int32_t i, double lnu,
+                                                   const TrialIn &v, int32_t *rec,
+                                                   long long *part, long long *sh) {
+  long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
+  if (t < a.ncpc) {
+    int32_t site = -1;
+    if (i >= 0) {
+      const double du = delta_u_of(a, v, lane);
+      if (lane == 0) {
+        const int dn = 1 - 2 * v.s;
+        const double xl = a.beta * (du + a.dmu0 * (double)dn);
+        const double margin = lnu + xl;
+        const bool ok = lnu < -xl;
+        valid = 1;
+        tie = fabs(margin) < TIE;
+        if (ok) {
+          acc = 1;
+          dn_acc = dn;
+          site = i;
+        }
+        if (a.tlog) {
+          const unsigned long long idx = atomicAdd(&a.ds->tlog_n, 1ull);
+          if ((int64_t)idx < a.tcap) {
+            const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+            double *L = a.tlog + 8 * idx;
+            L[0] = (double)w;
+            L[1] = (double)s;
+            L[2] = (double)colour_cell(a, (int)(g.v[0] >> 61), t);
+            L[3] = (double)i;
+            L[4] = (double)dn;
+            L[5] = ok ? 1.0 : 0.0;
+            L[6] = du;
+            L[7] = margin;
+          }
+        }
+      }
+    }
+    if (lane == 0) rec[t] = site;
+  }
+  long long v4[4] = {valid, acc, dn_acc, tie};
+  block_sums<4>(v4, sh);
+  if (threadIdx.x == 0) {
+    long long *P = part + NPART * blockIdx.x;
+    P[0] = v4[0];
+    P[1] = v4[1];
+    P[2] = v4[2];
+    P[3] = v4[3];
+    P[4] = v4[0];
+  }
+}
+
+// Site and trial data of group t in stage (w, s) (site -1: empty cell or
+// past the last active cell).
+__device__ __forceinline__ void pipe_trials_load(const SweepArgs &a, uint64_t w, int64_t s,
+                                                 int64_t t, int lane, int32_t &i, double &lnu,
+                                                 TrialIn &v) {
+  i = -1;
+  lnu = 0.0;
+  v.m = 0;
+  v.s = 0;
+  v.ri = 0.0;
+  if (t < a.ncpc) {
+    const int64_t q = ((int64_t)(w & 1) * a.S + s) * a.ncpc + t;
+    i = a.sites[q];
+    lnu = a.site_lnu[q];
+    if (i >= 0) load_trial(a, i, lane, v);
+  }
+}
+
+// Commit of an accepted trial at site i by the TL lanes of its group: rho_j
+// += delta_j of every neighbour entry, then the species and the velocity.
+__device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int lane) {
+  const int s0 = a.sp[i], s1 = 1 - s0;
+  const int m = a.cnt[i];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = lane + h * TL;
+    if (k < m) {
+      const int64_t e = (int64_t)i * KMAX + k;
+      const int32_t j = a.nj[e];
+      const double dd = a.ndd[e];
+      const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
+      a.rho[j] = a.rho[j] + delta;
+    }
+  }
+  if (lane == 0) {
+    a.sp[i] = (uint8_t)s1;
+    if (a.vx) {
+      const double f = sqrt(a.p.mass[s0] / a.p.mass[s1]);
+      a.vx[i] = a.vx[i] * f;
+      a.vy[i] = a.vy[i] * f;
+      a.vz[i] = a.vz[i] * f;
+    }
+  }
+}
+
+// One kernel of the pipeline; par is the launch parity (state read from
+// pipe.sm[par], written to pipe.sm[par ^ 1]).  Blocks [0, nblk) hold one
+// group of TL lanes per active cell; the blocks after them draw sites.
+__global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
+  __shared__ long long sh[BLOCK];
+  DevState *ds = a.ds;
+  const StageMachine m = ds->pipe.sm[par];
+  const uint64_t w_end = ds->pipe.w_end;
+  if (m.phase == SM_DONE) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ds->pipe.sm[par ^ 1] = m;
+    return;
+  }
+  const int64_t S = a.S, ncpc = a.ncpc;
+  if ((int64_t)blockIdx.x >= a.nblk) {
+    const int64_t t = ((int64_t)blockIdx.x - a.nblk) * BLOCK + threadIdx.x;
+    if (m.phase == SM_DECIDE && m.w + 1 < w_end && t < ncpc) {
+      const uint64_t w1 = m.w + 1;
+      const int64_t row = (int64_t)(w1 & 1) * S + m.s;
+      draw_site(a, w1, m.s, t, a.sites + row * ncpc, a.site_lnu + row * ncpc,
+                a.stage_lnug + row);
+    }
+    return;
+  }
+  const int lane = threadIdx.x % TL;
+  const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
+  // the parity of the stage counter picks the record and partial-sum buffers
+  const uint64_t gs = m.w * (uint64_t)S + (uint64_t)m.s;
+  const int64_t rstride = ncpc, pstride = (int64_t)NPART * a.nblk;
+  if (m.phase == SM_TRIAL) {
+    int32_t i;
+    double lnu;
+    TrialIn v;
+    pipe_trials_load(a, m.w, m.s, t, lane, i, lnu, v);
+    pipe_trials_finish(a, m.w, m.s, t, lane, i, lnu, v, a.rec + (gs & 1) * rstride,
+                       a.part + (gs & 1) * pstride, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      StageMachine n = m;
+      n.phase = SM_DECIDE;
+      ds->pipe.sm[par ^ 1] = n;
+      ds->pipe.used += 1;
+    }
+    return;
+  }
+  // SM_DECIDE: the next stage's trial data are read before the global test
+  // (they are used only if the test fails and the state stays as it is)
+  uint64_t w2 = m.w;
+  int64_t s2 = m.s + 1;
+  if (s2 == S) {
+    w2 += 1;
+    s2 = 0;
+  }
+  const bool more = w2 < w_end;
+  int32_t i2 = -1;
+  double lnu2 = 0.0;
+  TrialIn v;
+  v.m = 0;
+  v.s = 0;
+  v.ri = 0.0;
+  if (more) pipe_trials_load(a, w2, s2, t, lane, i2, lnu2, v);
+  const double lnug = a.stage_lnug[(int64_t)(m.w & 1) * S + m.s];
+  // global test of (w, s) (Eq. trans_vcsgc_par2) from the trial blocks' sums
+  const long long *P = a.part + (gs & 1) * pstride;
+  long long v5[5] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v5[k] += P[NPART * b + k];
+  }
+  block_sums<5>(v5, sh);
+  const unsigned long long nrec = (unsigned long long)v5[1];
+  const long long dn_tot = v5[2];
+  int gacc = -1;
+  double xg = 0.0, mg = 0.0;
+  if (nrec > 0) {
+    const double tt = (double)m.nb - a.ncbar;
+    const double dnd = (double)dn_tot;
+    xg = a.beta * a.kN * dnd * (dnd + 2.0 * tt);
+    mg = lnug + xg;
+    gacc = lnug < -xg ? 1 : 0;
+  }
+  const long long nb_new = m.nb + (gacc == 1 ? dn_tot : 0);
+  if (gacc == 1) {
+    if (t < ncpc) {
+      const int32_t i = a.rec[(gs & 1) * rstride + t];
+      if (i >= 0) pipe_commit(a, i, lane);
+    }
+  } else if (more) {
+    pipe_trials_finish(a, w2, s2, t, lane, i2, lnu2, v, a.rec + ((gs + 1) & 1) * rstride,
+                       a.part + ((gs + 1) & 1) * pstride, sh);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ds->n_b_cur = nb_new;
+    ds->trials += (unsigned long long)v5[0];
+    ds->stage1_pass += (unsigned long long)v5[4];
+    ds->local_acc += nrec;
+    ds->near_ties += (unsigned long long)v5[3];
+    ds->stages += 1;
+    if (gacc == 1) {
+      ds->stage_acc += 1;
+      ds->flips += nrec;
+    }
+    if (nrec > 0 && fabs(mg) < TIE) ds->near_ties += 1;
+    if (m.s == S - 1) {
+      ds->sum_n += (double)nb_new;
+      ds->sum_n2 += (double)nb_new * (double)nb_new;
+    }
+    if (a.slog) {
+      const unsigned long long idx = ds->slog_n++;
+      if ((int64_t)idx < a.scap) {
+        double *L = a.slog + 8 * idx;
+        L[0] = (double)m.w;
+        L[1] = (double)m.s;
+        L[2] = (double)(int)(philox(a.seed, a.replica, m.w, (uint64_t)m.s, 0, 0).v[0] >> 61);
+        L[3] = (double)dn_tot;
+        L[4] = (double)nrec;
+        L[5] = (double)gacc;
+        L[6] = xg;
+        L[7] = mg;
+      }
+    }
+    StageMachine n;
+    n.w = w2;
+    n.s = s2;
+    n.nb = nb_new;
+    n.phase = !more ? SM_DONE : (gacc == 1 ? SM_TRIAL : SM_DECIDE);
+    n.pad = 0;
+    ds->pipe.sm[par ^ 1] = n;
+    ds->pipe.used += 1;
+  }
+}
+
 __global__ void __launch_bounds__(BLOCK)
     k_descriptors(SweepArgs a, const int32_t *__restrict__ sites, int64_t n, int flip,
                   double *out) {
@@ -913,6 +1248,178 @@ static hipError_t build_stage_graph(vcsgc_ctx *c, const SweepArgs &a0, double dm
   return hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
 }
 
+// Graphs of pipeline kernels: `big` holds S launches (one sweep's worth when
+// no stage is accepted), `small` PIPE_SMALL; both have even length, so every
+// replay starts at launch parity 0.  The kernel arguments (parameters, seed)
+// are baked in; the graphs are rebuilt when they change.
+constexpr int PIPE_SMALL = 4;
+
+// With per-kernel timing on, `big` also starts and ends with an event-record
+// node: the span of its last replay, read when the call ends, over its
+// kernel count is the mean time per pipeline kernel (gaps between kernels
+// included).  Events between the kernels would stretch the pipeline.
+struct PipeGraph {
+  hipGraphExec_t big = nullptr, small = nullptr;
+  int64_t nbig = 0;
+  SweepArgs a0[2];  // arguments of the even / odd nodes
+  int par[2] = {0, 1};
+  double key[4] = {0, 0, 0, 0};
+  uint64_t seed = 0;
+  bool timed = false;
+  std::vector<hipEvent_t> ev;
+};
+
+void free_pipe_graph(vcsgc_ctx *c) {
+  PipeGraph *g = (PipeGraph *)c->pipe_graph;
+  if (!g) return;
+  if (g->big) (void)hipGraphExecDestroy(g->big);
+  if (g->small) (void)hipGraphExecDestroy(g->small);
+  for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
+  delete g;
+  c->pipe_graph = nullptr;
+}
+
+static hipError_t pipe_graph_of(PipeGraph *g, int64_t len, unsigned grid, bool timed,
+                                hipGraphExec_t *out) {
+  hipGraph_t graph;
+  hipError_t e = hipGraphCreate(&graph, 0);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t prev = nullptr;
+  void *params[2][2] = {{&g->a0[0], &g->par[0]}, {&g->a0[1], &g->par[1]}};
+  auto add_event = [&]() -> hipError_t {
+    hipEvent_t ev;
+    hipError_t e2 = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
+    if (e2 != hipSuccess) return e2;
+    g->ev.push_back(ev);
+    hipGraphNode_t node;
+    e2 = hipGraphAddEventRecordNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, ev);
+    if (e2 == hipSuccess) prev = node;
+    return e2;
+  };
+  if (timed) e = add_event();
+  for (int64_t q = 0; q < len && e == hipSuccess; ++q) {
+    hipKernelNodeParams kp = {};
+    kp.func = (void *)k_stage;
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(BLOCK);
+    kp.kernelParams = params[q & 1];
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  }
+  if (e == hipSuccess && timed) e = add_event();
+  if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  return e;
+}
+
+// Launch k (even) pipeline kernels starting at parity 0.
+static hipError_t pipe_launch(vcsgc_ctx *c, const SweepArgs &a, unsigned grid, int64_t k,
+                              PipeGraph *g) {
+  if (g) {
+    while (k >= g->nbig) {
+      hipError_t e = hipGraphLaunch(g->big, c->stream);
+      if (e != hipSuccess) return e;
+      k -= g->nbig;
+    }
+    while (k > 0) {
+      hipError_t e = hipGraphLaunch(g->small, c->stream);
+      if (e != hipSuccess) return e;
+      k -= PIPE_SMALL;
+    }
+    return hipSuccess;
+  }
+  for (int64_t q = 0; q < k; ++q) {
+    const int h = tstart(c, VCSGC_KT_STAGE);
+    k_stage<<<grid, BLOCK, 0, c->stream>>>(a, (int)(q & 1));
+    tstop(c, h);
+  }
+  return hipGetLastError();
+}
+
+// Sweeps w .. w + n_sweeps - 1 through the fused pipeline.  The number of
+// kernels a call needs is one per stage, plus one, plus one per accepted
+// stage; the host launches its estimate, reads the pipeline's progress and
+// launches more until the last stage has been decided.
+static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double kappa,
+                                  double cbar, double T, int64_t n_sweeps, bool use_graph,
+                                  bool timed) {
+  a.sites = c->m_sites;
+  a.site_lnu = c->m_lnu;
+  a.stage_lnug = c->m_lnug;
+  a.rec = c->m_rec;
+  a.part = c->m_part;
+  a.nblk = grid_for(a.ncpc * TL);
+  a.wdev = nullptr;
+  const unsigned grid = (unsigned)(a.nblk + grid_for(a.ncpc));
+  PipeGraph *g = nullptr;
+  if (use_graph) {
+    g = (PipeGraph *)c->pipe_graph;
+    if (!g || g->key[0] != dmu0 || g->key[1] != kappa || g->key[2] != cbar || g->key[3] != T ||
+        g->seed != a.seed || g->timed != timed) {
+      free_pipe_graph(c);
+      g = new PipeGraph();
+      c->pipe_graph = g;
+      g->key[0] = dmu0;
+      g->key[1] = kappa;
+      g->key[2] = cbar;
+      g->key[3] = T;
+      g->seed = a.seed;
+      g->a0[0] = g->a0[1] = a;
+      g->nbig = a.S + (a.S & 1);
+      g->timed = timed;
+      hipError_t e = pipe_graph_of(g, g->nbig, grid, timed, &g->big);
+      if (e == hipSuccess) e = pipe_graph_of(g, PIPE_SMALL, grid, false, &g->small);
+      if (e != hipSuccess) {
+        free_pipe_graph(c);
+        return e;
+      }
+    }
+  }
+  const uint64_t w0 = c->w, w_end = c->w + (uint64_t)n_sweeps;
+  k_sites_ring<<<grid_for(a.S * a.ncpc), BLOCK, 0, c->stream>>>(a, w0);
+  k_pipe_init<<<1, 64, 0, c->stream>>>(a.ds, (unsigned long long)w0, (unsigned long long)w_end);
+  const int64_t G = n_sweeps * a.S;
+  const int64_t step = use_graph ? PIPE_SMALL : 2;
+  auto round_up = [&](int64_t k) { return (k + step - 1) / step * step; };
+  int64_t k = round_up(1 + G + (int64_t)std::ceil((double)G * c->m_acc_rate) + 2);
+  hipError_t e = pipe_launch(c, a, grid, k, g);
+  if (e != hipSuccess) return e;
+  // every kernel before SM_DONE advances the state, so 2 G + 1 kernels always
+  // suffice; more would mean a broken pipeline state
+  int64_t launched = k;
+  for (;;) {
+    e = hipMemcpyAsync(c->h_pipe, &a.ds->pipe, sizeof(StageProgress), hipMemcpyDeviceToHost,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    const StageMachine m = c->h_pipe->sm[0];
+    if (m.phase == SM_DONE) break;
+    // stages still to decide, the pending trials, and the accepts expected among them
+    const int64_t left = (int64_t)(w_end - m.w) * a.S - m.s;
+    k = round_up(left + 1 + (int64_t)std::ceil((double)left * c->m_acc_rate) + 2);
+    if (left <= 0 || launched > 2 * G + 2 * step + 1) return hipErrorUnknown;
+    launched += k;
+    e = pipe_launch(c, a, grid, k, g);
+    if (e != hipSuccess) return e;
+  }
+  if (G > 0) {
+    const double extra = (double)c->h_pipe->used - 1.0 - (double)G;
+    c->m_acc_rate = extra > 0.0 ? extra / (double)G : 0.0;
+  }
+  if (g && g->timed) {
+    // span of the last replay of `big` (the stream is synchronized)
+    float ms = 0.f;
+    if (launched >= g->nbig && g->ev.size() == 2 &&
+        hipEventElapsedTime(&ms, g->ev[0], g->ev[1]) == hipSuccess) {
+      c->kt_ms[VCSGC_KT_STAGE] += ms;
+      c->kt_n[VCSGC_KT_STAGE] += g->nbig;
+    }
+    c->kt_seen[VCSGC_KT_STAGE] += launched;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
                          int64_t n_sweeps, uint64_t seed) {
   SweepArgs a;
@@ -972,6 +1479,13 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   const int gb = grid_for(a.ncpc * TL);
   a.nblk = gb;
   k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
+  // one trial per cell and stage: the fused pipeline (graphs of its kernels
+  // unless logs or per-kernel timing are on)
+  if (a.K == 1 && !a.da_mode && a.smp_cap == 0) {
+    if (n_sweeps == 0) return hipGetLastError();
+    const bool timed = (c->tmask & (1u << VCSGC_KT_STAGE)) != 0;
+    return launch_pipeline(c, a, dmu0, kappa, cbar, T, n_sweeps, !a.tlog && !a.slog, timed);
+  }
   // plain sweeps with no logs and no per-kernel timing replay a graph of one
   // sweep (no host work per stage); everything else launches stage by stage
   const bool per_kernel_timing = (c->tmask & ((1u << VCSGC_KT_TRIAL) | (1u << VCSGC_KT_COMMIT))) != 0;

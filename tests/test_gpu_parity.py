@@ -244,6 +244,45 @@ def test_stage_graph_replay(torch_cuda, oracle_mod):
     g.close()
 
 
+@pytest.mark.parametrize("log", [True, False])
+@pytest.mark.parametrize("kappa", [0.0, 10.0])
+def test_stage_pipeline_accepting_stages(torch_cuda, oracle_mod, kappa, log):
+    """The fused stage pipeline with many accepted stages (kappa = 0 accepts
+    every stage with a local accept): the extra trial kernels after accepted
+    stages, the host's top-up launches when its estimate falls short, direct
+    launches (logs) and graph replays all give the oracle's chain."""
+    d = W.c2(cbar=0.05)
+    r = _sweep_parity(oracle_mod, d, I.params("FS-P1"), 3, kappa=kappa, log=log,
+                      chunks=[1, 2], strategy="stage")
+    assert r["stage_accepts"] > 0
+    if kappa == 0.0:
+        assert r["stage_accepts"] * 2 > r["stages"]
+
+
+def test_stage_pipeline_timed_and_empty(torch_cuda, oracle_mod):
+    """Per-kernel timing of the pipeline (event nodes in its graphs) and a
+    call of zero sweeps leave the chain equal to the oracle's."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = W.c2(cbar=0.05)
+    g = gpu_context(d, pot)
+    g.set_tuning("stage", 1)
+    st = oracle_state(O, d, pot)
+    args = (d["dmu0"], 10.0, d["cbar"], d["T"])
+    g.kernel_timing(["stage"])
+    s0 = g.sweep(*args, 0, d["seed"])
+    assert s0["trials"] == 0 and s0["stages"] == 0
+    sg = g.sweep(*args, 2, d["seed"])
+    kt = g.kernel_times()
+    assert kt["stage"][2] >= sg["stages"] and kt["stage"][1] > 0
+    so, _, _ = O.sweep(st, *args, 2, d["seed"])
+    for key in ("trials", "local_accepts", "stage_accepts", "flips", "n_final"):
+        assert sg[key] == so[key], key
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    g.close()
+
+
 @pytest.mark.parametrize("k", [2, 5])
 def test_local_chain_parity(torch_cuda, oracle_mod, k):
     """k trials per active cell per stage: every trial (its dU, decision and
