@@ -105,8 +105,11 @@ __device__ __forceinline__ int64_t p_colour_cell(const RepD &r, int colour, int6
   return cx + (int64_t)r.n0 * (cy + (int64_t)r.n1 * cz);
 }
 
-// transmutation energy change by the PTL lanes of a group (in-order sums)
-__device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int lane) {
+// transmutation energy change by the PTL lanes of a group (in-order sums of
+// the terms the lanes leave in the group's LDS slots; a group is 16 lanes of
+// one wave, whose LDS accesses are performed in order)
+__device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int lane,
+                                            double2 *grp) {
   const int s = a.sp[i], s1 = 1 - s;
   const double ri = a.rho[i];
   const int m = a.cnt[i];
@@ -125,13 +128,22 @@ __device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int
       te[h] = embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
     }
   }
+  grp[lane] = make_double2(tp[0], te[0]);
+  grp[lane + PTL] = make_double2(tp[1], te[1]);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   double pair = 0.0, emb = 0.0;
-  for (int k = 0; k < m; ++k) {
-    const int h = k / PTL;
-    const double vp = __shfl(h ? tp[1] : tp[0], k % PTL, PTL);
-    const double ve = __shfl(h ? te[1] : te[0], k % PTL, PTL);
-    pair += vp;
-    emb += ve;
+  for (int k0 = 0; k0 < KMAX; k0 += 8) {
+    if (k0 >= m) break;
+    double2 q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = grp[k0 + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < m) {
+        pair += q[u].x;
+        emb += q[u].y;
+      }
   }
   const double own = embed(a.p, s1, ri) - embed(a.p, s, ri);
   return own + pair + emb;
@@ -139,6 +151,7 @@ __device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int
 
 __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
   __shared__ long long sh[BLOCK];
+  __shared__ double2 pterms[PGROUPS][KMAX];
   __shared__ int bflag;
   const int g = blockIdx.x;
   const int rix = a.wg_rep[g];
@@ -175,7 +188,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
         if (m > 0) {
           const U4 rr = philox(r.seed, r.key1, w, (uint64_t)s, (uint64_t)cell, 1);
           const int64_t i = catoms[c0 + draw_index(rr.v[0], m)];
-          const double du = p_delta_u(a, i, lane);
+          const double du = p_delta_u(a, i, lane, pterms[grp]);
           if (lane == 0) {
             const double u = unit_open(rr.v[1]);
             const int dn = 1 - 2 * (int)a.sp[i];

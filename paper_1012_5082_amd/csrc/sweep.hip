@@ -115,13 +115,20 @@ __device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int la
     }
 }
 
+// Per trial group, the (pair, embedding) terms of its KMAX entries in LDS.
+typedef double2 GroupTerms[KMAX];
+
 // dU of s_i -> 1 - s_i, evaluated by the TL lanes of one group:
 //   (F_{s'}(rho_i) - F_s(rho_i)) + sum_j [(eps_{s's_j} dd) g - (eps_{s s_j} dd) g]
 //   + sum_j [F_{s_j}(rho_j + (t_{s'} dd - t_s dd)) - F_{s_j}(rho_j)]
-// Each lane computes the terms of its entries; the two sums are then formed
-// in ascending entry order from the shuffled terms, so the rounding is that
-// of the sequential sums.  Every lane of the group returns the same value.
-__device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialIn &v, int lane) {
+// Each lane computes the terms of its entries and stores them in the group's
+// LDS slots; every lane then forms both sums in ascending entry order from
+// there (the rounding of the sequential sums; the slot reads do not wait on
+// the additions, so there is one LDS round trip per eight entries rather than
+// one per entry).  A group is 16 lanes of one wave, whose LDS accesses are
+// performed in order.  Every lane of the group returns the same value.
+__device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialIn &v, int lane,
+                                             double2 *grp) {
   const int s = v.s, s1 = 1 - s;
   const int m = v.m;
   double tp[2] = {0.0, 0.0}, te[2] = {0.0, 0.0};
@@ -137,23 +144,33 @@ __device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialIn &
       te[h] = embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
     }
   }
+  grp[lane] = make_double2(tp[0], te[0]);
+  grp[lane + TL] = make_double2(tp[1], te[1]);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // two independent in-order chains
   double pair = 0.0, emb = 0.0;
-  for (int k = 0; k < m; ++k) {
-    const int h = k / TL;
-    const double vp = __shfl(h ? tp[1] : tp[0], k % TL, TL);
-    const double ve = __shfl(h ? te[1] : te[0], k % TL, TL);
-    pair += vp;
-    emb += ve;
+  for (int k0 = 0; k0 < KMAX; k0 += 8) {
+    if (k0 >= m) break;
+    double2 q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = grp[k0 + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < m) {
+        pair += q[u].x;
+        emb += q[u].y;
+      }
   }
   const double own = embed(a.p, s1, v.ri) - embed(a.p, s, v.ri);
   return own + pair + emb;
 }
 
-__device__ __forceinline__ double delta_u_group(const SweepArgs &a, int64_t i, int lane) {
+__device__ __forceinline__ double delta_u_group(const SweepArgs &a, int64_t i, int lane,
+                                                double2 *grp) {
   TrialIn v;
   load_trial(a, i, lane, v);
-  return delta_u_of(a, v, lane);
+  return delta_u_of(a, v, lane, grp);
 }
 
 // Descriptor of site i (or of the state with s_i flipped), by the TL lanes
@@ -340,6 +357,7 @@ __global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
 __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, int64_t s, int par) {
   const uint64_t w = sweep_of(a, w_arg);
   __shared__ long long sh[BLOCK];
+  __shared__ GroupTerms terms[BLOCK / TL];
   const int lane = threadIdx.x % TL;
   const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
   long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
@@ -349,7 +367,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, in
     int32_t site = -1;
     if (si >= 0) {
       const int64_t i = si;
-      const double du = delta_u_group(a, i, lane);
+      const double du = delta_u_group(a, i, lane, terms[threadIdx.x / TL]);
       if (a.smp_cap > 0 && ((int64_t)(w * (uint64_t)a.S + (uint64_t)s) * a.ncpc + t) % a.smp_stride == 0) {
         double d[10];
         descriptor_group(a, i, lane, false, d);
@@ -416,6 +434,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_a
                                                        int par) {
   const uint64_t w = sweep_of(a, w_arg);
   __shared__ long long sh[BLOCK];
+  __shared__ GroupTerms terms[BLOCK / TL];
   const int lane = threadIdx.x % TL;
   const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
   const bool live = t < a.ncpc;
@@ -428,7 +447,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_a
     if (si >= 0) {
       const int64_t i = si;
       const double lnu = a.site_lnu[q];
-      const double du = delta_u_group(a, i, lane);
+      const double du = delta_u_group(a, i, lane, terms[threadIdx.x / TL]);
       const int s0 = a.sp[i];
       const int dn = 1 - 2 * s0;
       const double xl = a.beta * (du + a.dmu0 * (double)dn);
@@ -517,6 +536,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w_arg,
                                                     int par) {
   const uint64_t w = sweep_of(a, w_arg);
   __shared__ long long sh[BLOCK];
+  __shared__ GroupTerms terms[BLOCK / TL];
   __shared__ __bf16 zs[16 * MLP_KP];
   __shared__ __bf16 h1[16 * MLP_H], h2[16 * MLP_H];
   __shared__ float yv[16];
@@ -535,7 +555,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w_arg,
     if (a.dj)
       desc_du_group(a, i, lane, dfw, dfl, du);
     else
-      du = delta_u_group(a, i, lane);
+      du = delta_u_group(a, i, lane, terms[threadIdx.x / TL]);
   }
   // ---- surrogate value of the forward move
   if (a.da_mode == 1) {
@@ -891,12 +911,13 @@ __global__ void k_pipe_init(DevState *ds, unsigned long long w0, unsigned long l
 __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t w, int64_t s,
                                                    int64_t t, int lane, int32_t i, double lnu,
                                                    const TrialIn &v, int32_t *rec,
-                                                   long long *part, long long *sh) {
+                                                   long long *part, long long *sh,
+                                                   double2 *grp) {
   long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
   if (t < a.ncpc) {
     int32_t site = -1;
     if (i >= 0) {
-      const double du = delta_u_of(a, v, lane);
+      const double du = delta_u_of(a, v, lane, grp);
       if (lane == 0) {
         const int dn = 1 - 2 * v.s;
         const double xl = a.beta * (du + a.dmu0 * (double)dn);
@@ -990,6 +1011,7 @@ __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int l
 // group of TL lanes per active cell; the blocks after them draw sites.
 __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   __shared__ long long sh[BLOCK];
+  __shared__ GroupTerms terms[BLOCK / TL];
   DevState *ds = a.ds;
   const StageMachine m = ds->pipe.sm[par];
   const uint64_t w_end = ds->pipe.w_end;
@@ -1019,7 +1041,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
     TrialIn v;
     pipe_trials_load(a, m.w, m.s, t, lane, i, lnu, v);
     pipe_trials_finish(a, m.w, m.s, t, lane, i, lnu, v, a.rec + (gs & 1) * rstride,
-                       a.part + (gs & 1) * pstride, sh);
+                       a.part + (gs & 1) * pstride, sh, terms[threadIdx.x / TL]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       StageMachine n = m;
       n.phase = SM_DECIDE;
@@ -1072,7 +1094,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
     }
   } else if (more) {
     pipe_trials_finish(a, w2, s2, t, lane, i2, lnu2, v, a.rec + ((gs + 1) & 1) * rstride,
-                       a.part + ((gs + 1) & 1) * pstride, sh);
+                       a.part + ((gs + 1) & 1) * pstride, sh, terms[threadIdx.x / TL]);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ds->n_b_cur = nb_new;
