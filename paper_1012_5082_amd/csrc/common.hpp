@@ -165,9 +165,10 @@ constexpr int SCAN_CHUNK = 1024;  // values per block of the cell-count scan
 
 // Sums of N integer values over the block (exact, so the order is free):
 // butterfly inside each wave, then the per-wave totals through LDS.  sh
-// needs N * (BLOCK / 64) entries; contains two barriers, so every thread of
-// the block must call it.
-template <int N>
+// needs N * (BLOCK / 64) entries; contains two barriers (one with TAIL =
+// false, when sh is not written again before the kernel ends), so every
+// thread of the block must call it.
+template <int N, bool TAIL = true>
 __device__ __forceinline__ void block_sums(long long (&v)[N], long long *sh) {
 #pragma unroll
   for (int k = 0; k < N; ++k)
@@ -184,7 +185,7 @@ __device__ __forceinline__ void block_sums(long long (&v)[N], long long *sh) {
     for (int q = 0; q < BLOCK / 64; ++q) t += sh[q * N + k];
     v[k] = t;
   }
-  __syncthreads();
+  if (TAIL) __syncthreads();
 }
 
 inline int grid_for(int64_t n, int block = BLOCK) {

@@ -913,7 +913,7 @@ __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t 
                                                    const TrialIn &v, int32_t *rec,
                                                    long long *part, long long *sh,
                                                    double2 *grp) {
-  long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
+  long long valid = 0, dn_acc = 0, tie = 0;
   if (t < a.ncpc) {
     int32_t site = -1;
     if (i >= 0) {
@@ -926,7 +926,6 @@ __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t 
         valid = 1;
         tie = fabs(margin) < TIE;
         if (ok) {
-          acc = 1;
           dn_acc = dn;
           site = i;
         }
@@ -949,15 +948,16 @@ __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t 
     }
     if (lane == 0) rec[t] = site;
   }
-  long long v4[4] = {valid, acc, dn_acc, tie};
-  block_sums<4>(v4, sh);
+  // counts packed two to a word (each 32-bit field's sum over the grid stays
+  // below 2^31): (trials | accepts with dn = +1), (accepts with dn = -1 | ties);
+  // sh is this call's own scratch (no trailing barrier)
+  long long v2[2] = {valid | ((dn_acc > 0 ? 1ll : 0ll) << 32),
+                     (dn_acc < 0 ? 1ll : 0ll) | (tie << 32)};
+  block_sums<2, false>(v2, sh);
   if (threadIdx.x == 0) {
-    long long *P = part + NPART * blockIdx.x;
-    P[0] = v4[0];
-    P[1] = v4[1];
-    P[2] = v4[2];
-    P[3] = v4[3];
-    P[4] = v4[0];
+    long long *P = part + 2 * blockIdx.x;
+    P[0] = v2[0];
+    P[1] = v2[1];
   }
 }
 
@@ -1010,7 +1010,8 @@ __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int l
 // pipe.sm[par], written to pipe.sm[par ^ 1]).  Blocks [0, nblk) hold one
 // group of TL lanes per active cell; the blocks after them draw sites.
 __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
-  __shared__ long long sh[BLOCK];
+  __shared__ long long sh[BLOCK];  // the trials' block counts
+  __shared__ long long shd[BLOCK / 64 * 2];  // the global test's counts
   __shared__ GroupTerms terms[BLOCK / TL];
   DevState *ds = a.ds;
   const StageMachine m = ds->pipe.sm[par];
@@ -1034,7 +1035,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
   // the parity of the stage counter picks the record and partial-sum buffers
   const uint64_t gs = m.w * (uint64_t)S + (uint64_t)m.s;
-  const int64_t rstride = ncpc, pstride = (int64_t)NPART * a.nblk;
+  const int64_t rstride = ncpc, pstride = 2 * (int64_t)a.nblk;  // two words per trial block
   if (m.phase == SM_TRIAL) {
     int32_t i;
     double lnu;
@@ -1059,6 +1060,16 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
     s2 = 0;
   }
   const bool more = w2 < w_end;
+  // the trial blocks' counts of (w, s) and ln u_g first: their reads then
+  // overlap the trial reads below
+  const double lnug = a.stage_lnug[(int64_t)(m.w & 1) * S + m.s];
+  const longlong2 *P = (const longlong2 *)(a.part + (gs & 1) * pstride);
+  long long c2[2] = {0, 0};
+  for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
+    const longlong2 q = P[b];
+    c2[0] += q.x;
+    c2[1] += q.y;
+  }
   int32_t i2 = -1;
   double lnu2 = 0.0;
   TrialIn v;
@@ -1066,15 +1077,11 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   v.s = 0;
   v.ri = 0.0;
   if (more) pipe_trials_load(a, w2, s2, t, lane, i2, lnu2, v);
-  const double lnug = a.stage_lnug[(int64_t)(m.w & 1) * S + m.s];
-  // global test of (w, s) (Eq. trans_vcsgc_par2) from the trial blocks' sums
-  const long long *P = a.part + (gs & 1) * pstride;
-  long long v5[5] = {0, 0, 0, 0, 0};
-  for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) v5[k] += P[NPART * b + k];
-  }
-  block_sums<5>(v5, sh);
+  // global test of (w, s) (Eq. trans_vcsgc_par2) from the trial blocks' counts
+  block_sums<2, false>(c2, shd);
+  const long long n_valid = c2[0] & 0xffffffffll, n_plus = c2[0] >> 32;
+  const long long n_minus = c2[1] & 0xffffffffll, n_tie = c2[1] >> 32;
+  long long v5[5] = {n_valid, n_plus + n_minus, n_plus - n_minus, n_tie, n_valid};
   const unsigned long long nrec = (unsigned long long)v5[1];
   const long long dn_tot = v5[2];
   int gacc = -1;
