@@ -76,40 +76,47 @@ __device__ __forceinline__ uint64_t sweep_of(const SweepArgs &a, uint64_t w) {
 constexpr int TL = 16;
 static_assert(KMAX <= 2 * TL, "a trial group covers at most 2*TL neighbours");
 
-// What one lane of a trial group reads for the trial at site i: the site's
-// species, density and row length, and its neighbour entries k = lane and
-// k = lane + TL with their species and densities.  Entry k = lane always lies
-// inside the KMAX-entry row, so the row reads are issued together with those
-// of the site (unused entries beyond the row length are never dereferenced).
-struct TrialIn {
+// What one lane of a group of L lanes reads for the trial at site i: the
+// site's species, density and row length, and its neighbour entries
+// k = lane + h L with their species and densities.  Entries k < 16 always lie
+// inside the KMAX-entry row, so their row reads are issued together with
+// those of the site (unused entries beyond the row length are never
+// dereferenced); rows longer than 16 entries are rare.
+template <int L>
+struct TrialInT {
+  static constexpr int H = KMAX / L;
   int s, m;
   double ri;
-  int32_t j[2];
-  double dd[2], g[2], rj[2];
-  int sj[2];
+  int32_t j[H];
+  double dd[H], g[H], rj[H];
+  int sj[H];
 };
+typedef TrialInT<TL> TrialIn;
 
-__device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int lane, TrialIn &v) {
+template <int L>
+__device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int lane,
+                                           TrialInT<L> &v) {
+  constexpr int H = KMAX / L;
   v.s = a.sp[i];
   v.ri = a.rho[i];
   v.m = a.cnt[i];
-  const int64_t e0 = i * KMAX + lane;
-  v.j[0] = a.nj[e0];
-  v.dd[0] = a.ndd[e0];
-  v.g[0] = a.ng[e0];
-  v.j[1] = 0;
-  v.dd[1] = v.g[1] = 0.0;
-  v.sj[0] = v.sj[1] = 0;
-  v.rj[0] = v.rj[1] = 0.0;
-  if (lane + TL < v.m) {
-    const int64_t e1 = e0 + TL;
-    v.j[1] = a.nj[e1];
-    v.dd[1] = a.ndd[e1];
-    v.g[1] = a.ng[e1];
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int k = lane + h * L;
+    v.j[h] = 0;
+    v.dd[h] = v.g[h] = 0.0;
+    v.sj[h] = 0;
+    v.rj[h] = 0.0;
+    if ((h + 1) * L <= 16 || k < v.m) {
+      const int64_t e = i * KMAX + k;
+      v.j[h] = a.nj[e];
+      v.dd[h] = a.ndd[e];
+      v.g[h] = a.ng[e];
+    }
   }
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-    if (lane + h * TL < v.m) {
+  for (int h = 0; h < H; ++h)
+    if (lane + h * L < v.m) {
       v.sj[h] = a.sp[v.j[h]];
       v.rj[h] = a.rho[v.j[h]];
     }
@@ -118,34 +125,35 @@ __device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int la
 // Per trial group, the (pair, embedding) terms of its KMAX entries in LDS.
 typedef double2 GroupTerms[KMAX];
 
-// dU of s_i -> 1 - s_i, evaluated by the TL lanes of one group:
+// dU of s_i -> 1 - s_i, evaluated by the L lanes of one group:
 //   (F_{s'}(rho_i) - F_s(rho_i)) + sum_j [(eps_{s's_j} dd) g - (eps_{s s_j} dd) g]
 //   + sum_j [F_{s_j}(rho_j + (t_{s'} dd - t_s dd)) - F_{s_j}(rho_j)]
 // Each lane computes the terms of its entries and stores them in the group's
 // LDS slots; every lane then forms both sums in ascending entry order from
 // there (the rounding of the sequential sums; the slot reads do not wait on
 // the additions, so there is one LDS round trip per eight entries rather than
-// one per entry).  A group is 16 lanes of one wave, whose LDS accesses are
+// one per entry).  A group is L lanes of one wave, whose LDS accesses are
 // performed in order.  Every lane of the group returns the same value.
-__device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialIn &v, int lane,
+template <int L>
+__device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialInT<L> &v, int lane,
                                              double2 *grp) {
+  constexpr int H = KMAX / L;
   const int s = v.s, s1 = 1 - s;
   const int m = v.m;
-  double tp[2] = {0.0, 0.0}, te[2] = {0.0, 0.0};
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int k = lane + h * TL;
+  for (int h = 0; h < H; ++h) {
+    const int k = lane + h * L;
+    double tp = 0.0, te = 0.0;
     if (k < m) {
       const int sj = v.sj[h];
       const double dd = v.dd[h], g = v.g[h];
       const double rj = v.rj[h];
-      tp[h] = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
+      tp = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
       const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
-      te[h] = embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
+      te = embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
     }
+    grp[k] = make_double2(tp, te);
   }
-  grp[lane] = make_double2(tp[0], te[0]);
-  grp[lane + TL] = make_double2(tp[1], te[1]);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // two independent in-order chains
