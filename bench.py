@@ -79,7 +79,6 @@ TRAFFIC = {
     "forces": ("k_forces", "paper_1012_5082_amd/csrc/md.hip", "profiles/k_forces_c3_traffic.md"),
     "density": ("k_density_md", "paper_1012_5082_amd/csrc/md.hip",
                 "profiles/k_density_md_c3_traffic.md"),
-    "trial": ("k_trial", "paper_1012_5082_amd/csrc/sweep.hip", "profiles/k_trial_c3_traffic.md"),
     "stage": ("k_stage", "paper_1012_5082_amd/csrc/sweep.hip", "profiles/k_stage_c3_traffic.md"),
 }
 
