@@ -1459,7 +1459,7 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
 
 hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
                          int64_t n_sweeps, uint64_t seed) {
-  SweepArgs a;
+  SweepArgs a = {};
   a.n = c->n;
   a.n0 = c->nc[0];
   a.n1 = c->nc[1];
