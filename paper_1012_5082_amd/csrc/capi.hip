@@ -28,7 +28,7 @@ void free_all(vcsgc_ctx *c) {
                   c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
                   c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
                   c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos,
-                  c->md_tmp,     c->md_tcnt,    c->sites,      c->site_lnu,
+                  c->md_rows,    c->sites,      c->site_lnu,
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
                   c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnug,   c->m_rec,
                   c->m_part};
@@ -442,8 +442,6 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   A(dalloc(&c->bin_atoms, boff * c->bmax));
   if (single) {
     A(dalloc(&c->bin_pos, boff * c->bmax));
-    A(dalloc(&c->md_tmp, K * n));
-    A(dalloc(&c->md_tcnt, n));
     A(dalloc(&c->sites, reps[0].S * reps[0].ncpc));
     A(dalloc(&c->site_lnu, reps[0].S * reps[0].ncpc));
     A(dalloc(&c->stage_lnug, reps[0].S));
@@ -473,6 +471,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   A(dalloc(&c->mc_cnt, n));
   if (single) {
     A(dalloc(&c->md_j, K * n));
+    A(dalloc(&c->md_rows, K * n));
     A(dalloc(&c->md_cnt, n));
     A(dalloc(&c->xr, n));
     A(dalloc(&c->yr, n));
@@ -519,10 +518,11 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     return bail(dev_fail(c, e, "allocation"));
   if ((e = hipMemsetAsync(c->ds, 0, sizeof(vc::DevState), c->stream)) != hipSuccess)
     return bail(dev_fail(c, e, "init"));
-  // rows of the MD build always hold valid indices (empty until built)
-  if (c->md_tcnt &&
-      ((e = hipMemsetAsync(c->md_tcnt, 0, sizeof(int32_t) * n, c->stream)) != hipSuccess ||
-       (e = hipMemsetAsync(c->md_tmp, 0, sizeof(int32_t) * vc::KMAX * n, c->stream)) != hipSuccess))
+  // MD rows hold valid indices beyond their lengths too (empty until built)
+  if (c->md_j &&
+      ((e = hipMemsetAsync(c->md_j, 0, sizeof(int32_t) * vc::KMAX * n, c->stream)) != hipSuccess ||
+       (e = hipMemsetAsync(c->md_rows, 0, sizeof(int32_t) * vc::KMAX * n, c->stream)) != hipSuccess ||
+       (e = hipMemsetAsync(c->md_cnt, 0, sizeof(uint8_t) * n, c->stream)) != hipSuccess))
     return bail(dev_fail(c, e, "init"));
   for (const RepHost &r : c->reps) {
     if ((e = vc::launch_validate(c, r)) != hipSuccess) return bail(dev_fail(c, e, "validate"));
@@ -764,14 +764,14 @@ vcsgc_status md_steps_host(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
   VC_CHECK(c, vc::launch_forces(c), "forces");
   for (int64_t k = 0; k < n_steps; ++k) {
     // the closing half-kick of step k-1 is fused into the opening one of step k
-    VC_CHECK(c, vc::launch_kick_drift(c, dt_fs, k > 0), "kick-drift");
+    VC_CHECK(c, vc::launch_kick_drift(c, dt_fs, k > 0, 0), "kick-drift");
     int flag = 0;
-    VC_CHECK(c, hipMemcpyAsync(&flag, &c->ds->rebuild, sizeof(int), hipMemcpyDeviceToHost,
+    VC_CHECK(c, hipMemcpyAsync(&flag, &c->ds->rebuild[0], sizeof(int), hipMemcpyDeviceToHost,
                                c->stream),
              "copy");
     VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
     if (flag) {
-      VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild, 0, sizeof(int), c->stream), "reset");
+      VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild[0], 0, sizeof(int), c->stream), "reset");
       vcsgc_status st = refresh_md(c);
       if (st) return st;
     }
@@ -794,11 +794,13 @@ vcsgc_status md_steps_device(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
              "snapshot");
   VC_CHECK(c, hipMemsetAsync(&c->ds->md_rebuilds, 0, sizeof(unsigned long long), c->stream),
            "reset");
+  VC_CHECK(c, hipMemsetAsync(c->ds->rebuild, 0, 2 * sizeof(int), c->stream), "reset");
   VC_CHECK(c, vc::launch_pack(c), "pack");
   VC_CHECK(c, vc::launch_forces(c), "forces");
+  // step k uses the rebuild flag of parity k & 1 (its drift clears the other)
   for (int64_t k = 0; k < n_steps; ++k) {
-    VC_CHECK(c, vc::launch_kick_drift(c, dt_fs, k > 0), "kick-drift");
-    VC_CHECK(c, vc::launch_md_rebuild_cond(c), "neighbour list (MD)");
+    VC_CHECK(c, vc::launch_kick_drift(c, dt_fs, k > 0, (int)(k & 1)), "kick-drift");
+    VC_CHECK(c, vc::launch_md_rebuild_cond(c, (int)(k & 1)), "neighbour list (MD)");
     VC_CHECK(c, vc::launch_forces(c), "forces");
   }
   VC_CHECK(c, vc::launch_kick(c, dt_fs), "kick");
@@ -815,7 +817,7 @@ vcsgc_status md_steps_device(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
   VC_CHECK(c, hipMemcpyAsync(&c->ds->overflow, zero, 2 * sizeof(int), hipMemcpyHostToDevice,
                              c->stream),
            "reset");
-  VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild, 0, sizeof(int), c->stream), "reset");
+  VC_CHECK(c, hipMemsetAsync(c->ds->rebuild, 0, 2 * sizeof(int), c->stream), "reset");
   if (h.bin_overflow) {
     vcsgc_status st = grow_bins(c);
     if (st) return st;

@@ -2,6 +2,8 @@
 // independence distance, an even number per dimension so that cells whose
 // index parities agree are a full cell edge apart), the density cache of the
 // sweep, input validation and a fixed-shape FP64 reduction.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace vc {
@@ -204,22 +206,29 @@ hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r) {
 // ----------------------------------------------------------------------------
 // search bins: edge >= rc + skin, at most bmax atoms each (overflow flagged)
 // ----------------------------------------------------------------------------
-// cond (may be NULL): run only when *cond != 0 (device-decided MD rebuild)
-// pos (may be NULL) receives (x, y, z, i) of the atom in its slot
+// Grid-stride over the atoms (one atomic per distinct bin in a wave).
+// cond (may be NULL): run only when *cond != 0 (device-decided MD rebuild);
+// such a run also zeroes the MD row statistics that the list build then
+// accumulates.  pos (may be NULL) receives (x, y, z, i) of the atom in its slot.
 __global__ void k_bin_search(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ z, Grid g, int bmax, int32_t *count,
                              int32_t *atoms, double4 *pos, DevState *ds, const int *cond) {
   if (cond && *cond == 0) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double a = x[i], b2 = y[i], c2 = z[i];
-  const int b = cell_of(g, a, b2, c2);
-  const int slot = atomicAdd(&count[b], 1);
-  if (slot < bmax) {
-    atoms[(int64_t)b * bmax + slot] = (int32_t)i;
-    if (pos) pos[(int64_t)b * bmax + slot] = make_double4(a, b2, c2, (double)i);
-  } else {
-    atomicOr(&ds->bin_overflow, 1);
+  if (cond && blockIdx.x == 0 && threadIdx.x == 0) {
+    ds->pairs_md = 0ull;
+    ds->kmax_md = 0;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = x[i], b2 = y[i], c2 = z[i];
+    const int b = cell_of(g, a, b2, c2);
+    const int slot = wave_add_one(count, b);
+    if (slot < bmax) {
+      atoms[(int64_t)b * bmax + slot] = (int32_t)i;
+      if (pos) pos[(int64_t)b * bmax + slot] = make_double4(a, b2, c2, (double)i);
+    } else {
+      atomicOr(&ds->bin_overflow, 1);
+    }
   }
 }
 
@@ -234,25 +243,6 @@ hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r) {
                                                        c->reps.size() == 1 ? c->bin_pos : nullptr,
                                                        c->ds, nullptr);
   return hipGetLastError();
-}
-
-// clears the bin counts and the MD row statistics when a rebuild is pending
-__global__ void k_bins_clear_cond(int64_t nbins, int32_t *count, DevState *ds) {
-  if (ds->rebuild == 0) return;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b == 0) {
-    ds->pairs_md = 0ull;
-    ds->kmax_md = 0;
-  }
-  if (b < nbins) count[b] = 0;
-}
-
-// closes a pending rebuild: the list now matches the positions
-__global__ void k_rebuild_done(DevState *ds) {
-  if (threadIdx.x == 0 && ds->rebuild != 0) {
-    ds->rebuild = 0;
-    ds->md_rebuilds += 1ull;
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -407,282 +397,416 @@ hipError_t launch_mc_row_stats(vcsgc_ctx *c) {
   return hipGetLastError();
 }
 
+// Row statistics of a list (entries, longest row, overflow) of the block:
+// reduced in the block, then one atomic each into sum, mx and (when set)
+// ovf_flag.  Every thread of the block calls it, after its last use of LDS.
+__device__ __forceinline__ void block_row_stats(long long pairs, int kmx, bool ovf,
+                                                unsigned long long *sum, int *mx, int *ovf_flag) {
+  __shared__ long long sp[BLOCK / 64];
+  __shared__ int sk[BLOCK / 64], so[BLOCK / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    pairs += __shfl_xor(pairs, off);
+    const int o = __shfl_xor(kmx, off);
+    kmx = o > kmx ? o : kmx;
+  }
+  const int any_ovf = __ballot(ovf) != 0ull ? 1 : 0;
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sp[wv] = pairs;
+    sk[wv] = kmx;
+    so[wv] = any_ovf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tp = 0;
+    int tk = 0, to = 0;
+    for (int q = 0; q < BLOCK / 64; ++q) {
+      tp += sp[q];
+      tk = sk[q] > tk ? sk[q] : tk;
+      to |= so[q];
+    }
+    if (tp) atomicAdd(sum, (unsigned long long)tp);
+    if (tk) atomicMax(mx, tk);
+    if (to && ovf_flag) atomicOr(ovf_flag, 1);
+  }
+}
+
+__device__ __forceinline__ void md_row_stats(long long pairs, int kmx, bool ovf, DevState *ds) {
+  block_row_stats(pairs, kmx, ovf, &ds->pairs_md, &ds->kmax_md, &ds->overflow);
+}
+
 // r < rc + skin list, one lane per atom (used when some axis has fewer than
 // four search bins): the lane walks the surrounding search bins through the
-// packed (x, y, z, index) slots, appends hits to its
-// column-major row, then reloads the row into registers, sorts it by a fixed
-// bitonic network (ascending neighbour index) and writes it back.  The test
-// is r^2 < cut2: the list only has to hold every pair that can come within
-// rc before the next rebuild (its users test r < rc themselves).
-// cond (may be NULL): run only when *cond != 0.
+// packed (x, y, z, index) slots, appends hits to its row, then reloads the
+// row into registers, sorts it by a fixed bitonic network (ascending
+// neighbour index) and writes it back.  The test is r^2 < cut2: the list
+// only has to hold every pair that can come within rc before the next
+// rebuild (its users test r < rc themselves).  Row-major rows [i * KMAX + k]
+// (k_md_transpose then writes the column-major copy).
+// cond (may be NULL): run only when *cond != 0 (and count the rebuild).
 __global__ void __launch_bounds__(BLOCK)
     k_build_md(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                const double *__restrict__ z, Grid g, const int32_t *__restrict__ bcount,
                const double4 *__restrict__ bpos, int bmax, double cut2, int32_t *nj, uint8_t *cnt,
                double *xr, double *yr, double *zr, DevState *ds, const int *cond) {
   if (cond && *cond == 0) return;
+  if (cond && blockIdx.x == 0 && threadIdx.x == 0) ds->md_rebuilds += 1ull;
   const int64_t i = xcd_block() * BLOCK + threadIdx.x;
-  if (i >= n) return;
-  const double xi = x[i], yi = y[i], zi = z[i];
-  const int bx = cell_coord(xi, g.L0, g.n0), by = cell_coord(yi, g.L1, g.n1),
-            bz = cell_coord(zi, g.L2, g.n2);
-  const int n0 = g.n0 >= 3 ? 3 : 2, n1 = g.n1 >= 3 ? 3 : 2, n2 = g.n2 >= 3 ? 3 : 2;
-  const int s0 = g.n0 >= 3 ? -1 : 0, s1 = g.n1 >= 3 ? -1 : 0, s2 = g.n2 >= 3 ? -1 : 0;
   int c = 0;
-  for (int oz = 0; oz < n2; ++oz) {
-    const int zz = (bz + s2 + oz + g.n2) % g.n2;
-    for (int oy = 0; oy < n1; ++oy) {
-      const int yy = (by + s1 + oy + g.n1) % g.n1;
-      for (int ox = 0; ox < n0; ++ox) {
-        const int xx = (bx + s0 + ox + g.n0) % g.n0;
-        const int64_t nb = xx + (int64_t)g.n0 * (yy + (int64_t)g.n1 * zz);
-        const int m = min(bcount[nb], bmax);
-        const double4 *slot = bpos + nb * bmax;
-        for (int t = 0; t < m; t += 4) {
-          double4 q[4];
+  if (i < n) {
+    const double xi = x[i], yi = y[i], zi = z[i];
+    const int bx = cell_coord(xi, g.L0, g.n0), by = cell_coord(yi, g.L1, g.n1),
+              bz = cell_coord(zi, g.L2, g.n2);
+    const int n0 = g.n0 >= 3 ? 3 : 2, n1 = g.n1 >= 3 ? 3 : 2, n2 = g.n2 >= 3 ? 3 : 2;
+    const int s0 = g.n0 >= 3 ? -1 : 0, s1 = g.n1 >= 3 ? -1 : 0, s2 = g.n2 >= 3 ? -1 : 0;
+    int32_t *row = nj + i * KMAX;
+    for (int oz = 0; oz < n2; ++oz) {
+      const int zz = (bz + s2 + oz + g.n2) % g.n2;
+      for (int oy = 0; oy < n1; ++oy) {
+        const int yy = (by + s1 + oy + g.n1) % g.n1;
+        for (int ox = 0; ox < n0; ++ox) {
+          const int xx = (bx + s0 + ox + g.n0) % g.n0;
+          const int64_t nb = xx + (int64_t)g.n0 * (yy + (int64_t)g.n1 * zz);
+          const int m = min(bcount[nb], bmax);
+          const double4 *slot = bpos + nb * bmax;
+          for (int t = 0; t < m; t += 4) {
+            double4 q[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) q[u] = t + u < m ? slot[t + u] : make_double4(0, 0, 0, -1.0);
+            for (int u = 0; u < 4; ++u)
+              q[u] = t + u < m ? slot[t + u] : make_double4(0, 0, 0, -1.0);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int32_t j = (int32_t)q[u].w;
-            if (t + u < m && j != (int32_t)i) {
-              const double dx = min_image(q[u].x - xi, g.L0);
-              const double dy = min_image(q[u].y - yi, g.L1);
-              const double dz = min_image(q[u].z - zi, g.L2);
-              if ((dx * dx + dy * dy) + dz * dz < cut2) {
-                if (c < KMAX) nj[(int64_t)c * n + i] = j;
-                ++c;
+            for (int u = 0; u < 4; ++u) {
+              const int32_t j = (int32_t)q[u].w;
+              if (t + u < m && j != (int32_t)i) {
+                const double dx = min_image(q[u].x - xi, g.L0);
+                const double dy = min_image(q[u].y - yi, g.L1);
+                const double dz = min_image(q[u].z - zi, g.L2);
+                if ((dx * dx + dy * dy) + dz * dz < cut2) {
+                  if (c < KMAX) row[c] = j;
+                  ++c;
+                }
               }
             }
           }
         }
       }
     }
-  }
-  if (c > KMAX) {
-    atomicOr(&ds->overflow, 1);
-    c = KMAX;
-  }
-  int32_t v[KMAX];
+    const int cc = c < KMAX ? c : KMAX;
+    int32_t v[KMAX];
 #pragma unroll
-  for (int u = 0; u < KMAX; ++u) v[u] = u < c ? nj[(int64_t)u * n + i] : INT32_MAX;
+    for (int u = 0; u < KMAX; ++u) v[u] = u < cc ? row[u] : INT32_MAX;
 #pragma unroll
-  for (int k = 2; k <= KMAX; k <<= 1) {
+    for (int k = 2; k <= KMAX; k <<= 1) {
 #pragma unroll
-    for (int h = k >> 1; h > 0; h >>= 1) {
+      for (int h = k >> 1; h > 0; h >>= 1) {
 #pragma unroll
-      for (int a = 0; a < KMAX; ++a) {
-        const int b = a ^ h;
-        if (b > a) {
-          const int32_t lo = min(v[a], v[b]), hi = max(v[a], v[b]);
-          const bool up = (a & k) == 0;
-          v[a] = up ? lo : hi;
-          v[b] = up ? hi : lo;
+        for (int a = 0; a < KMAX; ++a) {
+          const int b = a ^ h;
+          if (b > a) {
+            const int32_t lo = min(v[a], v[b]), hi = max(v[a], v[b]);
+            const bool up = (a & k) == 0;
+            v[a] = up ? lo : hi;
+            v[b] = up ? hi : lo;
+          }
         }
       }
     }
-  }
 #pragma unroll
-  for (int u = 0; u < KMAX; ++u)
-    if (u < c) nj[(int64_t)u * n + i] = v[u];
-  cnt[i] = (uint8_t)c;
-  xr[i] = xi;
-  yr[i] = yi;
-  zr[i] = zi;
+    for (int u = 0; u < KMAX; ++u)
+      if (u < cc) row[u] = v[u];
+    cnt[i] = (uint8_t)cc;
+    xr[i] = xi;
+    yr[i] = yi;
+    zr[i] = zi;
+  }
+  md_row_stats(c < KMAX ? c : KMAX, c < KMAX ? c : KMAX, c > KMAX, ds);
 }
 
-// r < rc + skin list by super-bins of 2 x 2 x 2 search bins (every axis needs
-// at least four bins).  A block stages the 4 x 4 x 4 bins around its
-// super-bin in LDS once (positions relative to the super-bin origin, in
-// float, periodic images resolved), then four lanes per own atom test the
-// atom's 27 neighbouring bins from LDS and append hits to an LDS row.  The
-// float test uses cut2f = (cut + 1e-3)^2, a superset of r < cut (coordinates
-// are below 20 A, so the float error is below 1e-5 A); users of the list test
-// r < rc in FP64 themselves.  Rows go out unsorted, row-major, to tmp; the
-// finishing kernel sorts them and writes the column-major list.
-// Dynamic LDS: 64 * bmax float4.
-constexpr int SB_OWN = 64;  // own atoms per pass (four lanes each)
+// Block barrier for LDS traffic only: the fences are restricted to LDS, so
+// the barrier waits for this wave's LDS accesses but not for its global
+// loads and stores.
+__device__ __forceinline__ void block_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
-__global__ void __launch_bounds__(BLOCK)
-    k_build_md_sb(Grid g, int nsx, int nsy, const int32_t *__restrict__ bcount,
-                  const double4 *__restrict__ bpos, int bmax, float cut2f, int32_t *tmp,
-                  int32_t *tcnt, const int *cond) {
-  if (cond && *cond == 0) return;
-  extern __shared__ float4 cand[];
-  __shared__ int cnt[64], off[65], gbin[64];
-  __shared__ double shx[64], shy[64], shz[64];
-  __shared__ int rowlen[SB_OWN];
-  __shared__ int32_t hit[SB_OWN * KMAX];
-  __shared__ int own_bins[8], n_own_bins;
-  const int tid = threadIdx.x;
-  const int64_t sb = xcd_block();
-  const int sx = (int)(sb % nsx), sy = (int)((sb / nsx) % nsy), sz = (int)(sb / ((int64_t)nsx * nsy));
-  const double bw0 = g.L0 / g.n0, bw1 = g.L1 / g.n1, bw2 = g.L2 / g.n2;
-  // origin of the super-bin
-  const double o0 = (2 * sx) * bw0, o1 = (2 * sy) * bw1, o2 = (2 * sz) * bw2;
-  if (tid < 64) {
-    const int ux = tid & 3, uy = (tid >> 2) & 3, uz = tid >> 4;
-    int gx = 2 * sx - 1 + ux, gy = 2 * sy - 1 + uy, gz = 2 * sz - 1 + uz;
-    double hx = 0.0, hy = 0.0, hz = 0.0;  // image shift
-    if (gx < 0) { gx += g.n0; hx = -g.L0; } else if (gx >= g.n0) { gx -= g.n0; hx = g.L0; }
-    if (gy < 0) { gy += g.n1; hy = -g.L1; } else if (gy >= g.n1) { gy -= g.n1; hy = g.L1; }
-    if (gz < 0) { gz += g.n2; hz = -g.L2; } else if (gz >= g.n2) { gz -= g.n2; hz = g.L2; }
-    const int b = gx + g.n0 * (gy + g.n1 * gz);
-    gbin[tid] = b;
-    shx[tid] = hx;
-    shy[tid] = hy;
-    shz[tid] = hz;
-    cnt[tid] = min(bcount[b], bmax);
-  }
-  if (tid == 0) {
-    // own bins: local coordinates 1..2 that exist on the grid
-    int k = 0;
-    for (int uz = 1; uz <= 2; ++uz)
-      for (int uy = 1; uy <= 2; ++uy)
-        for (int ux = 1; ux <= 2; ++ux)
-          if (2 * sx + ux - 1 < g.n0 && 2 * sy + uy - 1 < g.n1 && 2 * sz + uz - 1 < g.n2)
-            own_bins[k++] = ux + 4 * (uy + 4 * uz);
-    n_own_bins = k;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    off[0] = 0;
-    for (int u = 0; u < 64; ++u) off[u + 1] = off[u] + cnt[u];
-  }
-  __syncthreads();
-  // stage every slot of the 64 bins: (x, y, z) relative to the origin, index in w
-  for (int q = tid; q < 64 * bmax; q += BLOCK) {
-    const int u = q / bmax, t = q - u * bmax;
-    if (t < cnt[u]) {
-      const double4 p = bpos[(int64_t)gbin[u] * bmax + t];
-      cand[off[u] + t] = make_float4((float)(p.x + shx[u] - o0), (float)(p.y + shy[u] - o1),
-                                     (float)(p.z + shz[u] - o2), __int_as_float((int32_t)p.w));
+// Exclusive scans over the block of two per-thread values (one value per
+// thread; BLOCK / 64 waves); returns the block totals.  Contains barriers:
+// every thread of the block calls it.
+__device__ __forceinline__ int2 block_scan2(int &a, int &b, int2 *wtot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int va = a, vb = b;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int ta = __shfl_up(va, d), tb = __shfl_up(vb, d);
+    if (lane >= d) {
+      va += ta;
+      vb += tb;
     }
   }
-  int n_own = 0;
-  for (int k = 0; k < n_own_bins; ++k) n_own += cnt[own_bins[k]];
-  __syncthreads();
-  for (int base = 0; base < n_own; base += SB_OWN) {
-    const int a = tid >> 2, l = tid & 3;
-    // own atom base + a: its bin and staged index
-    int ob = -1, si = -1;
-    {
-      int q = base + a;
-      for (int k = 0; k < n_own_bins && q >= 0; ++k) {
-        const int u = own_bins[k];
-        if (q < cnt[u]) {
-          ob = u;
-          si = off[u] + q;
-          q = -1;
-        } else {
-          q -= cnt[u];
+  if (lane == 63) wtot[wv] = make_int2(va, vb);
+  block_sync_lds();
+  int ba = 0, bb = 0, sa = 0, sb = 0;
+#pragma unroll
+  for (int q = 0; q < BLOCK / 64; ++q) {
+    const int2 t = wtot[q];
+    if (q < wv) {
+      ba += t.x;
+      bb += t.y;
+    }
+    sa += t.x;
+    sb += t.y;
+  }
+  a = ba + va - a;
+  b = bb + vb - b;
+  block_sync_lds();  // wtot may be written again after this
+  return make_int2(sa, sb);
+}
+
+// r < rc + skin list by regions of 4 x 4 x RZ search bins (every axis needs at
+// least four bins).  For each of its regions a block stages the 6 x 6 x
+// (RZ + 2) bins around it in LDS: positions relative to the region origin in
+// float, periodic images resolved, each bin's atoms contiguous.  One lane per
+// own atom then walks the atom's 27 neighbouring bins (nine runs of three
+// staged bins consecutive in x) and appends its hits to its row, row-major
+// and unsorted (k_md_finish sorts them); own atoms also record their
+// positions of this build.  The float test uses cut2f = (cut + 1e-3)^2, a
+// superset of r < cut (the float rounding of the relative coordinates stays
+// below 1e-4 A); users of the list test r < rc in FP64 themselves.
+// Grid-stride: the blocks on XCD x (blockIdx mod 8 == x; the grid is a
+// multiple of 8) take the x-th eighth of the regions, so neighbouring regions
+// share that XCD's L2.  BMAX is the bin capacity.
+// cond (may be NULL): run only when *cond != 0 (and count the rebuild).
+constexpr int RG_X = 4, RG_Y = 4;  // own bins of a region along x and y
+constexpr int RG_GRID = 2048;      // blocks of a region launch (at most)
+
+template <int BMAX, int RZ>
+__global__ void __launch_bounds__(BLOCK)
+    k_md_search(Grid g, int nrx, int nry, int64_t nreg, const int32_t *__restrict__ bcount,
+                const double4 *__restrict__ bpos, float cut2f, int32_t *rows, uint8_t *cnt,
+                double *xr, double *yr, double *zr, DevState *ds, const int *cond) {
+  constexpr int SX = RG_X + 2, SY = RG_Y + 2, SZ = RZ + 2, NST = SX * SY * SZ;
+  constexpr int OWN_CAP = RG_X * RG_Y * RZ * BMAX;
+  static_assert(NST <= BLOCK && NST <= 256, "one thread per staged bin, bin ids in a byte");
+  if (cond && *cond == 0) return;
+  if (cond && blockIdx.x == 0 && threadIdx.x == 0) ds->md_rebuilds += 1ull;
+  __shared__ float4 cand[NST * BMAX];
+  __shared__ int off[NST + 1];
+  __shared__ int gbin[NST];
+  __shared__ double3 shift[NST];
+  __shared__ int own_si[OWN_CAP];          // staged index of own atom q
+  __shared__ unsigned char own_b[OWN_CAP];  // staged bin of own atom q
+  __shared__ int own_off[NST];
+  __shared__ int2 wtot[BLOCK / 64];
+  const int tid = threadIdx.x;
+  const int xcd = (int)(blockIdx.x & 7u);
+  const int64_t per_xcd = gridDim.x >> 3;
+  const int64_t lo = nreg * xcd / 8, hi = nreg * (xcd + 1) / 8;
+  const double bw0 = g.L0 / g.n0, bw1 = g.L1 / g.n1, bw2 = g.L2 / g.n2;
+  long long pairs = 0;
+  int kmx = 0;
+  bool ovf = false;
+  for (int64_t rg = lo + (int64_t)(blockIdx.x >> 3); rg < hi; rg += per_xcd) {
+    const int rx = (int)(rg % nrx), ry = (int)((rg / nrx) % nry),
+              rz = (int)(rg / ((int64_t)nrx * nry));
+    const double o0 = (RG_X * rx) * bw0, o1 = (RG_Y * ry) * bw1, o2 = (RZ * rz) * bw2;
+    // staged bin tid: global bin, image shift, occupancy, own or not
+    int cn = 0, ocn = 0;
+    if (tid < NST) {
+      const int ux = tid % SX, uy = (tid / SX) % SY, uz = tid / (SX * SY);
+      int gx = RG_X * rx - 1 + ux, gy = RG_Y * ry - 1 + uy, gz = RZ * rz - 1 + uz;
+      const bool own = ux >= 1 && ux <= RG_X && uy >= 1 && uy <= RG_Y && uz >= 1 && uz <= RZ &&
+                       gx < g.n0 && gy < g.n1 && gz < g.n2;
+      double hx = 0.0, hy = 0.0, hz = 0.0;
+      if (gx < 0) { gx += g.n0; hx = -g.L0; } else if (gx >= g.n0) { gx -= g.n0; hx = g.L0; }
+      if (gy < 0) { gy += g.n1; hy = -g.L1; } else if (gy >= g.n1) { gy -= g.n1; hy = g.L1; }
+      if (gz < 0) { gz += g.n2; hz = -g.L2; } else if (gz >= g.n2) { gz -= g.n2; hz = g.L2; }
+      const int b = gx + g.n0 * (gy + g.n1 * gz);
+      cn = min(bcount[b], BMAX);
+      ocn = own ? cn : 0;
+      gbin[tid] = b;
+      shift[tid] = make_double3(hx, hy, hz);
+    }
+    block_sync_lds();  // the previous region's readers of off / cand are done
+    int os = cn, oo = ocn;
+    const int2 tot = block_scan2(os, oo, wtot);
+    if (tid < NST) {
+      off[tid] = os;
+      own_off[tid] = oo;
+    }
+    if (tid == 0) off[NST] = tot.x;
+    block_sync_lds();
+    // stage: staged atom c of bin u (off[u] <= c < off[u + 1]); four in flight
+    for (int c0 = 0; c0 < tot.x; c0 += 4 * BLOCK) {
+      double4 p[4];
+      int uu[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = c0 + k * BLOCK + tid;
+        uu[k] = -1;
+        if (c < tot.x) {
+          int lo_u = 0, hi_u = NST;  // off[lo_u] <= c < off[hi_u]
+          while (hi_u - lo_u > 1) {
+            const int mid = (lo_u + hi_u) >> 1;
+            if (off[mid] <= c) lo_u = mid; else hi_u = mid;
+          }
+          uu[k] = lo_u;
+          p[k] = bpos[(int64_t)gbin[lo_u] * BMAX + (c - off[lo_u])];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int u = uu[k];
+        if (u >= 0) {
+          const int c = c0 + k * BLOCK + tid;
+          const double3 h = shift[u];
+          cand[c] = make_float4((float)(p[k].x + h.x - o0), (float)(p[k].y + h.y - o1),
+                                (float)(p[k].z + h.z - o2), __int_as_float((int32_t)p[k].w));
+          const int ub = u % SX, vb = (u / SX) % SY, wb = u / (SX * SY);
+          if (ub >= 1 && ub <= RG_X && vb >= 1 && vb <= RG_Y && wb >= 1 && wb <= RZ &&
+              own_off[u] < (u + 1 < NST ? own_off[u + 1] : tot.y)) {
+            const int q = own_off[u] + (c - off[u]);
+            own_si[q] = c;
+            own_b[q] = (unsigned char)u;
+            const int32_t i = (int32_t)p[k].w;
+            xr[i] = p[k].x;
+            yr[i] = p[k].y;
+            zr[i] = p[k].z;
+          }
         }
       }
     }
-    if (l == 0) rowlen[a] = 0;
-    __syncthreads();
-    if (si >= 0) {
+    block_sync_lds();
+    // search: one lane per own atom
+    for (int q = tid; q < tot.y; q += BLOCK) {
+      const int si = own_si[q], u = own_b[q];
       const float4 me = cand[si];
-      const int lx = ob & 3, ly = (ob >> 2) & 3, lz = ob >> 4;
-      int phase = l;
+      const int32_t i = __float_as_int(me.w);
+      const int lx = u % SX, ly = (u / SX) % SY, lz = u / (SX * SY);
+      int32_t *row = rows + (int64_t)i * KMAX;
+      int c = 0;
       for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy) {
-          const int u0 = (lx - 1) + 4 * ((ly + dy) + 4 * (lz + dz));
-          const int a0 = off[u0], len = off[u0 + 3] - a0;
-          int t = phase;
-          for (; t < len; t += 4) {
-            const int ci = a0 + t;
-            if (ci == si) continue;
-            const float4 c = cand[ci];
-            const float dx = c.x - me.x, dyy = c.y - me.y, dzz = c.z - me.z;
-            if (dx * dx + dyy * dyy + dzz * dzz < cut2f) {
-              const int pos = atomicAdd(&rowlen[a], 1);
-              if (pos < KMAX) hit[a * KMAX + pos] = __float_as_int(c.w);
+          const int u0 = (lx - 1) + SX * ((ly + dy) + SY * (lz + dz));
+          const int a1 = off[u0 + 3];
+          for (int k = off[u0]; k < a1; ++k) {
+            const float4 cc = cand[k];
+            const float dx = cc.x - me.x, dyy = cc.y - me.y, dzz = cc.z - me.z;
+            if (dx * dx + dyy * dyy + dzz * dzz < cut2f && k != si) {
+              if (c < KMAX) row[c] = __float_as_int(cc.w);
+              ++c;
             }
           }
-          phase = t - len;
         }
+      cnt[i] = (uint8_t)(c < KMAX ? c : KMAX);
+      pairs += c < KMAX ? c : KMAX;
+      kmx = c > kmx ? c : kmx;
+      ovf = ovf || c > KMAX;
     }
-    __syncthreads();
-    if (si >= 0) {
-      const int32_t i = __float_as_int(cand[si].w);
-      const int len = rowlen[a];
-      const int c = len < KMAX ? len : KMAX;
-      for (int k = l; k < c; k += 4) tmp[(int64_t)i * KMAX + k] = hit[a * KMAX + k];
-      if (l == 0) tcnt[i] = len;
-    }
-    __syncthreads();
   }
+  md_row_stats(pairs, kmx < KMAX ? kmx : KMAX, ovf, ds);
 }
 
-// Sorts the rows of tmp (row-major, unsorted, tcnt entries) by a fixed
-// bitonic network, writes them column-major, and keeps the positions of this
-// build.  One lane per atom.
+// The rows written by the search, sorted (ascending neighbour index) in place
+// (row-major [i * KMAX + k]) and copied column-major [k * n + i] for the
+// lane-per-atom MD passes.  A block handles TR_ATOMS consecutive rows per
+// step through LDS: contiguous 16-byte reads, every entry placed at its rank
+// among its row's entries (four lanes per row), then contiguous writes of
+// both layouts.  Entries at or past a row's length are not written.
+// Grid-stride; cond (may be NULL): run only when *cond != 0.
+constexpr int TR_ATOMS = 64;
+constexpr int FIN_GRID = 4096;
+
 __global__ void __launch_bounds__(BLOCK)
-    k_md_rows_finish(int64_t n, const int32_t *__restrict__ tmp, const int32_t *__restrict__ tcnt,
-                     const double *__restrict__ x, const double *__restrict__ y,
-                     const double *__restrict__ z, int32_t *nj, uint8_t *cnt, double *xr,
-                     double *yr, double *zr, DevState *ds, const int *cond) {
+    k_md_finish(int64_t n, int32_t *rows, const uint8_t *__restrict__ cnt, int32_t *nj,
+                const int *cond) {
   if (cond && *cond == 0) return;
-  const int64_t i = xcd_block() * BLOCK + threadIdx.x;
-  if (i >= n) return;
-  int c = tcnt[i];
-  if (c > KMAX) {
-    atomicOr(&ds->overflow, 1);
-    c = KMAX;
-  }
-  int32_t v[KMAX];
+  __shared__ int32_t tile[TR_ATOMS][KMAX + 1], srt[TR_ATOMS][KMAX + 1];
+  __shared__ int m_s[TR_ATOMS];
+  const int tid = threadIdx.x;
+  constexpr int PARTS = KMAX / 4;  // int4 per row
+  for (int64_t a0 = (int64_t)blockIdx.x * TR_ATOMS; a0 < n;
+       a0 += (int64_t)gridDim.x * TR_ATOMS) {
 #pragma unroll
-  for (int u = 0; u < KMAX; ++u) v[u] = u < c ? tmp[i * KMAX + u] : INT32_MAX;
-#pragma unroll
-  for (int k = 2; k <= KMAX; k <<= 1) {
-#pragma unroll
-    for (int h = k >> 1; h > 0; h >>= 1) {
-#pragma unroll
-      for (int a = 0; a < KMAX; ++a) {
-        const int b = a ^ h;
-        if (b > a) {
-          const int32_t lo = min(v[a], v[b]), hi = max(v[a], v[b]);
-          const bool up = (a & k) == 0;
-          v[a] = up ? lo : hi;
-          v[b] = up ? hi : lo;
-        }
+    for (int r = 0; r < TR_ATOMS * PARTS / BLOCK; ++r) {
+      const int q = r * BLOCK + tid, a = q / PARTS, pt = q - a * PARTS;
+      if (a0 + a < n) {
+        const int4 v = ((const int4 *)(rows + (a0 + a) * KMAX))[pt];
+        tile[a][4 * pt + 0] = v.x;
+        tile[a][4 * pt + 1] = v.y;
+        tile[a][4 * pt + 2] = v.z;
+        tile[a][4 * pt + 3] = v.w;
       }
     }
-  }
+    if (tid < TR_ATOMS) m_s[tid] = a0 + tid < n ? cnt[a0 + tid] : 0;
+    block_sync_lds();
+    {  // ranks: four lanes per row (entries are distinct neighbour indices)
+      const int a = tid >> 2, l = tid & 3, m = m_s[a];
+      for (int e = l; e < m; e += 4) {
+        const int32_t v = tile[a][e];
+        int rank = 0;
+        for (int f = 0; f < m; ++f) rank += tile[a][f] < v ? 1 : 0;
+        srt[a][rank] = v;
+      }
+    }
+    block_sync_lds();
 #pragma unroll
-  for (int u = 0; u < KMAX; ++u)
-    if (u < c) nj[(int64_t)u * n + i] = v[u];
-  cnt[i] = (uint8_t)c;
-  xr[i] = x[i];
-  yr[i] = y[i];
-  zr[i] = z[i];
+    for (int r = 0; r < TR_ATOMS * PARTS / BLOCK; ++r) {
+      const int q = r * BLOCK + tid, a = q / PARTS, pt = q - a * PARTS;
+      if (a0 + a < n && 4 * pt < m_s[a])
+        ((int4 *)(rows + (a0 + a) * KMAX))[pt] =
+            make_int4(srt[a][4 * pt], srt[a][4 * pt + 1], srt[a][4 * pt + 2], srt[a][4 * pt + 3]);
+    }
+    {
+      const int a = tid % TR_ATOMS;
+#pragma unroll
+      for (int r = 0; r < KMAX * TR_ATOMS / BLOCK; ++r) {
+        const int k = r * (BLOCK / TR_ATOMS) + tid / TR_ATOMS;
+        if (k < m_s[a]) nj[(int64_t)k * n + a0 + a] = srt[a][k];
+      }
+    }
+    block_sync_lds();  // tile / srt / m_s are written again next step
+  }
 }
+static_assert(TR_ATOMS * (KMAX / 4) % BLOCK == 0 && KMAX * TR_ATOMS % BLOCK == 0 &&
+                  TR_ATOMS * 4 == BLOCK,
+              "whole rounds of the finishing pass");
 
-// the list build from filled search bins (super-bins when every axis has at
-// least four bins and the staged bins fit in LDS, else one lane per atom)
+// the list build from filled search bins (regions when every axis has at
+// least four bins and a bin holds at most 32 atoms, else one lane per atom),
+// then the sorted row-major and column-major rows
 hipError_t launch_md_build_chain(vcsgc_ctx *c, const Grid &g, const int *cond) {
   const RepHost &r = c->reps[0];
   const double cut = c->pot.rc + c->skin;
-  if (g.n0 >= 4 && g.n1 >= 4 && g.n2 >= 4 && c->bmax <= 32) {
-    const int nsx = (g.n0 + 1) / 2, nsy = (g.n1 + 1) / 2, nsz = (g.n2 + 1) / 2;
+  if (g.n0 >= 4 && g.n1 >= 4 && g.n2 >= 4 && (c->bmax == 16 || c->bmax == 32)) {
     const float cf = (float)(cut + 1e-3);
-    const size_t lds = sizeof(float4) * 64 * (size_t)c->bmax;
-    k_build_md_sb<<<(unsigned)((int64_t)nsx * nsy * nsz), BLOCK, lds, c->stream>>>(
-        g, nsx, nsy, c->bin_count, c->bin_pos, c->bmax, cf * cf, c->md_tmp, c->md_tcnt, cond);
-    k_md_rows_finish<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->md_tmp, c->md_tcnt, c->x,
-                                                              c->y, c->z, c->md_j, c->md_cnt,
-                                                              c->xr, c->yr, c->zr, c->ds, cond);
+    const int nrx = (g.n0 + RG_X - 1) / RG_X, nry = (g.n1 + RG_Y - 1) / RG_Y;
+    const int rz = c->bmax == 16 ? 2 : 1;
+    const int nrz = (g.n2 + rz - 1) / rz;
+    const int64_t nreg = (int64_t)nrx * nry * nrz;
+    const unsigned G = (unsigned)std::min<int64_t>((nreg + 7) / 8 * 8, RG_GRID);
+    if (c->bmax == 16)
+      k_md_search<16, 2><<<G, BLOCK, 0, c->stream>>>(g, nrx, nry, nreg, c->bin_count, c->bin_pos,
+                                                     cf * cf, c->md_rows, c->md_cnt, c->xr,
+                                                     c->yr, c->zr, c->ds, cond);
+    else
+      k_md_search<32, 1><<<G, BLOCK, 0, c->stream>>>(g, nrx, nry, nreg, c->bin_count, c->bin_pos,
+                                                     cf * cf, c->md_rows, c->md_cnt, c->xr,
+                                                     c->yr, c->zr, c->ds, cond);
   } else {
     k_build_md<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bin_count,
-                                                       c->bin_pos, c->bmax, cut * cut, c->md_j,
-                                                       c->md_cnt, c->xr, c->yr, c->zr, c->ds,
-                                                       cond);
+                                                       c->bin_pos, c->bmax, cut * cut,
+                                                       c->md_rows, c->md_cnt, c->xr, c->yr,
+                                                       c->zr, c->ds, cond);
   }
+  const unsigned GF = (unsigned)std::min<int64_t>((r.n + TR_ATOMS - 1) / TR_ATOMS, FIN_GRID);
+  k_md_finish<<<GF, BLOCK, 0, c->stream>>>(r.n, c->md_rows, c->md_cnt, c->md_j, cond);
   return hipGetLastError();
 }
 
-// r < rc + skin list (single-system contexts)
+// r < rc + skin list (single-system contexts), from bins already filled
 hipError_t launch_build_md_list(vcsgc_ctx *c) {
   const RepHost &r = c->reps[0];
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
@@ -692,32 +816,25 @@ hipError_t launch_build_md_list(vcsgc_ctx *c) {
   int h = tstart(c, VCSGC_KT_BUILD);
   e = launch_md_build_chain(c, g, nullptr);
   tstop(c, h);
-  if (e != hipSuccess) return e;
-  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_md,
-                                            nullptr);
-  return hipGetLastError();
+  return e;
 }
 
-// MD list rebuild decided on the device: every kernel of the chain returns
-// at once unless the last drift raised ds->rebuild.
-// Overflows are flagged as in the host-decided path; the caller checks them
-// once at the end of its steps.
-hipError_t launch_md_rebuild_cond(vcsgc_ctx *c) {
+// MD list rebuild decided on the device, for step parity par: every kernel
+// returns at once unless the last drift raised ds->rebuild[par].  The bin
+// counts were cleared by that drift.  Overflows are flagged as in the
+// host-decided path; the caller checks them once at the end of its steps.
+constexpr int BIN_GRID = 2048;  // blocks of a device-decided binning (at most)
+
+hipError_t launch_md_rebuild_cond(vcsgc_ctx *c, int par) {
   const RepHost &r = c->reps[0];
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
-  const int *cond = &c->ds->rebuild;
+  const int *cond = &c->ds->rebuild[par];
   int h = tstart(c, VCSGC_KT_BUILD);
-  k_bins_clear_cond<<<grid_for(r.nbins), BLOCK, 0, c->stream>>>(r.nbins, c->bin_count, c->ds);
-  k_bin_search<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bmax,
-                                                       c->bin_count, c->bin_atoms, c->bin_pos,
-                                                       c->ds, cond);
+  k_bin_search<<<std::min(grid_for(r.n), BIN_GRID), BLOCK, 0, c->stream>>>(
+      r.n, c->x, c->y, c->z, g, c->bmax, c->bin_count, c->bin_atoms, c->bin_pos, c->ds, cond);
   hipError_t e = launch_md_build_chain(c, g, cond);
-  if (e != hipSuccess) return e;
-  k_row_stats<<<512, BLOCK, 0, c->stream>>>(c->n, c->md_cnt, &c->ds->pairs_md, &c->ds->kmax_md,
-                                            cond);
-  k_rebuild_done<<<1, 64, 0, c->stream>>>(c->ds);
   tstop(c, h);
-  return hipGetLastError();
+  return e;
 }
 
 bool md_rebuild_on_device(const vcsgc_ctx *c) { return c->bin_pos != nullptr; }
@@ -739,7 +856,7 @@ __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
   rho[i] = s;
 }
 
-// The r < rc rows taken from a valid r < rc + skin list (MD rows, column-major,
+// The r < rc rows taken from a valid r < rc + skin list (MD rows, row-major,
 // ascending j): same entries, same order and the same dd, g values as a build
 // from the search bins, since r is evaluated by the same expression (the
 // packed positions are current whenever the MD list and its densities are).  A group
@@ -749,7 +866,7 @@ __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
 constexpr int MFM_G = 16;
 
 __global__ void __launch_bounds__(BLOCK)
-    k_mc_from_md(int64_t n, const double4 *__restrict__ ps4, Grid g, const int32_t *__restrict__ mdj,
+    k_mc_from_md(int64_t n, const double4 *__restrict__ ps4, Grid g, const int32_t *__restrict__ mdr,
                  const uint8_t *__restrict__ mdcnt, PotD p, int32_t *nj, double *ndd, double *ng,
                  uint8_t *cnt) {
   const int64_t gid = xcd_block() * BLOCK + threadIdx.x;
@@ -766,7 +883,7 @@ __global__ void __launch_bounds__(BLOCK)
     int32_t j = 0;
     double r = 0.0;
     if (k < m) {
-      j = mdj[(int64_t)k * n + i];
+      j = mdr[i * KMAX + k];
       const double4 qj = ps4[j];
       const double dx = min_image(qj.x - qi.x, g.L0);
       const double dy = min_image(qj.y - qi.y, g.L1);
@@ -792,7 +909,7 @@ hipError_t launch_mc_from_md(vcsgc_ctx *c) {
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   int h = tstart(c, VCSGC_KT_BUILD);
   k_mc_from_md<<<grid_for(c->n * MFM_G), BLOCK, 0, c->stream>>>(
-      c->n, c->ps4, g, c->md_j, c->md_cnt, c->pot, c->mc_j, c->mc_dd, c->mc_g,
+      c->n, c->ps4, g, c->md_rows, c->md_cnt, c->pot, c->mc_j, c->mc_dd, c->mc_g,
       c->mc_cnt);
   tstop(c, h);
   return hipGetLastError();

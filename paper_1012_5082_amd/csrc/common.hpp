@@ -64,7 +64,7 @@ struct DevState {
   int overflow;   // a neighbour row exceeded KMAX
   int bin_overflow;  // a search bin exceeded its capacity
   int bad_input;  // position outside the box / species not in {0,1}
-  int rebuild;    // MD: an atom moved more than skin/2
+  int rebuild[2];  // MD: an atom moved more than skin/2 (by the parity of the step)
   int kmax_used;  // longest row of the current r < rc list
   int kmax_md;    // longest row of the current r < rc + skin list
   unsigned long long pairs_mc, pairs_md;  // entries of the last r < rc / r < rc + skin lists
@@ -241,7 +241,6 @@ struct vcsgc_ctx {
   int bmax = 16;
   int32_t *bin_count = nullptr, *bin_atoms = nullptr;
   double4 *bin_pos = nullptr;  // (x, y, z, index) per bin slot (single-system contexts)
-  int32_t *md_tmp = nullptr, *md_tcnt = nullptr;  // unsorted MD rows (row-major) and lengths
   int32_t *sites = nullptr;  // trial sites of one sweep, S x (cells / 8) (single-system)
   double *site_lnu = nullptr;  // ln u of those trials
   double *stage_lnug = nullptr;  // ln u_g of the sweep's stages
@@ -267,8 +266,11 @@ struct vcsgc_ctx {
   int64_t smp_cap = 0, smp_stride = 1;
   double *dalog = nullptr;
   int64_t dacap = 0;
-  // r < rc + skin list for MD, and positions at its build
-  int32_t *md_j = nullptr;
+  // r < rc + skin list for MD, ascending neighbour index: column-major
+  // [k * n + i] for the lane-per-atom MD passes, and the same rows row-major
+  // [i * KMAX + k] in md_rows for the group-per-atom MC-list refresh; and
+  // positions at its build
+  int32_t *md_j = nullptr, *md_rows = nullptr;
   uint8_t *md_cnt = nullptr;
   double *xr = nullptr, *yr = nullptr, *zr = nullptr;
 
@@ -354,7 +356,7 @@ hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_build_mc_list(vcsgc_ctx *c, const RepHost &r);
 hipError_t launch_build_md_list(vcsgc_ctx *c);
-hipError_t launch_md_rebuild_cond(vcsgc_ctx *c);
+hipError_t launch_md_rebuild_cond(vcsgc_ctx *c, int par);
 bool md_rebuild_on_device(const vcsgc_ctx *c);
 hipError_t launch_mc_row_stats(vcsgc_ctx *c);
 hipError_t launch_build_desc_list(vcsgc_ctx *c, const RepHost &r);
@@ -371,7 +373,7 @@ hipError_t launch_reduce_sum(vcsgc_ctx *c, const double *v, int64_t n, double *o
 hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, double T,
                          int64_t n_sweeps, uint64_t seed);
 hipError_t launch_pack(vcsgc_ctx *c);
-hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first);
+hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par);
 hipError_t launch_kick(vcsgc_ctx *c, double dt);
 hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
 // persistent sweep (persist.hip)

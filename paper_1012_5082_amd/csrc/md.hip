@@ -201,16 +201,23 @@ hipError_t launch_energy(vcsgc_ctx *c) {
 }
 
 // [v += (dt/2)(F cm) (closing the previous step) ;] v += (dt/2)(F cm);
-// x = wrap(x + dt v); flag a list rebuild when an atom has moved more than
-// skin/2 from its position at the last build
+// x = wrap(x + dt v); raise ds->rebuild[par] when an atom has moved more than
+// skin/2 from its position at the last build.  Also readies the next
+// device-decided rebuild: the flag of the other parity (read by the previous
+// step's rebuild kernels, which have finished) is cleared, and so are the
+// search-bin counts (bcount may be NULL).
 __global__ void __launch_bounds__(BLOCK)
     k_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
                  const double *__restrict__ fx, const double *__restrict__ fy,
                  const double *__restrict__ fz, const uint8_t *__restrict__ sp,
                  const double *__restrict__ xr, const double *__restrict__ yr,
                  const double *__restrict__ zr, double4 *ps4, Box b, PotD p, double dt,
-                 double half_skin2, int kick_first, DevState *ds) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                 double half_skin2, int kick_first, int par, int32_t *bcount, int64_t nbins,
+                 DevState *ds) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bcount)
+    for (int64_t q = i; q < nbins; q += (int64_t)gridDim.x * blockDim.x) bcount[q] = 0;
+  if (i == 0) ds->rebuild[par ^ 1] = 0;
   if (i >= n) return;
   const int s = sp[i];
   const double cm = p.cm[s];
@@ -238,7 +245,8 @@ __global__ void __launch_bounds__(BLOCK)
   const double ex = min_image(nx - xr[i], b.L0);
   const double ey = min_image(ny - yr[i], b.L1);
   const double ez = min_image(nz - zr[i], b.L2);
-  if ((ex * ex + ey * ey) + ez * ez > half_skin2) atomicOr(&ds->rebuild, 1);
+  const unsigned long long moved = __ballot((ex * ex + ey * ey) + ez * ez > half_skin2);
+  if (moved && __lane_id() == __ffsll((long long)moved) - 1) atomicOr(&ds->rebuild[par], 1);
 }
 
 __global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, const double *__restrict__ fx,
@@ -253,13 +261,14 @@ __global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, const doub
   vz[i] = vz[i] + hdt * (fz[i] * cm);
 }
 
-hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first) {
+hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par) {
   Box b{c->box[0], c->box[1], c->box[2]};
   const double hs = 0.5 * c->skin;
   int h = tstart(c, VCSGC_KT_KICKDRIFT);
   k_kick_drift<<<grid_for(c->n), BLOCK, 0, c->stream>>>(
       c->n, c->x, c->y, c->z, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz, c->sp, c->xr, c->yr,
-      c->zr, c->ps4, b, c->pot, dt, hs * hs, kick_first ? 1 : 0, c->ds);
+      c->zr, c->ps4, b, c->pot, dt, hs * hs, kick_first ? 1 : 0, par, c->bin_count,
+      c->reps[0].nbins, c->ds);
   tstop(c, h);
   return hipGetLastError();
 }

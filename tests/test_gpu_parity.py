@@ -363,6 +363,84 @@ def test_md_parity(torch_cuda, oracle_mod):
     g.close()
 
 
+@pytest.mark.parametrize("n,skin", [(6, 0.75), (7, 0.3)])
+def test_md_parity_build_paths(torch_cuda, oracle_mod, n, skin):
+    """MD lists from both builders: a 6^3 box with a 0.75 A skin has three
+    search bins per axis (one lane per atom), a 7^3 box with the default skin
+    five (super-bins, odd count: the last super-bin is half empty).
+    Device-decided rebuilds happen in the 60 steps at 1000 K; positions,
+    velocities and forces stay bit for bit those of the oracle, and the
+    list statistics equal a fresh build at the final positions."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = _md_system(n=n, T=1000.0, seed=53 + n)
+    g = gpu_context(d, pot, velocities=True, skin=skin)
+    g.md(1.0, 60)
+    out = O.md(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"], d["species"], d["box"], pot,
+               1.0, 60)
+    names = ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz")
+    for nm, want in zip(names, out[:9]):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), want), nm
+    info = g.info()
+    assert info["md_rebuilds"] >= 1
+    x, y, z = out[0], out[1], out[2]
+    nl = O.neighbors(x, y, z, d["box"], pot.rc, vectors=False)
+    g.sweep(d["dmu0"], 0.0, d["cbar"], d["T"], 0, d["seed"])  # refreshes the r < rc list
+    assert g.info()["mc_pairs"] == nl.j.size
+    g.close()
+
+
+@pytest.mark.parametrize("path", ["pipeline", "da_perfect", "chain3", "persistent"])
+def test_sweep_paths_after_md(torch_cuda, oracle_mod, path):
+    """Sweeps right after MD run on the r < rc list filtered out of the MD
+    rows and on the last MD density pass: every sweep kernel family (fused
+    pipeline, delayed acceptance with a perfect surrogate, local chains with
+    their undo log, the persistent kernel) gives the oracle's chain bit for
+    bit, velocities included."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = _md_system(n=16, c=0.1, seed=47)
+    kappa, n_sw, k = 1.0, 2, 3 if path == "chain3" else 1
+    x, y, z, vx, vy, vz, *_ = O.md(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                                   d["species"], d["box"], pot, 1.0, 20)
+    g = gpu_context(d, pot, velocities=True)
+    g.md(1.0, 20)
+    if path == "da_perfect":
+        g.set_surrogate("perfect")
+    elif path == "chain3":
+        g.set_local_steps(k)
+    elif path == "persistent":
+        g.set_tuning("graph", 1)
+    nl = O.neighbors(x, y, z, d["box"], pot.rc, vectors=False)
+    assert np.array_equal(g.rho().cpu().numpy(), O.density(nl, d["species"], pot))
+    info = g.info()
+    S = info["stages_per_sweep"]
+    ncpc = int(np.prod(info["n_cells"])) // 8
+    assert info["mc_pairs"] == nl.j.size
+    log = path in ("pipeline", "chain3")
+    if log:
+        g.enable_log(n_sw * S * ncpc * k, n_sw * S)
+    sg = g.sweep(d["dmu0"], kappa, d["cbar"], d["T"], n_sw, d["seed"])
+    st = O.SweepState(x, y, z, d["box"], d["species"], pot, vx=vx, vy=vy, vz=vz)
+    over = None
+    if log:
+        tl_g, sl_g, _, _ = g.logs()
+        over = tie_overrides(tl_g, sl_g)
+    so, tl_o, sl_o = O.sweep(st, d["dmu0"], kappa, d["cbar"], d["T"], n_sw, d["seed"],
+                             log_trials=10 ** 8 if log else 0, log_stages=10 ** 8 if log else 0,
+                             overrides=over, local_steps=k)
+    if log:
+        compare_logs(tl_g, sl_g, tl_o, sl_o)
+    for key in ("trials", "local_accepts", "stages", "stage_accepts", "flips", "n_final"):
+        assert sg[key] == so[key], key
+    assert sg["flips"] > 0
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    for nm in ("vx", "vy", "vz"):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), getattr(st, nm)), nm
+    g.close()
+
+
 def test_hybrid_cycle_parity(torch_cuda, oracle_mod):
     """[1 sweep; 20 MD steps] x 3 with velocity rescaling on transmutation."""
     O = oracle_mod
