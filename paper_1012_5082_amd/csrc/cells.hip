@@ -691,12 +691,18 @@ __global__ void __launch_bounds__(BLOCK)
         for (int dy = -1; dy <= 1; ++dy) {
           const int u0 = (lx - 1) + SX * ((ly + dy) + SY * (lz + dz));
           const int a1 = off[u0 + 3];
-          for (int k = off[u0]; k < a1; ++k) {
-            const float4 cc = cand[k];
-            const float dx = cc.x - me.x, dyy = cc.y - me.y, dzz = cc.z - me.z;
-            if (dx * dx + dyy * dyy + dzz * dzz < cut2f && k != si) {
-              if (c < KMAX) row[c] = __float_as_int(cc.w);
-              ++c;
+          // four candidates in flight (reads clamped to the run's last one)
+          for (int k0 = off[u0]; k0 < a1; k0 += 4) {
+            float4 cc[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cc[v] = cand[min(k0 + v, a1 - 1)];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float dx = cc[v].x - me.x, dyy = cc[v].y - me.y, dzz = cc[v].z - me.z;
+              if (k0 + v < a1 && dx * dx + dyy * dyy + dzz * dzz < cut2f && k0 + v != si) {
+                if (c < KMAX) row[c] = __float_as_int(cc[v].w);
+                ++c;
+              }
             }
           }
         }
