@@ -748,12 +748,14 @@ __global__ void __launch_bounds__(BLOCK)
     }
     if (tid < TR_ATOMS) m_s[tid] = a0 + tid < n ? cnt[a0 + tid] : 0;
     block_sync_lds();
-    {  // ranks: four lanes per row (entries are distinct neighbour indices)
+    {  // ranks: four lanes per row; entries are distinct neighbour indices,
+       // and equal ones would keep their order, so the ranks are always a
+       // permutation of 0 .. m - 1 and every written slot is filled
       const int a = tid >> 2, l = tid & 3, m = m_s[a];
       for (int e = l; e < m; e += 4) {
         const int32_t v = tile[a][e];
         int rank = 0;
-        for (int f = 0; f < m; ++f) rank += tile[a][f] < v ? 1 : 0;
+        for (int f = 0; f < m; ++f) rank += (tile[a][f] < v || (tile[a][f] == v && f < e)) ? 1 : 0;
         srt[a][rank] = v;
       }
     }
