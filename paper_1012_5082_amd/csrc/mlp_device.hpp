@@ -57,29 +57,53 @@ __device__ __forceinline__ float silu(float a) { return a / (1.0f + expf(-a)); }
 // device view of a network handle (surrogate.hip)
 MlpDev mlp_dev(const vcsgc_mlp *m);
 
+// The weights a lane of a 256-thread block needs for the hidden layers:
+// its B fragments of w1 and w2 (output neuron n = 16 wave + l % 16, rows
+// 8 (l / 16) ..) and the two biases of neuron n.  Loading them ahead of the
+// descriptors takes the weight reads off the inference's critical path.
+struct MlpFrag {
+  bf16x8 w1, w2a, w2b;
+  float b1, b2;
+};
+
+__device__ __forceinline__ MlpFrag mlp_frag(const MlpDev &m) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int kb = (lane >> 4) * 8;
+  const int n = wv * 16 + (lane & 15);
+  MlpFrag f;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    f.w1[q] = m.w1[n * MLP_KP + kb + q];
+    f.w2a[q] = m.w2[n * MLP_H + kb + q];
+    f.w2b[q] = m.w2[n * MLP_H + 32 + kb + q];
+  }
+  f.b1 = m.b1[n];
+  f.b2 = m.b2[n];
+  return f;
+}
+
 // Inference for the 16 rows of zs (LDS, [16][32] bf16, rows already filled)
 // by the 4 waves of a 256-thread block; every wave computes one 16-neuron
 // tile of each hidden layer.  Writes y[16] (normalized output) to LDS.
-// Must be called by all 256 threads.
-__device__ __forceinline__ void mlp_block16(const MlpDev &m, const __bf16 *zs, __bf16 *h1,
-                                            __bf16 *h2, float *y) {
+// w3 holds the 64 output weights (device or LDS).  Must be called by all
+// 256 threads.
+__device__ __forceinline__ void mlp_block16f(const MlpDev &m, const MlpFrag &f,
+                                             const float *w3, const __bf16 *zs, __bf16 *h1,
+                                             __bf16 *h2, float *y) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, kb = (lane >> 4) * 8;
   const int n = wv * 16 + r;  // output neuron of this lane's B column
   // layer 1
   {
-    bf16x8 a, b;
+    bf16x8 a;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      a[q] = zs[r * MLP_KP + kb + q];
-      b[q] = m.w1[n * MLP_KP + kb + q];
-    }
+    for (int q = 0; q < 8; ++q) a[q] = zs[r * MLP_KP + kb + q];
     floatx4 c = {0.f, 0.f, 0.f, 0.f};
-    c = mfma16(a, b, c);
+    c = mfma16(a, f.w1, c);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = (lane >> 4) * 4 + q;
-      h1[row * MLP_H + n] = to_bf16(silu(c[q] + m.b1[n]));
+      h1[row * MLP_H + n] = to_bf16(silu(c[q] + f.b1));
     }
   }
   __syncthreads();
@@ -88,28 +112,30 @@ __device__ __forceinline__ void mlp_block16(const MlpDev &m, const __bf16 *zs, _
     floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < MLP_H; ks += 32) {
-      bf16x8 a, b;
+      bf16x8 a;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        a[q] = h1[r * MLP_H + ks + kb + q];
-        b[q] = m.w2[n * MLP_H + ks + kb + q];
-      }
-      c = mfma16(a, b, c);
+      for (int q = 0; q < 8; ++q) a[q] = h1[r * MLP_H + ks + kb + q];
+      c = mfma16(a, ks == 0 ? f.w2a : f.w2b, c);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = (lane >> 4) * 4 + q;
-      h2[row * MLP_H + n] = to_bf16(silu(c[q] + m.b2[n]));
+      h2[row * MLP_H + n] = to_bf16(silu(c[q] + f.b2));
     }
   }
   __syncthreads();
   // output layer: 16 dot products of length 64 in ascending k
   if (threadIdx.x < 16) {
     float acc = m.b3[0];
-    for (int k = 0; k < MLP_H; ++k) acc += m.w3[k] * (float)h2[threadIdx.x * MLP_H + k];
+    for (int k = 0; k < MLP_H; ++k) acc += w3[k] * (float)h2[threadIdx.x * MLP_H + k];
     y[threadIdx.x] = acc;
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void mlp_block16(const MlpDev &m, const __bf16 *zs, __bf16 *h1,
+                                            __bf16 *h2, float *y) {
+  mlp_block16f(m, mlp_frag(m), m.w3, zs, h1, h2, y);
 }
 
 }  // namespace vc

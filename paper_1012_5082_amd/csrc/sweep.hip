@@ -13,6 +13,8 @@
 // energy changes are independent and every rho_j has at most one writer per
 // stage.
 #include <cmath>
+#include <cstring>
+#include <type_traits>
 
 #include "mlp_device.hpp"
 
@@ -236,60 +238,87 @@ __device__ __forceinline__ void descriptor_group(const SweepArgs &a, int64_t i, 
 // sums are those of descriptor_group; dU is formed from the entries with
 // r < rc exactly as delta_u_group forms it from the r < rc list (the same
 // entries in the same order, the same (rc - r)^2 and c0 + c1 r from the same
-// r), so both give the same value.  All lanes return the same values.
+// r), so both give the same value.  Each lane reads both of its row entries
+// with the site (inside the KMAX-entry row), computes their terms and stores
+// them in the group's LDS slots; every lane then forms all sums in ascending
+// entry order from there, eight entries per LDS round trip.  All lanes
+// return the same values.
+struct DescTerm {
+  double rj, rjf, tp, te;
+  int code;  // shell + 1 (0: outside), B flag << 2, r < rc flag << 3
+};
+typedef DescTerm DescSlots[KMAX];
+
 __device__ __forceinline__ void desc_du_group(const SweepArgs &a, int64_t i, int lane,
-                                              double fwd[10], double flp[10], double &du) {
+                                              double fwd[10], double flp[10], double &du,
+                                              DescTerm *slot) {
   const int s = a.sp[i], s1 = 1 - s;
   const double ri = a.rho[i];
   const int m = a.dcnt[i];
-  int code[2] = {0, 0};  // shell + 1 (0: outside), B flag << 2, r < rc flag << 3
-  double rj[2] = {0.0, 0.0}, rjf[2] = {0.0, 0.0}, tp[2] = {0.0, 0.0}, te[2] = {0.0, 0.0};
+  int32_t jr[2];
+  double rr[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t e = i * KMAX + lane + h * TL;
+    jr[h] = a.dj[e];
+    rr[h] = a.dr[e];
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int k = lane + h * TL;
+    DescTerm q;
+    q.rj = q.rjf = q.tp = q.te = 0.0;
+    q.code = 0;
     if (k < m) {
-      const int64_t e = i * KMAX + k;
-      const int32_t j = a.dj[e];
-      const double r = a.dr[e];
+      const int32_t j = jr[h];
+      const double r = rr[h];
       const int shl = r < 2.68 ? 0 : (r < 3.46 ? 1 : (r < DESC_CUT ? 2 : -1));
       const int sj = a.sp[j];
       const double rho = a.rho[j];
-      rj[h] = rho;
-      rjf[h] = rho;
+      q.rj = rho;
+      q.rjf = rho;
       int in = 0;
       if (r < a.p.rc) {
         const double d = a.p.rc - r;
         const double dd = d * d;
         const double g = a.p.c0 + a.p.c1 * r;
         const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
-        rjf[h] = rho + delta;
-        tp[h] = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
-        te[h] = embed(a.p, sj, rho + delta) - embed(a.p, sj, rho);
+        q.rjf = rho + delta;
+        q.tp = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
+        q.te = embed(a.p, sj, rho + delta) - embed(a.p, sj, rho);
         in = 1;
       }
-      code[h] = (shl + 1) | (sj << 2) | (in << 3);
+      q.code = (shl + 1) | (sj << 2) | (in << 3);
     }
+    slot[k] = q;
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   double cnt[3] = {0.0, 0.0, 0.0}, cb[3] = {0.0, 0.0, 0.0};
   double rs[3] = {0.0, 0.0, 0.0}, rsf[3] = {0.0, 0.0, 0.0};
   double pair = 0.0, emb = 0.0;
-  for (int k = 0; k < m; ++k) {
-    const int h = k / TL, src = k % TL;
-    const int ck = __shfl(h ? code[1] : code[0], src, TL);
-    const double rk = __shfl(h ? rj[1] : rj[0], src, TL);
-    const double rkf = __shfl(h ? rjf[1] : rjf[0], src, TL);
-    const double vp = __shfl(h ? tp[1] : tp[0], src, TL);
-    const double ve = __shfl(h ? te[1] : te[0], src, TL);
-    const int sk = (ck & 3) - 1;
-    if (sk >= 0) {
-      cnt[sk] += 1.0;
-      cb[sk] += (double)((ck >> 2) & 1);
-      rs[sk] += rk;
-      rsf[sk] += rkf;
-    }
-    if (ck & 8) {
-      pair += vp;
-      emb += ve;
+  for (int k0 = 0; k0 < KMAX; k0 += 8) {
+    if (k0 >= m) break;
+    DescTerm q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = slot[k0 + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u >= m) break;
+      const int ck = q[u].code;
+      const int sk = (ck & 3) - 1;
+#pragma unroll
+      for (int sh = 0; sh < 3; ++sh)
+        if (sk == sh) {
+          cnt[sh] += 1.0;
+          cb[sh] += (double)((ck >> 2) & 1);
+          rs[sh] += q[u].rj;
+          rsf[sh] += q[u].rjf;
+        }
+      if (ck & 8) {
+        pair += q[u].tp;
+        emb += q[u].te;
+      }
     }
   }
   fwd[0] = (double)s;
@@ -548,6 +577,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w_arg,
   __shared__ __bf16 zs[16 * MLP_KP];
   __shared__ __bf16 h1[16 * MLP_H], h2[16 * MLP_H];
   __shared__ float yv[16];
+  __shared__ DescSlots dslots[BLOCK / TL];
   const int lane = threadIdx.x % TL, grp = threadIdx.x / TL;
   const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
   // site and ln u1 from the sweep's table (the plain test's draws)
@@ -561,7 +591,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w_arg,
   double dfw[10] = {}, dfl[10] = {};
   if (has) {
     if (a.dj)
-      desc_du_group(a, i, lane, dfw, dfl, du);
+      desc_du_group(a, i, lane, dfw, dfl, du, dslots[threadIdx.x / TL]);
     else
       du = delta_u_group(a, i, lane, terms[threadIdx.x / TL]);
   }
@@ -1014,13 +1044,156 @@ __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int l
   }
 }
 
+// Delayed-acceptance trials of stage (w, s) in the pipeline (the two-stage
+// test of k_trial_da for the block's 16 cells, sites and ln u from the
+// two-sweep ring): the record of each cell, the trial and surrogate logs,
+// and the block's counts into part (three words per block: (trials |
+// accepts with dn = +1 << 32), (accepts with dn = -1 | ties << 32), stage-1
+// passes).  Every thread of the block calls it.
+struct DaShared {
+  DescSlots dslots[BLOCK / TL];
+  __bf16 zs[16 * MLP_KP];
+  __bf16 h1[16 * MLP_H], h2[16 * MLP_H];
+  float yv[16];
+  float w3[MLP_H];  // output-layer weights
+};
+
+__device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, int64_t s,
+                                               int64_t t, int lane, int32_t *rec,
+                                               long long *part, long long *sh, double2 *grpt,
+                                               DaShared &ds_) {
+  const int grp = threadIdx.x / TL;
+  // the network's weights first: their reads overlap the descriptor reads
+  MlpFrag mf;
+  if (a.da_mode == 1) {
+    mf = mlp_frag(a.md);
+    if (threadIdx.x < MLP_H) ds_.w3[threadIdx.x] = a.md.w3[threadIdx.x];
+  }
+  const int64_t q = ((int64_t)(w & 1) * a.S + s) * a.ncpc + t;
+  const int64_t i = t < a.ncpc ? a.sites[q] : -1;
+  const double lnu1 = t < a.ncpc ? a.site_lnu[q] : 0.0;
+  const bool has = i >= 0;
+  const int dn = has ? 1 - 2 * (int)a.sp[i] : 0;
+  double du = 0.0, ef = 0.0, er = 0.0;
+  double dfw[10] = {}, dfl[10] = {};
+  if (has) {
+    if (a.dj)
+      desc_du_group(a, i, lane, dfw, dfl, du, ds_.dslots[grp]);
+    else
+      du = delta_u_group(a, i, lane, grpt);
+  }
+  if (a.da_mode == 1) {
+    for (int k = lane; k < MLP_KP; k += TL) {
+      double v = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < MLP_IN; ++qq) v = qq == k ? dfw[qq] : v;  // static indices
+      ds_.zs[grp * MLP_KP + k] = (has && k < MLP_IN) ? mlp_input(a.md, k, v) : to_bf16(0.0f);
+    }
+    __syncthreads();
+    mlp_block16f(a.md, mf, ds_.w3, ds_.zs, ds_.h1, ds_.h2, ds_.yv);
+    ef = (double)(ds_.yv[grp] * a.md.out_sd + a.md.out_mu);
+  } else if (a.da_mode == 2) {
+    ef = du;
+  }
+  const double sf = ef + a.dmu0 * (double)dn;
+  const double x1 = a.beta * sf;
+  const bool pass1 = has && lnu1 < -x1;
+  if (a.da_mode == 1) {
+    const int any = __syncthreads_or(pass1 ? 1 : 0);
+    if (any) {
+      for (int k = lane; k < MLP_KP; k += TL) {
+        double v = 0.0;
+#pragma unroll
+        for (int qq = 0; qq < MLP_IN; ++qq) v = qq == k ? dfl[qq] : v;
+        ds_.zs[grp * MLP_KP + k] = (pass1 && k < MLP_IN) ? mlp_input(a.md, k, v) : to_bf16(0.0f);
+      }
+      __syncthreads();
+      mlp_block16f(a.md, mf, ds_.w3, ds_.zs, ds_.h1, ds_.h2, ds_.yv);
+      er = (double)(ds_.yv[grp] * a.md.out_sd + a.md.out_mu);
+    }
+  } else if (a.da_mode == 2) {
+    er = -du;
+  }
+  int64_t cell = -1;
+  U4 r = {};
+  if (has && (pass1 || a.tlog || a.dalog)) {
+    const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+    cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+    r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
+  }
+  long long valid = 0, dn_acc = 0, tie = 0, p1 = 0;
+  if (lane == 0 && t < a.ncpc) {
+    int32_t site = -1;
+    if (has) {
+      bool ok = false;
+      double margin = lnu1 + x1;
+      if (pass1) {
+        const double sr = er - a.dmu0 * (double)dn;
+        const double xl = a.beta * (du + a.dmu0 * (double)dn);
+        const double xr = -(a.beta * sr);
+        const double l2 = (-xl + (xr < 0.0 ? xr : 0.0)) - (-x1 < 0.0 ? -x1 : 0.0);
+        const double lnu2 = log(unit_open(r.v[2]));
+        ok = lnu2 < l2;
+        margin = lnu2 - l2;
+      }
+      valid = 1;
+      p1 = pass1 ? 1 : 0;
+      tie = fabs(margin) < TIE;
+      if (ok) {
+        dn_acc = dn;
+        site = (int32_t)i;
+      }
+      if (a.tlog) {
+        const unsigned long long idx = atomicAdd(&a.ds->tlog_n, 1ull);
+        if ((int64_t)idx < a.tcap) {
+          double *L = a.tlog + 8 * idx;
+          L[0] = (double)w;
+          L[1] = (double)s;
+          L[2] = (double)cell;
+          L[3] = (double)i;
+          L[4] = (double)dn;
+          L[5] = ok ? 1.0 : 0.0;
+          L[6] = pass1 ? du : __builtin_nan("");
+          L[7] = margin;
+        }
+      }
+      if (a.dalog) {
+        const unsigned long long idx = atomicAdd(&a.ds->dalog_n, 1ull);
+        if ((int64_t)idx < a.dacap) {
+          double *L = a.dalog + 5 * idx;
+          L[0] = (double)w;
+          L[1] = (double)s;
+          L[2] = (double)cell;
+          L[3] = ef;
+          L[4] = pass1 ? er : __builtin_nan("");
+        }
+      }
+    }
+    rec[t] = site;
+  }
+  long long v3[3] = {valid | ((dn_acc > 0 ? 1ll : 0ll) << 32),
+                     (dn_acc < 0 ? 1ll : 0ll) | (tie << 32), p1};
+  block_sums<3, false>(v3, sh);
+  if (threadIdx.x == 0) {
+    long long *P = part + 3 * blockIdx.x;
+    P[0] = v3[0];
+    P[1] = v3[1];
+    P[2] = v3[2];
+  }
+}
+
 // One kernel of the pipeline; par is the launch parity (state read from
 // pipe.sm[par], written to pipe.sm[par ^ 1]).  Blocks [0, nblk) hold one
 // group of TL lanes per active cell; the blocks after them draw sites.
+// DA: the trials are delayed-acceptance trials (three count words per
+// trial block instead of two).
+template <bool DA>
 __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
+  constexpr int NPW = DA ? 3 : 2;  // count words per trial block
   __shared__ long long sh[BLOCK];  // the trials' block counts
-  __shared__ long long shd[BLOCK / 64 * 2];  // the global test's counts
+  __shared__ long long shd[BLOCK / 64 * 3];  // the global test's counts
   __shared__ GroupTerms terms[BLOCK / TL];
+  __shared__ typename std::conditional<DA, DaShared, char>::type dash;
   DevState *ds = a.ds;
   const StageMachine m = ds->pipe.sm[par];
   const uint64_t w_end = ds->pipe.w_end;
@@ -1043,14 +1216,19 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   const int64_t t = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / TL;
   // the parity of the stage counter picks the record and partial-sum buffers
   const uint64_t gs = m.w * (uint64_t)S + (uint64_t)m.s;
-  const int64_t rstride = ncpc, pstride = 2 * (int64_t)a.nblk;  // two words per trial block
+  const int64_t rstride = ncpc, pstride = NPW * (int64_t)a.nblk;
   if (m.phase == SM_TRIAL) {
-    int32_t i;
-    double lnu;
-    TrialIn v;
-    pipe_trials_load(a, m.w, m.s, t, lane, i, lnu, v);
-    pipe_trials_finish(a, m.w, m.s, t, lane, i, lnu, v, a.rec + (gs & 1) * rstride,
-                       a.part + (gs & 1) * pstride, sh, terms[threadIdx.x / TL]);
+    if constexpr (DA) {
+      pipe_trials_da(a, m.w, m.s, t, lane, a.rec + (gs & 1) * rstride,
+                     a.part + (gs & 1) * pstride, sh, terms[threadIdx.x / TL], dash);
+    } else {
+      int32_t i;
+      double lnu;
+      TrialIn v;
+      pipe_trials_load(a, m.w, m.s, t, lane, i, lnu, v);
+      pipe_trials_finish(a, m.w, m.s, t, lane, i, lnu, v, a.rec + (gs & 1) * rstride,
+                         a.part + (gs & 1) * pstride, sh, terms[threadIdx.x / TL]);
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       StageMachine n = m;
       n.phase = SM_DECIDE;
@@ -1071,12 +1249,11 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   // the trial blocks' counts of (w, s) and ln u_g first: their reads then
   // overlap the trial reads below
   const double lnug = a.stage_lnug[(int64_t)(m.w & 1) * S + m.s];
-  const longlong2 *P = (const longlong2 *)(a.part + (gs & 1) * pstride);
-  long long c2[2] = {0, 0};
+  const long long *P = a.part + (gs & 1) * pstride;
+  long long c3[3] = {0, 0, 0};
   for (int b = threadIdx.x; b < a.nblk; b += BLOCK) {
-    const longlong2 q = P[b];
-    c2[0] += q.x;
-    c2[1] += q.y;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) c3[k] += P[NPW * b + k];
   }
   int32_t i2 = -1;
   double lnu2 = 0.0;
@@ -1084,12 +1261,13 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   v.m = 0;
   v.s = 0;
   v.ri = 0.0;
-  if (more) pipe_trials_load(a, w2, s2, t, lane, i2, lnu2, v);
+  if (!DA && more) pipe_trials_load(a, w2, s2, t, lane, i2, lnu2, v);
   // global test of (w, s) (Eq. trans_vcsgc_par2) from the trial blocks' counts
-  block_sums<2, false>(c2, shd);
-  const long long n_valid = c2[0] & 0xffffffffll, n_plus = c2[0] >> 32;
-  const long long n_minus = c2[1] & 0xffffffffll, n_tie = c2[1] >> 32;
-  long long v5[5] = {n_valid, n_plus + n_minus, n_plus - n_minus, n_tie, n_valid};
+  block_sums<3, false>(c3, shd);
+  const long long n_valid = c3[0] & 0xffffffffll, n_plus = c3[0] >> 32;
+  const long long n_minus = c3[1] & 0xffffffffll, n_tie = c3[1] >> 32;
+  long long v5[5] = {n_valid, n_plus + n_minus, n_plus - n_minus, n_tie,
+                     DA ? c3[2] : n_valid};
   const unsigned long long nrec = (unsigned long long)v5[1];
   const long long dn_tot = v5[2];
   int gacc = -1;
@@ -1108,8 +1286,12 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
       if (i >= 0) pipe_commit(a, i, lane);
     }
   } else if (more) {
-    pipe_trials_finish(a, w2, s2, t, lane, i2, lnu2, v, a.rec + ((gs + 1) & 1) * rstride,
-                       a.part + ((gs + 1) & 1) * pstride, sh, terms[threadIdx.x / TL]);
+    if constexpr (DA)
+      pipe_trials_da(a, w2, s2, t, lane, a.rec + ((gs + 1) & 1) * rstride,
+                     a.part + ((gs + 1) & 1) * pstride, sh, terms[threadIdx.x / TL], dash);
+    else
+      pipe_trials_finish(a, w2, s2, t, lane, i2, lnu2, v, a.rec + ((gs + 1) & 1) * rstride,
+                         a.part + ((gs + 1) & 1) * pstride, sh, terms[threadIdx.x / TL]);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ds->n_b_cur = nb_new;
@@ -1201,6 +1383,8 @@ struct StageGraph {
   double key[4] = {0, 0, 0, 0};
   uint64_t seed = 0;
   int K = 1;
+  int da_mode = 0;
+  MlpDev md{};  // the network's device view baked into delayed-acceptance nodes
 };
 
 void free_stage_graph(vcsgc_ctx *c) {
@@ -1228,6 +1412,8 @@ static hipError_t build_stage_graph(vcsgc_ctx *c, const SweepArgs &a0, double dm
   g->key[3] = T;
   g->seed = seed;
   g->K = a0.K;
+  g->da_mode = a0.da_mode;
+  g->md = a0.md;
   hipError_t e = hipGraphCreate(&g->graph, 0);
   if (e != hipSuccess) return e;
   const int64_t S = a0.S;
@@ -1303,6 +1489,8 @@ struct PipeGraph {
   double key[4] = {0, 0, 0, 0};
   uint64_t seed = 0;
   bool timed = false;
+  int da_mode = 0;
+  MlpDev md{};  // the network's device view baked into delayed-acceptance nodes
   std::vector<hipEvent_t> ev;
 };
 
@@ -1336,7 +1524,7 @@ static hipError_t pipe_graph_of(PipeGraph *g, int64_t len, unsigned grid, bool t
   if (timed) e = add_event();
   for (int64_t q = 0; q < len && e == hipSuccess; ++q) {
     hipKernelNodeParams kp = {};
-    kp.func = (void *)k_stage;
+    kp.func = g->a0[0].da_mode ? (void *)k_stage<true> : (void *)k_stage<false>;
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(BLOCK);
     kp.kernelParams = params[q & 1];
@@ -1368,7 +1556,10 @@ static hipError_t pipe_launch(vcsgc_ctx *c, const SweepArgs &a, unsigned grid, i
   }
   for (int64_t q = 0; q < k; ++q) {
     const int h = tstart(c, VCSGC_KT_STAGE);
-    k_stage<<<grid, BLOCK, 0, c->stream>>>(a, (int)(q & 1));
+    if (a.da_mode)
+      k_stage<true><<<grid, BLOCK, 0, c->stream>>>(a, (int)(q & 1));
+    else
+      k_stage<false><<<grid, BLOCK, 0, c->stream>>>(a, (int)(q & 1));
     tstop(c, h);
   }
   return hipGetLastError();
@@ -1393,7 +1584,8 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
   if (use_graph) {
     g = (PipeGraph *)c->pipe_graph;
     if (!g || g->key[0] != dmu0 || g->key[1] != kappa || g->key[2] != cbar || g->key[3] != T ||
-        g->seed != a.seed || g->timed != timed) {
+        g->seed != a.seed || g->timed != timed || g->da_mode != a.da_mode ||
+        memcmp(&g->md, &a.md, sizeof(MlpDev)) != 0) {
       free_pipe_graph(c);
       g = new PipeGraph();
       c->pipe_graph = g;
@@ -1402,6 +1594,8 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
       g->key[2] = cbar;
       g->key[3] = T;
       g->seed = a.seed;
+      g->da_mode = a.da_mode;
+      g->md = a.md;
       g->a0[0] = g->a0[1] = a;
       g->nbig = a.S + (a.S & 1);
       g->timed = timed;
@@ -1511,25 +1705,28 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.u_j = c->u_j;
   a.u_rho = c->u_rho;
   a.u_v = c->u_v;
-  void *f_trial = a.K > 1 ? (void *)k_trial_chain : (void *)k_trial;
+  void *f_trial = a.da_mode ? (void *)k_trial_da
+                            : (a.K > 1 ? (void *)k_trial_chain : (void *)k_trial);
   void *f_commit = a.K > 1 ? (void *)k_commit_chain : (void *)k_commit;
   const int gb = grid_for(a.ncpc * TL);
   a.nblk = gb;
   k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
   // one trial per cell and stage: the fused pipeline (graphs of its kernels
   // unless logs or per-kernel timing are on)
-  if (a.K == 1 && !a.da_mode && a.smp_cap == 0) {
+  if (a.K == 1 && a.smp_cap == 0) {
     if (n_sweeps == 0) return hipGetLastError();
     const bool timed = (c->tmask & (1u << VCSGC_KT_STAGE)) != 0;
-    return launch_pipeline(c, a, dmu0, kappa, cbar, T, n_sweeps, !a.tlog && !a.slog, timed);
+    return launch_pipeline(c, a, dmu0, kappa, cbar, T, n_sweeps,
+                           !a.tlog && !a.slog && !a.dalog, timed);
   }
-  // plain sweeps with no logs and no per-kernel timing replay a graph of one
-  // sweep (no host work per stage); everything else launches stage by stage
+  // sweeps with no logs and no per-kernel timing replay a graph of one sweep
+  // (no host work per stage); everything else launches stage by stage
   const bool per_kernel_timing = (c->tmask & ((1u << VCSGC_KT_TRIAL) | (1u << VCSGC_KT_COMMIT))) != 0;
-  if (!a.da_mode && !a.tlog && !a.slog && a.smp_cap == 0 && !per_kernel_timing && n_sweeps > 0) {
+  if (!a.tlog && !a.slog && !a.dalog && a.smp_cap == 0 && !per_kernel_timing && n_sweeps > 0) {
     StageGraph *g = (StageGraph *)c->stage_graph;
     if (!g || !g->exec || g->key[0] != dmu0 || g->key[1] != kappa || g->key[2] != cbar ||
-        g->key[3] != T || g->seed != seed || g->K != a.K) {
+        g->key[3] != T || g->seed != seed || g->K != a.K || g->da_mode != a.da_mode ||
+        memcmp(&g->md, &a.md, sizeof(MlpDev)) != 0) {
       hipError_t e = build_stage_graph(c, a, dmu0, kappa, cbar, T, seed, f_trial, f_commit);
       if (e != hipSuccess) {
         free_stage_graph(c);

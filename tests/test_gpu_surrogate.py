@@ -169,6 +169,40 @@ def test_da_network_chain_matches_oracle_replay(torch_cuda, oracle_mod):
     net.close()
 
 
+def test_da_network_graph_replay_matches_direct(torch_cuda, oracle_mod):
+    """DA with the network, replayed as a graph of one sweep (no logs) and
+    launched stage by stage (the surrogate log forces that path): the same
+    chain bit for bit, over calls that change the parameters in between."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    r_dep = 8.01
+    m = _params(7)
+    m.out_mu, m.out_sd = float(np.float32(0.45)), float(np.float32(0.2))
+    net = _gpu_mlp(m)
+    runs = []
+    for logged in (True, False):
+        d, g = _c2_state(O, pot, sweeps=0, cbar=0.05, r_dep=r_dep)
+        g.set_surrogate("mlp", net)
+        if logged:
+            g.enable_surrogate_log(2 * 10 ** 6)
+        out = []
+        for cb, n_sw in ((0.05, 2), (0.10, 3), (0.05, 2)):
+            s = g.sweep(d["dmu0"], d["kappa"], cb, d["T"], n_sw, d["seed"])
+            out.append({k: s[k] for k in ("trials", "stage1_pass", "local_accepts",
+                                           "stage_accepts", "flips", "n_final")})
+        out.append(g.species.cpu().numpy().copy())
+        out.append(g.rho().cpu().numpy().copy())
+        runs.append(out)
+        g.close()
+    a, b = runs
+    for k in range(3):
+        assert a[k] == b[k], k
+    assert a[0]["stage1_pass"] < a[0]["trials"]
+    assert np.array_equal(a[3], b[3])
+    assert np.array_equal(a[4], b[4])
+    net.close()
+
+
 def test_sample_log_and_training(torch_cuda, oracle_mod):
     torch = torch_cuda
     pot = I.params("FS-P1")
