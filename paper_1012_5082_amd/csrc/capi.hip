@@ -30,7 +30,7 @@ void free_all(vcsgc_ctx *c) {
                   c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos,
                   c->md_rows,    c->sites,      c->site_lnu,
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
-                  c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnug,   c->m_rec,
+                  c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnu2,     c->m_lnug,   c->m_rec,
                   c->m_part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -450,6 +450,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     const int64_t S1 = reps[0].S, nc1 = reps[0].ncpc;
     A(dalloc(&c->m_sites, 2 * S1 * nc1));
     A(dalloc(&c->m_lnu, 2 * S1 * nc1));
+    A(dalloc(&c->m_lnu2, 2 * S1 * nc1));
     A(dalloc(&c->m_lnug, 2 * S1));
     A(dalloc(&c->m_rec, 2 * nc1));
     A(dalloc(&c->m_part, 2 * vc::NPART * (int64_t)vc::grid_for(nc1 * 16)));

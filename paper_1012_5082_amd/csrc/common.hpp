@@ -285,6 +285,7 @@ struct vcsgc_ctx {
   // stages' global tests, and records and trial-block sums of two stages
   int32_t *m_sites = nullptr;
   double *m_lnu = nullptr, *m_lnug = nullptr;
+  double *m_lnu2 = nullptr;  // ln u of the delayed-acceptance second stage
   int32_t *m_rec = nullptr;
   long long *m_part = nullptr;
   vc::StageProgress *h_pipe = nullptr;  // pinned copy of the pipeline's progress

@@ -133,6 +133,63 @@ __device__ __forceinline__ void mlp_block16f(const MlpDev &m, const MlpFrag &f,
   __syncthreads();
 }
 
+// Inference for the 32 rows of zs ([32][32] bf16): two 16-row tiles that share
+// every weight fragment.  The two tiles' products are independent, so their
+// latencies overlap; each row's value is the one mlp_block16f gives it.
+// h1, h2 hold [32][64]; writes y[32].  Must be called by all 256 threads.
+__device__ __forceinline__ void mlp_block32f(const MlpDev &m, const MlpFrag &f,
+                                             const float *w3, const __bf16 *zs, __bf16 *h1,
+                                             __bf16 *h2, float *y) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, kb = (lane >> 4) * 8;
+  const int n = wv * 16 + r;
+  {
+    bf16x8 a0, a1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      a0[q] = zs[r * MLP_KP + kb + q];
+      a1[q] = zs[(16 + r) * MLP_KP + kb + q];
+    }
+    floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+    c0 = mfma16(a0, f.w1, c0);
+    c1 = mfma16(a1, f.w1, c1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = (lane >> 4) * 4 + q;
+      h1[row * MLP_H + n] = to_bf16(silu(c0[q] + f.b1));
+      h1[(16 + row) * MLP_H + n] = to_bf16(silu(c1[q] + f.b1));
+    }
+  }
+  __syncthreads();
+  {
+    floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < MLP_H; ks += 32) {
+      bf16x8 a0, a1;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a0[q] = h1[r * MLP_H + ks + kb + q];
+        a1[q] = h1[(16 + r) * MLP_H + ks + kb + q];
+      }
+      c0 = mfma16(a0, ks == 0 ? f.w2a : f.w2b, c0);
+      c1 = mfma16(a1, ks == 0 ? f.w2a : f.w2b, c1);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = (lane >> 4) * 4 + q;
+      h2[row * MLP_H + n] = to_bf16(silu(c0[q] + f.b2));
+      h2[(16 + row) * MLP_H + n] = to_bf16(silu(c1[q] + f.b2));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    float acc = m.b3[0];
+    for (int k = 0; k < MLP_H; ++k) acc += w3[k] * (float)h2[threadIdx.x * MLP_H + k];
+    y[threadIdx.x] = acc;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void mlp_block16(const MlpDev &m, const __bf16 *zs, __bf16 *h1,
                                             __bf16 *h2, float *y) {
   mlp_block16f(m, mlp_frag(m), m.w3, zs, h1, h2, y);

@@ -58,6 +58,7 @@ struct SweepArgs {
   // ln u of their local tests
   int32_t *sites;
   double *site_lnu;
+  double *site_lnu2;  // DA second-stage ln u per site-table entry (fused pipeline only)
   double *stage_lnug;  // ln u_g of every stage's global test
   // graph replay: the sweep counter is read from here instead of the
   // kernel argument (advanced by k_next_sweep at the end of each sweep)
@@ -903,7 +904,8 @@ __global__ void __launch_bounds__(BLOCK) k_commit_chain(SweepArgs a, uint64_t w_
 // Site of active cell t in stage s of sweep w and ln u of its local test
 // (the draws of k_sites for one trial per cell); t == 0 also writes ln u_g.
 __device__ __forceinline__ void draw_site(const SweepArgs &a, uint64_t w, int64_t s, int64_t t,
-                                          int32_t *sites, double *lnus, double *lnug) {
+                                          int32_t *sites, double *lnus, double *lnug,
+                                          double *lnus2) {
   const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
   if (t == 0) *lnug = log(unit_open(g.v[1]));
   const int64_t cell = colour_cell(a, (int)(g.v[0] >> 61), t);
@@ -915,6 +917,7 @@ __device__ __forceinline__ void draw_site(const SweepArgs &a, uint64_t w, int64_
     const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
     site = a.catoms[st + draw_index(r.v[0], m)];
     lnu = log(unit_open(r.v[1]));
+    if (lnus2) lnus2[t] = log(unit_open(r.v[2]));
   }
   sites[t] = site;
   lnus[t] = lnu;
@@ -926,7 +929,8 @@ __global__ void __launch_bounds__(BLOCK) k_sites_ring(SweepArgs a, uint64_t w) {
   if (q >= a.S * a.ncpc) return;
   const int64_t s = q / a.ncpc, t = q - s * a.ncpc;
   const int64_t row = (int64_t)(w & 1) * a.S + s;
-  draw_site(a, w, s, t, a.sites + row * a.ncpc, a.site_lnu + row * a.ncpc, a.stage_lnug + row);
+  draw_site(a, w, s, t, a.sites + row * a.ncpc, a.site_lnu + row * a.ncpc, a.stage_lnug + row,
+            a.site_lnu2 ? a.site_lnu2 + row * a.ncpc : nullptr);
 }
 
 __global__ void k_pipe_init(DevState *ds, unsigned long long w0, unsigned long long w_end) {
@@ -1052,11 +1056,12 @@ __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int l
 // passes).  Every thread of the block calls it.
 struct DaShared {
   DescSlots dslots[BLOCK / TL];
-  __bf16 zs[16 * MLP_KP];
-  __bf16 h1[16 * MLP_H], h2[16 * MLP_H];
-  float yv[16];
+  __bf16 zs[32 * MLP_KP];  // rows 0..15 the current, 16..31 the flipped descriptors
+  __bf16 h1[32 * MLP_H], h2[32 * MLP_H];
+  float yv[32];
   float w3[MLP_H];  // output-layer weights
 };
+static_assert(BLOCK / TL == 16, "one network row per lane group");
 
 __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, int64_t s,
                                                int64_t t, int lane, int32_t *rec,
@@ -1072,6 +1077,7 @@ __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, i
   const int64_t q = ((int64_t)(w & 1) * a.S + s) * a.ncpc + t;
   const int64_t i = t < a.ncpc ? a.sites[q] : -1;
   const double lnu1 = t < a.ncpc ? a.site_lnu[q] : 0.0;
+  const double lnu2 = t < a.ncpc ? a.site_lnu2[q] : 0.0;  // drawn with the site
   const bool has = i >= 0;
   const int dn = has ? 1 - 2 * (int)a.sp[i] : 0;
   double du = 0.0, ef = 0.0, er = 0.0;
@@ -1082,44 +1088,35 @@ __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, i
     else
       du = delta_u_group(a, i, lane, grpt);
   }
+  // both network values in one pass; the flipped one is used only when the
+  // first stage passes
   if (a.da_mode == 1) {
     for (int k = lane; k < MLP_KP; k += TL) {
-      double v = 0.0;
+      double v = 0.0, vl = 0.0;
 #pragma unroll
-      for (int qq = 0; qq < MLP_IN; ++qq) v = qq == k ? dfw[qq] : v;  // static indices
-      ds_.zs[grp * MLP_KP + k] = (has && k < MLP_IN) ? mlp_input(a.md, k, v) : to_bf16(0.0f);
+      for (int qq = 0; qq < MLP_IN; ++qq) {  // static indices
+        v = qq == k ? dfw[qq] : v;
+        vl = qq == k ? dfl[qq] : vl;
+      }
+      const bool in = has && k < MLP_IN;
+      ds_.zs[grp * MLP_KP + k] = in ? mlp_input(a.md, k, v) : to_bf16(0.0f);
+      ds_.zs[(16 + grp) * MLP_KP + k] = in ? mlp_input(a.md, k, vl) : to_bf16(0.0f);
     }
     __syncthreads();
-    mlp_block16f(a.md, mf, ds_.w3, ds_.zs, ds_.h1, ds_.h2, ds_.yv);
+    mlp_block32f(a.md, mf, ds_.w3, ds_.zs, ds_.h1, ds_.h2, ds_.yv);
     ef = (double)(ds_.yv[grp] * a.md.out_sd + a.md.out_mu);
+    er = (double)(ds_.yv[16 + grp] * a.md.out_sd + a.md.out_mu);
   } else if (a.da_mode == 2) {
     ef = du;
+    er = -du;
   }
   const double sf = ef + a.dmu0 * (double)dn;
   const double x1 = a.beta * sf;
   const bool pass1 = has && lnu1 < -x1;
-  if (a.da_mode == 1) {
-    const int any = __syncthreads_or(pass1 ? 1 : 0);
-    if (any) {
-      for (int k = lane; k < MLP_KP; k += TL) {
-        double v = 0.0;
-#pragma unroll
-        for (int qq = 0; qq < MLP_IN; ++qq) v = qq == k ? dfl[qq] : v;
-        ds_.zs[grp * MLP_KP + k] = (pass1 && k < MLP_IN) ? mlp_input(a.md, k, v) : to_bf16(0.0f);
-      }
-      __syncthreads();
-      mlp_block16f(a.md, mf, ds_.w3, ds_.zs, ds_.h1, ds_.h2, ds_.yv);
-      er = (double)(ds_.yv[grp] * a.md.out_sd + a.md.out_mu);
-    }
-  } else if (a.da_mode == 2) {
-    er = -du;
-  }
-  int64_t cell = -1;
-  U4 r = {};
-  if (has && (pass1 || a.tlog || a.dalog)) {
+  int64_t cell = -1;  // for the logs only
+  if (has && (a.tlog || a.dalog)) {
     const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
     cell = colour_cell(a, (int)(g.v[0] >> 61), t);
-    r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
   }
   long long valid = 0, dn_acc = 0, tie = 0, p1 = 0;
   if (lane == 0 && t < a.ncpc) {
@@ -1132,7 +1129,6 @@ __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, i
         const double xl = a.beta * (du + a.dmu0 * (double)dn);
         const double xr = -(a.beta * sr);
         const double l2 = (-xl + (xr < 0.0 ? xr : 0.0)) - (-x1 < 0.0 ? -x1 : 0.0);
-        const double lnu2 = log(unit_open(r.v[2]));
         ok = lnu2 < l2;
         margin = lnu2 - l2;
       }
@@ -1208,7 +1204,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
       const uint64_t w1 = m.w + 1;
       const int64_t row = (int64_t)(w1 & 1) * S + m.s;
       draw_site(a, w1, m.s, t, a.sites + row * ncpc, a.site_lnu + row * ncpc,
-                a.stage_lnug + row);
+                a.stage_lnug + row, a.site_lnu2 ? a.site_lnu2 + row * ncpc : nullptr);
     }
     return;
   }
@@ -1574,6 +1570,7 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
                                   bool timed) {
   a.sites = c->m_sites;
   a.site_lnu = c->m_lnu;
+  a.site_lnu2 = a.da_mode ? c->m_lnu2 : nullptr;
   a.stage_lnug = c->m_lnug;
   a.rec = c->m_rec;
   a.part = c->m_part;
