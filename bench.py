@@ -80,6 +80,8 @@ TRAFFIC = {
     "density": ("k_density_md", "paper_1012_5082_amd/csrc/md.hip",
                 "profiles/k_density_md_c3_traffic.md"),
     "stage": ("k_stage", "paper_1012_5082_amd/csrc/sweep.hip", "profiles/k_stage_c3_traffic.md"),
+    "batch": ("k_stage_spec", "paper_1012_5082_amd/csrc/sweep.hip",
+              "profiles/k_stage_spec_c3_traffic.md"),
 }
 
 
@@ -236,7 +238,8 @@ def bench_surrogate(args):
     sp = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
     plain = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, descriptor=True,
                   r_dep=r_dep)
-    plain.set_tuning("stage", 1)
+    tiling = args.c5_tiling.split(":")
+    plain.set_tuning(tiling[0], int(tiling[1]))
     n_relax = 100
     plain.sweep(*sp, n_relax, d["seed"])
     # held-out accuracy on the polycrystal itself
@@ -250,6 +253,7 @@ def bench_surrogate(args):
     da = VCSGC(d["x"], d["y"], d["z"], d["box"], plain.species.cpu().numpy(), pot,
                descriptor=True, r_dep=r_dep)
     da.set_surrogate("mlp", net)
+    da.set_tuning(tiling[0], int(tiling[1]))
     n_blocks = max(1, (args.sweeps or 400) // 10)
     res = {}
     for name, g, seed in (("plain", plain, 5005), ("da", da, 5005)):
@@ -279,6 +283,7 @@ def bench_surrogate(args):
     out = {"metric": "MC trials/s @2M atoms, plain vs surrogate-DA (same <c>, <E>)",
            "value": res["da"]["trials_per_s"], "unit": "trials/s", "workload": "c5-surrogate-da",
            "n_sites": n, "r_dep": r_dep, "relax_sweeps": n_relax, "sweeps_each": 10 * n_blocks,
+           "tiling": args.c5_tiling,
            "plain": res["plain"], "da": res["da"],
            "speedup_trials": round(res["da"]["trials_per_s"] / res["plain"]["trials_per_s"], 3),
            "z_c": round(z["mean_c"], 3), "z_E": round(z["mean_E_per_atom"], 3),
@@ -303,6 +308,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
                     help="c3: hybrid cycle (default line); c4: replica batch; c5: surrogate DA")
     ap.add_argument("--sweeps", type=int, default=0, help="c4/c5: timed sweeps")
+    ap.add_argument("--c5-tiling", default="batch:8",
+                    help="c5: sweep tiling of both chains (strategy:trials_per_group)")
     ap.add_argument("--local-steps", type=int, default=1,
                     help="c3: trials per active cell per stage (1 = the plain scheme)")
     args = ap.parse_args()
@@ -413,9 +420,11 @@ def main():
     roof = None
     if abytes:
         ach = abytes / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1),
+        tcls = "batch" if dominant == "stage" and tuned["choice"][0] == "batch" else dominant
+        roof = {"bound": "hbm", "kernel": TRAFFIC[tcls][0] if tcls in TRAFFIC else dominant,
+                "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dominant), "bytes_per_launch": int(abytes),
+                "traffic": measured_traffic(tcls), "bytes_per_launch": int(abytes),
                 "avg_launch_us": round(avg_s * 1e6, 2), "timed_launches": launches,
                 "launches": all_launches}
 

@@ -170,11 +170,21 @@ vcsgc_status vcsgc_sweep_batch(vcsgc_ctx *ctx, const double *dmu0, const double 
 /* Execution tuning of the sweep (results do not depend on it):
  *   strategy 0: persistent launch captured in a HIP graph (default),
  *            1: persistent cooperative launch without a graph,
- *            2: one trial kernel and one commit kernel per stage (single
+ *            2: the stage pipeline, one kernel per stage: the global test of
+ *               the stage before it and the trials of its own (single
  *               system only);
- *   trials_per_group: active cells handled by each 16-lane trial group per
- *            stage in the persistent kernel (sets the number of workgroups
- *            per replica; raised automatically if the grid would not fit).
+ *            3: the batched stage pipeline: each kernel makes the trials of
+ *               up to trials_per_group consecutive stages of a sweep on the
+ *               state as it is, and the global tests of the batch tried by
+ *               the kernel before it, in order, up to the first accepted
+ *               stage, after which the trials are made again (single system
+ *               only; trials_per_group in [1, 16], capped at half the stages
+ *               of a sweep; with trial or stage logs on, or fewer than two
+ *               stages per sweep, it runs as strategy 2);
+ *   trials_per_group: strategies 0 and 1: active cells handled by each
+ *            16-lane trial group per stage in the persistent kernel (sets
+ *            the number of workgroups per replica; raised automatically if
+ *            the grid would not fit); strategy 3: stages per batch.
  * Synchronizes the stream. */
 vcsgc_status vcsgc_set_tuning(vcsgc_ctx *ctx, int32_t strategy, int32_t trials_per_group);
 /* Current tuning and the persistent grid size (any output may be NULL). */

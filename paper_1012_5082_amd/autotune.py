@@ -1,7 +1,8 @@
 """Autotuner for the sweep's execution tiling.
 
-Candidates: one trial kernel + one commit kernel per stage ("stage", single
-systems only) and the graph-captured persistent launch with 1, 2, 4 or 8
+Candidates: for single systems the stage pipeline ("stage", one kernel per
+stage) and the batched stage pipeline ("batch", 4, 8 or 16 stages tried per
+kernel); for all, the graph-captured persistent launch with 1, 2, 4 or 8
 active cells per 16-lane trial group per stage (which sets the number of
 workgroups per replica).  Results do not depend on the choice: every
 candidate produces the same chain, so the sweeps made while tuning are real
@@ -18,6 +19,7 @@ import os
 CACHE = os.environ.get("VCSGC_TUNING_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "vcsgc_tuning.json"))
 TPG = (1, 2, 4, 8)
+BATCH = (4, 8, 16)
 
 
 def _key(ctx):
@@ -60,7 +62,7 @@ def tune(ctx, sweep_fn, sweeps_per_candidate=2, use_cache=True):
         return {"choice": (s, t), "times_ms": tab[key]["times_ms"], "cached": True, "key": key}
     cands = [("graph", t) for t in TPG]
     if getattr(ctx, "n_rep", 1) == 1:
-        cands.insert(0, ("stage", 1))
+        cands = [("stage", 1)] + [("batch", b) for b in BATCH] + cands
     times = {}
     for s, t in cands:
         ctx.set_tuning(s, t)

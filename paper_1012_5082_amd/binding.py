@@ -76,7 +76,7 @@ class Info(C.Structure):
 
 KT_NAMES = ["trial", "commit", "density", "forces", "kick_drift", "kick", "build", "energy",
             "persist", "stage"]
-STRATEGIES = {"graph": 0, "persistent": 1, "stage": 2}
+STRATEGIES = {"graph": 0, "persistent": 1, "stage": 2, "batch": 3}
 
 
 class KTimes(C.Structure):

@@ -31,7 +31,7 @@ void free_all(vcsgc_ctx *c) {
                   c->md_rows,    c->sites,      c->site_lnu,
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
                   c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnu2,     c->m_lnug,   c->m_rec,
-                  c->m_part};
+                  c->m_part,     c->s_rec,      c->s_part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -454,6 +454,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->m_lnug, 2 * S1));
     A(dalloc(&c->m_rec, 2 * nc1));
     A(dalloc(&c->m_part, 2 * vc::NPART * (int64_t)vc::grid_for(nc1 * 16)));
+    A(dalloc(&c->s_rec, 2 * vc::SPEC_MAX * nc1));
+    A(dalloc(&c->s_part, 2 * vc::SPEC_MAX * 3 * (int64_t)vc::grid_for(nc1 * 16)));
     A(hipHostMalloc((void **)&c->h_pipe, sizeof(vc::StageProgress), hipHostMallocDefault));
   }
   A(dalloc(&c->cell_count, coff));
@@ -606,7 +608,7 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
                 "delayed acceptance and the sample log need one trial per cell per stage");
   // delayed acceptance, the training-sample log and local chains run with
   // per-stage launches
-  if ((c->strategy == 2 || c->da_mode || c->smp_cap > 0 || c->local_steps > 1) && R == 1) {
+  if ((c->strategy >= 2 || c->da_mode || c->smp_cap > 0 || c->local_steps > 1) && R == 1) {
     // one trial kernel and one commit kernel per stage
     VC_CHECK(c, vc::persist_sync_nb_to_stage(c), "sweep");
     VC_CHECK(c, vc::launch_sweeps(c, dmu0[0], kappa[0], cbar[0], T[0], n_sweeps, seed), "sweep");
@@ -668,9 +670,11 @@ vcsgc_status vcsgc_sweep_batch(vcsgc_ctx *c, const double *dmu0, const double *k
 vcsgc_status vcsgc_set_tuning(vcsgc_ctx *c, int32_t strategy, int32_t trials_per_group) {
   vcsgc_status st = check_ctx(c);
   if (st) return st;
-  if (strategy < 0 || strategy > 2 || trials_per_group < 1 || trials_per_group > 64)
-    return fail(c, VCSGC_E_INVALID_ARG, "strategy in {0,1,2}, trials_per_group in [1,64]");
-  if (strategy == 2 && c->reps.size() != 1)
+  if (strategy < 0 || strategy > 3 || trials_per_group < 1 || trials_per_group > 64)
+    return fail(c, VCSGC_E_INVALID_ARG, "strategy in {0,1,2,3}, trials_per_group in [1,64]");
+  if (strategy == 3 && trials_per_group > vc::SPEC_MAX)
+    return fail(c, VCSGC_E_INVALID_ARG, "stages per batch in [1,16]");
+  if (strategy >= 2 && c->reps.size() != 1)
     return fail(c, VCSGC_E_INVALID_ARG, "per-stage launches need a single-system context");
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   c->strategy = strategy;

@@ -46,8 +46,22 @@ struct StageMachine {
   int phase;             // SM_TRIAL: its trials are next; SM_DECIDE: its global test is next
   int pad;
 };
+// Progress of the batched pipeline: each kernel makes the trials of a batch
+// of up to SPEC_MAX consecutive stages of one sweep (on the state as it is,
+// that is, assuming that every stage of the batch before them is rejected)
+// and the global tests of the batch the kernel before it tried.  A batch is
+// none when its length is 0; the call is done when both are none.
+constexpr int SPEC_MAX = 16;  // stages per batch, at most
+constexpr int SPEC_NDEC = 32; // blocks that make the global tests (and share a commit)
+struct SpecMachine {
+  unsigned long long dw, tw;  // sweep of the batch to test / to try
+  long long ds, ts;           // its first stage
+  long long nb;               // n_B before the batch to test
+  int dn, tn;                 // batch lengths
+};
 struct StageProgress {
   StageMachine sm[2];
+  SpecMachine spec[2];
   unsigned long long w_end;    // first sweep past the end of the call
   unsigned long long used;     // pipeline kernels that did work in the call
 };
@@ -288,8 +302,11 @@ struct vcsgc_ctx {
   double *m_lnu2 = nullptr;  // ln u of the delayed-acceptance second stage
   int32_t *m_rec = nullptr;
   long long *m_part = nullptr;
+  int32_t *s_rec = nullptr;    // batched pipeline: [2][SPEC_MAX][ncpc] records
+  long long *s_part = nullptr; // [2][SPEC_MAX][trial blocks][3] block counts
   vc::StageProgress *h_pipe = nullptr;  // pinned copy of the pipeline's progress
   double m_acc_rate = 0.05;             // accepted stages per stage, last call
+  double m_spec_rate = 0.0;             // batched pipeline: kernels per stage, last call
   void *pipe_graph = nullptr;           // graphs of pipeline kernels
   long long *part = nullptr;  // per trial block: trials, local accepts, sum dn, near ties
   int64_t npart = 0;

@@ -12,6 +12,7 @@
 // Cells of one colour are at least one cell edge (>= 2 rc) apart, so their
 // energy changes are independent and every rho_j has at most one writer per
 // stage.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -69,6 +70,8 @@ struct SweepArgs {
   int K;
   int32_t *u_site, *u_j;
   double *u_rho, *u_v;
+  // batched pipeline: stages per batch (at most SPEC_MAX and S / 2)
+  int D;
 };
 
 __device__ __forceinline__ uint64_t sweep_of(const SweepArgs &a, uint64_t w) {
@@ -949,11 +952,11 @@ __global__ void k_pipe_init(DevState *ds, unsigned long long w0, unsigned long l
 }
 
 // Local tests of stage (w, s) from the loaded trial data: the record of the
-// group's cell, the trial log, and the block's partial sums into part.
+// group's cell, the trial log, and the block's two count words into P.
 __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t w, int64_t s,
                                                    int64_t t, int lane, int32_t i, double lnu,
                                                    const TrialIn &v, int32_t *rec,
-                                                   long long *part, long long *sh,
+                                                   long long *P, long long *sh,
                                                    double2 *grp) {
   long long valid = 0, dn_acc = 0, tie = 0;
   if (t < a.ncpc) {
@@ -997,7 +1000,6 @@ __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t 
                      (dn_acc < 0 ? 1ll : 0ll) | (tie << 32)};
   block_sums<2, false>(v2, sh);
   if (threadIdx.x == 0) {
-    long long *P = part + 2 * blockIdx.x;
     P[0] = v2[0];
     P[1] = v2[1];
   }
@@ -1051,9 +1053,9 @@ __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int l
 // Delayed-acceptance trials of stage (w, s) in the pipeline (the two-stage
 // test of k_trial_da for the block's 16 cells, sites and ln u from the
 // two-sweep ring): the record of each cell, the trial and surrogate logs,
-// and the block's counts into part (three words per block: (trials |
-// accepts with dn = +1 << 32), (accepts with dn = -1 | ties << 32), stage-1
-// passes).  Every thread of the block calls it.
+// and the block's three count words into P ((trials | accepts with dn = +1
+// << 32), (accepts with dn = -1 | ties << 32), stage-1 passes).  Every
+// thread of the block calls it.
 struct DaShared {
   DescSlots dslots[BLOCK / TL];
   __bf16 zs[32 * MLP_KP];  // rows 0..15 the current, 16..31 the flipped descriptors
@@ -1065,7 +1067,7 @@ static_assert(BLOCK / TL == 16, "one network row per lane group");
 
 __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, int64_t s,
                                                int64_t t, int lane, int32_t *rec,
-                                               long long *part, long long *sh, double2 *grpt,
+                                               long long *P, long long *sh, double2 *grpt,
                                                DaShared &ds_) {
   const int grp = threadIdx.x / TL;
   // the network's weights first: their reads overlap the descriptor reads
@@ -1171,7 +1173,6 @@ __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, i
                      (dn_acc < 0 ? 1ll : 0ll) | (tie << 32), p1};
   block_sums<3, false>(v3, sh);
   if (threadIdx.x == 0) {
-    long long *P = part + 3 * blockIdx.x;
     P[0] = v3[0];
     P[1] = v3[1];
     P[2] = v3[2];
@@ -1216,14 +1217,16 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   if (m.phase == SM_TRIAL) {
     if constexpr (DA) {
       pipe_trials_da(a, m.w, m.s, t, lane, a.rec + (gs & 1) * rstride,
-                     a.part + (gs & 1) * pstride, sh, terms[threadIdx.x / TL], dash);
+                     a.part + (gs & 1) * pstride + NPW * blockIdx.x, sh,
+                     terms[threadIdx.x / TL], dash);
     } else {
       int32_t i;
       double lnu;
       TrialIn v;
       pipe_trials_load(a, m.w, m.s, t, lane, i, lnu, v);
       pipe_trials_finish(a, m.w, m.s, t, lane, i, lnu, v, a.rec + (gs & 1) * rstride,
-                         a.part + (gs & 1) * pstride, sh, terms[threadIdx.x / TL]);
+                         a.part + (gs & 1) * pstride + NPW * blockIdx.x, sh,
+                         terms[threadIdx.x / TL]);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       StageMachine n = m;
@@ -1284,10 +1287,12 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   } else if (more) {
     if constexpr (DA)
       pipe_trials_da(a, w2, s2, t, lane, a.rec + ((gs + 1) & 1) * rstride,
-                     a.part + ((gs + 1) & 1) * pstride, sh, terms[threadIdx.x / TL], dash);
+                     a.part + ((gs + 1) & 1) * pstride + NPW * blockIdx.x, sh,
+                     terms[threadIdx.x / TL], dash);
     else
       pipe_trials_finish(a, w2, s2, t, lane, i2, lnu2, v, a.rec + ((gs + 1) & 1) * rstride,
-                         a.part + ((gs + 1) & 1) * pstride, sh, terms[threadIdx.x / TL]);
+                         a.part + ((gs + 1) & 1) * pstride + NPW * blockIdx.x, sh,
+                         terms[threadIdx.x / TL]);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ds->n_b_cur = nb_new;
@@ -1467,6 +1472,238 @@ static hipError_t build_stage_graph(vcsgc_ctx *c, const SweepArgs &a0, double dm
   return hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
 }
 
+// ---------------------------------------------------------------------------
+// Batched pipeline.  A stage whose global test fails leaves the state as it
+// was, so the trials of the stages after it are those made on the state
+// before it.  Each kernel therefore makes the trials of a batch of up to D
+// consecutive stages of one sweep at once, and the next kernel tests the
+// batch's stages in order: every stage up to the first accepted one is
+// decided, that stage is committed, and the trials after it (and the batch
+// tried meanwhile, on the state before the commit) are made again.  The
+// chain is the one-stage-at-a-time chain, stage for stage.
+//
+// Site tables: the rows of sweep w + 1 are drawn for the stages of each tested
+// batch of sweep w.  With D <= S / 2, a batch tried in the kernel that tests
+// the last batch of sweep w lies in [0, D) of sweep w + 1, whose rows were
+// drawn when the first stages of sweep w were tested, and the rows being drawn
+// lie in [S - D, S).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void spec_after(uint64_t w, int64_t s, int64_t n, int64_t S,
+                                           unsigned long long &w2, long long &s2) {
+  s2 = s + n;
+  w2 = w;
+  if (s2 >= S) {
+    w2 += 1;
+    s2 -= S;
+  }
+}
+
+__device__ __forceinline__ int spec_len(uint64_t w, int64_t s, int64_t S, uint64_t w_end, int D) {
+  return w < w_end ? (int)(S - s < D ? S - s : D) : 0;
+}
+
+__global__ void k_spec_init(DevState *ds, unsigned long long w0, unsigned long long w_end,
+                            long long S, int D) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    SpecMachine m;
+    m.dw = m.tw = w0;
+    m.ds = m.ts = 0;
+    m.nb = ds->n_b_cur;
+    m.dn = 0;
+    m.tn = spec_len(w0, 0, S, w_end, D);
+    ds->pipe.spec[0] = m;
+    ds->pipe.spec[1] = m;
+    ds->pipe.w_end = w_end;
+    ds->pipe.used = 0;
+  }
+}
+
+// One kernel of the batched pipeline; par is the launch parity (state read
+// from pipe.spec[par], written to pipe.spec[par ^ 1]; the batch tried here
+// goes to slot par of the record and count buffers, the tested batch is in
+// slot par ^ 1).  Blocks [0, SPEC_NDEC) test the batch (each on its own,
+// block 0 writes the results) and share the commit; the next D nblk blocks
+// hold one group of TL lanes per active cell and stage of the tried batch;
+// the blocks after them draw the site tables of the next sweep.
+template <bool DA>
+__global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
+  constexpr int NPW = DA ? 3 : 2;  // count words per trial block
+  __shared__ long long sh[BLOCK];
+  __shared__ GroupTerms terms[BLOCK / TL];
+  __shared__ typename std::conditional<DA, DaShared, char>::type dash;
+  __shared__ long long tot[SPEC_MAX][NPW];
+  __shared__ double lg[SPEC_MAX];
+  __shared__ int kacc;
+  DevState *ds = a.ds;
+  const SpecMachine m = ds->pipe.spec[par];
+  if (m.dn == 0 && m.tn == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ds->pipe.spec[par ^ 1] = m;
+    return;
+  }
+  const int64_t S = a.S, ncpc = a.ncpc, nblk = a.nblk;
+  const int64_t kstride = nblk * NPW;  // count words per stage
+  const int lane = threadIdx.x % TL, grp = threadIdx.x / TL;
+  const int64_t b = blockIdx.x;
+  if (b >= SPEC_NDEC) {
+    const int64_t bt = b - SPEC_NDEC;
+    if (bt < (int64_t)a.D * nblk) {
+      const int k = (int)(bt / nblk);
+      if (k >= m.tn) return;
+      const int64_t lb = bt - (int64_t)k * nblk;
+      const int64_t t = lb * (BLOCK / TL) + grp;
+      const int64_t s = m.ts + k;
+      int32_t *rec = a.rec + ((int64_t)par * SPEC_MAX + k) * ncpc;
+      long long *P = a.part + ((int64_t)par * SPEC_MAX + k) * kstride + lb * NPW;
+      if constexpr (DA) {
+        pipe_trials_da(a, m.tw, s, t, lane, rec, P, sh, terms[grp], dash);
+      } else {
+        int32_t i;
+        double lnu;
+        TrialIn v;
+        pipe_trials_load(a, m.tw, s, t, lane, i, lnu, v);
+        pipe_trials_finish(a, m.tw, s, t, lane, i, lnu, v, rec, P, sh, terms[grp]);
+      }
+      return;
+    }
+    const int64_t q = (bt - (int64_t)a.D * nblk) * BLOCK + threadIdx.x;
+    const int64_t k = q / ncpc, t = q - k * ncpc;
+    if (k < m.dn && m.dw + 1 < ds->pipe.w_end) {
+      const uint64_t w1 = m.dw + 1;
+      const int64_t row = (int64_t)(w1 & 1) * S + m.ds + k;
+      draw_site(a, w1, m.ds + k, t, a.sites + row * ncpc, a.site_lnu + row * ncpc,
+                a.stage_lnug + row, a.site_lnu2 ? a.site_lnu2 + row * ncpc : nullptr);
+    }
+    return;
+  }
+  const uint64_t w_end = ds->pipe.w_end;
+  if (m.dn == 0) {
+    // nothing to test: the batch tried now starts from the committed state
+    if (b == 0 && threadIdx.x == 0) {
+      SpecMachine n;
+      n.nb = m.nb;
+      n.dw = m.tw;
+      n.ds = m.ts;
+      n.dn = m.tn;
+      spec_after(m.tw, m.ts, m.tn, S, n.tw, n.ts);
+      n.tn = spec_len(n.tw, n.ts, S, w_end, a.D);
+      ds->pipe.spec[par ^ 1] = n;
+      ds->pipe.used += 1;
+    }
+    return;
+  }
+  // the tested batch's counts per stage (exact integer sums) and ln u_g
+  {
+    const long long *P0 = a.part + (int64_t)(par ^ 1) * SPEC_MAX * kstride;
+    const int wv = threadIdx.x >> 6, wl = threadIdx.x & 63;
+    for (int k = wv; k < m.dn; k += BLOCK / 64) {
+      long long c[NPW];
+#pragma unroll
+      for (int q = 0; q < NPW; ++q) c[q] = 0;
+      for (int64_t lb = wl; lb < nblk; lb += 64)
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) c[q] += P0[k * kstride + lb * NPW + q];
+#pragma unroll
+      for (int q = 0; q < NPW; ++q)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) c[q] += __shfl_xor(c[q], off);
+      if (wl == 0)
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) tot[k][q] = c[q];
+    }
+    if (threadIdx.x < m.dn)
+      lg[threadIdx.x] = log(unit_open(
+          philox(a.seed, a.replica, m.dw, (uint64_t)(m.ds + threadIdx.x), 0, 0).v[1]));
+  }
+  __syncthreads();
+  // global tests (Eq. trans_vcsgc_par2) in stage order, up to the first accepted one
+  if (threadIdx.x == 0) {
+    long long nb = m.nb;
+    int ka = -1, nk = 0;
+    unsigned long long trials = 0, pass1 = 0, lacc = 0, ties = 0, flips = 0;
+    bool sweep_end = false;
+    for (int k = 0; k < m.dn; ++k) {
+      const long long c0 = tot[k][0], c1 = tot[k][1];
+      const long long n_valid = c0 & 0xffffffffll, n_plus = c0 >> 32;
+      const long long n_minus = c1 & 0xffffffffll, n_tie = c1 >> 32;
+      const long long nrec = n_plus + n_minus, dn_tot = n_plus - n_minus;
+      int gacc = -1;
+      double mg = 0.0;
+      if (nrec > 0) {
+        const double tt = (double)nb - a.ncbar;
+        const double dnd = (double)dn_tot;
+        const double xg = a.beta * a.kN * dnd * (dnd + 2.0 * tt);
+        mg = lg[k] + xg;
+        gacc = lg[k] < -xg ? 1 : 0;
+      }
+      if (gacc == 1) nb += dn_tot;
+      trials += (unsigned long long)n_valid;
+      pass1 += (unsigned long long)(DA ? tot[k][NPW - 1] : n_valid);
+      lacc += (unsigned long long)nrec;
+      ties += (unsigned long long)n_tie;
+      if (nrec > 0 && fabs(mg) < TIE) ties += 1;
+      nk = k + 1;
+      if (m.ds + k == S - 1) sweep_end = true;
+      if (gacc == 1) {
+        ka = k;
+        flips = (unsigned long long)nrec;
+        break;
+      }
+    }
+    kacc = ka;
+    if (b == 0) {
+      ds->n_b_cur = nb;
+      ds->trials += trials;
+      ds->stage1_pass += pass1;
+      ds->local_acc += lacc;
+      ds->near_ties += ties;
+      ds->stages += (unsigned long long)nk;
+      if (ka >= 0) {
+        ds->stage_acc += 1;
+        ds->flips += flips;
+      }
+      if (sweep_end) {
+        ds->sum_n += (double)nb;
+        ds->sum_n2 += (double)nb * (double)nb;
+      }
+      SpecMachine n;
+      n.nb = nb;
+      if (ka >= 0) {
+        // the batch tried now saw the state before the commit: it is dropped
+        n.dw = m.dw;
+        n.ds = m.ds;
+        n.dn = 0;
+        spec_after(m.dw, m.ds, ka + 1, S, n.tw, n.ts);
+      } else {
+        n.dw = m.tw;
+        n.ds = m.ts;
+        n.dn = m.tn;
+        spec_after(m.tw, m.ts, m.tn, S, n.tw, n.ts);
+      }
+      n.tn = spec_len(n.tw, n.ts, S, w_end, a.D);
+      ds->pipe.spec[par ^ 1] = n;
+      ds->pipe.used += 1;
+    }
+  }
+  __syncthreads();
+  const int ka = kacc;
+  if (ka < 0) return;
+  // commit of the accepted stage: 16 records per group, the groups' flips
+  // one after the other (sites of one stage have disjoint neighbourhoods)
+  const int32_t *R = a.rec + ((int64_t)(par ^ 1) * SPEC_MAX + ka) * ncpc;
+  for (int64_t t0 = (b * (BLOCK / TL) + grp) * TL; t0 < ncpc; t0 += (int64_t)SPEC_NDEC * BLOCK) {
+    const int64_t tt = t0 + lane;
+    const int32_t r = tt < ncpc ? R[tt] : -1;
+    const unsigned long long bal = __ballot(r >= 0);
+    unsigned gm = (unsigned)(bal >> ((threadIdx.x & 63) & ~(TL - 1))) & 0xFFFFu;
+    while (gm) {
+      const int src = __ffs(gm) - 1;
+      gm &= gm - 1;
+      pipe_commit(a, __shfl(r, src, TL), lane);
+    }
+  }
+}
+
 // Graphs of pipeline kernels: `big` holds S launches (one sweep's worth when
 // no stage is accepted), `small` PIPE_SMALL; both have even length, so every
 // replay starts at launch parity 0.  The kernel arguments (parameters, seed)
@@ -1486,9 +1723,16 @@ struct PipeGraph {
   uint64_t seed = 0;
   bool timed = false;
   int da_mode = 0;
+  int spec_d = 0;  // batched pipeline: stages per batch (0: one stage per kernel)
+  bool big_ran = false;  // `big` launched in the current call (its events recorded)
   MlpDev md{};  // the network's device view baked into delayed-acceptance nodes
   std::vector<hipEvent_t> ev;
 };
+
+static void *pipe_kernel(const SweepArgs &a) {
+  if (a.D > 0) return a.da_mode ? (void *)k_stage_spec<true> : (void *)k_stage_spec<false>;
+  return a.da_mode ? (void *)k_stage<true> : (void *)k_stage<false>;
+}
 
 void free_pipe_graph(vcsgc_ctx *c) {
   PipeGraph *g = (PipeGraph *)c->pipe_graph;
@@ -1520,7 +1764,7 @@ static hipError_t pipe_graph_of(PipeGraph *g, int64_t len, unsigned grid, bool t
   if (timed) e = add_event();
   for (int64_t q = 0; q < len && e == hipSuccess; ++q) {
     hipKernelNodeParams kp = {};
-    kp.func = g->a0[0].da_mode ? (void *)k_stage<true> : (void *)k_stage<false>;
+    kp.func = pipe_kernel(g->a0[0]);
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(BLOCK);
     kp.kernelParams = params[q & 1];
@@ -1541,6 +1785,7 @@ static hipError_t pipe_launch(vcsgc_ctx *c, const SweepArgs &a, unsigned grid, i
     while (k >= g->nbig) {
       hipError_t e = hipGraphLaunch(g->big, c->stream);
       if (e != hipSuccess) return e;
+      g->big_ran = true;
       k -= g->nbig;
     }
     while (k > 0) {
@@ -1550,39 +1795,46 @@ static hipError_t pipe_launch(vcsgc_ctx *c, const SweepArgs &a, unsigned grid, i
     }
     return hipSuccess;
   }
+  void *f = pipe_kernel(a);
   for (int64_t q = 0; q < k; ++q) {
     const int h = tstart(c, VCSGC_KT_STAGE);
-    if (a.da_mode)
-      k_stage<true><<<grid, BLOCK, 0, c->stream>>>(a, (int)(q & 1));
-    else
-      k_stage<false><<<grid, BLOCK, 0, c->stream>>>(a, (int)(q & 1));
+    int par = (int)(q & 1);
+    SweepArgs aq = a;
+    void *args[] = {&aq, &par};
+    hipError_t e = hipLaunchKernel(f, dim3(grid), dim3(BLOCK), args, 0, c->stream);
     tstop(c, h);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
 
-// Sweeps w .. w + n_sweeps - 1 through the fused pipeline.  The number of
-// kernels a call needs is one per stage, plus one, plus one per accepted
-// stage; the host launches its estimate, reads the pipeline's progress and
-// launches more until the last stage has been decided.
+// Sweeps w .. w + n_sweeps - 1 through the fused pipeline (a.D = 0: one
+// stage per kernel; the kernels a call needs are one per stage, plus one,
+// plus one per accepted stage) or the batched pipeline (a.D stages per
+// kernel; about one kernel per D stages plus one per accepted stage).  The
+// host launches its estimate, reads the pipeline's progress and launches
+// more until the last stage has been decided.
 static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double kappa,
                                   double cbar, double T, int64_t n_sweeps, bool use_graph,
                                   bool timed) {
+  const bool spec = a.D > 0;
   a.sites = c->m_sites;
   a.site_lnu = c->m_lnu;
   a.site_lnu2 = a.da_mode ? c->m_lnu2 : nullptr;
   a.stage_lnug = c->m_lnug;
-  a.rec = c->m_rec;
-  a.part = c->m_part;
+  a.rec = spec ? c->s_rec : c->m_rec;
+  a.part = spec ? c->s_part : c->m_part;
   a.nblk = grid_for(a.ncpc * TL);
   a.wdev = nullptr;
-  const unsigned grid = (unsigned)(a.nblk + grid_for(a.ncpc));
+  const unsigned grid =
+      spec ? (unsigned)(SPEC_NDEC + (int64_t)a.D * a.nblk + grid_for((int64_t)a.D * a.ncpc))
+           : (unsigned)(a.nblk + grid_for(a.ncpc));
   PipeGraph *g = nullptr;
   if (use_graph) {
     g = (PipeGraph *)c->pipe_graph;
     if (!g || g->key[0] != dmu0 || g->key[1] != kappa || g->key[2] != cbar || g->key[3] != T ||
         g->seed != a.seed || g->timed != timed || g->da_mode != a.da_mode ||
-        memcmp(&g->md, &a.md, sizeof(MlpDev)) != 0) {
+        g->spec_d != a.D || memcmp(&g->md, &a.md, sizeof(MlpDev)) != 0) {
       free_pipe_graph(c);
       g = new PipeGraph();
       c->pipe_graph = g;
@@ -1592,9 +1844,11 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
       g->key[3] = T;
       g->seed = a.seed;
       g->da_mode = a.da_mode;
+      g->spec_d = a.D;
       g->md = a.md;
       g->a0[0] = g->a0[1] = a;
-      g->nbig = a.S + (a.S & 1);
+      const int64_t per_sweep = spec ? (a.S + a.D - 1) / a.D : a.S;
+      g->nbig = per_sweep + (per_sweep & 1);
       g->timed = timed;
       hipError_t e = pipe_graph_of(g, g->nbig, grid, timed, &g->big);
       if (e == hipSuccess) e = pipe_graph_of(g, PIPE_SMALL, grid, false, &g->small);
@@ -1604,41 +1858,65 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
       }
     }
   }
+  if (g) g->big_ran = false;
   const uint64_t w0 = c->w, w_end = c->w + (uint64_t)n_sweeps;
   k_sites_ring<<<grid_for(a.S * a.ncpc), BLOCK, 0, c->stream>>>(a, w0);
-  k_pipe_init<<<1, 64, 0, c->stream>>>(a.ds, (unsigned long long)w0, (unsigned long long)w_end);
+  if (spec)
+    k_spec_init<<<1, 64, 0, c->stream>>>(a.ds, (unsigned long long)w0,
+                                         (unsigned long long)w_end, (long long)a.S, a.D);
+  else
+    k_pipe_init<<<1, 64, 0, c->stream>>>(a.ds, (unsigned long long)w0,
+                                         (unsigned long long)w_end);
   const int64_t G = n_sweeps * a.S;
   const int64_t step = use_graph ? PIPE_SMALL : 2;
   auto round_up = [&](int64_t k) { return (k + step - 1) / step * step; };
-  int64_t k = round_up(1 + G + (int64_t)std::ceil((double)G * c->m_acc_rate) + 2);
+  const double spec_rate = c->m_spec_rate > 0.0 ? c->m_spec_rate : 1.0 / a.D + 0.1;
+  auto estimate = [&](int64_t left) {
+    if (spec) return round_up((int64_t)std::ceil((double)left * spec_rate) + 2);
+    return round_up(left + 1 + (int64_t)std::ceil((double)left * c->m_acc_rate) + 2);
+  };
+  int64_t k = estimate(G);
   hipError_t e = pipe_launch(c, a, grid, k, g);
   if (e != hipSuccess) return e;
-  // every kernel before SM_DONE advances the state, so 2 G + 1 kernels always
-  // suffice; more would mean a broken pipeline state
+  // every kernel before the end decides a stage or tries a batch that the
+  // next one tests, so 2 G + 1 kernels always suffice; more would mean a
+  // broken pipeline state
   int64_t launched = k;
   for (;;) {
     e = hipMemcpyAsync(c->h_pipe, &a.ds->pipe, sizeof(StageProgress), hipMemcpyDeviceToHost,
                        c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return e;
-    const StageMachine m = c->h_pipe->sm[0];
-    if (m.phase == SM_DONE) break;
-    // stages still to decide, the pending trials, and the accepts expected among them
-    const int64_t left = (int64_t)(w_end - m.w) * a.S - m.s;
-    k = round_up(left + 1 + (int64_t)std::ceil((double)left * c->m_acc_rate) + 2);
+    int64_t left;
+    if (spec) {
+      const SpecMachine m = c->h_pipe->spec[0];
+      if (m.dn == 0 && m.tn == 0) break;
+      left = m.dn > 0 ? (int64_t)(w_end - m.dw) * a.S - m.ds
+                      : (int64_t)(w_end - m.tw) * a.S - m.ts;
+    } else {
+      const StageMachine m = c->h_pipe->sm[0];
+      if (m.phase == SM_DONE) break;
+      // stages still to decide, the pending trials, and the accepts expected among them
+      left = (int64_t)(w_end - m.w) * a.S - m.s;
+    }
+    k = estimate(left);
     if (left <= 0 || launched > 2 * G + 2 * step + 1) return hipErrorUnknown;
     launched += k;
     e = pipe_launch(c, a, grid, k, g);
     if (e != hipSuccess) return e;
   }
   if (G > 0) {
-    const double extra = (double)c->h_pipe->used - 1.0 - (double)G;
-    c->m_acc_rate = extra > 0.0 ? extra / (double)G : 0.0;
+    if (spec) {
+      c->m_spec_rate = (double)c->h_pipe->used / (double)G;
+    } else {
+      const double extra = (double)c->h_pipe->used - 1.0 - (double)G;
+      c->m_acc_rate = extra > 0.0 ? extra / (double)G : 0.0;
+    }
   }
   if (g && g->timed) {
     // span of the last replay of `big` (the stream is synchronized)
     float ms = 0.f;
-    if (launched >= g->nbig && g->ev.size() == 2 &&
+    if (g->big_ran && g->ev.size() == 2 &&
         hipEventElapsedTime(&ms, g->ev[0], g->ev[1]) == hipSuccess) {
       c->kt_ms[VCSGC_KT_STAGE] += ms;
       c->kt_n[VCSGC_KT_STAGE] += g->nbig;
@@ -1713,8 +1991,12 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   if (a.K == 1 && a.smp_cap == 0) {
     if (n_sweeps == 0) return hipGetLastError();
     const bool timed = (c->tmask & (1u << VCSGC_KT_STAGE)) != 0;
-    return launch_pipeline(c, a, dmu0, kappa, cbar, T, n_sweeps,
-                           !a.tlog && !a.slog && !a.dalog, timed);
+    const bool logs = a.tlog || a.slog || a.dalog;
+    // batches of stages (strategy 3) when nothing is logged per trial or
+    // stage: a dropped batch's trials would otherwise be logged
+    if (c->strategy == 3 && !logs && a.S >= 2)
+      a.D = (int)std::min<int64_t>({(int64_t)c->trials_per_group, (int64_t)SPEC_MAX, a.S / 2});
+    return launch_pipeline(c, a, dmu0, kappa, cbar, T, n_sweeps, !logs, timed);
   }
   // sweeps with no logs and no per-kernel timing replay a graph of one sweep
   // (no host work per stage); everything else launches stage by stage

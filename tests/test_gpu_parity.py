@@ -259,6 +259,45 @@ def test_stage_pipeline_accepting_stages(torch_cuda, oracle_mod, kappa, log):
         assert r["stage_accepts"] * 2 > r["stages"]
 
 
+@pytest.mark.parametrize("D,kappa", [(1, 10.0), (4, 0.0), (8, 1000.0), (16, 10.0)])
+def test_batched_pipeline_parity(torch_cuda, oracle_mod, D, kappa):
+    """Batches of D stages tried on the state as it is and tested in order up
+    to the first accepted stage (whose commit drops the trials after it): the
+    chain equals the oracle's, across calls, with few and with most stages
+    accepted (kappa = 0)."""
+    d = W.c2(cbar=0.05)
+    r = _sweep_parity(oracle_mod, d, I.params("FS-P1"), 3, kappa=kappa, log=False,
+                      chunks=[1, 2], strategy="batch", trials_per_group=D)
+    assert r["stage_accepts"] > 0
+
+
+def test_batched_pipeline_timed_and_retuned(torch_cuda, oracle_mod):
+    """The batched pipeline with per-kernel timing (event nodes in its graphs),
+    a change of batch length between calls and a call of zero sweeps."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = W.c2(cbar=0.05)
+    g = gpu_context(d, pot)
+    g.set_tuning("batch", 8)
+    st = oracle_state(O, d, pot)
+    args = (d["dmu0"], 10.0, d["cbar"], d["T"])
+    g.kernel_timing(["stage"])
+    s0 = g.sweep(*args, 0, d["seed"])
+    assert s0["trials"] == 0 and s0["stages"] == 0
+    for D, n_sw in ((8, 2), (3, 1)):
+        g.set_tuning("batch", D)
+        sg = g.sweep(*args, n_sw, d["seed"])
+        so, _, _ = O.sweep(st, *args, n_sw, d["seed"])
+        for key in ("trials", "local_accepts", "stages", "stage_accepts", "flips", "n_final"):
+            assert sg[key] == so[key], key
+        assert sg["sum_n"] == so["sum_n"] and sg["sum_n2"] == so["sum_n2"]
+    kt = g.kernel_times()
+    assert kt["stage"][1] > 0 and kt["stage"][0] > 0
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    g.close()
+
+
 def test_stage_pipeline_timed_and_empty(torch_cuda, oracle_mod):
     """Per-kernel timing of the pipeline (event nodes in its graphs) and a
     call of zero sweeps leave the chain equal to the oracle's."""
@@ -390,7 +429,8 @@ def test_md_parity_build_paths(torch_cuda, oracle_mod, n, skin):
     g.close()
 
 
-@pytest.mark.parametrize("path", ["pipeline", "da_perfect", "chain3", "persistent"])
+@pytest.mark.parametrize("path", ["pipeline", "da_perfect", "chain3", "persistent", "batch",
+                                  "da_batch"])
 def test_sweep_paths_after_md(torch_cuda, oracle_mod, path):
     """Sweeps right after MD run on the r < rc list filtered out of the MD
     rows and on the last MD density pass: every sweep kernel family (fused
@@ -405,8 +445,10 @@ def test_sweep_paths_after_md(torch_cuda, oracle_mod, path):
                                    d["species"], d["box"], pot, 1.0, 20)
     g = gpu_context(d, pot, velocities=True)
     g.md(1.0, 20)
-    if path == "da_perfect":
+    if path in ("da_perfect", "da_batch"):
         g.set_surrogate("perfect")
+    if path in ("batch", "da_batch"):
+        g.set_tuning("batch", 4)
     elif path == "chain3":
         g.set_local_steps(k)
     elif path == "persistent":

@@ -105,11 +105,12 @@ def test_descriptors_match_oracle(torch_cuda, oracle_mod):
     g.close()
 
 
-@pytest.mark.parametrize("desc", [False, True])
-def test_da_perfect_surrogate_equals_plain(torch_cuda, oracle_mod, desc):
+@pytest.mark.parametrize("desc,batch", [(False, 0), (True, 0), (True, 8)])
+def test_da_perfect_surrogate_equals_plain(torch_cuda, oracle_mod, desc, batch):
     """With the exact dU as surrogate the chain is the plain one, bit for bit;
     with the descriptor list present dU comes from that list's r < rc
-    entries instead of the r < rc list, and must be the same number."""
+    entries instead of the r < rc list, and must be the same number.  Also
+    through the batched pipeline (batch > 0 stages per kernel)."""
     pot = I.params("FS-P1")
     d = W.c2(cbar=0.05)
     from paper_1012_5082_amd.binding import VCSGC
@@ -120,6 +121,8 @@ def test_da_perfect_surrogate_equals_plain(torch_cuda, oracle_mod, desc):
         a.close()
         a = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, r_dep=8.01)
     b.set_surrogate("perfect")
+    if batch:
+        b.set_tuning("batch", batch)
     args = (d["dmu0"], 5.0, 0.05, d["T"], 5, d["seed"])
     sa, sb = a.sweep(*args), b.sweep(*args)
     for k in ("trials", "local_accepts", "stage_accepts", "flips", "n_final"):
@@ -169,10 +172,12 @@ def test_da_network_chain_matches_oracle_replay(torch_cuda, oracle_mod):
     net.close()
 
 
-def test_da_network_graph_replay_matches_direct(torch_cuda, oracle_mod):
-    """DA with the network, replayed as a graph of one sweep (no logs) and
-    launched stage by stage (the surrogate log forces that path): the same
-    chain bit for bit, over calls that change the parameters in between."""
+@pytest.mark.parametrize("batch", [0, 8])
+def test_da_network_graph_replay_matches_direct(torch_cuda, oracle_mod, batch):
+    """DA with the network, replayed as a graph (no logs; stage by stage, or
+    batches of stages when batch > 0) and launched stage by stage (the
+    surrogate log forces that path): the same chain bit for bit, over calls
+    that change the parameters in between."""
     O = oracle_mod
     pot = I.params("FS-P1")
     r_dep = 8.01
@@ -183,6 +188,8 @@ def test_da_network_graph_replay_matches_direct(torch_cuda, oracle_mod):
     for logged in (True, False):
         d, g = _c2_state(O, pot, sweeps=0, cbar=0.05, r_dep=r_dep)
         g.set_surrogate("mlp", net)
+        if batch:
+            g.set_tuning("batch", batch)
         if logged:
             g.enable_surrogate_log(2 * 10 ** 6)
         out = []
