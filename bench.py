@@ -85,11 +85,12 @@ TRAFFIC = {
 }
 
 
-def measured_traffic(cls):
+def measured_traffic(cls, tiling=None):
     """HBM bytes per launch of the kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the counter
-    reads for a copy kernel of known size), or None when there is none or the
-    kernel's source has changed since the counters were taken."""
+    reads for a copy kernel of known size), or None when there is none, the
+    kernel's source has changed since the counters were taken, or the
+    summary names a sweep tiling other than this run's."""
     import hashlib
     import re
     ent = TRAFFIC.get(cls)
@@ -105,6 +106,9 @@ def measured_traffic(cls):
     want = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     val = re.search(r"traffic_bytes_per_launch:\s*([0-9]+)", text)
     if not want or not val or want.group(1) != sha:
+        return None
+    til = re.search(r"tiling:\s*(\S+)", text)
+    if til and tiling is not None and til.group(1) != tiling:
         return None
     return int(val.group(1))
 
@@ -204,7 +208,10 @@ def bench_surrogate(args):
        range) is first relaxed by plain sweeps; from that state a plain and a
        delayed-acceptance chain run with identical parameters: trials/s,
        exact-accepted moves/s, pre-rejection rate, and <c>, <E> (energy every
-       10 sweeps, outside the timed sweeps) with blocked errors."""
+       10 sweeps, outside the timed sweeps) with blocked errors;
+    4. step 3 twice: both chains on the stage pipeline (one stage per
+       kernel), then each chain on its fastest tiling (stage pipeline or
+       batches of 2..16 stages, from a few timed sweeps of each)."""
     import numpy as np
     import torch
     from paper_1012_5082_amd import inputs as I
@@ -238,8 +245,7 @@ def bench_surrogate(args):
     sp = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
     plain = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, descriptor=True,
                   r_dep=r_dep)
-    tiling = args.c5_tiling.split(":")
-    plain.set_tuning(tiling[0], int(tiling[1]))
+    plain.set_tuning("batch", 16)
     n_relax = 100
     plain.sweep(*sp, n_relax, d["seed"])
     # held-out accuracy on the polycrystal itself
@@ -250,50 +256,81 @@ def bench_surrogate(args):
     rmse = float(torch.sqrt(torch.mean((pred - he) ** 2)))
     std_e = float(torch.std(he))
     plain.disable_sample_log()
-    da = VCSGC(d["x"], d["y"], d["z"], d["box"], plain.species.cpu().numpy(), pot,
-               descriptor=True, r_dep=r_dep)
-    da.set_surrogate("mlp", net)
-    da.set_tuning(tiling[0], int(tiling[1]))
+    relaxed = plain.species.cpu().numpy().copy()
+    plain.close()
+
+    def chain(name):
+        g = VCSGC(d["x"], d["y"], d["z"], d["box"], relaxed, pot, descriptor=True, r_dep=r_dep)
+        if name == "da":
+            g.set_surrogate("mlp", net)
+        return g
+
+    # each chain's fastest tiling: a few timed sweeps per candidate
+    def fastest(name):
+        g = chain(name)
+        times = {}
+        for tl in ("stage:1", "batch:2", "batch:4", "batch:8", "batch:16"):
+            st, k = tl.split(":")
+            g.set_tuning(st, int(k))
+            g.sweep(*sp, 1, 4242)
+            _, dt = _timed(lambda: g.sweep(*sp, 5, 4243))
+            times[tl] = round(dt / 5 * 1e3, 3)
+        g.close()
+        return min(times, key=times.get), times
+
     n_blocks = max(1, (args.sweeps or 400) // 10)
-    res = {}
-    for name, g, seed in (("plain", plain, 5005), ("da", da, 5005)):
-        g.sweep(*sp, 2, seed + 999)  # warmup
-        cs, es, trials, flips, pass1, secs = [], [], 0, 0, 0, 0.0
-        for k in range(n_blocks):
-            s, dt = _timed(lambda: g.sweep(*sp, 10, seed))
-            secs += dt
-            trials += s["trials"]
-            flips += s["flips"]
-            pass1 += s["stage1_pass"]
-            cs.append(s["sum_n"] / 10 / n)
-            es.append(g.energy() / n)
-        cm, ce = _blocked(cs)
-        em, ee = _blocked(es)
-        res[name] = {"trials_per_s": round(trials / secs, 1),
-                     "exact_accepted_per_s": round(flips / secs, 1),
-                     "ms_per_sweep": round(secs / (10 * n_blocks) * 1e3, 3),
-                     "pre_rejection_rate": (round(1.0 - pass1 / trials, 5) if name == "da"
-                                            else 0.0),
-                     "mean_c": cm, "mean_c_err": ce, "mean_E_per_atom": em, "mean_E_err": ee}
-        log(f"c5 {name}: {res[name]}")
-    z = {}
-    for key, err in (("mean_c", "mean_c_err"), ("mean_E_per_atom", "mean_E_err")):
-        z[key] = abs(res["plain"][key] - res["da"][key]) / max(
-            1e-30, float(np.hypot(res["plain"][err], res["da"][err])))
+    choice = {nm: fastest(nm) for nm in ("plain", "da")}
+    settings = (("per_stage", {"plain": "stage:1", "da": "stage:1"}),
+                ("fastest", {nm: choice[nm][0] for nm in ("plain", "da")}))
+    runs = {}
+    for label, tilings in settings:
+        res = {}
+        for name in ("plain", "da"):
+            g = chain(name)
+            st, k = tilings[name].split(":")
+            g.set_tuning(st, int(k))
+            seed = 5005
+            g.sweep(*sp, 2, seed + 999)  # warmup
+            cs, es, trials, flips, pass1, secs = [], [], 0, 0, 0, 0.0
+            for b in range(n_blocks):
+                s, dt = _timed(lambda: g.sweep(*sp, 10, seed))
+                secs += dt
+                trials += s["trials"]
+                flips += s["flips"]
+                pass1 += s["stage1_pass"]
+                cs.append(s["sum_n"] / 10 / n)
+                es.append(g.energy() / n)
+            g.close()
+            cm, ce = _blocked(cs)
+            em, ee = _blocked(es)
+            res[name] = {"tiling": tilings[name], "trials_per_s": round(trials / secs, 1),
+                         "exact_accepted_per_s": round(flips / secs, 1),
+                         "ms_per_sweep": round(secs / (10 * n_blocks) * 1e3, 3),
+                         "pre_rejection_rate": (round(1.0 - pass1 / trials, 5) if name == "da"
+                                                else 0.0),
+                         "mean_c": cm, "mean_c_err": ce, "mean_E_per_atom": em,
+                         "mean_E_err": ee}
+            log(f"c5 {label} {name}: {res[name]}")
+        z = {}
+        for key, err in (("mean_c", "mean_c_err"), ("mean_E_per_atom", "mean_E_err")):
+            z[key] = abs(res["plain"][key] - res["da"][key]) / max(
+                1e-30, float(np.hypot(res["plain"][err], res["da"][err])))
+        res["da_over_plain_exact_accepted"] = round(
+            res["da"]["exact_accepted_per_s"] / res["plain"]["exact_accepted_per_s"], 3)
+        res["z_c"] = round(z["mean_c"], 3)
+        res["z_E"] = round(z["mean_E_per_atom"], 3)
+        runs[label] = res
+    best = runs["fastest"]
     out = {"metric": "MC trials/s @2M atoms, plain vs surrogate-DA (same <c>, <E>)",
-           "value": res["da"]["trials_per_s"], "unit": "trials/s", "workload": "c5-surrogate-da",
+           "value": best["da"]["trials_per_s"], "unit": "trials/s", "workload": "c5-surrogate-da",
            "n_sites": n, "r_dep": r_dep, "relax_sweeps": n_relax, "sweeps_each": 10 * n_blocks,
-           "tiling": args.c5_tiling,
-           "plain": res["plain"], "da": res["da"],
-           "speedup_trials": round(res["da"]["trials_per_s"] / res["plain"]["trials_per_s"], 3),
-           "z_c": round(z["mean_c"], 3), "z_E": round(z["mean_E_per_atom"], 3),
+           "tiling_ms_per_sweep": {nm: choice[nm][1] for nm in choice},
+           "per_stage": runs["per_stage"], "fastest": best,
            "surrogate": {"train_samples": int(desc.shape[0]), "log_seconds": round(t_log, 2),
                          "train_seconds": round(t_train, 2),
                          "loss_first": rep["loss_first"], "loss_last": rep["loss_last"],
                          "steps": rep["steps"], "heldout_rmse_eV": rmse,
                          "heldout_dE_std_eV": std_e, "heldout_samples": int(hd.shape[0])}}
-    plain.close()
-    da.close()
     net.close()
     return out
 
@@ -308,10 +345,12 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
                     help="c3: hybrid cycle (default line); c4: replica batch; c5: surrogate DA")
     ap.add_argument("--sweeps", type=int, default=0, help="c4/c5: timed sweeps")
-    ap.add_argument("--c5-tiling", default="batch:8",
-                    help="c5: sweep tiling of both chains (strategy:trials_per_group)")
     ap.add_argument("--local-steps", type=int, default=1,
                     help="c3: trials per active cell per stage (1 = the plain scheme)")
+    ap.add_argument("--tiling", default="batch:16",
+                    help="c3: sweep tiling strategy:k, or 'auto' for the autotuner")
+    ap.add_argument("--relax", type=int, default=30,
+                    help="c3: untimed sweeps before the warmup cycles")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -349,17 +388,24 @@ def main():
     sweep_args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
     md_steps, dt = d["md_steps"], d["dt"]
 
-    # the autotuner's timing sweeps are real sweeps of the chain (warmup);
-    # local chains always run stage by stage
+    # tiling: local chains always run stage by stage; otherwise the given one,
+    # or the autotuner's (its timing sweeps are real sweeps of the chain)
     if args.local_steps > 1:
         g.set_tuning("stage", 1)
-        g.sweep(*sweep_args, 2, d["seed"], stats=False)
         tuned = {"choice": ("stage", 1), "times_ms": {}}
-    else:
+    elif args.tiling == "auto":
         from paper_1012_5082_amd import autotune
         tuned = autotune.tune(g, lambda k: g.sweep(*sweep_args, k, d["seed"], stats=False),
                               use_cache=False)
-    log(f"autotune: {tuned['choice']} from {tuned['times_ms']}")
+    else:
+        st, k = args.tiling.split(":")
+        g.set_tuning(st, int(k))
+        tuned = {"choice": (st, int(k)), "times_ms": {}}
+    log(f"tiling: {tuned['choice']} {tuned['times_ms']}")
+    # the chain settles out of its initial transient (most local accepts and
+    # accepted stages come in the first sweeps) before the warmup cycles
+    if args.relax > 0:
+        g.sweep(*sweep_args, args.relax, d["seed"], stats=False)
     for k in range(args.warmup):
         g.sweep(*sweep_args, 1, d["seed"])
         g.md(dt, md_steps)
@@ -424,7 +470,8 @@ def main():
         roof = {"bound": "hbm", "kernel": TRAFFIC[tcls][0] if tcls in TRAFFIC else dominant,
                 "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(tcls), "bytes_per_launch": int(abytes),
+                "traffic": measured_traffic(tcls, "%s:%d" % tuple(tuned["choice"])),
+                "bytes_per_launch": int(abytes),
                 "avg_launch_us": round(avg_s * 1e6, 2), "timed_launches": launches,
                 "launches": all_launches}
 

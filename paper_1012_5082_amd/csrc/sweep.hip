@@ -1530,7 +1530,10 @@ template <bool DA>
 __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
   constexpr int NPW = DA ? 3 : 2;  // count words per trial block
   __shared__ long long sh[BLOCK];
-  __shared__ GroupTerms terms[BLOCK / TL];
+  // delayed acceptance: the descriptor slots of a group also hold its dU terms
+  // when there is no descriptor list (the two are never used together)
+  static_assert(sizeof(DescSlots) >= sizeof(GroupTerms), "terms fit the descriptor slots");
+  __shared__ typename std::conditional<DA, char, GroupTerms[BLOCK / TL]>::type terms;
   __shared__ typename std::conditional<DA, DaShared, char>::type dash;
   __shared__ long long tot[SPEC_MAX][NPW];
   __shared__ double lg[SPEC_MAX];
@@ -1556,7 +1559,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
       int32_t *rec = a.rec + ((int64_t)par * SPEC_MAX + k) * ncpc;
       long long *P = a.part + ((int64_t)par * SPEC_MAX + k) * kstride + lb * NPW;
       if constexpr (DA) {
-        pipe_trials_da(a, m.tw, s, t, lane, rec, P, sh, terms[grp], dash);
+        pipe_trials_da(a, m.tw, s, t, lane, rec, P, sh, (double2 *)dash.dslots[grp], dash);
       } else {
         int32_t i;
         double lnu;
