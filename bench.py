@@ -62,11 +62,11 @@ def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials):
         return 73 * n
     if kind == "trial":
         k = pairs_mc / n
-        return trials * (26 + 29 * k)
+        return trials * (26 + 21 * k)
     if kind == "stage":
         k = pairs_mc / n
         nt, ncells = trials
-        return nt * (26 + 29 * k) + ncells * 24
+        return nt * (26 + 21 * k) + ncells * 24
     return None
 
 

@@ -22,8 +22,8 @@ hipError_t dalloc(T **p, size_t count) {
 
 void free_all(vcsgc_ctx *c) {
   void *ptrs[] = {c->bin_count,  c->bin_atoms,  c->cell_count, c->cell_start, c->cell_atoms,
-                  c->cell_fill,  c->mc_j,       c->mc_dd,
-                  c->mc_g,       c->mc_cnt,     c->md_j,       c->md_cnt,    c->xr,   c->yr,
+                  c->cell_fill,  c->mc_j,       c->mc_r,
+                  c->mc_cnt,     c->md_j,       c->md_cnt,    c->xr,   c->yr,
                   c->zr,         c->rho,        c->rho_f,      c->fp,        c->eatom, c->red,
                   c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
                   c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
@@ -35,7 +35,7 @@ void free_all(vcsgc_ctx *c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
-  if (c->h_pipe) (void)hipHostFree(c->h_pipe);
+  if (c->h_state) (void)hipHostFree(c->h_state);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
@@ -456,7 +456,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->m_part, 2 * vc::NPART * (int64_t)vc::grid_for(nc1 * 16)));
     A(dalloc(&c->s_rec, 2 * vc::SPEC_MAX * nc1));
     A(dalloc(&c->s_part, 2 * vc::SPEC_MAX * 3 * (int64_t)vc::grid_for(nc1 * 16)));
-    A(hipHostMalloc((void **)&c->h_pipe, sizeof(vc::StageProgress), hipHostMallocDefault));
+    A(hipHostMalloc((void **)&c->h_state, sizeof(vc::DevState), hipHostMallocDefault));
   }
   A(dalloc(&c->cell_count, coff));
   A(dalloc(&c->cell_start, coff + R));
@@ -469,8 +469,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->scan_tmp, mx));
   }
   A(dalloc(&c->mc_j, K * n));
-  A(dalloc(&c->mc_dd, K * n));
-  A(dalloc(&c->mc_g, K * n));
+  A(dalloc(&c->mc_r, K * n));
   A(dalloc(&c->mc_cnt, n));
   if (single) {
     A(dalloc(&c->md_j, K * n));
@@ -611,12 +610,16 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
   if ((c->strategy >= 2 || c->da_mode || c->smp_cap > 0 || c->local_steps > 1) && R == 1) {
     // one trial kernel and one commit kernel per stage
     VC_CHECK(c, vc::persist_sync_nb_to_stage(c), "sweep");
+    c->h_state_final = false;
     VC_CHECK(c, vc::launch_sweeps(c, dmu0[0], kappa[0], cbar[0], T[0], n_sweeps, seed), "sweep");
-    VC_CHECK(c, vc::persist_sync_nb_from_stage(c), "sweep");
+    // the pipelines end with the device state read and n_B synchronized
+    const bool have = c->h_state_final;
+    c->h_state_final = false;
+    if (!have) VC_CHECK(c, vc::persist_sync_nb_from_stage(c), "sweep");
     c->w += (uint64_t)n_sweeps;
     if (out) {
-      hipError_t e;
-      vc::DevState h = read_state(c, &e);
+      hipError_t e = hipSuccess;
+      vc::DevState h = have ? *c->h_state : read_state(c, &e);
       if (e != hipSuccess) return dev_fail(c, e, "sweep");
       out->trials = (int64_t)h.trials;
       out->local_accepts = (int64_t)h.local_acc;

@@ -248,8 +248,9 @@ hipError_t launch_bin_search(vcsgc_ctx *c, const RepHost &r) {
 // ----------------------------------------------------------------------------
 // neighbour lists from the search bins.  Every pair with r < cutoff, r from
 // the minimum-image separation as sqrt((dx^2 + dy^2) + dz^2), rows sorted by
-// neighbour index.  Column-major rows: entry k of atom i at [k * n + i].
-// MC rows additionally store dd = (rc - r)^2 and g = c0 + c1 r.
+// neighbour index.  Row-major rows: entry k of atom i at [i * KMAX + k],
+// with the neighbour's index and r (its users form (rc - r)^2 and c0 + c1 r
+// from r).
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ double pair_r(const double *__restrict__ x,
                                          const double *__restrict__ y,
@@ -269,13 +270,13 @@ __device__ __forceinline__ double pair_r(const double *__restrict__ x,
 // ([i * KMAX + k]) for the group-per-trial sweep kernels.
 constexpr int BG = 32;
 
-// MODE 1: MC rows ((rc - r)^2 and c0 + c1 r), 2: descriptor rows (r)
+// MODE 1: MC rows, 2: descriptor rows (both keep r)
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK)
     k_build(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
             const double *__restrict__ z, Grid g, const int32_t *__restrict__ bcount,
             const int32_t *__restrict__ batoms, int bmax, double cutoff, PotD p, int32_t *nj,
-            double *ndd, double *ng, uint8_t *cnt, DevState *ds, int64_t aoff) {
+            double *nr, uint8_t *cnt, DevState *ds, int64_t aoff) {
   __shared__ int32_t rowbuf[BLOCK / BG][KMAX];
   __shared__ int rowcount[BLOCK / BG];
   const int lane = threadIdx.x % BG, grp = threadIdx.x / BG;
@@ -323,14 +324,7 @@ __global__ void __launch_bounds__(BLOCK)
       for (int b = 0; b < count; ++b) rank += rowbuf[grp][b] < j ? 1 : 0;
       const int64_t e = ig * KMAX + rank;
       nj[e] = (int32_t)(aoff + j);
-      const double r = pair_r(x, y, z, g, xi, yi, zi, j);
-      if (MODE == 1) {
-        const double d = p.rc - r;
-        ndd[e] = d * d;
-        ng[e] = p.c0 + p.c1 * r;
-      } else {
-        ndd[e] = r;
-      }
+      nr[e] = pair_r(x, y, z, g, xi, yi, zi, j);
     }
   }
 }
@@ -372,7 +366,7 @@ hipError_t launch_build_mc_list(vcsgc_ctx *c, const RepHost &r) {
   int h = tstart(c, VCSGC_KT_BUILD);
   k_build<1><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
       r.n, c->x + r.aoff, c->y + r.aoff, c->z + r.aoff, g, c->bin_count + r.boff,
-      c->bin_atoms + r.boff * c->bmax, c->bmax, c->pot.rc, c->pot, c->mc_j, c->mc_dd, c->mc_g,
+      c->bin_atoms + r.boff * c->bmax, c->bmax, c->pot.rc, c->pot, c->mc_j, c->mc_r,
       c->mc_cnt, c->ds, r.aoff);
   tstop(c, h);
   return hipGetLastError();
@@ -383,7 +377,7 @@ hipError_t launch_build_desc_list(vcsgc_ctx *c, const RepHost &r) {
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   k_build<2><<<grid_for(r.n * BG), BLOCK, 0, c->stream>>>(
       r.n, c->x + r.aoff, c->y + r.aoff, c->z + r.aoff, g, c->bin_count + r.boff,
-      c->bin_atoms + r.boff * c->bmax, c->bmax, DESC_CUT, c->pot, c->d_j, c->d_r, nullptr,
+      c->bin_atoms + r.boff * c->bmax, c->bmax, DESC_CUT, c->pot, c->d_j, c->d_r,
       c->d_cnt, c->ds, r.aoff);
   return hipGetLastError();
 }
@@ -851,7 +845,7 @@ bool md_rebuild_on_device(const vcsgc_ctx *c) { return c->bin_pos != nullptr; }
 // density cache: rho_i = sum_j t_{s_j} (rc - r_ij)^2, ascending j (row-major MC rows)
 // ----------------------------------------------------------------------------
 __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
-                             const double *__restrict__ ndd, const uint8_t *__restrict__ cnt,
+                             const double *__restrict__ nr, const uint8_t *__restrict__ cnt,
                              const uint8_t *__restrict__ sp, PotD p, double *rho) {
   const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -859,13 +853,13 @@ __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
   const int m = cnt[i];
   for (int k = 0; k < m; ++k) {
     const int32_t j = nj[i * KMAX + k];
-    s += p.t[sp[j]] * ndd[i * KMAX + k];
+    s += p.t[sp[j]] * pair_dd(p, nr[i * KMAX + k]);
   }
   rho[i] = s;
 }
 
 // The r < rc rows taken from a valid r < rc + skin list (MD rows, row-major,
-// ascending j): same entries, same order and the same dd, g values as a build
+// ascending j): same entries, same order and the same r values as a build
 // from the search bins, since r is evaluated by the same expression (the
 // packed positions are current whenever the MD list and its densities are).  A group
 // of MFM_G lanes per atom: lane l tests entries l, l + MFM_G, ...; the hits of
@@ -875,7 +869,7 @@ constexpr int MFM_G = 16;
 
 __global__ void __launch_bounds__(BLOCK)
     k_mc_from_md(int64_t n, const double4 *__restrict__ ps4, Grid g, const int32_t *__restrict__ mdr,
-                 const uint8_t *__restrict__ mdcnt, PotD p, int32_t *nj, double *ndd, double *ng,
+                 const uint8_t *__restrict__ mdcnt, PotD p, int32_t *nj, double *nr,
                  uint8_t *cnt) {
   const int64_t gid = xcd_block() * BLOCK + threadIdx.x;
   const int64_t i = gid / MFM_G;
@@ -903,9 +897,7 @@ __global__ void __launch_bounds__(BLOCK)
     if (hit) {
       const int64_t e = i * KMAX + base + __popcll(gm & ((1ull << l) - 1ull));
       nj[e] = j;
-      const double d = p.rc - r;
-      ndd[e] = d * d;
-      ng[e] = p.c0 + p.c1 * r;
+      nr[e] = r;
     }
     base += __popcll(gm);
   }
@@ -917,14 +909,13 @@ hipError_t launch_mc_from_md(vcsgc_ctx *c) {
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   int h = tstart(c, VCSGC_KT_BUILD);
   k_mc_from_md<<<grid_for(c->n * MFM_G), BLOCK, 0, c->stream>>>(
-      c->n, c->ps4, g, c->md_rows, c->md_cnt, c->pot, c->mc_j, c->mc_dd, c->mc_g,
-      c->mc_cnt);
+      c->n, c->ps4, g, c->md_rows, c->md_cnt, c->pot, c->mc_j, c->mc_r, c->mc_cnt);
   tstop(c, h);
   return hipGetLastError();
 }
 
 hipError_t launch_density_mc(vcsgc_ctx *c) {
-  k_density_mc<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->mc_j, c->mc_dd, c->mc_cnt, c->sp,
+  k_density_mc<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->mc_j, c->mc_r, c->mc_cnt, c->sp,
                                                         c->pot, c->rho);
   return hipGetLastError();
 }

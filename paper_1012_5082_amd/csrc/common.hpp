@@ -137,6 +137,14 @@ __device__ __forceinline__ uint32_t draw_index(uint64_t w, uint32_t m) {
 // Finnis-Sinclair EAM pieces.  With d = rc - r, dd = d*d, g = c0 + c1 r:
 //   phi_XY = (eps_XY dd) g,  f_X = t_X dd,  F_X(rho) = -A_X sqrt(max(rho,0)).
 // ---------------------------------------------------------------------------
+// (rc - r)^2 and c0 + c1 r of a pair at distance r < rc (the r < rc list
+// keeps r; every user forms these the same way)
+__device__ __forceinline__ double pair_dd(const PotD &p, double r) {
+  const double d = p.rc - r;
+  return d * d;
+}
+__device__ __forceinline__ double pair_g(const PotD &p, double r) { return p.c0 + p.c1 * r; }
+
 __device__ __forceinline__ double embed(const PotD &p, int s, double rho) {
   return -p.A[s] * sqrt(rho > 0.0 ? rho : 0.0);
 }
@@ -264,9 +272,9 @@ struct vcsgc_ctx {
   void *stage_graph = nullptr;  // per-stage sweep replayed as a HIP graph (sweep.hip)
   int64_t nbins_total = 0;     // bins of all replicas
 
-  // r < rc list, column-major rows [k * n + i]: neighbour, (rc-r)^2, c0 + c1 r
+  // r < rc list, row-major rows [i * KMAX + k]: neighbour and r
   int32_t *mc_j = nullptr;
-  double *mc_dd = nullptr, *mc_g = nullptr;
+  double *mc_r = nullptr;  // r of each r < rc entry
   uint8_t *mc_cnt = nullptr;
   // r < 4.41 A descriptor list (row-major: neighbour, distance), when enabled
   bool desc = false;
@@ -304,7 +312,10 @@ struct vcsgc_ctx {
   long long *m_part = nullptr;
   int32_t *s_rec = nullptr;    // batched pipeline: [2][SPEC_MAX][ncpc] records
   long long *s_part = nullptr; // [2][SPEC_MAX][trial blocks][3] block counts
-  vc::StageProgress *h_pipe = nullptr;  // pinned copy of the pipeline's progress
+  // pinned copy of the device state, read by the pipeline's progress checks;
+  // h_state_final: the last check saw the call's end (statistics included)
+  vc::DevState *h_state = nullptr;
+  bool h_state_final = false;
   double m_acc_rate = 0.05;             // accepted stages per stage, last call
   double m_spec_rate = 0.0;             // batched pipeline: kernels per stage, last call
   void *pipe_graph = nullptr;           // graphs of pipeline kernels

@@ -50,7 +50,7 @@ struct PersistArgs {
   RepState *rs;
   const int32_t *wg_rep;
   const int32_t *cstart, *catoms, *nj;
-  const double *ndd, *ng;
+  const double *nr;  // r of each r < rc entry
   const uint8_t *cnt;
   uint8_t *sp;
   double *rho;
@@ -121,7 +121,8 @@ __device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int
       const int64_t e = i * KMAX + k;
       const int32_t j = a.nj[e];
       const int sj = a.sp[j];
-      const double dd = a.ndd[e], g = a.ng[e];
+      const double r = a.nr[e];
+      const double dd = pair_dd(a.p, r), g = pair_g(a.p, r);
       const double rj = a.rho[j];
       tp[h] = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
       const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
@@ -268,7 +269,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
             if (k < m) {
               const int64_t e = (int64_t)i * KMAX + k;
               const int32_t j = a.nj[e];
-              const double dd = a.ndd[e];
+              const double dd = pair_dd(a.p, a.nr[e]);
               const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
               a.rho[j] = a.rho[j] + delta;
             }
@@ -360,8 +361,7 @@ static PersistArgs make_args(vcsgc_ctx *c) {
   a.cstart = c->cell_start;
   a.catoms = c->cell_atoms;
   a.nj = c->mc_j;
-  a.ndd = c->mc_dd;
-  a.ng = c->mc_g;
+  a.nr = c->mc_r;
   a.cnt = c->mc_cnt;
   a.sp = c->sp;
   a.rho = c->rho;

@@ -31,7 +31,7 @@ struct SweepArgs {
   PotD p;
   const int32_t *cstart, *catoms;
   const int32_t *nj;
-  const double *ndd, *ng;
+  const double *nr;  // r of each r < rc entry
   const uint8_t *cnt;
   uint8_t *sp;
   double *rho;
@@ -116,8 +116,9 @@ __device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int la
     if ((h + 1) * L <= 16 || k < v.m) {
       const int64_t e = i * KMAX + k;
       v.j[h] = a.nj[e];
-      v.dd[h] = a.ndd[e];
-      v.g[h] = a.ng[e];
+      const double r = a.nr[e];
+      v.dd[h] = pair_dd(a.p, r);
+      v.g[h] = pair_g(a.p, r);
     }
   }
 #pragma unroll
@@ -526,7 +527,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_a
           if (e < m) {
             const int64_t ee = i * KMAX + e;
             const int32_t j = a.nj[ee];
-            const double dd = a.ndd[ee];
+            const double dd = pair_dd(a.p, a.nr[ee]);
             const double old = a.rho[j];
             a.u_j[uq * KMAX + e] = j;
             a.u_rho[uq * KMAX + e] = old;
@@ -820,7 +821,7 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, i
         if (k < m) {
           const int64_t e = (int64_t)i * KMAX + k;
           jr[h] = a.nj[e];
-          ddr[h] = a.ndd[e];
+          ddr[h] = pair_dd(a.p, a.nr[e]);
         }
       }
     }
@@ -1034,7 +1035,7 @@ __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int l
     if (k < m) {
       const int64_t e = (int64_t)i * KMAX + k;
       const int32_t j = a.nj[e];
-      const double dd = a.ndd[e];
+      const double dd = pair_dd(a.p, a.nr[e]);
       const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
       a.rho[j] = a.rho[j] + delta;
     }
@@ -1850,7 +1851,9 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
       g->spec_d = a.D;
       g->md = a.md;
       g->a0[0] = g->a0[1] = a;
-      const int64_t per_sweep = spec ? (a.S + a.D - 1) / a.D : a.S;
+      // one sweep's kernels when no stage is accepted (the batched pipeline
+      // needs one more to test its last batch)
+      const int64_t per_sweep = spec ? (a.S + a.D - 1) / a.D + 1 : a.S;
       g->nbig = per_sweep + (per_sweep & 1);
       g->timed = timed;
       hipError_t e = pipe_graph_of(g, g->nbig, grid, timed, &g->big);
@@ -1875,7 +1878,7 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
   auto round_up = [&](int64_t k) { return (k + step - 1) / step * step; };
   const double spec_rate = c->m_spec_rate > 0.0 ? c->m_spec_rate : 1.0 / a.D + 0.1;
   auto estimate = [&](int64_t left) {
-    if (spec) return round_up((int64_t)std::ceil((double)left * spec_rate) + 2);
+    if (spec) return round_up((int64_t)std::ceil((double)left * spec_rate) + 1);
     return round_up(left + 1 + (int64_t)std::ceil((double)left * c->m_acc_rate) + 2);
   };
   int64_t k = estimate(G);
@@ -1886,18 +1889,21 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
   // broken pipeline state
   int64_t launched = k;
   for (;;) {
-    e = hipMemcpyAsync(c->h_pipe, &a.ds->pipe, sizeof(StageProgress), hipMemcpyDeviceToHost,
-                       c->stream);
+    // the persistent path's n_B and the whole device state: when the call
+    // has ended, this one read also serves its statistics
+    e = persist_sync_nb_from_stage(c);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->h_state, a.ds, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return e;
     int64_t left;
     if (spec) {
-      const SpecMachine m = c->h_pipe->spec[0];
+      const SpecMachine m = c->h_state->pipe.spec[0];
       if (m.dn == 0 && m.tn == 0) break;
       left = m.dn > 0 ? (int64_t)(w_end - m.dw) * a.S - m.ds
                       : (int64_t)(w_end - m.tw) * a.S - m.ts;
     } else {
-      const StageMachine m = c->h_pipe->sm[0];
+      const StageMachine m = c->h_state->pipe.sm[0];
       if (m.phase == SM_DONE) break;
       // stages still to decide, the pending trials, and the accepts expected among them
       left = (int64_t)(w_end - m.w) * a.S - m.s;
@@ -1910,9 +1916,9 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
   }
   if (G > 0) {
     if (spec) {
-      c->m_spec_rate = (double)c->h_pipe->used / (double)G;
+      c->m_spec_rate = (double)c->h_state->pipe.used / (double)G;
     } else {
-      const double extra = (double)c->h_pipe->used - 1.0 - (double)G;
+      const double extra = (double)c->h_state->pipe.used - 1.0 - (double)G;
       c->m_acc_rate = extra > 0.0 ? extra / (double)G : 0.0;
     }
   }
@@ -1926,6 +1932,7 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
     }
     c->kt_seen[VCSGC_KT_STAGE] += launched;
   }
+  c->h_state_final = true;
   return hipSuccess;
 }
 
@@ -1949,8 +1956,7 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.cstart = c->cell_start;
   a.catoms = c->cell_atoms;
   a.nj = c->mc_j;
-  a.ndd = c->mc_dd;
-  a.ng = c->mc_g;
+  a.nr = c->mc_r;
   a.cnt = c->mc_cnt;
   a.sp = c->sp;
   a.rho = c->rho;
