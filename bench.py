@@ -35,11 +35,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials):
+def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials, fused=0.0):
     """Compulsory HBM bytes of one launch (each array element counted once).
 
     forces    : (x,y,z,F') packed (32) + species (1) + row length (1) + neighbour
-                indices (4 per r < rc + skin pair) + fx,fy,fz written (24)
+                indices (4 per r < rc + skin pair) + fx,fy,fz written (24); a
+                launch that runs the next step's kick and drift instead of
+                storing the forces reads x,y,z, v and the reference positions
+                (72) and writes x,y,z, v and the packed positions (80) in place
+                of the 24 bytes of forces; `fused` is the share of such launches
     density   : (x,y,z,species) packed (32) + species (1) + row length (1) +
                 indices (4 per pair) + rho, F' (16) and (x,y,z,F') (32) written
     kick_drift: x,y,z,v,F,species,reference positions read (105), x,y,z,v and the
@@ -53,7 +57,7 @@ def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials):
                 the next sweep's draw: cell start/atom read (8+4), site and ln u
                 written (4+8); `trials` is then (trials, active cells) per launch"""
     if kind == "forces":
-        return 58 * n + 4 * pairs_md
+        return (58 + fused * (72 + 80 - 24)) * n + 4 * pairs_md
     if kind == "density":
         return 82 * n + 4 * pairs_md
     if kind == "kick_drift":
@@ -462,7 +466,10 @@ def main():
         nc = info["n_cells"]
         ncpc = nc[0] * nc[1] * nc[2] // 8
         per_launch_trials = (trials / max(1, all_launches), stages * ncpc / max(1, all_launches))
-    abytes = algorithmic_bytes(dominant, n, pairs_md, pairs_mc, per_launch_trials)
+    # every MD call of md_steps steps makes md_steps force passes with the
+    # next step's kick and drift and one that stores the forces
+    abytes = algorithmic_bytes(dominant, n, pairs_md, pairs_mc, per_launch_trials,
+                               fused=md_steps / (md_steps + 1))
     roof = None
     if abytes:
         ach = abytes / avg_s / 1e9

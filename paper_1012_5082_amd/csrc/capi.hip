@@ -804,12 +804,16 @@ vcsgc_status md_steps_device(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
            "reset");
   VC_CHECK(c, hipMemsetAsync(c->ds->rebuild, 0, 2 * sizeof(int), c->stream), "reset");
   VC_CHECK(c, vc::launch_pack(c), "pack");
-  VC_CHECK(c, vc::launch_forces(c), "forces");
-  // step k uses the rebuild flag of parity k & 1 (its drift clears the other)
+  // step k uses the rebuild flag of parity k & 1 (its drift clears the
+  // other); its kick and drift run inside the force pass before it, and
+  // the last force pass stores the forces for the closing half kick
+  VC_CHECK(c, vc::launch_forces_kick_drift(c, dt_fs, false, 0), "forces");
   for (int64_t k = 0; k < n_steps; ++k) {
-    VC_CHECK(c, vc::launch_kick_drift(c, dt_fs, k > 0, (int)(k & 1)), "kick-drift");
     VC_CHECK(c, vc::launch_md_rebuild_cond(c, (int)(k & 1)), "neighbour list (MD)");
-    VC_CHECK(c, vc::launch_forces(c), "forces");
+    if (k + 1 < n_steps)
+      VC_CHECK(c, vc::launch_forces_kick_drift(c, dt_fs, true, (int)((k + 1) & 1)), "forces");
+    else
+      VC_CHECK(c, vc::launch_forces(c), "forces");
   }
   VC_CHECK(c, vc::launch_kick(c, dt_fs), "kick");
   hipError_t e;

@@ -403,6 +403,9 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
                          int64_t n_sweeps, uint64_t seed);
 hipError_t launch_pack(vcsgc_ctx *c);
 hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par);
+// density and force passes whose forces go straight into the next step's
+// kick and drift (the forces are not stored)
+hipError_t launch_forces_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par);
 hipError_t launch_kick(vcsgc_ctx *c, double dt);
 hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
 // persistent sweep (persist.hip)

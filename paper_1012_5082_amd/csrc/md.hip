@@ -87,6 +87,64 @@ __global__ void __launch_bounds__(BLOCK)
   pf4[i] = make_double4(qi.x, qi.y, qi.z, f);
 }
 
+// [v += (dt/2)(F cm) (closing the previous step) ;] v += (dt/2)(F cm);
+// x = wrap(x + dt v); raise ds->rebuild[par] when an atom has moved more than
+// skin/2 from its position at the last build.  Also readies the next
+// device-decided rebuild: the flag of the other parity (read by the previous
+// step's rebuild kernels, which have finished) is cleared, and so are the
+// search-bin counts (bcount may be NULL).
+struct KickDrift {
+  double *x, *y, *z, *vx, *vy, *vz;
+  const double *xr, *yr, *zr;  // positions at the last MD-list build
+  double4 *ps4;
+  double dt, half_skin2;
+  int kick_first, par;
+  int32_t *bcount;
+  int64_t nbins;
+  DevState *ds;
+};
+
+// The step's clearing work, by thread i of a grid of `threads`.
+__device__ __forceinline__ void kick_drift_clear(const KickDrift &k, int64_t i, int64_t threads) {
+  if (k.bcount)
+    for (int64_t q = i; q < k.nbins; q += threads) k.bcount[q] = 0;
+  if (i == 0) k.ds->rebuild[k.par ^ 1] = 0;
+}
+
+// Kick and drift of atom i (species s) from its force; every active lane of
+// the wave takes part in the rebuild vote.
+__device__ __forceinline__ void kick_drift_atom(const KickDrift &k, int64_t i, int s, double fxi,
+                                                double fyi, double fzi, const Box &b,
+                                                const PotD &p) {
+  const double cm = p.cm[s];
+  const double hdt = 0.5 * k.dt;
+  const double ax = fxi * cm, ay = fyi * cm, az = fzi * cm;
+  double ux = k.vx[i], uy = k.vy[i], uz = k.vz[i];
+  if (k.kick_first) {
+    ux = ux + hdt * ax;
+    uy = uy + hdt * ay;
+    uz = uz + hdt * az;
+  }
+  ux = ux + hdt * ax;
+  uy = uy + hdt * ay;
+  uz = uz + hdt * az;
+  k.vx[i] = ux;
+  k.vy[i] = uy;
+  k.vz[i] = uz;
+  const double nx = wrap_box(k.x[i] + k.dt * ux, b.L0);
+  const double ny = wrap_box(k.y[i] + k.dt * uy, b.L1);
+  const double nz = wrap_box(k.z[i] + k.dt * uz, b.L2);
+  k.x[i] = nx;
+  k.y[i] = ny;
+  k.z[i] = nz;
+  k.ps4[i] = make_double4(nx, ny, nz, (double)s);
+  const double ex = min_image(nx - k.xr[i], b.L0);
+  const double ey = min_image(ny - k.yr[i], b.L1);
+  const double ez = min_image(nz - k.zr[i], b.L2);
+  const unsigned long long moved = __ballot((ex * ex + ey * ey) + ez * ez > k.half_skin2);
+  if (moved && __lane_id() == __ffsll((long long)moved) - 1) atomicOr(&k.ds->rebuild[k.par], 1);
+}
+
 // F_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i) / r with
 // phi'(r) = eps ((-2 d)(c0 + c1 r) + c1 d^2) and f'_X(r) = (-2 t_X) d, d = rc - r,
 // summed in entry order
@@ -136,20 +194,29 @@ __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, c
   }
 }
 
+// KD: the forces are not stored but go straight into the next step's kick
+// and drift (the positions it writes are not read by this pass, which
+// gathers pf4).
+template <bool KD>
 __global__ void __launch_bounds__(BLOCK)
     k_forces(int64_t n, const double4 *__restrict__ pf4, const int32_t *__restrict__ nj,
              const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
-             double *fx, double *fy, double *fz) {
+             double *fx, double *fy, double *fz, KickDrift kd) {
   const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+  if (KD) kick_drift_clear(kd, i, (int64_t)gridDim.x * blockDim.x);
   if (i >= n) return;
   const double4 qi = pf4[i];
   const int si = sp[i];
   const int m = cnt[i];
   double ax = 0.0, ay = 0.0, az = 0.0;
   force_row(n, i, m, si, qi, pf4, nj, sp, b, p, ax, ay, az);
-  fx[i] = ax;
-  fy[i] = ay;
-  fz[i] = az;
+  if (KD) {
+    kick_drift_atom(kd, i, si, ax, ay, az, b, p);
+  } else {
+    fx[i] = ax;
+    fy[i] = ay;
+    fz[i] = az;
+  }
 }
 
 // E_i = F_{s_i}(rho_i) + 0.5 sum_j (eps d^2)(c0 + c1 r)
@@ -183,8 +250,45 @@ hipError_t launch_forces(vcsgc_ctx *c) {
                                                         b, c->pot, c->rho_f, c->fp, c->pf4);
   tstop(c, h);
   h = tstart(c, VCSGC_KT_FORCES);
-  k_forces<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b,
-                                                    c->pot, c->fx, c->fy, c->fz);
+  k_forces<false><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+      c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->fx, c->fy, c->fz, KickDrift{});
+  tstop(c, h);
+  return hipGetLastError();
+}
+
+static KickDrift kick_drift_args(vcsgc_ctx *c, double dt, bool kick_first, int par) {
+  const double hs = 0.5 * c->skin;
+  KickDrift k{};
+  k.x = c->x;
+  k.y = c->y;
+  k.z = c->z;
+  k.vx = c->vx;
+  k.vy = c->vy;
+  k.vz = c->vz;
+  k.xr = c->xr;
+  k.yr = c->yr;
+  k.zr = c->zr;
+  k.ps4 = c->ps4;
+  k.dt = dt;
+  k.half_skin2 = hs * hs;
+  k.kick_first = kick_first ? 1 : 0;
+  k.par = par;
+  k.bcount = c->bin_count;
+  k.nbins = c->reps[0].nbins;
+  k.ds = c->ds;
+  return k;
+}
+
+hipError_t launch_forces_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par) {
+  Box b{c->box[0], c->box[1], c->box[2]};
+  int h = tstart(c, VCSGC_KT_DENSITY);
+  k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
+                                                        b, c->pot, c->rho_f, c->fp, c->pf4);
+  tstop(c, h);
+  h = tstart(c, VCSGC_KT_FORCES);
+  k_forces<true><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+      c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->fx, c->fy, c->fz,
+      kick_drift_args(c, dt, kick_first, par));
   tstop(c, h);
   return hipGetLastError();
 }
@@ -200,53 +304,14 @@ hipError_t launch_energy(vcsgc_ctx *c) {
   return hipGetLastError();
 }
 
-// [v += (dt/2)(F cm) (closing the previous step) ;] v += (dt/2)(F cm);
-// x = wrap(x + dt v); raise ds->rebuild[par] when an atom has moved more than
-// skin/2 from its position at the last build.  Also readies the next
-// device-decided rebuild: the flag of the other parity (read by the previous
-// step's rebuild kernels, which have finished) is cleared, and so are the
-// search-bin counts (bcount may be NULL).
 __global__ void __launch_bounds__(BLOCK)
-    k_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
-                 const double *__restrict__ fx, const double *__restrict__ fy,
-                 const double *__restrict__ fz, const uint8_t *__restrict__ sp,
-                 const double *__restrict__ xr, const double *__restrict__ yr,
-                 const double *__restrict__ zr, double4 *ps4, Box b, PotD p, double dt,
-                 double half_skin2, int kick_first, int par, int32_t *bcount, int64_t nbins,
-                 DevState *ds) {
+    k_kick_drift(int64_t n, const double *__restrict__ fx, const double *__restrict__ fy,
+                 const double *__restrict__ fz, const uint8_t *__restrict__ sp, Box b, PotD p,
+                 KickDrift k) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (bcount)
-    for (int64_t q = i; q < nbins; q += (int64_t)gridDim.x * blockDim.x) bcount[q] = 0;
-  if (i == 0) ds->rebuild[par ^ 1] = 0;
+  kick_drift_clear(k, i, (int64_t)gridDim.x * blockDim.x);
   if (i >= n) return;
-  const int s = sp[i];
-  const double cm = p.cm[s];
-  const double hdt = 0.5 * dt;
-  const double ax = fx[i] * cm, ay = fy[i] * cm, az = fz[i] * cm;
-  double ux = vx[i], uy = vy[i], uz = vz[i];
-  if (kick_first) {
-    ux = ux + hdt * ax;
-    uy = uy + hdt * ay;
-    uz = uz + hdt * az;
-  }
-  ux = ux + hdt * ax;
-  uy = uy + hdt * ay;
-  uz = uz + hdt * az;
-  vx[i] = ux;
-  vy[i] = uy;
-  vz[i] = uz;
-  const double nx = wrap_box(x[i] + dt * ux, b.L0);
-  const double ny = wrap_box(y[i] + dt * uy, b.L1);
-  const double nz = wrap_box(z[i] + dt * uz, b.L2);
-  x[i] = nx;
-  y[i] = ny;
-  z[i] = nz;
-  ps4[i] = make_double4(nx, ny, nz, (double)s);
-  const double ex = min_image(nx - xr[i], b.L0);
-  const double ey = min_image(ny - yr[i], b.L1);
-  const double ez = min_image(nz - zr[i], b.L2);
-  const unsigned long long moved = __ballot((ex * ex + ey * ey) + ez * ez > half_skin2);
-  if (moved && __lane_id() == __ffsll((long long)moved) - 1) atomicOr(&ds->rebuild[par], 1);
+  kick_drift_atom(k, i, sp[i], fx[i], fy[i], fz[i], b, p);
 }
 
 __global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, const double *__restrict__ fx,
@@ -263,12 +328,10 @@ __global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, const doub
 
 hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par) {
   Box b{c->box[0], c->box[1], c->box[2]};
-  const double hs = 0.5 * c->skin;
   int h = tstart(c, VCSGC_KT_KICKDRIFT);
-  k_kick_drift<<<grid_for(c->n), BLOCK, 0, c->stream>>>(
-      c->n, c->x, c->y, c->z, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz, c->sp, c->xr, c->yr,
-      c->zr, c->ps4, b, c->pot, dt, hs * hs, kick_first ? 1 : 0, par, c->bin_count,
-      c->reps[0].nbins, c->ds);
+  k_kick_drift<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->fx, c->fy, c->fz, c->sp, b,
+                                                        c->pot,
+                                                        kick_drift_args(c, dt, kick_first, par));
   tstop(c, h);
   return hipGetLastError();
 }
