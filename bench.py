@@ -41,11 +41,11 @@ def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials, fused=0.0):
     forces    : (x,y,z,F') packed (32) + species (1) + row length (1) + neighbour
                 indices (4 per r < rc + skin pair) + fx,fy,fz written (24); a
                 launch that runs the next step's kick and drift instead of
-                storing the forces reads x,y,z, v and the reference positions
-                (72) and writes x,y,z, v and the packed positions (80) in place
-                of the 24 bytes of forces; `fused` is the share of such launches
+                storing the forces reads v and the reference positions (48)
+                and writes x,y,z, v and the packed positions (80) in place of
+                the 24 bytes of forces; `fused` is the share of such launches
     density   : (x,y,z,species) packed (32) + species (1) + row length (1) +
-                indices (4 per pair) + rho, F' (16) and (x,y,z,F') (32) written
+                indices (4 per pair) + rho (8) and (x,y,z,F') (32) written
     kick_drift: x,y,z,v,F,species,reference positions read (105), x,y,z,v and the
                 packed positions written (80)
     kick      : v, F, species read (49), v written (24)
@@ -57,9 +57,9 @@ def algorithmic_bytes(kind, n, pairs_md, pairs_mc, trials, fused=0.0):
                 the next sweep's draw: cell start/atom read (8+4), site and ln u
                 written (4+8); `trials` is then (trials, active cells) per launch"""
     if kind == "forces":
-        return (58 + fused * (72 + 80 - 24)) * n + 4 * pairs_md
+        return (58 + fused * (48 + 80 - 24)) * n + 4 * pairs_md
     if kind == "density":
-        return 82 * n + 4 * pairs_md
+        return 74 * n + 4 * pairs_md
     if kind == "kick_drift":
         return 185 * n
     if kind == "kick":

@@ -24,7 +24,7 @@ void free_all(vcsgc_ctx *c) {
   void *ptrs[] = {c->bin_count,  c->bin_atoms,  c->cell_count, c->cell_start, c->cell_atoms,
                   c->cell_fill,  c->mc_j,       c->mc_r,
                   c->mc_cnt,     c->md_j,       c->md_cnt,    c->xr,   c->yr,
-                  c->zr,         c->rho,        c->rho_f,      c->fp,        c->eatom, c->red,
+                  c->zr,         c->rho,        c->rho_f,      c->eatom, c->red,
                   c->rec,        c->ds,         c->ps4,        c->pf4,       c->part,
                   c->d_reps,     c->d_rs,       c->d_wg_rep,   c->d_j,        c->d_r,
                   c->d_cnt,      c->scan_tmp,   c->snap,       c->bin_pos,
@@ -481,7 +481,6 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->ps4, n));
     A(dalloc(&c->pf4, n));
     A(dalloc(&c->rho_f, n));
-    A(dalloc(&c->fp, n));
     A(dalloc(&c->eatom, n));
   }
   if (c->desc) {

@@ -299,7 +299,7 @@ struct vcsgc_ctx {
   double4 *ps4 = nullptr;  // MD: (x, y, z, species) packed for neighbour gathers
   double4 *pf4 = nullptr;  // MD: (x, y, z, F') written by the density pass
   double *rho = nullptr;                        // density cache of the sweep
-  double *rho_f = nullptr, *fp = nullptr;        // fresh density and F' (energy, MD)
+  double *rho_f = nullptr;  // fresh density (energy, MD)
   double *eatom = nullptr, *red = nullptr;
   int32_t *rec = nullptr;  // per active cell: locally accepted site or -1
   // fused stage pipeline (single system, one trial per cell and stage): site

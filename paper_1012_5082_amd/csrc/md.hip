@@ -70,12 +70,12 @@ __device__ __forceinline__ double density_row(int64_t n, int64_t i, int m, const
   return s;
 }
 
-// rho_i and F'_i = -A_{s_i} / (2 sqrt(rho_i)); also writes (x_i, y_i, z_i,
-// F'_i) for the force pass
+// rho_i, and (x_i, y_i, z_i, F'_i) with F'_i = -A_{s_i} / (2 sqrt(rho_i)) for
+// the force pass
 __global__ void __launch_bounds__(BLOCK)
     k_density_md(int64_t n, const double4 *__restrict__ ps4, const int32_t *__restrict__ nj,
                  const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
-                 double *rho, double *fp, double4 *pf4) {
+                 double *rho, double4 *pf4) {
   const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 qi = ps4[i];
@@ -83,7 +83,6 @@ __global__ void __launch_bounds__(BLOCK)
   const double s = density_row(n, i, m, qi, ps4, nj, b, p);
   rho[i] = s;
   const double f = dembed(p, sp[i], s);
-  fp[i] = f;
   pf4[i] = make_double4(qi.x, qi.y, qi.z, f);
 }
 
@@ -113,9 +112,9 @@ __device__ __forceinline__ void kick_drift_clear(const KickDrift &k, int64_t i, 
 
 // Kick and drift of atom i (species s) from its force; every active lane of
 // the wave takes part in the rebuild vote.
-__device__ __forceinline__ void kick_drift_atom(const KickDrift &k, int64_t i, int s, double fxi,
-                                                double fyi, double fzi, const Box &b,
-                                                const PotD &p) {
+__device__ __forceinline__ void kick_drift_atom(const KickDrift &k, int64_t i, int s, double x0,
+                                                double y0, double z0, double fxi, double fyi,
+                                                double fzi, const Box &b, const PotD &p) {
   const double cm = p.cm[s];
   const double hdt = 0.5 * k.dt;
   const double ax = fxi * cm, ay = fyi * cm, az = fzi * cm;
@@ -131,9 +130,9 @@ __device__ __forceinline__ void kick_drift_atom(const KickDrift &k, int64_t i, i
   k.vx[i] = ux;
   k.vy[i] = uy;
   k.vz[i] = uz;
-  const double nx = wrap_box(k.x[i] + k.dt * ux, b.L0);
-  const double ny = wrap_box(k.y[i] + k.dt * uy, b.L1);
-  const double nz = wrap_box(k.z[i] + k.dt * uz, b.L2);
+  const double nx = wrap_box(x0 + k.dt * ux, b.L0);
+  const double ny = wrap_box(y0 + k.dt * uy, b.L1);
+  const double nz = wrap_box(z0 + k.dt * uz, b.L2);
   k.x[i] = nx;
   k.y[i] = ny;
   k.z[i] = nz;
@@ -211,7 +210,8 @@ __global__ void __launch_bounds__(BLOCK)
   double ax = 0.0, ay = 0.0, az = 0.0;
   force_row(n, i, m, si, qi, pf4, nj, sp, b, p, ax, ay, az);
   if (KD) {
-    kick_drift_atom(kd, i, si, ax, ay, az, b, p);
+    // the packed positions equal x, y, z bit for bit
+    kick_drift_atom(kd, i, si, qi.x, qi.y, qi.z, ax, ay, az, b, p);
   } else {
     fx[i] = ax;
     fy[i] = ay;
@@ -247,7 +247,7 @@ hipError_t launch_forces(vcsgc_ctx *c) {
   Box b{c->box[0], c->box[1], c->box[2]};
   int h = tstart(c, VCSGC_KT_DENSITY);
   k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
-                                                        b, c->pot, c->rho_f, c->fp, c->pf4);
+                                                        b, c->pot, c->rho_f, c->pf4);
   tstop(c, h);
   h = tstart(c, VCSGC_KT_FORCES);
   k_forces<false><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
@@ -283,7 +283,7 @@ hipError_t launch_forces_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, in
   Box b{c->box[0], c->box[1], c->box[2]};
   int h = tstart(c, VCSGC_KT_DENSITY);
   k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
-                                                        b, c->pot, c->rho_f, c->fp, c->pf4);
+                                                        b, c->pot, c->rho_f, c->pf4);
   tstop(c, h);
   h = tstart(c, VCSGC_KT_FORCES);
   k_forces<true><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
@@ -297,7 +297,7 @@ hipError_t launch_energy(vcsgc_ctx *c) {
   Box b{c->box[0], c->box[1], c->box[2]};
   int h = tstart(c, VCSGC_KT_ENERGY);
   k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
-                                                        b, c->pot, c->rho_f, c->fp, c->pf4);
+                                                        b, c->pot, c->rho_f, c->pf4);
   k_energy<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->rho_f,
                                                     b, c->pot, c->eatom);
   tstop(c, h);
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(BLOCK)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   kick_drift_clear(k, i, (int64_t)gridDim.x * blockDim.x);
   if (i >= n) return;
-  kick_drift_atom(k, i, sp[i], fx[i], fy[i], fz[i], b, p);
+  kick_drift_atom(k, i, sp[i], k.x[i], k.y[i], k.z[i], fx[i], fy[i], fz[i], b, p);
 }
 
 __global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, const double *__restrict__ fx,
