@@ -80,6 +80,9 @@ __device__ __forceinline__ uint64_t sweep_of(const SweepArgs &a, uint64_t w) {
 
 // Lanes per trial: lane k of a group handles neighbour entries k and k + TL.
 constexpr int TL = 16;
+// lanes per trial in the batched pipeline's plain trials (four entries each):
+// twice the trials in flight per wave, which that throughput-bound kernel needs
+constexpr int TL_BATCH = 8;
 static_assert(KMAX <= 2 * TL, "a trial group covers at most 2*TL neighbours");
 
 // What one lane of a group of L lanes reads for the trial at site i: the
@@ -954,9 +957,10 @@ __global__ void k_pipe_init(DevState *ds, unsigned long long w0, unsigned long l
 
 // Local tests of stage (w, s) from the loaded trial data: the record of the
 // group's cell, the trial log, and the block's two count words into P.
+template <int W>
 __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t w, int64_t s,
                                                    int64_t t, int lane, int32_t i, double lnu,
-                                                   const TrialIn &v, int32_t *rec,
+                                                   const TrialInT<W> &v, int32_t *rec,
                                                    long long *P, long long *sh,
                                                    double2 *grp) {
   long long valid = 0, dn_acc = 0, tie = 0;
@@ -1008,9 +1012,10 @@ __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t 
 
 // Site and trial data of group t in stage (w, s) (site -1: empty cell or
 // past the last active cell).
+template <int L>
 __device__ __forceinline__ void pipe_trials_load(const SweepArgs &a, uint64_t w, int64_t s,
                                                  int64_t t, int lane, int32_t &i, double &lnu,
-                                                 TrialIn &v) {
+                                                 TrialInT<L> &v) {
   i = -1;
   lnu = 0.0;
   v.m = 0;
@@ -1530,11 +1535,12 @@ __global__ void k_spec_init(DevState *ds, unsigned long long w0, unsigned long l
 template <bool DA>
 __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
   constexpr int NPW = DA ? 3 : 2;  // count words per trial block
+  constexpr int LT = DA ? TL : TL_BATCH;  // lanes per trial
   __shared__ long long sh[BLOCK];
   // delayed acceptance: the descriptor slots of a group also hold its dU terms
   // when there is no descriptor list (the two are never used together)
   static_assert(sizeof(DescSlots) >= sizeof(GroupTerms), "terms fit the descriptor slots");
-  __shared__ typename std::conditional<DA, char, GroupTerms[BLOCK / TL]>::type terms;
+  __shared__ typename std::conditional<DA, char, GroupTerms[BLOCK / LT]>::type terms;
   __shared__ typename std::conditional<DA, DaShared, char>::type dash;
   __shared__ long long tot[SPEC_MAX][NPW];
   __shared__ double lg[SPEC_MAX];
@@ -1547,15 +1553,15 @@ __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
   }
   const int64_t S = a.S, ncpc = a.ncpc, nblk = a.nblk;
   const int64_t kstride = nblk * NPW;  // count words per stage
-  const int lane = threadIdx.x % TL, grp = threadIdx.x / TL;
   const int64_t b = blockIdx.x;
   if (b >= SPEC_NDEC) {
     const int64_t bt = b - SPEC_NDEC;
     if (bt < (int64_t)a.D * nblk) {
       const int k = (int)(bt / nblk);
       if (k >= m.tn) return;
+      const int lane = threadIdx.x % LT, grp = threadIdx.x / LT;
       const int64_t lb = bt - (int64_t)k * nblk;
-      const int64_t t = lb * (BLOCK / TL) + grp;
+      const int64_t t = lb * (BLOCK / LT) + grp;
       const int64_t s = m.ts + k;
       int32_t *rec = a.rec + ((int64_t)par * SPEC_MAX + k) * ncpc;
       long long *P = a.part + ((int64_t)par * SPEC_MAX + k) * kstride + lb * NPW;
@@ -1564,7 +1570,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
       } else {
         int32_t i;
         double lnu;
-        TrialIn v;
+        TrialInT<LT> v;
         pipe_trials_load(a, m.tw, s, t, lane, i, lnu, v);
         pipe_trials_finish(a, m.tw, s, t, lane, i, lnu, v, rec, P, sh, terms[grp]);
       }
@@ -1692,8 +1698,10 @@ __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
   __syncthreads();
   const int ka = kacc;
   if (ka < 0) return;
-  // commit of the accepted stage: 16 records per group, the groups' flips
-  // one after the other (sites of one stage have disjoint neighbourhoods)
+  // commit of the accepted stage: 16 records per group of TL lanes, the
+  // groups' flips one after the other (sites of one stage have disjoint
+  // neighbourhoods)
+  const int lane = threadIdx.x % TL, grp = threadIdx.x / TL;
   const int32_t *R = a.rec + ((int64_t)(par ^ 1) * SPEC_MAX + ka) * ncpc;
   for (int64_t t0 = (b * (BLOCK / TL) + grp) * TL; t0 < ncpc; t0 += (int64_t)SPEC_NDEC * BLOCK) {
     const int64_t tt = t0 + lane;
@@ -1828,7 +1836,7 @@ static hipError_t launch_pipeline(vcsgc_ctx *c, SweepArgs a, double dmu0, double
   a.stage_lnug = c->m_lnug;
   a.rec = spec ? c->s_rec : c->m_rec;
   a.part = spec ? c->s_part : c->m_part;
-  a.nblk = grid_for(a.ncpc * TL);
+  a.nblk = grid_for(a.ncpc * (spec && !a.da_mode ? TL_BATCH : TL));
   a.wdev = nullptr;
   const unsigned grid =
       spec ? (unsigned)(SPEC_NDEC + (int64_t)a.D * a.nblk + grid_for((int64_t)a.D * a.ncpc))
