@@ -81,7 +81,8 @@ __device__ __forceinline__ uint64_t sweep_of(const SweepArgs &a, uint64_t w) {
 // Lanes per trial: lane k of a group handles neighbour entries k and k + TL.
 constexpr int TL = 16;
 // lanes per trial in the batched pipeline's plain trials (four entries each):
-// twice the trials in flight per wave, which that throughput-bound kernel needs
+// twice the trials in flight per wave, which that throughput-bound kernel
+// needs (measured: 16 lanes 7% slower per sweep, 4 lanes within 1%)
 constexpr int TL_BATCH = 8;
 static_assert(KMAX <= 2 * TL, "a trial group covers at most 2*TL neighbours");
 
