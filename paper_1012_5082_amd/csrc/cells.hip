@@ -46,22 +46,29 @@ __device__ __forceinline__ int cell_of(const Grid &g, double a, double b, double
 
 // atomicAdd(&counter[key], 1) for every active lane, with one atomic per
 // distinct key in the wave (neighbouring atoms mostly share a cell); returns
-// the lane's old value plus its rank among the lanes with the same key
+// the lane's old value plus its rank among the lanes with the same key.  The
+// lanes are first grouped by key (ballots only); then the first lane of every
+// group adds the group's size, all groups at once, so the wave waits for one
+// round of atomics rather than one per distinct key.
 __device__ __forceinline__ int32_t wave_add_one(int32_t *counter, int key) {
   const int lane = __lane_id();
   unsigned long long todo = __ballot(1);
-  int32_t slot = 0;
+  int leader_of = lane, rank = 0, size = 0;
   while (todo) {
     const int leader = __ffsll((long long)todo) - 1;
     const int lkey = __shfl(key, leader);
     const unsigned long long same = __ballot(key == lkey) & todo;
-    int32_t base = 0;
-    if (lane == leader) base = atomicAdd(&counter[lkey], (int32_t)__popcll(same));
-    base = __shfl(base, leader);
-    if (same & (1ull << lane)) slot = base + (int32_t)__popcll(same & ((1ull << lane) - 1ull));
+    if (same & (1ull << lane)) {
+      leader_of = leader;
+      rank = (int)__popcll(same & ((1ull << lane) - 1ull));
+    }
+    if (lane == leader) size = (int)__popcll(same);
     todo &= ~same;
   }
-  return slot;
+  int32_t base = 0;
+  if (lane == leader_of) base = atomicAdd(&counter[key], (int32_t)size);
+  base = __shfl(base, leader_of);
+  return base + (int32_t)rank;
 }
 
 __global__ void k_cell_count(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
