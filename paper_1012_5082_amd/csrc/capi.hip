@@ -115,6 +115,7 @@ vcsgc_status refresh_mc(vcsgc_ctx *c) {
     if (h.overflow)
       return fail(c, VCSGC_E_OVERFLOW, "a site has more than 32 neighbours within rc");
     c->kmax_used = h.kmax_used;
+    c->mc_stats_stale = false;
     c->mc_valid = true;
     return VCSGC_OK;
   }
@@ -127,7 +128,7 @@ vcsgc_status refresh_mc(vcsgc_ctx *c) {
 vcsgc_status refresh_mc_from_md(vcsgc_ctx *c) {
   VC_CHECK(c, vc::launch_bin_cells(c, c->reps[0]), "binning");
   VC_CHECK(c, vc::launch_mc_from_md(c), "neighbour list");
-  VC_CHECK(c, vc::launch_mc_row_stats(c), "neighbour list");
+  c->mc_stats_stale = true;  // taken when asked for (vcsgc_get_info)
   VC_CHECK(c, hipMemcpyAsync(c->rho, c->rho_f, sizeof(double) * c->n, hipMemcpyDeviceToDevice,
                              c->stream),
            "density");
@@ -952,6 +953,10 @@ vcsgc_status vcsgc_get_info(vcsgc_ctx *c, vcsgc_info *out) {
   for (int d = 0; d < 3; ++d) out->n_cells[d] = c->nc[d];
   out->stages_per_sweep = c->reps.size() == 1 ? vc::stages_per_sweep(c) : c->S;
   out->kmax = vc::KMAX;
+  if (c->mc_valid && c->mc_stats_stale) {
+    VC_CHECK(c, vc::launch_mc_row_stats(c), "neighbour list");
+    c->mc_stats_stale = false;
+  }
   hipError_t e;
   vc::DevState h = read_state(c, &e);
   if (e != hipSuccess) return dev_fail(c, e, "info");

@@ -329,6 +329,7 @@ struct vcsgc_ctx {
   bool rho_f_fresh = false;
   uint64_t w = 0;  // sweep counter
   int kmax_used = 0;
+  bool mc_stats_stale = false;  // the r < rc list's row statistics not yet taken
   int64_t md_rebuilds = 0;
 
   double *tlog = nullptr, *slog = nullptr;

@@ -343,11 +343,12 @@ __device__ __forceinline__ void desc_du_group(const SweepArgs &a, int64_t i, int
   du = own + pair + emb;
 }
 
+// Cell of active-cell index t (< ncpc < 2^31) in a stage of the given colour.
 __device__ __forceinline__ int64_t colour_cell(const SweepArgs &a, int colour, int64_t t) {
-  const int hx = a.n0 >> 1, hy = a.n1 >> 1;
-  const int64_t ia = t % hx, ib = (t / hx) % hy, ic = t / ((int64_t)hx * hy);
-  const int64_t cx = 2 * ia + (colour & 1), cy = 2 * ib + ((colour >> 1) & 1),
-                cz = 2 * ic + ((colour >> 2) & 1);
+  const uint32_t hx = (uint32_t)(a.n0 >> 1), hy = (uint32_t)(a.n1 >> 1);
+  const uint32_t u = (uint32_t)t, q = u / hx, ia = u - q * hx, ic = q / hy, ib = q - ic * hy;
+  const int64_t cx = 2 * (int64_t)ia + (colour & 1), cy = 2 * (int64_t)ib + ((colour >> 1) & 1),
+                cz = 2 * (int64_t)ic + ((colour >> 2) & 1);
   return cx + (int64_t)a.n0 * (cy + (int64_t)a.n1 * cz);
 }
 
@@ -911,10 +912,10 @@ __global__ void __launch_bounds__(BLOCK) k_commit_chain(SweepArgs a, uint64_t w_
 
 // Site of active cell t in stage s of sweep w and ln u of its local test
 // (the draws of k_sites for one trial per cell); t == 0 also writes ln u_g.
-__device__ __forceinline__ void draw_site(const SweepArgs &a, uint64_t w, int64_t s, int64_t t,
-                                          int32_t *sites, double *lnus, double *lnug,
-                                          double *lnus2) {
-  const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+// g: the stage's own counter draw, philox(seed, replica, w, s, 0, 0).
+__device__ __forceinline__ void draw_site_g(const SweepArgs &a, uint64_t w, int64_t s, int64_t t,
+                                            const U4 &g, int32_t *sites, double *lnus,
+                                            double *lnug, double *lnus2) {
   if (t == 0) *lnug = log(unit_open(g.v[1]));
   const int64_t cell = colour_cell(a, (int)(g.v[0] >> 61), t);
   const int32_t st = a.cstart[cell];
@@ -931,14 +932,32 @@ __device__ __forceinline__ void draw_site(const SweepArgs &a, uint64_t w, int64_
   lnus[t] = lnu;
 }
 
+__device__ __forceinline__ void draw_site(const SweepArgs &a, uint64_t w, int64_t s, int64_t t,
+                                          int32_t *sites, double *lnus, double *lnug,
+                                          double *lnus2) {
+  draw_site_g(a, w, s, t, philox(a.seed, a.replica, w, (uint64_t)s, 0, 0), sites, lnus, lnug,
+              lnus2);
+}
+
 // The whole site table of sweep w (into its half of the two-sweep ring).
+// (When a stage has at least BLOCK active cells, a block spans at most two
+// stages, whose counter draws two threads make for the whole block.)
 __global__ void __launch_bounds__(BLOCK) k_sites_ring(SweepArgs a, uint64_t w) {
-  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  __shared__ U4 gs[2];
+  const int64_t q0 = (int64_t)blockIdx.x * BLOCK, q = q0 + threadIdx.x;
+  const int64_t s0 = q0 / a.ncpc;
+  const bool shared = a.ncpc >= BLOCK;
+  if (shared) {
+    if (threadIdx.x < 2 && s0 + threadIdx.x < a.S)
+      gs[threadIdx.x] = philox(a.seed, a.replica, w, (uint64_t)(s0 + threadIdx.x), 0, 0);
+    __syncthreads();
+  }
   if (q >= a.S * a.ncpc) return;
   const int64_t s = q / a.ncpc, t = q - s * a.ncpc;
   const int64_t row = (int64_t)(w & 1) * a.S + s;
-  draw_site(a, w, s, t, a.sites + row * a.ncpc, a.site_lnu + row * a.ncpc, a.stage_lnug + row,
-            a.site_lnu2 ? a.site_lnu2 + row * a.ncpc : nullptr);
+  const U4 g = shared ? gs[s - s0] : philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
+  draw_site_g(a, w, s, t, g, a.sites + row * a.ncpc, a.site_lnu + row * a.ncpc,
+              a.stage_lnug + row, a.site_lnu2 ? a.site_lnu2 + row * a.ncpc : nullptr);
 }
 
 __global__ void k_pipe_init(DevState *ds, unsigned long long w0, unsigned long long w_end) {
