@@ -69,8 +69,11 @@ bool is_fin(double v) { return std::isfinite(v); }
 vc::DevState read_state(vcsgc_ctx *c, hipError_t *e) {
   vc::DevState h;
   std::memset(&h, 0, sizeof(h));
-  *e = hipMemcpyAsync(&h, c->ds, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  // through the pinned copy when there is one (a pageable copy is staged)
+  vc::DevState *dst = c->h_state ? c->h_state : &h;
+  *e = hipMemcpyAsync(dst, c->ds, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (*e == hipSuccess) *e = hipStreamSynchronize(c->stream);
+  if (*e == hipSuccess && dst != &h) h = *dst;
   return h;
 }
 
