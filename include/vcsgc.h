@@ -46,6 +46,7 @@ typedef enum {
   VCSGC_E_DEVICE = -4,
   VCSGC_E_STATE = -5,
   VCSGC_E_NO_SURROGATE = -6,
+  VCSGC_E_BARRIER_TIMEOUT = -7, /* a bounded wait of the persistent sweep timed out (sticky) */
   VCSGC_E_OVERFLOW = -8
 } vcsgc_status;
 
@@ -86,7 +87,10 @@ typedef struct {
 
 typedef struct {
   uint64_t sweeps_done; /* cumulative sweep counter w (Philox counter word 0) */
-  int64_t n_b;          /* current number of B atoms */
+  int64_t n_b;          /* current number of B atoms (get only; set recounts it) */
+  uint64_t seed;        /* Philox key word 0 of the last sweep call (0 before any) */
+  double *rho_dev;      /* caller DEVICE buffer of N doubles or NULL: get copies the
+                           density cache into it, set restores the cache from it */
 } vcsgc_state;
 
 typedef struct {
@@ -191,6 +195,15 @@ vcsgc_status vcsgc_set_tuning(vcsgc_ctx *ctx, int32_t strategy, int32_t trials_p
 vcsgc_status vcsgc_get_tuning(vcsgc_ctx *ctx, int32_t *strategy, int32_t *trials_per_group,
                               int32_t *workgroups);
 
+/* Bound on the waits of the persistent sweep (strategies 0 and 1): a
+ * workgroup that polls a per-replica barrier `polls` times without seeing
+ * every workgroup of its replica arrive abandons the call; vcsgc_sweep and
+ * vcsgc_sweep_batch then return VCSGC_E_BARRIER_TIMEOUT and the context is
+ * left in the error state (part of a stage may have been committed).
+ * polls >= 1; the default, 2^24 polls with a short sleep each, is seconds.
+ * For failure-handling tests and diagnostics. */
+vcsgc_status vcsgc_set_wait_limit(vcsgc_ctx *ctx, uint32_t polls);
+
 /* Fresh EAM evaluation at the current positions and species: rho, per-atom
  * energies E_i = F_{s_i}(rho_i) + 1/2 sum_j phi(r_ij) and, if want_forces,
  * forces F_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i)/r
@@ -223,8 +236,17 @@ vcsgc_status vcsgc_set_log(vcsgc_ctx *ctx, double *tlog_dev, int64_t tcap, doubl
 /* Number of records written so far (may exceed the capacity). */
 vcsgc_status vcsgc_log_counts(vcsgc_ctx *ctx, int64_t *n_trials, int64_t *n_stages);
 
-/* Chain state for checkpoint/resume: the cumulative sweep counter and n_B.
- * set_state only moves the counter (n_B is recomputed from the species). */
+/* Chain state for checkpoint/resume: the cumulative sweep counter, n_B, the
+ * seed of the last sweep call and, through rho_dev, the density cache
+ * rho_i = sum_j f_{s_j}(r_ij) that the trials of Eq. trans_vcsgc_par1 read.
+ * The cache is updated in place by every committed flip, so after many
+ * commits it differs in the last bits from a fresh sum; restoring it (with
+ * the caller's species and positions) continues the chain bit for bit.
+ * set_state: sets the counter and the recorded seed, recounts n_B from the
+ * species, rebuilds the cell and neighbour lists from the positions and, if
+ * rho_dev is not NULL, replaces the fresh density cache by rho_dev (else the
+ * fresh sum is kept).  Synchronizes the stream.  Errors: VCSGC_E_INVALID_ARG
+ * for a NULL state. */
 vcsgc_status vcsgc_get_state(vcsgc_ctx *ctx, vcsgc_state *out);
 vcsgc_status vcsgc_set_state(vcsgc_ctx *ctx, const vcsgc_state *in);
 

@@ -1,0 +1,95 @@
+"""Calibrate dmu0 for the 16-grain polycrystal workload (1.96M sites, 700 K,
+cbar = 0.03, kappa = 1000 eV) on that system itself, with the oracle only.
+
+Parameter strategy of Sec. III.C: the acceptance of the parallel VC-SGC
+sweep is largest when dmu0 equals the chemical driving force dmu of the
+state being sampled, and Eq. gforce gives that driving force from a VC-SGC
+run: dmu = phi + 2 kappa <c> = dmu0 + 2 kappa (<c> - cbar) (kappa per site).
+The fixed point dmu0 <- dmu is iterated here.
+
+The alloy is supersaturated at this concentration and temperature, so the
+driving force of the chain drifts as B atoms cluster; the estimate is taken
+over the window of sweeps a benchmark run covers from the initial species
+(WINDOW sweeps with the benchmark's seed), with <c> averaged over every
+stage of the window.  Positions: the workload's lattice after MD_STEPS
+velocity-Verlet steps of 1 fs from its Maxwell-Boltzmann velocities at 700 K
+(a thermal snapshot, held fixed while the sweeps run).
+
+Writes paper_1012_5082_amd/dmu_c3.json.  Calls only the oracle and the
+seeded input generators.
+
+    python oracle/calibrate_dmu_c3.py
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1012_5082_amd import inputs as I  # noqa: E402
+from paper_1012_5082_amd import workloads as W  # noqa: E402
+
+OUT = os.path.join(ROOT, "paper_1012_5082_amd", "dmu_c3.json")
+MD_STEPS = 60
+WINDOW = 25
+MAX_ITERS = 6
+TOL = 2e-4  # eV
+
+
+def window_stats(x, y, z, d, pot, nl, dmu0, threads):
+    """WINDOW sweeps from the initial species: per-stage mean n, mean local
+    drift dn_tot and stage acceptance."""
+    st = O.SweepState(x, y, z, d["box"], d["species"], pot, nl=nl)
+    n0 = int(st.n_b[0])
+    _, sl = O.sweep_omp(st, dmu0, d["kappa"], d["cbar"], d["T"], WINDOW, d["seed"],
+                        threads=threads, log_stages=WINDOW * 400)
+    dn, acc = sl[:, 3], sl[:, 5]
+    n_stage = n0 + np.cumsum(np.where(acc > 0, dn, 0))
+    return float(np.mean(n_stage)), float(np.mean(dn)), float(np.mean(acc > 0))
+
+
+def main():
+    threads = len(os.sched_getaffinity(0))
+    pot = I.params("FS-P1")
+    t0 = time.time()
+    d = W.c3(calibrated=False)
+    N = d["x"].size
+    print(f"c3: {N} sites, start dmu0 = {d['dmu0']:+.5f} (rigid-lattice table)", flush=True)
+    out = O.md(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"], d["species"], d["box"], pot,
+               d["dt"], MD_STEPS)
+    x, y, z = out[0], out[1], out[2]
+    print(f"thermal snapshot after {MD_STEPS} MD steps ({time.time() - t0:.0f} s)", flush=True)
+    nl = O.neighbors(x, y, z, d["box"], pot.rc, vectors=False)
+    dmu0 = d["dmu0"]
+    iters = []
+    for it in range(MAX_ITERS):
+        n_mean, drift, acc = window_stats(x, y, z, d, pot, nl, dmu0, threads)
+        est = dmu0 + 2.0 * d["kappa"] * (n_mean / N - d["cbar"])
+        iters.append({"dmu0": round(dmu0, 6), "mean_n_minus_Ncbar": round(n_mean - N * d["cbar"], 3),
+                      "mean_local_dn_tot": round(drift, 3), "stage_acceptance": round(acc, 4),
+                      "gforce_dmu": round(est, 6)})
+        print(iters[-1], flush=True)
+        done = abs(est - dmu0) < TOL
+        dmu0 = est
+        if done:
+            break
+    res = {"T": d["T"], "cbar": d["cbar"], "kappa": d["kappa"], "n_sites": N,
+           "dmu0": round(dmu0, 5),
+           "method": (f"Eq. gforce fixed point dmu0 <- dmu0 + 2 kappa (<c> - cbar), <c> over every "
+                      f"stage of {WINDOW} sweeps from the initial species (seed {d['seed']}), "
+                      f"positions after {MD_STEPS} MD steps of 1 fs at 700 K, FS-P1"),
+           "iterations": iters}
+    with open(OUT, "w") as f:
+        json.dump(res, f, indent=1)
+    print("wrote", OUT, f"({time.time() - t0:.0f} s)")
+
+
+if __name__ == "__main__":
+    main()

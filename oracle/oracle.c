@@ -932,6 +932,18 @@ static int or_da_local(const or_da *da, int64_t w, int64_t s, int64_t c, int64_t
       *status = -3;
       return 0;
     }
+    if (da->dlog && da->dstart) {
+      /* the descriptors the surrogate values were computed from, at this
+       * trial's state, for checking those values against or_mlp_forward */
+      or_da *dm = (or_da *)da;
+      if (dm->dn < dm->dcap) {
+        double *L = dm->dlog + 23 * dm->dn;
+        L[0] = (double)w; L[1] = (double)s; L[2] = (double)c;
+        or_descriptor(i, da->dstart, da->dnj, da->dnr, species, rho, p, 0, L + 3);
+        or_descriptor(i, da->dstart, da->dnj, da->dnr, species, rho, p, 1, L + 13);
+      }
+      dm->dn++;
+    }
   } else if (da->mode == OR_DA_PERFECT) {
     du = or_delta_u(i, start, nj, nr, species, rho, p);
     have_du = 1;
@@ -1031,5 +1043,162 @@ int or_md(int64_t n, double *x, double *y, double *z, double *vx, double *vy, do
       vz[i] = vz[i] + hdt * (fz[i] * c);
     }
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* All-core CPU baseline of the plain sweep (one trial per active cell per   */
+/* stage, no surrogate).  Same chain as or_sweep: the trials of a stage's    */
+/* active cells read only state that no other trial of the stage writes     */
+/* (same-colour cells are at least r_dep >= 2 rc apart, Sec. III.A), so they */
+/* are evaluated by several threads; the integer sum dn_tot, the counters    */
+/* and the record list are then taken serially in ascending cell order, the  */
+/* global test is the serial one, and the commits touch disjoint             */
+/* neighbourhoods.  Every value is therefore bitwise that of or_sweep.       */
+/* ------------------------------------------------------------------------ */
+#include <omp.h>
+
+int or_sweep_omp(int64_t n, const double *x, const double *y, const double *z,
+                 const double box[3], const int64_t *start, const int32_t *nj,
+                 const double *nr, uint8_t *species, double *rho, int64_t *n_b,
+                 const or_pot *p, const or_sweep_args *a, double *vx, double *vy, double *vz,
+                 double *slog, int64_t scap, int64_t *sn, int n_threads, or_stats *st) {
+  if (a->local_steps > 1 || a->one_cell) return -3;
+  if (n < 1 || !(a->temp > 0.0) || !(a->kappa >= 0.0)) return -1;
+  int32_t nc[3];
+  if (or_cell_grid(box, a->r_dep, nc)) return -2;
+  int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
+  int32_t *cstart = (int32_t *)calloc((size_t)ncells + 1, sizeof(int32_t));
+  int32_t *catoms = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *cof = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  for (int64_t i = 0; i < n; ++i) {
+    const double *u[3] = {x, y, z};
+    int b[3];
+    for (int d = 0; d < 3; ++d) {
+      b[d] = (int)(u[d][i] / (box[d] / nc[d]));
+      if (b[d] < 0) b[d] = 0;
+      if (b[d] >= nc[d]) b[d] = nc[d] - 1;
+    }
+    cof[i] = b[0] + nc[0] * (b[1] + nc[1] * b[2]);
+    cstart[cof[i] + 1]++;
+  }
+  for (int64_t c = 0; c < ncells; ++c) cstart[c + 1] += cstart[c];
+  {
+    int32_t *fill = (int32_t *)malloc((size_t)ncells * sizeof(int32_t));
+    memcpy(fill, cstart, (size_t)ncells * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) catoms[fill[cof[i]]++] = (int32_t)i;
+    free(fill);
+  }
+  /* the cells of each colour in ascending id */
+  int64_t *col_cells = (int64_t *)malloc((size_t)ncells * sizeof(int64_t));
+  int64_t col_start[9] = {0};
+  for (int64_t c = 0; c < ncells; ++c) {
+    int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((int64_t)nc[0] * nc[1]));
+    col_start[1 + ((cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2))]++;
+  }
+  for (int k = 0; k < 8; ++k) col_start[k + 1] += col_start[k];
+  {
+    int64_t fill[8];
+    memcpy(fill, col_start, sizeof(fill));
+    for (int64_t c = 0; c < ncells; ++c) {
+      int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((int64_t)nc[0] * nc[1]));
+      col_cells[fill[(cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2)]++] = c;
+    }
+  }
+  int64_t S = 8 * ((n + ncells - 1) / ncells);
+  double beta = 1.0 / (OR_KB * a->temp);
+  double kN = a->kappa / (double)n;
+  uint64_t key[2] = {a->seed, a->replica};
+  int64_t maxc = 0;
+  for (int k = 0; k < 8; ++k)
+    if (col_start[k + 1] - col_start[k] > maxc) maxc = col_start[k + 1] - col_start[k];
+  int64_t *t_site = (int64_t *)malloc((size_t)(maxc > 0 ? maxc : 1) * sizeof(int64_t));
+  int8_t *t_state = (int8_t *)malloc((size_t)(maxc > 0 ? maxc : 1)); /* -1 empty, 0 reject, 1 accept */
+  int8_t *t_tie = (int8_t *)malloc((size_t)(maxc > 0 ? maxc : 1));
+  int32_t *rec = (int32_t *)malloc((size_t)(maxc > 0 ? maxc : 1) * sizeof(int32_t));
+  memset(st, 0, sizeof(*st));
+  int64_t nsl = 0;
+  if (n_threads < 1) n_threads = 1;
+
+  for (int64_t w = a->w0; w < a->w0 + a->n_sweeps; ++w) {
+    for (int64_t s = 0; s < S; ++s) {
+      uint64_t ctr[4] = {(uint64_t)w, (uint64_t)s, 0, 0}, g[4];
+      or_philox4x64_10(key, ctr, g);
+      int colour = (int)(g[0] >> 61);
+      const int64_t *cells = col_cells + col_start[colour];
+      int64_t m_act = col_start[colour + 1] - col_start[colour];
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+      for (int64_t q = 0; q < m_act; ++q) {
+        int64_t c = cells[q];
+        if (cstart[c + 1] == cstart[c]) {
+          t_state[q] = -1;
+          continue;
+        }
+        uint64_t tc[4] = {(uint64_t)w, (uint64_t)s, (uint64_t)c, 1}, t[4];
+        or_philox4x64_10(key, tc, t);
+        int64_t i = or_site(t, cstart, catoms, c);
+        int dn;
+        double du, margin;
+        int acc = or_local_test(i, t, start, nj, nr, species, rho, p, beta, a->dmu0, &du, &dn,
+                                &margin);
+        t_site[q] = i;
+        t_state[q] = (int8_t)acc;
+        t_tie[q] = (int8_t)(fabs(margin) < OR_TIE);
+      }
+      int64_t nrec = 0, dn_tot = 0;
+      for (int64_t q = 0; q < m_act; ++q) {
+        if (t_state[q] < 0) continue;
+        st->trials++;
+        st->near_ties += t_tie[q];
+        if (t_state[q]) {
+          st->local_accepts++;
+          rec[nrec++] = (int32_t)t_site[q];
+          dn_tot += 1 - 2 * (int)species[t_site[q]];
+        }
+      }
+      st->stages++;
+      int gacc = -1;
+      double xg = 0.0, mg = 0.0;
+      if (nrec > 0) {
+        double tt = (double)*n_b - (double)n * a->cbar;
+        double dnd = (double)dn_tot;
+        xg = beta * kN * dnd * (dnd + 2.0 * tt);
+        double lnug = log(or_unit(g[1]));
+        mg = lnug + xg;
+        gacc = lnug < -xg;
+        if (fabs(mg) < OR_TIE) st->near_ties++;
+        if (gacc) {
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+          for (int64_t k = 0; k < nrec; ++k) {
+            int64_t i = rec[k];
+            int s0 = species[i];
+            or_commit(i, start, nj, nr, species, rho, p);
+            if (vx) {
+              double m0 = s0 ? a->mass_b : a->mass_a, m1 = s0 ? a->mass_a : a->mass_b;
+              double f = sqrt(m0 / m1);
+              vx[i] = vx[i] * f;
+              vy[i] = vy[i] * f;
+              vz[i] = vz[i] * f;
+            }
+          }
+          *n_b += dn_tot;
+          st->flips += nrec;
+          st->stage_accepts++;
+        }
+      }
+      if (slog && nsl < scap) {
+        double *L = slog + 8 * nsl;
+        L[0] = (double)w; L[1] = (double)s; L[2] = (double)colour; L[3] = (double)dn_tot;
+        L[4] = (double)nrec; L[5] = (double)gacc; L[6] = xg; L[7] = mg;
+      }
+      nsl++;
+    }
+    st->sum_n += (double)*n_b;
+    st->sum_n2 += (double)*n_b * (double)*n_b;
+  }
+  st->n_final = *n_b;
+  if (sn) *sn = nsl;
+  free(t_site); free(t_state); free(t_tie); free(rec);
+  free(col_cells); free(cstart); free(catoms); free(cof);
   return 0;
 }

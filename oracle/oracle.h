@@ -90,6 +90,16 @@ int or_sweep(int64_t n, const double *x, const double *y, const double *z, const
              double *slog, int64_t scap, int64_t *sn,
              const double *over, int64_t n_over, or_stats *st);
 
+/* All-core CPU baseline of or_sweep for the plain scheme (local_steps 1, no
+ * one-cell mode, no trial log or overrides): the trials of each stage run on
+ * n_threads OpenMP threads; counters, records, the global test and the
+ * commits are those of or_sweep, so the chain is bitwise the same. */
+int or_sweep_omp(int64_t n, const double *x, const double *y, const double *z,
+                 const double box[3], const int64_t *start, const int32_t *nj,
+                 const double *nr, uint8_t *species, double *rho, int64_t *n_b,
+                 const or_pot *p, const or_sweep_args *a, double *vx, double *vy, double *vz,
+                 double *slog, int64_t scap, int64_t *sn, int n_threads, or_stats *st);
+
 /* ---- surrogate delayed acceptance ------------------------------------ */
 
 /* Local descriptor of site i (10 values): [s_i, nB1, nB2, nB3, n1, n2, n3,
@@ -143,6 +153,12 @@ typedef struct {
   const int32_t *dnj;
   const double *dnr;
   int64_t stage1_pass; /* out: trials passing the surrogate stage */
+  /* OR_DA_TABLE with the descriptor list given: every trial appends
+   * (w, s, cell, descriptor of the current state [10], descriptor of the
+   * state with the site flipped [10]) to dlog (23 doubles per row, at most
+   * dcap rows); dn counts the rows (it may exceed dcap). */
+  double *dlog;
+  int64_t dcap, dn;
 } or_da;
 
 /* The same sweep with the delayed-acceptance local test (Christen & Fox):

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("VCSGC_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 SRC = os.path.join(_HERE, "oracle.c")
 
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11"]
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11", "-fopenmp"]
 
 
 def build(force: bool = True) -> str:
@@ -62,7 +62,8 @@ class Mlp(C.Structure):
 class Da(C.Structure):
     _fields_ = [("mode", C.c_int), ("table", C.c_void_p), ("n_table", C.c_int64),
                 ("mlp", C.c_void_p), ("dstart", C.c_void_p), ("dnj", C.c_void_p),
-                ("dnr", C.c_void_p), ("stage1_pass", C.c_int64)]
+                ("dnr", C.c_void_p), ("stage1_pass", C.c_int64), ("dlog", C.c_void_p),
+                ("dcap", C.c_int64), ("dn", C.c_int64)]
 
 
 DA_MODES = {"off": 0, "table": 1, "perfect": 2, "zero": 3, "mlp": 4}
@@ -96,6 +97,9 @@ def lib():
         L.or_sweep.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                _P, _P, _P, _P, C.c_int64, _P, _P, C.c_int64, _P, _P,
                                C.c_int64, _P]
+        L.or_sweep_omp.restype = C.c_int
+        L.or_sweep_omp.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                   _P, _P, _P, _P, C.c_int64, _P, C.c_int, _P]
         L.or_sweep_da.restype = C.c_int
         L.or_sweep_da.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                   _P, _P, C.c_int64, _P, _P, C.c_int64, _P, _P]
@@ -274,6 +278,32 @@ def sweep(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, replica=0, r_dep
     return s.as_dict(), tlog, slog
 
 
+def sweep_omp(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, threads=None, replica=0,
+              r_dep=None, log_stages=0, mass_a=55.845, mass_b=63.546):
+    """or_sweep's plain chain with the trials of each stage on several host
+    threads (bitwise the serial chain); returns (stats, slog)."""
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    if r_dep is None:
+        r_dep = 2.0 * st.pot.rc
+    a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
+                  int(st.w), int(n_sweeps), float(r_dep), 0, float(mass_a), float(mass_b), 1)
+    slog = np.zeros((max(log_stages, 0), 8)) if log_stages else None
+    sn = np.zeros(1, dtype=np.int64)
+    s = Stats()
+    P = pot_struct(st.pot)
+    rc = lib().or_sweep_omp(st.n, _p(st.x), _p(st.y), _p(st.z), _p(st.box), _p(st.nl.start),
+                            _p(st.nl.j), _p(st.nl.r), _p(st.species), _p(st.rho), _p(st.n_b),
+                            C.byref(P), C.byref(a), _p(st.vx), _p(st.vy), _p(st.vz),
+                            _p(slog), int(log_stages), _p(sn), int(threads), C.byref(s))
+    if rc != 0:
+        raise ValueError(f"or_sweep_omp failed ({rc})")
+    st.w += int(n_sweeps)
+    if slog is not None:
+        slog = slog[:min(int(sn[0]), log_stages)]
+    return s.as_dict(), slog
+
+
 def md(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, mass_a=55.845, mass_b=63.546):
     """Velocity Verlet; returns new arrays (x, y, z, vx, vy, vz, fx, fy, fz, rho)."""
     x, y, z = _f64(x).copy(), _f64(y).copy(), _f64(z).copy()
@@ -366,8 +396,11 @@ def mlp_grad(m: MlpParams, d, t, bf16_emul=False):
 
 def sweep_da(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, mode, replica=0, r_dep=None,
              one_cell=False, table=None, mlp: MlpParams | None = None,
-             desc_nl: NeighborList | None = None, log_trials=0, log_stages=0):
-    """Delayed-acceptance sweeps; returns (stats, stage-1 passes, tlog, slog)."""
+             desc_nl: NeighborList | None = None, log_trials=0, log_stages=0, log_desc=0):
+    """Delayed-acceptance sweeps; returns (stats, stage-1 passes, tlog, slog),
+    and with log_desc > 0 (table mode with desc_nl) also the descriptor log:
+    rows (w, s, cell, current-state descriptor [10], flipped-state
+    descriptor [10]) of every trial, at the trial's state."""
     L = lib()
     if r_dep is None:
         r_dep = 2.0 * st.pot.rc
@@ -387,6 +420,10 @@ def sweep_da(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, mode, replica
         da.mlp = C.cast(C.pointer(ms), C.c_void_p)
     if desc_nl is not None:
         da.dstart, da.dnj, da.dnr = _p(desc_nl.start), _p(desc_nl.j), _p(desc_nl.r)
+    dlog = None
+    if log_desc:
+        dlog = np.zeros((log_desc, 23))
+        da.dlog, da.dcap = _p(dlog), int(log_desc)
     tlog = np.zeros((max(log_trials, 0), 8)) if log_trials else None
     slog = np.zeros((max(log_stages, 0), 8)) if log_stages else None
     tn, sn = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
@@ -403,4 +440,6 @@ def sweep_da(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, mode, replica
         tlog = tlog[:min(int(tn[0]), log_trials)]
     if slog is not None:
         slog = slog[:min(int(sn[0]), log_stages)]
+    if dlog is not None:
+        return s.as_dict(), int(da.stage1_pass), tlog, slog, dlog[:min(int(da.dn), log_desc)]
     return s.as_dict(), int(da.stage1_pass), tlog, slog

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvcsgc.so")
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BOX_TOO_SMALL", -3: "OUT_OF_MEMORY", -4: "DEVICE",
-          -5: "STATE", -6: "NO_SURROGATE", -8: "OVERFLOW"}
+          -5: "STATE", -6: "NO_SURROGATE", -7: "BARRIER_TIMEOUT", -8: "OVERFLOW"}
 
 
 class VcsgcError(RuntimeError):
@@ -65,7 +65,8 @@ N_PARAMS = 4929
 
 
 class State(C.Structure):
-    _fields_ = [("sweeps_done", C.c_uint64), ("n_b", C.c_int64)]
+    _fields_ = [("sweeps_done", C.c_uint64), ("n_b", C.c_int64), ("seed", C.c_uint64),
+                ("rho_dev", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -126,6 +127,8 @@ def lib():
         L.vcsgc_get_info.argtypes = [_P, C.POINTER(Info)]
         L.vcsgc_kernel_timing.restype = st
         L.vcsgc_kernel_timing.argtypes = [_P, C.c_uint32]
+        L.vcsgc_set_wait_limit.restype = st
+        L.vcsgc_set_wait_limit.argtypes = [_P, C.c_uint32]
         L.vcsgc_set_local_steps.restype = st
         L.vcsgc_set_local_steps.argtypes = [_P, C.c_int32]
         L.vcsgc_kernel_timing_sampled.restype = st
@@ -314,13 +317,25 @@ class VCSGC:
             sl = sl[np.lexsort((sl[:, 1], sl[:, 0]))]
         return tl, sl, nt.value, ns.value
 
-    def get_state(self):
+    def get_state(self, with_rho=False):
+        """Checkpoint: sweep counter, n_B, seed of the last call and, with
+        with_rho, a device copy of the density cache."""
+        import torch
         st = State()
+        rho = None
+        if with_rho:
+            rho = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            st.rho_dev = rho.data_ptr()
         self._check(lib().vcsgc_get_state(self._h, C.byref(st)), "get_state")
-        return {"sweeps_done": st.sweeps_done, "n_b": st.n_b}
+        out = {"sweeps_done": st.sweeps_done, "n_b": st.n_b, "seed": st.seed}
+        if with_rho:
+            out["rho"] = rho
+        return out
 
-    def set_state(self, sweeps_done):
-        st = State(int(sweeps_done), 0)
+    def set_state(self, sweeps_done, seed=0, rho=None):
+        """Resume: counter and seed; rho (a device tensor of N doubles) replaces
+        the density cache."""
+        st = State(int(sweeps_done), 0, int(seed), None if rho is None else rho.data_ptr())
         self._check(lib().vcsgc_set_state(self._h, C.byref(st)), "set_state")
 
     def rho(self):
@@ -356,6 +371,10 @@ class VCSGC:
     def set_tuning(self, strategy="graph", trials_per_group=1):
         self._check(lib().vcsgc_set_tuning(self._h, STRATEGIES[strategy], int(trials_per_group)),
                     "set_tuning")
+
+    def set_wait_limit(self, polls):
+        """Polls before a persistent-sweep barrier wait is abandoned."""
+        self._check(lib().vcsgc_set_wait_limit(self._h, int(polls)), "set_wait_limit")
 
     def set_local_steps(self, k):
         """Trials per active cell per stage (local chains; 1 = the plain scheme)."""
@@ -556,3 +575,4 @@ class Mlp:
                                          desc.shape[0], g.ctypes.data_as(_P), C.byref(loss)),
                     "grad")
         return loss.value, g
+

@@ -604,6 +604,7 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
     vcsgc_status st = ensure_mc(c);
     if (st) return st;
   }
+  c->last_seed = seed;
   if (n_sweeps > 0) c->rho_f_fresh = false;
   if (c->local_steps > 1 && (c->da_mode || c->smp_cap > 0))
     return fail(c, VCSGC_E_INVALID_ARG,
@@ -644,10 +645,13 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
     vc::tstop(c, h);
   }
   c->w += (uint64_t)n_sweeps;
-  if (out) {
-    int err = 0;
-    VC_CHECK(c, vc::persist_read_stats(c, out, &err), "sweep");
-    if (err) return fail(c, VCSGC_E_DEVICE, "barrier wait exceeded its limit");
+  // the timeout flags are read after every call, with or without statistics:
+  // a workgroup that left a timed-out wait may have committed part of a stage
+  int err = 0;
+  VC_CHECK(c, vc::persist_read_stats(c, out, &err), "sweep");
+  if (err) {
+    c->sticky = true;
+    return fail(c, VCSGC_E_BARRIER_TIMEOUT, "persistent sweep: a barrier wait exceeded its limit");
   }
   return VCSGC_OK;
 }
@@ -671,6 +675,19 @@ vcsgc_status vcsgc_sweep_batch(vcsgc_ctx *c, const double *dmu0, const double *k
   if (st) return st;
   if (!dmu0 || !kappa || !cbar || !T) return fail(c, VCSGC_E_INVALID_ARG, "null parameter array");
   return sweep_impl(c, dmu0, kappa, cbar, T, n_sweeps, seed, out);
+}
+
+vcsgc_status vcsgc_set_wait_limit(vcsgc_ctx *c, uint32_t polls) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (polls < 1) return fail(c, VCSGC_E_INVALID_ARG, "polls must be >= 1");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  c->spin_limit = polls;
+  if (c->graph_exec) {  // its kernel node holds the old limit
+    (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+  }
+  return VCSGC_OK;
 }
 
 vcsgc_status vcsgc_set_tuning(vcsgc_ctx *c, int32_t strategy, int32_t trials_per_group) {
@@ -904,6 +921,15 @@ vcsgc_status vcsgc_get_state(vcsgc_ctx *c, vcsgc_state *out) {
   VC_CHECK(c, vc::persist_read_stats(c, &s, &err), "state");  // n_final of replica 0
   out->sweeps_done = c->w;
   out->n_b = s.n_final;
+  out->seed = c->last_seed;
+  if (out->rho_dev) {
+    st = ensure_mc(c);
+    if (st) return st;
+    VC_CHECK(c, hipMemcpyAsync(out->rho_dev, c->rho, sizeof(double) * c->n,
+                               hipMemcpyDeviceToDevice, c->stream),
+             "state");
+    VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  }
   return VCSGC_OK;
 }
 
@@ -912,9 +938,18 @@ vcsgc_status vcsgc_set_state(vcsgc_ctx *c, const vcsgc_state *in) {
   if (st) return st;
   if (!in) return fail(c, VCSGC_E_INVALID_ARG, "null input");
   c->w = in->sweeps_done;
+  c->last_seed = in->seed;
   VC_CHECK(c, vc::persist_count(c), "state");  // n_B recounted from the species
   c->mc_valid = false;  // species may have been restored: fresh density cache
   c->rho_f_fresh = false;
+  if (in->rho_dev) {
+    // lists for the current positions (with a fresh cache), then the saved cache
+    st = refresh_mc(c);
+    if (st) return st;
+    VC_CHECK(c, hipMemcpyAsync(c->rho, in->rho_dev, sizeof(double) * c->n,
+                               hipMemcpyDeviceToDevice, c->stream),
+             "state");
+  }
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   return VCSGC_OK;
 }

@@ -328,6 +328,7 @@ struct vcsgc_ctx {
   // the MD and energy paths, cleared by anything that changes species)
   bool rho_f_fresh = false;
   uint64_t w = 0;  // sweep counter
+  uint64_t last_seed = 0;  // seed of the last sweep call (checkpoint state)
   int kmax_used = 0;
   bool mc_stats_stale = false;  // the r < rc list's row statistics not yet taken
   int64_t md_rebuilds = 0;

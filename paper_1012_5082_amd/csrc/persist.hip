@@ -40,7 +40,10 @@ struct RepState {
   long long n_b[2];
   unsigned long long trials, local_acc, stages, stage_acc, flips, near_ties;
   double sum_n, sum_n2;
-  unsigned int bar;
+  // 64-bit arrival counter: it grows by G per barrier (two barriers per
+  // stage) and is zeroed only once per call, so a 32-bit counter would wrap
+  // within one long call (2 S G per sweep)
+  unsigned long long bar;
   int err;
   long long n_final;
 };
@@ -68,7 +71,7 @@ struct PersistArgs {
 
 // Barrier of the G workgroups of one replica on a monotonically increasing
 // counter; returns false if the wait timed out.
-__device__ __forceinline__ bool rep_barrier(RepState *st, int G, unsigned int target,
+__device__ __forceinline__ bool rep_barrier(RepState *st, int G, unsigned long long target,
                                             unsigned int spin_limit, int *flag) {
   if (G == 1) {
     __syncthreads();
@@ -78,7 +81,7 @@ __device__ __forceinline__ bool rep_barrier(RepState *st, int G, unsigned int ta
   if (threadIdx.x == 0) {
     *flag = 0;
     // one release on arrival (writes back this CU's dirty L2 lines once) ...
-    __hip_atomic_fetch_add(&st->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&st->bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     // ... polling with relaxed device-coherent loads (an acquiring load would
     // invalidate the caches on every poll) ...
     unsigned int it = 0;
@@ -170,7 +173,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
   const int32_t *cstart = a.cstart + r.cso;
   const int32_t *catoms = a.catoms + r.aoff;
   int32_t *rec = a.rec + r.roff;
-  unsigned int nbar = 0;
+  unsigned long long nbar = 0;
   int64_t stage_no = 0;
 
   for (int64_t sw = 0; sw < r.n_sweeps; ++sw) {
@@ -232,7 +235,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
         P[3] = v4[3];
       }
       nbar += 1;
-      if (!rep_barrier(st, r.G, nbar * (unsigned)r.G, a.spin_limit, &bflag)) return;
+      if (!rep_barrier(st, r.G, nbar * (unsigned long long)r.G, a.spin_limit, &bflag)) return;
       // ---- global factor, identical in every workgroup of the replica
       long long pa = 0, pd = 0, pv = 0, pt = 0;
       for (int k = threadIdx.x; k < r.G; k += BLOCK) {
@@ -319,12 +322,13 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
         }
       }
       nbar += 1;
-      if (!rep_barrier(st, r.G, nbar * (unsigned)r.G, a.spin_limit, &bflag)) return;
+      if (!rep_barrier(st, r.G, nbar * (unsigned long long)r.G, a.spin_limit, &bflag)) return;
     }
   }
 }
 
-// zero the barrier counters and per-call counters; n_b[0] <- current n_B
+// zero the barrier counters, the timeout flag and the per-call counters;
+// n_b[0] <- current n_B
 __global__ void k_persist_reset(RepState *rs, int R) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= R) return;
@@ -335,6 +339,7 @@ __global__ void k_persist_reset(RepState *rs, int R) {
   s.sum_n = 0.0;
   s.sum_n2 = 0.0;
   s.bar = 0;
+  s.err = 0;
 }
 
 }  // namespace vc

@@ -12,7 +12,8 @@
   c4   64 rigid bcc replicas of uneven size (2,000 to 250,000 sites,
        log-uniform) on a T x kappa x cbar grid
 
-dmu0 comes from dmu_table.json (written by oracle/calibrate_dmu.py).
+dmu0 comes from dmu_table.json (written by oracle/calibrate_dmu.py); c3 takes
+it from dmu_c3.json (oracle/calibrate_dmu_c3.py, calibrated on c3 itself).
 """
 from __future__ import annotations
 
@@ -53,11 +54,28 @@ def c2(cbar=0.05, seed=1002):
                 dmu0=dmu_s(600.0, cbar), seed=2002, name="c2-bcc40-thermal")
 
 
-def c3(seed=1003, cbar=0.03, T=700.0, with_velocities=True):
+def dmu_c3(T: float, cbar: float, kappa: float):
+    """dmu0 calibrated on the polycrystal itself (dmu_c3.json, written by
+    oracle/calibrate_dmu_c3.py), or None for another operating point."""
+    path = os.path.join(HERE, "dmu_c3.json")
+    if not os.path.exists(path):
+        return None
+    e = json.load(open(path))
+    if e["T"] == T and e["cbar"] == cbar and e["kappa"] == kappa:
+        return float(e["dmu0"])
+    return None
+
+
+def c3(seed=1003, cbar=0.03, T=700.0, with_velocities=True, calibrated=True):
+    """calibrated: dmu0 from the calibration on this system when there is one
+    for (T, cbar), else from the rigid-lattice table."""
     x, y, z, box, grain = I.voronoi_poly(100, 16, seed)
     sp = I.initial_species(x.size, cbar, seed + 10)
+    dmu0 = dmu_c3(T, cbar, 1000.0) if calibrated else None
+    if dmu0 is None:
+        dmu0 = dmu_s(T, cbar)
     d = dict(x=x, y=y, z=z, box=box, species=sp, grain=grain, T=T, kappa=1000.0, cbar=cbar,
-             dmu0=dmu_s(T, cbar), seed=2003, dt=1.0, md_steps=20, name="c3-voronoi16")
+             dmu0=dmu0, seed=2003, dt=1.0, md_steps=20, name="c3-voronoi16")
     if with_velocities:
         d["vx"], d["vy"], d["vz"] = I.mb_velocities(sp, T, seed + 20)
     return d

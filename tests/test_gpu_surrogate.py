@@ -19,6 +19,16 @@ from parity_utils import compare_logs
 
 pytestmark = pytest.mark.gpu
 
+# Tolerances of the network against the oracle's emulation (BF16 operands,
+# FP64 sums), set from measured errors: the GPU sums in FP32 in the MFMA
+# units' order and evaluates SiLU in FP32, so now and then a hidden
+# activation rounds to the neighbouring BF16 value.  Measured on MI355X:
+# forward max 1.9e-7 / median 9.6e-9 (1,000 samples), in-sweep block max
+# 1.5e-4 / median 9.6e-9 (390,295 values), gradient at most 7.5e-6 per
+# tensor.
+FWD_MAX, FWD_MEDIAN = 1e-3, 1e-7   # of (max |dE| + out_sd)
+GRAD_REL = 1e-4                    # per parameter tensor, norm-wise
+
 TENSORS = [("w1", 0, 640), ("b1", 640, 704), ("w2", 704, 4800), ("b2", 4800, 4864),
            ("w3", 4864, 4928), ("b3", 4928, 4929)]
 
@@ -62,8 +72,10 @@ def test_mlp_forward_matches_oracle(torch_cuda, oracle_mod):
     _, want = oracle_mod.mlp_forward(m, d, bf16_emul=True)
     err = np.abs(got - want)
     scale = np.abs(want).max() + m.out_sd
-    assert err.max() <= 5e-3 * scale, (err.max(), scale)
-    assert np.median(err) <= 5e-4 * scale, np.median(err)
+    print(f"network forward vs oracle: max err {err.max() / scale:.3e}, "
+          f"median {np.median(err) / scale:.3e} of scale {scale:.4f} eV")
+    assert err.max() <= FWD_MAX * scale, (err.max(), scale)
+    assert np.median(err) <= FWD_MEDIAN * scale, np.median(err)
     g.close()
 
 
@@ -75,9 +87,13 @@ def test_mlp_gradient_matches_oracle(torch_cuda, oracle_mod):
     loss_g, grad_g = g.grad(torch.tensor(d, device="cuda"), torch.tensor(t, device="cuda"))
     loss_o, grad_o = oracle_mod.mlp_grad(m, d, t, bf16_emul=True)
     assert abs(loss_g - loss_o) <= 1e-3 * loss_o
+    rels = {}
     for name, a, b in TENSORS:
-        rel = np.linalg.norm(grad_g[a:b] - grad_o[a:b]) / np.linalg.norm(grad_o[a:b])
-        assert rel <= 1e-2, (name, rel)
+        rels[name] = float(np.linalg.norm(grad_g[a:b] - grad_o[a:b]) / np.linalg.norm(grad_o[a:b]))
+    print("gradient rel. norm error per tensor: " +
+          ", ".join(f"{k} {v:.2e}" for k, v in rels.items()) + f"; loss {loss_g:.6e} vs {loss_o:.6e}")
+    for name, rel in rels.items():
+        assert rel <= GRAD_REL, (name, rel)
     g.close()
 
 
@@ -157,9 +173,26 @@ def test_da_network_chain_matches_oracle_replay(torch_cuda, oracle_mod):
     assert table.shape[0] == nt
     assert 0 < sg["stage1_pass"] < sg["trials"]
     st = O.SweepState(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
-    so, p1, tl_o, sl_o = O.sweep_da(st, *args, n_sw, d["seed"], "table", r_dep=r_dep, table=table,
-                                    log_trials=10 ** 8, log_stages=10 ** 8)
+    dnl = O.neighbors(d["x"], d["y"], d["z"], d["box"], O.DESC_CUTOFF, vectors=False)
+    so, p1, tl_o, sl_o, dlog = O.sweep_da(st, *args, n_sw, d["seed"], "table", r_dep=r_dep,
+                                          table=table, desc_nl=dnl, log_trials=10 ** 8,
+                                          log_stages=10 ** 8, log_desc=nt + 1)
     assert p1 == sg["stage1_pass"]
+    # the values the in-sweep network block produced, against the oracle's
+    # network (BF16 operand rounding, FP64 sums) on the oracle's own
+    # descriptors of the same trials at the same states
+    assert dlog.shape[0] == table.shape[0]
+    assert np.array_equal(dlog[:, :3], table[:, :3])
+    _, want_f = O.mlp_forward(m, dlog[:, 3:13], bf16_emul=True)
+    _, want_r = O.mlp_forward(m, dlog[:, 13:23], bf16_emul=True)
+    surv = ~np.isnan(table[:, 4])
+    assert surv.sum() == sg["stage1_pass"]
+    err = np.concatenate([np.abs(table[:, 3] - want_f), np.abs(table[surv, 4] - want_r[surv])])
+    scale = max(np.abs(want_f).max(), np.abs(want_r[surv]).max()) + m.out_sd
+    print(f"in-sweep network vs oracle: {err.size} values, max err {err.max() / scale:.3e}, "
+          f"median {np.median(err) / scale:.3e} of scale {scale:.4f} eV")
+    assert err.max() <= FWD_MAX * scale, (err.max(), scale)
+    assert np.median(err) <= FWD_MEDIAN * scale, (np.median(err), scale)
     for k in ("trials", "local_accepts", "stage_accepts", "flips", "n_final"):
         assert sg[k] == so[k], k
     # dU is logged (and compared) for survivors only
