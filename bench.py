@@ -129,19 +129,53 @@ def copy_calib():
     print(json.dumps({"copy_bytes": n * 8, "launches": 5}))
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(d, pot):
-    """The oracle as it stands, timed on this host: one sweep of the same
-    system (the neighbour list is built first, untimed)."""
+    """The oracle as it stands, timed on this host on a bounded sample of the
+    same workload: one serial sweep (the headline leg), three sweeps of the
+    same chain with each stage's trials on all host cores of this process
+    (bitwise the serial chain), and three serial velocity-Verlet steps of the
+    same system (neighbour list rebuilt at every force evaluation)."""
     from oracle import oracle as O
+    threads = min(16, len(os.sched_getaffinity(0)))
     t0 = time.perf_counter()
     st = O.SweepState(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
     setup = time.perf_counter() - t0
+    args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
     t0 = time.perf_counter()
-    s, _, _ = O.sweep(st, d["dmu0"], d["kappa"], d["cbar"], d["T"], 1, d["seed"])
+    s, _, _ = O.sweep(st, *args, 1, d["seed"])
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s3, _ = O.sweep_omp(st, *args, 3, d["seed"], threads=threads)
+    dt3 = time.perf_counter() - t0
+    md_steps = 3
+    t0 = time.perf_counter()
+    O.md(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"], d["species"], d["box"], pot,
+         d["dt"], md_steps)
+    dtm = time.perf_counter() - t0
+    n = d["x"].size
     return {"value": s["trials"] / dt, "unit": "trials/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 sweep ({s['trials']} trials) of the same {d['x'].size}-site system, "
-                      f"serial FP64 C oracle, {dt:.2f} s (neighbour list {setup:.1f} s untimed)"}
+            "sample": f"1 sweep ({s['trials']} trials) of the same {n}-site system, "
+                      f"serial FP64 C oracle, {dt:.2f} s (neighbour list {setup:.1f} s untimed)",
+            "openmp": {"value": round(s3["trials"] / dt3, 1), "unit": "trials/s",
+                       "cores": threads, "kind": "oracle",
+                       "sample": f"the next 3 sweeps ({s3['trials']} trials), each stage's "
+                                 f"trials on {threads} threads, {dt3:.2f} s"},
+            "md": {"value": round(n * md_steps / dtm, 1), "unit": "atom-steps/s", "cores": 1,
+                   "kind": "oracle",
+                   "sample": f"{md_steps} velocity-Verlet steps of the same system "
+                             f"({md_steps + 1} force evaluations, each with its neighbour "
+                             f"list), serial, {dtm:.2f} s"},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def _timed(fn):
@@ -351,9 +385,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=0, help="c4/c5: timed sweeps")
     ap.add_argument("--local-steps", type=int, default=1,
                     help="c3: trials per active cell per stage (1 = the plain scheme)")
-    ap.add_argument("--tiling", default="batch:16",
+    ap.add_argument("--tiling", default="batch:4",
                     help="c3: sweep tiling strategy:k, or 'auto' for the autotuner")
-    ap.add_argument("--relax", type=int, default=30,
+    ap.add_argument("--relax", type=int, default=0,
                     help="c3: untimed sweeps before the warmup cycles")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -406,8 +440,8 @@ def main():
         g.set_tuning(st, int(k))
         tuned = {"choice": (st, int(k)), "times_ms": {}}
     log(f"tiling: {tuned['choice']} {tuned['times_ms']}")
-    # the chain settles out of its initial transient (most local accepts and
-    # accepted stages come in the first sweeps) before the warmup cycles
+    # optional untimed sweeps before the warmup cycles (none by default: the
+    # timed cycles follow the chain from its initial state)
     if args.relax > 0:
         g.sweep(*sweep_args, args.relax, d["seed"], stats=False)
     for k in range(args.warmup):
@@ -431,9 +465,11 @@ def main():
     log("breakdown (ms per cycle, launches): " + ", ".join(
         f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(breakdown.items(), key=lambda t: -t[1][0])))
 
-    # timed region: K hybrid cycles; the dominant kernel class timed per launch
-    # (one launch in SAMPLE for the per-stage sweep kernels)
-    g.kernel_timing([dominant], every=SAMPLE if dominant in ("trial", "commit", "stage") else 1)
+    # timed region: K hybrid cycles; the dominant kernel class and the sweep
+    # kernel class timed per launch (one launch in SAMPLE of the per-stage
+    # sweep kernels; the pipelines time the span of each graph replay)
+    sweep_cls = "stage" if "stage" in breakdown else ("trial" if "trial" in breakdown else None)
+    g.kernel_timing(sorted({dominant} | ({sweep_cls} if sweep_cls else set())), every=SAMPLE)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     trials = 0
@@ -455,32 +491,42 @@ def main():
     mc_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
     md_ms = sum(b.elapsed_time(c) for _, b, c in ev)
     kt = g.kernel_times()
-    tot_ms, launches, all_launches = kt[dominant]
-    avg_s = tot_ms / launches / 1e3
-
     info2 = g.info()
     pairs_md = info2["md_pairs"]
     pairs_mc = info["mc_pairs"]
-    per_launch_trials = trials / max(1, all_launches) if dominant == "trial" else 0
-    if dominant == "stage":
-        nc = info["n_cells"]
-        ncpc = nc[0] * nc[1] * nc[2] // 8
-        per_launch_trials = (trials / max(1, all_launches), stages * ncpc / max(1, all_launches))
-    # every MD call of md_steps steps makes md_steps force passes with the
-    # next step's kick and drift and one that stores the forces
-    abytes = algorithmic_bytes(dominant, n, pairs_md, pairs_mc, per_launch_trials,
-                               fused=md_steps / (md_steps + 1))
-    roof = None
-    if abytes:
+    nc = info["n_cells"]
+    ncpc = nc[0] * nc[1] * nc[2] // 8
+
+    def roof_entry(cls):
+        """HBM roofline of one kernel class over the timed region: algorithmic
+        bytes per launch / mean launch duration (HIP events)."""
+        if cls not in kt:
+            return None
+        tot_ms, launches, all_launches = kt[cls]
+        avg_s = tot_ms / launches / 1e3
+        per_launch = 0
+        if cls == "trial":
+            per_launch = trials / max(1, all_launches)
+        elif cls == "stage":
+            per_launch = (trials / max(1, all_launches), stages * ncpc / max(1, all_launches))
+        # every MD call of md_steps steps makes md_steps force passes with the
+        # next step's kick and drift and one that stores the forces
+        abytes = algorithmic_bytes(cls, n, pairs_md, pairs_mc, per_launch,
+                                   fused=md_steps / (md_steps + 1))
+        if not abytes:
+            return None
         ach = abytes / avg_s / 1e9
-        tcls = "batch" if dominant == "stage" and tuned["choice"][0] == "batch" else dominant
-        roof = {"bound": "hbm", "kernel": TRAFFIC[tcls][0] if tcls in TRAFFIC else dominant,
+        tcls = "batch" if cls == "stage" and tuned["choice"][0] == "batch" else cls
+        return {"bound": "hbm", "kernel": TRAFFIC[tcls][0] if tcls in TRAFFIC else cls,
                 "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(tcls, "%s:%d" % tuple(tuned["choice"])),
                 "bytes_per_launch": int(abytes),
                 "avg_launch_us": round(avg_s * 1e6, 2), "timed_launches": launches,
                 "launches": all_launches}
+
+    roof = roof_entry(dominant)
+    roof_sweep = roof_entry(sweep_cls) if sweep_cls else None
 
     value = trials / (mc_ms / 1e3)
     md_rate = n * md_steps * args.steps / (md_ms / 1e3)
@@ -507,6 +553,8 @@ def main():
         "top_kernel": top,
         "autotune_ms_per_sweep": {k: round(v, 3) for k, v in tuned["times_ms"].items()},
         "roofline": roof,
+        "roofline_sweep": roof_sweep,
+        "dmu0": d["dmu0"],
     }
     g.close()
     if not args.no_cpu_baseline:

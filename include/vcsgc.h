@@ -221,6 +221,26 @@ vcsgc_status eam_energy_forces(vcsgc_ctx *ctx, double *energy_eV, int want_force
  * next sweep. */
 vcsgc_status md_verlet_step(vcsgc_ctx *ctx, double dt_fs, int64_t n_steps);
 
+/* Nose-Hoover thermostat for later md_verlet_step calls (the paper's Fe-Cu
+ * runs thermostat their MD, Sec. IV.B).  T_K > 0 switches it on: equations
+ * of motion dx/dt = v, dv/dt = F/m - xi v, dxi/dt = (2K - g kB T)/Q,
+ * deta/dt = xi, with K the kinetic energy, g = 3N - 3 and
+ * Q = g kB T tau_fs^2 (eV fs^2); T_K = 0 switches it off (NVE).  xi (1/fs)
+ * and eta set the thermostat state.  A step is the symmetric splitting
+ *   thermostat(dt/2); v += dt/2 a; x += dt v; forces; v += dt/2 a;
+ *   thermostat(dt/2),
+ * where a thermostat half step is xi += (dt/4) G; v *= s; K *= s^2;
+ * eta += xi dt/2; xi += (dt/4) G, G = (2K - g kB T)/Q, with
+ * s = (1 - xi dt/4)/(1 + xi dt/4) (the (1,1) Pade form of exp(-xi dt/2),
+ * which keeps the splitting time reversible) and K summed afresh after each
+ * closing kick in a fixed order (chunks of 256 atoms).  The conserved
+ * quantity is K + U + Q xi^2 / 2 + g kB T eta.  Needs a single-system
+ * context with velocities.  Errors: VCSGC_E_INVALID_ARG. */
+vcsgc_status vcsgc_set_thermostat(vcsgc_ctx *ctx, double T_K, double tau_fs, double xi,
+                                  double eta);
+/* Current thermostat state (either output may be NULL; synchronizes). */
+vcsgc_status vcsgc_get_thermostat(vcsgc_ctx *ctx, double *xi, double *eta);
+
 /* Message of the last error on this context (or of the last failed create when
  * ctx is NULL).  The string is owned by the library. */
 const char *vcsgc_last_error(const vcsgc_ctx *ctx);
@@ -281,10 +301,11 @@ typedef struct {
  * pair of HIP events recorded on the context's stream around the launch;
  * resets the accumulated times.  mask = 0 disables timing. */
 vcsgc_status vcsgc_kernel_timing(vcsgc_ctx *ctx, uint32_t mask);
-/* As vcsgc_kernel_timing, but only one launch in `every` (>= 1) of each
- * class is timed (launch index mod every == 0 since this call), for classes
- * launched hundreds of times per call where the event pairs themselves would
- * add host work; count then holds the timed launches. */
+/* As vcsgc_kernel_timing, but only one launch in `every` (>= 1) of each of
+ * the per-stage sweep classes (TRIAL, COMMIT, STAGE) is timed (launch index
+ * mod every == 0 since this call): they are launched hundreds of times per
+ * call, where the event pairs themselves would add host work.  The other
+ * classes are timed at every launch; count holds the timed launches. */
 vcsgc_status vcsgc_kernel_timing_sampled(vcsgc_ctx *ctx, uint32_t mask, int32_t every);
 /* Accumulated times since the last vcsgc_kernel_timing call (synchronizes). */
 vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *ctx, vcsgc_ktimes *out);

@@ -1202,3 +1202,138 @@ int or_sweep_omp(int64_t n, const double *x, const double *y, const double *z,
   free(col_cells); free(cstart); free(catoms); free(cof);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Nose-Hoover thermostat (NVT) for the MD part of the hybrid scheme         */
+/* ------------------------------------------------------------------------ */
+/* Fixed-shape sum of v[0..n): the values are cut into chunks of 256
+ * consecutive entries (zeros past n); a chunk's sum is taken by halving
+ * strides (a[t] += a[t + h] for h = 128, 64, ..., 1); chunk sum c is added,
+ * in ascending c, to accumulator c mod 256 (each starting at 0); the 256
+ * accumulators are combined by halving strides again. */
+double or_tree_sum(int64_t n, const double *v) {
+  int64_t nch = (n + 255) / 256;
+  double acc[256];
+  for (int t = 0; t < 256; ++t) acc[t] = 0.0;
+  for (int64_t c = 0; c < nch; ++c) {
+    double a[256];
+    for (int t = 0; t < 256; ++t) {
+      int64_t i = 256 * c + t;
+      a[t] = i < n ? v[i] : 0.0;
+    }
+    for (int h = 128; h > 0; h >>= 1)
+      for (int t = 0; t < h; ++t) a[t] = a[t] + a[t + h];
+    acc[c % 256] = acc[c % 256] + a[0];
+  }
+  for (int h = 128; h > 0; h >>= 1)
+    for (int t = 0; t < h; ++t) acc[t] = acc[t] + acc[t + h];
+  return acc[0];
+}
+
+/* Kinetic energy (eV): K = 1/2 sum_i m_i |v_i|^2 / ACC, with the per-atom
+ * terms m_i ((vx^2 + vy^2) + vz^2) summed by or_tree_sum. */
+static double or_kinetic(int64_t n, const double *vx, const double *vy, const double *vz,
+                         const uint8_t *species, double mass_a, double mass_b, double *work) {
+  for (int64_t i = 0; i < n; ++i) {
+    double m = species[i] ? mass_b : mass_a;
+    work[i] = m * ((vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i]);
+  }
+  return 0.5 * or_tree_sum(n, work) / OR_ACC;
+}
+
+/* Half step (dt/2) of the thermostat variables for kinetic energy *K, with
+ * G = (2K - g kB T) / Q:
+ *   xi += (dt/4) G;  s = (1 - xi dt/4) / (1 + xi dt/4);  K <- K s s;
+ *   eta += xi dt/2;  xi += (dt/4) G(K);
+ * s is the (1,1) Pade form of exp(-xi dt/2), the factor the friction
+ * -xi v applies to the velocities over dt/2; s(-xi) = 1/s(xi), so the
+ * splitting stays time reversible.  Returns s. */
+static double or_nh_half(double dt, double g, double kT, double Q, double *K, double *xi,
+                         double *eta) {
+  double q4 = 0.25 * dt;
+  *xi = *xi + q4 * ((2.0 * *K - g * kT) / Q);
+  double a = *xi * q4;
+  double s = (1.0 - a) / (1.0 + a);
+  *K = *K * s * s;
+  *eta = *eta + *xi * (0.5 * dt);
+  *xi = *xi + q4 * ((2.0 * *K - g * kT) / Q);
+  return s;
+}
+
+/*
+ * Nose-Hoover NVT (one thermostat; equations of motion dx/dt = v,
+ * dv/dt = F/m - xi v, dxi/dt = (2K - g kB T)/Q, deta/dt = xi, with
+ * g = 3N - 3 and Q = g kB T tau^2), integrated by the symmetric splitting
+ *   thermostat(dt/2); v += (dt/2) a; x = wrap(x + dt v); forces;
+ *   v += (dt/2) a; thermostat(dt/2),
+ * with K computed fresh (or_kinetic) at the start of each thermostat half
+ * step that follows a kick or starts the call, and carried by K <- K s s
+ * otherwise.  The velocity factors of consecutive half steps are applied one
+ * after the other, v = (v s1) s2.  xi (1/fs) and eta (fs^-1 * fs) carry over
+ * between calls through xi_io and eta_io.  Conserved:
+ *   H = K + U + Q xi^2 / 2 + g kB T eta.
+ */
+int or_md_nvt(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+              const uint8_t *species, const double box[3], const or_pot *p, double mass_a,
+              double mass_b, double dt, int64_t n_steps, double temp, double tau, double *xi_io,
+              double *eta_io, double *fx, double *fy, double *fz, double *rho) {
+  double cm[2] = {OR_ACC / mass_a, OR_ACC / mass_b};
+  double hdt = 0.5 * dt;
+  double g = 3.0 * (double)n - 3.0;
+  double kT = OR_KB * temp;
+  double Q = g * kT * tau * tau;
+  double xi = *xi_io, eta = *eta_io;
+  double *work = (double *)malloc((size_t)n * sizeof(double));
+  if (!work) return -1;
+  if (or_eval_forces(n, x, y, z, species, box, p, fx, fy, fz, rho)) {
+    free(work);
+    return -1;
+  }
+  double K = or_kinetic(n, vx, vy, vz, species, mass_a, mass_b, work);
+  double s_pend = 1.0; /* factor of the end-of-step half step, not yet applied */
+  int have_pend = 0;
+  for (int64_t step = 0; step < n_steps; ++step) {
+    double s = or_nh_half(dt, g, kT, Q, &K, &xi, &eta);
+    for (int64_t i = 0; i < n; ++i) {
+      double c = cm[species[i]];
+      if (have_pend) {
+        vx[i] = vx[i] * s_pend;
+        vy[i] = vy[i] * s_pend;
+        vz[i] = vz[i] * s_pend;
+      }
+      vx[i] = vx[i] * s;
+      vy[i] = vy[i] * s;
+      vz[i] = vz[i] * s;
+      vx[i] = vx[i] + hdt * (fx[i] * c);
+      vy[i] = vy[i] + hdt * (fy[i] * c);
+      vz[i] = vz[i] + hdt * (fz[i] * c);
+      x[i] = or_wrap(x[i] + dt * vx[i], box[0]);
+      y[i] = or_wrap(y[i] + dt * vy[i], box[1]);
+      z[i] = or_wrap(z[i] + dt * vz[i], box[2]);
+    }
+    if (or_eval_forces(n, x, y, z, species, box, p, fx, fy, fz, rho)) {
+      free(work);
+      return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      double c = cm[species[i]];
+      vx[i] = vx[i] + hdt * (fx[i] * c);
+      vy[i] = vy[i] + hdt * (fy[i] * c);
+      vz[i] = vz[i] + hdt * (fz[i] * c);
+    }
+    K = or_kinetic(n, vx, vy, vz, species, mass_a, mass_b, work);
+    s_pend = or_nh_half(dt, g, kT, Q, &K, &xi, &eta);
+    have_pend = 1;
+  }
+  if (have_pend) {
+    for (int64_t i = 0; i < n; ++i) {
+      vx[i] = vx[i] * s_pend;
+      vy[i] = vy[i] * s_pend;
+      vz[i] = vz[i] * s_pend;
+    }
+  }
+  *xi_io = xi;
+  *eta_io = eta;
+  free(work);
+  return 0;
+}

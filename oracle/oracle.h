@@ -184,6 +184,20 @@ int or_md(int64_t n, double *x, double *y, double *z, double *vx, double *vy, do
           double mass_a, double mass_b, double dt, int64_t n_steps,
           double *fx, double *fy, double *fz, double *rho);
 
+/* Fixed-shape sum (chunks of 256 summed by halving strides, chunk c added to
+ * accumulator c mod 256 in ascending c, accumulators combined by halving
+ * strides): the order in which totals that steer a trajectory are taken. */
+double or_tree_sum(int64_t n, const double *v);
+
+/* Nose-Hoover NVT velocity Verlet, n_steps steps of dt (fs) at temp (K) with
+ * coupling time tau (fs): Q = g kB T tau^2, g = 3N - 3.  xi_io / eta_io carry
+ * the thermostat friction (1/fs) and its time integral in and out.  tau =
+ * infinity gives or_md's NVE steps bit for bit. */
+int or_md_nvt(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+              const uint8_t *species, const double box[3], const or_pot *p, double mass_a,
+              double mass_b, double dt, int64_t n_steps, double temp, double tau, double *xi_io,
+              double *eta_io, double *fx, double *fy, double *fz, double *rho);
+
 #ifdef __cplusplus
 }
 #endif

@@ -112,6 +112,12 @@ def lib():
         L.or_md.restype = C.c_int
         L.or_md.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
                             C.c_double, C.c_double, C.c_int64, _P, _P, _P, _P]
+        L.or_tree_sum.restype = C.c_double
+        L.or_tree_sum.argtypes = [C.c_int64, _P]
+        L.or_md_nvt.restype = C.c_int
+        L.or_md_nvt.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
+                                C.c_double, C.c_double, C.c_int64, C.c_double, C.c_double,
+                                _P, _P, _P, _P, _P, _P]
         _lib = L
     return _lib
 
@@ -318,6 +324,31 @@ def md(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, mass_a=55.845, mass_
     if rc != 0:
         raise ValueError("or_md failed")
     return x, y, z, vx, vy, vz, fx, fy, fz, rho
+
+
+def tree_sum(v) -> float:
+    v = _f64(v)
+    return lib().or_tree_sum(v.size, _p(v))
+
+
+def md_nvt(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, T, tau, xi=0.0, eta=0.0,
+           mass_a=55.845, mass_b=63.546):
+    """Nose-Hoover NVT velocity Verlet; returns new arrays
+    (x, y, z, vx, vy, vz, fx, fy, fz, rho) and the thermostat state (xi, eta)."""
+    x, y, z = _f64(x).copy(), _f64(y).copy(), _f64(z).copy()
+    vx, vy, vz = _f64(vx).copy(), _f64(vy).copy(), _f64(vz).copy()
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    n = x.size
+    fx, fy, fz, rho = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    th = np.array([xi, eta], dtype=np.float64)
+    P = pot_struct(pot)
+    rc = lib().or_md_nvt(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(sp), _p(_f64(box)),
+                         C.byref(P), float(mass_a), float(mass_b), float(dt), int(n_steps),
+                         float(T), float(tau), _p(th[0:1]), _p(th[1:2]), _p(fx), _p(fy), _p(fz),
+                         _p(rho))
+    if rc != 0:
+        raise ValueError("or_md_nvt failed")
+    return (x, y, z, vx, vy, vz, fx, fy, fz, rho), (float(th[0]), float(th[1]))
 
 
 # ---------------------------------------------------------------------------

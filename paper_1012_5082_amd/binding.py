@@ -127,6 +127,10 @@ def lib():
         L.vcsgc_get_info.argtypes = [_P, C.POINTER(Info)]
         L.vcsgc_kernel_timing.restype = st
         L.vcsgc_kernel_timing.argtypes = [_P, C.c_uint32]
+        L.vcsgc_set_thermostat.restype = st
+        L.vcsgc_set_thermostat.argtypes = [_P, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.vcsgc_get_thermostat.restype = st
+        L.vcsgc_get_thermostat.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.vcsgc_set_wait_limit.restype = st
         L.vcsgc_set_wait_limit.argtypes = [_P, C.c_uint32]
         L.vcsgc_set_local_steps.restype = st
@@ -288,6 +292,17 @@ class VCSGC:
 
     def md(self, dt, n_steps):
         self._check(lib().md_verlet_step(self._h, float(dt), int(n_steps)), "md")
+
+    def set_thermostat(self, T, tau, xi=0.0, eta=0.0):
+        """Nose-Hoover NVT for later md() calls (T = 0: NVE)."""
+        self._check(lib().vcsgc_set_thermostat(self._h, float(T), float(tau), float(xi),
+                                               float(eta)), "set_thermostat")
+
+    def thermostat(self):
+        """(xi, eta) of the thermostat."""
+        xi, eta = C.c_double(), C.c_double()
+        self._check(lib().vcsgc_get_thermostat(self._h, C.byref(xi), C.byref(eta)), "thermostat")
+        return xi.value, eta.value
 
     def enable_log(self, trial_cap, stage_cap):
         import torch

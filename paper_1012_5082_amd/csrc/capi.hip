@@ -31,7 +31,7 @@ void free_all(vcsgc_ctx *c) {
                   c->md_rows,    c->sites,      c->site_lnu,
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
                   c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnu2,     c->m_lnug,   c->m_rec,
-                  c->m_part,     c->s_rec,      c->s_part};
+                  c->m_part,     c->s_rec,      c->s_part,     c->nvt,        c->nvt_part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -237,7 +237,10 @@ namespace vc {
 
 int tstart(vcsgc_ctx *c, int cls) {
   if (!(c->tmask & (1u << cls))) return -1;
-  if (c->kt_seen[cls]++ % c->t_every != 0) return -1;
+  // the sampling applies to the per-stage sweep classes, launched hundreds
+  // of times per call; the others are timed at every launch
+  const bool sampled = cls == VCSGC_KT_TRIAL || cls == VCSGC_KT_COMMIT || cls == VCSGC_KT_STAGE;
+  if (c->kt_seen[cls]++ % (sampled ? c->t_every : 1) != 0) return -1;
   // timing-only events: no system-scope fence when recorded (the stream is
   // synchronized before the times are read)
   hipEvent_t ev[2];
@@ -486,6 +489,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     A(dalloc(&c->pf4, n));
     A(dalloc(&c->rho_f, n));
     A(dalloc(&c->eatom, n));
+    A(dalloc(&c->nvt, 8));
+    A(dalloc(&c->nvt_part, (n + vc::BLOCK - 1) / vc::BLOCK));
   }
   if (c->desc) {
     A(dalloc(&c->d_j, K * n));
@@ -859,9 +864,112 @@ vcsgc_status md_steps_device(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
   return md_steps_host(c, dt_fs, n_steps);
 }
 
+// Nose-Hoover NVT steps: per step the thermostat's half steps at the step
+// boundary, the scaled kick and drift, the rebuild decision (on the device
+// when the search bins allow it, else read by the host), forces, and the
+// closing kick with the kinetic-energy chunk sums.  On a bin or row overflow
+// of a device-decided rebuild the call's entry state (positions,
+// velocities, xi, eta) is restored and the steps are redone with host
+// decisions.
+vcsgc_status md_nvt_steps(vcsgc_ctx *c, double dt_fs, int64_t n_steps, bool dev) {
+  const size_t nb = sizeof(double) * (size_t)c->n;
+  double *state[6] = {c->x, c->y, c->z, c->vx, c->vy, c->vz};
+  if (dev) {
+    if (!c->snap) VC_CHECK(c, dalloc(&c->snap, 6 * (size_t)c->n), "allocation");
+    for (int k = 0; k < 6; ++k)
+      VC_CHECK(c, hipMemcpyAsync(c->snap + k * c->n, state[k], nb, hipMemcpyDeviceToDevice,
+                                 c->stream),
+               "snapshot");
+    VC_CHECK(c, hipMemcpyAsync(c->nvt + 5, c->nvt, 2 * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream),
+             "snapshot");
+    VC_CHECK(c, hipMemsetAsync(&c->ds->md_rebuilds, 0, sizeof(unsigned long long), c->stream),
+             "reset");
+  }
+  VC_CHECK(c, hipMemsetAsync(c->ds->rebuild, 0, 2 * sizeof(int), c->stream), "reset");
+  VC_CHECK(c, vc::launch_pack(c), "pack");
+  VC_CHECK(c, vc::launch_forces(c), "forces");
+  VC_CHECK(c, vc::launch_nvt_ke(c, dt_fs, false), "thermostat");
+  VC_CHECK(c, vc::launch_nvt_thermo(c, dt_fs, 2), "thermostat");
+  for (int64_t k = 0; k < n_steps; ++k) {
+    const int par = dev ? (int)(k & 1) : 0;
+    VC_CHECK(c, vc::launch_nvt_kick_drift(c, dt_fs, par), "kick-drift");
+    if (dev) {
+      VC_CHECK(c, vc::launch_md_rebuild_cond(c, par), "neighbour list (MD)");
+    } else {
+      int flag = 0;
+      VC_CHECK(c, hipMemcpyAsync(&flag, &c->ds->rebuild[0], sizeof(int), hipMemcpyDeviceToHost,
+                                 c->stream),
+               "copy");
+      VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+      if (flag) {
+        VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild[0], 0, sizeof(int), c->stream), "reset");
+        vcsgc_status st = refresh_md(c);
+        if (st) return st;
+      }
+    }
+    VC_CHECK(c, vc::launch_forces(c), "forces");
+    VC_CHECK(c, vc::launch_nvt_ke(c, dt_fs, true), "thermostat");
+    VC_CHECK(c, vc::launch_nvt_thermo(c, dt_fs, k + 1 < n_steps ? 3 : 1), "thermostat");
+  }
+  if (n_steps > 0) VC_CHECK(c, vc::launch_nvt_scale(c), "thermostat");
+  if (!dev) return VCSGC_OK;
+  hipError_t e;
+  vc::DevState h = read_state(c, &e);
+  if (e != hipSuccess) return dev_fail(c, e, "MD");
+  c->md_rebuilds += (int64_t)h.md_rebuilds;
+  if (!h.bin_overflow && !h.overflow) return VCSGC_OK;
+  for (int k = 0; k < 6; ++k)
+    VC_CHECK(c, hipMemcpyAsync(state[k], c->snap + k * c->n, nb, hipMemcpyDeviceToDevice,
+                               c->stream),
+             "restore");
+  VC_CHECK(c, hipMemcpyAsync(c->nvt, c->nvt + 5, 2 * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream),
+           "restore");
+  const int zero[2] = {0, 0};
+  VC_CHECK(c, hipMemcpyAsync(&c->ds->overflow, zero, 2 * sizeof(int), hipMemcpyHostToDevice,
+                             c->stream),
+           "reset");
+  if (h.bin_overflow) {
+    vcsgc_status st = grow_bins(c);
+    if (st) return st;
+  }
+  vcsgc_status st = refresh_md(c);
+  if (st) return st;
+  return md_nvt_steps(c, dt_fs, n_steps, false);
+}
+
 }  // namespace
 
 extern "C" {
+
+vcsgc_status vcsgc_set_thermostat(vcsgc_ctx *c, double T_K, double tau_fs, double xi,
+                                  double eta) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (c->reps.size() != 1 || !c->nvt)
+    return fail(c, VCSGC_E_INVALID_ARG, "the thermostat needs a single-system MD context");
+  if (!is_fin(T_K) || T_K < 0.0 || !(tau_fs > 0.0) || !is_fin(xi) || !is_fin(eta))
+    return fail(c, VCSGC_E_INVALID_ARG, "need T >= 0, tau > 0 and finite xi, eta");
+  const double h[2] = {xi, eta};
+  VC_CHECK(c, hipMemcpyAsync(c->nvt, h, sizeof(h), hipMemcpyHostToDevice, c->stream), "copy");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  c->nvt_T = T_K;
+  c->nvt_tau = tau_fs;
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_get_thermostat(vcsgc_ctx *c, double *xi, double *eta) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (!c->nvt) return fail(c, VCSGC_E_INVALID_ARG, "not an MD context");
+  double h[2];
+  VC_CHECK(c, hipMemcpyAsync(h, c->nvt, sizeof(h), hipMemcpyDeviceToHost, c->stream), "copy");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  if (xi) *xi = h[0];
+  if (eta) *eta = h[1];
+  return VCSGC_OK;
+}
 
 vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
   vcsgc_status st = check_ctx(c);
@@ -877,8 +985,11 @@ vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
     if (st) return st;
   }
   if (n_steps > 0) c->mc_valid = false;
-  st = (n_steps > 0 && vc::md_rebuild_on_device(c)) ? md_steps_device(c, dt_fs, n_steps)
-                                                    : md_steps_host(c, dt_fs, n_steps);
+  if (c->nvt_T > 0.0)
+    st = md_nvt_steps(c, dt_fs, n_steps, vc::md_rebuild_on_device(c));
+  else
+    st = (n_steps > 0 && vc::md_rebuild_on_device(c)) ? md_steps_device(c, dt_fs, n_steps)
+                                                      : md_steps_host(c, dt_fs, n_steps);
   if (st) return st;
   c->rho_f_fresh = true;  // the last force pass ran at the final positions
   return VCSGC_OK;

@@ -256,6 +256,11 @@ struct vcsgc_ctx {
           *cell_fill = nullptr;
   int32_t *scan_tmp = nullptr;  // chunk sums of the cell-count scan
   double *snap = nullptr;       // x, y, z, vx, vy, vz at the start of an MD call (6 n)
+  // Nose-Hoover thermostat of md_verlet_step (off while nvt_T == 0): device
+  // state nvt = (xi, eta, K, s1, s2, xi and eta at the call's start), per-chunk
+  // kinetic-energy sums nvt_part [ceil(n / 256)]
+  double nvt_T = 0.0, nvt_tau = 0.0;
+  double *nvt = nullptr, *nvt_part = nullptr;
 
   // search bins for neighbour lists: edge >= rc + skin, fixed capacity per bin
   int nb[3] = {0, 0, 0};
@@ -409,6 +414,11 @@ hipError_t launch_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par);
 // kick and drift (the forces are not stored)
 hipError_t launch_forces_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par);
 hipError_t launch_kick(vcsgc_ctx *c, double dt);
+// Nose-Hoover NVT (md.hip)
+hipError_t launch_nvt_ke(vcsgc_ctx *c, double dt, bool closing_kick);
+hipError_t launch_nvt_thermo(vcsgc_ctx *c, double dt, int mode);  // bit 0: end half, 1: start half
+hipError_t launch_nvt_kick_drift(vcsgc_ctx *c, double dt, int par);
+hipError_t launch_nvt_scale(vcsgc_ctx *c);
 hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
 // persistent sweep (persist.hip)
 int persist_block();

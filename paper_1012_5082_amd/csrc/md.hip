@@ -101,6 +101,7 @@ struct KickDrift {
   int32_t *bcount;
   int64_t nbins;
   DevState *ds;
+  const double *nvt;  // Nose-Hoover: v = (v s1) s2 before the kick (nvt[3], nvt[4]); NULL: none
 };
 
 // The step's clearing work, by thread i of a grid of `threads`.
@@ -119,6 +120,15 @@ __device__ __forceinline__ void kick_drift_atom(const KickDrift &k, int64_t i, i
   const double hdt = 0.5 * k.dt;
   const double ax = fxi * cm, ay = fyi * cm, az = fzi * cm;
   double ux = k.vx[i], uy = k.vy[i], uz = k.vz[i];
+  if (k.nvt) {
+    const double s1 = k.nvt[3], s2 = k.nvt[4];
+    ux = ux * s1;
+    uy = uy * s1;
+    uz = uz * s1;
+    ux = ux * s2;
+    uy = uy * s2;
+    uz = uz * s2;
+  }
   if (k.kick_first) {
     ux = ux + hdt * ax;
     uy = uy + hdt * ay;
@@ -341,6 +351,142 @@ hipError_t launch_kick(vcsgc_ctx *c, double dt) {
   k_kick<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz,
                                                   c->sp, c->pot, dt);
   tstop(c, h);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Nose-Hoover NVT.  Per step: the thermostat's half steps at the step
+// boundary (one block), the scaled kick and drift, forces, the closing kick
+// fused with the kinetic-energy chunk sums.  The kinetic energy that steers
+// the thermostat is summed in a fixed shape: chunks of 256 atoms by halving
+// strides (one block per chunk), chunk c into accumulator c mod 256, and the
+// accumulators by halving strides again.
+// ---------------------------------------------------------------------------
+// chunk sums of m ((vx^2 + vy^2) + vz^2), after the closing half kick if KICK
+template <bool KICK>
+__global__ void __launch_bounds__(BLOCK)
+    k_nvt_ke(int64_t n, double *vx, double *vy, double *vz, const double *__restrict__ fx,
+             const double *__restrict__ fy, const double *__restrict__ fz,
+             const uint8_t *__restrict__ sp, PotD p, double dt, double *part) {
+  __shared__ double a[BLOCK];
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  double t = 0.0;
+  if (i < n) {
+    const int s = sp[i];
+    double ux = vx[i], uy = vy[i], uz = vz[i];
+    if (KICK) {
+      const double cm = p.cm[s];
+      const double hdt = 0.5 * dt;
+      ux = ux + hdt * (fx[i] * cm);
+      uy = uy + hdt * (fy[i] * cm);
+      uz = uz + hdt * (fz[i] * cm);
+      vx[i] = ux;
+      vy[i] = uy;
+      vz[i] = uz;
+    }
+    t = p.mass[s] * ((ux * ux + uy * uy) + uz * uz);
+  }
+  a[threadIdx.x] = t;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) a[threadIdx.x] = a[threadIdx.x] + a[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = a[0];
+}
+
+struct NvtPar {
+  double dt, g, kT, Q;
+};
+
+// one half step (dt/2) of xi, eta and the carried kinetic energy K; returns
+// the velocity factor s = (1 - xi dt/4) / (1 + xi dt/4)
+__device__ __forceinline__ double nh_half(const NvtPar &q, double &K, double &xi, double &eta) {
+  const double q4 = 0.25 * q.dt;
+  xi = xi + q4 * ((2.0 * K - q.g * q.kT) / q.Q);
+  const double a = xi * q4;
+  const double s = (1.0 - a) / (1.0 + a);
+  K = K * s * s;
+  eta = eta + xi * (0.5 * q.dt);
+  xi = xi + q4 * ((2.0 * K - q.g * q.kT) / q.Q);
+  return s;
+}
+
+// K from the chunk sums; the end-of-step half (mode bit 0) and the next
+// step's opening half (bit 1); nvt = (xi, eta, K, s1, s2)
+__global__ void __launch_bounds__(BLOCK)
+    k_nvt_thermo(int64_t nch, const double *__restrict__ part, double *nvt, NvtPar q, int mode) {
+  __shared__ double a[BLOCK];
+  double acc = 0.0;
+  for (int64_t c = threadIdx.x; c < nch; c += BLOCK) acc = acc + part[c];
+  a[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) a[threadIdx.x] = a[threadIdx.x] + a[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double K = 0.5 * a[0] / ACC;
+    double xi = nvt[0], eta = nvt[1];
+    double s1 = 1.0, s2 = 1.0;
+    if (mode & 1) s1 = nh_half(q, K, xi, eta);
+    if (mode & 2) s2 = nh_half(q, K, xi, eta);
+    nvt[0] = xi;
+    nvt[1] = eta;
+    nvt[2] = K;
+    nvt[3] = s1;
+    nvt[4] = s2;
+  }
+}
+
+// v = v s1 (the last end-of-step half of a call)
+__global__ void k_nvt_scale(int64_t n, double *vx, double *vy, double *vz,
+                            const double *__restrict__ nvt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s1 = nvt[3];
+  vx[i] = vx[i] * s1;
+  vy[i] = vy[i] * s1;
+  vz[i] = vz[i] * s1;
+}
+
+hipError_t launch_nvt_ke(vcsgc_ctx *c, double dt, bool closing_kick) {
+  const unsigned nch = (unsigned)((c->n + BLOCK - 1) / BLOCK);
+  int h = tstart(c, VCSGC_KT_KICK);
+  if (closing_kick)
+    k_nvt_ke<true><<<nch, BLOCK, 0, c->stream>>>(c->n, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz,
+                                                 c->sp, c->pot, dt, c->nvt_part);
+  else
+    k_nvt_ke<false><<<nch, BLOCK, 0, c->stream>>>(c->n, c->vx, c->vy, c->vz, c->fx, c->fy,
+                                                  c->fz, c->sp, c->pot, dt, c->nvt_part);
+  tstop(c, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_nvt_thermo(vcsgc_ctx *c, double dt, int mode) {
+  NvtPar q;
+  q.dt = dt;
+  q.g = 3.0 * (double)c->n - 3.0;
+  q.kT = KB * c->nvt_T;
+  q.Q = q.g * q.kT * c->nvt_tau * c->nvt_tau;
+  k_nvt_thermo<<<1, BLOCK, 0, c->stream>>>((c->n + BLOCK - 1) / BLOCK, c->nvt_part, c->nvt, q,
+                                          mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_nvt_kick_drift(vcsgc_ctx *c, double dt, int par) {
+  Box b{c->box[0], c->box[1], c->box[2]};
+  KickDrift k = kick_drift_args(c, dt, false, par);
+  k.nvt = c->nvt;
+  int h = tstart(c, VCSGC_KT_KICKDRIFT);
+  k_kick_drift<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->fx, c->fy, c->fz, c->sp, b,
+                                                        c->pot, k);
+  tstop(c, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_nvt_scale(vcsgc_ctx *c) {
+  k_nvt_scale<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->vx, c->vy, c->vz, c->nvt);
   return hipGetLastError();
 }
 
