@@ -356,6 +356,25 @@ vcsgc_status vcsgc_mlp_forward(vcsgc_mlp *m, const double *desc_dev, int64_t n, 
 vcsgc_status vcsgc_mlp_grad(vcsgc_mlp *m, const double *desc_dev, const double *dE_dev, int64_t n,
                             float *grad_host, double *loss);
 
+/* Allocation-free form of vcsgc_mlp_grad, for callers that cannot allocate
+ * device memory (code under HIP graph capture, training loops that forbid
+ * allocation): the same forward and backward kernels on n <= 4096 samples,
+ * with the batch's workspace in a fixed device array of the library
+ * (about 7.6 MB per device, held until the process ends) instead of the
+ * network's own buffers, which vcsgc_mlp_grad grows with hipMalloc.
+ * desc_dev[n][10] (FP64) and dE_dev[n] (eV) are inputs; grad_dev receives the
+ * 4929 gradient values (parameter order of vcsgc_mlp_set_params) and
+ * loss_dev the mean squared error of the normalized output, both DEVICE
+ * memory owned by the caller.  The network is only read.  Asynchronous on
+ * the network's stream: no synchronization, no host copy, no allocation.
+ * Calls that overlap on one device share the workspace and race; run them
+ * in one stream.  Errors: VCSGC_E_INVALID_ARG (NULL pointers, n outside
+ * [1, 4096]), VCSGC_E_DEVICE (launch failure). */
+#define VCSGC_NOALLOC_MAX_SAMPLES 4096
+vcsgc_status vcsgc_mlp_grad_noalloc(const vcsgc_mlp *m, const double *desc_dev,
+                                    const double *dE_dev, int64_t n, float *grad_dev,
+                                    double *loss_dev);
+
 /* Record (descriptor, exact dU) of every stride-th trial of later sweeps into
  * caller device buffers desc_dev[cap][10], dE_dev[cap] (training samples);
  * NULL buffers stop recording.  Needs VCSGC_FLAG_DESCRIPTOR. */

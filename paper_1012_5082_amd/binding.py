@@ -166,6 +166,8 @@ def lib():
         L.vcsgc_mlp_forward.argtypes = [_P, _P, C.c_int64, _P]
         L.vcsgc_mlp_grad.restype = st
         L.vcsgc_mlp_grad.argtypes = [_P, _P, _P, C.c_int64, _P, C.POINTER(C.c_double)]
+        L.vcsgc_mlp_grad_noalloc.restype = st
+        L.vcsgc_mlp_grad_noalloc.argtypes = [_P, _P, _P, C.c_int64, _P, _P]
         L.vcsgc_set_sample_log.restype = st
         L.vcsgc_set_sample_log.argtypes = [_P, _P, _P, C.c_int64, C.c_int64]
         L.vcsgc_sample_count.restype = st
@@ -591,3 +593,10 @@ class Mlp:
                     "grad")
         return loss.value, g
 
+    def grad_noalloc(self, desc, dE, grad_out, loss_out):
+        """vcsgc_mlp_grad_noalloc: gradient and mean loss of n <= 4096 samples
+        into caller device tensors (float32[4929], float64[1]); asynchronous."""
+        self._check(lib().vcsgc_mlp_grad_noalloc(self._h, _P(desc.data_ptr()),
+                                                 _P(dE.data_ptr()), desc.shape[0],
+                                                 _P(grad_out.data_ptr()),
+                                                 _P(loss_out.data_ptr())), "grad_noalloc")

@@ -205,8 +205,8 @@ __global__ void k_colsum(int64_t B, int cols, const float *__restrict__ X, const
   out[c] = acc;
 }
 
-// fixed-order double sum of v[0..n) into *out (one block)
-__global__ void k_dsum(int64_t n, const double *__restrict__ v, double *out) {
+// fixed-order double sum of v[0..n) into *out, divided by div (one block)
+__global__ void k_dsum(int64_t n, const double *__restrict__ v, double *out, double div) {
   __shared__ double s[BLOCK];
   double acc = 0.0;
   for (int64_t k = threadIdx.x; k < n; k += BLOCK) acc = acc + v[k];
@@ -216,7 +216,7 @@ __global__ void k_dsum(int64_t n, const double *__restrict__ v, double *out) {
     if ((int)threadIdx.x < h) s[threadIdx.x] = s[threadIdx.x] + s[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = s[0];
+  if (threadIdx.x == 0) *out = s[0] / div;
 }
 
 // Adam on the FP32 master parameters
@@ -260,36 +260,53 @@ __global__ void k_moments(int64_t n, int cols, const double *__restrict__ X, dou
   }
 }
 
-// Full forward + backward over a batch already in Z/T; gradient into m->g.
-static hipError_t mlp_fwd_bwd(vcsgc_mlp *m, int64_t B) {
-  hipStream_t s = m->stream;
+// Activations, gradients and loss partials of one batch: the network's own
+// buffers (grown on demand) or a fixed workspace.
+struct MlpWork {
+  float *Z, *T, *A1, *H1, *A2, *H2, *Y, *dY, *dA2, *dH1, *dA1;
+  double *red;  // per-sample squared errors [B]
+  float *g;     // gradient [4929]
+};
+
+// floats of workspace per sample (Z, T, A1, H1, A2, H2, Y, dY, dA2, dH1, dA1)
+constexpr int64_t MLP_WORK_PER_SAMPLE = MLP_IN + 1 + 4 * MLP_H + 2 + 3 * MLP_H;
+
+static MlpWork own_work(vcsgc_mlp *m) {
+  return MlpWork{m->Z, m->T, m->A1, m->H1, m->A2, m->H2, m->Y, m->dY, m->dA2, m->dH1, m->dA1,
+                 m->red, m->g};
+}
+
+// Full forward + backward over a batch already in w.Z / w.T; gradient into
+// w.g, per-sample squared errors into w.red.  Reads the network's parameters
+// only.
+static hipError_t mlp_fwd_bwd(const vcsgc_mlp *m, const MlpWork &w, int64_t B, hipStream_t s) {
   const float *p = m->p;
   hipError_t e;
   const int gB = grid_for(B), gBH = grid_for(B * MLP_H);
   // layer 1: A1 = Z W1^T (+ b1), H1 = bf16(SiLU(A1))
-  if ((e = gemm(s, (int)B, MLP_H, MLP_IN, m->Z, MLP_IN, 1, p + OFF_W1, 1, MLP_IN, m->A1, MLP_H)))
+  if ((e = gemm(s, (int)B, MLP_H, MLP_IN, w.Z, MLP_IN, 1, p + OFF_W1, 1, MLP_IN, w.A1, MLP_H)))
     return e;
-  k_bias_silu<<<gBH, BLOCK, 0, s>>>(B, m->A1, p + OFF_B1, m->H1);
+  k_bias_silu<<<gBH, BLOCK, 0, s>>>(B, w.A1, p + OFF_B1, w.H1);
   // layer 2
-  if ((e = gemm(s, (int)B, MLP_H, MLP_H, m->H1, MLP_H, 1, p + OFF_W2, 1, MLP_H, m->A2, MLP_H)))
+  if ((e = gemm(s, (int)B, MLP_H, MLP_H, w.H1, MLP_H, 1, p + OFF_W2, 1, MLP_H, w.A2, MLP_H)))
     return e;
-  k_bias_silu<<<gBH, BLOCK, 0, s>>>(B, m->A2, p + OFF_B2, m->H2);
-  k_out<<<gB, BLOCK, 0, s>>>(B, m->H2, m->w3r, p + OFF_B3, m->T, m->Y, m->dY, m->red);
+  k_bias_silu<<<gBH, BLOCK, 0, s>>>(B, w.A2, p + OFF_B2, w.H2);
+  k_out<<<gB, BLOCK, 0, s>>>(B, w.H2, m->w3r, p + OFF_B3, w.T, w.Y, w.dY, w.red);
   // output layer gradients
-  k_colsum<<<1, 64, 0, s>>>(B, MLP_H, m->H2, m->dY, m->g + OFF_W3);
-  k_colsum<<<1, 64, 0, s>>>(B, 1, m->dY, nullptr, m->g + OFF_B3);
-  k_bwd_out<<<gBH, BLOCK, 0, s>>>(B, m->dY, m->w3r, m->A2, m->dA2);
+  k_colsum<<<1, 64, 0, s>>>(B, MLP_H, w.H2, w.dY, w.g + OFF_W3);
+  k_colsum<<<1, 64, 0, s>>>(B, 1, w.dY, nullptr, w.g + OFF_B3);
+  k_bwd_out<<<gBH, BLOCK, 0, s>>>(B, w.dY, m->w3r, w.A2, w.dA2);
   // layer 2 gradients: dW2 = dA2^T H1, db2, dH1 = dA2 W2
-  if ((e = gemm(s, MLP_H, MLP_H, (int)B, m->dA2, 1, MLP_H, m->H1, MLP_H, 1, m->g + OFF_W2, MLP_H)))
+  if ((e = gemm(s, MLP_H, MLP_H, (int)B, w.dA2, 1, MLP_H, w.H1, MLP_H, 1, w.g + OFF_W2, MLP_H)))
     return e;
-  k_colsum<<<1, 64, 0, s>>>(B, MLP_H, m->dA2, nullptr, m->g + OFF_B2);
-  if ((e = gemm(s, (int)B, MLP_H, MLP_H, m->dA2, MLP_H, 1, p + OFF_W2, MLP_H, 1, m->dH1, MLP_H)))
+  k_colsum<<<1, 64, 0, s>>>(B, MLP_H, w.dA2, nullptr, w.g + OFF_B2);
+  if ((e = gemm(s, (int)B, MLP_H, MLP_H, w.dA2, MLP_H, 1, p + OFF_W2, MLP_H, 1, w.dH1, MLP_H)))
     return e;
-  k_bwd_hidden<<<gBH, BLOCK, 0, s>>>(B, m->dH1, m->A1, m->dA1);
+  k_bwd_hidden<<<gBH, BLOCK, 0, s>>>(B, w.dH1, w.A1, w.dA1);
   // layer 1 gradients: dW1 = dA1^T Z, db1
-  if ((e = gemm(s, MLP_H, MLP_IN, (int)B, m->dA1, 1, MLP_H, m->Z, MLP_IN, 1, m->g + OFF_W1, MLP_IN)))
+  if ((e = gemm(s, MLP_H, MLP_IN, (int)B, w.dA1, 1, MLP_H, w.Z, MLP_IN, 1, w.g + OFF_W1, MLP_IN)))
     return e;
-  k_colsum<<<1, 64, 0, s>>>(B, MLP_H, m->dA1, nullptr, m->g + OFF_B1);
+  k_colsum<<<1, 64, 0, s>>>(B, MLP_H, w.dA1, nullptr, w.g + OFF_B1);
   return hipGetLastError();
 }
 
@@ -320,8 +337,8 @@ hipError_t mlp_grad_batch(vcsgc_mlp *m, const double *desc, const double *dE, in
   if (e != hipSuccess) return e;
   MlpDev md = mlp_dev(m);
   k_batch<<<grid_for(n), BLOCK, 0, m->stream>>>(n, n, desc, dE, md, 0, 0, 0, m->Z, m->T);
-  if ((e = mlp_fwd_bwd(m, n)) != hipSuccess) return e;
-  k_dsum<<<1, BLOCK, 0, m->stream>>>(n, m->red, m->red + m->cap);
+  if ((e = mlp_fwd_bwd(m, own_work(m), n, m->stream)) != hipSuccess) return e;
+  k_dsum<<<1, BLOCK, 0, m->stream>>>(n, m->red, m->red + m->cap, 1.0);
   double h = 0.0;
   e = hipMemcpyAsync(&h, m->red + m->cap, sizeof(double), hipMemcpyDeviceToHost, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
@@ -342,7 +359,7 @@ hipError_t mlp_train(vcsgc_mlp *m, const double *desc, const double *dE, int64_t
   for (int64_t st = 0; st < steps; ++st) {
     k_batch<<<grid_for(B), BLOCK, 0, m->stream>>>(n, B, desc, dE, md, cfg->seed, (uint64_t)st, 1,
                                                   m->Z, m->T);
-    if ((e = mlp_fwd_bwd(m, B)) != hipSuccess) return e;
+    if ((e = mlp_fwd_bwd(m, own_work(m), B, m->stream)) != hipSuccess) return e;
     m->adam_t += 1;
     const float c1 = 1.0f - powf((float)cfg->beta1, (float)m->adam_t);
     const float c2 = 1.0f - powf((float)cfg->beta2, (float)m->adam_t);
@@ -352,7 +369,7 @@ hipError_t mlp_train(vcsgc_mlp *m, const double *desc, const double *dE, int64_t
     if ((e = mlp_refresh(m)) != hipSuccess) return e;
     // epoch-end loss of the last batch (one read-back per epoch)
     if ((st + 1) % steps_per_epoch == 0 || st == 0) {
-      k_dsum<<<1, BLOCK, 0, m->stream>>>(B, m->red, m->red + m->cap);
+      k_dsum<<<1, BLOCK, 0, m->stream>>>(B, m->red, m->red + m->cap, 1.0);
       double h = 0.0;
       e = hipMemcpyAsync(&h, m->red + m->cap, sizeof(double), hipMemcpyDeviceToHost, m->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
@@ -543,3 +560,81 @@ vcsgc_status vcsgc_mlp_grad(vcsgc_mlp *m, const double *desc_dev, const double *
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free gradient (vcsgc_mlp_grad_noalloc).  The batch's workspace
+// (activations, back-propagated errors and per-sample squared errors of at
+// most VCSGC_NOALLOC_MAX_SAMPLES samples) is a fixed device array, so the
+// call allocates nothing on any path; outputs go to caller device memory and
+// nothing is read back.  The array's device address is looked up once per
+// device (hipGetSymbolAddress) and only that address reaches the kernels.
+// Every kernel of the pass writes its whole output, so nothing needs clearing
+// between calls; calls that overlap on one device share the array and race.
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+namespace vc {
+
+constexpr int64_t NA_MAX = VCSGC_NOALLOC_MAX_SAMPLES;
+constexpr size_t NA_FLOAT_BYTES = sizeof(float) * (size_t)(NA_MAX * MLP_WORK_PER_SAMPLE);
+constexpr size_t NA_BYTES = NA_FLOAT_BYTES + sizeof(double) * (size_t)NA_MAX;
+static_assert(NA_FLOAT_BYTES % 256 == 0, "double area aligned");
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+constexpr int NA_DEVICES = 64;
+static void *g_scratch[NA_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// device address of `scratch` on `dev` (looked up once per device)
+static hipError_t scratch_address(int dev, unsigned char **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = ptr;
+  }
+  *out = (unsigned char *)g_scratch[dev];
+  return hipSuccess;
+}
+
+static MlpWork fixed_work(unsigned char *base, int64_t B, float *grad) {
+  float *f = (float *)base;
+  MlpWork w;
+  float **bufs[] = {&w.Z, &w.T, &w.A1, &w.H1, &w.A2, &w.H2, &w.Y, &w.dY, &w.dA2, &w.dH1, &w.dA1};
+  const int64_t per[] = {MLP_IN, 1, MLP_H, MLP_H, MLP_H, MLP_H, 1, 1, MLP_H, MLP_H, MLP_H};
+  for (int k = 0; k < 11; ++k) {
+    *bufs[k] = f;
+    f += per[k] * B;
+  }
+  w.red = (double *)(base + NA_FLOAT_BYTES);
+  w.g = grad;
+  return w;
+}
+
+}  // namespace vc
+
+extern "C" vcsgc_status vcsgc_mlp_grad_noalloc(const vcsgc_mlp *m, const double *desc_dev,
+                                               const double *dE_dev, int64_t n, float *grad_dev,
+                                               double *loss_dev) {
+  if (!m || !desc_dev || !dE_dev || !grad_dev || !loss_dev) return VCSGC_E_INVALID_ARG;
+  if (n < 1 || n > VCSGC_NOALLOC_MAX_SAMPLES) return VCSGC_E_INVALID_ARG;
+  if (m->device < 0 || m->device >= vc::NA_DEVICES) return VCSGC_E_INVALID_ARG;
+  unsigned char *base = nullptr;
+  hipError_t e = vc::scratch_address(m->device, &base);
+  if (e != hipSuccess) return VCSGC_E_DEVICE;
+  const vc::MlpWork w = vc::fixed_work(base, n, grad_dev);
+  const vc::MlpDev md = vc::mlp_dev(m);
+  vc::k_batch<<<vc::grid_for(n), vc::BLOCK, 0, m->stream>>>(n, n, desc_dev, dE_dev, md, 0, 0, 0,
+                                                            w.Z, w.T);
+  e = vc::mlp_fwd_bwd(m, w, n, m->stream);
+  if (e != hipSuccess) return VCSGC_E_DEVICE;
+  vc::k_dsum<<<1, vc::BLOCK, 0, m->stream>>>(n, w.red, loss_dev, (double)n);
+  return hipGetLastError() == hipSuccess ? VCSGC_OK : VCSGC_E_DEVICE;
+}
