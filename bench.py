@@ -4,14 +4,24 @@ One step = one hybrid cycle of the 1.96M-site Voronoi polycrystal: one
 parallel VC-SGC sweep (N trials) followed by 20 velocity-Verlet steps
 (dt = 1 fs), the 1:20 interleaving of the paper's production run.
 
+The chain starts from the workload's initial state at the dmu0 calibrated
+on this system (paper_1012_5082_amd/dmu_c3.json): W warmup cycles, then K
+timed cycles.
+
 Reported (one JSON line):
   value               MC trials/s of the sweeps in the timed region
                       (trials / summed sweep time, HIP events on the stream)
+  accepted_flips_per_s, stage_acceptance
+                      exact-accepted transmutations per second of sweep time
+                      and the share of stages the global factor accepted
   md_atom_steps_per_s MD atom-steps/s of the MD parts of the same cycles
   ms_per_step         wall time per hybrid cycle
-  roofline            the kernel with the largest summed time: algorithmic
-                      bytes per launch / average launch duration (HIP events)
-  cpu_baseline        the oracle on host cores (one sweep of the same system)
+  roofline            the kernel class with the largest time in the timed
+                      cycles: algorithmic bytes per launch / mean launch
+                      duration (HIP events)
+  roofline_sweep      the same for the sweep kernel
+  cpu_baseline        the oracle on host cores: one serial sweep of the same
+                      system, three sweeps on all cores, three serial MD steps
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --copy-calib      (plain device copy, for counter scaling)
@@ -376,8 +386,8 @@ def bench_surrogate(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
@@ -387,6 +397,8 @@ def main():
                     help="c3: trials per active cell per stage (1 = the plain scheme)")
     ap.add_argument("--tiling", default="batch:4",
                     help="c3: sweep tiling strategy:k, or 'auto' for the autotuner")
+    ap.add_argument("--skin", type=float, default=0.3,
+                    help="c3: MD neighbour-list skin (A)")
     ap.add_argument("--relax", type=int, default=0,
                     help="c3: untimed sweeps before the warmup cycles")
     args = ap.parse_args()
@@ -419,7 +431,7 @@ def main():
     n = d["x"].size
     log(f"workload {d['name']}: {n} sites generated in {time.perf_counter() - t0:.1f} s")
     g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
-              vz=d["vz"])
+              vz=d["vz"], skin=args.skin)
     if args.local_steps > 1:
         g.set_local_steps(args.local_steps)
     info = g.info()
@@ -450,26 +462,13 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} cycles done")
 
-    # kernel breakdown over one extra cycle (untimed for the headline numbers):
-    # every class sampled one launch in SAMPLE (an event pair per launch costs
-    # host time next to the ~10 us sweep kernels); the per-cycle time of a
-    # class is its mean timed launch times all its launches
+    # timed region: K hybrid cycles.  Every kernel class is timed with HIP
+    # events on the context's stream, one launch in SAMPLE of each (event
+    # pairs at every launch would add host and stream work; the pipelines
+    # time the span of each graph replay); the dominant class is the one with
+    # the largest time over the timed cycles.
     g.kernel_timing(["trial", "commit", "stage", "density", "forces", "kick_drift", "kick",
                      "build", "persist"], every=SAMPLE)
-    g.sweep(*sweep_args, 1, d["seed"])
-    g.md(dt, md_steps)
-    kt0 = g.kernel_times()
-    breakdown = {k: (v[0] / v[1] * v[2], v[2]) for k, v in kt0.items()}
-    top = max(breakdown, key=lambda k: breakdown[k][0])
-    dominant = max((k for k in breakdown if k in HAS_BYTES), key=lambda k: breakdown[k][0])
-    log("breakdown (ms per cycle, launches): " + ", ".join(
-        f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(breakdown.items(), key=lambda t: -t[1][0])))
-
-    # timed region: K hybrid cycles; the dominant kernel class and the sweep
-    # kernel class timed per launch (one launch in SAMPLE of the per-stage
-    # sweep kernels; the pipelines time the span of each graph replay)
-    sweep_cls = "stage" if "stage" in breakdown else ("trial" if "trial" in breakdown else None)
-    g.kernel_timing(sorted({dominant} | ({sweep_cls} if sweep_cls else set())), every=SAMPLE)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     trials = 0
@@ -491,6 +490,13 @@ def main():
     mc_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
     md_ms = sum(b.elapsed_time(c) for _, b, c in ev)
     kt = g.kernel_times()
+    # per cycle: mean timed launch x all launches of the class
+    breakdown = {k: (v[0] / v[1] * v[2] / args.steps, v[2] / args.steps) for k, v in kt.items()}
+    top = max(breakdown, key=lambda k: breakdown[k][0])
+    dominant = max((k for k in breakdown if k in HAS_BYTES), key=lambda k: breakdown[k][0])
+    sweep_cls = "stage" if "stage" in breakdown else ("trial" if "trial" in breakdown else None)
+    log("breakdown (ms per cycle, launches per cycle): " + ", ".join(
+        f"{k}={v[0]:.3f}/{v[1]:.0f}" for k, v in sorted(breakdown.items(), key=lambda t: -t[1][0])))
     info2 = g.info()
     pairs_md = info2["md_pairs"]
     pairs_mc = info["mc_pairs"]

@@ -301,11 +301,11 @@ typedef struct {
  * pair of HIP events recorded on the context's stream around the launch;
  * resets the accumulated times.  mask = 0 disables timing. */
 vcsgc_status vcsgc_kernel_timing(vcsgc_ctx *ctx, uint32_t mask);
-/* As vcsgc_kernel_timing, but only one launch in `every` (>= 1) of each of
- * the per-stage sweep classes (TRIAL, COMMIT, STAGE) is timed (launch index
- * mod every == 0 since this call): they are launched hundreds of times per
- * call, where the event pairs themselves would add host work.  The other
- * classes are timed at every launch; count holds the timed launches. */
+/* As vcsgc_kernel_timing, but only one launch in `every` (>= 1) of each
+ * class is timed (launch index mod every == 0 since this call), so that the
+ * event pairs themselves add little host and stream work next to kernels
+ * launched hundreds of times per call; count then holds the timed launches.
+ * (The pipelines time the span of whole graph replays either way.) */
 vcsgc_status vcsgc_kernel_timing_sampled(vcsgc_ctx *ctx, uint32_t mask, int32_t every);
 /* Accumulated times since the last vcsgc_kernel_timing call (synchronizes). */
 vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *ctx, vcsgc_ktimes *out);

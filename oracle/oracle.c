@@ -115,10 +115,75 @@ static int or_try_pair(nbuf *row, int32_t j, int32_t code, double dx, double dy,
   return 0;
 }
 
-int64_t or_neighbors(int64_t n, const double *x, const double *y, const double *z,
-                     const double box[3], double cutoff, int mode, int64_t cap,
-                     int64_t *start, int32_t *nj, double *nr,
-                     double *ndx, double *ndy, double *ndz) {
+/* Candidate search of a neighbour list: mode 1 minimum image over all
+ * pairs, 2 explicit image sums, 3 the 27 bins of edge >= cutoff around the
+ * atom's bin. */
+typedef struct {
+  int mode, nb[3];
+  int32_t *bin_start, *bin_atoms, *bin_of;
+} nbr_grid;
+
+/* Row i of the neighbour list (all j with r < cutoff), ascending (j, image). */
+static void or_nbr_row(int64_t i, int64_t n, const double *x, const double *y, const double *z,
+                       const double box[3], double cutoff, const nbr_grid *G, nbuf *rowp) {
+  const int mode = G->mode;
+  const int *nb = G->nb;
+  const int32_t *bin_start = G->bin_start, *bin_atoms = G->bin_atoms, *bin_of = G->bin_of;
+  nbuf row = *rowp;
+  row.n = 0;
+  if (mode == 1) {
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      or_try_pair(&row, (int32_t)j, 13, or_mimage(x[j] - x[i], box[0]),
+                  or_mimage(y[j] - y[i], box[1]), or_mimage(z[j] - z[i], box[2]), cutoff);
+    }
+  } else if (mode == 2) {
+    for (int64_t j = 0; j < n; ++j) {
+      for (int sz = -1; sz <= 1; ++sz)
+        for (int sy = -1; sy <= 1; ++sy)
+          for (int sx = -1; sx <= 1; ++sx) {
+            if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
+            int code = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
+            or_try_pair(&row, (int32_t)j, code, (x[j] - x[i]) + sx * box[0],
+                        (y[j] - y[i]) + sy * box[1], (z[j] - z[i]) + sz * box[2], cutoff);
+          }
+    }
+  } else {
+    int b = bin_of[i];
+    int bx = b % nb[0], by = (b / nb[0]) % nb[1], bz = b / (nb[0] * nb[1]);
+    for (int oz = -1; oz <= 1; ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          int cx = (bx + ox + nb[0]) % nb[0];
+          int cy = (by + oy + nb[1]) % nb[1];
+          int cz = (bz + oz + nb[2]) % nb[2];
+          int c = cx + nb[0] * (cy + nb[1] * cz);
+          for (int32_t k = bin_start[c]; k < bin_start[c + 1]; ++k) {
+            int32_t j = bin_atoms[k];
+            if (j == i) continue;
+            or_try_pair(&row, j, 13, or_mimage(x[j] - x[i], box[0]),
+                        or_mimage(y[j] - y[i], box[1]), or_mimage(z[j] - z[i], box[2]),
+                        cutoff);
+          }
+        }
+  }
+  /* ascending (j, image) by insertion sort */
+  for (int64_t a = 1; a < row.n; ++a) {
+    nent v = row.e[a];
+    int64_t b = a - 1;
+    while (b >= 0 && cmp_nent(&row.e[b], &v) > 0) {
+      row.e[b + 1] = row.e[b];
+      --b;
+    }
+    row.e[b + 1] = v;
+  }
+  *rowp = row;
+}
+
+/* Mode choice (mode 0: bins when the box holds three cutoffs per axis,
+ * else minimum image, else image sums) and, for mode 3, the bins. */
+static int or_nbr_setup(int64_t n, const double *x, const double *y, const double *z,
+                        const double box[3], double cutoff, int mode, nbr_grid *G) {
   double Lmin = box[0];
   if (box[1] < Lmin) Lmin = box[1];
   if (box[2] < Lmin) Lmin = box[2];
@@ -154,56 +219,31 @@ int64_t or_neighbors(int64_t n, const double *x, const double *y, const double *
     free(fill);
   }
 
+  G->mode = mode;
+  for (int d = 0; d < 3; ++d) G->nb[d] = nb[d];
+  G->bin_start = bin_start;
+  G->bin_atoms = bin_atoms;
+  G->bin_of = bin_of;
+  return 0;
+}
+
+static void or_nbr_free(nbr_grid *G) {
+  free(G->bin_start);
+  free(G->bin_atoms);
+  free(G->bin_of);
+}
+
+int64_t or_neighbors(int64_t n, const double *x, const double *y, const double *z,
+                     const double box[3], double cutoff, int mode, int64_t cap,
+                     int64_t *start, int32_t *nj, double *nr,
+                     double *ndx, double *ndy, double *ndz) {
+  nbr_grid G;
+  if (or_nbr_setup(n, x, y, z, box, cutoff, mode, &G)) return -1;
+
   nbuf row = {0, 0, 0};
   int64_t total = 0;
   for (int64_t i = 0; i < n; ++i) {
-    row.n = 0;
-    if (mode == 1) {
-      for (int64_t j = 0; j < n; ++j) {
-        if (j == i) continue;
-        or_try_pair(&row, (int32_t)j, 13, or_mimage(x[j] - x[i], box[0]),
-                    or_mimage(y[j] - y[i], box[1]), or_mimage(z[j] - z[i], box[2]), cutoff);
-      }
-    } else if (mode == 2) {
-      for (int64_t j = 0; j < n; ++j) {
-        for (int sz = -1; sz <= 1; ++sz)
-          for (int sy = -1; sy <= 1; ++sy)
-            for (int sx = -1; sx <= 1; ++sx) {
-              if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
-              int code = (sx + 1) + 3 * ((sy + 1) + 3 * (sz + 1));
-              or_try_pair(&row, (int32_t)j, code, (x[j] - x[i]) + sx * box[0],
-                          (y[j] - y[i]) + sy * box[1], (z[j] - z[i]) + sz * box[2], cutoff);
-            }
-      }
-    } else {
-      int b = bin_of[i];
-      int bx = b % nb[0], by = (b / nb[0]) % nb[1], bz = b / (nb[0] * nb[1]);
-      for (int oz = -1; oz <= 1; ++oz)
-        for (int oy = -1; oy <= 1; ++oy)
-          for (int ox = -1; ox <= 1; ++ox) {
-            int cx = (bx + ox + nb[0]) % nb[0];
-            int cy = (by + oy + nb[1]) % nb[1];
-            int cz = (bz + oz + nb[2]) % nb[2];
-            int c = cx + nb[0] * (cy + nb[1] * cz);
-            for (int32_t k = bin_start[c]; k < bin_start[c + 1]; ++k) {
-              int32_t j = bin_atoms[k];
-              if (j == i) continue;
-              or_try_pair(&row, j, 13, or_mimage(x[j] - x[i], box[0]),
-                          or_mimage(y[j] - y[i], box[1]), or_mimage(z[j] - z[i], box[2]),
-                          cutoff);
-            }
-          }
-    }
-    /* ascending (j, image) by insertion sort */
-    for (int64_t a = 1; a < row.n; ++a) {
-      nent v = row.e[a];
-      int64_t b = a - 1;
-      while (b >= 0 && cmp_nent(&row.e[b], &v) > 0) {
-        row.e[b + 1] = row.e[b];
-        --b;
-      }
-      row.e[b + 1] = v;
-    }
+    or_nbr_row(i, n, x, y, z, box, cutoff, &G, &row);
     if (start) start[i] = total;
     for (int64_t k = 0; k < row.n; ++k, ++total) {
       if (total < cap) {
@@ -217,9 +257,7 @@ int64_t or_neighbors(int64_t n, const double *x, const double *y, const double *
   }
   if (start) start[n] = total;
   free(row.e);
-  free(bin_start);
-  free(bin_atoms);
-  free(bin_of);
+  or_nbr_free(&G);
   return total;
 }
 
@@ -268,14 +306,17 @@ static double or_dembed(const or_pot *p, int a, double rho) {
 }
 
 /* rho_i = sum_j f_{s_j}(r_ij), in neighbour order. */
+static double or_density_row(int64_t i, const int64_t *start, const int32_t *nj,
+                             const double *nr, const uint8_t *species, const or_pot *p) {
+  double s = 0.0;
+  for (int64_t e = start[i]; e < start[i + 1]; ++e)
+    if (nr[e] < p->rc) s += or_f(p, species[nj[e]], nr[e]);
+  return s;
+}
+
 void or_density(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
                 const uint8_t *species, const or_pot *p, double *rho) {
-  for (int64_t i = 0; i < n; ++i) {
-    double s = 0.0;
-    for (int64_t e = start[i]; e < start[i + 1]; ++e)
-      if (nr[e] < p->rc) s += or_f(p, species[nj[e]], nr[e]);
-    rho[i] = s;
-  }
+  for (int64_t i = 0; i < n; ++i) rho[i] = or_density_row(i, start, nj, nr, species, p);
 }
 
 /* E_i = F_{s_i}(rho_i) + (1/2) sum_j phi_{s_i s_j}(r_ij); U = sum_i E_i. */
@@ -295,6 +336,28 @@ double or_energy_total(int64_t n, const double *e) {
   return s;
 }
 
+static void or_force_row(int64_t i, const int64_t *start, const int32_t *nj, const double *nr,
+                         const double *ndx, const double *ndy, const double *ndz,
+                         const uint8_t *species, const or_pot *p, const double *fp,
+                         double *fx, double *fy, double *fz) {
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  int si = species[i];
+  for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+    double r = nr[e];
+    if (!(r < p->rc)) continue;
+    int32_t j = nj[e];
+    int sj = species[j];
+    double s = or_dphi(p, si, sj, r) + fp[i] * or_df(p, sj, r) + fp[j] * or_df(p, si, r);
+    double coef = s / r;
+    ax += coef * ndx[e];
+    ay += coef * ndy[e];
+    az += coef * ndz[e];
+  }
+  fx[i] = ax;
+  fy[i] = ay;
+  fz[i] = az;
+}
+
 /* F_i = -dU/dx_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i) / r */
 void or_forces(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
                const double *ndx, const double *ndy, const double *ndz,
@@ -302,24 +365,8 @@ void or_forces(int64_t n, const int64_t *start, const int32_t *nj, const double 
                double *fx, double *fy, double *fz) {
   double *fp = (double *)malloc((size_t)n * sizeof(double));
   for (int64_t i = 0; i < n; ++i) fp[i] = or_dembed(p, species[i], rho[i]);
-  for (int64_t i = 0; i < n; ++i) {
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    int si = species[i];
-    for (int64_t e = start[i]; e < start[i + 1]; ++e) {
-      double r = nr[e];
-      if (!(r < p->rc)) continue;
-      int32_t j = nj[e];
-      int sj = species[j];
-      double s = or_dphi(p, si, sj, r) + fp[i] * or_df(p, sj, r) + fp[j] * or_df(p, si, r);
-      double coef = s / r;
-      ax += coef * ndx[e];
-      ay += coef * ndy[e];
-      az += coef * ndz[e];
-    }
-    fx[i] = ax;
-    fy[i] = ay;
-    fz[i] = az;
-  }
+  for (int64_t i = 0; i < n; ++i)
+    or_force_row(i, start, nj, nr, ndx, ndy, ndz, species, p, fp, fx, fy, fz);
   free(fp);
 }
 
@@ -1335,5 +1382,97 @@ int or_md_nvt(int64_t n, double *x, double *y, double *z, double *vx, double *vy
   *xi_io = xi;
   *eta_io = eta;
   free(work);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* All-core CPU baseline of or_md: the same per-atom arithmetic (neighbour   */
+/* rows, densities, forces, kicks) with the atoms split over n_threads       */
+/* OpenMP threads.  Rows are built twice (count, then fill at the row's      */
+/* offset), so the list is the serial one and every value is bitwise         */
+/* or_md's.                                                                  */
+/* ------------------------------------------------------------------------ */
+static int or_eval_forces_omp(int64_t n, const double *x, const double *y, const double *z,
+                              const uint8_t *species, const double box[3], const or_pot *p,
+                              double *fx, double *fy, double *fz, double *rho, int n_threads) {
+  nbr_grid G;
+  if (or_nbr_setup(n, x, y, z, box, p->rc, 0, &G)) return -1;
+  int64_t *start = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+#pragma omp parallel num_threads(n_threads)
+  {
+    nbuf row = {0, 0, 0};
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      or_nbr_row(i, n, x, y, z, box, p->rc, &G, &row);
+      start[i + 1] = row.n;
+    }
+    free(row.e);
+  }
+  start[0] = 0;
+  for (int64_t i = 0; i < n; ++i) start[i + 1] += start[i];
+  int64_t tot = start[n];
+  int32_t *nj = (int32_t *)malloc((size_t)(tot > 0 ? tot : 1) * sizeof(int32_t));
+  double *nr = (double *)malloc((size_t)(tot > 0 ? tot : 1) * sizeof(double));
+  double *dx = (double *)malloc((size_t)(tot > 0 ? tot : 1) * sizeof(double));
+  double *dy = (double *)malloc((size_t)(tot > 0 ? tot : 1) * sizeof(double));
+  double *dz = (double *)malloc((size_t)(tot > 0 ? tot : 1) * sizeof(double));
+  double *fp = (double *)malloc((size_t)n * sizeof(double));
+#pragma omp parallel num_threads(n_threads)
+  {
+    nbuf row = {0, 0, 0};
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      or_nbr_row(i, n, x, y, z, box, p->rc, &G, &row);
+      for (int64_t k = 0; k < row.n; ++k) {
+        int64_t e = start[i] + k;
+        nj[e] = row.e[k].j;
+        nr[e] = row.e[k].r;
+        dx[e] = row.e[k].dx;
+        dy[e] = row.e[k].dy;
+        dz[e] = row.e[k].dz;
+      }
+    }
+    free(row.e);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) rho[i] = or_density_row(i, start, nj, nr, species, p);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) fp[i] = or_dembed(p, species[i], rho[i]);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+      or_force_row(i, start, nj, nr, dx, dy, dz, species, p, fp, fx, fy, fz);
+  }
+  or_nbr_free(&G);
+  free(start); free(nj); free(nr); free(dx); free(dy); free(dz); free(fp);
+  return 0;
+}
+
+int or_md_omp(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+              const uint8_t *species, const double box[3], const or_pot *p,
+              double mass_a, double mass_b, double dt, int64_t n_steps,
+              double *fx, double *fy, double *fz, double *rho, int n_threads) {
+  double cm[2] = {OR_ACC / mass_a, OR_ACC / mass_b};
+  double hdt = 0.5 * dt;
+  if (n_threads < 1) n_threads = 1;
+  if (or_eval_forces_omp(n, x, y, z, species, box, p, fx, fy, fz, rho, n_threads)) return -1;
+  for (int64_t step = 0; step < n_steps; ++step) {
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+    for (int64_t i = 0; i < n; ++i) {
+      double c = cm[species[i]];
+      vx[i] = vx[i] + hdt * (fx[i] * c);
+      vy[i] = vy[i] + hdt * (fy[i] * c);
+      vz[i] = vz[i] + hdt * (fz[i] * c);
+      x[i] = or_wrap(x[i] + dt * vx[i], box[0]);
+      y[i] = or_wrap(y[i] + dt * vy[i], box[1]);
+      z[i] = or_wrap(z[i] + dt * vz[i], box[2]);
+    }
+    if (or_eval_forces_omp(n, x, y, z, species, box, p, fx, fy, fz, rho, n_threads)) return -1;
+#pragma omp parallel for schedule(static) num_threads(n_threads)
+    for (int64_t i = 0; i < n; ++i) {
+      double c = cm[species[i]];
+      vx[i] = vx[i] + hdt * (fx[i] * c);
+      vy[i] = vy[i] + hdt * (fy[i] * c);
+      vz[i] = vz[i] + hdt * (fz[i] * c);
+    }
+  }
   return 0;
 }

@@ -184,6 +184,13 @@ int or_md(int64_t n, double *x, double *y, double *z, double *vx, double *vy, do
           double mass_a, double mass_b, double dt, int64_t n_steps,
           double *fx, double *fy, double *fz, double *rho);
 
+/* or_md with the atoms of every loop split over n_threads OpenMP threads
+ * (all-core CPU baseline; bitwise or_md). */
+int or_md_omp(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+              const uint8_t *species, const double box[3], const or_pot *p,
+              double mass_a, double mass_b, double dt, int64_t n_steps,
+              double *fx, double *fy, double *fz, double *rho, int n_threads);
+
 /* Fixed-shape sum (chunks of 256 summed by halving strides, chunk c added to
  * accumulator c mod 256 in ascending c, accumulators combined by halving
  * strides): the order in which totals that steer a trajectory are taken. */

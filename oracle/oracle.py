@@ -112,6 +112,9 @@ def lib():
         L.or_md.restype = C.c_int
         L.or_md.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
                             C.c_double, C.c_double, C.c_int64, _P, _P, _P, _P]
+        L.or_md_omp.restype = C.c_int
+        L.or_md_omp.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
+                                C.c_double, C.c_double, C.c_int64, _P, _P, _P, _P, C.c_int]
         L.or_tree_sum.restype = C.c_double
         L.or_tree_sum.argtypes = [C.c_int64, _P]
         L.or_md_nvt.restype = C.c_int
@@ -323,6 +326,25 @@ def md(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, mass_a=55.845, mass_
                      _p(fx), _p(fy), _p(fz), _p(rho))
     if rc != 0:
         raise ValueError("or_md failed")
+    return x, y, z, vx, vy, vz, fx, fy, fz, rho
+
+
+def md_omp(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, threads=None, mass_a=55.845,
+           mass_b=63.546):
+    """md() with every per-atom loop on several host threads (bitwise md())."""
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    x, y, z = _f64(x).copy(), _f64(y).copy(), _f64(z).copy()
+    vx, vy, vz = _f64(vx).copy(), _f64(vy).copy(), _f64(vz).copy()
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    n = x.size
+    fx, fy, fz, rho = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    P = pot_struct(pot)
+    rc = lib().or_md_omp(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(sp), _p(_f64(box)),
+                         C.byref(P), float(mass_a), float(mass_b), float(dt), int(n_steps),
+                         _p(fx), _p(fy), _p(fz), _p(rho), int(threads))
+    if rc != 0:
+        raise ValueError("or_md_omp failed")
     return x, y, z, vx, vy, vz, fx, fy, fz, rho
 
 

@@ -237,10 +237,7 @@ namespace vc {
 
 int tstart(vcsgc_ctx *c, int cls) {
   if (!(c->tmask & (1u << cls))) return -1;
-  // the sampling applies to the per-stage sweep classes, launched hundreds
-  // of times per call; the others are timed at every launch
-  const bool sampled = cls == VCSGC_KT_TRIAL || cls == VCSGC_KT_COMMIT || cls == VCSGC_KT_STAGE;
-  if (c->kt_seen[cls]++ % (sampled ? c->t_every : 1) != 0) return -1;
+  if (c->kt_seen[cls]++ % c->t_every != 0) return -1;
   // timing-only events: no system-scope fence when recorded (the stream is
   // synchronized before the times are read)
   hipEvent_t ev[2];

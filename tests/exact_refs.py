@@ -77,3 +77,13 @@ def batch_means(series, n_batches=20):
 def lattice_shells(a):
     """bcc shells inside 3.6 A: (count, distance)."""
     return [(8, a * math.sqrt(3.0) / 2.0), (6, a)]
+
+
+def batch_variance(series, n_batches=20):
+    """Variance about the whole series' mean and its standard error from
+    non-overlapping batches (each batch's mean square deviation)."""
+    s = np.asarray(series, dtype=np.float64)
+    m = s.size // n_batches
+    dev2 = (s[: m * n_batches] - s[: m * n_batches].mean()) ** 2
+    bv = dev2.reshape(n_batches, m).mean(axis=1)
+    return float(bv.mean()), float(bv.std(ddof=1) / math.sqrt(n_batches))

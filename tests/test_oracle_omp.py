@@ -1,7 +1,8 @@
-"""The all-core CPU baseline (or_sweep_omp) is the serial oracle's chain,
-bit for bit: the same species, density cache, velocities, counters and stage
+"""The all-core CPU baselines are the serial oracle bit for bit: or_sweep_omp
+gives the same species, density cache, velocities, counters and stage
 records after several calls, at a kappa that accepts most stages and at one
-that rejects most of them."""
+that rejects most of them; or_md_omp gives the same positions, velocities,
+forces and densities as or_md."""
 import numpy as np
 import pytest
 
@@ -29,3 +30,16 @@ def test_omp_sweep_is_the_serial_chain(oracle_mod, kappa, dmu0):
             assert np.array_equal(u.view(np.uint64), v.view(np.uint64))
         assert a.n_b[0] == b.n_b[0] and a.w == b.w
     assert sa["stage_accepts"] > 0
+
+
+def test_omp_md_is_the_serial_md(oracle_mod):
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    x, y, z, box = I.bcc(12, 12, 12)
+    x, y, z = I.thermalize(x, y, z, box, 0.05, 41)
+    sp = I.initial_species(x.size, 0.1, 42)
+    vx, vy, vz = I.mb_velocities(sp, 1200.0, 43)
+    a = O.md(x, y, z, vx, vy, vz, sp, box, pot, 2.0, 15)
+    b = O.md_omp(x, y, z, vx, vy, vz, sp, box, pot, 2.0, 15, threads=4)
+    for u, v in zip(a, b):
+        assert np.array_equal(u.view(np.uint64), v.view(np.uint64))
