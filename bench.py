@@ -397,6 +397,8 @@ def main():
                     help="c3: trials per active cell per stage (1 = the plain scheme)")
     ap.add_argument("--tiling", default="batch:4",
                     help="c3: sweep tiling strategy:k, or 'auto' for the autotuner")
+    ap.add_argument("--colours", type=int, default=8, choices=[8, 27],
+                    help="c3: colours of the sweep (27: cells of edge >= r_dep / 2)")
     ap.add_argument("--skin", type=float, default=0.3,
                     help="c3: MD neighbour-list skin (A)")
     ap.add_argument("--relax", type=int, default=0,
@@ -431,7 +433,7 @@ def main():
     n = d["x"].size
     log(f"workload {d['name']}: {n} sites generated in {time.perf_counter() - t0:.1f} s")
     g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
-              vz=d["vz"], skin=args.skin)
+              vz=d["vz"], skin=args.skin, colours=args.colours)
     if args.local_steps > 1:
         g.set_local_steps(args.local_steps)
     info = g.info()
@@ -545,7 +547,7 @@ def main():
                                f"(100^3-cell box), FS-P1 EAM, kappa=1000 eV, cbar=0.03, "
                                f"T=700 K, step = 1 VC-SGC sweep + 20 MD steps (dt=1 fs)",
                    "n_sites": n, "n_cells": info["n_cells"],
-                   "stages_per_sweep": info["stages_per_sweep"],
+                   "stages_per_sweep": info["stages_per_sweep"], "colours": args.colours,
                    "variant": ("plain" if args.local_steps == 1
                                else f"local chains of {args.local_steps} trials per cell"),
                    "sweep_tiling": list(tuned["choice"]),

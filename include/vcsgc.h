@@ -37,6 +37,14 @@ typedef struct vcsgc_mlp vcsgc_mlp; /* opaque surrogate network, library-owned *
 
 /* vcsgc_system.flags */
 #define VCSGC_FLAG_DESCRIPTOR 1u /* keep the r < 4.41 A descriptor list (surrogate, sample log) */
+/* A finer colouring than the eight octants of Sec. III.A: cells of edge
+ * >= r_dep / 2, a multiple of three per dimension, coloured by their indices
+ * modulo 3 (27 colours); same-colour cells are two cell edges, >= r_dep,
+ * apart, so their trials stay independent.  A stage draws its colour as
+ * floor(w0 27 / 2^64) from its Philox word (eight colours: w0 >> 61), and a
+ * sweep has 27 ceil(N / N_cells) stages, each with about 2.4 times the
+ * trials of an eight-colour stage. */
+#define VCSGC_FLAG_COLOURS27 2u
 
 typedef enum {
   VCSGC_OK = 0,

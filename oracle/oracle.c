@@ -427,17 +427,36 @@ static void or_commit(int64_t i, const int64_t *start, const int32_t *nj, const 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Cells (Sec. III.A): the box is cut into an even number of cells of edge   */
-/* >= r_dep per dimension; cells whose index parities agree form one of      */
-/* eight colours, and same-colour cells are a full cell edge apart, so       */
-/* trial sites chosen in them do not interact (octant scheme, Fig. 5).       */
+/* Cells (Sec. III.A): with colour period P per axis, the box is cut into a  */
+/* multiple of P cells of edge >= r_dep / (P - 1) per dimension; cells whose */
+/* indices agree modulo P form one of P^3 colours, and same-colour cells are */
+/* P - 1 cell edges (>= r_dep) apart, so trial sites chosen in them do not    */
+/* interact.  P = 2 is the octant scheme of Fig. 5 (eight colours); P = 3 a  */
+/* finer colouring (27 colours on cells of edge >= r_dep / 2).               */
 /* ------------------------------------------------------------------------ */
-int or_cell_grid(const double box[3], double r_dep, int32_t nc[3]) {
+int or_cell_grid_p(const double box[3], double r_dep, int period, int32_t nc[3]) {
+  if (period < 2 || period > 3) return -1;
+  const double edge = r_dep / (double)(period - 1);
   for (int d = 0; d < 3; ++d) {
-    nc[d] = 2 * (int32_t)floor(box[d] / (2.0 * r_dep));
-    if (nc[d] < 2) return -1;
+    nc[d] = period * (int32_t)floor(box[d] / ((double)period * edge));
+    if (nc[d] < period) return -1;
   }
   return 0;
+}
+
+int or_cell_grid(const double box[3], double r_dep, int32_t nc[3]) {
+  return or_cell_grid_p(box, r_dep, 2, nc);
+}
+
+/* Colour of cell (cx, cy, cz): its indices modulo P, (cx % P) + P ((cy % P) + P (cz % P)). */
+static int or_cell_colour(int64_t c, const int32_t nc[3], int period) {
+  int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((int64_t)nc[0] * nc[1]));
+  return (cx % period) + period * ((cy % period) + period * (cz % period));
+}
+
+/* Colour of a stage: floor(w0 C / 2^64) for C = P^3 colours (w0 >> 61 for eight). */
+static int or_stage_colour(uint64_t w0, int ncol) {
+  return (int)or_index(w0, (uint64_t)ncol);
 }
 
 static int or_over(const double *over, int64_t n_over, int64_t w, int64_t s, int64_t cell,
@@ -585,10 +604,12 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
   const int64_t K = a->local_steps > 1 ? a->local_steps : 1;
   if (K > 1 && da && da->mode != OR_DA_OFF) return -3; /* delayed acceptance: one step only */
   if (n < 1 || !(a->temp > 0.0) || !(a->kappa >= 0.0)) return -1;
+  const int P = a->colour_period > 0 ? a->colour_period : 2;
+  const int NCOL = P * P * P;
   int32_t nc[3] = {1, 1, 1};
   int64_t ncells = 1;
   if (!a->one_cell) {
-    if (or_cell_grid(box, a->r_dep, nc)) return -2;
+    if (or_cell_grid_p(box, a->r_dep, P, nc)) return -2;
     ncells = (int64_t)nc[0] * nc[1] * nc[2];
   }
   /* counting sort of sites into cells; ascending index inside each cell */
@@ -618,11 +639,8 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
     for (int64_t i = 0; i < n; ++i) catoms[fill[cof[i]]++] = (int32_t)i;
     free(fill);
   }
-  for (int64_t c = 0; c < ncells; ++c) {
-    int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((int64_t)nc[0] * nc[1]));
-    ccol[c] = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
-  }
-  int64_t S = a->one_cell ? (n + K - 1) / K : 8 * ((((n + ncells - 1) / ncells) + K - 1) / K);
+  for (int64_t c = 0; c < ncells; ++c) ccol[c] = or_cell_colour(c, nc, P);
+  int64_t S = a->one_cell ? (n + K - 1) / K : NCOL * ((((n + ncells - 1) / ncells) + K - 1) / K);
 
   double beta = 1.0 / (OR_KB * a->temp);
   double kN = a->kappa / (double)n;
@@ -636,7 +654,7 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
     for (int64_t s = 0; s < S; ++s) {
       uint64_t ctr[4] = {(uint64_t)w, (uint64_t)s, 0, 0}, g[4];
       or_philox4x64_10(key, ctr, g);
-      int colour = (int)(g[0] >> 61);
+      int colour = or_stage_colour(g[0], NCOL);
       int64_t nrec = 0, dn_tot = 0;
       if (K > 1) {
         /* local chains: every step on the state left by the previous one;
@@ -1112,8 +1130,10 @@ int or_sweep_omp(int64_t n, const double *x, const double *y, const double *z,
                  double *slog, int64_t scap, int64_t *sn, int n_threads, or_stats *st) {
   if (a->local_steps > 1 || a->one_cell) return -3;
   if (n < 1 || !(a->temp > 0.0) || !(a->kappa >= 0.0)) return -1;
+  const int P = a->colour_period > 0 ? a->colour_period : 2;
+  const int NCOL = P * P * P;
   int32_t nc[3];
-  if (or_cell_grid(box, a->r_dep, nc)) return -2;
+  if (or_cell_grid_p(box, a->r_dep, P, nc)) return -2;
   int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
   int32_t *cstart = (int32_t *)calloc((size_t)ncells + 1, sizeof(int32_t));
   int32_t *catoms = (int32_t *)malloc((size_t)n * sizeof(int32_t));
@@ -1138,26 +1158,20 @@ int or_sweep_omp(int64_t n, const double *x, const double *y, const double *z,
   }
   /* the cells of each colour in ascending id */
   int64_t *col_cells = (int64_t *)malloc((size_t)ncells * sizeof(int64_t));
-  int64_t col_start[9] = {0};
-  for (int64_t c = 0; c < ncells; ++c) {
-    int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((int64_t)nc[0] * nc[1]));
-    col_start[1 + ((cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2))]++;
-  }
-  for (int k = 0; k < 8; ++k) col_start[k + 1] += col_start[k];
+  int64_t col_start[28] = {0};
+  for (int64_t c = 0; c < ncells; ++c) col_start[1 + or_cell_colour(c, nc, P)]++;
+  for (int k = 0; k < NCOL; ++k) col_start[k + 1] += col_start[k];
   {
-    int64_t fill[8];
+    int64_t fill[27];
     memcpy(fill, col_start, sizeof(fill));
-    for (int64_t c = 0; c < ncells; ++c) {
-      int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((int64_t)nc[0] * nc[1]));
-      col_cells[fill[(cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2)]++] = c;
-    }
+    for (int64_t c = 0; c < ncells; ++c) col_cells[fill[or_cell_colour(c, nc, P)]++] = c;
   }
-  int64_t S = 8 * ((n + ncells - 1) / ncells);
+  int64_t S = NCOL * ((n + ncells - 1) / ncells);
   double beta = 1.0 / (OR_KB * a->temp);
   double kN = a->kappa / (double)n;
   uint64_t key[2] = {a->seed, a->replica};
   int64_t maxc = 0;
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < NCOL; ++k)
     if (col_start[k + 1] - col_start[k] > maxc) maxc = col_start[k + 1] - col_start[k];
   int64_t *t_site = (int64_t *)malloc((size_t)(maxc > 0 ? maxc : 1) * sizeof(int64_t));
   int8_t *t_state = (int8_t *)malloc((size_t)(maxc > 0 ? maxc : 1)); /* -1 empty, 0 reject, 1 accept */
@@ -1171,7 +1185,7 @@ int or_sweep_omp(int64_t n, const double *x, const double *y, const double *z,
     for (int64_t s = 0; s < S; ++s) {
       uint64_t ctr[4] = {(uint64_t)w, (uint64_t)s, 0, 0}, g[4];
       or_philox4x64_10(key, ctr, g);
-      int colour = (int)(g[0] >> 61);
+      int colour = or_stage_colour(g[0], NCOL);
       const int64_t *cells = col_cells + col_start[colour];
       int64_t m_act = col_start[colour + 1] - col_start[colour];
 #pragma omp parallel for schedule(static) num_threads(n_threads)

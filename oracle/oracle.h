@@ -50,6 +50,9 @@ double or_delta_u(int64_t i, const int64_t *start, const int32_t *nj, const doub
 
 /* Link cells for the sweep: 2*floor(L/(2 r_dep)) cells per dimension. */
 int or_cell_grid(const double box[3], double r_dep, int32_t nc[3]);
+/* With colour period P (2 or 3): P*floor(L/(P r_dep/(P-1))) cells per
+ * dimension, of edge >= r_dep/(P-1); colours are the indices modulo P. */
+int or_cell_grid_p(const double box[3], double r_dep, int period, int32_t nc[3]);
 
 typedef struct {
   double dmu0;      /* eV: Delta mu_0 = phi + 2 kappa c0 (local factor) */
@@ -62,6 +65,7 @@ typedef struct {
   int32_t one_cell; /* serial mode: one cell holding every site, N stages per sweep */
   double mass_a, mass_b; /* for velocity rescaling on transmutation */
   int32_t local_steps;   /* trials per active cell per stage (0 or 1: one) */
+  int32_t colour_period; /* 0 or 2: eight colours; 3: 27 colours on cells of edge >= r_dep/2 */
 } or_sweep_args;
 
 typedef struct {

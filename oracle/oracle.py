@@ -41,7 +41,7 @@ class SweepArgs(C.Structure):
                 ("temp", C.c_double), ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("w0", C.c_int64), ("n_sweeps", C.c_int64), ("r_dep", C.c_double),
                 ("one_cell", C.c_int32), ("mass_a", C.c_double), ("mass_b", C.c_double),
-                ("local_steps", C.c_int32)]
+                ("local_steps", C.c_int32), ("colour_period", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -93,6 +93,8 @@ def lib():
         L.or_delta_u.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P]
         L.or_cell_grid.restype = C.c_int
         L.or_cell_grid.argtypes = [_P, C.c_double, _P]
+        L.or_cell_grid_p.restype = C.c_int
+        L.or_cell_grid_p.argtypes = [_P, C.c_double, C.c_int, _P]
         L.or_sweep.restype = C.c_int
         L.or_sweep.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                _P, _P, _P, _P, C.c_int64, _P, _P, C.c_int64, _P, _P,
@@ -223,10 +225,10 @@ def delta_u(nl: NeighborList, i, species, rho, pot) -> float:
                             C.byref(P))
 
 
-def cell_grid(box, r_dep):
+def cell_grid(box, r_dep, period=2):
     box = _f64(box)
     nc = np.zeros(3, dtype=np.int32)
-    if lib().or_cell_grid(_p(box), float(r_dep), _p(nc)):
+    if lib().or_cell_grid_p(_p(box), float(r_dep), int(period), _p(nc)):
         raise ValueError("box too small for two cells of edge r_dep")
     return nc
 
@@ -255,15 +257,16 @@ class SweepState:
 
 def sweep(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, replica=0, r_dep=None,
           one_cell=False, log_trials=0, log_stages=0, overrides=None,
-          mass_a=55.845, mass_b=63.546, local_steps=1):
+          mass_a=55.845, mass_b=63.546, local_steps=1, colour_period=2):
     """Run n_sweeps sweeps from the state's sweep counter; returns (stats, tlog, slog).
-    local_steps = k: k trials per active cell per stage (exact local chains)."""
+    local_steps = k: k trials per active cell per stage (exact local chains);
+    colour_period 3: 27 colours on cells of edge >= r_dep / 2."""
     L = lib()
     if r_dep is None:
         r_dep = 2.0 * st.pot.rc
     a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
                   int(st.w), int(n_sweeps), float(r_dep), int(bool(one_cell)),
-                  float(mass_a), float(mass_b), int(local_steps))
+                  float(mass_a), float(mass_b), int(local_steps), int(colour_period))
     tlog = np.zeros((max(log_trials, 0), 8)) if log_trials else None
     slog = np.zeros((max(log_stages, 0), 8)) if log_stages else None
     tn = np.zeros(1, dtype=np.int64)
@@ -288,7 +291,7 @@ def sweep(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, replica=0, r_dep
 
 
 def sweep_omp(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, threads=None, replica=0,
-              r_dep=None, log_stages=0, mass_a=55.845, mass_b=63.546):
+              r_dep=None, log_stages=0, mass_a=55.845, mass_b=63.546, colour_period=2):
     """or_sweep's plain chain with the trials of each stage on several host
     threads (bitwise the serial chain); returns (stats, slog)."""
     if threads is None:
@@ -296,7 +299,8 @@ def sweep_omp(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, threads=None
     if r_dep is None:
         r_dep = 2.0 * st.pot.rc
     a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
-                  int(st.w), int(n_sweeps), float(r_dep), 0, float(mass_a), float(mass_b), 1)
+                  int(st.w), int(n_sweeps), float(r_dep), 0, float(mass_a), float(mass_b), 1,
+                  int(colour_period))
     slog = np.zeros((max(log_stages, 0), 8)) if log_stages else None
     sn = np.zeros(1, dtype=np.int64)
     s = Stats()
@@ -449,7 +453,8 @@ def mlp_grad(m: MlpParams, d, t, bf16_emul=False):
 
 def sweep_da(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, mode, replica=0, r_dep=None,
              one_cell=False, table=None, mlp: MlpParams | None = None,
-             desc_nl: NeighborList | None = None, log_trials=0, log_stages=0, log_desc=0):
+             desc_nl: NeighborList | None = None, log_trials=0, log_stages=0, log_desc=0,
+             colour_period=2):
     """Delayed-acceptance sweeps; returns (stats, stage-1 passes, tlog, slog),
     and with log_desc > 0 (table mode with desc_nl) also the descriptor log:
     rows (w, s, cell, current-state descriptor [10], flipped-state
@@ -458,7 +463,8 @@ def sweep_da(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, mode, replica
     if r_dep is None:
         r_dep = 2.0 * st.pot.rc
     a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
-                  int(st.w), int(n_sweeps), float(r_dep), int(bool(one_cell)), 55.845, 63.546)
+                  int(st.w), int(n_sweeps), float(r_dep), int(bool(one_cell)), 55.845, 63.546, 1,
+                  int(colour_period))
     da = Da()
     da.mode = DA_MODES[mode]
     keep = []

@@ -60,6 +60,7 @@ class TrainReport(C.Structure):
 
 
 FLAG_DESCRIPTOR = 1
+FLAG_COLOURS27 = 2
 SURROGATE_MODES = {"off": 0, "mlp": 1, "perfect": 2, "zero": 3}
 N_PARAMS = 4929
 
@@ -221,7 +222,7 @@ class VCSGC:
 
     def __init__(self, x, y, z, box, species, pot, vx=None, vy=None, vz=None, forces=False,
                  skin=0.3, r_dep=0.0, mass_a=55.845, mass_b=63.546, device="cuda", stream=None,
-                 descriptor=False):
+                 descriptor=False, colours=8):
         import torch
         L = lib()
         self.device = torch.device(device)
@@ -250,7 +251,9 @@ class VCSGC:
         sysd.pot = pot_struct(pot, mass_a, mass_b)
         sysd.skin = float(skin)
         sysd.r_dep = float(r_dep)
-        sysd.flags = FLAG_DESCRIPTOR if descriptor else 0
+        if colours not in (8, 27):
+            raise ValueError("colours must be 8 or 27")
+        sysd.flags = (FLAG_DESCRIPTOR if descriptor else 0) | (FLAG_COLOURS27 if colours == 27 else 0)
         self._sys = sysd
         h = _P()
         rc = L.vcsgc_create(C.byref(sysd), _stream_handle(stream), C.byref(h))
@@ -466,7 +469,7 @@ class VCSGCBatch(VCSGC):
     x, y, z, box, species (numpy); arrays are concatenated on the device."""
 
     def __init__(self, reps, pot, r_dep=0.0, mass_a=55.845, mass_b=63.546, device="cuda",
-                 stream=None):
+                 stream=None, colours=8):
         import torch
         L = lib()
         self.device = torch.device(device)
@@ -492,6 +495,9 @@ class VCSGCBatch(VCSGC):
         sysd.pot = pot_struct(pot, mass_a, mass_b)
         sysd.skin = 0.3
         sysd.r_dep = float(r_dep)
+        if colours not in (8, 27):
+            raise ValueError("colours must be 8 or 27")
+        sysd.flags = FLAG_COLOURS27 if colours == 27 else 0
         self._sys = sysd
         self.stream = stream
         h = _P()

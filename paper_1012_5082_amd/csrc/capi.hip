@@ -351,6 +351,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   const double r_dep = sys->r_dep == 0.0 ? 2.0 * P.rc : sys->r_dep;
   if (!(r_dep >= 2.0 * P.rc) || !is_fin(r_dep))
     return fail(nullptr, VCSGC_E_INVALID_ARG, "r_dep must be >= 2 rc");
+  const int per = (sys->flags & VCSGC_FLAG_COLOURS27) ? 3 : 2, ncol = per * per * per;
 
   std::vector<RepHost> reps((size_t)R);
   int64_t aoff = 0, coff = 0, boff = 0, roff = 0;
@@ -363,10 +364,11 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
       r.box[d] = rep_box[3 * k + d];
       if (!(r.box[d] > 0.0) || !is_fin(r.box[d]))
         return fail(nullptr, VCSGC_E_INVALID_ARG, "box edges must be positive and finite");
-      r.nc[d] = 2 * (int)std::floor(r.box[d] / (2.0 * r_dep));
-      if (r.nc[d] < 2)
+      r.nc[d] = per * (int)std::floor(r.box[d] / ((double)per * (r_dep / (double)(per - 1))));
+      if (r.nc[d] < per)
         return fail(nullptr, VCSGC_E_BOX_TOO_SMALL,
-                    "box must hold two cells of edge r_dep in every dimension");
+                    per == 2 ? "box must hold two cells of edge r_dep in every dimension"
+                             : "box must hold three cells of edge r_dep / 2 in every dimension");
       const double bin_edge = (sys->flags & VCSGC_FLAG_DESCRIPTOR)
                                   ? std::max(P.rc + sys->skin, vc::DESC_CUT)
                                   : P.rc + sys->skin;
@@ -377,8 +379,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     r.ncells = (int64_t)r.nc[0] * r.nc[1] * r.nc[2];
     r.coff = coff;
     r.cso = coff + k;
-    r.S = 8 * ((r.n + r.ncells - 1) / r.ncells);
-    r.ncpc = r.ncells / 8;
+    r.S = (int64_t)ncol * ((r.n + r.ncells - 1) / r.ncells);
+    r.ncpc = r.ncells / ncol;
     r.roff = roff;
     r.nbins = (int64_t)r.nb[0] * r.nb[1] * r.nb[2];
     r.boff = boff;
@@ -402,6 +404,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     c->nb[d] = r0.nb[d];
   }
   c->ncells = r0.ncells;
+  c->per = per;
+  c->ncol = ncol;
   c->S = r0.S;
   c->nbins = r0.nbins;
   c->nbins_total = boff;
@@ -732,7 +736,7 @@ vcsgc_status vcsgc_set_local_steps(vcsgc_ctx *c, int32_t k) {
   c->sites = c->u_site = c->u_j = nullptr;
   c->site_lnu = c->stage_lnug = c->u_rho = c->u_v = nullptr;
   c->local_steps = k;
-  const int64_t ncpc = c->ncells / 8, K = k;
+  const int64_t ncpc = c->ncells / c->ncol, K = k;
   const int64_t tab = vc::stages_per_sweep(c) * ncpc * K;
   VC_CHECK(c, dalloc(&c->sites, tab), "allocation");
   VC_CHECK(c, dalloc(&c->site_lnu, tab), "allocation");

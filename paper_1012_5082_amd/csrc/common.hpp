@@ -129,6 +129,11 @@ __device__ __forceinline__ double unit_open(uint64_t w) {
 }
 
 // uniform index in [0, m): floor(w m / 2^64)
+// colour of a stage: floor(w ncol / 2^64) (w >> 61 for eight colours)
+__device__ __forceinline__ int stage_colour(uint64_t w, int ncol) {
+  return (int)__umul64hi(w, (uint64_t)ncol);
+}
+
 __device__ __forceinline__ uint32_t draw_index(uint64_t w, uint32_t m) {
   return (uint32_t)__umul64hi(w, (uint64_t)m);
 }
@@ -225,7 +230,7 @@ inline int grid_for(int64_t n, int block = BLOCK) {
 struct RepHost {
   int64_t n = 0, aoff = 0;
   double box[3] = {0, 0, 0};
-  int nc[3] = {0, 0, 0};     // link cells per dimension (even, edge >= r_dep)
+  int nc[3] = {0, 0, 0};     // link cells per dimension (a multiple of the colour period)
   int64_t ncells = 0;
   int64_t coff = 0;          // offset of the replica's cells in per-cell arrays
   int64_t cso = 0;           // offset of its (ncells + 1)-entry cell_start block
@@ -333,6 +338,9 @@ struct vcsgc_ctx {
   // the MD and energy paths, cleared by anything that changes species)
   bool rho_f_fresh = false;
   uint64_t w = 0;  // sweep counter
+  // colour period per axis: 2 (eight colours, cells of edge >= r_dep) or 3
+  // (27 colours, cells of edge >= r_dep / 2); ncol = per^3
+  int per = 2, ncol = 8;
   uint64_t last_seed = 0;  // seed of the last sweep call (checkpoint state)
   int kmax_used = 0;
   bool mc_stats_stale = false;  // the r < rc list's row statistics not yet taken
@@ -385,7 +393,7 @@ void tstop(vcsgc_ctx *c, int h);
 // for local chains of k trials (8 ceil(N / N_cells) for k = 1).
 inline int64_t stages_per_sweep(const vcsgc_ctx *c) {
   const int64_t m = (c->n + c->ncells - 1) / c->ncells;
-  return 8 * ((m + c->local_steps - 1) / c->local_steps);
+  return (int64_t)c->ncol * ((m + c->local_steps - 1) / c->local_steps);
 }
 
 hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r);

@@ -29,6 +29,7 @@ static_assert(KMAX <= 2 * PTL, "a trial group covers at most 2*PTL neighbours");
 struct RepD {
   int64_t n, aoff;
   int n0, n1, n2;
+  int per, ncol;  // colour period per axis, colours
   int64_t cso, ncpc, roff, S;
   double beta, dmu0, kN, ncbar;
   uint64_t seed, key1;
@@ -101,10 +102,11 @@ __device__ __forceinline__ bool rep_barrier(RepState *st, int G, unsigned long l
 }
 
 __device__ __forceinline__ int64_t p_colour_cell(const RepD &r, int colour, int64_t t) {
-  const int hx = r.n0 >> 1, hy = r.n1 >> 1;
+  const int P = r.per;
+  const int hx = r.n0 / P, hy = r.n1 / P;
   const int64_t ia = t % hx, ib = (t / hx) % hy, ic = t / ((int64_t)hx * hy);
-  const int64_t cx = 2 * ia + (colour & 1), cy = 2 * ib + ((colour >> 1) & 1),
-                cz = 2 * ic + ((colour >> 2) & 1);
+  const int64_t cx = P * ia + colour % P, cy = P * ib + (colour / P) % P,
+                cz = P * ic + colour / (P * P);
   return cx + (int64_t)r.n0 * (cy + (int64_t)r.n1 * cz);
 }
 
@@ -181,7 +183,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
     for (int64_t s = 0; s < r.S; ++s, ++stage_no) {
       const int par = (int)(stage_no & 1);
       const U4 gs = philox(r.seed, r.key1, w, (uint64_t)s, 0, 0);
-      const int colour = (int)(gs.v[0] >> 61);
+      const int colour = stage_colour(gs.v[0], r.ncol);
       long long valid = 0, acc = 0, dn_acc = 0, tie = 0;
       // ---- trials
       for (int64_t t = t_lo + grp; t < t_hi; t += PGROUPS) {
@@ -400,6 +402,8 @@ hipError_t persist_stage_params(vcsgc_ctx *c, const double *dmu0, const double *
     d.n = r.n;
     d.aoff = r.aoff;
     d.n0 = r.nc[0];
+    d.per = c->per;
+    d.ncol = c->ncol;
     d.n1 = r.nc[1];
     d.n2 = r.nc[2];
     d.cso = r.cso;

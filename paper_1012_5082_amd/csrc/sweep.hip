@@ -25,6 +25,7 @@ struct SweepArgs {
   int64_t n;
   int n0, n1, n2;
   int64_t ncpc;  // cells per colour
+  int per, ncol;  // colour period per axis, colours
   int64_t S;
   double beta, dmu0, kN, ncbar;
   uint64_t seed, replica;
@@ -343,12 +344,15 @@ __device__ __forceinline__ void desc_du_group(const SweepArgs &a, int64_t i, int
   du = own + pair + emb;
 }
 
-// Cell of active-cell index t (< ncpc < 2^31) in a stage of the given colour.
+// Cell of active-cell index t (< ncpc < 2^31) in a stage of the given colour:
+// cell (per ia + colour % per, per ib + (colour / per) % per, per ic + colour / per^2).
 __device__ __forceinline__ int64_t colour_cell(const SweepArgs &a, int colour, int64_t t) {
-  const uint32_t hx = (uint32_t)(a.n0 >> 1), hy = (uint32_t)(a.n1 >> 1);
+  const uint32_t P = (uint32_t)a.per;
+  const uint32_t hx = (uint32_t)a.n0 / P, hy = (uint32_t)a.n1 / P;
   const uint32_t u = (uint32_t)t, q = u / hx, ia = u - q * hx, ic = q / hy, ib = q - ic * hy;
-  const int64_t cx = 2 * (int64_t)ia + (colour & 1), cy = 2 * (int64_t)ib + ((colour >> 1) & 1),
-                cz = 2 * (int64_t)ic + ((colour >> 2) & 1);
+  const uint32_t k = (uint32_t)colour, k1 = k / P;
+  const int64_t cx = (int64_t)(P * ia + (k - k1 * P)), cy = (int64_t)(P * ib + (k1 % P)),
+                cz = (int64_t)(P * ic + k1 / P);
   return cx + (int64_t)a.n0 * (cy + (int64_t)a.n1 * cz);
 }
 
@@ -383,7 +387,7 @@ __global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
   const int64_t s = q / a.ncpc, t = q - s * a.ncpc;
   const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
   if (t == 0) a.stage_lnug[s] = log(unit_open(g.v[1]));
-  const int64_t cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+  const int64_t cell = colour_cell(a, stage_colour(g.v[0], a.ncol), t);
   const int32_t st = a.cstart[cell];
   const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
   // trial k of the cell's chain: Philox(key, (w, s, cell, 1 + k))
@@ -445,7 +449,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, in
             double *L = a.tlog + 8 * idx;
             L[0] = (double)w;
             L[1] = (double)s;
-            L[2] = (double)colour_cell(a, (int)(g.v[0] >> 61), t);
+            L[2] = (double)colour_cell(a, stage_colour(g.v[0], a.ncol), t);
             L[3] = (double)i;
             L[4] = (double)dn;
             L[5] = ok ? 1.0 : 0.0;
@@ -514,7 +518,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_a
             double *L = a.tlog + 8 * idx;
             L[0] = (double)w;
             L[1] = (double)s;
-            L[2] = (double)(colour_cell(a, (int)(g.v[0] >> 61), t) * a.K + k);
+            L[2] = (double)(colour_cell(a, stage_colour(g.v[0], a.ncol), t) * a.K + k);
             L[3] = (double)i;
             L[4] = (double)dn;
             L[5] = ok ? 1.0 : 0.0;
@@ -644,7 +648,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_da(SweepArgs a, uint64_t w_arg,
   U4 r = {};
   if (has && (pass1 || a.tlog || a.dalog)) {
     const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
-    cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+    cell = colour_cell(a, stage_colour(g.v[0], a.ncol), t);
     r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
   }
   long long valid = 0, acc = 0, dn_acc = 0, tie = 0, p1 = 0;
@@ -790,7 +794,7 @@ __device__ __forceinline__ void stage_stats(const SweepArgs &a, uint64_t w, int6
         double *L = a.slog + 8 * idx;
         L[0] = (double)w;
         L[1] = (double)s;
-        L[2] = (double)(int)(philox(a.seed, a.replica, w, (uint64_t)s, 0, 0).v[0] >> 61);
+        L[2] = (double)stage_colour(philox(a.seed, a.replica, w, (uint64_t)s, 0, 0).v[0], a.ncol);
         L[3] = (double)dn_tot;
         L[4] = (double)nrec;
         L[5] = (double)gacc;
@@ -917,7 +921,7 @@ __device__ __forceinline__ void draw_site_g(const SweepArgs &a, uint64_t w, int6
                                             const U4 &g, int32_t *sites, double *lnus,
                                             double *lnug, double *lnus2) {
   if (t == 0) *lnug = log(unit_open(g.v[1]));
-  const int64_t cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+  const int64_t cell = colour_cell(a, stage_colour(g.v[0], a.ncol), t);
   const int32_t st = a.cstart[cell];
   const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
   int32_t site = -1;
@@ -1006,7 +1010,7 @@ __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t 
             double *L = a.tlog + 8 * idx;
             L[0] = (double)w;
             L[1] = (double)s;
-            L[2] = (double)colour_cell(a, (int)(g.v[0] >> 61), t);
+            L[2] = (double)colour_cell(a, stage_colour(g.v[0], a.ncol), t);
             L[3] = (double)i;
             L[4] = (double)dn;
             L[5] = ok ? 1.0 : 0.0;
@@ -1144,7 +1148,7 @@ __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, i
   int64_t cell = -1;  // for the logs only
   if (has && (a.tlog || a.dalog)) {
     const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
-    cell = colour_cell(a, (int)(g.v[0] >> 61), t);
+    cell = colour_cell(a, stage_colour(g.v[0], a.ncol), t);
   }
   long long valid = 0, dn_acc = 0, tie = 0, p1 = 0;
   if (lane == 0 && t < a.ncpc) {
@@ -1342,7 +1346,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
         double *L = a.slog + 8 * idx;
         L[0] = (double)m.w;
         L[1] = (double)m.s;
-        L[2] = (double)(int)(philox(a.seed, a.replica, m.w, (uint64_t)m.s, 0, 0).v[0] >> 61);
+        L[2] = (double)stage_colour(philox(a.seed, a.replica, m.w, (uint64_t)m.s, 0, 0).v[0], a.ncol);
         L[3] = (double)dn_tot;
         L[4] = (double)nrec;
         L[5] = (double)gacc;
@@ -1971,7 +1975,9 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.n0 = c->nc[0];
   a.n1 = c->nc[1];
   a.n2 = c->nc[2];
-  a.ncpc = c->ncells / 8;
+  a.per = c->per;
+  a.ncol = c->ncol;
+  a.ncpc = c->ncells / c->ncol;
   a.K = c->local_steps;
   a.S = stages_per_sweep(c);
   a.beta = 1.0 / (KB * T);

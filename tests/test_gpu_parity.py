@@ -544,3 +544,90 @@ def test_full_size_c3_sweep_and_md(torch_cuda, oracle_mod, c3_data):
 
 def x_size(d):
     return d["x"].size
+
+
+@pytest.mark.parametrize("path", ["stage_logged", "batch", "graph", "chain3", "da_perfect"])
+def test_colours27_parity(torch_cuda, oracle_mod, path):
+    """The 27-colour scheme (cells of edge >= r_dep / 2, colours by indices
+    modulo 3) on every sweep kernel family: the chain equals the oracle's
+    chain with the same colouring, bit for bit (trial and stage logs too on
+    the logged path)."""
+    O = oracle_mod
+    from paper_1012_5082_amd.binding import VCSGC
+    pot = I.params("FS-P1")
+    d = W.c2(cbar=0.05)
+    k = 3 if path == "chain3" else 1
+    args = (d["dmu0"], 10.0, d["cbar"], d["T"])
+    g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, colours=27)
+    info = g.info()
+    nc = np.array(info["n_cells"])
+    assert np.all(nc % 3 == 0) and np.array_equal(nc, O.cell_grid(d["box"], 2 * pot.rc, 3))
+    ncells = int(np.prod(nc))
+    assert info["stages_per_sweep"] == 27 * -(-d["x"].size // ncells)
+    if path == "stage_logged":
+        g.set_tuning("stage", 1)
+        g.enable_log(3 * info["stages_per_sweep"] * (ncells // 27), 3 * info["stages_per_sweep"])
+    elif path == "batch":
+        g.set_tuning("batch", 4)
+    elif path == "graph":
+        g.set_tuning("graph", 1)
+    elif path == "chain3":
+        g.set_local_steps(k)
+    elif path == "da_perfect":
+        g.set_surrogate("perfect")
+    sg = g.sweep(*args, 2, d["seed"])
+    sg2 = g.sweep(*args, 1, d["seed"])
+    st = oracle_state(O, d, pot)
+    log = path == "stage_logged"
+    over = None
+    if log:
+        tl_g, sl_g, _, _ = g.logs()
+        over = tie_overrides(tl_g, sl_g)
+    so, tl_o, sl_o = O.sweep(st, *args, 3, d["seed"], log_trials=10 ** 8 if log else 0,
+                             log_stages=10 ** 8 if log else 0, overrides=over, local_steps=k,
+                             colour_period=3)
+    if log:
+        compare_logs(tl_g, sl_g, tl_o, sl_o)
+    for key in ("trials", "local_accepts", "stages", "stage_accepts", "flips"):
+        assert sg[key] + sg2[key] == so[key], key
+    assert sg2["n_final"] == so["n_final"]
+    assert so["stage_accepts"] > 0
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    g.close()
+
+
+def test_colours27_after_md_and_replicas(torch_cuda, oracle_mod):
+    """27 colours after MD with velocities (batched pipeline), and in a
+    replica batch (persistent launch): both equal the oracle."""
+    O = oracle_mod
+    from paper_1012_5082_amd.binding import VCSGC, VCSGCBatch
+    pot = I.params("FS-P1")
+    d = _md_system(n=16, c=0.1, seed=49)
+    x, y, z, vx, vy, vz, *_ = O.md(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                                   d["species"], d["box"], pot, 1.0, 20)
+    g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
+              vz=d["vz"], colours=27)
+    g.md(1.0, 20)
+    g.set_tuning("batch", 4)
+    sg = g.sweep(d["dmu0"], 1.0, d["cbar"], d["T"], 2, d["seed"])
+    st = O.SweepState(x, y, z, d["box"], d["species"], pot, vx=vx, vy=vy, vz=vz)
+    so, _, _ = O.sweep(st, d["dmu0"], 1.0, d["cbar"], d["T"], 2, d["seed"], colour_period=3)
+    for key in ("trials", "local_accepts", "stages", "stage_accepts", "flips", "n_final"):
+        assert sg[key] == so[key], key
+    assert sg["flips"] > 0
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    for nm in ("vx", "vy", "vz"):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), getattr(st, nm)), nm
+    g.close()
+    reps = _replica_set(n_rep=4, seed=57)
+    b = VCSGCBatch(reps, pot, colours=27)
+    par = [np.array([r[k] for r in reps]) for k in ("dmu0", "kappa", "cbar", "T")]
+    s1 = b.sweep_batch(*par, 2, 888)
+    for k, r in enumerate(reps):
+        stk = O.SweepState(r["x"], r["y"], r["z"], r["box"], r["species"], pot)
+        sok, _, _ = O.sweep(stk, r["dmu0"], r["kappa"], r["cbar"], r["T"], 2, 888, replica=k,
+                            colour_period=3)
+        assert s1[k]["flips"] == sok["flips"] and s1[k]["n_final"] == sok["n_final"], k
+        assert np.array_equal(b.replica_species(k), stk.species), k
+    b.close()

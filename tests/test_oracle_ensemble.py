@@ -18,10 +18,10 @@ import exact_refs as X
 from paper_1012_5082_amd import inputs as I
 
 
-def _chain(O, st, n_sweeps, dmu0, kappa, cbar, T, seed, one_cell=False, energy=False):
+def _chain(O, st, n_sweeps, dmu0, kappa, cbar, T, seed, one_cell=False, energy=False, period=2):
     ns, us = [], []
     for _ in range(n_sweeps):
-        O.sweep(st, dmu0, kappa, cbar, T, 1, seed, one_cell=one_cell)
+        O.sweep(st, dmu0, kappa, cbar, T, 1, seed, one_cell=one_cell, colour_period=period)
         ns.append(int(st.n_b[0]))
         if energy:
             us.append(O.energy_total(O.energy_atoms(st.nl, st.species, st.pot)))
@@ -50,13 +50,15 @@ def test_ideal_sgc_closed_form(oracle_mod):
     assert abs(ns.var() / (st.n * c * (1 - c)) - 1.0) < 0.2
 
 
-@pytest.mark.parametrize("kappa,cbar,dmu0", [(2.0, 0.2, 0.0), (10.0, 0.2, 0.0)])
-def test_ideal_vcsgc_exact_distribution(oracle_mod, kappa, cbar, dmu0):
+@pytest.mark.parametrize("kappa,cbar,dmu0,period", [(2.0, 0.2, 0.0, 2), (10.0, 0.2, 0.0, 2),
+                                                   (2.0, 0.2, 0.0, 3)])
+def test_ideal_vcsgc_exact_distribution(oracle_mod, kappa, cbar, dmu0, period):
+    """period 3: the 27-colour scheme (cells of edge >= r_dep / 2)."""
     O = oracle_mod
     st = _c1_state(O, I.params("IDEAL"), c_init=cbar)
     T = 600.0
-    _chain(O, st, 30, dmu0, kappa, cbar, T, seed=202)
-    ns, _ = _chain(O, st, 600, dmu0, kappa, cbar, T, seed=202)
+    _chain(O, st, 30, dmu0, kappa, cbar, T, seed=202, period=period)
+    ns, _ = _chain(O, st, 600, dmu0, kappa, cbar, T, seed=202, period=period)
     p = X.normalize(X.vcsgc_logw_ideal(st.n, T, dmu0, kappa, cbar))
     m, v = X.moments(p)
     mean, err = X.batch_means(ns)
@@ -81,7 +83,8 @@ def test_ideal_vcsgc_wrong_sign_is_distinguishable():
     assert abs(m2 - m) > 20 * math.sqrt(v)
 
 
-def test_indep_poisson_binomial(oracle_mod):
+@pytest.mark.parametrize("period", [2, 3])
+def test_indep_poisson_binomial(oracle_mod, period):
     O = oracle_mod
     pot = I.params("INDEP")
     st = _c1_state(O, pot, c_init=0.1, thermal=41)
@@ -91,8 +94,8 @@ def test_indep_poisson_binomial(oracle_mod):
     de = (-pot.a_b + pot.a_a) * np.sqrt(rho)
     p = X.normalize(X.vcsgc_logw_indep(de, T, dmu0, kappa, cbar))
     m, v = X.moments(p)
-    _chain(O, st, 30, dmu0, kappa, cbar, T, seed=303)
-    ns, _ = _chain(O, st, 600, dmu0, kappa, cbar, T, seed=303)
+    _chain(O, st, 30, dmu0, kappa, cbar, T, seed=303, period=period)
+    ns, _ = _chain(O, st, 600, dmu0, kappa, cbar, T, seed=303, period=period)
     mean, err = X.batch_means(ns)
     assert abs(mean - m) < 3 * err, (mean, m, err)
     assert abs(ns.var() / v - 1.0) < 0.25
@@ -231,17 +234,32 @@ def test_rho_cache_matches_fresh_density(oracle_mod):
     assert np.max(np.abs(fresh - st.rho)) < 1e-12
 
 
-def test_same_stage_sites_are_independent(oracle_mod):
+@pytest.mark.parametrize("period", [2, 3])
+def test_same_stage_sites_are_independent(oracle_mod, period):
     """Within a stage every pair of trial sites is at least 2 rc apart (no
-    site's energy change depends on another's species or density)."""
+    site's energy change depends on another's species or density), for the
+    eight-colour octant scheme and the 27-colour scheme on half-width cells;
+    a stage's trials are the non-empty cells of one colour, C ceil(N / N_cells)
+    stages per sweep."""
     O = oracle_mod
     pot = I.params("FS-P1")
     x, y, z, box = I.bcc(20, 20, 20)
     x, y, z = I.thermalize(x, y, z, box, 0.05, 81)
     sp = I.initial_species(x.size, 0.05, 82)
     st = O.SweepState(x, y, z, box, sp, pot)
-    _, tl, _ = O.sweep(st, -0.37, 1000.0, 0.05, 600.0, 1, 99, log_trials=200000)
+    _, tl, sl = O.sweep(st, -0.37, 1000.0, 0.05, 600.0, 1, 99, log_trials=300000,
+                        log_stages=10000, colour_period=period)
+    nc = O.cell_grid(box, 2 * pot.rc, period)
+    ncells = int(np.prod(nc))
+    assert np.all(nc % period == 0)
+    assert np.all(box / nc >= 2 * pot.rc / (period - 1))
+    ncol = period ** 3
+    assert sl.shape[0] == ncol * -(-x.size // ncells)
+    assert set(np.unique(sl[:, 2]).astype(int)) <= set(range(ncol))
+    assert len(np.unique(sl[:, 2])) == ncol
     stages = tl[:, 1].astype(int)
+    counts = np.bincount(stages, minlength=sl.shape[0])
+    assert counts.max() <= ncells // ncol
     for s in np.unique(stages)[:40]:
         sites = tl[stages == s, 3].astype(int)
         P = np.stack([x[sites], y[sites], z[sites]], 1)
