@@ -214,7 +214,7 @@ def bench_replicas(args):
         x, y, z, box = I.bcc(r["nx"], r["ny"], r["nz"])
         reps.append(dict(x=x, y=y, z=z, box=box,
                          species=I.initial_species(x.size, r["cbar"], r["seed"]), **r))
-    b = VCSGCBatch(reps, pot)
+    b = VCSGCBatch(reps, pot, colours=args.colours)
     par = [np.array([r[k] for r in reps]) for k in ("dmu0", "kappa", "cbar", "T")]
     seed = 4004
     tuned = autotune.tune(b, lambda k: b.sweep_batch(*par, k, seed, stats=False), use_cache=False)
@@ -230,6 +230,7 @@ def bench_replicas(args):
            "sites_total": int(sum(sizes)), "sites_min": min(sizes), "sites_max": max(sizes),
            "sweeps": n_sw, "seconds": round(dt, 4), "flips_per_s": round(flips / dt, 1),
            "tiling": list(tuned["choice"]), "workgroups": b.tuning()["workgroups"],
+           "colours": args.colours,
            "autotune_ms_per_sweep": {k: round(v, 3) for k, v in tuned["times_ms"].items()},
            "mean_c_first8": [round(c, 5) for c in cmean[:8]],
            "cbar_first8": [round(float(r["cbar"]), 5) for r in reps[:8]]}
@@ -398,7 +399,7 @@ def main():
     ap.add_argument("--tiling", default="batch:4",
                     help="c3: sweep tiling strategy:k, or 'auto' for the autotuner")
     ap.add_argument("--colours", type=int, default=8, choices=[8, 27],
-                    help="c3: colours of the sweep (27: cells of edge >= r_dep / 2)")
+                    help="c3, c4: colours of the sweep (27: cells of edge >= r_dep / 2)")
     ap.add_argument("--skin", type=float, default=0.3,
                     help="c3: MD neighbour-list skin (A)")
     ap.add_argument("--relax", type=int, default=0,
