@@ -437,20 +437,41 @@ __device__ __forceinline__ void md_row_stats(long long pairs, int kmx, bool ovf,
   block_row_stats(pairs, kmx, ovf, &ds->pairs_md, &ds->kmax_md, &ds->overflow);
 }
 
+// v[0 .. KMAX) sorted ascending in place by a fixed bitonic network (static
+// register indices throughout).
+__device__ __forceinline__ void sort_row(int32_t (&v)[KMAX]) {
+#pragma unroll
+  for (int k = 2; k <= KMAX; k <<= 1) {
+#pragma unroll
+    for (int h = k >> 1; h > 0; h >>= 1) {
+#pragma unroll
+      for (int a = 0; a < KMAX; ++a) {
+        const int b = a ^ h;
+        if (b > a) {
+          const int32_t lo = min(v[a], v[b]), hi = max(v[a], v[b]);
+          const bool up = (a & k) == 0;
+          v[a] = up ? lo : hi;
+          v[b] = up ? hi : lo;
+        }
+      }
+    }
+  }
+}
+
 // r < rc + skin list, one lane per atom (used when some axis has fewer than
 // four search bins): the lane walks the surrounding search bins through the
-// packed (x, y, z, index) slots, appends hits to its row, then reloads the
-// row into registers, sorts it by a fixed bitonic network (ascending
-// neighbour index) and writes it back.  The test is r^2 < cut2: the list
-// only has to hold every pair that can come within rc before the next
-// rebuild (its users test r < rc themselves).  Row-major rows [i * KMAX + k]
-// (k_md_transpose then writes the column-major copy).
+// packed (x, y, z, index) slots and appends hits to its row; INT32_MAX fills
+// the rest of the row.  The test is r^2 < cut2: the list only has to hold
+// every pair that can come within rc before the next rebuild (its users test
+// r < rc themselves).  Row-major rows [i * KMAX + k], unsorted (k_md_finish
+// then sorts them into the column-major list and writes the row lengths and
+// the positions of this build).
 // cond (may be NULL): run only when *cond != 0 (and count the rebuild).
 __global__ void __launch_bounds__(BLOCK)
     k_build_md(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                const double *__restrict__ z, Grid g, const int32_t *__restrict__ bcount,
-               const double4 *__restrict__ bpos, int bmax, double cut2, int32_t *nj, uint8_t *cnt,
-               double *xr, double *yr, double *zr, DevState *ds, const int *cond) {
+               const double4 *__restrict__ bpos, int bmax, double cut2, int32_t *nj, DevState *ds,
+               const int *cond) {
   if (cond && *cond == 0) return;
   if (cond && blockIdx.x == 0 && threadIdx.x == 0) ds->md_rebuilds += 1ull;
   const int64_t i = xcd_block() * BLOCK + threadIdx.x;
@@ -493,33 +514,7 @@ __global__ void __launch_bounds__(BLOCK)
         }
       }
     }
-    const int cc = c < KMAX ? c : KMAX;
-    int32_t v[KMAX];
-#pragma unroll
-    for (int u = 0; u < KMAX; ++u) v[u] = u < cc ? row[u] : INT32_MAX;
-#pragma unroll
-    for (int k = 2; k <= KMAX; k <<= 1) {
-#pragma unroll
-      for (int h = k >> 1; h > 0; h >>= 1) {
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a) {
-          const int b = a ^ h;
-          if (b > a) {
-            const int32_t lo = min(v[a], v[b]), hi = max(v[a], v[b]);
-            const bool up = (a & k) == 0;
-            v[a] = up ? lo : hi;
-            v[b] = up ? hi : lo;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < KMAX; ++u)
-      if (u < cc) row[u] = v[u];
-    cnt[i] = (uint8_t)cc;
-    xr[i] = xi;
-    yr[i] = yi;
-    zr[i] = zi;
+    for (int u = c; u < KMAX; ++u) row[u] = INT32_MAX;
   }
   md_row_stats(c < KMAX ? c : KMAX, c < KMAX ? c : KMAX, c > KMAX, ds);
 }
@@ -569,37 +564,43 @@ __device__ __forceinline__ int2 block_scan2(int &a, int &b, int2 *wtot) {
 // r < rc + skin list by regions of 4 x 4 x RZ search bins (every axis needs at
 // least four bins).  For each of its regions a block stages the 6 x 6 x
 // (RZ + 2) bins around it in LDS: positions relative to the region origin in
-// float, periodic images resolved, each bin's atoms contiguous.  One lane per
-// own atom then walks the atom's 27 neighbouring bins (nine runs of three
-// staged bins consecutive in x) and appends its hits to its row, row-major
-// and unsorted (k_md_finish sorts them); own atoms also record their
-// positions of this build.  The float test uses cut2f = (cut + 1e-3)^2, a
-// superset of r < cut (the float rounding of the relative coordinates stays
-// below 1e-4 A); users of the list test r < rc in FP64 themselves.
-// Grid-stride: the blocks on XCD x (blockIdx mod 8 == x; the grid is a
-// multiple of 8) take the x-th eighth of the regions, so neighbouring regions
-// share that XCD's L2.  BMAX is the bin capacity.
+// float, periodic images resolved, each bin's atoms contiguous (at most CAP
+// staged atoms: a denser region raises the bin-overflow flag, which has the
+// bins grown to the next capacity, whose kernel stages every slot).  One lane
+// per own atom then walks the atom's 27 neighbouring bins (nine runs of three
+// staged bins consecutive in x) and notes the staged index of each hit in its
+// own LDS column; at the end it stores the whole row of its hits' atom
+// indices (row-major, unsorted, INT32_MAX after the last hit) in 16-byte
+// pieces, so that every line of a row is written at once.  The float test uses
+// cut2f = (cut + 1e-3)^2, a superset of r < cut (the float rounding of the
+// relative coordinates stays below 1e-4 A); users of the list test r < rc in
+// FP64 themselves.  Grid-stride: the blocks on XCD x (blockIdx mod 8 == x;
+// the grid is a multiple of 8) take the x-th eighth of the regions, so
+// neighbouring regions share that XCD's L2.  BMAX is the bin capacity.
 // cond (may be NULL): run only when *cond != 0 (and count the rebuild).
 constexpr int RG_X = 4, RG_Y = 4;  // own bins of a region along x and y
 constexpr int RG_GRID = 2048;      // blocks of a region launch (at most)
 
-template <int BMAX, int RZ>
+template <int BMAX, int RZ, int CAP>
 __global__ void __launch_bounds__(BLOCK)
     k_md_search(Grid g, int nrx, int nry, int64_t nreg, const int32_t *__restrict__ bcount,
-                const double4 *__restrict__ bpos, float cut2f, int32_t *rows, uint8_t *cnt,
-                double *xr, double *yr, double *zr, DevState *ds, const int *cond) {
+                const double4 *__restrict__ bpos, float cut2f, int32_t *rows, DevState *ds,
+                const int *cond) {
   constexpr int SX = RG_X + 2, SY = RG_Y + 2, SZ = RZ + 2, NST = SX * SY * SZ;
   constexpr int OWN_CAP = RG_X * RG_Y * RZ * BMAX;
   static_assert(NST <= BLOCK && NST <= 256, "one thread per staged bin, bin ids in a byte");
+  static_assert(CAP <= NST * BMAX && CAP + 3 <= 65536, "staged indices in 16 bits");
   if (cond && *cond == 0) return;
   if (cond && blockIdx.x == 0 && threadIdx.x == 0) ds->md_rebuilds += 1ull;
-  __shared__ float4 cand[NST * BMAX];
+  __shared__ float4 cand[CAP + 3];  // + 3: the search reads up to 3 past a run
   __shared__ int off[NST + 1];
   __shared__ int gbin[NST];
-  __shared__ double3 shift[NST];
-  __shared__ int own_si[OWN_CAP];          // staged index of own atom q
+  __shared__ char4 shc[NST];                // periodic image of staged bin u: -1, 0, +1 per axis
+  __shared__ int own_si[OWN_CAP];           // staged index of own atom q
   __shared__ unsigned char own_b[OWN_CAP];  // staged bin of own atom q
   __shared__ int own_off[NST];
+  // column t: staged indices of lane t's hits, its own atom among them
+  __shared__ unsigned short hit[KMAX + 1][BLOCK];
   __shared__ int2 wtot[BLOCK / 64];
   const int tid = threadIdx.x;
   const int xcd = (int)(blockIdx.x & 7u);
@@ -620,19 +621,23 @@ __global__ void __launch_bounds__(BLOCK)
       int gx = RG_X * rx - 1 + ux, gy = RG_Y * ry - 1 + uy, gz = RZ * rz - 1 + uz;
       const bool own = ux >= 1 && ux <= RG_X && uy >= 1 && uy <= RG_Y && uz >= 1 && uz <= RZ &&
                        gx < g.n0 && gy < g.n1 && gz < g.n2;
-      double hx = 0.0, hy = 0.0, hz = 0.0;
-      if (gx < 0) { gx += g.n0; hx = -g.L0; } else if (gx >= g.n0) { gx -= g.n0; hx = g.L0; }
-      if (gy < 0) { gy += g.n1; hy = -g.L1; } else if (gy >= g.n1) { gy -= g.n1; hy = g.L1; }
-      if (gz < 0) { gz += g.n2; hz = -g.L2; } else if (gz >= g.n2) { gz -= g.n2; hz = g.L2; }
+      signed char hx = 0, hy = 0, hz = 0;
+      if (gx < 0) { gx += g.n0; hx = -1; } else if (gx >= g.n0) { gx -= g.n0; hx = 1; }
+      if (gy < 0) { gy += g.n1; hy = -1; } else if (gy >= g.n1) { gy -= g.n1; hy = 1; }
+      if (gz < 0) { gz += g.n2; hz = -1; } else if (gz >= g.n2) { gz -= g.n2; hz = 1; }
       const int b = gx + g.n0 * (gy + g.n1 * gz);
       cn = min(bcount[b], BMAX);
       ocn = own ? cn : 0;
       gbin[tid] = b;
-      shift[tid] = make_double3(hx, hy, hz);
+      shc[tid] = make_char4(hx, hy, hz, 0);
     }
     block_sync_lds();  // the previous region's readers of off / cand are done
     int os = cn, oo = ocn;
     const int2 tot = block_scan2(os, oo, wtot);
+    if (tot.x > CAP) {  // uniform over the block
+      if (tid == 0) atomicOr(&ds->bin_overflow, 1);
+      continue;
+    }
     if (tid < NST) {
       off[tid] = os;
       own_off[tid] = oo;
@@ -640,6 +645,7 @@ __global__ void __launch_bounds__(BLOCK)
     if (tid == 0) off[NST] = tot.x;
     block_sync_lds();
     // stage: staged atom c of bin u (off[u] <= c < off[u + 1]); four in flight
+#pragma unroll 1
     for (int c0 = 0; c0 < tot.x; c0 += 4 * BLOCK) {
       double4 p[4];
       int uu[4];
@@ -662,19 +668,17 @@ __global__ void __launch_bounds__(BLOCK)
         const int u = uu[k];
         if (u >= 0) {
           const int c = c0 + k * BLOCK + tid;
-          const double3 h = shift[u];
-          cand[c] = make_float4((float)(p[k].x + h.x - o0), (float)(p[k].y + h.y - o1),
-                                (float)(p[k].z + h.z - o2), __int_as_float((int32_t)p[k].w));
+          const char4 h = shc[u];
+          // the image shift is exactly -L, 0 or +L
+          cand[c] = make_float4((float)(p[k].x + h.x * g.L0 - o0),
+                                (float)(p[k].y + h.y * g.L1 - o1),
+                                (float)(p[k].z + h.z * g.L2 - o2), __int_as_float((int32_t)p[k].w));
           const int ub = u % SX, vb = (u / SX) % SY, wb = u / (SX * SY);
           if (ub >= 1 && ub <= RG_X && vb >= 1 && vb <= RG_Y && wb >= 1 && wb <= RZ &&
               own_off[u] < (u + 1 < NST ? own_off[u + 1] : tot.y)) {
             const int q = own_off[u] + (c - off[u]);
             own_si[q] = c;
             own_b[q] = (unsigned char)u;
-            const int32_t i = (int32_t)p[k].w;
-            xr[i] = p[k].x;
-            yr[i] = p[k].y;
-            zr[i] = p[k].z;
           }
         }
       }
@@ -686,106 +690,95 @@ __global__ void __launch_bounds__(BLOCK)
       const float4 me = cand[si];
       const int32_t i = __float_as_int(me.w);
       const int lx = u % SX, ly = (u / SX) % SY, lz = u / (SX * SY);
-      int32_t *row = rows + (int64_t)i * KMAX;
+      // every candidate's index goes to slot c, which advances on a hit (no
+      // branch per candidate); the atom itself (d2 = 0) is one of the hits
       int c = 0;
       for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy) {
           const int u0 = (lx - 1) + SX * ((ly + dy) + SY * (lz + dz));
           const int a1 = off[u0 + 3];
-          // four candidates in flight (reads clamped to the run's last one)
+          // four candidates in flight (at most three read past the run)
+#pragma unroll 1
           for (int k0 = off[u0]; k0 < a1; k0 += 4) {
             float4 cc[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) cc[v] = cand[min(k0 + v, a1 - 1)];
+            for (int v = 0; v < 4; ++v) cc[v] = cand[k0 + v];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const float dx = cc[v].x - me.x, dyy = cc[v].y - me.y, dzz = cc[v].z - me.z;
-              if (k0 + v < a1 && dx * dx + dyy * dyy + dzz * dzz < cut2f && k0 + v != si) {
-                if (c < KMAX) row[c] = __float_as_int(cc[v].w);
-                ++c;
-              }
+              const float d2 = __builtin_fmaf(dzz, dzz, __builtin_fmaf(dyy, dyy, dx * dx));
+              hit[min(c, KMAX)][tid] = (unsigned short)(k0 + v);
+              c += (k0 + v < a1 && d2 < cut2f) ? 1 : 0;
             }
           }
         }
-      cnt[i] = (uint8_t)(c < KMAX ? c : KMAX);
-      pairs += c < KMAX ? c : KMAX;
-      kmx = c > kmx ? c : kmx;
-      ovf = ovf || c > KMAX;
+      // c - 1 neighbours; the atom's own slot is skipped by taking the last
+      // stored slot in its place (the own slot is the last one, or the last
+      // one lies beyond the entries read)
+      const int nb = c - 1, cc = nb < KMAX ? nb : KMAX;
+      const int last = hit[min(c - 1, KMAX)][tid];
+#pragma unroll
+      for (int u = 0; u < KMAX; u += 4) {
+        int32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          int sk = hit[u + k][tid];
+          sk = sk == si ? last : sk;
+          w[k] = u + k < cc ? __float_as_int(cand[min(sk, CAP - 1)].w) : INT32_MAX;
+        }
+        *(int4 *)(rows + (int64_t)i * KMAX + u) = make_int4(w[0], w[1], w[2], w[3]);
+      }
+      pairs += cc;
+      kmx = nb > kmx ? nb : kmx;
+      ovf = ovf || nb > KMAX;
     }
   }
   md_row_stats(pairs, kmx < KMAX ? kmx : KMAX, ovf, ds);
 }
 
-// The rows written by the search, sorted (ascending neighbour index) in place
-// (row-major [i * KMAX + k]) and copied column-major [k * n + i] for the
-// lane-per-atom MD passes.  A block handles TR_ATOMS consecutive rows per
-// step through LDS: contiguous 16-byte reads, every entry placed at its rank
-// among its row's entries (four lanes per row), then contiguous writes of
-// both layouts.  Entries at or past a row's length are not written.
-// Grid-stride; cond (may be NULL): run only when *cond != 0.
-constexpr int TR_ATOMS = 64;
+// The rows written by the search (row-major [i * KMAX + k], unsorted,
+// INT32_MAX after the last entry) sorted into the column-major list
+// [k * n + i] of the lane-per-atom MD passes, with the row lengths and the
+// positions of this build (the search ran at the current positions).  One
+// lane per atom: the row's 16-byte pieces into registers, a fixed sorting
+// network, then the entries before the padding stored column-major
+// (consecutive atoms, consecutive addresses).  Grid-stride; cond (may be
+// NULL): run only when *cond != 0.
 constexpr int FIN_GRID = 4096;
 
 __global__ void __launch_bounds__(BLOCK)
-    k_md_finish(int64_t n, int32_t *rows, const uint8_t *__restrict__ cnt, int32_t *nj,
-                const int *cond) {
+    k_md_finish(int64_t n, const int32_t *__restrict__ rows, const double *__restrict__ x,
+                const double *__restrict__ y, const double *__restrict__ z, int32_t *nj,
+                uint8_t *cnt, double *xr, double *yr, double *zr, const int *cond) {
   if (cond && *cond == 0) return;
-  __shared__ int32_t tile[TR_ATOMS][KMAX + 1], srt[TR_ATOMS][KMAX + 1];
-  __shared__ int m_s[TR_ATOMS];
-  const int tid = threadIdx.x;
-  constexpr int PARTS = KMAX / 4;  // int4 per row
-  for (int64_t a0 = (int64_t)blockIdx.x * TR_ATOMS; a0 < n;
-       a0 += (int64_t)gridDim.x * TR_ATOMS) {
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = xcd_block() * BLOCK + threadIdx.x; i < n; i += stride) {
+    int32_t v[KMAX];
 #pragma unroll
-    for (int r = 0; r < TR_ATOMS * PARTS / BLOCK; ++r) {
-      const int q = r * BLOCK + tid, a = q / PARTS, pt = q - a * PARTS;
-      if (a0 + a < n) {
-        const int4 v = ((const int4 *)(rows + (a0 + a) * KMAX))[pt];
-        tile[a][4 * pt + 0] = v.x;
-        tile[a][4 * pt + 1] = v.y;
-        tile[a][4 * pt + 2] = v.z;
-        tile[a][4 * pt + 3] = v.w;
-      }
+    for (int u = 0; u < KMAX; u += 4) {
+      const int4 q = *(const int4 *)(rows + i * KMAX + u);
+      v[u] = q.x;
+      v[u + 1] = q.y;
+      v[u + 2] = q.z;
+      v[u + 3] = q.w;
     }
-    if (tid < TR_ATOMS) m_s[tid] = a0 + tid < n ? cnt[a0 + tid] : 0;
-    block_sync_lds();
-    {  // ranks: four lanes per row; entries are distinct neighbour indices,
-       // and equal ones would keep their order, so the ranks are always a
-       // permutation of 0 .. m - 1 and every written slot is filled
-      const int a = tid >> 2, l = tid & 3, m = m_s[a];
-      for (int e = l; e < m; e += 4) {
-        const int32_t v = tile[a][e];
-        int rank = 0;
-        for (int f = 0; f < m; ++f) rank += (tile[a][f] < v || (tile[a][f] == v && f < e)) ? 1 : 0;
-        srt[a][rank] = v;
-      }
-    }
-    block_sync_lds();
+    sort_row(v);
+    int m = 0;
 #pragma unroll
-    for (int r = 0; r < TR_ATOMS * PARTS / BLOCK; ++r) {
-      const int q = r * BLOCK + tid, a = q / PARTS, pt = q - a * PARTS;
-      if (a0 + a < n && 4 * pt < m_s[a])
-        ((int4 *)(rows + (a0 + a) * KMAX))[pt] =
-            make_int4(srt[a][4 * pt], srt[a][4 * pt + 1], srt[a][4 * pt + 2], srt[a][4 * pt + 3]);
+    for (int k = 0; k < KMAX; ++k) {
+      if (v[k] != INT32_MAX) nj[(int64_t)k * n + i] = v[k];
+      m += v[k] != INT32_MAX ? 1 : 0;
     }
-    {
-      const int a = tid % TR_ATOMS;
-#pragma unroll
-      for (int r = 0; r < KMAX * TR_ATOMS / BLOCK; ++r) {
-        const int k = r * (BLOCK / TR_ATOMS) + tid / TR_ATOMS;
-        if (k < m_s[a]) nj[(int64_t)k * n + a0 + a] = srt[a][k];
-      }
-    }
-    block_sync_lds();  // tile / srt / m_s are written again next step
+    cnt[i] = (uint8_t)m;
+    xr[i] = x[i];
+    yr[i] = y[i];
+    zr[i] = z[i];
   }
 }
-static_assert(TR_ATOMS * (KMAX / 4) % BLOCK == 0 && KMAX * TR_ATOMS % BLOCK == 0 &&
-                  TR_ATOMS * 4 == BLOCK,
-              "whole rounds of the finishing pass");
 
 // the list build from filled search bins (regions when every axis has at
 // least four bins and a bin holds at most 32 atoms, else one lane per atom),
-// then the sorted row-major and column-major rows
+// then the column-major rows, their lengths and the positions of the build
 hipError_t launch_md_build_chain(vcsgc_ctx *c, const Grid &g, const int *cond) {
   const RepHost &r = c->reps[0];
   const double cut = c->pot.rc + c->skin;
@@ -796,22 +789,22 @@ hipError_t launch_md_build_chain(vcsgc_ctx *c, const Grid &g, const int *cond) {
     const int nrz = (g.n2 + rz - 1) / rz;
     const int64_t nreg = (int64_t)nrx * nry * nrz;
     const unsigned G = (unsigned)std::min<int64_t>((nreg + 7) / 8 * 8, RG_GRID);
+    // 16-slot bins: up to eight staged atoms per bin on average (a denser
+    // region has the bins grown); 32-slot bins: every slot
     if (c->bmax == 16)
-      k_md_search<16, 2><<<G, BLOCK, 0, c->stream>>>(g, nrx, nry, nreg, c->bin_count, c->bin_pos,
-                                                     cf * cf, c->md_rows, c->md_cnt, c->xr,
-                                                     c->yr, c->zr, c->ds, cond);
+      k_md_search<16, 2, 6 * 6 * 4 * 8><<<G, BLOCK, 0, c->stream>>>(
+          g, nrx, nry, nreg, c->bin_count, c->bin_pos, cf * cf, c->md_rows, c->ds, cond);
     else
-      k_md_search<32, 1><<<G, BLOCK, 0, c->stream>>>(g, nrx, nry, nreg, c->bin_count, c->bin_pos,
-                                                     cf * cf, c->md_rows, c->md_cnt, c->xr,
-                                                     c->yr, c->zr, c->ds, cond);
+      k_md_search<32, 1, 6 * 6 * 3 * 32><<<G, BLOCK, 0, c->stream>>>(
+          g, nrx, nry, nreg, c->bin_count, c->bin_pos, cf * cf, c->md_rows, c->ds, cond);
   } else {
     k_build_md<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, c->x, c->y, c->z, g, c->bin_count,
                                                        c->bin_pos, c->bmax, cut * cut,
-                                                       c->md_rows, c->md_cnt, c->xr, c->yr,
-                                                       c->zr, c->ds, cond);
+                                                       c->md_rows, c->ds, cond);
   }
-  const unsigned GF = (unsigned)std::min<int64_t>((r.n + TR_ATOMS - 1) / TR_ATOMS, FIN_GRID);
-  k_md_finish<<<GF, BLOCK, 0, c->stream>>>(r.n, c->md_rows, c->md_cnt, c->md_j, cond);
+  const unsigned GF = (unsigned)std::min<int64_t>((r.n + BLOCK - 1) / BLOCK, FIN_GRID);
+  k_md_finish<<<GF, BLOCK, 0, c->stream>>>(r.n, c->md_rows, c->x, c->y, c->z, c->md_j, c->md_cnt,
+                                           c->xr, c->yr, c->zr, cond);
   return hipGetLastError();
 }
 
@@ -865,17 +858,18 @@ __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
   rho[i] = s;
 }
 
-// The r < rc rows taken from a valid r < rc + skin list (MD rows, row-major,
-// ascending j): same entries, same order and the same r values as a build
-// from the search bins, since r is evaluated by the same expression (the
-// packed positions are current whenever the MD list and its densities are).  A group
-// of MFM_G lanes per atom: lane l tests entries l, l + MFM_G, ...; the hits of
-// a pass are placed by a ballot prefix count, so the row keeps the MD order
-// and the stores of a group are contiguous.
+// The r < rc rows taken from a valid r < rc + skin list (the column-major MD
+// list, ascending j): same entries, same order and the same r values as a
+// build from the search bins, since r is evaluated by the same expression
+// (the packed positions are current whenever the MD list and its densities
+// are).  A group of MFM_G lanes per atom: lane l tests entries l, l + MFM_G,
+// ...; the hits of a pass are placed by a ballot prefix count, so the row
+// keeps the MD order and the stores of a group are contiguous.  An index
+// load of a wave covers MFM_G entries of 64 / MFM_G consecutive atoms.
 constexpr int MFM_G = 8;  // measured per sweep: 16 lanes 1% and 4 lanes 12% slower
 
 __global__ void __launch_bounds__(BLOCK)
-    k_mc_from_md(int64_t n, const double4 *__restrict__ ps4, Grid g, const int32_t *__restrict__ mdr,
+    k_mc_from_md(int64_t n, const double4 *__restrict__ ps4, Grid g, const int32_t *__restrict__ mdj,
                  const uint8_t *__restrict__ mdcnt, PotD p, int32_t *nj, double *nr,
                  uint8_t *cnt) {
   const int64_t gid = xcd_block() * BLOCK + threadIdx.x;
@@ -892,7 +886,7 @@ __global__ void __launch_bounds__(BLOCK)
     int32_t j = 0;
     double r = 0.0;
     if (k < m) {
-      j = mdr[i * KMAX + k];
+      j = mdj[(int64_t)k * n + i];
       const double4 qj = ps4[j];
       const double dx = min_image(qj.x - qi.x, g.L0);
       const double dy = min_image(qj.y - qi.y, g.L1);
@@ -916,7 +910,7 @@ hipError_t launch_mc_from_md(vcsgc_ctx *c) {
   Grid g{r.box[0], r.box[1], r.box[2], r.nb[0], r.nb[1], r.nb[2]};
   int h = tstart(c, VCSGC_KT_BUILD);
   k_mc_from_md<<<grid_for(c->n * MFM_G), BLOCK, 0, c->stream>>>(
-      c->n, c->ps4, g, c->md_rows, c->md_cnt, c->pot, c->mc_j, c->mc_r, c->mc_cnt);
+      c->n, c->ps4, g, c->md_j, c->md_cnt, c->pot, c->mc_j, c->mc_r, c->mc_cnt);
   tstop(c, h);
   return hipGetLastError();
 }

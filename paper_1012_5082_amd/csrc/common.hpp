@@ -298,10 +298,10 @@ struct vcsgc_ctx {
   int64_t smp_cap = 0, smp_stride = 1;
   double *dalog = nullptr;
   int64_t dacap = 0;
-  // r < rc + skin list for MD, ascending neighbour index: column-major
-  // [k * n + i] for the lane-per-atom MD passes, and the same rows row-major
-  // [i * KMAX + k] in md_rows for the group-per-atom MC-list refresh; and
-  // positions at its build
+  // r < rc + skin list for MD, ascending neighbour index, column-major
+  // [k * n + i] (md_rows: the search's unsorted row-major rows
+  // [i * KMAX + k], sorted into md_j by the finishing pass); and positions
+  // at its build
   int32_t *md_j = nullptr, *md_rows = nullptr;
   uint8_t *md_cnt = nullptr;
   double *xr = nullptr, *yr = nullptr, *zr = nullptr;

@@ -97,6 +97,53 @@ def test_eam_parity_c2(torch_cuda, oracle_mod):
     _eam_parity(oracle_mod, W.c2(cbar=0.10), I.params("FS-P1"))
 
 
+def _dense_bins_system(kind):
+    """Systems whose search bins need the larger bin capacity.  "cluster": a
+    10^3 bcc block with a vacancy of radius 6 A holding a cluster of 20
+    atoms within 0.4 A (20 atoms in one bin: more than its 16 slots).
+    "clusters": 16 atoms within 0.05 A of every bin centre of a 7^3 grid of
+    4.2 A bins (no bin over 16, but more staged atoms around a region than
+    the 16-slot search stages; clusters 4.1 A apart, beyond rc + skin)."""
+    rng = np.random.default_rng(61 if kind == "cluster" else 62)
+    if kind == "cluster":
+        x, y, z, box = I.bcc(10, 10, 10)
+        c = 0.5 * box
+        keep = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) > 6.0
+        off = rng.uniform(-0.4, 0.4, size=(20, 3)) / np.sqrt(3.0)
+        x = np.concatenate([x[keep], c[0] + off[:, 0]])
+        y = np.concatenate([y[keep], c[1] + off[:, 1]])
+        z = np.concatenate([z[keep], c[2] + off[:, 2]])
+    else:
+        b = 4.2
+        box = np.full(3, 7 * b)
+        g = (np.arange(7) + 0.5) * b
+        cx, cy, cz = [a.ravel() for a in np.meshgrid(g, g, g, indexing="ij")]
+        k = np.arange(16)
+        grid = 0.025 * np.stack([k % 2, (k // 2) % 2, k // 4], axis=1) - [0.0125, 0.0125, 0.0375]
+        off = grid[None] + rng.uniform(-0.003, 0.003, size=(cx.size, 16, 3))
+        x = (cx[:, None] + off[..., 0]).ravel()
+        y = (cy[:, None] + off[..., 1]).ravel()
+        z = (cz[:, None] + off[..., 2]).ravel()
+    sp = I.initial_species(x.size, 0.2, 63)
+    return dict(x=x, y=y, z=z, box=np.asarray(box, dtype=np.float64), species=sp)
+
+
+@pytest.mark.parametrize("kind", ["cluster", "clusters"])
+def test_eam_parity_dense_bins(torch_cuda, oracle_mod, kind):
+    """Bins grown on the way (the 32-slot search): densities, energies and
+    forces still equal the oracle's bit for bit, and the MD list holds every
+    pair within rc + skin."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = _dense_bins_system(kind)
+    _eam_parity(O, d, pot)
+    g = gpu_context(d, pot, forces=True)
+    g.energy(forces=True)
+    nl = O.neighbors(d["x"], d["y"], d["z"], d["box"], pot.rc + 0.3, vectors=False)
+    assert g.info()["md_pairs"] == nl.j.size
+    g.close()
+
+
 def _sweep_parity(O, d, pot, n_sweeps, kappa=None, cbar=None, log=True, chunks=None,
                   strategy="graph", trials_per_group=1):
     kappa = d["kappa"] if kappa is None else kappa
@@ -424,8 +471,12 @@ def test_md_parity_build_paths(torch_cuda, oracle_mod, n, skin):
     assert info["md_rebuilds"] >= 1
     x, y, z = out[0], out[1], out[2]
     nl = O.neighbors(x, y, z, d["box"], pot.rc, vectors=False)
-    g.sweep(d["dmu0"], 0.0, d["cbar"], d["T"], 0, d["seed"])  # refreshes the r < rc list
+    # the r < rc list filtered out of the MD list and the density cache from
+    # the last MD density pass
+    g.sweep(d["dmu0"], 0.0, d["cbar"], d["T"], 0, d["seed"])
     assert g.info()["mc_pairs"] == nl.j.size
+    assert g.info()["mc_kmax_used"] == int(np.diff(nl.start).max())
+    assert np.array_equal(g.rho().cpu().numpy(), O.density(nl, d["species"], pot))
     g.close()
 
 
