@@ -396,7 +396,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=0, help="c4/c5: timed sweeps")
     ap.add_argument("--local-steps", type=int, default=1,
                     help="c3: trials per active cell per stage (1 = the plain scheme)")
-    ap.add_argument("--tiling", default="batch:4",
+    ap.add_argument("--tiling", default="batch:3",
                     help="c3: sweep tiling strategy:k, or 'auto' for the autotuner")
     ap.add_argument("--colours", type=int, default=8, choices=[8, 27],
                     help="c3, c4: colours of the sweep (27: cells of edge >= r_dep / 2)")

@@ -407,6 +407,14 @@ vcsgc_status vcsgc_descriptors(vcsgc_ctx *ctx, const int32_t *sites_dev, int64_t
 /* Diagnostics: out[i] = sqrt(in[i]) in FP64 on the device, n >= 0. */
 vcsgc_status vcsgc_selftest_sqrt(const double *in_dev, double *out_dev, int64_t n,
                                  hipStream_t stream);
+/* Diagnostics: the square root and quotient of the MD density and force
+ * passes, sqrt_dev[i] = sqrt(a[i]) and div_dev[i] = a[i] / b[i] (Newton-
+ * Raphson refinements of reciprocal(-square-root) estimates with a final
+ * fused-multiply-add correction; meant for 2^-767 <= a[i] <= DBL_MAX and, for
+ * the quotient, normal operands whose quotient is far from the ends of the
+ * exponent range, where both are correctly rounded), n >= 0. */
+vcsgc_status vcsgc_selftest_md_math(const double *a_dev, const double *b_dev, double *sqrt_dev,
+                                    double *div_dev, int64_t n, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -181,6 +181,8 @@ def lib():
         L.vcsgc_descriptors.argtypes = [_P, _P, C.c_int64, C.c_int32, _P]
         L.vcsgc_selftest_sqrt.restype = st
         L.vcsgc_selftest_sqrt.argtypes = [_P, _P, C.c_int64, _P]
+        L.vcsgc_selftest_md_math.restype = st
+        L.vcsgc_selftest_md_math.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
         _lib = L
     return _lib
 
@@ -214,6 +216,19 @@ def selftest_sqrt(x):
         raise VcsgcError(rc, "selftest_sqrt")
     torch.cuda.synchronize()
     return out
+
+
+def selftest_md_math(a, b):
+    """(sqrt(a), a / b) as the MD passes compute them, for CUDA float64
+    tensors a, b of one shape (diagnostic)."""
+    import torch
+    sq, q = torch.empty_like(a), torch.empty_like(a)
+    rc = lib().vcsgc_selftest_md_math(_P(a.data_ptr()), _P(b.data_ptr()), _P(sq.data_ptr()),
+                                      _P(q.data_ptr()), a.numel(), _stream_handle())
+    if rc:
+        raise VcsgcError(rc, "selftest_md_math")
+    torch.cuda.synchronize()
+    return sq, q
 
 
 class VCSGC:

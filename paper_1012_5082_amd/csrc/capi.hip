@@ -1199,4 +1199,12 @@ vcsgc_status vcsgc_selftest_sqrt(const double *in_dev, double *out_dev, int64_t 
   return e == hipSuccess ? VCSGC_OK : VCSGC_E_DEVICE;
 }
 
+vcsgc_status vcsgc_selftest_md_math(const double *a_dev, const double *b_dev, double *sqrt_dev,
+                                    double *div_dev, int64_t n, hipStream_t stream) {
+  if (n < 0 || (n > 0 && (!a_dev || !b_dev || !sqrt_dev || !div_dev)))
+    return VCSGC_E_INVALID_ARG;
+  hipError_t e = vc::launch_md_math(a_dev, b_dev, sqrt_dev, div_dev, n, stream);
+  return e == hipSuccess ? VCSGC_OK : VCSGC_E_DEVICE;
+}
+
 }  // extern "C"

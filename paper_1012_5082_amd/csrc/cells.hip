@@ -973,4 +973,20 @@ hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s) 
   return hipGetLastError();
 }
 
+__global__ void k_md_math(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                          double *sq, double *q) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    sq[i] = sqrt_md(a[i]);
+    q[i] = div_md(a[i], b[i]);
+  }
+}
+
+hipError_t launch_md_math(const double *a, const double *b, double *sq, double *q, int64_t n,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_md_math<<<grid_for(n), BLOCK, 0, s>>>(n, a, b, sq, q);
+  return hipGetLastError();
+}
+
 }  // namespace vc

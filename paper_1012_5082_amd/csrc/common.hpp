@@ -150,6 +150,45 @@ __device__ __forceinline__ double pair_dd(const PotD &p, double r) {
 }
 __device__ __forceinline__ double pair_g(const PotD &p, double r) { return p.c0 + p.c1 * r; }
 
+// Square root of the MD passes, for 2^-767 <= x <= DBL_MAX: an estimate of
+// 1/sqrt(x) refined by one coupled Newton-Raphson step for g ~ sqrt(x) and
+// h ~ 1/(2 sqrt(x)) (Goldschmidt's iteration), then two corrections
+// g += (x - g^2) h whose residuals are exact in a fused multiply-add
+// (Markstein, IA-64 and Elementary Functions, 2000).  Over that range the
+// result is the correctly rounded square root (vcsgc_selftest_md_math checks
+// it against the host's); outside it (0, denormals, inf) it is not meant to
+// be used: there the library's sqrt rescales the argument first.
+__device__ __forceinline__ double sqrt_md(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  d = __builtin_fma(-g, g, x);
+  return __builtin_fma(d, h, g);
+}
+
+// Quotient a / b of the force pass, for normal b and a whose quotient stays
+// far from the ends of the exponent range (the force pass divides an
+// O(1) eV/A scalar by r in [1e-3, 10] A): a reciprocal estimate refined by
+// two Newton-Raphson steps, the quotient q = a y, and one correction
+// q + (a - b q) y with the residual exact in a fused multiply-add
+// (Markstein's theorem for the last step).  Over that range it is the
+// correctly rounded quotient (vcsgc_selftest_md_math checks it against the
+// host's division); a zero a may come back with either sign.
+__device__ __forceinline__ double div_md(double a, double b) {
+  double y = __builtin_amdgcn_rcp(b);
+  double t = __builtin_fma(-b, y, 1.0);
+  y = __builtin_fma(y, t, y);
+  t = __builtin_fma(-b, y, 1.0);
+  y = __builtin_fma(y, t, y);
+  const double q = a * y;
+  const double e = __builtin_fma(-b, q, a);
+  return __builtin_fma(e, y, q);
+}
+
 __device__ __forceinline__ double embed(const PotD &p, int s, double rho) {
   return -p.A[s] * sqrt(rho > 0.0 ? rho : 0.0);
 }
@@ -428,6 +467,8 @@ hipError_t launch_nvt_thermo(vcsgc_ctx *c, double dt, int mode);  // bit 0: end 
 hipError_t launch_nvt_kick_drift(vcsgc_ctx *c, double dt, int par);
 hipError_t launch_nvt_scale(vcsgc_ctx *c);
 hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
+hipError_t launch_md_math(const double *a, const double *b, double *sq, double *q, int64_t n,
+                          hipStream_t s);
 // persistent sweep (persist.hip)
 int persist_block();
 int persist_groups();

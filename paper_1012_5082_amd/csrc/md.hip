@@ -59,10 +59,12 @@ __device__ __forceinline__ double density_row(int64_t n, int64_t i, int m, const
         const double dx = min_image_sel(q[u].x - qi.x, b.L0);
         const double dy = min_image_sel(q[u].y - qi.y, b.L1);
         const double dz = min_image_sel(q[u].z - qi.z, b.L2);
-        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+        const double r = sqrt_md((dx * dx + dy * dy) + dz * dz);
         const double d = p.rc - r;
         const double term = (q[u].w != 0.0 ? t1 : t0) * (d * d);
-        // a skipped pair adds +0.0: s is never -0.0, so s + 0.0 == s
+        // a skipped pair adds +0.0: s is never -0.0, so s + 0.0 == s (the
+        // padding entries, the atom itself at r^2 = 0, have r = NaN from
+        // sqrt_md, which the select drops)
         s += (k0 + g + u < m && r < p.rc) ? term : 0.0;
       }
     }
@@ -183,7 +185,7 @@ __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, c
         const double dx = min_image(q[u].x - qi.x, b.L0);
         const double dy = min_image(q[u].y - qi.y, b.L1);
         const double dz = min_image(q[u].z - qi.z, b.L2);
-        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+        const double r = sqrt_md((dx * dx + dy * dy) + dz * dz);
         // branch kept here: the select form evaluates the FP64 division for
         // every list entry and measured slower than this one
         if (k0 + g + u < m && r < p.rc) {
@@ -193,7 +195,7 @@ __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, c
           const double dfj = -2.0 * tj * d;
           const double dfi = -2.0 * ti * d;
           const double s = dphi + fpi * dfj + q[u].w * dfi;
-          const double coef = s / r;
+          const double coef = div_md(s, r);
           ax += coef * dx;
           ay += coef * dy;
           az += coef * dz;

@@ -41,6 +41,54 @@ def test_device_sqrt_correctly_rounded(torch_cuda):
     assert np.array_equal(got.view(np.int64), np.sqrt(vals).view(np.int64))
 
 
+def _md_math_inputs(torch, gen, n):
+    """n square-root arguments a and divisor pairs (a2, b) on the GPU: a third
+    each of random bit patterns over [2^-767, 2^1023), uniform r^2 in
+    (1e-6, 64) and arguments just above the squares of random numbers
+    (where the rounding of the root is hardest); quotients of signed
+    uniform and random-exponent numerators by uniform and random-exponent
+    divisors."""
+    k = n // 3
+    dev = "cuda"
+    lo, hi = 256, 2047  # biased exponents of 2^-767 and of the largest finite binade
+    bits = (torch.randint(lo, hi, (k,), device=dev, generator=gen, dtype=torch.int64) << 52) | \
+        torch.randint(0, 1 << 52, (k,), device=dev, generator=gen, dtype=torch.int64)
+    a1 = bits.view(torch.float64)
+    a2 = 1e-6 + 64.0 * torch.rand(k, device=dev, generator=gen, dtype=torch.float64)
+    y = 1e-2 + 8.0 * torch.rand(n - 2 * k, device=dev, generator=gen, dtype=torch.float64)
+    u = torch.nextafter(y, torch.full_like(y, float("inf"))) - y
+    a3 = y * y + y * u
+    a = torch.cat([a1, a2, a3])
+    num = torch.cat([200.0 * torch.rand(n - k, device=dev, generator=gen, dtype=torch.float64) - 100.0,
+                     torch.ldexp(torch.rand(k, device=dev, generator=gen, dtype=torch.float64) + 0.5,
+                                 torch.randint(-900, 900, (k,), device=dev, generator=gen))])
+    den = torch.cat([1e-3 + 10.0 * torch.rand(n - k, device=dev, generator=gen, dtype=torch.float64),
+                     torch.ldexp(torch.rand(k, device=dev, generator=gen, dtype=torch.float64) + 0.5,
+                                 torch.randint(-60, 60, (k,), device=dev, generator=gen))])
+    return a, num, den
+
+
+def test_md_math_correctly_rounded(torch_cuda):
+    """The MD passes' square root and quotient are correctly rounded over the
+    ranges they serve: 10^9 arguments of each against the library's sqrt and
+    the device's IEEE division, and 2 x 10^7 of each against the host's."""
+    torch = torch_cuda
+    from paper_1012_5082_amd.binding import selftest_md_math, selftest_sqrt
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    for chunk in range(10):
+        a, num, den = _md_math_inputs(torch, gen, 100_000_000)
+        sq, _ = selftest_md_math(a, den)
+        assert torch.equal(sq.view(torch.int64), selftest_sqrt(a).view(torch.int64)), chunk
+        _, q = selftest_md_math(num, den)
+        assert torch.equal(q.view(torch.int64), (num / den).view(torch.int64)), chunk
+        if chunk < 2:  # host references on every tenth argument
+            an, nn, dn = a[::10].cpu().numpy(), num[::10].cpu().numpy(), den[::10].cpu().numpy()
+            assert np.array_equal(sq[::10].cpu().numpy().view(np.int64), np.sqrt(an).view(np.int64))
+            assert np.array_equal(q[::10].cpu().numpy().view(np.int64), (nn / dn).view(np.int64))
+        del a, num, den, sq, q
+
+
 def test_create_rejects_bad_input(torch_cuda):
     from paper_1012_5082_amd.binding import VCSGC, VcsgcError
     pot = I.params("FS-P1")
