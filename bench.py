@@ -249,12 +249,13 @@ def _blocked(series, nb=10):
 def bench_surrogate(args):
     """Surrogate delayed acceptance on the 1.96M-site polycrystal.
 
-    1. training samples: (descriptor, exact dU) of every 128th trial of plain
-       sweeps of the 40^3 thermal bcc system at cbar = 0.02, 0.05, 0.10
-       (about 10^6 pairs);
-    2. hand-written training (BF16 MFMA forward/backward, Adam);
-    3. the polycrystal (cells of edge >= 8.01 A, the descriptor's dependence
-       range) is first relaxed by plain sweeps; from that state a plain and a
+    1. the polycrystal (cells of edge >= 8.01 A, the descriptor's dependence
+       range) is first relaxed by 100 plain sweeps; the (descriptor, exact
+       dU) pair of every 128th trial of the last 80 of them is logged (10^6
+       pairs) and two further sweeps give held-out pairs;
+    2. hand-written training on the logged pairs (BF16 MFMA forward/backward,
+       Adam);
+    3. from the relaxed state a plain and a
        delayed-acceptance chain run with identical parameters: trials/s,
        exact-accepted moves/s, pre-rejection rate, and <c>, <E> (energy every
        10 sweeps, outside the timed sweeps) with blocked errors;
@@ -267,27 +268,6 @@ def bench_surrogate(args):
     from paper_1012_5082_amd import workloads as W
     from paper_1012_5082_amd.binding import VCSGC, Mlp
     pot = I.params("FS-P1")
-    descs, des = [], []
-    t0 = time.perf_counter()
-    for cb in (0.02, 0.05, 0.10):
-        d = W.c2(cbar=cb)
-        g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, descriptor=True)
-        g.sweep(d["dmu0"], d["kappa"], cb, d["T"], 20, d["seed"])
-        g.enable_sample_log(340000, 128)
-        g.sweep(d["dmu0"], d["kappa"], cb, d["T"], 345, d["seed"])
-        a, e = g.samples()
-        descs.append(a.clone())
-        des.append(e.clone())
-        g.close()
-    desc = torch.cat(descs)[:1000000].contiguous()
-    dE = torch.cat(des)[:1000000].contiguous()
-    t_log = time.perf_counter() - t0
-    log(f"c5: {desc.shape[0]} training samples in {t_log:.1f} s")
-    net = Mlp(seed=7)
-    net.fit_normalization(desc, dE)
-    rep, t_train = _timed(lambda: net.train(desc, dE, epochs=10, batch=4096, lr=2e-3, seed=11))
-    log(f"c5: trained {rep} in {t_train:.1f} s")
-
     d = W.c3(with_velocities=False)
     n = d["x"].size
     r_dep = 8.01
@@ -295,16 +275,26 @@ def bench_surrogate(args):
     plain = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, descriptor=True,
                   r_dep=r_dep)
     plain.set_tuning("batch", 16)
-    n_relax = 100
-    plain.sweep(*sp, n_relax, d["seed"])
-    # held-out accuracy on the polycrystal itself
+    n_relax, n_unlogged = 100, 20
+    t0 = time.perf_counter()
+    plain.sweep(*sp, n_unlogged, d["seed"])
+    plain.enable_sample_log(1_000_000, 128)
+    plain.sweep(*sp, n_relax - n_unlogged, d["seed"])
+    desc, dE = (t.clone() for t in plain.samples())
+    t_log = time.perf_counter() - t0
+    log(f"c5: {desc.shape[0]} training samples from the relaxation sweeps in {t_log:.1f} s")
+    # held-out pairs from two further sweeps
     plain.enable_sample_log(200000, 97)
     plain.sweep(*sp, 2, d["seed"] + 1)
     hd, he = plain.samples()
+    plain.disable_sample_log()
+    net = Mlp(seed=7)
+    net.fit_normalization(desc, dE)
+    rep, t_train = _timed(lambda: net.train(desc, dE, epochs=10, batch=4096, lr=2e-3, seed=11))
+    log(f"c5: trained {rep} in {t_train:.1f} s")
     pred = net.forward(hd.contiguous())
     rmse = float(torch.sqrt(torch.mean((pred - he) ** 2)))
     std_e = float(torch.std(he))
-    plain.disable_sample_log()
     relaxed = plain.species.cpu().numpy().copy()
     plain.close()
 
