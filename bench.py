@@ -439,6 +439,7 @@ def main():
     elif args.tiling == "auto":
         from paper_1012_5082_amd import autotune
         tuned = autotune.tune(g, lambda k: g.sweep(*sweep_args, k, d["seed"], stats=False),
+                              op=sweep_args,
                               use_cache=False)
     else:
         st, k = args.tiling.split(":")

@@ -197,6 +197,51 @@ __device__ __forceinline__ double dembed(const PotD &p, int s, double rho) {
   return rho > 0.0 ? -p.A[s] / (2.0 * sqrt(rho)) : 0.0;
 }
 
+// What flipping a site from species s to 1 - s changes, in the order every
+// sweep path evaluates it (Eq. of the transmutation energy; the r < rc list
+// gives each neighbour entry dd = (rc - r)^2 and g = c0 + c1 r):
+//   the neighbour's density shifts by t_{1-s} dd - t_s dd;
+//   the pair energy with a neighbour of species sj by
+//     (eps_{1-s,sj} dd) g - (eps_{s,sj} dd) g;
+//   that neighbour's embedding energy by F_sj(rho_j + shift) - F_sj(rho_j);
+//   the site's own embedding energy by F_{1-s}(rho_i) - F_s(rho_i).
+// dU is the own term plus the in-order sums of the pair and embedding terms.
+__device__ __forceinline__ double flip_rho_shift(const PotD &p, int s, double dd) {
+  return p.t[1 - s] * dd - p.t[s] * dd;
+}
+__device__ __forceinline__ double flip_pair_term(const PotD &p, int s, int sj, double dd,
+                                                 double g) {
+  return p.eps[1 - s + sj] * dd * g - p.eps[s + sj] * dd * g;
+}
+__device__ __forceinline__ double flip_embed_term(const PotD &p, int sj, double rj, double shift) {
+  return embed(p, sj, rj + shift) - embed(p, sj, rj);
+}
+__device__ __forceinline__ double flip_own_term(const PotD &p, int s, double ri) {
+  return embed(p, 1 - s, ri) - embed(p, s, ri);
+}
+
+// The in-order sums of the (pair, embedding) terms of entries 0 .. m-1 held
+// in LDS slots (written by the lanes of one wave, whose LDS accesses are
+// performed in order): eight slots are read per round, so the reads do not
+// wait on the additions.
+__device__ __forceinline__ void sum_flip_terms(const double2 *grp, int m, double &pair,
+                                               double &emb) {
+  pair = 0.0;
+  emb = 0.0;
+  for (int k0 = 0; k0 < KMAX; k0 += 8) {
+    if (k0 >= m) break;
+    double2 q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = grp[k0 + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < m) {
+        pair += q[u].x;
+        emb += q[u].y;
+      }
+  }
+}
+
 __device__ __forceinline__ double min_image(double d, double L) {
   const double h = 0.5 * L;
   if (d > h) return d - L;

@@ -115,7 +115,7 @@ __device__ __forceinline__ int64_t p_colour_cell(const RepD &r, int colour, int6
 // one wave, whose LDS accesses are performed in order)
 __device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int lane,
                                             double2 *grp) {
-  const int s = a.sp[i], s1 = 1 - s;
+  const int s = a.sp[i];
   const double ri = a.rho[i];
   const int m = a.cnt[i];
   double tp[2] = {0.0, 0.0}, te[2] = {0.0, 0.0};
@@ -129,29 +129,17 @@ __device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int
       const double r = a.nr[e];
       const double dd = pair_dd(a.p, r), g = pair_g(a.p, r);
       const double rj = a.rho[j];
-      tp[h] = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
-      const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
-      te[h] = embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
+      tp[h] = flip_pair_term(a.p, s, sj, dd, g);
+      te[h] = flip_embed_term(a.p, sj, rj, flip_rho_shift(a.p, s, dd));
     }
   }
   grp[lane] = make_double2(tp[0], te[0]);
   grp[lane + PTL] = make_double2(tp[1], te[1]);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  double pair = 0.0, emb = 0.0;
-  for (int k0 = 0; k0 < KMAX; k0 += 8) {
-    if (k0 >= m) break;
-    double2 q[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) q[u] = grp[k0 + u];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (k0 + u < m) {
-        pair += q[u].x;
-        emb += q[u].y;
-      }
-  }
-  const double own = embed(a.p, s1, ri) - embed(a.p, s, ri);
+  double pair, emb;
+  sum_flip_terms(grp, m, pair, emb);
+  const double own = flip_own_term(a.p, s, ri);
   return own + pair + emb;
 }
 
@@ -275,7 +263,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
               const int64_t e = (int64_t)i * KMAX + k;
               const int32_t j = a.nj[e];
               const double dd = pair_dd(a.p, a.nr[e]);
-              const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
+              const double delta = flip_rho_shift(a.p, s0, dd);
               a.rho[j] = a.rho[j] + delta;
             }
           }

@@ -150,7 +150,7 @@ template <int L>
 __device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialInT<L> &v, int lane,
                                              double2 *grp) {
   constexpr int H = KMAX / L;
-  const int s = v.s, s1 = 1 - s;
+  const int s = v.s;
   const int m = v.m;
 #pragma unroll
   for (int h = 0; h < H; ++h) {
@@ -160,29 +160,17 @@ __device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialInT<
       const int sj = v.sj[h];
       const double dd = v.dd[h], g = v.g[h];
       const double rj = v.rj[h];
-      tp = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
-      const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
-      te = embed(a.p, sj, rj + delta) - embed(a.p, sj, rj);
+      tp = flip_pair_term(a.p, s, sj, dd, g);
+      te = flip_embed_term(a.p, sj, rj, flip_rho_shift(a.p, s, dd));
     }
     grp[k] = make_double2(tp, te);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // two independent in-order chains
-  double pair = 0.0, emb = 0.0;
-  for (int k0 = 0; k0 < KMAX; k0 += 8) {
-    if (k0 >= m) break;
-    double2 q[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) q[u] = grp[k0 + u];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (k0 + u < m) {
-        pair += q[u].x;
-        emb += q[u].y;
-      }
-  }
-  const double own = embed(a.p, s1, v.ri) - embed(a.p, s, v.ri);
+  double pair, emb;
+  sum_flip_terms(grp, m, pair, emb);
+  const double own = flip_own_term(a.p, s, v.ri);
   return own + pair + emb;
 }
 
@@ -217,7 +205,7 @@ __device__ __forceinline__ void descriptor_group(const SweepArgs &a, int64_t i, 
       if (flip && r < a.p.rc) {
         const double d = a.p.rc - r;
         const double dd = d * d;
-        rho = rho + (a.p.t[s1] * dd - a.p.t[s] * dd);
+        rho = rho + flip_rho_shift(a.p, s, dd);
       }
       rj[h] = rho;
     }
@@ -292,10 +280,10 @@ __device__ __forceinline__ void desc_du_group(const SweepArgs &a, int64_t i, int
         const double d = a.p.rc - r;
         const double dd = d * d;
         const double g = a.p.c0 + a.p.c1 * r;
-        const double delta = a.p.t[s1] * dd - a.p.t[s] * dd;
+        const double delta = flip_rho_shift(a.p, s, dd);
         q.rjf = rho + delta;
-        q.tp = a.p.eps[s1 + sj] * dd * g - a.p.eps[s + sj] * dd * g;
-        q.te = embed(a.p, sj, rho + delta) - embed(a.p, sj, rho);
+        q.tp = flip_pair_term(a.p, s, sj, dd, g);
+        q.te = flip_embed_term(a.p, sj, rho, delta);
         in = 1;
       }
       q.code = (shl + 1) | (sj << 2) | (in << 3);
@@ -340,7 +328,7 @@ __device__ __forceinline__ void desc_du_group(const SweepArgs &a, int64_t i, int
     fwd[7 + k] = cnt[k] > 0.0 ? rs[k] / cnt[k] : 0.0;
     flp[7 + k] = cnt[k] > 0.0 ? rsf[k] / cnt[k] : 0.0;
   }
-  const double own = embed(a.p, s1, ri) - embed(a.p, s, ri);
+  const double own = flip_own_term(a.p, s, ri);
   du = own + pair + emb;
 }
 
@@ -540,7 +528,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_a
             const double old = a.rho[j];
             a.u_j[uq * KMAX + e] = j;
             a.u_rho[uq * KMAX + e] = old;
-            a.rho[j] = old + (a.p.t[s1] * dd - a.p.t[s0] * dd);
+            a.rho[j] = old + flip_rho_shift(a.p, s0, dd);
           }
         }
         if (lane == 0) {
@@ -844,7 +832,7 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, i
       const int k = lane + h * TL;
       if (k < m) {
         const double dd = ddr[h];
-        const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
+        const double delta = flip_rho_shift(a.p, s0, dd);
         a.rho[jr[h]] = a.rho[jr[h]] + delta;
       }
     }
@@ -1065,7 +1053,7 @@ __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int l
       const int64_t e = (int64_t)i * KMAX + k;
       const int32_t j = a.nj[e];
       const double dd = pair_dd(a.p, a.nr[e]);
-      const double delta = a.p.t[s1] * dd - a.p.t[s0] * dd;
+      const double delta = flip_rho_shift(a.p, s0, dd);
       a.rho[j] = a.rho[j] + delta;
     }
   }

@@ -66,3 +66,14 @@ def test_bench_runs_on_one_gpu_only():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_autotune_cache_key_names_operating_point():
+    """The tiling cache separates operating points (the batched pipeline's
+    cost depends on how often stages are accepted) and buckets the shape."""
+    from paper_1012_5082_amd.autotune import cache_key
+    a = cache_key("gfx950", 1, 1956428, 6859, (-0.21919, 1000.0, 0.03, 700.0))
+    b = cache_key("gfx950", 1, 1956428, 6859, (-0.22622, 1000.0, 0.03, 700.0))
+    c = cache_key("gfx950", 1, 1900000, 7000, (-0.21919, 1000.0, 0.03, 700.0))
+    assert a != b and a == c
+    assert cache_key("gfx950", 1, 1956428, 6859) != a
