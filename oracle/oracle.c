@@ -262,45 +262,87 @@ int64_t or_neighbors(int64_t n, const double *x, const double *y, const double *
 }
 
 /* ------------------------------------------------------------------------ */
-/* Potential (Finnis-Sinclair form; species 0 = A, 1 = B)                    */
+/* Potential (Finnis-Sinclair form or tables; species 0 = A, 1 = B)         */
 /* ------------------------------------------------------------------------ */
+void or_spline_coeffs(int32_t n, const double *y, double *c) {
+  for (int32_t k = 0; k + 1 < n; ++k) {
+    double mk = k == 0 ? y[1] - y[0] : 0.5 * (y[k + 1] - y[k - 1]);
+    double mk1 = k + 2 == n ? y[n - 1] - y[n - 2] : 0.5 * (y[k + 2] - y[k]);
+    double d = y[k + 1] - y[k];
+    c[4 * k + 0] = y[k];
+    c[4 * k + 1] = mk;
+    c[4 * k + 2] = (3.0 * d - 2.0 * mk) - mk1;
+    c[4 * k + 3] = (mk + mk1) - 2.0 * d;
+  }
+}
+
+double or_spline_eval(const double *c, int32_t n, double x, double inv_h, double *der) {
+  double p = x * inv_h;
+  double top = (double)(n - 1);
+  double pc = p < 0.0 ? 0.0 : (p > top ? top : p);
+  int32_t k = (int32_t)pc;
+  if (k > n - 2) k = n - 2;
+  double t = p - (double)k;
+  const double *a = c + 4 * k;
+  if (der) *der = (((3.0 * a[3]) * t + 2.0 * a[2]) * t + a[1]) * inv_h;
+  return ((a[3] * t + a[2]) * t + a[1]) * t + a[0];
+}
+
 static double or_eps(const or_pot *p, int a, int b) {
   int s = a + b;
   return s == 0 ? p->eps_aa : (s == 1 ? p->eps_ab : p->eps_bb);
 }
 
-/* phi_XY(r) = (eps_XY (rc - r)^2) (c0 + c1 r) */
+/* phi_XY(r) = (eps_XY (rc - r)^2) (c0 + c1 r), or the table's */
 static double or_phi(const or_pot *p, int a, int b, double r) {
+  if (p->tab) return or_spline_eval(p->cphi[a + b], p->nr, r, p->inv_dr, NULL);
   double d = p->rc - r;
   return or_eps(p, a, b) * (d * d) * (p->c0 + p->c1 * r);
 }
 
-/* phi'_XY(r) = eps_XY ((-2 (rc - r)) (c0 + c1 r) + c1 (rc - r)^2) */
+/* phi'_XY(r) = eps_XY ((-2 (rc - r)) (c0 + c1 r) + c1 (rc - r)^2), or the table's */
 static double or_dphi(const or_pot *p, int a, int b, double r) {
+  if (p->tab) {
+    double g;
+    or_spline_eval(p->cphi[a + b], p->nr, r, p->inv_dr, &g);
+    return g;
+  }
   double d = p->rc - r;
   return or_eps(p, a, b) * (-2.0 * d * (p->c0 + p->c1 * r) + p->c1 * (d * d));
 }
 
-/* f_X(r) = t_X (rc - r)^2 */
+/* f_X(r) = t_X (rc - r)^2, or the table's */
 static double or_f(const or_pot *p, int a, double r) {
+  if (p->tab) return or_spline_eval(p->cf[a], p->nr, r, p->inv_dr, NULL);
   double d = p->rc - r;
   return (a ? p->t_b : p->t_a) * (d * d);
 }
 
-/* f'_X(r) = (-2 t_X) (rc - r) */
+/* f'_X(r) = (-2 t_X) (rc - r), or the table's */
 static double or_df(const or_pot *p, int a, double r) {
+  if (p->tab) {
+    double g;
+    or_spline_eval(p->cf[a], p->nr, r, p->inv_dr, &g);
+    return g;
+  }
   double d = p->rc - r;
   return -2.0 * (a ? p->t_b : p->t_a) * d;
 }
 
-/* F_X(rho) = -A_X sqrt(max(rho, 0)) */
+/* F_X(rho) = -A_X sqrt(max(rho, 0)), or the table's */
 static double or_embed(const or_pot *p, int a, double rho) {
+  if (p->tab) return or_spline_eval(p->cF[a], p->nrho, rho, p->inv_drho, NULL);
   double A = a ? p->a_b : p->a_a;
   return -A * sqrt(rho > 0.0 ? rho : 0.0);
 }
 
-/* F'_X(rho) = -A_X / (2 sqrt(rho)), and 0 at rho = 0 */
+/* F'_X(rho) = -A_X / (2 sqrt(rho)), and 0 at rho = 0; or the table's */
 static double or_dembed(const or_pot *p, int a, double rho) {
+  if (p->tab) {
+    double g;
+    or_spline_eval(p->cF[a], p->nrho, rho, p->inv_drho, &g);
+    return g;
+  }
   double A = a ? p->a_b : p->a_a;
   return rho > 0.0 ? -A / (2.0 * sqrt(rho)) : 0.0;
 }

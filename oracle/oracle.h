@@ -18,10 +18,33 @@ extern "C" {
 #endif
 
 /* Analytic Finnis-Sinclair EAM: phi_XY = eps_XY (rc-r)^2 (c0 + c1 r),
- * f_X = t_X (rc-r)^2, F_X(rho) = -A_X sqrt(rho); zero for r >= rc. */
+ * f_X = t_X (rc-r)^2, F_X(rho) = -A_X sqrt(rho); zero for r >= rc.
+ * With tab != 0 the potential is tabulated instead (a general EAM, Sec. II):
+ * f_A, f_B and phi_AA, phi_AB, phi_BB at the radial knots r_k = k dr
+ * (k = 0 .. nr-1), F_A and F_B at the density knots rho_k = k drho
+ * (k = 0 .. nrho-1), each interpolated by the piecewise cubic of
+ * or_spline_coeffs (cf, cphi, cF: 4 coefficients per interval); f and phi are
+ * zero for r >= rc, and F is evaluated outside its knots by the end
+ * intervals' cubics.  Only rc of the analytic fields is used then. */
 typedef struct {
   double rc, c0, c1, eps_aa, eps_ab, eps_bb, t_a, t_b, a_a, a_b;
+  int32_t tab, nr, nrho, pad_;
+  double inv_dr, inv_drho;
+  const double *cf[2], *cphi[3], *cF[2];
 } or_pot;
+
+/* Piecewise cubic through y[0 .. n-1] (n >= 2) at unit-spaced knots: the
+ * cubic Hermite interpolant whose knot slopes are central differences
+ * m_k = (y_{k+1} - y_{k-1}) / 2, one-sided at the two ends.  Interval k
+ * (0 <= k < n-1) gets c[4k .. 4k+3] = (a0, a1, a2, a3) with
+ * p(t) = ((a3 t + a2) t + a1) t + a0 for t in [0, 1]:
+ *   a0 = y_k, a1 = m_k, a2 = (3 d - 2 m_k) - m_{k+1}, a3 = (m_k + m_{k+1}) - 2 d,
+ *   d = y_{k+1} - y_k. */
+void or_spline_coeffs(int32_t n, const double *y, double *c);
+/* The interpolant at x (knots at x = k h, inv_h = 1/h) and, if der != NULL,
+ * its derivative in x: p = x inv_h, k = floor(p) limited to [0, n-2],
+ * t = p - k (outside the knots the end interval's cubic continues). */
+double or_spline_eval(const double *c, int32_t n, double x, double inv_h, double *der);
 
 /* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
 void or_philox4x64_10(const uint64_t key[2], const uint64_t ctr[4], uint64_t out[4]);

@@ -33,7 +33,10 @@ def build(force: bool = True) -> str:
 
 class Pot(C.Structure):
     _fields_ = [(k, C.c_double) for k in
-                ("rc", "c0", "c1", "eps_aa", "eps_ab", "eps_bb", "t_a", "t_b", "a_a", "a_b")]
+                ("rc", "c0", "c1", "eps_aa", "eps_ab", "eps_bb", "t_a", "t_b", "a_a", "a_b")] + [
+        ("tab", C.c_int32), ("nr", C.c_int32), ("nrho", C.c_int32), ("pad_", C.c_int32),
+        ("inv_dr", C.c_double), ("inv_drho", C.c_double),
+        ("cf", C.c_void_p * 2), ("cphi", C.c_void_p * 3), ("cF", C.c_void_p * 2)]
 
 
 class SweepArgs(C.Structure):
@@ -81,6 +84,9 @@ def lib():
             build(force=False)
         L = C.CDLL(LIB_PATH)
         L.or_philox4x64_10.argtypes = [_P, _P, _P]
+        L.or_spline_coeffs.argtypes = [C.c_int32, _P, _P]
+        L.or_spline_eval.restype = C.c_double
+        L.or_spline_eval.argtypes = [_P, C.c_int32, C.c_double, C.c_double, _P]
         L.or_neighbors.restype = C.c_int64
         L.or_neighbors.argtypes = [C.c_int64, _P, _P, _P, _P, C.c_double, C.c_int, C.c_int64,
                                    _P, _P, _P, _P, _P, _P]
@@ -135,8 +141,42 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def spline_coeffs(y) -> np.ndarray:
+    """The oracle's piecewise-cubic coefficients (4 per interval) through y."""
+    y = _f64(y)
+    c = np.zeros(4 * (y.size - 1))
+    lib().or_spline_coeffs(int(y.size), _p(y), _p(c))
+    return c
+
+
+def spline_eval(c, n, x, inv_h):
+    """(value, derivative) of the interpolant with coefficients c at x."""
+    d = C.c_double()
+    v = lib().or_spline_eval(_p(_f64(c)), int(n), float(x), float(inv_h), C.byref(d))
+    return v, d.value
+
+
 def pot_struct(pot) -> Pot:
-    return Pot(*pot.as_tuple())
+    """The oracle's potential: analytic Finnis-Sinclair parameters, or a table
+    (paper_1012_5082_amd.inputs.EamTable) with its coefficients computed here;
+    they are kept on the table object as long as it lives."""
+    if not hasattr(pot, "phi"):
+        return Pot(*pot.as_tuple())
+    co = getattr(pot, "_oracle_coeffs", None)
+    if co is None:
+        co = ([spline_coeffs(pot.f[x]) for x in (0, 1)],
+              [spline_coeffs(pot.phi[k]) for k in (0, 1, 2)],
+              [spline_coeffs(pot.F[x]) for x in (0, 1)])
+        pot._oracle_coeffs = co
+    P = Pot(pot.rc, *([0.0] * 9))
+    P.tab, P.nr, P.nrho = 1, pot.nr, pot.nrho
+    P.inv_dr, P.inv_drho = 1.0 / pot.dr, 1.0 / pot.drho
+    for k in range(2):
+        P.cf[k] = co[0][k].ctypes.data
+        P.cF[k] = co[2][k].ctypes.data
+    for k in range(3):
+        P.cphi[k] = co[1][k].ctypes.data
+    return P
 
 
 def philox(key, ctr) -> np.ndarray:

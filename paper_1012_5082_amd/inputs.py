@@ -84,6 +84,79 @@ def params(name: str = "FS-P1") -> EamFS:
 
 
 # --------------------------------------------------------------------------
+# Tabulated potentials (a general two-species EAM given by tables, the form
+# the paper's Fe-Cu potentials come in): f_A, f_B, phi_AA, phi_AB, phi_BB at
+# the radial knots r_k = k dr (k < nr), F_A, F_B at the density knots
+# rho_k = k drho (k < nrho).  Pair and density terms vanish for r >= rc.
+# The sets below tabulate closed forms on the knots; how the tables are
+# interpolated is the consumer's business.
+# --------------------------------------------------------------------------
+@dataclass(eq=False)
+class EamTable:
+    rc: float
+    dr: float
+    drho: float
+    f: np.ndarray     # (2, nr)
+    phi: np.ndarray   # (3, nr): AA, AB, BB
+    F: np.ndarray     # (2, nrho)
+
+    @property
+    def nr(self) -> int:
+        return int(self.f.shape[1])
+
+    @property
+    def nrho(self) -> int:
+        return int(self.F.shape[1])
+
+
+def _tabulate(rc, dr, drho, rho_max, f, phi, F) -> EamTable:
+    nr = int(math.ceil(rc / dr)) + 2
+    nrho = int(math.ceil(rho_max / drho)) + 1
+    r = dr * np.arange(nr, dtype=np.float64)
+    rho = drho * np.arange(nrho, dtype=np.float64)
+    inside = r < rc
+    tf = np.stack([np.where(inside, f(x, r), 0.0) for x in (0, 1)])
+    tphi = np.stack([np.where(inside, phi(k, r), 0.0) for k in (0, 1, 2)])
+    tF = np.stack([F(x, rho) for x in (0, 1)])
+    return EamTable(rc, dr, drho, np.ascontiguousarray(tf), np.ascontiguousarray(tphi),
+                    np.ascontiguousarray(tF))
+
+
+def table_fs(pot: EamFS, dr: float = 0.005, drho: float = 0.02,
+             rho_max: float = 80.0) -> EamTable:
+    """The Finnis-Sinclair functions of `pot` on the knots."""
+    eps = (pot.eps_aa, pot.eps_ab, pot.eps_bb)
+    t = (pot.t_a, pot.t_b)
+    A = (pot.a_a, pot.a_b)
+    return _tabulate(pot.rc, dr, drho, rho_max,
+                     lambda x, r: t[x] * (pot.rc - r) ** 2,
+                     lambda k, r: eps[k] * (pot.rc - r) ** 2 * (pot.c0 + pot.c1 * r),
+                     lambda x, rho: -A[x] * np.sqrt(rho))
+
+
+def table_x(dr: float = 0.01, drho: float = 0.05, rho_max: float = 80.0) -> EamTable:
+    """A tabulated EAM unlike the Finnis-Sinclair form in every function: a
+    cubic density tail, an extra cubic pair term and a linear embedding term
+    (the FS-P1 parameters otherwise)."""
+    p = PARAM_SETS["FS-P1"]
+    eps = (p.eps_aa, p.eps_ab, p.eps_bb)
+    t = (p.t_a, p.t_b)
+    A = (p.a_a, p.a_b)
+    return _tabulate(p.rc, dr, drho, rho_max,
+                     lambda x, r: t[x] * (p.rc - r) ** 2 * (1.0 + 0.3 * (p.rc - r)),
+                     lambda k, r: eps[k] * ((p.rc - r) ** 2 * (p.c0 + p.c1 * r)
+                                            + 0.05 * (p.rc - r) ** 3),
+                     lambda x, rho: -A[x] * np.sqrt(rho) + (0.002 + 0.001 * x) * rho)
+
+
+TABLE_SETS = {"TAB-FS1": lambda: table_fs(PARAM_SETS["FS-P1"]), "TAB-X": table_x}
+
+
+def table(name: str) -> EamTable:
+    return TABLE_SETS[name]()
+
+
+# --------------------------------------------------------------------------
 # Structures
 # --------------------------------------------------------------------------
 def wrap(u: np.ndarray, L: float) -> np.ndarray:

@@ -64,12 +64,21 @@ MUTATIONS = [
      "return or_tree_sum(n, work) / OR_ACC;"),
     ("fixed-shape sum drops the last chunk", "int64_t nch = (n + 255) / 256;",
      "int64_t nch = n / 256;"),
+    ("spline slopes one-sided everywhere",
+     "double mk = k == 0 ? y[1] - y[0] : 0.5 * (y[k + 1] - y[k - 1]);",
+     "double mk = y[k + 1] - y[k];"),
+    ("spline derivative not scaled by the knot spacing",
+     "if (der) *der = (((3.0 * a[3]) * t + 2.0 * a[2]) * t + a[1]) * inv_h;",
+     "if (der) *der = (((3.0 * a[3]) * t + 2.0 * a[2]) * t + a[1]);"),
+    ("tabulated pair function of the wrong species pair",
+     "if (p->tab) return or_spline_eval(p->cphi[a + b], p->nr, r, p->inv_dr, NULL);",
+     "if (p->tab) return or_spline_eval(p->cphi[a], p->nr, r, p->inv_dr, NULL);"),
 ]
 
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_eam.py",
          "tests/test_oracle_ensemble.py", "tests/test_oracle_md.py",
          "tests/test_oracle_surrogate.py", "tests/test_oracle_localchain.py",
-         "tests/test_oracle_nvt.py"]
+         "tests/test_oracle_nvt.py", "tests/test_oracle_table.py"]
 
 
 def main():
