@@ -127,6 +127,12 @@ def measured_traffic(cls, tiling=None):
     return int(val.group(1))
 
 
+def potential(name):
+    """The analytic FS-P1 set, or a tabulated EAM (TAB-FS1 tabulates FS-P1)."""
+    from paper_1012_5082_amd import inputs as I
+    return I.params(name) if name == "FS-P1" else I.table(name)
+
+
 def copy_calib():
     import torch
     n = 1 << 27  # 128 Mi doubles = 1 GiB
@@ -208,7 +214,7 @@ def bench_replicas(args):
     from paper_1012_5082_amd import inputs as I
     from paper_1012_5082_amd import workloads as W
     from paper_1012_5082_amd.binding import VCSGCBatch
-    pot = I.params("FS-P1")
+    pot = potential(args.potential)
     reps = []
     for r in W.c4_replicas():
         x, y, z, box = I.bcc(r["nx"], r["ny"], r["nz"])
@@ -230,7 +236,7 @@ def bench_replicas(args):
            "sites_total": int(sum(sizes)), "sites_min": min(sizes), "sites_max": max(sizes),
            "sweeps": n_sw, "seconds": round(dt, 4), "flips_per_s": round(flips / dt, 1),
            "tiling": list(tuned["choice"]), "workgroups": b.tuning()["workgroups"],
-           "colours": args.colours,
+           "colours": args.colours, "potential": args.potential,
            "autotune_ms_per_sweep": {k: round(v, 3) for k, v in tuned["times_ms"].items()},
            "mean_c_first8": [round(c, 5) for c in cmean[:8]],
            "cbar_first8": [round(float(r["cbar"]), 5) for r in reps[:8]]}
@@ -390,6 +396,8 @@ def main():
                     help="c3: sweep tiling strategy:k, or 'auto' for the autotuner")
     ap.add_argument("--colours", type=int, default=8, choices=[8, 27],
                     help="c3, c4: colours of the sweep (27: cells of edge >= r_dep / 2)")
+    ap.add_argument("--potential", default="FS-P1", choices=["FS-P1", "TAB-FS1", "TAB-X"],
+                    help="c3, c4: the analytic Finnis-Sinclair set, or a tabulated EAM")
     ap.add_argument("--skin", type=float, default=0.3,
                     help="c3: MD neighbour-list skin (A)")
     ap.add_argument("--relax", type=int, default=0,
@@ -418,7 +426,7 @@ def main():
     from paper_1012_5082_amd import workloads as W
     from paper_1012_5082_amd.binding import VCSGC
 
-    pot = I.params("FS-P1")
+    pot = potential(args.potential)
     t0 = time.perf_counter()
     d = W.c3()
     n = d["x"].size
@@ -540,6 +548,7 @@ def main():
                                f"T=700 K, step = 1 VC-SGC sweep + 20 MD steps (dt=1 fs)",
                    "n_sites": n, "n_cells": info["n_cells"],
                    "stages_per_sweep": info["stages_per_sweep"], "colours": args.colours,
+                   "potential": args.potential,
                    "variant": ("plain" if args.local_steps == 1
                                else f"local chains of {args.local_steps} trials per cell"),
                    "sweep_tiling": list(tuned["choice"]),

@@ -67,6 +67,30 @@ typedef struct {
   double rc, c0, c1, eps_aa, eps_ab, eps_bb, t_a, t_b, a_a, a_b, mass_a, mass_b;
 } vcsgc_eam_fs;
 
+/* A tabulated two-species EAM (a general embedded-atom potential, the
+ * class of short-range potentials named in the Introduction and Sec. III;
+ * published EAM potentials are commonly distributed as such tables):
+ * f_A, f_B and phi_AA, phi_AB, phi_BB at the radial knots r_k = k dr
+ * (k = 0 .. nr-1), F_A and F_B at the density knots rho_k = k drho
+ * (k = 0 .. nrho-1).  Each function is interpolated by the cubic Hermite
+ * interpolant whose knot slopes are central differences (one-sided at the
+ * two ends): on interval k, with t = x/h - k,
+ *   p(t) = ((a3 t + a2) t + a1) t + a0,  a0 = y_k,  a1 = m_k,
+ *   a2 = (3 d - 2 m_k) - m_{k+1},  a3 = (m_k + m_{k+1}) - 2 d,
+ *   d = y_{k+1} - y_k,  m_k = (y_{k+1} - y_{k-1}) / 2,
+ * with k = floor(x/h) limited to [0, n-2] (outside the knots the end
+ * interval's cubic continues) and x/h formed as x times the rounded 1/h;
+ * derivatives are p'(t) / h.  f and phi are zero for r >= rc.  The arrays
+ * are host memory, read during vcsgc_create. */
+typedef struct {
+  int32_t nr, nrho;   /* knots, >= 2 each */
+  double dr, drho;    /* knot spacings, > 0 */
+  double rc;          /* cutoff, > 0, at most (nr - 1) dr */
+  const double *f[2];    /* f_A, f_B: nr values each */
+  const double *phi[3];  /* phi_AA, phi_AB, phi_BB: nr values each */
+  const double *F[2];    /* F_A, F_B: nrho values each */
+} vcsgc_eam_table;
+
 typedef struct {
   int64_t n_atoms;  /* N >= 2 */
   double box[3];    /* orthorhombic periodic box edges, Angstrom */
@@ -78,6 +102,9 @@ typedef struct {
   double skin;   /* MD neighbour-list skin (A), >= 0; typical 0.3 */
   double r_dep;  /* independence distance for the cell colouring; 0 => 2 rc */
   uint32_t flags;        /* VCSGC_FLAG_* */
+  /* NULL: the analytic potential pot; else the tabulated potential (then
+   * pot supplies only mass_a and mass_b, and rc is table->rc) */
+  const vcsgc_eam_table *table;
 } vcsgc_system;
 
 /* Per-call statistics (host struct). */

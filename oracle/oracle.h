@@ -19,7 +19,8 @@ extern "C" {
 
 /* Analytic Finnis-Sinclair EAM: phi_XY = eps_XY (rc-r)^2 (c0 + c1 r),
  * f_X = t_X (rc-r)^2, F_X(rho) = -A_X sqrt(rho); zero for r >= rc.
- * With tab != 0 the potential is tabulated instead (a general EAM, Sec. II):
+ * With tab != 0 the potential is tabulated instead (a general embedded-atom
+ * potential, the class named in the Introduction and Sec. III):
  * f_A, f_B and phi_AA, phi_AB, phi_BB at the radial knots r_k = k dr
  * (k = 0 .. nr-1), F_A and F_B at the density knots rho_k = k drho
  * (k = 0 .. nrho-1), each interpolated by the piecewise cubic of

@@ -30,13 +30,20 @@ class EamFS(C.Structure):
                                           "t_b", "a_a", "a_b", "mass_a", "mass_b")]
 
 
+class EamTableC(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nrho", C.c_int32), ("dr", C.c_double),
+                ("drho", C.c_double), ("rc", C.c_double), ("f", C.c_void_p * 2),
+                ("phi", C.c_void_p * 3), ("F", C.c_void_p * 2)]
+
+
 class System(C.Structure):
     _fields_ = [("n_atoms", C.c_int64), ("box", C.c_double * 3),
                 ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
                 ("fx", C.c_void_p), ("fy", C.c_void_p), ("fz", C.c_void_p),
                 ("species", C.c_void_p), ("pot", EamFS), ("skin", C.c_double),
-                ("r_dep", C.c_double), ("flags", C.c_uint32)]
+                ("r_dep", C.c_double), ("flags", C.c_uint32),
+                ("table", C.POINTER(EamTableC))]
 
 
 class Stats(C.Structure):
@@ -203,7 +210,29 @@ def _dev(a, dtype, device):
 
 
 def pot_struct(pot, mass_a=55.845, mass_b=63.546) -> EamFS:
+    """The analytic parameters, or for a tabulated potential (an object with
+    rc, dr, drho and tables f, phi, F) only its cutoff and the masses."""
+    if hasattr(pot, "phi"):
+        return EamFS(float(pot.rc), *([0.0] * 9), mass_a, mass_b)
     return EamFS(*pot.as_tuple(), mass_a, mass_b)
+
+
+def table_struct(pot):
+    """(EamTableC, the host arrays it points to) for a tabulated potential,
+    or (None, None).  The arrays must outlive the create call."""
+    if not hasattr(pot, "phi"):
+        return None, None
+    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in
+            (pot.f[0], pot.f[1], pot.phi[0], pot.phi[1], pot.phi[2], pot.F[0], pot.F[1])]
+    t = EamTableC()
+    t.nr, t.nrho = int(keep[0].size), int(keep[5].size)
+    t.dr, t.drho, t.rc = float(pot.dr), float(pot.drho), float(pot.rc)
+    for k in range(2):
+        t.f[k] = keep[k].ctypes.data
+        t.F[k] = keep[5 + k].ctypes.data
+    for k in range(3):
+        t.phi[k] = keep[2 + k].ctypes.data
+    return t, keep
 
 
 def selftest_sqrt(x):
@@ -264,6 +293,9 @@ class VCSGC:
         sysd.fx, sysd.fy, sysd.fz = ptr(self.fx), ptr(self.fy), ptr(self.fz)
         sysd.species = ptr(self.species)
         sysd.pot = pot_struct(pot, mass_a, mass_b)
+        tab, tab_keep = table_struct(pot)
+        if tab is not None:
+            sysd.table = C.pointer(tab)
         sysd.skin = float(skin)
         sysd.r_dep = float(r_dep)
         if colours not in (8, 27):
@@ -508,6 +540,9 @@ class VCSGCBatch(VCSGC):
         sysd.x, sysd.y, sysd.z = self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr()
         sysd.species = self.species.data_ptr()
         sysd.pot = pot_struct(pot, mass_a, mass_b)
+        tab, tab_keep = table_struct(pot)
+        if tab is not None:
+            sysd.table = C.pointer(tab)
         sysd.skin = 0.3
         sysd.r_dep = float(r_dep)
         if colours not in (8, 27):

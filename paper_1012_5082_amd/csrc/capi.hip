@@ -31,7 +31,8 @@ void free_all(vcsgc_ctx *c) {
                   c->md_rows,    c->sites,      c->site_lnu,
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
                   c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnu2,     c->m_lnug,   c->m_rec,
-                  c->m_part,     c->s_rec,      c->s_part,     c->nvt,        c->nvt_part};
+                  c->m_part,     c->s_rec,      c->s_part,     c->nvt,        c->nvt_part,
+                  c->tab_coef};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -175,7 +176,7 @@ vcsgc_status assign_workgroups(vcsgc_ctx *c) {
   int dev_cu = 0, per_cu = 0;
   VC_CHECK(c, hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, c->device),
            "device query");
-  VC_CHECK(c, vc::persist_max_blocks(&per_cu), "occupancy query");
+  VC_CHECK(c, vc::persist_max_blocks(&per_cu, c->pot.tab != 0), "occupancy query");
   const int cap = dev_cu * (per_cu > 0 ? per_cu : 1);
   const int R = (int)c->reps.size();
   if (R > cap) return fail(c, VCSGC_E_INVALID_ARG, "more replicas than co-resident workgroups");
@@ -325,6 +326,23 @@ vcsgc_status vcsgc_get_kernel_timing(vcsgc_ctx *c, vcsgc_ktimes *out) {
 
 namespace {
 
+// Coefficients (a0, a1, a2, a3) per interval of the cubic Hermite
+// interpolant through y[0 .. n-1] at unit-spaced knots, knot slopes by
+// central differences and one-sided at the two ends (the interpolation
+// vcsgc_eam_table defines).
+void hermite_coeffs(int32_t n, const double *y, double *c) {
+  for (int32_t k = 0; k + 1 < n; ++k) {
+    const double m0 = k == 0 ? y[1] - y[0] : 0.5 * (y[k + 1] - y[k - 1]);
+    const double m1 = k + 2 == n ? y[n - 1] - y[n - 2] : 0.5 * (y[k + 2] - y[k]);
+    const double d = y[k + 1] - y[k];
+    double *a = c + 4 * (int64_t)k;
+    a[0] = y[k];
+    a[1] = m0;
+    a[2] = (3.0 * d - 2.0 * m0) - m1;
+    a[3] = (m0 + m1) - 2.0 * d;
+  }
+}
+
 // Shared by vcsgc_create (one replica) and vcsgc_create_batch.
 vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atoms,
                          const double *rep_box, hipStream_t stream, vcsgc_ctx **out) {
@@ -334,11 +352,29 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     return fail(nullptr, VCSGC_E_INVALID_ARG, "n_atoms must be in [2, 2^31)");
   if (!sys->x || !sys->y || !sys->z || !sys->species)
     return fail(nullptr, VCSGC_E_INVALID_ARG, "positions and species are required");
-  const double pv[] = {P.rc, P.c0, P.c1, P.eps_aa, P.eps_ab, P.eps_bb, P.t_a, P.t_b, P.a_a, P.a_b};
-  for (double v : pv)
-    if (!is_fin(v)) return fail(nullptr, VCSGC_E_INVALID_ARG, "non-finite potential parameter");
-  if (!(P.rc > 0.0)) return fail(nullptr, VCSGC_E_INVALID_ARG, "rc must be positive");
-  if (!(sys->skin >= 0.0) || !is_fin(sys->skin) || sys->skin > P.rc)
+  const vcsgc_eam_table *T = sys->table;
+  if (T) {
+    if (T->nr < 2 || T->nrho < 2 || !(T->dr > 0.0) || !(T->drho > 0.0) || !is_fin(T->dr) ||
+        !is_fin(T->drho) || !(T->rc > 0.0) || !is_fin(T->rc) ||
+        T->rc > (double)(T->nr - 1) * T->dr)
+      return fail(nullptr, VCSGC_E_INVALID_ARG,
+                  "table needs nr, nrho >= 2, dr, drho > 0 and 0 < rc <= (nr - 1) dr");
+    const double *arrs[] = {T->f[0], T->f[1], T->phi[0], T->phi[1], T->phi[2], T->F[0], T->F[1]};
+    for (int k = 0; k < 7; ++k) {
+      if (!arrs[k]) return fail(nullptr, VCSGC_E_INVALID_ARG, "missing table");
+      const int32_t nk = k < 5 ? T->nr : T->nrho;
+      for (int32_t q = 0; q < nk; ++q)
+        if (!is_fin(arrs[k][q])) return fail(nullptr, VCSGC_E_INVALID_ARG, "non-finite table value");
+    }
+  } else {
+    const double pv[] = {P.rc, P.c0, P.c1, P.eps_aa, P.eps_ab, P.eps_bb,
+                         P.t_a, P.t_b, P.a_a, P.a_b};
+    for (double v : pv)
+      if (!is_fin(v)) return fail(nullptr, VCSGC_E_INVALID_ARG, "non-finite potential parameter");
+  }
+  const double rc = T ? T->rc : P.rc;
+  if (!(rc > 0.0)) return fail(nullptr, VCSGC_E_INVALID_ARG, "rc must be positive");
+  if (!(sys->skin >= 0.0) || !is_fin(sys->skin) || sys->skin > rc)
     return fail(nullptr, VCSGC_E_INVALID_ARG, "skin must be in [0, rc]");
   const bool has_v = sys->vx || sys->vy || sys->vz;
   if (has_v && !(sys->vx && sys->vy && sys->vz))
@@ -348,8 +384,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     return fail(nullptr, VCSGC_E_INVALID_ARG, "forces must be all set or all NULL");
   if (has_v && (!(P.mass_a > 0.0) || !(P.mass_b > 0.0) || !is_fin(P.mass_a) || !is_fin(P.mass_b)))
     return fail(nullptr, VCSGC_E_INVALID_ARG, "masses must be positive with velocities");
-  const double r_dep = sys->r_dep == 0.0 ? 2.0 * P.rc : sys->r_dep;
-  if (!(r_dep >= 2.0 * P.rc) || !is_fin(r_dep))
+  const double r_dep = sys->r_dep == 0.0 ? 2.0 * rc : sys->r_dep;
+  if (!(r_dep >= 2.0 * rc) || !is_fin(r_dep))
     return fail(nullptr, VCSGC_E_INVALID_ARG, "r_dep must be >= 2 rc");
   const int per = (sys->flags & VCSGC_FLAG_COLOURS27) ? 3 : 2, ncol = per * per * per;
 
@@ -370,8 +406,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
                     per == 2 ? "box must hold two cells of edge r_dep in every dimension"
                              : "box must hold three cells of edge r_dep / 2 in every dimension");
       const double bin_edge = (sys->flags & VCSGC_FLAG_DESCRIPTOR)
-                                  ? std::max(P.rc + sys->skin, vc::DESC_CUT)
-                                  : P.rc + sys->skin;
+                                  ? std::max(rc + sys->skin, vc::DESC_CUT)
+                                  : rc + sys->skin;
       r.nb[d] = (int)std::floor(r.box[d] / bin_edge);
       if (r.nb[d] < 2)
         return fail(nullptr, VCSGC_E_BOX_TOO_SMALL, "box too small for the neighbour search");
@@ -422,7 +458,7 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   c->skin = sys->skin;
   c->r_dep = r_dep;
   vc::PotD &p = c->pot;
-  p.rc = P.rc;
+  p.rc = rc;
   p.c0 = P.c0;
   p.c1 = P.c1;
   p.eps[0] = P.eps_aa;
@@ -439,6 +475,32 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   c->bmax = 16;
   c->strategy = 0;
   c->desc = (sys->flags & VCSGC_FLAG_DESCRIPTOR) != 0;
+  if (T) {
+    // the interpolants' coefficients: f_A, f_B, phi_AA, phi_AB, phi_BB, then F_A, F_B
+    const int64_t nir = T->nr - 1, nid = T->nrho - 1;
+    std::vector<double> co((size_t)(4 * (5 * nir + 2 * nid)));
+    const double *arrs[] = {T->f[0], T->f[1], T->phi[0], T->phi[1], T->phi[2], T->F[0], T->F[1]};
+    size_t o = 0;
+    for (int k = 0; k < 7; ++k) {
+      const int32_t nk = k < 5 ? T->nr : T->nrho;
+      hermite_coeffs(nk, arrs[k], co.data() + o);
+      o += (size_t)4 * (nk - 1);
+    }
+    hipError_t e1 = dalloc(&c->tab_coef, co.size());
+    if (e1 == hipSuccess)
+      e1 = hipMemcpy(c->tab_coef, co.data(), sizeof(double) * co.size(), hipMemcpyHostToDevice);
+    if (e1 != hipSuccess) {
+      free_all(c);
+      delete c;
+      return fail(nullptr, VCSGC_E_OUT_OF_MEMORY, "table upload");
+    }
+    p.tab = 1;
+    p.nr = T->nr;
+    p.nrho = T->nrho;
+    p.inv_dr = 1.0 / T->dr;
+    p.inv_drho = 1.0 / T->drho;
+    p.tc = c->tab_coef;
+  }
 
   const int64_t n = c->n, K = vc::KMAX;
   const bool single = R == 1;

@@ -842,7 +842,7 @@ hipError_t launch_md_rebuild_cond(vcsgc_ctx *c, int par) {
 bool md_rebuild_on_device(const vcsgc_ctx *c) { return c->bin_pos != nullptr; }
 
 // ----------------------------------------------------------------------------
-// density cache: rho_i = sum_j t_{s_j} (rc - r_ij)^2, ascending j (row-major MC rows)
+// density cache: rho_i = sum_j f_{s_j}(r_ij), ascending j (row-major MC rows)
 // ----------------------------------------------------------------------------
 __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
                              const double *__restrict__ nr, const uint8_t *__restrict__ cnt,
@@ -853,7 +853,7 @@ __global__ void k_density_mc(int64_t n, const int32_t *__restrict__ nj,
   const int m = cnt[i];
   for (int k = 0; k < m; ++k) {
     const int32_t j = nj[i * KMAX + k];
-    s += p.t[sp[j]] * pair_dd(p, nr[i * KMAX + k]);
+    s += pot_f(p, sp[j], nr[i * KMAX + k]);
   }
   rho[i] = s;
 }

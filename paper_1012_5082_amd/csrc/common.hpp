@@ -33,6 +33,13 @@ struct PotD {
   double A[2];
   double cm[2];    // ACC / mass
   double mass[2];  // u
+  // tabulated potential (tab != 0; then only rc, cm and mass above are
+  // used): piecewise-cubic coefficients, 4 per interval, of f_A, f_B,
+  // phi_AA, phi_AB, phi_BB over the nr - 1 radial intervals, then F_A, F_B
+  // over the nrho - 1 density intervals
+  int tab, nr, nrho;
+  double inv_dr, inv_drho;
+  const double *tc;
 };
 
 // Progress of the fused stage pipeline of one call: stage s of sweep w and
@@ -189,35 +196,126 @@ __device__ __forceinline__ double div_md(double a, double b) {
   return __builtin_fma(e, y, q);
 }
 
+// The interpolant of a tabulated EAM function (a general embedded-atom
+// potential, Introduction and Sec. III): knots at x = k h (k < n),
+// coefficients (a0, a1, a2, a3) per interval of the
+// cubic Hermite interpolant with central-difference knot slopes (one-sided
+// at the ends), p = x / h by the rounded 1/h, k = floor(p) limited to
+// [0, n - 2], t = p - k (outside the knots the end interval continues):
+// value ((a3 t + a2) t + a1) t + a0, derivative ((3 a3 t + 2 a2) t + a1) / h.
+__device__ __forceinline__ double spline_at(const double *c, int n, double x, double inv_h,
+                                            double *der) {
+  const double p = x * inv_h;
+  const double top = (double)(n - 1);
+  const double pc = p > 0.0 ? (p < top ? p : top) : 0.0;  // (a NaN p gives 0)
+  int k = (int)pc;
+  k = k > n - 2 ? n - 2 : k;
+  const double t = p - (double)k;
+  const double4 a = *(const double4 *)(c + 4 * (int64_t)k);
+  if (der) *der = (((3.0 * a.w) * t + 2.0 * a.z) * t + a.y) * inv_h;
+  return ((a.w * t + a.z) * t + a.y) * t + a.x;
+}
+// radial table k: 0, 1 = f_A, f_B; 2, 3, 4 = phi_AA, phi_AB, phi_BB
+__device__ __forceinline__ const double *tab_radial(const PotD &p, int k) {
+  return p.tc + 4 * (int64_t)k * (p.nr - 1);
+}
+__device__ __forceinline__ const double *tab_embed(const PotD &p, int s) {
+  return p.tc + 4 * (5 * (int64_t)(p.nr - 1) + (int64_t)s * (p.nrho - 1));
+}
+
+// The potential's form for the helpers below: F = 0 analytic, 1 tabulated
+// (fixed at compile time), -1 (the default) read from p.tab.
+template <int F>
+__device__ __forceinline__ bool pot_tab(const PotD &p) {
+  return F < 0 ? p.tab != 0 : F == 1;
+}
+
+// f_X(r), f'_X(r), phi_XY(r), phi'_XY(r) for r < rc: the Finnis-Sinclair
+// forms t_X d^2, (-2 t_X) d, (eps_XY d^2)(c0 + c1 r) and
+// eps_XY ((-2 d)(c0 + c1 r) + c1 d^2) with d = rc - r, or the tables
+template <int F = -1>
+__device__ __forceinline__ double pot_f(const PotD &p, int s, double r) {
+  if (pot_tab<F>(p)) return spline_at(tab_radial(p, s), p.nr, r, p.inv_dr, nullptr);
+  return p.t[s] * pair_dd(p, r);
+}
+template <int F = -1>
+__device__ __forceinline__ double pot_df(const PotD &p, int s, double r) {
+  if (pot_tab<F>(p)) {
+    double g;
+    spline_at(tab_radial(p, s), p.nr, r, p.inv_dr, &g);
+    return g;
+  }
+  return -2.0 * p.t[s] * (p.rc - r);
+}
+template <int F = -1>
+__device__ __forceinline__ double pot_phi(const PotD &p, int a, int b, double r) {
+  if (pot_tab<F>(p)) return spline_at(tab_radial(p, 2 + a + b), p.nr, r, p.inv_dr, nullptr);
+  return p.eps[a + b] * pair_dd(p, r) * pair_g(p, r);
+}
+template <int F = -1>
+__device__ __forceinline__ double pot_dphi(const PotD &p, int a, int b, double r) {
+  if (pot_tab<F>(p)) {
+    double g;
+    spline_at(tab_radial(p, 2 + a + b), p.nr, r, p.inv_dr, &g);
+    return g;
+  }
+  const double d = p.rc - r;
+  return p.eps[a + b] * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
+}
+
+// F_X(rho) = -A_X sqrt(max(rho, 0)) and F'_X(rho) (0 at rho <= 0), or the tables
+template <int F = -1>
 __device__ __forceinline__ double embed(const PotD &p, int s, double rho) {
+  if (pot_tab<F>(p)) return spline_at(tab_embed(p, s), p.nrho, rho, p.inv_drho, nullptr);
   return -p.A[s] * sqrt(rho > 0.0 ? rho : 0.0);
 }
 
+template <int F = -1>
 __device__ __forceinline__ double dembed(const PotD &p, int s, double rho) {
+  if (pot_tab<F>(p)) {
+    double g;
+    spline_at(tab_embed(p, s), p.nrho, rho, p.inv_drho, &g);
+    return g;
+  }
   return rho > 0.0 ? -p.A[s] / (2.0 * sqrt(rho)) : 0.0;
 }
 
 // What flipping a site from species s to 1 - s changes, in the order every
-// sweep path evaluates it (Eq. of the transmutation energy; the r < rc list
-// gives each neighbour entry dd = (rc - r)^2 and g = c0 + c1 r):
-//   the neighbour's density shifts by t_{1-s} dd - t_s dd;
+// sweep path evaluates it (Eq. of the transmutation energy), for a
+// neighbour entry at distance r < rc:
+//   the neighbour's density shifts by f_{1-s}(r) - f_s(r);
 //   the pair energy with a neighbour of species sj by
-//     (eps_{1-s,sj} dd) g - (eps_{s,sj} dd) g;
+//     phi_{1-s,sj}(r) - phi_{s,sj}(r);
 //   that neighbour's embedding energy by F_sj(rho_j + shift) - F_sj(rho_j);
 //   the site's own embedding energy by F_{1-s}(rho_i) - F_s(rho_i).
 // dU is the own term plus the in-order sums of the pair and embedding terms.
-__device__ __forceinline__ double flip_rho_shift(const PotD &p, int s, double dd) {
+// (Finnis-Sinclair: with dd = (rc - r)^2, g = c0 + c1 r the shift is
+// t_{1-s} dd - t_s dd and the pair change (eps_{1-s,sj} dd) g - (eps_{s,sj} dd) g.)
+// the Finnis-Sinclair forms from dd and g formed beforehand
+__device__ __forceinline__ double flip_rho_shift_fs(const PotD &p, int s, double dd) {
   return p.t[1 - s] * dd - p.t[s] * dd;
 }
-__device__ __forceinline__ double flip_pair_term(const PotD &p, int s, int sj, double dd,
-                                                 double g) {
+__device__ __forceinline__ double flip_pair_term_fs(const PotD &p, int s, int sj, double dd,
+                                                    double g) {
   return p.eps[1 - s + sj] * dd * g - p.eps[s + sj] * dd * g;
 }
-__device__ __forceinline__ double flip_embed_term(const PotD &p, int sj, double rj, double shift) {
-  return embed(p, sj, rj + shift) - embed(p, sj, rj);
+template <int F = -1>
+__device__ __forceinline__ double flip_rho_shift(const PotD &p, int s, double r) {
+  if (pot_tab<F>(p)) return pot_f<F>(p, 1 - s, r) - pot_f<F>(p, s, r);
+  return flip_rho_shift_fs(p, s, pair_dd(p, r));
 }
+template <int F = -1>
+__device__ __forceinline__ double flip_pair_term(const PotD &p, int s, int sj, double r) {
+  if (pot_tab<F>(p)) return pot_phi<F>(p, 1 - s, sj, r) - pot_phi<F>(p, s, sj, r);
+  return flip_pair_term_fs(p, s, sj, pair_dd(p, r), pair_g(p, r));
+}
+template <int F = -1>
+__device__ __forceinline__ double flip_embed_term(const PotD &p, int sj, double rj, double shift) {
+  return embed<F>(p, sj, rj + shift) - embed<F>(p, sj, rj);
+}
+template <int F = -1>
 __device__ __forceinline__ double flip_own_term(const PotD &p, int s, double ri) {
-  return embed(p, 1 - s, ri) - embed(p, s, ri);
+  return embed<F>(p, 1 - s, ri) - embed<F>(p, s, ri);
 }
 
 // The in-order sums of the (pair, embedding) terms of entries 0 .. m-1 held
@@ -350,6 +448,7 @@ struct vcsgc_ctx {
   // kinetic-energy sums nvt_part [ceil(n / 256)]
   double nvt_T = 0.0, nvt_tau = 0.0;
   double *nvt = nullptr, *nvt_part = nullptr;
+  double *tab_coef = nullptr;  // tabulated potential's coefficients (PotD::tc)
 
   // search bins for neighbour lists: edge >= rc + skin, fixed capacity per bin
   int nb[3] = {0, 0, 0};
@@ -519,7 +618,7 @@ int persist_block();
 int persist_groups();
 size_t repd_size();
 size_t repstate_size();
-hipError_t persist_max_blocks(int *per_cu);
+hipError_t persist_max_blocks(int *per_cu, bool tab);
 hipError_t persist_stage_params(vcsgc_ctx *c, const double *dmu0, const double *kappa,
                                 const double *cbar, const double *T, int64_t n_sweeps,
                                 uint64_t seed);

@@ -35,9 +35,10 @@ hipError_t launch_pack(vcsgc_ctx *c) {
   return hipGetLastError();
 }
 
-// rho_i = sum_{j: r < rc} t_{s_j} (rc - r)^2 over the row of i, in entry
-// order: the indices of up to IB entries in one round, then the gathers UNR
-// at a time
+// rho_i = sum_{j: r < rc} f_{s_j}(r) over the row of i, in entry order
+// (f_X = t_X (rc - r)^2, or the tables when TAB): the indices of up to IB
+// entries in one round, then the gathers UNR at a time
+template <bool TAB>
 __device__ __forceinline__ double density_row(int64_t n, int64_t i, int m, const double4 &qi,
                                               const double4 *__restrict__ ps4,
                                               const int32_t *__restrict__ nj, const Box &b,
@@ -60,20 +61,28 @@ __device__ __forceinline__ double density_row(int64_t n, int64_t i, int m, const
         const double dy = min_image_sel(q[u].y - qi.y, b.L1);
         const double dz = min_image_sel(q[u].z - qi.z, b.L2);
         const double r = sqrt_md((dx * dx + dy * dy) + dz * dz);
-        const double d = p.rc - r;
-        const double term = (q[u].w != 0.0 ? t1 : t0) * (d * d);
+        const bool in = k0 + g + u < m && r < p.rc;
+        double term;
+        if (TAB) {
+          term = spline_at(tab_radial(p, q[u].w != 0.0 ? 1 : 0), p.nr, in ? r : 0.0, p.inv_dr,
+                           nullptr);
+        } else {
+          const double d = p.rc - r;
+          term = (q[u].w != 0.0 ? t1 : t0) * (d * d);
+        }
         // a skipped pair adds +0.0: s is never -0.0, so s + 0.0 == s (the
         // padding entries, the atom itself at r^2 = 0, have r = NaN from
         // sqrt_md, which the select drops)
-        s += (k0 + g + u < m && r < p.rc) ? term : 0.0;
+        s += in ? term : 0.0;
       }
     }
   }
   return s;
 }
 
-// rho_i, and (x_i, y_i, z_i, F'_i) with F'_i = -A_{s_i} / (2 sqrt(rho_i)) for
-// the force pass
+// rho_i, and (x_i, y_i, z_i, F'_i) with F'_i = F'_{s_i}(rho_i) for the force
+// pass
+template <bool TAB>
 __global__ void __launch_bounds__(BLOCK)
     k_density_md(int64_t n, const double4 *__restrict__ ps4, const int32_t *__restrict__ nj,
                  const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
@@ -82,7 +91,7 @@ __global__ void __launch_bounds__(BLOCK)
   if (i >= n) return;
   const double4 qi = ps4[i];
   const int m = cnt[i];
-  const double s = density_row(n, i, m, qi, ps4, nj, b, p);
+  const double s = density_row<TAB>(n, i, m, qi, ps4, nj, b, p);
   rho[i] = s;
   const double f = dembed(p, sp[i], s);
   pf4[i] = make_double4(qi.x, qi.y, qi.z, f);
@@ -158,7 +167,8 @@ __device__ __forceinline__ void kick_drift_atom(const KickDrift &k, int64_t i, i
 
 // F_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i) / r with
 // phi'(r) = eps ((-2 d)(c0 + c1 r) + c1 d^2) and f'_X(r) = (-2 t_X) d, d = rc - r,
-// summed in entry order
+// summed in entry order (Finnis-Sinclair forms, or the tables when TAB)
+template <bool TAB>
 __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, const double4 &qi,
                                           const double4 *__restrict__ pf4,
                                           const int32_t *__restrict__ nj,
@@ -189,11 +199,18 @@ __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, c
         // branch kept here: the select form evaluates the FP64 division for
         // every list entry and measured slower than this one
         if (k0 + g + u < m && r < p.rc) {
-          const double d = p.rc - r;
-          const double eps = sj[u] ? e1 : e0, tj = sj[u] ? t1 : t0;
-          const double dphi = eps * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
-          const double dfj = -2.0 * tj * d;
-          const double dfi = -2.0 * ti * d;
+          double dphi, dfj, dfi;
+          if (TAB) {
+            spline_at(tab_radial(p, 2 + si + sj[u]), p.nr, r, p.inv_dr, &dphi);
+            spline_at(tab_radial(p, sj[u]), p.nr, r, p.inv_dr, &dfj);
+            spline_at(tab_radial(p, si), p.nr, r, p.inv_dr, &dfi);
+          } else {
+            const double d = p.rc - r;
+            const double eps = sj[u] ? e1 : e0, tj = sj[u] ? t1 : t0;
+            dphi = eps * (-2.0 * d * (p.c0 + p.c1 * r) + p.c1 * (d * d));
+            dfj = -2.0 * tj * d;
+            dfi = -2.0 * ti * d;
+          }
           const double s = dphi + fpi * dfj + q[u].w * dfi;
           const double coef = div_md(s, r);
           ax += coef * dx;
@@ -207,8 +224,8 @@ __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, c
 
 // KD: the forces are not stored but go straight into the next step's kick
 // and drift (the positions it writes are not read by this pass, which
-// gathers pf4).
-template <bool KD>
+// gathers pf4).  TAB: tabulated potential.
+template <bool KD, bool TAB>
 __global__ void __launch_bounds__(BLOCK)
     k_forces(int64_t n, const double4 *__restrict__ pf4, const int32_t *__restrict__ nj,
              const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
@@ -220,7 +237,7 @@ __global__ void __launch_bounds__(BLOCK)
   const int si = sp[i];
   const int m = cnt[i];
   double ax = 0.0, ay = 0.0, az = 0.0;
-  force_row(n, i, m, si, qi, pf4, nj, sp, b, p, ax, ay, az);
+  force_row<TAB>(n, i, m, si, qi, pf4, nj, sp, b, p, ax, ay, az);
   if (KD) {
     // the packed positions equal x, y, z bit for bit
     kick_drift_atom(kd, i, si, qi.x, qi.y, qi.z, ax, ay, az, b, p);
@@ -231,7 +248,7 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
-// E_i = F_{s_i}(rho_i) + 0.5 sum_j (eps d^2)(c0 + c1 r)
+// E_i = F_{s_i}(rho_i) + 0.5 sum_j phi_{s_i s_j}(r)
 __global__ void k_energy(int64_t n, const double4 *__restrict__ ps4, const int32_t *__restrict__ nj,
                          const uint8_t *__restrict__ cnt, const double *__restrict__ rho, Box b,
                          PotD p, double *e) {
@@ -249,21 +266,38 @@ __global__ void k_energy(int64_t n, const double4 *__restrict__ ps4, const int32
     const double dz = min_image(qj.z - qi.z, b.L2);
     const double r = sqrt((dx * dx + dy * dy) + dz * dz);
     if (!(r < p.rc)) continue;
-    const double d = p.rc - r;
-    ps += p.eps[si + (int)qj.w] * (d * d) * (p.c0 + p.c1 * r);
+    ps += pot_phi(p, si, (int)qj.w, r);
   }
   e[i] = embed(p, si, rho[i]) + 0.5 * ps;
+}
+
+// the density pass and the force pass for the context's potential form
+static void density_md_launch(vcsgc_ctx *c, const Box &b) {
+  if (c->pot.tab)
+    k_density_md<true><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+        c->n, c->ps4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->rho_f, c->pf4);
+  else
+    k_density_md<false><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+        c->n, c->ps4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->rho_f, c->pf4);
+}
+
+template <bool KD>
+static void forces_launch(vcsgc_ctx *c, const Box &b, const KickDrift &kd) {
+  if (c->pot.tab)
+    k_forces<KD, true><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+        c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->fx, c->fy, c->fz, kd);
+  else
+    k_forces<KD, false><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+        c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->fx, c->fy, c->fz, kd);
 }
 
 hipError_t launch_forces(vcsgc_ctx *c) {
   Box b{c->box[0], c->box[1], c->box[2]};
   int h = tstart(c, VCSGC_KT_DENSITY);
-  k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
-                                                        b, c->pot, c->rho_f, c->pf4);
+  density_md_launch(c, b);
   tstop(c, h);
   h = tstart(c, VCSGC_KT_FORCES);
-  k_forces<false><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
-      c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->fx, c->fy, c->fz, KickDrift{});
+  forces_launch<false>(c, b, KickDrift{});
   tstop(c, h);
   return hipGetLastError();
 }
@@ -294,13 +328,10 @@ static KickDrift kick_drift_args(vcsgc_ctx *c, double dt, bool kick_first, int p
 hipError_t launch_forces_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, int par) {
   Box b{c->box[0], c->box[1], c->box[2]};
   int h = tstart(c, VCSGC_KT_DENSITY);
-  k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
-                                                        b, c->pot, c->rho_f, c->pf4);
+  density_md_launch(c, b);
   tstop(c, h);
   h = tstart(c, VCSGC_KT_FORCES);
-  k_forces<true><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
-      c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->fx, c->fy, c->fz,
-      kick_drift_args(c, dt, kick_first, par));
+  forces_launch<true>(c, b, kick_drift_args(c, dt, kick_first, par));
   tstop(c, h);
   return hipGetLastError();
 }
@@ -308,8 +339,7 @@ hipError_t launch_forces_kick_drift(vcsgc_ctx *c, double dt, bool kick_first, in
 hipError_t launch_energy(vcsgc_ctx *c) {
   Box b{c->box[0], c->box[1], c->box[2]};
   int h = tstart(c, VCSGC_KT_ENERGY);
-  k_density_md<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->sp,
-                                                        b, c->pot, c->rho_f, c->pf4);
+  density_md_launch(c, b);
   k_energy<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->ps4, c->md_j, c->md_cnt, c->rho_f,
                                                     b, c->pot, c->eatom);
   tstop(c, h);

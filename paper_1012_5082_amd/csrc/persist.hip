@@ -113,6 +113,7 @@ __device__ __forceinline__ int64_t p_colour_cell(const RepD &r, int colour, int6
 // transmutation energy change by the PTL lanes of a group (in-order sums of
 // the terms the lanes leave in the group's LDS slots; a group is 16 lanes of
 // one wave, whose LDS accesses are performed in order)
+template <int F>
 __device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int lane,
                                             double2 *grp) {
   const int s = a.sp[i];
@@ -127,10 +128,9 @@ __device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int
       const int32_t j = a.nj[e];
       const int sj = a.sp[j];
       const double r = a.nr[e];
-      const double dd = pair_dd(a.p, r), g = pair_g(a.p, r);
       const double rj = a.rho[j];
-      tp[h] = flip_pair_term(a.p, s, sj, dd, g);
-      te[h] = flip_embed_term(a.p, sj, rj, flip_rho_shift(a.p, s, dd));
+      tp[h] = flip_pair_term<F>(a.p, s, sj, r);
+      te[h] = flip_embed_term<F>(a.p, sj, rj, flip_rho_shift<F>(a.p, s, r));
     }
   }
   grp[lane] = make_double2(tp[0], te[0]);
@@ -139,11 +139,15 @@ __device__ __forceinline__ double p_delta_u(const PersistArgs &a, int64_t i, int
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   double pair, emb;
   sum_flip_terms(grp, m, pair, emb);
-  const double own = flip_own_term(a.p, s, ri);
+  const double own = flip_own_term<F>(a.p, s, ri);
   return own + pair + emb;
 }
 
+// TAB: the potential's form (analytic or tabulated) fixed at compile time,
+// so each variant keeps only its own arithmetic and registers.
+template <bool TAB>
 __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
+  constexpr int F = TAB ? 1 : 0;
   __shared__ long long sh[BLOCK];
   __shared__ double2 pterms[PGROUPS][KMAX];
   __shared__ int bflag;
@@ -182,7 +186,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
         if (m > 0) {
           const U4 rr = philox(r.seed, r.key1, w, (uint64_t)s, (uint64_t)cell, 1);
           const int64_t i = catoms[c0 + draw_index(rr.v[0], m)];
-          const double du = p_delta_u(a, i, lane, pterms[grp]);
+          const double du = p_delta_u<F>(a, i, lane, pterms[grp]);
           if (lane == 0) {
             const double u = unit_open(rr.v[1]);
             const int dn = 1 - 2 * (int)a.sp[i];
@@ -262,8 +266,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persistent(PersistArgs a) {
             if (k < m) {
               const int64_t e = (int64_t)i * KMAX + k;
               const int32_t j = a.nj[e];
-              const double dd = pair_dd(a.p, a.nr[e]);
-              const double delta = flip_rho_shift(a.p, s0, dd);
+              const double delta = flip_rho_shift<F>(a.p, s0, a.nr[e]);
               a.rho[j] = a.rho[j] + delta;
             }
           }
@@ -344,8 +347,15 @@ int persist_groups() { return PGROUPS; }
 size_t repd_size() { return sizeof(RepD); }
 size_t repstate_size() { return sizeof(RepState); }
 
-hipError_t persist_max_blocks(int *per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent, BLOCK, 0);
+static const void *persist_kernel(bool tab) {
+  return tab ? (const void *)k_sweep_persistent<true> : (const void *)k_sweep_persistent<false>;
+}
+
+hipError_t persist_max_blocks(int *per_cu, bool tab) {
+  return tab ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent<true>,
+                                                             BLOCK, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sweep_persistent<false>,
+                                                             BLOCK, 0);
 }
 
 static PersistArgs make_args(vcsgc_ctx *c) {
@@ -443,7 +453,7 @@ static hipError_t build_graph(vcsgc_ctx *c) {
   *ga = make_args(c);
   void *sargs[] = {ga};
   hipKernelNodeParams sp = {};
-  sp.func = (void *)k_sweep_persistent;
+  sp.func = const_cast<void *>(persist_kernel(c->pot.tab != 0));
   sp.gridDim = dim3((unsigned)c->grid_total);
   sp.blockDim = dim3(BLOCK);
   sp.kernelParams = sargs;
@@ -475,7 +485,7 @@ hipError_t launch_persistent(vcsgc_ctx *c, bool use_graph) {
   if (e != hipSuccess) return e;
   PersistArgs a = make_args(c);
   void *args[] = {&a};
-  return hipLaunchCooperativeKernel((const void *)k_sweep_persistent, dim3((unsigned)c->grid_total),
+  return hipLaunchCooperativeKernel(persist_kernel(c->pot.tab != 0), dim3((unsigned)c->grid_total),
                                     dim3(BLOCK), args, 0, c->stream);
 }
 

@@ -99,12 +99,15 @@ struct TrialInT {
   int s, m;
   double ri;
   int32_t j[H];
+  // Finnis-Sinclair: dd = (rc - r)^2 and g = c0 + c1 r, formed while the
+  // gathers are in flight; tabulated potential: dd holds r
   double dd[H], g[H], rj[H];
   int sj[H];
 };
 typedef TrialInT<TL> TrialIn;
 
-template <int L>
+// F: the potential's form (0 analytic, 1 tabulated, -1 read from a.p.tab)
+template <int L, int F>
 __device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int lane,
                                            TrialInT<L> &v) {
   constexpr int H = KMAX / L;
@@ -122,8 +125,12 @@ __device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int la
       const int64_t e = i * KMAX + k;
       v.j[h] = a.nj[e];
       const double r = a.nr[e];
-      v.dd[h] = pair_dd(a.p, r);
-      v.g[h] = pair_g(a.p, r);
+      if (pot_tab<F>(a.p)) {
+        v.dd[h] = r;
+      } else {
+        v.dd[h] = pair_dd(a.p, r);
+        v.g[h] = pair_g(a.p, r);
+      }
     }
   }
 #pragma unroll
@@ -138,15 +145,15 @@ __device__ __forceinline__ void load_trial(const SweepArgs &a, int64_t i, int la
 typedef double2 GroupTerms[KMAX];
 
 // dU of s_i -> 1 - s_i, evaluated by the L lanes of one group:
-//   (F_{s'}(rho_i) - F_s(rho_i)) + sum_j [(eps_{s's_j} dd) g - (eps_{s s_j} dd) g]
-//   + sum_j [F_{s_j}(rho_j + (t_{s'} dd - t_s dd)) - F_{s_j}(rho_j)]
+//   (F_{s'}(rho_i) - F_s(rho_i)) + sum_j [phi_{s's_j}(r) - phi_{s s_j}(r)]
+//   + sum_j [F_{s_j}(rho_j + (f_{s'}(r) - f_s(r))) - F_{s_j}(rho_j)]
 // Each lane computes the terms of its entries and stores them in the group's
 // LDS slots; every lane then forms both sums in ascending entry order from
 // there (the rounding of the sequential sums; the slot reads do not wait on
 // the additions, so there is one LDS round trip per eight entries rather than
 // one per entry).  A group is L lanes of one wave, whose LDS accesses are
 // performed in order.  Every lane of the group returns the same value.
-template <int L>
+template <int L, int F>
 __device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialInT<L> &v, int lane,
                                              double2 *grp) {
   constexpr int H = KMAX / L;
@@ -158,10 +165,16 @@ __device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialInT<
     double tp = 0.0, te = 0.0;
     if (k < m) {
       const int sj = v.sj[h];
-      const double dd = v.dd[h], g = v.g[h];
       const double rj = v.rj[h];
-      tp = flip_pair_term(a.p, s, sj, dd, g);
-      te = flip_embed_term(a.p, sj, rj, flip_rho_shift(a.p, s, dd));
+      if (pot_tab<F>(a.p)) {
+        const double r = v.dd[h];
+        tp = flip_pair_term<1>(a.p, s, sj, r);
+        te = flip_embed_term<1>(a.p, sj, rj, flip_rho_shift<1>(a.p, s, r));
+      } else {
+        const double dd = v.dd[h], g = v.g[h];
+        tp = flip_pair_term_fs(a.p, s, sj, dd, g);
+        te = flip_embed_term<0>(a.p, sj, rj, flip_rho_shift_fs(a.p, s, dd));
+      }
     }
     grp[k] = make_double2(tp, te);
   }
@@ -170,22 +183,23 @@ __device__ __forceinline__ double delta_u_of(const SweepArgs &a, const TrialInT<
   // two independent in-order chains
   double pair, emb;
   sum_flip_terms(grp, m, pair, emb);
-  const double own = flip_own_term(a.p, s, v.ri);
+  const double own = flip_own_term<F>(a.p, s, v.ri);
   return own + pair + emb;
 }
 
+template <int F = -1>
 __device__ __forceinline__ double delta_u_group(const SweepArgs &a, int64_t i, int lane,
                                                 double2 *grp) {
   TrialIn v;
-  load_trial(a, i, lane, v);
-  return delta_u_of(a, v, lane, grp);
+  load_trial<TL, F>(a, i, lane, v);
+  return delta_u_of<TL, F>(a, v, lane, grp);
 }
 
 // Descriptor of site i (or of the state with s_i flipped), by the TL lanes
 // of a group: [s_i, nB1, nB2, nB3, n1, n2, n3, rho1, rho2, rho3] over the
 // shells r < 2.68, [2.68, 3.46), [3.46, 4.41) A; the shell sums run in
 // ascending neighbour order.  In the flipped state every neighbour within rc
-// has rho_j + (t_{s'} - t_s)(rc - r)^2.  All lanes return the same values.
+// has rho_j + (f_{s'}(r) - f_s(r)).  All lanes return the same values.
 __device__ __forceinline__ void descriptor_group(const SweepArgs &a, int64_t i, int lane,
                                                  bool flip, double out[10]) {
   const int s = a.sp[i], s1 = 1 - s;
@@ -202,11 +216,7 @@ __device__ __forceinline__ void descriptor_group(const SweepArgs &a, int64_t i, 
       shl[h] = r < 2.68 ? 0 : (r < 3.46 ? 1 : (r < DESC_CUT ? 2 : -1));
       bj[h] = a.sp[j];
       double rho = a.rho[j];
-      if (flip && r < a.p.rc) {
-        const double d = a.p.rc - r;
-        const double dd = d * d;
-        rho = rho + flip_rho_shift(a.p, s, dd);
-      }
+      if (flip && r < a.p.rc) rho = rho + flip_rho_shift(a.p, s, r);
       rj[h] = rho;
     }
   }
@@ -277,12 +287,9 @@ __device__ __forceinline__ void desc_du_group(const SweepArgs &a, int64_t i, int
       q.rjf = rho;
       int in = 0;
       if (r < a.p.rc) {
-        const double d = a.p.rc - r;
-        const double dd = d * d;
-        const double g = a.p.c0 + a.p.c1 * r;
-        const double delta = flip_rho_shift(a.p, s, dd);
+        const double delta = flip_rho_shift(a.p, s, r);
         q.rjf = rho + delta;
-        q.tp = flip_pair_term(a.p, s, sj, dd, g);
+        q.tp = flip_pair_term(a.p, s, sj, r);
         q.te = flip_embed_term(a.p, sj, rho, delta);
         in = 1;
       }
@@ -392,7 +399,9 @@ __global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
   }
 }
 
-// one group of TL lanes per active cell
+// one group of TL lanes per active cell; F: the potential's form (0
+// analytic, 1 tabulated)
+template <int F>
 __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, int64_t s, int par) {
   const uint64_t w = sweep_of(a, w_arg);
   __shared__ long long sh[BLOCK];
@@ -406,7 +415,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, in
     int32_t site = -1;
     if (si >= 0) {
       const int64_t i = si;
-      const double du = delta_u_group(a, i, lane, terms[threadIdx.x / TL]);
+      const double du = delta_u_group<F>(a, i, lane, terms[threadIdx.x / TL]);
       if (a.smp_cap > 0 && ((int64_t)(w * (uint64_t)a.S + (uint64_t)s) * a.ncpc + t) % a.smp_stride == 0) {
         double d[10];
         descriptor_group(a, i, lane, false, d);
@@ -469,6 +478,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial(SweepArgs a, uint64_t w_arg, in
 // between trials so that every lane sees the group's updates.  Chains of
 // different active cells touch disjoint atoms (same-colour cells are a cell
 // edge >= 2 rc apart), so they run side by side.
+template <int F>
 __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_arg, int64_t s,
                                                        int par) {
   const uint64_t w = sweep_of(a, w_arg);
@@ -486,7 +496,7 @@ __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_a
     if (si >= 0) {
       const int64_t i = si;
       const double lnu = a.site_lnu[q];
-      const double du = delta_u_group(a, i, lane, terms[threadIdx.x / TL]);
+      const double du = delta_u_group<F>(a, i, lane, terms[threadIdx.x / TL]);
       const int s0 = a.sp[i];
       const int dn = 1 - 2 * s0;
       const double xl = a.beta * (du + a.dmu0 * (double)dn);
@@ -524,11 +534,11 @@ __global__ void __launch_bounds__(BLOCK) k_trial_chain(SweepArgs a, uint64_t w_a
           if (e < m) {
             const int64_t ee = i * KMAX + e;
             const int32_t j = a.nj[ee];
-            const double dd = pair_dd(a.p, a.nr[ee]);
+            const double r = a.nr[ee];
             const double old = a.rho[j];
             a.u_j[uq * KMAX + e] = j;
             a.u_rho[uq * KMAX + e] = old;
-            a.rho[j] = old + flip_rho_shift(a.p, s0, dd);
+            a.rho[j] = old + flip_rho_shift<F>(a.p, s0, r);
           }
         }
         if (lane == 0) {
@@ -795,6 +805,7 @@ __device__ __forceinline__ void stage_stats(const SweepArgs &a, uint64_t w, int6
 
 
 // one group of TL lanes per active cell: lane k updates rho of entries k, k + TL
+template <int F>
 __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, int64_t s, int par,
                                                   int last) {
   const uint64_t w = sweep_of(a, w_arg);
@@ -806,7 +817,7 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, i
   int32_t i = -1;
   int s0 = 0, m = 0;
   int32_t jr[2] = {0, 0};
-  double ddr[2] = {0.0, 0.0};
+  double rr[2] = {0.0, 0.0};
   if (t < a.ncpc) {
     i = a.rec[t];
     if (i >= 0) {
@@ -818,7 +829,7 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, i
         if (k < m) {
           const int64_t e = (int64_t)i * KMAX + k;
           jr[h] = a.nj[e];
-          ddr[h] = pair_dd(a.p, a.nr[e]);
+          rr[h] = a.nr[e];
         }
       }
     }
@@ -831,8 +842,7 @@ __global__ void __launch_bounds__(BLOCK) k_commit(SweepArgs a, uint64_t w_arg, i
     for (int h = 0; h < 2; ++h) {
       const int k = lane + h * TL;
       if (k < m) {
-        const double dd = ddr[h];
-        const double delta = flip_rho_shift(a.p, s0, dd);
+        const double delta = flip_rho_shift<F>(a.p, s0, rr[h]);
         a.rho[jr[h]] = a.rho[jr[h]] + delta;
       }
     }
@@ -969,7 +979,7 @@ __global__ void k_pipe_init(DevState *ds, unsigned long long w0, unsigned long l
 
 // Local tests of stage (w, s) from the loaded trial data: the record of the
 // group's cell, the trial log, and the block's two count words into P.
-template <int W>
+template <int F, int W>
 __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t w, int64_t s,
                                                    int64_t t, int lane, int32_t i, double lnu,
                                                    const TrialInT<W> &v, int32_t *rec,
@@ -979,7 +989,7 @@ __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t 
   if (t < a.ncpc) {
     int32_t site = -1;
     if (i >= 0) {
-      const double du = delta_u_of(a, v, lane, grp);
+      const double du = delta_u_of<W, F>(a, v, lane, grp);
       if (lane == 0) {
         const int dn = 1 - 2 * v.s;
         const double xl = a.beta * (du + a.dmu0 * (double)dn);
@@ -1024,7 +1034,7 @@ __device__ __forceinline__ void pipe_trials_finish(const SweepArgs &a, uint64_t 
 
 // Site and trial data of group t in stage (w, s) (site -1: empty cell or
 // past the last active cell).
-template <int L>
+template <int F, int L>
 __device__ __forceinline__ void pipe_trials_load(const SweepArgs &a, uint64_t w, int64_t s,
                                                  int64_t t, int lane, int32_t &i, double &lnu,
                                                  TrialInT<L> &v) {
@@ -1037,12 +1047,13 @@ __device__ __forceinline__ void pipe_trials_load(const SweepArgs &a, uint64_t w,
     const int64_t q = ((int64_t)(w & 1) * a.S + s) * a.ncpc + t;
     i = a.sites[q];
     lnu = a.site_lnu[q];
-    if (i >= 0) load_trial(a, i, lane, v);
+    if (i >= 0) load_trial<L, F>(a, i, lane, v);
   }
 }
 
 // Commit of an accepted trial at site i by the TL lanes of its group: rho_j
 // += delta_j of every neighbour entry, then the species and the velocity.
+template <int F>
 __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int lane) {
   const int s0 = a.sp[i], s1 = 1 - s0;
   const int m = a.cnt[i];
@@ -1052,8 +1063,7 @@ __device__ __forceinline__ void pipe_commit(const SweepArgs &a, int32_t i, int l
     if (k < m) {
       const int64_t e = (int64_t)i * KMAX + k;
       const int32_t j = a.nj[e];
-      const double dd = pair_dd(a.p, a.nr[e]);
-      const double delta = flip_rho_shift(a.p, s0, dd);
+      const double delta = flip_rho_shift<F>(a.p, s0, a.nr[e]);
       a.rho[j] = a.rho[j] + delta;
     }
   }
@@ -1083,6 +1093,7 @@ struct DaShared {
 };
 static_assert(BLOCK / TL == 16, "one network row per lane group");
 
+template <int F>
 __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, int64_t s,
                                                int64_t t, int lane, int32_t *rec,
                                                long long *P, long long *sh, double2 *grpt,
@@ -1106,7 +1117,7 @@ __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, i
     if (a.dj)
       desc_du_group(a, i, lane, dfw, dfl, du, ds_.dslots[grp]);
     else
-      du = delta_u_group(a, i, lane, grpt);
+      du = delta_u_group<F>(a, i, lane, grpt);
   }
   // both network values in one pass; the flipped one is used only when the
   // first stage passes
@@ -1201,8 +1212,9 @@ __device__ __forceinline__ void pipe_trials_da(const SweepArgs &a, uint64_t w, i
 // pipe.sm[par], written to pipe.sm[par ^ 1]).  Blocks [0, nblk) hold one
 // group of TL lanes per active cell; the blocks after them draw sites.
 // DA: the trials are delayed-acceptance trials (three count words per
-// trial block instead of two).
-template <bool DA>
+// trial block instead of two).  F: the potential's form (0 analytic, 1
+// tabulated).
+template <bool DA, int F>
 __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   constexpr int NPW = DA ? 3 : 2;  // count words per trial block
   __shared__ long long sh[BLOCK];  // the trials' block counts
@@ -1234,17 +1246,17 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   const int64_t rstride = ncpc, pstride = NPW * (int64_t)a.nblk;
   if (m.phase == SM_TRIAL) {
     if constexpr (DA) {
-      pipe_trials_da(a, m.w, m.s, t, lane, a.rec + (gs & 1) * rstride,
-                     a.part + (gs & 1) * pstride + NPW * blockIdx.x, sh,
-                     terms[threadIdx.x / TL], dash);
+      pipe_trials_da<F>(a, m.w, m.s, t, lane, a.rec + (gs & 1) * rstride,
+                        a.part + (gs & 1) * pstride + NPW * blockIdx.x, sh,
+                        terms[threadIdx.x / TL], dash);
     } else {
       int32_t i;
       double lnu;
       TrialIn v;
-      pipe_trials_load(a, m.w, m.s, t, lane, i, lnu, v);
-      pipe_trials_finish(a, m.w, m.s, t, lane, i, lnu, v, a.rec + (gs & 1) * rstride,
-                         a.part + (gs & 1) * pstride + NPW * blockIdx.x, sh,
-                         terms[threadIdx.x / TL]);
+      pipe_trials_load<F>(a, m.w, m.s, t, lane, i, lnu, v);
+      pipe_trials_finish<F>(a, m.w, m.s, t, lane, i, lnu, v, a.rec + (gs & 1) * rstride,
+                            a.part + (gs & 1) * pstride + NPW * blockIdx.x, sh,
+                            terms[threadIdx.x / TL]);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       StageMachine n = m;
@@ -1278,7 +1290,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   v.m = 0;
   v.s = 0;
   v.ri = 0.0;
-  if (!DA && more) pipe_trials_load(a, w2, s2, t, lane, i2, lnu2, v);
+  if (!DA && more) pipe_trials_load<F>(a, w2, s2, t, lane, i2, lnu2, v);
   // global test of (w, s) (Eq. trans_vcsgc_par2) from the trial blocks' counts
   block_sums<3, false>(c3, shd);
   const long long n_valid = c3[0] & 0xffffffffll, n_plus = c3[0] >> 32;
@@ -1300,17 +1312,17 @@ __global__ void __launch_bounds__(BLOCK) k_stage(SweepArgs a, int par) {
   if (gacc == 1) {
     if (t < ncpc) {
       const int32_t i = a.rec[(gs & 1) * rstride + t];
-      if (i >= 0) pipe_commit(a, i, lane);
+      if (i >= 0) pipe_commit<F>(a, i, lane);
     }
   } else if (more) {
     if constexpr (DA)
-      pipe_trials_da(a, w2, s2, t, lane, a.rec + ((gs + 1) & 1) * rstride,
-                     a.part + ((gs + 1) & 1) * pstride + NPW * blockIdx.x, sh,
-                     terms[threadIdx.x / TL], dash);
+      pipe_trials_da<F>(a, w2, s2, t, lane, a.rec + ((gs + 1) & 1) * rstride,
+                        a.part + ((gs + 1) & 1) * pstride + NPW * blockIdx.x, sh,
+                        terms[threadIdx.x / TL], dash);
     else
-      pipe_trials_finish(a, w2, s2, t, lane, i2, lnu2, v, a.rec + ((gs + 1) & 1) * rstride,
-                         a.part + ((gs + 1) & 1) * pstride + NPW * blockIdx.x, sh,
-                         terms[threadIdx.x / TL]);
+      pipe_trials_finish<F>(a, w2, s2, t, lane, i2, lnu2, v, a.rec + ((gs + 1) & 1) * rstride,
+                            a.part + ((gs + 1) & 1) * pstride + NPW * blockIdx.x, sh,
+                            terms[threadIdx.x / TL]);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ds->n_b_cur = nb_new;
@@ -1544,7 +1556,7 @@ __global__ void k_spec_init(DevState *ds, unsigned long long w0, unsigned long l
 // block 0 writes the results) and share the commit; the next D nblk blocks
 // hold one group of TL lanes per active cell and stage of the tried batch;
 // the blocks after them draw the site tables of the next sweep.
-template <bool DA>
+template <bool DA, int F>
 __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
   constexpr int NPW = DA ? 3 : 2;  // count words per trial block
   constexpr int LT = DA ? TL : TL_BATCH;  // lanes per trial
@@ -1578,13 +1590,13 @@ __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
       int32_t *rec = a.rec + ((int64_t)par * SPEC_MAX + k) * ncpc;
       long long *P = a.part + ((int64_t)par * SPEC_MAX + k) * kstride + lb * NPW;
       if constexpr (DA) {
-        pipe_trials_da(a, m.tw, s, t, lane, rec, P, sh, (double2 *)dash.dslots[grp], dash);
+        pipe_trials_da<F>(a, m.tw, s, t, lane, rec, P, sh, (double2 *)dash.dslots[grp], dash);
       } else {
         int32_t i;
         double lnu;
         TrialInT<LT> v;
-        pipe_trials_load(a, m.tw, s, t, lane, i, lnu, v);
-        pipe_trials_finish(a, m.tw, s, t, lane, i, lnu, v, rec, P, sh, terms[grp]);
+        pipe_trials_load<F>(a, m.tw, s, t, lane, i, lnu, v);
+        pipe_trials_finish<F>(a, m.tw, s, t, lane, i, lnu, v, rec, P, sh, terms[grp]);
       }
       return;
     }
@@ -1723,7 +1735,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage_spec(SweepArgs a, int par) {
     while (gm) {
       const int src = __ffs(gm) - 1;
       gm &= gm - 1;
-      pipe_commit(a, __shfl(r, src, TL), lane);
+      pipe_commit<F>(a, __shfl(r, src, TL), lane);
     }
   }
 }
@@ -1754,8 +1766,12 @@ struct PipeGraph {
 };
 
 static void *pipe_kernel(const SweepArgs &a) {
-  if (a.D > 0) return a.da_mode ? (void *)k_stage_spec<true> : (void *)k_stage_spec<false>;
-  return a.da_mode ? (void *)k_stage<true> : (void *)k_stage<false>;
+  if (a.p.tab) {
+    if (a.D > 0) return a.da_mode ? (void *)k_stage_spec<true, 1> : (void *)k_stage_spec<false, 1>;
+    return a.da_mode ? (void *)k_stage<true, 1> : (void *)k_stage<false, 1>;
+  }
+  if (a.D > 0) return a.da_mode ? (void *)k_stage_spec<true, 0> : (void *)k_stage_spec<false, 0>;
+  return a.da_mode ? (void *)k_stage<true, 0> : (void *)k_stage<false, 0>;
 }
 
 void free_pipe_graph(vcsgc_ctx *c) {
@@ -2011,9 +2027,11 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.u_j = c->u_j;
   a.u_rho = c->u_rho;
   a.u_v = c->u_v;
+  const bool tab = a.p.tab != 0;
   void *f_trial = a.da_mode ? (void *)k_trial_da
-                            : (a.K > 1 ? (void *)k_trial_chain : (void *)k_trial);
-  void *f_commit = a.K > 1 ? (void *)k_commit_chain : (void *)k_commit;
+                  : a.K > 1 ? (tab ? (void *)k_trial_chain<1> : (void *)k_trial_chain<0>)
+                            : (tab ? (void *)k_trial<1> : (void *)k_trial<0>);
+  void *f_commit = a.K > 1 ? (void *)k_commit_chain : (tab ? (void *)k_commit<1> : (void *)k_commit<0>);
   const int gb = grid_for(a.ncpc * TL);
   a.nblk = gb;
   k_init<<<1, BLOCK, 0, c->stream>>>(c->ds);
@@ -2059,20 +2077,17 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
     k_sites<<<grid_for(a.S * a.ncpc), BLOCK, 0, c->stream>>>(a, w);
     for (int64_t s = 0; s < a.S; ++s, ++q) {
       const int par = (int)(q & 1);
+      int last = s == a.S - 1;
+      void *ta[] = {&a, (void *)&w, &s, (void *)&par};
+      void *ca[] = {&a, (void *)&w, &s, (void *)&par, &last};
       int h = tstart(c, VCSGC_KT_TRIAL);
-      if (a.da_mode)
-        k_trial_da<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
-      else if (a.K > 1)
-        k_trial_chain<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
-      else
-        k_trial<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par);
+      hipError_t e = hipLaunchKernel(f_trial, dim3(gb), dim3(BLOCK), ta, 0, c->stream);
       tstop(c, h);
+      if (e != hipSuccess) return e;
       h = tstart(c, VCSGC_KT_COMMIT);
-      if (a.K > 1)
-        k_commit_chain<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par, s == a.S - 1);
-      else
-        k_commit<<<gb, BLOCK, 0, c->stream>>>(a, w, s, par, s == a.S - 1);
+      e = hipLaunchKernel(f_commit, dim3(gb), dim3(BLOCK), ca, 0, c->stream);
       tstop(c, h);
+      if (e != hipSuccess) return e;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -1,5 +1,6 @@
-"""Pins of the oracle's tabulated EAM (a general two-species EAM given by
-tables, Sec. II; the paper's own Fe-Cu potentials come in this form).
+"""Pins of the oracle's tabulated EAM (a general two-species embedded-atom
+potential given by tables: the class of short-range potentials named in the
+Introduction and Sec. III, the class of the Fe-Cu potentials of Sec. IV.B).
 
 The interpolant is checked against what it must reproduce by construction:
 the knot values, exact quadratics (central-difference slopes are exact for
