@@ -1442,6 +1442,195 @@ int or_md_nvt(int64_t n, double *x, double *y, double *z, double *vx, double *vy
 }
 
 /* ------------------------------------------------------------------------ */
+/* Conjugate-gradient relaxation of the positions at fixed species and box   */
+/* (Sec. IV.B relaxes the nanocrystal's grain boundaries by conjugate-       */
+/* gradient minimization before its MD and MC/MD runs; the variant is not    */
+/* given there).  Nonlinear conjugate gradients with the Polak-Ribiere        */
+/* coefficient clipped at zero (PR+) and a backtracking line search under    */
+/* the sufficient-decrease (Armijo) condition, as in Nocedal and Wright,     */
+/* Numerical Optimization (2nd ed.), Sec. 3.1 (backtracking) and Sec. 5.2    */
+/* (PR+).  The steps, in order:                                               */
+/*   E, F at x;  d = F;  gg = F.F                                             */
+/*   loop:                                                                     */
+/*     sqrt(gg) <= ftol: FORCE;  it >= max_iter: ITER;  ev >= max_eval: EVAL  */
+/*     sl = F.d;  sl <= 0: d = F, sl = F.d (restart along the force)          */
+/*     dm = sqrt(max_i |d_i|^2);  a = dmax / dm, after the first iteration    */
+/*       the smaller of that and 2 dE_prev / sl (the minimizer of the        */
+/*       quadratic through the last decrease, Nocedal and Wright, Sec. 3.5)  */
+/*     up to CG_TRIALS trials: x' = wrap(x + a d) per component, E' and F'   */
+/*       at x' (ev += 1); E' <= E - c1 a sl and E' < E: accepted (the      */
+/*       second test matters only once c1 a sl is below the rounding of E); */
+/*       else a = a / 2                                                       */
+/*     none accepted: LINESEARCH (x, E, F unchanged)                           */
+/*     b = (F'.F' - F'.F) / gg, clipped at 0;  d = F' + b d                    */
+/*     dE = E - E';  x, E, F, gg = x', E', F', F'.F';  it += 1                 */
+/*     dE <= etol |E|: ENERGY                                                   */
+/* E = or_tree_sum of the atoms' energies; each dot product is or_tree_sum   */
+/* of the per-atom terms (ax bx + ay by) + az bz.                             */
+/* ------------------------------------------------------------------------ */
+#define CG_TRIALS 41
+#define CG_C1 1e-4
+
+/* energy (returned through *e_tot), forces and densities at x */
+static int or_eval_energy_forces(int64_t n, const double *x, const double *y, const double *z,
+                                 const uint8_t *species, const double box[3], const or_pot *p,
+                                 double *fx, double *fy, double *fz, double *rho, double *e,
+                                 double *e_tot) {
+  int64_t cap = 32 * n + 64;
+  for (;;) {
+    int64_t *start = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *nj = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
+    double *nr = (double *)malloc((size_t)cap * sizeof(double));
+    double *dx = (double *)malloc((size_t)cap * sizeof(double));
+    double *dy = (double *)malloc((size_t)cap * sizeof(double));
+    double *dz = (double *)malloc((size_t)cap * sizeof(double));
+    int64_t tot = or_neighbors(n, x, y, z, box, p->rc, 0, cap, start, nj, nr, dx, dy, dz);
+    int ok = tot >= 0 && tot <= cap;
+    if (ok) {
+      or_density(n, start, nj, nr, species, p, rho);
+      or_energy_atoms(n, start, nj, nr, species, p, rho, e);
+      or_forces(n, start, nj, nr, dx, dy, dz, species, p, rho, fx, fy, fz);
+      *e_tot = or_tree_sum(n, e);
+    }
+    free(start); free(nj); free(nr); free(dx); free(dy); free(dz);
+    if (tot < 0) return -1;
+    if (ok) return 0;
+    cap = tot;
+  }
+}
+
+/* or_tree_sum of (ax bx + ay by) + az bz over the atoms */
+static double or_dot3(int64_t n, const double *ax, const double *ay, const double *az,
+                      const double *bx, const double *by, const double *bz, double *work) {
+  for (int64_t i = 0; i < n; ++i) work[i] = (ax[i] * bx[i] + ay[i] * by[i]) + az[i] * bz[i];
+  return or_tree_sum(n, work);
+}
+
+int or_cg(int64_t n, double *x, double *y, double *z, const uint8_t *species,
+          const double box[3], const or_pot *p, int64_t max_iter, int64_t max_eval, double etol,
+          double ftol, double dmax, int steepest, double *fx, double *fy, double *fz,
+          double *rho, int64_t *iters_out, int64_t *evals_out, double *e_out, double *fnorm_out,
+          int *reason_out, double *log, int64_t log_cap) {
+  size_t nb = (size_t)n * sizeof(double);
+  double *buf = (double *)malloc(12 * nb);
+  if (!buf) return -1;
+  double *dx = buf, *dy = buf + n, *dz = buf + 2 * n;
+  double *xt = buf + 3 * n, *yt = buf + 4 * n, *zt = buf + 5 * n;
+  double *gx = buf + 6 * n, *gy = buf + 7 * n, *gz = buf + 8 * n;
+  double *e = buf + 9 * n, *work = buf + 10 * n, *rt = buf + 11 * n;
+  double E = 0.0;
+  int rc = -1;
+  if (or_eval_energy_forces(n, x, y, z, species, box, p, fx, fy, fz, rho, e, &E)) goto out;
+  for (int64_t i = 0; i < n; ++i) {
+    dx[i] = fx[i];
+    dy[i] = fy[i];
+    dz[i] = fz[i];
+  }
+  double gg = or_dot3(n, fx, fy, fz, fx, fy, fz, work);
+  int64_t it = 0, ev = 0;
+  int reason;
+  double dE_prev = 0.0;
+  for (;;) {
+    if (sqrt(gg) <= ftol) {
+      reason = OR_CG_FORCE;
+      break;
+    }
+    if (it >= max_iter) {
+      reason = OR_CG_ITER;
+      break;
+    }
+    if (ev >= max_eval) {
+      reason = OR_CG_EVAL;
+      break;
+    }
+    double sl = or_dot3(n, fx, fy, fz, dx, dy, dz, work);
+    int restart = 0;
+    if (!(sl > 0.0)) {
+      for (int64_t i = 0; i < n; ++i) {
+        dx[i] = fx[i];
+        dy[i] = fy[i];
+        dz[i] = fz[i];
+      }
+      sl = or_dot3(n, fx, fy, fz, dx, dy, dz, work);
+      restart = 1;
+    }
+    double dm2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double q = (dx[i] * dx[i] + dy[i] * dy[i]) + dz[i] * dz[i];
+      if (q > dm2) dm2 = q;
+    }
+    double a = dmax / sqrt(dm2);
+    if (it > 0) {
+      double a1 = 2.0 * dE_prev / sl;
+      if (a1 < a) a = a1;
+    }
+    double Et = 0.0;
+    int accepted = 0;
+    for (int t = 0; t < CG_TRIALS; ++t) {
+      for (int64_t i = 0; i < n; ++i) {
+        xt[i] = or_wrap(x[i] + a * dx[i], box[0]);
+        yt[i] = or_wrap(y[i] + a * dy[i], box[1]);
+        zt[i] = or_wrap(z[i] + a * dz[i], box[2]);
+      }
+      if (or_eval_energy_forces(n, xt, yt, zt, species, box, p, gx, gy, gz, rt, e, &Et)) goto out;
+      ev += 1;
+      if (Et <= E - CG_C1 * a * sl && Et < E) {
+        accepted = 1;
+        break;
+      }
+      a = a * 0.5;
+    }
+    if (!accepted) {
+      reason = OR_CG_LINESEARCH;
+      break;
+    }
+    double g_new = or_dot3(n, gx, gy, gz, gx, gy, gz, work);
+    double g_mix = or_dot3(n, gx, gy, gz, fx, fy, fz, work);
+    double b = (g_new - g_mix) / gg;
+    if (!(b > 0.0) || steepest) b = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      dx[i] = gx[i] + b * dx[i];
+      dy[i] = gy[i] + b * dy[i];
+      dz[i] = gz[i] + b * dz[i];
+    }
+    double dE = E - Et;
+    dE_prev = dE;
+    if (log && it < log_cap) {
+      double *L = log + 6 * it;
+      L[0] = E;
+      L[1] = Et;
+      L[2] = a;
+      L[3] = sl;
+      L[4] = b;
+      L[5] = (double)restart;
+    }
+    memcpy(x, xt, nb);
+    memcpy(y, yt, nb);
+    memcpy(z, zt, nb);
+    memcpy(fx, gx, nb);
+    memcpy(fy, gy, nb);
+    memcpy(fz, gz, nb);
+    memcpy(rho, rt, nb);
+    E = Et;
+    gg = g_new;
+    it += 1;
+    if (dE <= etol * fabs(E)) {
+      reason = OR_CG_ENERGY;
+      break;
+    }
+  }
+  *iters_out = it;
+  *evals_out = ev;
+  *e_out = E;
+  *fnorm_out = sqrt(gg);
+  *reason_out = reason;
+  rc = 0;
+out:
+  free(buf);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* All-core CPU baseline of or_md: the same per-atom arithmetic (neighbour   */
 /* rows, densities, forces, kicks) with the atoms split over n_threads       */
 /* OpenMP threads.  Rows are built twice (count, then fill at the row's      */

@@ -233,6 +233,19 @@ int or_md_nvt(int64_t n, double *x, double *y, double *z, double *vx, double *vy
               double mass_b, double dt, int64_t n_steps, double temp, double tau, double *xi_io,
               double *eta_io, double *fx, double *fy, double *fz, double *rho);
 
+/* Conjugate-gradient relaxation (PR+ nonlinear CG with a backtracking
+ * Armijo line search; the steps are listed above or_cg in oracle.c).  x, y,
+ * z are relaxed in place; fx, fy, fz and rho are those at the final
+ * positions.  steepest != 0 forces b = 0 (steepest descent, for tests).
+ * log (may be NULL) receives per iteration (E, E', a, sl, b, restart).
+ * Stop reasons: */
+enum { OR_CG_FORCE = 1, OR_CG_ENERGY = 2, OR_CG_ITER = 3, OR_CG_EVAL = 4, OR_CG_LINESEARCH = 5 };
+int or_cg(int64_t n, double *x, double *y, double *z, const uint8_t *species,
+          const double box[3], const or_pot *p, int64_t max_iter, int64_t max_eval, double etol,
+          double ftol, double dmax, int steepest, double *fx, double *fy, double *fz,
+          double *rho, int64_t *iters_out, int64_t *evals_out, double *e_out, double *fnorm_out,
+          int *reason_out, double *log, int64_t log_cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -129,6 +129,10 @@ def lib():
         L.or_md_nvt.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
                                 C.c_double, C.c_double, C.c_int64, C.c_double, C.c_double,
                                 _P, _P, _P, _P, _P, _P]
+        L.or_cg.restype = C.c_int
+        L.or_cg.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, C.c_int64, C.c_int64,
+                            C.c_double, C.c_double, C.c_double, C.c_int, _P, _P, _P, _P, _P,
+                            _P, _P, _P, _P, _P, C.c_int64]
         _lib = L
     return _lib
 
@@ -415,6 +419,35 @@ def md_nvt(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, T, tau, xi=0.0, 
     if rc != 0:
         raise ValueError("or_md_nvt failed")
     return (x, y, z, vx, vy, vz, fx, fy, fz, rho), (float(th[0]), float(th[1]))
+
+
+CG_REASONS = {1: "force", 2: "energy", 3: "iterations", 4: "evaluations", 5: "line search"}
+
+
+def cg(x, y, z, species, box, pot, max_iter=1000, max_eval=100000, etol=0.0, ftol=1e-6,
+       dmax=0.1, steepest=False, log_cap=0):
+    """Conjugate-gradient relaxation (PR+ with a backtracking Armijo line
+    search) at fixed species and box.  Returns (x, y, z, fx, fy, fz, rho),
+    a dict (iterations, evaluations, energy, fnorm, reason) and the
+    per-iteration log rows (E, E', a, sl, b, restart)."""
+    x, y, z = _f64(x).copy(), _f64(y).copy(), _f64(z).copy()
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    n = x.size
+    fx, fy, fz, rho = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    it, ev = np.zeros(1, np.int64), np.zeros(1, np.int64)
+    e, fn = np.zeros(1), np.zeros(1)
+    reason = np.zeros(1, np.int32)
+    log = np.zeros((max(log_cap, 1), 6))
+    P = pot_struct(pot)
+    rc = lib().or_cg(n, _p(x), _p(y), _p(z), _p(sp), _p(_f64(box)), C.byref(P), int(max_iter),
+                     int(max_eval), float(etol), float(ftol), float(dmax), int(bool(steepest)),
+                     _p(fx), _p(fy), _p(fz), _p(rho), _p(it), _p(ev), _p(e), _p(fn),
+                     _p(reason), _p(log) if log_cap > 0 else None, int(log_cap))
+    if rc != 0:
+        raise ValueError("or_cg failed")
+    info = dict(iterations=int(it[0]), evaluations=int(ev[0]), energy=float(e[0]),
+                fnorm=float(fn[0]), reason=int(reason[0]))
+    return (x, y, z, fx, fy, fz, rho), info, log[:min(info["iterations"], log_cap)]
 
 
 # ---------------------------------------------------------------------------

@@ -73,12 +73,20 @@ MUTATIONS = [
     ("tabulated pair function of the wrong species pair",
      "if (p->tab) return or_spline_eval(p->cphi[a + b], p->nr, r, p->inv_dr, NULL);",
      "if (p->tab) return or_spline_eval(p->cphi[a], p->nr, r, p->inv_dr, NULL);"),
+    ("relaxation step against the direction", "xt[i] = or_wrap(x[i] + a * dx[i], box[0]);",
+     "xt[i] = or_wrap(x[i] - a * dx[i], box[0]);"),
+    ("decrease test with the wrong sign", "if (Et <= E - CG_C1 * a * sl && Et < E) {",
+     "if (Et <= E + CG_C1 * a * sl) {"),
+    ("Polak-Ribiere terms swapped", "double b = (g_new - g_mix) / gg;",
+     "double b = (g_mix - g_new) / gg;"),
+    ("direction update keeps the old force", "dx[i] = gx[i] + b * dx[i];",
+     "dx[i] = fx[i] + b * dx[i];"),
 ]
 
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_eam.py",
          "tests/test_oracle_ensemble.py", "tests/test_oracle_md.py",
          "tests/test_oracle_surrogate.py", "tests/test_oracle_localchain.py",
-         "tests/test_oracle_nvt.py", "tests/test_oracle_table.py"]
+         "tests/test_oracle_nvt.py", "tests/test_oracle_table.py", "tests/test_oracle_cg.py"]
 
 
 def main():
