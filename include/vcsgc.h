@@ -256,6 +256,54 @@ vcsgc_status eam_energy_forces(vcsgc_ctx *ctx, double *energy_eV, int want_force
  * next sweep. */
 vcsgc_status md_verlet_step(vcsgc_ctx *ctx, double dt_fs, int64_t n_steps);
 
+/* Conjugate-gradient relaxation of the positions at fixed species and box
+ * (Sec. IV.B relaxes the nanocrystal's grain boundaries by conjugate-gradient
+ * minimization before its MD and MC/MD runs).  Nonlinear conjugate gradients
+ * with the Polak-Ribiere coefficient clipped at zero and a backtracking
+ * line search under the sufficient-decrease condition (Nocedal and Wright,
+ * Numerical Optimization, Secs. 3.1, 3.5 and 5.2):
+ *   E, F at x;  d = F;  gg = F.F;  then per iteration:
+ *     stop if sqrt(gg) <= ftol (FORCE), iterations == max_iter (ITER) or
+ *       evaluations >= max_eval (EVAL), in that order;
+ *     sl = F.d, and if sl <= 0: d = F, sl = F.d (restart);
+ *     a = dmax / max_i |d_i|, after the first iteration at most
+ *       2 dE_prev / sl (dE_prev the last iteration's decrease);
+ *     up to VCSGC_CG_TRIALS trials x' = wrap(x + a d), E' and F' at x',
+ *       accepted when E' <= E - VCSGC_CG_C1 a sl and E' < E, else a /= 2;
+ *       none accepted: stop (LINESEARCH) with x, E and F unchanged;
+ *     b = max(0, (F'.F' - F'.F) / gg);  d = F' + b d;
+ *     dE = E - E';  x, E, F, gg = x', E', F', F'.F';
+ *     stop if dE <= etol |E| (ENERGY).
+ * E is summed over the atoms' energies, and each dot product over the
+ * per-atom terms (a_x b_x + a_y b_y) + a_z b_z, in the fixed shape of
+ * eam_energy_forces.  sys.x/y/z are relaxed in place and sys.fx/fy/fz
+ * (required) hold the forces at the final positions; velocities and species
+ * are untouched.  The MD list is rebuilt as in md_verlet_step; the sweep's
+ * lists are rebuilt before the next sweep.  res (host, may be NULL)
+ * receives the counts, the final energy and |F|.  Single-system contexts.
+ * Errors: VCSGC_E_INVALID_ARG (no force arrays, max_iter or max_eval < 0,
+ * non-finite etol, ftol < 0, dmax outside (0, half the shortest box
+ * edge)). */
+#define VCSGC_CG_TRIALS 41
+#define VCSGC_CG_C1 1e-4
+enum { VCSGC_CG_FORCE = 1, VCSGC_CG_ENERGY = 2, VCSGC_CG_ITER = 3, VCSGC_CG_EVAL = 4,
+       VCSGC_CG_LINESEARCH = 5 };
+typedef struct {
+  int64_t max_iter;  /* line searches */
+  int64_t max_eval;  /* energy evaluations (checked before each line search) */
+  double etol;       /* relative energy decrease that ends the run */
+  double ftol;       /* |F| (2-norm of the 3N-vector, eV/A) that ends the run */
+  double dmax;       /* largest single-atom move of a line search's first trial (A) */
+} vcsgc_cg_params;
+typedef struct {
+  int64_t iterations, evaluations;
+  double energy;  /* eV, at the final positions */
+  double fnorm;   /* eV/A */
+  int32_t reason; /* VCSGC_CG_* */
+} vcsgc_cg_result;
+vcsgc_status vcsgc_minimize(vcsgc_ctx *ctx, const vcsgc_cg_params *params,
+                            vcsgc_cg_result *res);
+
 /* Nose-Hoover thermostat for later md_verlet_step calls (the paper's Fe-Cu
  * runs thermostat their MD, Sec. IV.B).  T_K > 0 switches it on: equations
  * of motion dx/dt = v, dv/dt = F/m - xi v, dxi/dt = (2K - g kB T)/Q,

@@ -88,6 +88,16 @@ KT_NAMES = ["trial", "commit", "density", "forces", "kick_drift", "kick", "build
 STRATEGIES = {"graph": 0, "persistent": 1, "stage": 2, "batch": 3}
 
 
+class CgParams(C.Structure):
+    _fields_ = [("max_iter", C.c_int64), ("max_eval", C.c_int64), ("etol", C.c_double),
+                ("ftol", C.c_double), ("dmax", C.c_double)]
+
+
+class CgResult(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("evaluations", C.c_int64), ("energy", C.c_double),
+                ("fnorm", C.c_double), ("reason", C.c_int32)]
+
+
 class KTimes(C.Structure):
     _fields_ = [("total_ms", C.c_double * len(KT_NAMES)), ("count", C.c_int64 * len(KT_NAMES)),
                 ("launches", C.c_int64 * len(KT_NAMES))]
@@ -190,6 +200,8 @@ def lib():
         L.vcsgc_selftest_sqrt.argtypes = [_P, _P, C.c_int64, _P]
         L.vcsgc_selftest_md_math.restype = st
         L.vcsgc_selftest_md_math.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
+        L.vcsgc_minimize.restype = st
+        L.vcsgc_minimize.argtypes = [_P, C.POINTER(CgParams), C.POINTER(CgResult)]
         _lib = L
     return _lib
 
@@ -344,6 +356,15 @@ class VCSGC:
 
     def md(self, dt, n_steps):
         self._check(lib().md_verlet_step(self._h, float(dt), int(n_steps)), "md")
+
+    def minimize(self, max_iter=1000, max_eval=100000, etol=0.0, ftol=1e-6, dmax=0.1):
+        """Conjugate-gradient relaxation of the positions (vcsgc_minimize);
+        returns dict(iterations, evaluations, energy, fnorm, reason)."""
+        p = CgParams(int(max_iter), int(max_eval), float(etol), float(ftol), float(dmax))
+        r = CgResult()
+        self._check(lib().vcsgc_minimize(self._h, C.byref(p), C.byref(r)), "minimize")
+        return dict(iterations=r.iterations, evaluations=r.evaluations, energy=r.energy,
+                    fnorm=r.fnorm, reason=r.reason)
 
     def set_thermostat(self, T, tau, xi=0.0, eta=0.0):
         """Nose-Hoover NVT for later md() calls (T = 0: NVE)."""

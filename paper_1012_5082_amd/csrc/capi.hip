@@ -32,7 +32,7 @@ void free_all(vcsgc_ctx *c) {
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
                   c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnu2,     c->m_lnug,   c->m_rec,
                   c->m_part,     c->s_rec,      c->s_part,     c->nvt,        c->nvt_part,
-                  c->tab_coef};
+                  c->tab_coef,   c->cg};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -1002,6 +1002,51 @@ vcsgc_status md_nvt_steps(vcsgc_ctx *c, double dt_fs, int64_t n_steps, bool dev)
   return md_nvt_steps(c, dt_fs, n_steps, false);
 }
 
+// Energy (fixed-shape total into *e) and forces at the current positions:
+// the MD list is rebuilt first when the last move raised ds->rebuild[0].
+vcsgc_status cg_eval(vcsgc_ctx *c, bool check_list, double *e) {
+  if (check_list) {
+    int flag = 0;
+    VC_CHECK(c, hipMemcpyAsync(&flag, &c->ds->rebuild[0], sizeof(int), hipMemcpyDeviceToHost,
+                               c->stream),
+             "copy");
+    VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+    if (flag) {
+      VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild[0], 0, sizeof(int), c->stream), "reset");
+      vcsgc_status st = refresh_md(c);
+      if (st) return st;
+    }
+  }
+  VC_CHECK(c, vc::launch_energy(c), "energy");
+  VC_CHECK(c, vc::launch_forces(c), "forces");
+  double *out = c->red + (c->n + vc::BLOCK - 1) / vc::BLOCK + 1;
+  VC_CHECK(c, vc::launch_reduce_sum(c, c->eatom, c->n, out), "reduce");
+  VC_CHECK(c, hipMemcpyAsync(e, out, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  return VCSGC_OK;
+}
+
+// the two totals of mode 0 or 1 (launch_cg_totals) on the host
+vcsgc_status cg_totals(vcsgc_ctx *c, int mode, const double *u, double out[2]) {
+  const int64_t nch = (c->n + vc::BLOCK - 1) / vc::BLOCK;
+  double *part = c->cg + 9 * c->n, *dev_out = part + 2 * nch;
+  VC_CHECK(c, vc::launch_cg_totals(c, mode, u, part, dev_out), "relaxation");
+  VC_CHECK(c, hipMemcpyAsync(out, dev_out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+           "copy");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  return VCSGC_OK;
+}
+
+// three device vectors of n doubles into one of 3 n
+vcsgc_status cg_gather3(vcsgc_ctx *c, double *dst, double *a, double *b, double *d) {
+  const size_t nb = sizeof(double) * (size_t)c->n;
+  double *src[3] = {a, b, d};
+  for (int k = 0; k < 3; ++k)
+    VC_CHECK(c, hipMemcpyAsync(dst + k * c->n, src[k], nb, hipMemcpyDeviceToDevice, c->stream),
+             "copy");
+  return VCSGC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1031,6 +1076,114 @@ vcsgc_status vcsgc_get_thermostat(vcsgc_ctx *c, double *xi, double *eta) {
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   if (xi) *xi = h[0];
   if (eta) *eta = h[1];
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_minimize(vcsgc_ctx *c, const vcsgc_cg_params *prm, vcsgc_cg_result *res) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (c->reps.size() != 1) return fail(c, VCSGC_E_INVALID_ARG, "not available on a batch context");
+  if (!prm || !c->fx)
+    return fail(c, VCSGC_E_INVALID_ARG, "relaxation needs parameters and force arrays");
+  const double lmin = std::min({c->box[0], c->box[1], c->box[2]});
+  if (prm->max_iter < 0 || prm->max_eval < 0 || !is_fin(prm->etol) || !is_fin(prm->ftol) ||
+      prm->ftol < 0.0 || !is_fin(prm->dmax) || !(prm->dmax > 0.0) || !(prm->dmax < 0.5 * lmin))
+    return fail(c, VCSGC_E_INVALID_ARG,
+                "need max_iter, max_eval >= 0, finite etol, ftol >= 0, 0 < dmax < L/2");
+  const int64_t n = c->n;
+  if (!c->cg) VC_CHECK(c, dalloc(&c->cg, 9 * (size_t)n + 2 * (size_t)((n + vc::BLOCK - 1) / vc::BLOCK) + 8),
+                       "allocation");
+  double *d = c->cg, *x0 = c->cg + 3 * n, *f0 = c->cg + 6 * n;
+  c->rho_f_fresh = false;
+  if (!c->md_valid) {
+    st = refresh_md(c);
+    if (st) return st;
+  }
+  VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild[0], 0, sizeof(int), c->stream), "reset");
+  VC_CHECK(c, vc::launch_pack(c), "pack");
+  double E = 0.0;
+  st = cg_eval(c, false, &E);
+  if (st) return st;
+  VC_CHECK(c, vc::launch_cg_dir(c, d, 0.0, true), "relaxation");
+  double t[2];
+  st = cg_totals(c, 1, d, t);
+  if (st) return st;
+  double gg = t[0], dE_prev = 0.0;
+  int64_t it = 0, ev = 0;
+  int32_t reason = 0;
+  bool moved = false;
+  for (;;) {
+    if (std::sqrt(gg) <= prm->ftol) {
+      reason = VCSGC_CG_FORCE;
+      break;
+    }
+    if (it >= prm->max_iter) {
+      reason = VCSGC_CG_ITER;
+      break;
+    }
+    if (ev >= prm->max_eval) {
+      reason = VCSGC_CG_EVAL;
+      break;
+    }
+    if ((st = cg_totals(c, 0, d, t))) return st;
+    double sl = t[0], dm2 = t[1];
+    if (!(sl > 0.0)) {  // not a descent direction: restart along the force
+      VC_CHECK(c, vc::launch_cg_dir(c, d, 0.0, true), "relaxation");
+      if ((st = cg_totals(c, 0, d, t))) return st;
+      sl = t[0];
+      dm2 = t[1];
+    }
+    double a = prm->dmax / std::sqrt(dm2);
+    if (it > 0) {
+      const double a1 = 2.0 * dE_prev / sl;
+      if (a1 < a) a = a1;
+    }
+    if ((st = cg_gather3(c, x0, c->x, c->y, c->z))) return st;
+    if ((st = cg_gather3(c, f0, c->fx, c->fy, c->fz))) return st;
+    double Et = 0.0;
+    bool accepted = false;
+    for (int k = 0; k < VCSGC_CG_TRIALS; ++k) {
+      VC_CHECK(c, vc::launch_cg_move(c, x0, d, a), "relaxation");
+      moved = true;
+      if ((st = cg_eval(c, true, &Et))) return st;
+      ev += 1;
+      if (Et <= E - VCSGC_CG_C1 * a * sl && Et < E) {
+        accepted = true;
+        break;
+      }
+      a = a * 0.5;
+    }
+    if (!accepted) {  // back to the line search's start (forces recomputed there)
+      VC_CHECK(c, vc::launch_cg_move(c, x0, d, 0.0), "relaxation");
+      double e_back = 0.0;
+      if ((st = cg_eval(c, true, &e_back))) return st;
+      reason = VCSGC_CG_LINESEARCH;
+      break;
+    }
+    if ((st = cg_totals(c, 1, f0, t))) return st;
+    const double g_new = t[0], g_mix = t[1];
+    double b = (g_new - g_mix) / gg;
+    if (!(b > 0.0)) b = 0.0;
+    VC_CHECK(c, vc::launch_cg_dir(c, d, b, false), "relaxation");
+    const double dE = E - Et;
+    dE_prev = dE;
+    E = Et;
+    gg = g_new;
+    it += 1;
+    if (dE <= prm->etol * std::fabs(E)) {
+      reason = VCSGC_CG_ENERGY;
+      break;
+    }
+  }
+  if (moved) c->mc_valid = false;
+  c->rho_f_fresh = true;  // the last evaluation ran at the final positions
+  if (res) {
+    res->iterations = it;
+    res->evaluations = ev;
+    res->energy = E;
+    res->fnorm = std::sqrt(gg);
+    res->reason = reason;
+  }
   return VCSGC_OK;
 }
 

@@ -449,6 +449,9 @@ struct vcsgc_ctx {
   double nvt_T = 0.0, nvt_tau = 0.0;
   double *nvt = nullptr, *nvt_part = nullptr;
   double *tab_coef = nullptr;  // tabulated potential's coefficients (PotD::tc)
+  // conjugate-gradient relaxation: direction d, start positions x0 and
+  // forces f0 of the line search (3 n each), chunk values, totals
+  double *cg = nullptr;
 
   // search bins for neighbour lists: edge >= rc + skin, fixed capacity per bin
   int nb[3] = {0, 0, 0};
@@ -610,6 +613,12 @@ hipError_t launch_nvt_ke(vcsgc_ctx *c, double dt, bool closing_kick);
 hipError_t launch_nvt_thermo(vcsgc_ctx *c, double dt, int mode);  // bit 0: end half, 1: start half
 hipError_t launch_nvt_kick_drift(vcsgc_ctx *c, double dt, int par);
 hipError_t launch_nvt_scale(vcsgc_ctx *c);
+// conjugate-gradient relaxation: trial positions x = wrap(x0 + a d); the
+// totals (mode 0: F . u and max |u_i|^2; mode 1: F . F and F . u) into
+// out[0..1] through part [2 ceil(n / BLOCK)]; d = F or d = F + b d
+hipError_t launch_cg_move(vcsgc_ctx *c, const double *x0, const double *d, double a);
+hipError_t launch_cg_totals(vcsgc_ctx *c, int mode, const double *u, double *part, double *out);
+hipError_t launch_cg_dir(vcsgc_ctx *c, double *d, double b, bool copy);
 hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
 hipError_t launch_md_math(const double *a, const double *b, double *sq, double *q, int64_t n,
                           hipStream_t s);

@@ -522,4 +522,149 @@ hipError_t launch_nvt_scale(vcsgc_ctx *c) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Conjugate-gradient relaxation: the per-atom work of the minimizer driven
+// from the host (trial positions, the fixed-shape totals that steer it, the
+// direction update).  Vectors of 3n doubles hold the x, y and z components
+// one after the other.  Totals are taken in the fixed shape of the energy
+// reduction: chunks of BLOCK atoms by halving strides, chunk c into
+// accumulator c mod BLOCK, the accumulators by halving strides.
+// ---------------------------------------------------------------------------
+// x = wrap(x0 + a d) per component, ps4 packed alongside; raises
+// ds->rebuild[0] when an atom is more than skin/2 from its position at the
+// last MD-list build
+__global__ void __launch_bounds__(BLOCK)
+    k_cg_move(int64_t n, const double *__restrict__ x0, const double *__restrict__ d, double a,
+              double *x, double *y, double *z, const uint8_t *__restrict__ sp, double4 *ps4,
+              const double *__restrict__ xr, const double *__restrict__ yr,
+              const double *__restrict__ zr, Box b, double half_skin2, DevState *ds) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  bool far = false;
+  if (i < n) {
+    const double nx = wrap_box(x0[i] + a * d[i], b.L0);
+    const double ny = wrap_box(x0[n + i] + a * d[n + i], b.L1);
+    const double nz = wrap_box(x0[2 * n + i] + a * d[2 * n + i], b.L2);
+    x[i] = nx;
+    y[i] = ny;
+    z[i] = nz;
+    ps4[i] = make_double4(nx, ny, nz, (double)sp[i]);
+    const double ex = min_image(nx - xr[i], b.L0);
+    const double ey = min_image(ny - yr[i], b.L1);
+    const double ez = min_image(nz - zr[i], b.L2);
+    far = (ex * ex + ey * ey) + ez * ez > half_skin2;
+  }
+  const unsigned long long moved = __ballot(far);
+  if (moved && __lane_id() == __ffsll((long long)moved) - 1) atomicOr(&ds->rebuild[0], 1);
+}
+
+// Chunk values of two totals, per-atom dot terms (a_x b_x + a_y b_y) + a_z b_z:
+// MODE 0: F . u and max_i |u_i|^2;  MODE 1: F . F and F . u.
+// part[c] and part[nch + c] for chunk c.
+template <int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_cg_part(int64_t n, const double *__restrict__ fx, const double *__restrict__ fy,
+              const double *__restrict__ fz, const double *__restrict__ u, double *part) {
+  __shared__ double s0[BLOCK], s1[BLOCK];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + t;
+  double a = 0.0, q = 0.0;
+  if (i < n) {
+    const double gx = fx[i], gy = fy[i], gz = fz[i];
+    const double ux = u[i], uy = u[n + i], uz = u[2 * n + i];
+    if (MODE == 0) {
+      a = (gx * ux + gy * uy) + gz * uz;
+      q = (ux * ux + uy * uy) + uz * uz;
+    } else {
+      a = (gx * gx + gy * gy) + gz * gz;
+      q = (gx * ux + gy * uy) + gz * uz;
+    }
+  }
+  s0[t] = a;
+  s1[t] = q;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      s0[t] = s0[t] + s0[t + h];
+      s1[t] = MODE == 0 ? fmax(s1[t], s1[t + h]) : s1[t] + s1[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int64_t nch = gridDim.x;
+    part[blockIdx.x] = s0[0];
+    part[nch + blockIdx.x] = s1[0];
+  }
+}
+
+// the two totals from the chunk values (one block): out[0], out[1]
+template <int MODE>
+__global__ void __launch_bounds__(BLOCK)
+    k_cg_total(int64_t nch, const double *__restrict__ part, double *out) {
+  __shared__ double s0[BLOCK], s1[BLOCK];
+  const int t = threadIdx.x;
+  double a = 0.0, q = 0.0;
+  for (int64_t c = t; c < nch; c += BLOCK) {
+    a = a + part[c];
+    q = MODE == 0 ? fmax(q, part[nch + c]) : q + part[nch + c];
+  }
+  s0[t] = a;
+  s1[t] = q;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      s0[t] = s0[t] + s0[t + h];
+      s1[t] = MODE == 0 ? fmax(s1[t], s1[t + h]) : s1[t] + s1[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = s0[0];
+    out[1] = s1[0];
+  }
+}
+
+// d = F (copy) or d = F + b d
+__global__ void __launch_bounds__(BLOCK)
+    k_cg_dir(int64_t n, const double *__restrict__ fx, const double *__restrict__ fy,
+             const double *__restrict__ fz, double *d, double b, int copy) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  if (copy) {
+    d[i] = fx[i];
+    d[n + i] = fy[i];
+    d[2 * n + i] = fz[i];
+  } else {
+    d[i] = fx[i] + b * d[i];
+    d[n + i] = fy[i] + b * d[n + i];
+    d[2 * n + i] = fz[i] + b * d[2 * n + i];
+  }
+}
+
+hipError_t launch_cg_move(vcsgc_ctx *c, const double *x0, const double *d, double a) {
+  Box b{c->box[0], c->box[1], c->box[2]};
+  const double hs = 0.5 * c->skin;
+  k_cg_move<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, x0, d, a, c->x, c->y, c->z, c->sp,
+                                                     c->ps4, c->xr, c->yr, c->zr, b, hs * hs,
+                                                     c->ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_totals(vcsgc_ctx *c, int mode, const double *u, double *part, double *out) {
+  const int nch = grid_for(c->n);
+  if (mode == 0) {
+    k_cg_part<0><<<nch, BLOCK, 0, c->stream>>>(c->n, c->fx, c->fy, c->fz, u, part);
+    k_cg_total<0><<<1, BLOCK, 0, c->stream>>>(nch, part, out);
+  } else {
+    k_cg_part<1><<<nch, BLOCK, 0, c->stream>>>(c->n, c->fx, c->fy, c->fz, u, part);
+    k_cg_total<1><<<1, BLOCK, 0, c->stream>>>(nch, part, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_dir(vcsgc_ctx *c, double *d, double b, bool copy) {
+  k_cg_dir<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->fx, c->fy, c->fz, d, b,
+                                                    copy ? 1 : 0);
+  return hipGetLastError();
+}
+
 }  // namespace vc
