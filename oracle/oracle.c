@@ -1442,6 +1442,183 @@ int or_md_nvt(int64_t n, double *x, double *y, double *z, double *vx, double *vy
 }
 
 /* ------------------------------------------------------------------------ */
+/* Isotropic NPT: the Nose-Hoover thermostat and barostat of the paper's     */
+/* Fe-Cu runs (Sec. IV.B), in the form of Martyna, Tobias and Klein,        */
+/* J. Chem. Phys. 101, 4177 (1994), with one thermostat acting on the        */
+/* particles and on the barostat:                                             */
+/*   dx/dt = v + ve x,  dv/dt = F/m - (1 + 3/g) ve v - xi v,  dL/dt = ve L    */
+/*   dpe/dt = 3V (P - P_ext) + (3/g) 2K - xi pe,   ve = pe / W                */
+/*   dxi/dt = (2K + pe^2/W - (g + 1) kB T) / Q,    deta/dt = xi               */
+/* with g = 3N - 3, Q = (g + 1) kB T tau_T^2, W = (g + 1) kB T tau_P^2, the   */
+/* pressure P = (2K + Vir) / (3V) and the virial Vir = -1/2 sum_i w_i,        */
+/* w_i = sum_j s_ij r_ij (s_ij the pair factor of F_i, r < rc).  Conserved:   */
+/*   H = K + U + pe^2/(2W) + P_ext V + Q xi^2/2 + (g + 1) kB T eta.           */
+/* A step of dt (h = dt/2) is the symmetric splitting                         */
+/*   T(h) B(h) V(h) X(dt) [forces] V(h) B(h) T(h):                            */
+/*   T(h): xi += (h/2) G; s = (1 - xi h/2)/(1 + xi h/2); v *= s; pe *= s;     */
+/*         K *= s^2; eta += xi h; xi += (h/2) G (G from the updated K, pe)    */
+/*   B(h): pe += h (3V (P - P_ext) + (3/g) 2K)                                */
+/*   V(h): c = exp(-(1 + 3/g) ve h/2); v *= c; v += h a; v *= c               */
+/*   X(dt): q = exp(ve h); x *= q; x += dt v; x *= q; L *= q twice; wrap      */
+/* K is summed afresh (or_kinetic) at the start and after the second V(h),   */
+/* and carried through the thermostat's scalings otherwise; Vir is that of    */
+/* the last force evaluation.  Totals are or_tree_sum over the atoms.         */
+/* ------------------------------------------------------------------------ */
+static void or_virial(int64_t n, const int64_t *start, const int32_t *nj, const double *nr,
+                      const uint8_t *species, const or_pot *p, const double *rho, double *w) {
+  for (int64_t i = 0; i < n; ++i) {
+    double fpi = or_dembed(p, species[i], rho[i]);
+    int si = species[i];
+    double acc = 0.0;
+    for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+      double r = nr[e];
+      if (!(r < p->rc)) continue;
+      int32_t j = nj[e];
+      int sj = species[j];
+      double fpj = or_dembed(p, sj, rho[j]);
+      double s = or_dphi(p, si, sj, r) + fpi * or_df(p, sj, r) + fpj * or_df(p, si, r);
+      acc += s * r;
+    }
+    w[i] = acc;
+  }
+}
+
+/* forces, densities and the virial Vir = -1/2 sum_i w_i at x */
+static int or_eval_forces_virial(int64_t n, const double *x, const double *y, const double *z,
+                                 const uint8_t *species, const double box[3], const or_pot *p,
+                                 double *fx, double *fy, double *fz, double *rho, double *w,
+                                 double *vir) {
+  int64_t cap = 32 * n + 64;
+  for (;;) {
+    int64_t *start = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *nj = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
+    double *nr = (double *)malloc((size_t)cap * sizeof(double));
+    double *dx = (double *)malloc((size_t)cap * sizeof(double));
+    double *dy = (double *)malloc((size_t)cap * sizeof(double));
+    double *dz = (double *)malloc((size_t)cap * sizeof(double));
+    int64_t tot = or_neighbors(n, x, y, z, box, p->rc, 0, cap, start, nj, nr, dx, dy, dz);
+    int ok = tot >= 0 && tot <= cap;
+    if (ok) {
+      or_density(n, start, nj, nr, species, p, rho);
+      or_forces(n, start, nj, nr, dx, dy, dz, species, p, rho, fx, fy, fz);
+      or_virial(n, start, nj, nr, species, p, rho, w);
+      *vir = -0.5 * or_tree_sum(n, w);
+    }
+    free(start); free(nj); free(nr); free(dx); free(dy); free(dz);
+    if (tot < 0) return -1;
+    if (ok) return 0;
+    cap = tot;
+  }
+}
+
+/* the thermostat's half step T(h) with the barostat momentum; returns s */
+static double or_npt_thermo(double h, double g1kT, double Q, double W, double *K, double *pe,
+                            double *xi, double *eta) {
+  double q = 0.5 * h;
+  *xi = *xi + q * ((2.0 * *K + *pe * *pe / W - g1kT) / Q);
+  double a = *xi * q;
+  double s = (1.0 - a) / (1.0 + a);
+  *K = *K * s * s;
+  *pe = *pe * s;
+  *eta = *eta + *xi * h;
+  *xi = *xi + q * ((2.0 * *K + *pe * *pe / W - g1kT) / Q);
+  return s;
+}
+
+int or_md_npt(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+              const uint8_t *species, double box[3], const or_pot *p, double mass_a,
+              double mass_b, double dt, int64_t n_steps, double temp, double tau_t,
+              double p_ext, double tau_p, double *state, double *fx, double *fy, double *fz,
+              double *rho, double *vir_out) {
+  double cm[2] = {OR_ACC / mass_a, OR_ACC / mass_b};
+  double h = 0.5 * dt;
+  double g = 3.0 * (double)n - 3.0;
+  double g1kT = (g + 1.0) * (OR_KB * temp);
+  double Q = g1kT * tau_t * tau_t;
+  double W = g1kT * tau_p * tau_p;
+  double xi = state[0], eta = state[1], pe = state[2];
+  double *work = (double *)malloc((size_t)n * sizeof(double));
+  if (!work) return -1;
+  double vir = 0.0;
+  if (or_eval_forces_virial(n, x, y, z, species, box, p, fx, fy, fz, rho, work, &vir)) {
+    free(work);
+    return -1;
+  }
+  double K = or_kinetic(n, vx, vy, vz, species, mass_a, mass_b, work);
+  for (int64_t step = 0; step < n_steps; ++step) {
+    /* T(h) */
+    double s = or_npt_thermo(h, g1kT, Q, W, &K, &pe, &xi, &eta);
+    for (int64_t i = 0; i < n; ++i) {
+      vx[i] = vx[i] * s;
+      vy[i] = vy[i] * s;
+      vz[i] = vz[i] * s;
+    }
+    /* B(h) */
+    double V = box[0] * box[1] * box[2];
+    double P = (2.0 * K + vir) / (3.0 * V);
+    pe = pe + h * (3.0 * V * (P - p_ext) + (3.0 / g) * (2.0 * K));
+    /* V(h) X(dt) */
+    double ve = pe / W;
+    double c = exp(-(1.0 + 3.0 / g) * ve * (0.5 * h));
+    double q = exp(ve * h);
+    double L[3] = {box[0] * q * q, box[1] * q * q, box[2] * q * q};
+    for (int64_t i = 0; i < n; ++i) {
+      double k = cm[species[i]];
+      vx[i] = vx[i] * c;
+      vy[i] = vy[i] * c;
+      vz[i] = vz[i] * c;
+      vx[i] = vx[i] + h * (fx[i] * k);
+      vy[i] = vy[i] + h * (fy[i] * k);
+      vz[i] = vz[i] + h * (fz[i] * k);
+      vx[i] = vx[i] * c;
+      vy[i] = vy[i] * c;
+      vz[i] = vz[i] * c;
+      x[i] = or_wrap((x[i] * q + dt * vx[i]) * q, L[0]);
+      y[i] = or_wrap((y[i] * q + dt * vy[i]) * q, L[1]);
+      z[i] = or_wrap((z[i] * q + dt * vz[i]) * q, L[2]);
+    }
+    box[0] = L[0];
+    box[1] = L[1];
+    box[2] = L[2];
+    if (or_eval_forces_virial(n, x, y, z, species, box, p, fx, fy, fz, rho, work, &vir)) {
+      free(work);
+      return -1;
+    }
+    /* V(h) */
+    for (int64_t i = 0; i < n; ++i) {
+      double k = cm[species[i]];
+      vx[i] = vx[i] * c;
+      vy[i] = vy[i] * c;
+      vz[i] = vz[i] * c;
+      vx[i] = vx[i] + h * (fx[i] * k);
+      vy[i] = vy[i] + h * (fy[i] * k);
+      vz[i] = vz[i] + h * (fz[i] * k);
+      vx[i] = vx[i] * c;
+      vy[i] = vy[i] * c;
+      vz[i] = vz[i] * c;
+    }
+    K = or_kinetic(n, vx, vy, vz, species, mass_a, mass_b, work);
+    /* B(h) */
+    V = box[0] * box[1] * box[2];
+    P = (2.0 * K + vir) / (3.0 * V);
+    pe = pe + h * (3.0 * V * (P - p_ext) + (3.0 / g) * (2.0 * K));
+    /* T(h) */
+    s = or_npt_thermo(h, g1kT, Q, W, &K, &pe, &xi, &eta);
+    for (int64_t i = 0; i < n; ++i) {
+      vx[i] = vx[i] * s;
+      vy[i] = vy[i] * s;
+      vz[i] = vz[i] * s;
+    }
+  }
+  state[0] = xi;
+  state[1] = eta;
+  state[2] = pe;
+  *vir_out = vir;
+  free(work);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Conjugate-gradient relaxation of the positions at fixed species and box   */
 /* (Sec. IV.B relaxes the nanocrystal's grain boundaries by conjugate-       */
 /* gradient minimization before its MD and MC/MD runs; the variant is not    */

@@ -233,6 +233,18 @@ int or_md_nvt(int64_t n, double *x, double *y, double *z, double *vx, double *vy
               double mass_b, double dt, int64_t n_steps, double temp, double tau, double *xi_io,
               double *eta_io, double *fx, double *fy, double *fz, double *rho);
 
+/* Isotropic NPT velocity Verlet (Nose-Hoover thermostat and MTK barostat;
+ * the equations and the splitting are listed above or_md_npt in oracle.c):
+ * n_steps of dt (fs) at temp (K), thermostat time tau_t (fs), pressure p_ext
+ * (eV/A^3) and barostat time tau_p (fs).  box (in/out) scales with the
+ * positions; state = (xi, eta, pe) in and out; vir_out receives the virial
+ * of the last force evaluation (eV). */
+int or_md_npt(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+              const uint8_t *species, double box[3], const or_pot *p, double mass_a,
+              double mass_b, double dt, int64_t n_steps, double temp, double tau_t,
+              double p_ext, double tau_p, double *state, double *fx, double *fy, double *fz,
+              double *rho, double *vir_out);
+
 /* Conjugate-gradient relaxation (PR+ nonlinear CG with a backtracking
  * Armijo line search; the steps are listed above or_cg in oracle.c).  x, y,
  * z are relaxed in place; fx, fy, fz and rho are those at the final

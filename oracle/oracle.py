@@ -129,6 +129,10 @@ def lib():
         L.or_md_nvt.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
                                 C.c_double, C.c_double, C.c_int64, C.c_double, C.c_double,
                                 _P, _P, _P, _P, _P, _P]
+        L.or_md_npt.restype = C.c_int
+        L.or_md_npt.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double,
+                                C.c_double, C.c_double, C.c_int64, C.c_double, C.c_double,
+                                C.c_double, C.c_double, _P, _P, _P, _P, _P, _P]
         L.or_cg.restype = C.c_int
         L.or_cg.argtypes = [C.c_int64, _P, _P, _P, _P, _P, _P, C.c_int64, C.c_int64,
                             C.c_double, C.c_double, C.c_double, C.c_int, _P, _P, _P, _P, _P,
@@ -419,6 +423,31 @@ def md_nvt(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, T, tau, xi=0.0, 
     if rc != 0:
         raise ValueError("or_md_nvt failed")
     return (x, y, z, vx, vy, vz, fx, fy, fz, rho), (float(th[0]), float(th[1]))
+
+
+def md_npt(x, y, z, vx, vy, vz, species, box, pot, dt, n_steps, T, tau_t, p_ext, tau_p,
+           xi=0.0, eta=0.0, pe=0.0, mass_a=55.845, mass_b=63.546):
+    """Isotropic NPT (Nose-Hoover thermostat and barostat) velocity Verlet;
+    returns (x, y, z, vx, vy, vz, fx, fy, fz, rho), the new box, the state
+    (xi, eta, pe) and the virial of the last force evaluation.  p_ext in
+    eV/A^3."""
+    x, y, z = _f64(x).copy(), _f64(y).copy(), _f64(z).copy()
+    vx, vy, vz = _f64(vx).copy(), _f64(vy).copy(), _f64(vz).copy()
+    sp = np.ascontiguousarray(species, dtype=np.uint8)
+    n = x.size
+    fx, fy, fz, rho = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    b = _f64(box).copy()
+    st = np.array([xi, eta, pe], dtype=np.float64)
+    vir = np.zeros(1)
+    P = pot_struct(pot)
+    rc = lib().or_md_npt(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(sp), _p(b),
+                         C.byref(P), float(mass_a), float(mass_b), float(dt), int(n_steps),
+                         float(T), float(tau_t), float(p_ext), float(tau_p), _p(st), _p(fx),
+                         _p(fy), _p(fz), _p(rho), _p(vir))
+    if rc != 0:
+        raise ValueError("or_md_npt failed")
+    return ((x, y, z, vx, vy, vz, fx, fy, fz, rho), b, (float(st[0]), float(st[1]), float(st[2])),
+            float(vir[0]))
 
 
 CG_REASONS = {1: "force", 2: "energy", 3: "iterations", 4: "evaluations", 5: "line search"}

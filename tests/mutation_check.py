@@ -73,6 +73,12 @@ MUTATIONS = [
     ("tabulated pair function of the wrong species pair",
      "if (p->tab) return or_spline_eval(p->cphi[a + b], p->nr, r, p->inv_dr, NULL);",
      "if (p->tab) return or_spline_eval(p->cphi[a], p->nr, r, p->inv_dr, NULL);"),
+    ("virial sign", "      acc += s * r;\n    }\n    w[i] = acc;", "      acc -= s * r;\n    }\n    w[i] = acc;"),
+    ("barostat without the 3/g kinetic coupling", "c = exp(-(1.0 + 3.0 / g) * ve * (0.5 * h));",
+     "c = exp(-ve * (0.5 * h));"),
+    ("barostat momentum not thermostatted", "  *pe = *pe * s;\n", "\n"),
+    ("external pressure with the wrong sign", "pe = pe + h * (3.0 * V * (P - p_ext)",
+     "pe = pe + h * (3.0 * V * (P + p_ext)"),
     ("relaxation step against the direction", "xt[i] = or_wrap(x[i] + a * dx[i], box[0]);",
      "xt[i] = or_wrap(x[i] - a * dx[i], box[0]);"),
     ("decrease test with the wrong sign", "if (Et <= E - CG_C1 * a * sl && Et < E) {",
@@ -86,7 +92,8 @@ MUTATIONS = [
 TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_eam.py",
          "tests/test_oracle_ensemble.py", "tests/test_oracle_md.py",
          "tests/test_oracle_surrogate.py", "tests/test_oracle_localchain.py",
-         "tests/test_oracle_nvt.py", "tests/test_oracle_table.py", "tests/test_oracle_cg.py"]
+         "tests/test_oracle_nvt.py", "tests/test_oracle_table.py", "tests/test_oracle_cg.py",
+         "tests/test_oracle_npt.py"]
 
 
 def main():
