@@ -256,6 +256,40 @@ vcsgc_status eam_energy_forces(vcsgc_ctx *ctx, double *energy_eV, int want_force
  * next sweep. */
 vcsgc_status md_verlet_step(vcsgc_ctx *ctx, double dt_fs, int64_t n_steps);
 
+/* Nose-Hoover barostat for later md_verlet_step calls (the paper's Fe-Cu runs
+ * hold temperature and pressure with the Nose-Hoover thermostat and
+ * barostat, Sec. IV.B); it needs the thermostat on (vcsgc_set_thermostat).
+ * Isotropic form of Martyna, Tobias and Klein (J. Chem. Phys. 101, 4177
+ * (1994)) with the thermostat acting on particles and barostat:
+ *   dx/dt = v + ve x,  dv/dt = F/m - (1 + 3/g) ve v - xi v,  dL/dt = ve L,
+ *   dpe/dt = 3V (P - p_ext) + (3/g) 2K - xi pe,  ve = pe / W,
+ *   dxi/dt = (2K + pe^2/W - (g + 1) kB T) / Q,  deta/dt = xi,
+ * g = 3N - 3, Q = (g + 1) kB T tau_T^2, W = (g + 1) kB T tau_p_fs^2,
+ * P = (2K + Vir) / (3V), Vir = -1/2 sum_i sum_j s_ij r_ij over r < rc
+ * (s_ij = phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)).  Conserved:
+ * K + U + pe^2/(2W) + p_ext V + Q xi^2/2 + (g + 1) kB T eta.  A step of dt
+ * (h = dt/2) is T(h) B(h) V(h) X(dt) [forces] V(h) B(h) T(h):
+ *   T(h): xi += (h/2) G; s = (1 - xi h/2)/(1 + xi h/2); v *= s; pe *= s;
+ *         K *= s^2; eta += xi h; xi += (h/2) G  (G from the current K, pe);
+ *   B(h): pe += h (3V (P - p_ext) + (3/g) 2K);
+ *   V(h): c = exp(-(1 + 3/g) ve h/2); v *= c; v += h a; v *= c;
+ *   X(dt): q = exp(ve h); x = (x q + dt v) q, wrapped; every edge L *= q q;
+ * K is summed afresh after each closing kick and at the start of a call,
+ * and carried through the scalings otherwise; K and the virial are summed
+ * in the fixed shape of eam_energy_forces.  p_ext in eV/A^3
+ * (1 eV/A^3 = 160.2176634 GPa), pe in eV fs; tau_p_fs = 0 switches the
+ * barostat off.  The search bins follow the box (at most the grid of
+ * creation); a box that shrinks below two bins per axis ends
+ * md_verlet_step with VCSGC_E_BOX_TOO_SMALL, and a sweep on a box whose
+ * cells have shrunk below r_dep fails the same way.  Single-system MD
+ * contexts.  Errors: VCSGC_E_INVALID_ARG. */
+vcsgc_status vcsgc_set_barostat(vcsgc_ctx *ctx, double p_ext, double tau_p_fs, double pe);
+
+/* The barostat momentum (eV fs), the box edges (A, host box[3]) and the
+ * virial of the last force evaluation of an NPT call (eV); any pointer may
+ * be NULL. */
+vcsgc_status vcsgc_get_barostat(vcsgc_ctx *ctx, double *pe, double *box, double *virial);
+
 /* Conjugate-gradient relaxation of the positions at fixed species and box
  * (Sec. IV.B relaxes the nanocrystal's grain boundaries by conjugate-gradient
  * minimization before its MD and MC/MD runs).  Nonlinear conjugate gradients

@@ -200,6 +200,10 @@ def lib():
         L.vcsgc_selftest_sqrt.argtypes = [_P, _P, C.c_int64, _P]
         L.vcsgc_selftest_md_math.restype = st
         L.vcsgc_selftest_md_math.argtypes = [_P, _P, _P, _P, C.c_int64, _P]
+        L.vcsgc_set_barostat.restype = st
+        L.vcsgc_set_barostat.argtypes = [_P, C.c_double, C.c_double, C.c_double]
+        L.vcsgc_get_barostat.restype = st
+        L.vcsgc_get_barostat.argtypes = [_P, C.POINTER(C.c_double), _P, C.POINTER(C.c_double)]
         L.vcsgc_minimize.restype = st
         L.vcsgc_minimize.argtypes = [_P, C.POINTER(CgParams), C.POINTER(CgResult)]
         _lib = L
@@ -356,6 +360,20 @@ class VCSGC:
 
     def md(self, dt, n_steps):
         self._check(lib().md_verlet_step(self._h, float(dt), int(n_steps)), "md")
+
+    def set_barostat(self, p_ext, tau_p, pe=0.0):
+        """Nose-Hoover barostat (p_ext in eV/A^3, tau_p in fs; 0: off) for
+        later md() calls; needs the thermostat."""
+        self._check(lib().vcsgc_set_barostat(self._h, float(p_ext), float(tau_p), float(pe)),
+                    "set_barostat")
+
+    def barostat(self):
+        """(pe, box, virial) after the last NPT call."""
+        pe, vir = C.c_double(), C.c_double()
+        box = np.zeros(3)
+        self._check(lib().vcsgc_get_barostat(self._h, C.byref(pe), box.ctypes.data_as(C.c_void_p),
+                                             C.byref(vir)), "barostat")
+        return pe.value, box, vir.value
 
     def minimize(self, max_iter=1000, max_eval=100000, etol=0.0, ftol=1e-6, dmax=0.1):
         """Conjugate-gradient relaxation of the positions (vcsgc_minimize);

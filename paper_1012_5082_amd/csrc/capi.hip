@@ -32,7 +32,7 @@ void free_all(vcsgc_ctx *c) {
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
                   c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnu2,     c->m_lnug,   c->m_rec,
                   c->m_part,     c->s_rec,      c->s_part,     c->nvt,        c->nvt_part,
-                  c->tab_coef,   c->cg};
+                  c->tab_coef,   c->cg,         c->npt_part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -163,6 +163,7 @@ vcsgc_status refresh_md(vcsgc_ctx *c) {
       return fail(c, VCSGC_E_OVERFLOW, "a site has more than 32 neighbours within rc + skin");
     c->md_valid = true;
     c->md_rebuilds += 1;
+    for (int d = 0; d < 3; ++d) c->box_build[d] = c->box[d];
     return VCSGC_OK;
   }
 }
@@ -475,6 +476,11 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   c->bmax = 16;
   c->strategy = 0;
   c->desc = (sys->flags & VCSGC_FLAG_DESCRIPTOR) != 0;
+  c->bin_edge = c->desc ? std::max(rc + sys->skin, vc::DESC_CUT) : rc + sys->skin;
+  for (int d = 0; d < 3; ++d) {
+    c->nb_max[d] = r0.nb[d];
+    c->box_build[d] = r0.box[d];
+  }
   if (T) {
     // the interpolants' coefficients: f_A, f_B, phi_AA, phi_AB, phi_BB, then F_A, F_B
     const int64_t nir = T->nr - 1, nid = T->nrho - 1;
@@ -668,6 +674,11 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
     if (!valid_params(dmu0[k], kappa[k], cbar[k], T[k]))
       return fail(c, VCSGC_E_INVALID_ARG,
                   "need finite dmu0, kappa >= 0, cbar in [0,1], T > 0 for every replica");
+  if (R == 1)  // the box may have changed under the barostat
+    for (int d = 0; d < 3; ++d)
+      if (c->box[d] / (double)c->nc[d] < c->r_dep / (double)(c->per - 1))
+        return fail(c, VCSGC_E_BOX_TOO_SMALL,
+                    "the box has shrunk below the sweep's cell grid (edge < r_dep)");
   {
     vcsgc_status st = ensure_mc(c);
     if (st) return st;
@@ -1047,6 +1058,124 @@ vcsgc_status cg_gather3(vcsgc_ctx *c, double *dst, double *a, double *b, double 
   return VCSGC_OK;
 }
 
+// New box edges L (single-system context): the search bins are re-gridded
+// to floor(L / bin_edge) per axis, at most the grid of creation (whose
+// arrays hold it).  False if an axis would hold fewer than two bins.
+bool set_box(vcsgc_ctx *c, const double L[3]) {
+  int nb[3];
+  for (int d = 0; d < 3; ++d) {
+    nb[d] = std::min(c->nb_max[d], (int)std::floor(L[d] / c->bin_edge));
+    if (nb[d] < 2) return false;
+  }
+  RepHost &r = c->reps[0];
+  for (int d = 0; d < 3; ++d) {
+    c->box[d] = r.box[d] = L[d];
+    c->nb[d] = r.nb[d] = nb[d];
+  }
+  c->nbins = r.nbins = (int64_t)nb[0] * nb[1] * nb[2];
+  return true;
+}
+
+// the thermostat's half step with the barostat momentum (as in the NPT
+// splitting documented at vcsgc_set_barostat); returns the velocity factor
+double npt_thermo(double h, double g1kT, double Q, double W, double &K, double &pe, double &xi,
+                  double &eta) {
+  const double q = 0.5 * h;
+  xi = xi + q * ((2.0 * K + pe * pe / W - g1kT) / Q);
+  const double a = xi * q;
+  const double s = (1.0 - a) / (1.0 + a);
+  K = K * s * s;
+  pe = pe * s;
+  eta = eta + xi * h;
+  xi = xi + q * ((2.0 * K + pe * pe / W - g1kT) / Q);
+  return s;
+}
+
+// Forces with the virial terms at the current positions, the closing kick
+// (if kick), and the totals: *K (eV) and *vir (eV).
+vcsgc_status npt_forces_sums(vcsgc_ctx *c, bool kick, double cv, double h, double *K,
+                             double *vir) {
+  const int64_t nch = (c->n + vc::BLOCK - 1) / vc::BLOCK;
+  double *out = c->npt_part + 2 * nch;
+  VC_CHECK(c, vc::launch_forces_virial(c, c->eatom), "forces");
+  VC_CHECK(c, vc::launch_npt_sums(c, kick, cv, h, c->eatom, c->npt_part, out), "barostat");
+  double t[2];
+  VC_CHECK(c, hipMemcpyAsync(t, out, sizeof(t), hipMemcpyDeviceToHost, c->stream), "copy");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  *K = 0.5 * t[0] / vc::ACC;
+  *vir = -0.5 * t[1];
+  return VCSGC_OK;
+}
+
+// Nose-Hoover NPT steps, driven from the host (the box changes every step;
+// its edges are kernel arguments).  The MD list is rebuilt on the host's
+// decision; c->eatom holds the per-atom virial terms.
+vcsgc_status md_npt_steps(vcsgc_ctx *c, double dt, int64_t n_steps) {
+  const int64_t n = c->n;
+  if (!c->npt_part)
+    VC_CHECK(c, dalloc(&c->npt_part, 2 * (size_t)((n + vc::BLOCK - 1) / vc::BLOCK) + 8),
+             "allocation");
+  double th[2];
+  VC_CHECK(c, hipMemcpyAsync(th, c->nvt, sizeof(th), hipMemcpyDeviceToHost, c->stream), "copy");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  double xi = th[0], eta = th[1], pe = c->npt_pe;
+  const double h = 0.5 * dt;
+  const double g = 3.0 * (double)n - 3.0;
+  const double g1kT = (g + 1.0) * (vc::KB * c->nvt_T);
+  const double Q = g1kT * c->nvt_tau * c->nvt_tau;
+  const double W = g1kT * c->npt_tau * c->npt_tau;
+  const double rc = c->pot.rc, reach = c->pot.rc + c->skin;
+  VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild[0], 0, sizeof(int), c->stream), "reset");
+  VC_CHECK(c, vc::launch_pack(c), "pack");
+  double K = 0.0, vir = 0.0;
+  vcsgc_status st = npt_forces_sums(c, false, 1.0, h, &K, &vir);
+  if (st) return st;
+  double s_pend = 1.0;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    const double s = npt_thermo(h, g1kT, Q, W, K, pe, xi, eta);
+    double V = c->box[0] * c->box[1] * c->box[2];
+    double P = (2.0 * K + vir) / (3.0 * V);
+    pe = pe + h * (3.0 * V * (P - c->npt_p) + (3.0 / g) * (2.0 * K));
+    const double ve = pe / W;
+    const double cv = std::exp(-(1.0 + 3.0 / g) * ve * (0.5 * h));
+    const double q = std::exp(ve * h);
+    const double L[3] = {c->box[0] * q * q, c->box[1] * q * q, c->box[2] * q * q};
+    if (!set_box(c, L)) {
+      VC_CHECK(c, vc::launch_scale_v(c, s_pend), "barostat");
+      return fail(c, VCSGC_E_BOX_TOO_SMALL, "the box has shrunk below two search bins");
+    }
+    double lam[3], lmin = 1e300;
+    for (int d = 0; d < 3; ++d) {
+      lam[d] = L[d] / c->box_build[d];
+      lmin = std::min(lmin, lam[d]);
+    }
+    const double thr = 0.5 * (lmin * reach - rc);
+    VC_CHECK(c, vc::launch_npt_kick_drift(c, s_pend, s, cv, h, dt, q, lam, thr), "kick-drift");
+    int flag = 0;
+    VC_CHECK(c, hipMemcpyAsync(&flag, &c->ds->rebuild[0], sizeof(int), hipMemcpyDeviceToHost,
+                               c->stream),
+             "copy");
+    VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+    if (flag) {
+      VC_CHECK(c, hipMemsetAsync(&c->ds->rebuild[0], 0, sizeof(int), c->stream), "reset");
+      if ((st = refresh_md(c))) return st;
+    }
+    if ((st = npt_forces_sums(c, true, cv, h, &K, &vir))) return st;
+    V = c->box[0] * c->box[1] * c->box[2];
+    P = (2.0 * K + vir) / (3.0 * V);
+    pe = pe + h * (3.0 * V * (P - c->npt_p) + (3.0 / g) * (2.0 * K));
+    s_pend = npt_thermo(h, g1kT, Q, W, K, pe, xi, eta);
+  }
+  if (n_steps > 0) VC_CHECK(c, vc::launch_scale_v(c, s_pend), "barostat");
+  th[0] = xi;
+  th[1] = eta;
+  VC_CHECK(c, hipMemcpyAsync(c->nvt, th, sizeof(th), hipMemcpyHostToDevice, c->stream), "copy");
+  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  c->npt_pe = pe;
+  c->npt_vir = vir;
+  return VCSGC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1064,6 +1193,29 @@ vcsgc_status vcsgc_set_thermostat(vcsgc_ctx *c, double T_K, double tau_fs, doubl
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   c->nvt_T = T_K;
   c->nvt_tau = tau_fs;
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_set_barostat(vcsgc_ctx *c, double p_ext, double tau_p_fs, double pe) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (c->reps.size() != 1 || !c->nvt)
+    return fail(c, VCSGC_E_INVALID_ARG, "the barostat needs a single-system MD context");
+  if (!is_fin(p_ext) || !is_fin(tau_p_fs) || tau_p_fs < 0.0 || !is_fin(pe))
+    return fail(c, VCSGC_E_INVALID_ARG, "need finite p_ext and pe and tau_p >= 0");
+  c->npt_p = p_ext;
+  c->npt_tau = tau_p_fs;
+  c->npt_pe = pe;
+  return VCSGC_OK;
+}
+
+vcsgc_status vcsgc_get_barostat(vcsgc_ctx *c, double *pe, double *box, double *virial) {
+  vcsgc_status st = check_ctx(c);
+  if (st) return st;
+  if (pe) *pe = c->npt_pe;
+  if (box)
+    for (int d = 0; d < 3; ++d) box[d] = c->box[d];
+  if (virial) *virial = c->npt_vir;
   return VCSGC_OK;
 }
 
@@ -1200,8 +1352,12 @@ vcsgc_status md_verlet_step(vcsgc_ctx *c, double dt_fs, int64_t n_steps) {
     st = refresh_md(c);
     if (st) return st;
   }
+  if (c->npt_tau > 0.0 && !(c->nvt_T > 0.0))
+    return fail(c, VCSGC_E_INVALID_ARG, "the barostat needs the thermostat (vcsgc_set_thermostat)");
   if (n_steps > 0) c->mc_valid = false;
-  if (c->nvt_T > 0.0)
+  if (c->npt_tau > 0.0)
+    st = md_npt_steps(c, dt_fs, n_steps);
+  else if (c->nvt_T > 0.0)
     st = md_nvt_steps(c, dt_fs, n_steps, vc::md_rebuild_on_device(c));
   else
     st = (n_steps > 0 && vc::md_rebuild_on_device(c)) ? md_steps_device(c, dt_fs, n_steps)

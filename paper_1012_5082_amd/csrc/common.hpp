@@ -452,6 +452,16 @@ struct vcsgc_ctx {
   // conjugate-gradient relaxation: direction d, start positions x0 and
   // forces f0 of the line search (3 n each), chunk values, totals
   double *cg = nullptr;
+  // Nose-Hoover barostat of md_verlet_step (off while npt_tau == 0): external
+  // pressure (eV/A^3), coupling time, momentum pe (eV fs) and the last
+  // virial (eV), host-side; npt_part: chunk values [2 ceil(n / 256) + 8];
+  // box_build: the box at the last MD-list build; nb_max and bin_edge: the
+  // search-bin grid of creation and its minimum edge
+  double npt_p = 0.0, npt_tau = 0.0, npt_pe = 0.0, npt_vir = 0.0;
+  double *npt_part = nullptr;
+  double box_build[3] = {0, 0, 0};
+  int nb_max[3] = {0, 0, 0};
+  double bin_edge = 0.0;
 
   // search bins for neighbour lists: edge >= rc + skin, fixed capacity per bin
   int nb[3] = {0, 0, 0};
@@ -619,6 +629,16 @@ hipError_t launch_nvt_scale(vcsgc_ctx *c);
 hipError_t launch_cg_move(vcsgc_ctx *c, const double *x0, const double *d, double a);
 hipError_t launch_cg_totals(vcsgc_ctx *c, int mode, const double *u, double *part, double *out);
 hipError_t launch_cg_dir(vcsgc_ctx *c, double *d, double b, bool copy);
+// NPT: forces with the per-atom virial terms w; the step's scalings, kick
+// and drift (launch_npt_kick_drift); the closing kick (if kick) with the
+// totals of m v^2 and w into out[0..1] through part [2 ceil(n / BLOCK)];
+// v *= s
+hipError_t launch_forces_virial(vcsgc_ctx *c, double *w);
+hipError_t launch_npt_kick_drift(vcsgc_ctx *c, double f1, double f2, double cv, double h,
+                                 double dt, double q, const double lam[3], double thr);
+hipError_t launch_npt_sums(vcsgc_ctx *c, bool kick, double cv, double h, const double *w,
+                           double *part, double *out);
+hipError_t launch_scale_v(vcsgc_ctx *c, double s);
 hipError_t launch_sqrt(const double *in, double *out, int64_t n, hipStream_t s);
 hipError_t launch_md_math(const double *a, const double *b, double *sq, double *q, int64_t n,
                           hipStream_t s);

@@ -167,13 +167,16 @@ __device__ __forceinline__ void kick_drift_atom(const KickDrift &k, int64_t i, i
 
 // F_i = sum_j [phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)] (x_j - x_i) / r with
 // phi'(r) = eps ((-2 d)(c0 + c1 r) + c1 d^2) and f'_X(r) = (-2 t_X) d, d = rc - r,
-// summed in entry order (Finnis-Sinclair forms, or the tables when TAB)
-template <bool TAB>
+// summed in entry order (Finnis-Sinclair forms, or the tables when TAB).
+// VIR: also *wv += s r for each pair, s = phi'(r) + F'_i f'_{s_j}(r) + F'_j f'_{s_i}(r)
+// (the atom's share of the virial sum), in the same order.
+template <bool TAB, bool VIR = false>
 __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, const double4 &qi,
                                           const double4 *__restrict__ pf4,
                                           const int32_t *__restrict__ nj,
                                           const uint8_t *__restrict__ sp, const Box &b,
-                                          const PotD &p, double &ax, double &ay, double &az) {
+                                          const PotD &p, double &ax, double &ay, double &az,
+                                          double *wv = nullptr) {
   const double fpi = qi.w;
   const double e0 = p.eps[si], e1 = p.eps[si + 1], t0 = p.t[0], t1 = p.t[1], ti = p.t[si];
   for (int k0 = 0; k0 < m; k0 += IB) {
@@ -212,6 +215,7 @@ __device__ __forceinline__ void force_row(int64_t n, int64_t i, int m, int si, c
             dfi = -2.0 * ti * d;
           }
           const double s = dphi + fpi * dfj + q[u].w * dfi;
+          if (VIR) *wv = *wv + s * r;
           const double coef = div_md(s, r);
           ax += coef * dx;
           ay += coef * dy;
@@ -246,6 +250,25 @@ __global__ void __launch_bounds__(BLOCK)
     fy[i] = ay;
     fz[i] = az;
   }
+}
+
+// forces and w_i = sum_j s_ij r_ij (the virial is -1/2 sum_i w_i)
+template <bool TAB>
+__global__ void __launch_bounds__(BLOCK)
+    k_forces_vir(int64_t n, const double4 *__restrict__ pf4, const int32_t *__restrict__ nj,
+                 const uint8_t *__restrict__ cnt, const uint8_t *__restrict__ sp, Box b, PotD p,
+                 double *fx, double *fy, double *fz, double *w) {
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 qi = pf4[i];
+  const int si = sp[i];
+  const int m = cnt[i];
+  double ax = 0.0, ay = 0.0, az = 0.0, wv = 0.0;
+  force_row<TAB, true>(n, i, m, si, qi, pf4, nj, sp, b, p, ax, ay, az, &wv);
+  fx[i] = ax;
+  fy[i] = ay;
+  fz[i] = az;
+  w[i] = wv;
 }
 
 // E_i = F_{s_i}(rho_i) + 0.5 sum_j phi_{s_i s_j}(r)
@@ -658,6 +681,172 @@ hipError_t launch_cg_totals(vcsgc_ctx *c, int mode, const double *u, double *par
     k_cg_part<1><<<nch, BLOCK, 0, c->stream>>>(c->n, c->fx, c->fy, c->fz, u, part);
     k_cg_total<1><<<1, BLOCK, 0, c->stream>>>(nch, part, out);
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Isotropic NPT (Nose-Hoover thermostat and barostat), the per-atom parts of
+// a step driven from the host: the scalings, kicks and drift of the
+// splitting T(h) B(h) V(h) X(dt) [forces] V(h) B(h) T(h) (h = dt/2) take
+// their factors from the host, which integrates the thermostat and barostat
+// variables from the fixed-shape totals of the kinetic energy and virial.
+// ---------------------------------------------------------------------------
+// v = ((v f1) f2) c; v += h a; v = v c; x = wrap((x q + dt v) q) in the new
+// box; ps4 packed; raises ds->rebuild[0] when some atom is farther than thr
+// from its list-build position scaled to the new box (lam = L / L_build per
+// axis), or always when thr <= 0
+__global__ void __launch_bounds__(BLOCK)
+    k_npt_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                     double *vz, const double *__restrict__ fx, const double *__restrict__ fy,
+                     const double *__restrict__ fz, const uint8_t *__restrict__ sp, PotD p,
+                     double f1, double f2, double c, double h, double dt, double q, Box b,
+                     double lx, double ly, double lz, double thr,
+                     const double *__restrict__ xr, const double *__restrict__ yr,
+                     const double *__restrict__ zr, double4 *ps4, DevState *ds) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  bool far = false;
+  if (i < n) {
+    const int s = sp[i];
+    const double cm = p.cm[s];
+    double ux = vx[i], uy = vy[i], uz = vz[i];
+    ux = ux * f1;
+    uy = uy * f1;
+    uz = uz * f1;
+    ux = ux * f2;
+    uy = uy * f2;
+    uz = uz * f2;
+    ux = ux * c;
+    uy = uy * c;
+    uz = uz * c;
+    ux = ux + h * (fx[i] * cm);
+    uy = uy + h * (fy[i] * cm);
+    uz = uz + h * (fz[i] * cm);
+    ux = ux * c;
+    uy = uy * c;
+    uz = uz * c;
+    vx[i] = ux;
+    vy[i] = uy;
+    vz[i] = uz;
+    const double nx = wrap_box((x[i] * q + dt * ux) * q, b.L0);
+    const double ny = wrap_box((y[i] * q + dt * uy) * q, b.L1);
+    const double nz = wrap_box((z[i] * q + dt * uz) * q, b.L2);
+    x[i] = nx;
+    y[i] = ny;
+    z[i] = nz;
+    ps4[i] = make_double4(nx, ny, nz, (double)s);
+    const double ex = min_image(nx - lx * xr[i], b.L0);
+    const double ey = min_image(ny - ly * yr[i], b.L1);
+    const double ez = min_image(nz - lz * zr[i], b.L2);
+    far = !(thr > 0.0) || (ex * ex + ey * ey) + ez * ez > thr * thr;
+  }
+  const unsigned long long moved = __ballot(far);
+  if (moved && __lane_id() == __ffsll((long long)moved) - 1) atomicOr(&ds->rebuild[0], 1);
+}
+
+// [v = v c; v += h a; v = v c;] chunk values of m ((vx^2 + vy^2) + vz^2)
+// into part[c] and of w into part[nch + c]
+template <bool KICK>
+__global__ void __launch_bounds__(BLOCK)
+    k_npt_kick_sums(int64_t n, double *vx, double *vy, double *vz,
+                    const double *__restrict__ fx, const double *__restrict__ fy,
+                    const double *__restrict__ fz, const uint8_t *__restrict__ sp, PotD p,
+                    double c, double h, const double *__restrict__ w, double *part) {
+  __shared__ double s0[BLOCK], s1[BLOCK];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + t;
+  double a = 0.0, q = 0.0;
+  if (i < n) {
+    const int s = sp[i];
+    double ux = vx[i], uy = vy[i], uz = vz[i];
+    if (KICK) {
+      const double cm = p.cm[s];
+      ux = ux * c;
+      uy = uy * c;
+      uz = uz * c;
+      ux = ux + h * (fx[i] * cm);
+      uy = uy + h * (fy[i] * cm);
+      uz = uz + h * (fz[i] * cm);
+      ux = ux * c;
+      uy = uy * c;
+      uz = uz * c;
+      vx[i] = ux;
+      vy[i] = uy;
+      vz[i] = uz;
+    }
+    a = p.mass[s] * ((ux * ux + uy * uy) + uz * uz);
+    q = w[i];
+  }
+  s0[t] = a;
+  s1[t] = q;
+  __syncthreads();
+  for (int hh = BLOCK / 2; hh > 0; hh >>= 1) {
+    if (t < hh) {
+      s0[t] = s0[t] + s0[t + hh];
+      s1[t] = s1[t] + s1[t + hh];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int64_t nch = gridDim.x;
+    part[blockIdx.x] = s0[0];
+    part[nch + blockIdx.x] = s1[0];
+  }
+}
+
+// v *= s
+__global__ void k_scale_v(int64_t n, double *vx, double *vy, double *vz, double s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  vx[i] = vx[i] * s;
+  vy[i] = vy[i] * s;
+  vz[i] = vz[i] * s;
+}
+
+hipError_t launch_forces_virial(vcsgc_ctx *c, double *w) {
+  Box b{c->box[0], c->box[1], c->box[2]};
+  int h = tstart(c, VCSGC_KT_DENSITY);
+  density_md_launch(c, b);
+  tstop(c, h);
+  h = tstart(c, VCSGC_KT_FORCES);
+  if (c->pot.tab)
+    k_forces_vir<true><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+        c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->fx, c->fy, c->fz, w);
+  else
+    k_forces_vir<false><<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+        c->n, c->pf4, c->md_j, c->md_cnt, c->sp, b, c->pot, c->fx, c->fy, c->fz, w);
+  tstop(c, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_npt_kick_drift(vcsgc_ctx *c, double f1, double f2, double cv, double h,
+                                 double dt, double q, const double lam[3], double thr) {
+  Box b{c->box[0], c->box[1], c->box[2]};
+  int t = tstart(c, VCSGC_KT_KICKDRIFT);
+  k_npt_kick_drift<<<grid_for(c->n), BLOCK, 0, c->stream>>>(
+      c->n, c->x, c->y, c->z, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz, c->sp, c->pot, f1, f2,
+      cv, h, dt, q, b, lam[0], lam[1], lam[2], thr, c->xr, c->yr, c->zr, c->ps4, c->ds);
+  tstop(c, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_npt_sums(vcsgc_ctx *c, bool kick, double cv, double h, const double *w,
+                           double *part, double *out) {
+  const int nch = grid_for(c->n);
+  int t = tstart(c, VCSGC_KT_KICK);
+  if (kick)
+    k_npt_kick_sums<true><<<nch, BLOCK, 0, c->stream>>>(c->n, c->vx, c->vy, c->vz, c->fx, c->fy,
+                                                        c->fz, c->sp, c->pot, cv, h, w, part);
+  else
+    k_npt_kick_sums<false><<<nch, BLOCK, 0, c->stream>>>(c->n, c->vx, c->vy, c->vz, c->fx,
+                                                         c->fy, c->fz, c->sp, c->pot, cv, h, w,
+                                                         part);
+  k_cg_total<1><<<1, BLOCK, 0, c->stream>>>(nch, part, out);
+  tstop(c, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_v(vcsgc_ctx *c, double s) {
+  k_scale_v<<<grid_for(c->n), BLOCK, 0, c->stream>>>(c->n, c->vx, c->vy, c->vz, s);
   return hipGetLastError();
 }
 
