@@ -629,6 +629,93 @@ static int or_local_test(int64_t i, const uint64_t t[4], const int64_t *start,
   return lnu < -xl;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Grown domains (Sec. III.A, Fig. 6): cells of edge e per axis (at least     */
+/* 2 r_dep), each holding eight cubic domains of edge e - r_dep, one per     */
+/* corner: domain k spans [0, e - r_dep) along axis d when bit d of k is 0   */
+/* and [e - (e - r_dep), e) when it is 1, in coordinates u = x - b e from    */
+/* the cell's corner (b the cell index along the axis).  Domains of one k in */
+/* different cells are r_dep apart, so trials in them do not interact; the   */
+/* domains of a cell overlap, and an atom in m of them gets weight 8 / m, so */
+/* that the centre is not sampled more often than the rim.  Lists per (cell, */
+/* k): the atoms of the domain in ascending index with the inclusive prefix  */
+/* sums of their weights.                                                     */
+/* ------------------------------------------------------------------------ */
+static int or_grown_grid(const double box[3], double r_dep, double grow_edge, int32_t nc[3]) {
+  double emin = grow_edge > 2.0 * r_dep ? grow_edge : 2.0 * r_dep;
+  for (int d = 0; d < 3; ++d) {
+    nc[d] = (int32_t)floor(box[d] / emin);
+    if (nc[d] < 1) return -1;
+  }
+  return 0;
+}
+
+/* domain bits of atom i (bit 2d: in the low interval of axis d, bit 2d+1: in
+ * the high one) and its weight 8 / m */
+static int or_grown_bits(int64_t i, const double *x, const double *y, const double *z,
+                         const double box[3], const int32_t nc[3], double r_dep, int *w) {
+  const double *pos[3] = {x, y, z};
+  int bits = 0, m = 1;
+  for (int d = 0; d < 3; ++d) {
+    double e = box[d] / (double)nc[d];
+    double ld = e - r_dep;
+    int b = (int)(pos[d][i] / (box[d] / (double)nc[d]));
+    if (b < 0) b = 0;
+    if (b >= nc[d]) b = nc[d] - 1;
+    double u = pos[d][i] - (double)b * e;
+    int lo = u < ld, hi = u >= e - ld;
+    bits |= (lo << (2 * d)) | (hi << (2 * d + 1));
+    m *= lo + hi;
+  }
+  *w = 8 / m;
+  return bits;
+}
+
+static int or_in_domain(int bits, int k) {
+  for (int d = 0; d < 3; ++d)
+    if (!((bits >> (2 * d + ((k >> d) & 1))) & 1)) return 0;
+  return 1;
+}
+
+/* per (cell c, domain k) at q = 8 c + k: dstart[q] .. dstart[q + 1] into
+ * dlist (atom) and dcum (inclusive prefix sums of the weights) */
+static void or_grown_lists(int64_t ncells, const int32_t *cstart, const int32_t *catoms,
+                           const double *x, const double *y, const double *z, const double box[3],
+                           const int32_t nc[3], double r_dep, int32_t *dstart, int32_t *dlist,
+                           int32_t *dcum) {
+  int32_t o = 0;
+  for (int64_t c = 0; c < ncells; ++c) {
+    for (int k = 0; k < 8; ++k) {
+      dstart[8 * c + k] = o;
+      int32_t cum = 0;
+      for (int32_t q = cstart[c]; q < cstart[c + 1]; ++q) {
+        int32_t i = catoms[q];
+        int w;
+        int bits = or_grown_bits(i, x, y, z, box, nc, r_dep, &w);
+        if (!or_in_domain(bits, k)) continue;
+        cum += w;
+        dlist[o] = i;
+        dcum[o] = cum;
+        o++;
+      }
+    }
+  }
+  dstart[8 * ncells] = o;
+}
+
+/* Site of a trial in domain k of cell c: with W the domain's total weight,
+ * r = floor(w0 W / 2^64) and the first atom whose prefix sum exceeds r;
+ * -1 for an empty domain. */
+static int64_t or_grown_site(const uint64_t t[4], const int32_t *dstart, const int32_t *dlist,
+                             const int32_t *dcum, int64_t c, int k) {
+  int32_t a = dstart[8 * c + k], b = dstart[8 * c + k + 1];
+  if (a == b) return -1;
+  uint64_t r = or_index(t[0], (uint64_t)dcum[b - 1]);
+  for (int32_t q = a; q < b; ++q)
+    if ((uint64_t)dcum[q] > r) return dlist[q];
+  return -1;
+}
+
 /* Site of a trial: the floor(w0 m / 2^64)-th of the cell's m atoms. */
 static int64_t or_site(const uint64_t t[4], const int32_t *cstart, const int32_t *catoms,
                        int64_t c) {
@@ -646,11 +733,15 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
   const int64_t K = a->local_steps > 1 ? a->local_steps : 1;
   if (K > 1 && da && da->mode != OR_DA_OFF) return -3; /* delayed acceptance: one step only */
   if (n < 1 || !(a->temp > 0.0) || !(a->kappa >= 0.0)) return -1;
-  const int P = a->colour_period > 0 ? a->colour_period : 2;
+  const int grown = a->grow_edge > 0.0 && !a->one_cell;
+  const int P = grown ? 2 : (a->colour_period > 0 ? a->colour_period : 2);
   const int NCOL = P * P * P;
   int32_t nc[3] = {1, 1, 1};
   int64_t ncells = 1;
-  if (!a->one_cell) {
+  if (grown) {
+    if (!(a->r_dep > 0.0) || or_grown_grid(box, a->r_dep, a->grow_edge, nc)) return -2;
+    ncells = (int64_t)nc[0] * nc[1] * nc[2];
+  } else if (!a->one_cell) {
     if (or_cell_grid_p(box, a->r_dep, P, nc)) return -2;
     ncells = (int64_t)nc[0] * nc[1] * nc[2];
   }
@@ -682,7 +773,16 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
     free(fill);
   }
   for (int64_t c = 0; c < ncells; ++c) ccol[c] = or_cell_colour(c, nc, P);
-  int64_t S = a->one_cell ? (n + K - 1) / K : NCOL * ((((n + ncells - 1) / ncells) + K - 1) / K);
+  int32_t *dstart = NULL, *dlist = NULL, *dcum = NULL;
+  if (grown) {
+    dstart = (int32_t *)malloc((size_t)(8 * ncells + 1) * sizeof(int32_t));
+    dlist = (int32_t *)malloc((size_t)(8 * n) * sizeof(int32_t));
+    dcum = (int32_t *)malloc((size_t)(8 * n) * sizeof(int32_t));
+    or_grown_lists(ncells, cstart, catoms, x, y, z, box, nc, a->r_dep, dstart, dlist, dcum);
+  }
+  int64_t S = a->one_cell ? (n + K - 1) / K
+              : grown     ? (((n + ncells - 1) / ncells) + K - 1) / K
+                          : NCOL * ((((n + ncells - 1) / ncells) + K - 1) / K);
 
   double beta = 1.0 / (OR_KB * a->temp);
   double kN = a->kappa / (double)n;
@@ -702,13 +802,15 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
         /* local chains: every step on the state left by the previous one;
          * accepted flips are applied at once and logged for undoing */
         for (int64_t c = 0; c < ncells; ++c) {
-          if (!a->one_cell && ccol[c] != colour) continue;
-          int64_t m = cstart[c + 1] - cstart[c];
+          if (!a->one_cell && !grown && ccol[c] != colour) continue;
+          int64_t m = grown ? dstart[8 * c + colour + 1] - dstart[8 * c + colour]
+                            : cstart[c + 1] - cstart[c];
           if (m == 0) continue;
           for (int64_t q = 0; q < K; ++q) {
             uint64_t tc[4] = {(uint64_t)w, (uint64_t)s, (uint64_t)c, (uint64_t)(1 + q)}, t[4];
             or_philox4x64_10(key, tc, t);
-            int64_t i = or_site(t, cstart, catoms, c);
+            int64_t i = grown ? or_grown_site(t, dstart, dlist, dcum, c, colour)
+                              : or_site(t, cstart, catoms, c);
             int dn;
             double du, margin;
             int acc = or_local_test(i, t, start, nj, nr, species, rho, p, beta, a->dmu0, &du, &dn,
@@ -736,12 +838,14 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
         }
       }
       for (int64_t c = 0; c < ncells && K == 1; ++c) {
-        if (!a->one_cell && ccol[c] != colour) continue;
-        int64_t m = cstart[c + 1] - cstart[c];
+        if (!a->one_cell && !grown && ccol[c] != colour) continue;
+        int64_t m = grown ? dstart[8 * c + colour + 1] - dstart[8 * c + colour]
+                          : cstart[c + 1] - cstart[c];
         if (m == 0) continue;
         uint64_t tc[4] = {(uint64_t)w, (uint64_t)s, (uint64_t)c, 1}, t[4];
         or_philox4x64_10(key, tc, t);
-        int64_t i = or_site(t, cstart, catoms, c);
+        int64_t i = grown ? or_grown_site(t, dstart, dlist, dcum, c, colour)
+                          : or_site(t, cstart, catoms, c);
         int dn = 1 - 2 * (int)species[i];
         double du, margin;
         int acc;
@@ -751,6 +855,7 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
                             &du, &margin, &pass1, &status);
           if (status) {
             free(rec); free(cstart); free(catoms); free(cof); free(ccol);
+            free(dstart); free(dlist); free(dcum);
             return status;
           }
           if (pass1) da->stage1_pass++;
@@ -837,6 +942,9 @@ static int sweep_core(int64_t n, const double *x, const double *y, const double 
   free(catoms);
   free(cof);
   free(ccol);
+  free(dstart);
+  free(dlist);
+  free(dcum);
   return 0;
 }
 
@@ -1170,7 +1278,7 @@ int or_sweep_omp(int64_t n, const double *x, const double *y, const double *z,
                  const double *nr, uint8_t *species, double *rho, int64_t *n_b,
                  const or_pot *p, const or_sweep_args *a, double *vx, double *vy, double *vz,
                  double *slog, int64_t scap, int64_t *sn, int n_threads, or_stats *st) {
-  if (a->local_steps > 1 || a->one_cell) return -3;
+  if (a->local_steps > 1 || a->one_cell || a->grow_edge > 0.0) return -3;
   if (n < 1 || !(a->temp > 0.0) || !(a->kappa >= 0.0)) return -1;
   const int P = a->colour_period > 0 ? a->colour_period : 2;
   const int NCOL = P * P * P;

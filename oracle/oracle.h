@@ -90,6 +90,7 @@ typedef struct {
   double mass_a, mass_b; /* for velocity rescaling on transmutation */
   int32_t local_steps;   /* trials per active cell per stage (0 or 1: one) */
   int32_t colour_period; /* 0 or 2: eight colours; 3: 27 colours on cells of edge >= r_dep/2 */
+  double grow_edge;      /* > 0: grown domains in cells of edge >= max(grow_edge, 2 r_dep) */
 } or_sweep_args;
 
 typedef struct {
@@ -106,6 +107,12 @@ typedef struct {
  * undone as a whole by the global factor on its net dn_tot.  A sweep then has
  * 8 ceil(ceil(N / N_cells) / k) stages (ceil(N / k) in one-cell mode).  In the
  * trial log and the overrides the cell field holds cell * k + q.
+ * With grow_edge > 0 the domains are grown (Sec. III.A, Fig. 6): cells of
+ * edge e >= max(grow_edge, 2 r_dep) per axis, and in each cell eight
+ * overlapping cubic domains of edge e - r_dep, one per corner; a stage
+ * draws one of the eight and every cell makes a trial in it, the site drawn
+ * with weight 8 / m (m the number of the cell's domains holding the atom);
+ * a sweep has ceil(ceil(N / N_cells) / k) stages (see or_grown_lists).
  * tlog: trial log, 8 doubles per trial (w, s, cell, site, dn, acc, dU, margin),
  * slog: stage log, 8 doubles per stage (w, s, colour, dn_tot, nrec, acc, xg, margin),
  * over: near-tie decisions to adopt, 4 doubles each (w, s, cell or -1, decision).

@@ -44,7 +44,8 @@ class SweepArgs(C.Structure):
                 ("temp", C.c_double), ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("w0", C.c_int64), ("n_sweeps", C.c_int64), ("r_dep", C.c_double),
                 ("one_cell", C.c_int32), ("mass_a", C.c_double), ("mass_b", C.c_double),
-                ("local_steps", C.c_int32), ("colour_period", C.c_int32)]
+                ("local_steps", C.c_int32), ("colour_period", C.c_int32),
+                ("grow_edge", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -305,16 +306,18 @@ class SweepState:
 
 def sweep(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, replica=0, r_dep=None,
           one_cell=False, log_trials=0, log_stages=0, overrides=None,
-          mass_a=55.845, mass_b=63.546, local_steps=1, colour_period=2):
+          mass_a=55.845, mass_b=63.546, local_steps=1, colour_period=2, grow_edge=0.0):
     """Run n_sweeps sweeps from the state's sweep counter; returns (stats, tlog, slog).
     local_steps = k: k trials per active cell per stage (exact local chains);
-    colour_period 3: 27 colours on cells of edge >= r_dep / 2."""
+    colour_period 3: 27 colours on cells of edge >= r_dep / 2; grow_edge > 0:
+    grown domains in cells of edge >= max(grow_edge, 2 r_dep)."""
     L = lib()
     if r_dep is None:
         r_dep = 2.0 * st.pot.rc
     a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
                   int(st.w), int(n_sweeps), float(r_dep), int(bool(one_cell)),
-                  float(mass_a), float(mass_b), int(local_steps), int(colour_period))
+                  float(mass_a), float(mass_b), int(local_steps), int(colour_period),
+                  float(grow_edge))
     tlog = np.zeros((max(log_trials, 0), 8)) if log_trials else None
     slog = np.zeros((max(log_stages, 0), 8)) if log_stages else None
     tn = np.zeros(1, dtype=np.int64)
@@ -556,7 +559,7 @@ def mlp_grad(m: MlpParams, d, t, bf16_emul=False):
 def sweep_da(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, mode, replica=0, r_dep=None,
              one_cell=False, table=None, mlp: MlpParams | None = None,
              desc_nl: NeighborList | None = None, log_trials=0, log_stages=0, log_desc=0,
-             colour_period=2):
+             colour_period=2, grow_edge=0.0):
     """Delayed-acceptance sweeps; returns (stats, stage-1 passes, tlog, slog),
     and with log_desc > 0 (table mode with desc_nl) also the descriptor log:
     rows (w, s, cell, current-state descriptor [10], flipped-state
@@ -566,7 +569,7 @@ def sweep_da(st: SweepState, dmu0, kappa, cbar, T, n_sweeps, seed, mode, replica
         r_dep = 2.0 * st.pot.rc
     a = SweepArgs(float(dmu0), float(kappa), float(cbar), float(T), int(seed), int(replica),
                   int(st.w), int(n_sweeps), float(r_dep), int(bool(one_cell)), 55.845, 63.546, 1,
-                  int(colour_period))
+                  int(colour_period), float(grow_edge))
     da = Da()
     da.mode = DA_MODES[mode]
     keep = []

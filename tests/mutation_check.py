@@ -79,6 +79,12 @@ MUTATIONS = [
     ("barostat momentum not thermostatted", "  *pe = *pe * s;\n", "\n"),
     ("external pressure with the wrong sign", "pe = pe + h * (3.0 * V * (P - p_ext)",
      "pe = pe + h * (3.0 * V * (P + p_ext)"),
+    ("grown-domain weight m instead of 8 / m", "  *w = 8 / m;\n  return bits;", "  *w = m;\n  return bits;"),
+    ("grown-domain high interval from the wrong end", "int lo = u < ld, hi = u >= e - ld;",
+     "int lo = u < ld, hi = u >= ld;"),
+    ("grown domains with eight times the stages",
+     "              : grown     ? (((n + ncells - 1) / ncells) + K - 1) / K",
+     "              : grown     ? 8 * ((((n + ncells - 1) / ncells) + K - 1) / K)"),
     ("relaxation step against the direction", "xt[i] = or_wrap(x[i] + a * dx[i], box[0]);",
      "xt[i] = or_wrap(x[i] - a * dx[i], box[0]);"),
     ("decrease test with the wrong sign", "if (Et <= E - CG_C1 * a * sl && Et < E) {",
@@ -93,7 +99,7 @@ TESTS = ["tests/test_oracle_philox.py", "tests/test_oracle_eam.py",
          "tests/test_oracle_ensemble.py", "tests/test_oracle_md.py",
          "tests/test_oracle_surrogate.py", "tests/test_oracle_localchain.py",
          "tests/test_oracle_nvt.py", "tests/test_oracle_table.py", "tests/test_oracle_cg.py",
-         "tests/test_oracle_npt.py"]
+         "tests/test_oracle_npt.py", "tests/test_oracle_grown.py"]
 
 
 def main():
