@@ -396,6 +396,9 @@ def main():
                     help="c3: sweep tiling strategy:k, or 'auto' for the autotuner")
     ap.add_argument("--colours", type=int, default=8, choices=[8, 27],
                     help="c3, c4: colours of the sweep (27: cells of edge >= r_dep / 2)")
+    ap.add_argument("--grow-edge", type=float, default=0.0,
+                    help="c3: grown overlapping domains in cells of edge >= max(this, 2 r_dep) "
+                         "instead of the colouring (0: off)")
     ap.add_argument("--potential", default="FS-P1", choices=["FS-P1", "TAB-FS1", "TAB-X"],
                     help="c3, c4: the analytic Finnis-Sinclair set, or a tabulated EAM")
     ap.add_argument("--skin", type=float, default=0.3,
@@ -432,7 +435,7 @@ def main():
     n = d["x"].size
     log(f"workload {d['name']}: {n} sites generated in {time.perf_counter() - t0:.1f} s")
     g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
-              vz=d["vz"], skin=args.skin, colours=args.colours)
+              vz=d["vz"], skin=args.skin, colours=args.colours, grow_edge=args.grow_edge)
     if args.local_steps > 1:
         g.set_local_steps(args.local_steps)
     info = g.info()
@@ -548,7 +551,7 @@ def main():
                                f"T=700 K, step = 1 VC-SGC sweep + 20 MD steps (dt=1 fs)",
                    "n_sites": n, "n_cells": info["n_cells"],
                    "stages_per_sweep": info["stages_per_sweep"], "colours": args.colours,
-                   "potential": args.potential,
+                   "grow_edge": args.grow_edge, "potential": args.potential,
                    "variant": ("plain" if args.local_steps == 1
                                else f"local chains of {args.local_steps} trials per cell"),
                    "sweep_tiling": list(tuned["choice"]),

@@ -105,6 +105,22 @@ typedef struct {
   /* NULL: the analytic potential pot; else the tabulated potential (then
    * pot supplies only mass_a and mass_b, and rc is table->rc) */
   const vcsgc_eam_table *table;
+  /* > 0: grown domains (Sec. III.A, Fig. 6) instead of the colouring:
+   * cells of edge e >= max(grow_edge, 2 r_dep) per axis (at least one),
+   * each holding eight overlapping cubic domains of edge e - r_dep, one per
+   * corner (bit d of corner k: [0, e - r_dep) or [r_dep', e) along axis d,
+   * r_dep' = e - (e - r_dep), from the cell's corner).  A stage draws the
+   * corner k = floor(w0 8 / 2^64) of Philox(key, (w, s, 0, 0)) and every cell
+   * makes one trial in its domain k (none if it is empty): with W the
+   * domain's summed weights 8 / m (m the number of the cell's domains
+   * holding the atom, ascending atom order), the site is the first whose
+   * running sum exceeds floor(w0 W / 2^64), w0 from Philox(key, (w, s, cell,
+   * 1)).  Same-corner domains of different cells are r_dep apart.  A sweep
+   * has ceil(N / N_cells) stages.  Single-system contexts with the
+   * eight-colour scheme; sweeps run on the pipeline strategies (the default
+   * becomes three stages per batch); the cell grid is that of creation.
+   * 0: the colouring. */
+  double grow_edge;
 } vcsgc_system;
 
 /* Per-call statistics (host struct). */

@@ -43,7 +43,7 @@ class System(C.Structure):
                 ("fx", C.c_void_p), ("fy", C.c_void_p), ("fz", C.c_void_p),
                 ("species", C.c_void_p), ("pot", EamFS), ("skin", C.c_double),
                 ("r_dep", C.c_double), ("flags", C.c_uint32),
-                ("table", C.POINTER(EamTableC))]
+                ("table", C.POINTER(EamTableC)), ("grow_edge", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -282,7 +282,7 @@ class VCSGC:
 
     def __init__(self, x, y, z, box, species, pot, vx=None, vy=None, vz=None, forces=False,
                  skin=0.3, r_dep=0.0, mass_a=55.845, mass_b=63.546, device="cuda", stream=None,
-                 descriptor=False, colours=8):
+                 descriptor=False, colours=8, grow_edge=0.0):
         import torch
         L = lib()
         self.device = torch.device(device)
@@ -317,6 +317,7 @@ class VCSGC:
         if colours not in (8, 27):
             raise ValueError("colours must be 8 or 27")
         sysd.flags = (FLAG_DESCRIPTOR if descriptor else 0) | (FLAG_COLOURS27 if colours == 27 else 0)
+        sysd.grow_edge = float(grow_edge)
         self._sys = sysd
         h = _P()
         rc = L.vcsgc_create(C.byref(sysd), _stream_handle(stream), C.byref(h))

@@ -32,7 +32,8 @@ void free_all(vcsgc_ctx *c) {
                   c->u_site,     c->u_j,        c->u_rho,      c->u_v,
                   c->stage_lnug, c->m_sites,   c->m_lnu,      c->m_lnu2,     c->m_lnug,   c->m_rec,
                   c->m_part,     c->s_rec,      c->s_part,     c->nvt,        c->nvt_part,
-                  c->tab_coef,   c->cg,         c->npt_part};
+                  c->tab_coef,   c->cg,         c->npt_part,   c->g_start,    c->g_list,
+                  c->g_cum,      c->g_cnt};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_reps) (void)hipHostFree(c->h_reps);
@@ -389,6 +390,12 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   if (!(r_dep >= 2.0 * rc) || !is_fin(r_dep))
     return fail(nullptr, VCSGC_E_INVALID_ARG, "r_dep must be >= 2 rc");
   const int per = (sys->flags & VCSGC_FLAG_COLOURS27) ? 3 : 2, ncol = per * per * per;
+  const double ge = sys->grow_edge;
+  if (!is_fin(ge) || ge < 0.0) return fail(nullptr, VCSGC_E_INVALID_ARG, "grow_edge must be >= 0");
+  const bool grown = ge > 0.0;
+  if (grown && (R != 1 || per != 2))
+    return fail(nullptr, VCSGC_E_INVALID_ARG,
+                "grown domains need a single system and the eight-colour scheme");
 
   std::vector<RepHost> reps((size_t)R);
   int64_t aoff = 0, coff = 0, boff = 0, roff = 0;
@@ -401,11 +408,18 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
       r.box[d] = rep_box[3 * k + d];
       if (!(r.box[d] > 0.0) || !is_fin(r.box[d]))
         return fail(nullptr, VCSGC_E_INVALID_ARG, "box edges must be positive and finite");
-      r.nc[d] = per * (int)std::floor(r.box[d] / ((double)per * (r_dep / (double)(per - 1))));
-      if (r.nc[d] < per)
-        return fail(nullptr, VCSGC_E_BOX_TOO_SMALL,
-                    per == 2 ? "box must hold two cells of edge r_dep in every dimension"
-                             : "box must hold three cells of edge r_dep / 2 in every dimension");
+      if (grown) {
+        r.nc[d] = (int)std::floor(r.box[d] / std::max(ge, 2.0 * r_dep));
+        if (r.nc[d] < 1)
+          return fail(nullptr, VCSGC_E_BOX_TOO_SMALL,
+                      "box must hold one cell of edge max(grow_edge, 2 r_dep) in every dimension");
+      } else {
+        r.nc[d] = per * (int)std::floor(r.box[d] / ((double)per * (r_dep / (double)(per - 1))));
+        if (r.nc[d] < per)
+          return fail(nullptr, VCSGC_E_BOX_TOO_SMALL,
+                      per == 2 ? "box must hold two cells of edge r_dep in every dimension"
+                               : "box must hold three cells of edge r_dep / 2 in every dimension");
+      }
       const double bin_edge = (sys->flags & VCSGC_FLAG_DESCRIPTOR)
                                   ? std::max(rc + sys->skin, vc::DESC_CUT)
                                   : rc + sys->skin;
@@ -416,8 +430,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
     r.ncells = (int64_t)r.nc[0] * r.nc[1] * r.nc[2];
     r.coff = coff;
     r.cso = coff + k;
-    r.S = (int64_t)ncol * ((r.n + r.ncells - 1) / r.ncells);
-    r.ncpc = r.ncells / ncol;
+    r.S = (grown ? 1 : (int64_t)ncol) * ((r.n + r.ncells - 1) / r.ncells);
+    r.ncpc = grown ? r.ncells : r.ncells / ncol;
     r.roff = roff;
     r.nbins = (int64_t)r.nb[0] * r.nb[1] * r.nb[2];
     r.boff = boff;
@@ -475,6 +489,8 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   p.cm[1] = P.mass_b > 0.0 ? vc::ACC / P.mass_b : 0.0;
   c->bmax = 16;
   c->strategy = 0;
+  c->grown = grown;
+  c->grow_edge = ge;
   c->desc = (sys->flags & VCSGC_FLAG_DESCRIPTOR) != 0;
   c->bin_edge = c->desc ? std::max(rc + sys->skin, vc::DESC_CUT) : rc + sys->skin;
   for (int d = 0; d < 3; ++d) {
@@ -541,8 +557,15 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
   {
     int64_t mx = 1;
     for (const RepHost &r : c->reps)
-      mx = std::max<int64_t>(mx, (std::max(r.ncells, r.nbins) + vc::SCAN_CHUNK - 1) / vc::SCAN_CHUNK);
+      mx = std::max<int64_t>(mx, (std::max({r.ncells, r.nbins, grown ? 8 * r.ncells : 0}) +
+                                  vc::SCAN_CHUNK - 1) / vc::SCAN_CHUNK);
     A(dalloc(&c->scan_tmp, mx));
+  }
+  if (grown) {
+    A(dalloc(&c->g_start, 8 * c->ncells + 1));
+    A(dalloc(&c->g_cnt, 8 * c->ncells));
+    A(dalloc(&c->g_list, 8 * n));
+    A(dalloc(&c->g_cum, 8 * n));
   }
   A(dalloc(&c->mc_j, K * n));
   A(dalloc(&c->mc_r, K * n));
@@ -615,6 +638,10 @@ vcsgc_status create_impl(const vcsgc_system *sys, int R, const int64_t *rep_atom
                        "positions must lie in [0, L) and species in {0, 1}"));
   }
   if ((e = vc::persist_count(c)) != hipSuccess) return bail(dev_fail(c, e, "count"));
+  if (grown) {  // the batched pipeline, three stages per batch
+    c->strategy = 3;
+    c->trials_per_group = 3;
+  }
   st = refresh_mc(c);
   if (st != VCSGC_OK) return bail(st);
   *out = c;
@@ -676,7 +703,8 @@ vcsgc_status sweep_impl(vcsgc_ctx *c, const double *dmu0, const double *kappa, c
                   "need finite dmu0, kappa >= 0, cbar in [0,1], T > 0 for every replica");
   if (R == 1)  // the box may have changed under the barostat
     for (int d = 0; d < 3; ++d)
-      if (c->box[d] / (double)c->nc[d] < c->r_dep / (double)(c->per - 1))
+      if (c->box[d] / (double)c->nc[d] <
+          (c->grown ? 2.0 * c->r_dep : c->r_dep / (double)(c->per - 1)))
         return fail(c, VCSGC_E_BOX_TOO_SMALL,
                     "the box has shrunk below the sweep's cell grid (edge < r_dep)");
   {
@@ -778,6 +806,8 @@ vcsgc_status vcsgc_set_tuning(vcsgc_ctx *c, int32_t strategy, int32_t trials_per
     return fail(c, VCSGC_E_INVALID_ARG, "stages per batch in [1,16]");
   if (strategy >= 2 && c->reps.size() != 1)
     return fail(c, VCSGC_E_INVALID_ARG, "per-stage launches need a single-system context");
+  if (strategy < 2 && c->grown)
+    return fail(c, VCSGC_E_INVALID_ARG, "grown domains run on the pipeline strategies (2, 3)");
   VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
   c->strategy = strategy;
   if (trials_per_group != c->trials_per_group) {
@@ -809,7 +839,7 @@ vcsgc_status vcsgc_set_local_steps(vcsgc_ctx *c, int32_t k) {
   c->sites = c->u_site = c->u_j = nullptr;
   c->site_lnu = c->stage_lnug = c->u_rho = c->u_v = nullptr;
   c->local_steps = k;
-  const int64_t ncpc = c->ncells / c->ncol, K = k;
+  const int64_t ncpc = vc::active_cells(c), K = k;
   const int64_t tab = vc::stages_per_sweep(c) * ncpc * K;
   VC_CHECK(c, dalloc(&c->sites, tab), "allocation");
   VC_CHECK(c, dalloc(&c->site_lnu, tab), "allocation");

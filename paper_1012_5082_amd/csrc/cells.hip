@@ -193,6 +193,70 @@ __global__ void __launch_bounds__(64) k_cell_sort(int64_t m, const int32_t *__re
 
 // cells of one replica; cell_atoms holds global atom indices, cell_start the
 // positions inside the replica's segment of cell_atoms
+// ----------------------------------------------------------------------------
+// grown domains: in cells of edge e, eight cubic domains of edge e - r_dep,
+// one per corner (bit d of the corner k: the low interval [0, e - r_dep) or
+// the high one [e - (e - r_dep), e) along axis d, in coordinates from the
+// cell's corner).  Per (cell c, corner k) at q = 8 c + k: the atoms of the
+// domain in ascending index and the inclusive sums of their weights 8 / m,
+// m the number of the cell's domains holding the atom.
+// ----------------------------------------------------------------------------
+struct GrownGeo {
+  double L0, L1, L2, r_dep;
+  int n0, n1, n2;
+};
+
+// domain bits (2d: low interval of axis d, 2d + 1: high one) and weight
+__device__ __forceinline__ int grown_bits(double px, double py, double pz, const GrownGeo &g,
+                                          int &w) {
+  const double pos[3] = {px, py, pz}, L[3] = {g.L0, g.L1, g.L2};
+  const int nc[3] = {g.n0, g.n1, g.n2};
+  int bits = 0, m = 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double e = L[d] / (double)nc[d];
+    const double ld = e - g.r_dep;
+    const int b = cell_coord(pos[d], L[d], nc[d]);
+    const double u = pos[d] - (double)b * e;
+    const int lo = u < ld, hi = u >= e - ld;
+    bits |= (lo << (2 * d)) | (hi << (2 * d + 1));
+    m *= lo + hi;
+  }
+  w = 8 / m;
+  return bits;
+}
+
+// one thread per (cell, corner): FILL false counts the domain's atoms into
+// cnt[q]; FILL true writes them from start[q]
+template <bool FILL>
+__global__ void __launch_bounds__(BLOCK)
+    k_grown_lists(int64_t ncells, const int32_t *__restrict__ cstart,
+                  const int32_t *__restrict__ catoms, const double *__restrict__ x,
+                  const double *__restrict__ y, const double *__restrict__ z, GrownGeo g,
+                  int32_t *cnt, const int32_t *__restrict__ start, int32_t *list, int32_t *cum) {
+  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (q >= 8 * ncells) return;
+  const int64_t c = q >> 3;
+  const int k = (int)(q & 7);
+  int32_t o = FILL ? start[q] : 0, acc = 0, m = 0;
+  for (int32_t j = cstart[c]; j < cstart[c + 1]; ++j) {
+    const int32_t i = catoms[j];
+    int w;
+    const int bits = grown_bits(x[i], y[i], z[i], g, w);
+    const bool in = ((bits >> (k & 1)) & 1) && ((bits >> (2 + ((k >> 1) & 1))) & 1) &&
+                    ((bits >> (4 + ((k >> 2) & 1))) & 1);
+    if (!in) continue;
+    acc += w;
+    if (FILL) {
+      list[o] = i;
+      cum[o] = acc;
+      ++o;
+    }
+    ++m;
+  }
+  if (!FILL) cnt[q] = m;
+}
+
 hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r) {
   Grid g{r.box[0], r.box[1], r.box[2], r.nc[0], r.nc[1], r.nc[2]};
   int32_t *count = c->cell_count + r.coff, *fill = c->cell_fill + r.coff;
@@ -207,6 +271,18 @@ hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r) {
                                               INT32_MAX, nullptr);
   k_cell_fill<<<grid_for(r.n), BLOCK, 0, c->stream>>>(r.n, x, y, z, g, fill, atoms, r.aoff);
   k_cell_sort<<<(unsigned)r.ncells, 64, 0, c->stream>>>(r.ncells, start, atoms);
+  if (c->grown) {  // single-system contexts only
+    GrownGeo gg{r.box[0], r.box[1], r.box[2], c->r_dep, r.nc[0], r.nc[1], r.nc[2]};
+    const int64_t nq = 8 * r.ncells;
+    k_grown_lists<false><<<grid_for(nq), BLOCK, 0, c->stream>>>(
+        r.ncells, start, atoms, x, y, z, gg, c->g_cnt, nullptr, nullptr, nullptr);
+    const int nch = (int)((nq + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    k_scan_sums<<<nch, 256, 0, c->stream>>>(nq, c->g_cnt, c->scan_tmp, INT32_MAX, nullptr);
+    k_scan_apply<<<nch, 256, 0, c->stream>>>(nq, c->g_cnt, c->scan_tmp, c->g_start, nullptr,
+                                             INT32_MAX, nullptr);
+    k_grown_lists<true><<<grid_for(nq), BLOCK, 0, c->stream>>>(
+        r.ncells, start, atoms, x, y, z, gg, nullptr, c->g_start, c->g_list, c->g_cum);
+  }
   return hipGetLastError();
 }
 

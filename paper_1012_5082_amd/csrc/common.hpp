@@ -452,6 +452,13 @@ struct vcsgc_ctx {
   // conjugate-gradient relaxation: direction d, start positions x0 and
   // forces f0 of the line search (3 n each), chunk values, totals
   double *cg = nullptr;
+  // grown domains (single system): cells of edge >= max(grow_edge, 2 r_dep),
+  // per (cell c, corner k) at q = 8 c + k the domain's atoms g_list and
+  // inclusive weight sums g_cum from g_start[q] to g_start[q + 1]; g_cnt the
+  // counts of the build
+  bool grown = false;
+  double grow_edge = 0.0;
+  int32_t *g_start = nullptr, *g_list = nullptr, *g_cum = nullptr, *g_cnt = nullptr;
   // Nose-Hoover barostat of md_verlet_step (off while npt_tau == 0): external
   // pressure (eV/A^3), coupling time, momentum pe (eV fs) and the last
   // virial (eV), host-side; npt_part: chunk values [2 ceil(n / 256) + 8];
@@ -587,9 +594,16 @@ void tstop(vcsgc_ctx *c, int h);
 
 // Stages per sweep of a single-system context: 8 ceil(ceil(N / N_cells) / k)
 // for local chains of k trials (8 ceil(N / N_cells) for k = 1).
+// active cells of a stage: the cells of one colour, or every cell with
+// grown domains (one trial in the stage's domain of each)
+inline int64_t active_cells(const vcsgc_ctx *c) {
+  return c->grown ? c->ncells : c->ncells / c->ncol;
+}
+
 inline int64_t stages_per_sweep(const vcsgc_ctx *c) {
   const int64_t m = (c->n + c->ncells - 1) / c->ncells;
-  return (int64_t)c->ncol * ((m + c->local_steps - 1) / c->local_steps);
+  const int64_t per_cell = (m + c->local_steps - 1) / c->local_steps;
+  return c->grown ? per_cell : (int64_t)c->ncol * per_cell;
 }
 
 hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r);

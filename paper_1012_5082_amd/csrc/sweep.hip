@@ -73,6 +73,10 @@ struct SweepArgs {
   double *u_rho, *u_v;
   // batched pipeline: stages per batch (at most SPEC_MAX and S / 2)
   int D;
+  // grown domains: every cell active, the stage's colour is the corner of
+  // the domain drawn in; per (cell, corner) the domain's atoms and weight sums
+  int grown;
+  const int32_t *gstart, *glist, *gcum;
 };
 
 __device__ __forceinline__ uint64_t sweep_of(const SweepArgs &a, uint64_t w) {
@@ -339,9 +343,26 @@ __device__ __forceinline__ void desc_du_group(const SweepArgs &a, int64_t i, int
   du = own + pair + emb;
 }
 
+// Grown domains: the site of draw w0 in domain (cell, corner) q, the first
+// atom whose inclusive weight sum exceeds floor(w0 W / 2^64), W the
+// domain's total weight (the domain holds at least one atom).
+__device__ __forceinline__ int32_t grown_pick(const SweepArgs &a, int64_t q, uint64_t w0) {
+  int32_t lo = a.gstart[q], hi = a.gstart[q + 1] - 1;
+  const uint32_t r = draw_index(w0, (uint32_t)a.gcum[hi]);
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((uint32_t)a.gcum[mid] > r)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return a.glist[lo];
+}
+
 // Cell of active-cell index t (< ncpc < 2^31) in a stage of the given colour:
 // cell (per ia + colour % per, per ib + (colour / per) % per, per ic + colour / per^2).
 __device__ __forceinline__ int64_t colour_cell(const SweepArgs &a, int colour, int64_t t) {
+  if (a.grown) return t;  // every cell is active
   const uint32_t P = (uint32_t)a.per;
   const uint32_t hx = (uint32_t)a.n0 / P, hy = (uint32_t)a.n1 / P;
   const uint32_t u = (uint32_t)t, q = u / hx, ia = u - q * hx, ic = q / hy, ib = q - ic * hy;
@@ -382,16 +403,18 @@ __global__ void __launch_bounds__(BLOCK) k_sites(SweepArgs a, uint64_t w_arg) {
   const int64_t s = q / a.ncpc, t = q - s * a.ncpc;
   const U4 g = philox(a.seed, a.replica, w, (uint64_t)s, 0, 0);
   if (t == 0) a.stage_lnug[s] = log(unit_open(g.v[1]));
-  const int64_t cell = colour_cell(a, stage_colour(g.v[0], a.ncol), t);
-  const int32_t st = a.cstart[cell];
-  const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
+  const int colour = stage_colour(g.v[0], a.ncol);
+  const int64_t cell = colour_cell(a, colour, t);
+  const int64_t gq = 8 * cell + colour;
+  const int32_t st = a.grown ? a.gstart[gq] : a.cstart[cell];
+  const uint32_t m = (uint32_t)((a.grown ? a.gstart[gq + 1] : a.cstart[cell + 1]) - st);
   // trial k of the cell's chain: Philox(key, (w, s, cell, 1 + k))
   for (int k = 0; k < a.K; ++k) {
     int32_t site = -1;
     double lnu = 0.0;
     if (m > 0) {
       const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1 + (uint64_t)k);
-      site = a.catoms[st + draw_index(r.v[0], m)];
+      site = a.grown ? grown_pick(a, gq, r.v[0]) : a.catoms[st + draw_index(r.v[0], m)];
       lnu = log(unit_open(r.v[1]));
     }
     a.sites[q * a.K + k] = site;
@@ -919,14 +942,16 @@ __device__ __forceinline__ void draw_site_g(const SweepArgs &a, uint64_t w, int6
                                             const U4 &g, int32_t *sites, double *lnus,
                                             double *lnug, double *lnus2) {
   if (t == 0) *lnug = log(unit_open(g.v[1]));
-  const int64_t cell = colour_cell(a, stage_colour(g.v[0], a.ncol), t);
-  const int32_t st = a.cstart[cell];
-  const uint32_t m = (uint32_t)(a.cstart[cell + 1] - st);
+  const int colour = stage_colour(g.v[0], a.ncol);
+  const int64_t cell = colour_cell(a, colour, t);
+  const int64_t gq = 8 * cell + colour;
+  const int32_t st = a.grown ? a.gstart[gq] : a.cstart[cell];
+  const uint32_t m = (uint32_t)((a.grown ? a.gstart[gq + 1] : a.cstart[cell + 1]) - st);
   int32_t site = -1;
   double lnu = 0.0;
   if (m > 0) {
     const U4 r = philox(a.seed, a.replica, w, (uint64_t)s, (uint64_t)cell, 1);
-    site = a.catoms[st + draw_index(r.v[0], m)];
+    site = a.grown ? grown_pick(a, gq, r.v[0]) : a.catoms[st + draw_index(r.v[0], m)];
     lnu = log(unit_open(r.v[1]));
     if (lnus2) lnus2[t] = log(unit_open(r.v[2]));
   }
@@ -1981,9 +2006,13 @@ hipError_t launch_sweeps(vcsgc_ctx *c, double dmu0, double kappa, double cbar, d
   a.n2 = c->nc[2];
   a.per = c->per;
   a.ncol = c->ncol;
-  a.ncpc = c->ncells / c->ncol;
+  a.ncpc = active_cells(c);
   a.K = c->local_steps;
   a.S = stages_per_sweep(c);
+  a.grown = c->grown ? 1 : 0;
+  a.gstart = c->g_start;
+  a.glist = c->g_list;
+  a.gcum = c->g_cum;
   a.beta = 1.0 / (KB * T);
   a.dmu0 = dmu0;
   a.kN = kappa / (double)c->n;
