@@ -1161,7 +1161,20 @@ vcsgc_status md_npt_steps(vcsgc_ctx *c, double dt, int64_t n_steps) {
   vcsgc_status st = npt_forces_sums(c, false, 1.0, h, &K, &vir);
   if (st) return st;
   double s_pend = 1.0;
+  // writes the thermostat and barostat state back (the velocities take the
+  // pending end-of-step factor)
+  auto finish = [&](double xi_, double eta_, double pe_) -> vcsgc_status {
+    VC_CHECK(c, vc::launch_scale_v(c, s_pend), "barostat");
+    th[0] = xi_;
+    th[1] = eta_;
+    VC_CHECK(c, hipMemcpyAsync(c->nvt, th, sizeof(th), hipMemcpyHostToDevice, c->stream), "copy");
+    VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+    c->npt_pe = pe_;
+    c->npt_vir = vir;
+    return VCSGC_OK;
+  };
   for (int64_t k = 0; k < n_steps; ++k) {
+    const double xi0 = xi, eta0 = eta, pe0 = pe;
     const double s = npt_thermo(h, g1kT, Q, W, K, pe, xi, eta);
     double V = c->box[0] * c->box[1] * c->box[2];
     double P = (2.0 * K + vir) / (3.0 * V);
@@ -1170,8 +1183,8 @@ vcsgc_status md_npt_steps(vcsgc_ctx *c, double dt, int64_t n_steps) {
     const double cv = std::exp(-(1.0 + 3.0 / g) * ve * (0.5 * h));
     const double q = std::exp(ve * h);
     const double L[3] = {c->box[0] * q * q, c->box[1] * q * q, c->box[2] * q * q};
-    if (!set_box(c, L)) {
-      VC_CHECK(c, vc::launch_scale_v(c, s_pend), "barostat");
+    if (!set_box(c, L)) {  // the state of the last complete step is kept
+      if ((st = finish(xi0, eta0, pe0))) return st;
       return fail(c, VCSGC_E_BOX_TOO_SMALL, "the box has shrunk below two search bins");
     }
     double lam[3], lmin = 1e300;
@@ -1196,14 +1209,7 @@ vcsgc_status md_npt_steps(vcsgc_ctx *c, double dt, int64_t n_steps) {
     pe = pe + h * (3.0 * V * (P - c->npt_p) + (3.0 / g) * (2.0 * K));
     s_pend = npt_thermo(h, g1kT, Q, W, K, pe, xi, eta);
   }
-  if (n_steps > 0) VC_CHECK(c, vc::launch_scale_v(c, s_pend), "barostat");
-  th[0] = xi;
-  th[1] = eta;
-  VC_CHECK(c, hipMemcpyAsync(c->nvt, th, sizeof(th), hipMemcpyHostToDevice, c->stream), "copy");
-  VC_CHECK(c, hipStreamSynchronize(c->stream), "sync");
-  c->npt_pe = pe;
-  c->npt_vir = vir;
-  return VCSGC_OK;
+  return finish(xi, eta, pe);
 }
 
 }  // namespace
