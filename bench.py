@@ -206,6 +206,45 @@ def _timed(fn):
     return out, a.elapsed_time(b) / 1e3
 
 
+def bench_production(args):
+    """The paper's production schedule on the polycrystal (Sec. IV.B): CG
+    relaxation of the grain boundaries, NPT equilibration at 700 K and zero
+    pressure, then VC-SGC MC/MD cycles of one sweep and 20 NPT steps of
+    2.5 fs; warmup cycles, then timed ones (sweep and MD timed apart)."""
+    from paper_1012_5082_amd import production as PR
+    from paper_1012_5082_amd import workloads as W
+    from paper_1012_5082_amd.binding import VCSGC
+    pot = potential(args.potential)
+    d = W.c3()
+    n = d["x"].size
+    g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
+              vz=d["vz"], forces=True, skin=args.skin)
+    st, k = args.tiling.split(":")
+    g.set_tuning(st, int(k))
+    s = PR.Schedule(dmu0=d["dmu0"], kappa=d["kappa"], cbar=d["cbar"], T=d["T"], seed=d["seed"])
+    pre = PR.relax_and_equilibrate(g, s)
+    log(f"production: relaxed ({pre['relax']['iterations']} line searches, {pre['relax_s']:.2f} s), "
+        f"equilibrated ({s.equil_steps} steps, {pre['equil_s']:.2f} s)")
+    PR.cycles(g, s, args.warmup, stats=False)
+    r = PR.cycles(g, s, args.steps)
+    out = {"metric": "MC trials/s and MD atom-steps/s on the production schedule",
+           "value": round(r["trials"] / r["mc_s"], 1), "unit": "trials/s",
+           "workload": f"c3-voronoi16 production schedule: {n} sites, CG relaxation, "
+                       f"{s.equil_steps} NPT steps, then cycles of 1 sweep + {s.md_per_sweep} "
+                       f"Nose-Hoover NPT steps of {s.dt} fs at {s.T} K, p = {s.p_ext} eV/A^3",
+           "cycles": args.steps, "warmup": args.warmup, "potential": args.potential,
+           "mc_ms_per_sweep": round(r["mc_s"] / args.steps * 1e3, 3),
+           "md_ms_per_step": round(r["md_s"] / (args.steps * s.md_per_sweep) * 1e3, 4),
+           "md_atom_steps_per_s": round(n * s.md_per_sweep * args.steps / r["md_s"], 1),
+           "stage_acceptance": round(r["stage_accepts"] / max(r["stages"], 1), 4),
+           "accepted_flips_per_s": round(r["flips"] / r["mc_s"], 1),
+           "relax": pre["relax"], "relax_s": round(pre["relax_s"], 3),
+           "equil_s": round(pre["equil_s"], 3), "box_after_equilibration": pre["box"],
+           "sweep_tiling": args.tiling}
+    g.close()
+    return out
+
+
 def bench_replicas(args):
     """64 rigid bcc replicas of uneven size on a T x kappa x cbar grid, all in
     one graph-captured persistent launch per call; tiling from the autotuner."""
@@ -387,8 +426,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
-                    help="c3: hybrid cycle (default line); c4: replica batch; c5: surrogate DA")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "production"],
+                    help="c3: hybrid cycle (default line); c4: replica batch; c5: surrogate DA; "
+                         "production: the paper's schedule (CG, NPT at 2.5 fs) on c3")
     ap.add_argument("--sweeps", type=int, default=0, help="c4/c5: timed sweeps")
     ap.add_argument("--local-steps", type=int, default=1,
                     help="c3: trials per active cell per stage (1 = the plain scheme)")
@@ -423,6 +463,9 @@ def main():
         return
     if args.workload == "c5":
         print(json.dumps(bench_surrogate(args)), flush=True)
+        return
+    if args.workload == "production":
+        print(json.dumps(bench_production(args)), flush=True)
         return
 
     from paper_1012_5082_amd import inputs as I

@@ -1,0 +1,59 @@
+"""The production schedule (paper_1012_5082_amd.production: CG relaxation,
+NPT equilibration, VC-SGC MC/MD cycles with NPT steps of 2.5 fs) on a small
+Voronoi polycrystal, against the same sequence of oracle calls, bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_1012_5082_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_production_schedule_matches_oracle(torch_cuda, oracle_mod):
+    O = oracle_mod
+    from paper_1012_5082_amd import production as PR
+    from paper_1012_5082_amd.binding import VCSGC
+    pot = I.params("FS-P1")
+    x, y, z, box, _ = I.voronoi_poly(12, 4, 23)
+    sp = I.initial_species(x.size, 0.04, 24)
+    vx, vy, vz = I.mb_velocities(sp, 700.0, 25)
+    # skin 0.1 A: before relaxation some boundary sites have 33 neighbours
+    # within rc + 0.3 A, more than a list row holds
+    g = VCSGC(x, y, z, box, sp, pot, vx=vx, vy=vy, vz=vz, forces=True, skin=0.1)
+    g.set_tuning("batch", 3)
+    s = PR.Schedule(dmu0=-0.25, cbar=0.04, relax_iter=30, equil_steps=40, tau_p=300.0, seed=99)
+    print(f"[production] n={x.size}", flush=True)
+    pre = PR.relax_and_equilibrate(g, s)
+    agg = PR.cycles(g, s, 3)
+
+    (x1, y1, z1, *_), ro, _ = O.cg(x, y, z, sp, box, pot, max_iter=s.relax_iter,
+                                    ftol=s.relax_ftol, dmax=s.relax_dmax)
+    assert pre["relax"] == ro
+    st, b, state, _ = O.md_npt(x1, y1, z1, vx, vy, vz, sp, box, pot, s.dt, s.equil_steps, s.T,
+                               s.tau_t, s.p_ext, s.tau_p)
+    assert pre["box"] == list(b)
+    spc, trials, flips = sp, 0, 0
+    for cyc in range(3):
+        ost = O.SweepState(*st[:3], b, spc, pot, vx=st[3], vy=st[4], vz=st[5])
+        ost.w = cyc
+        so, _, _ = O.sweep(ost, s.dmu0, s.kappa, s.cbar, s.T, 1, s.seed)
+        trials += so["trials"]
+        flips += so["flips"]
+        spc = ost.species
+        st, b, state, _ = O.md_npt(*st[:3], ost.vx, ost.vy, ost.vz, spc, b, pot, s.dt,
+                                   s.md_per_sweep, s.T, s.tau_t, s.p_ext, s.tau_p, *state)
+    assert (agg["trials"], agg["flips"]) == (trials, flips) and flips > 0
+    assert np.array_equal(g.species.cpu().numpy(), spc)
+    for nm, want in zip(("x", "y", "z", "vx", "vy", "vz"), st[:6]):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), want), nm
+    assert np.array_equal(g.barostat()[1], b)
+    g.close()
