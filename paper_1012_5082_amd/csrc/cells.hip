@@ -226,35 +226,65 @@ __device__ __forceinline__ int grown_bits(double px, double py, double pz, const
   return bits;
 }
 
-// one thread per (cell, corner): FILL false counts the domain's atoms into
-// cnt[q]; FILL true writes them from start[q]
+// One wave per cell, 64 of its atoms (ascending index) at a time: every lane
+// takes one atom's domain bits and weight, and per corner a ballot ranks the
+// members and a wave scan sums their weights.  FILL false writes the
+// domains' counts to cnt[8 c + k]; FILL true writes the lists from start[q].
+constexpr int GROWN_WAVES = BLOCK / 64;
+
 template <bool FILL>
 __global__ void __launch_bounds__(BLOCK)
     k_grown_lists(int64_t ncells, const int32_t *__restrict__ cstart,
                   const int32_t *__restrict__ catoms, const double *__restrict__ x,
                   const double *__restrict__ y, const double *__restrict__ z, GrownGeo g,
                   int32_t *cnt, const int32_t *__restrict__ start, int32_t *list, int32_t *cum) {
-  const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (q >= 8 * ncells) return;
-  const int64_t c = q >> 3;
-  const int k = (int)(q & 7);
-  int32_t o = FILL ? start[q] : 0, acc = 0, m = 0;
-  for (int32_t j = cstart[c]; j < cstart[c + 1]; ++j) {
-    const int32_t i = catoms[j];
-    int w;
-    const int bits = grown_bits(x[i], y[i], z[i], g, w);
-    const bool in = ((bits >> (k & 1)) & 1) && ((bits >> (2 + ((k >> 1) & 1))) & 1) &&
-                    ((bits >> (4 + ((k >> 2) & 1))) & 1);
-    if (!in) continue;
-    acc += w;
-    if (FILL) {
-      list[o] = i;
-      cum[o] = acc;
-      ++o;
-    }
-    ++m;
+  const int64_t c = (int64_t)blockIdx.x * GROWN_WAVES + threadIdx.x / 64;
+  if (c >= ncells) return;  // whole waves leave together
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int32_t off[8], run[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    off[k] = FILL ? start[8 * c + k] : 0;
+    run[k] = 0;
   }
-  if (!FILL) cnt[q] = m;
+  const int32_t lo = cstart[c], hi = cstart[c + 1];
+  for (int32_t j0 = lo; j0 < hi; j0 += 64) {
+    const int32_t j = j0 + lane;
+    int bits = 0, w = 0, i = 0;
+    if (j < hi) {
+      i = catoms[j];
+      bits = grown_bits(x[i], y[i], z[i], g, w);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool in = ((bits >> (k & 1)) & 1) && ((bits >> (2 + ((k >> 1) & 1))) & 1) &&
+                      ((bits >> (4 + ((k >> 2) & 1))) & 1);
+      const unsigned long long mask = __ballot(in);
+      if (FILL) {
+        // inclusive sum of the members' weights over the lanes up to this one
+        int v = in ? w : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int u = __shfl_up(v, d, 64);
+          if (lane >= d) v += u;
+        }
+        if (in) {
+          const int32_t o = off[k] + (int32_t)__popcll(mask & below);
+          list[o] = i;
+          cum[o] = run[k] + v;
+        }
+        run[k] += __shfl(v, 63, 64);
+      }
+      off[k] += (int32_t)__popcll(mask);
+    }
+  }
+  if (!FILL && lane < 8) {
+    int32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v = lane == k ? off[k] : v;
+    cnt[8 * c + lane] = v;
+  }
 }
 
 hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r) {
@@ -274,14 +304,15 @@ hipError_t launch_bin_cells(vcsgc_ctx *c, const RepHost &r) {
   if (c->grown) {  // single-system contexts only
     GrownGeo gg{r.box[0], r.box[1], r.box[2], c->r_dep, r.nc[0], r.nc[1], r.nc[2]};
     const int64_t nq = 8 * r.ncells;
-    k_grown_lists<false><<<grid_for(nq), BLOCK, 0, c->stream>>>(
-        r.ncells, start, atoms, x, y, z, gg, c->g_cnt, nullptr, nullptr, nullptr);
+    const unsigned gb = (unsigned)((r.ncells + GROWN_WAVES - 1) / GROWN_WAVES);
+    k_grown_lists<false><<<gb, BLOCK, 0, c->stream>>>(r.ncells, start, atoms, x, y, z, gg,
+                                                      c->g_cnt, nullptr, nullptr, nullptr);
     const int nch = (int)((nq + SCAN_CHUNK - 1) / SCAN_CHUNK);
     k_scan_sums<<<nch, 256, 0, c->stream>>>(nq, c->g_cnt, c->scan_tmp, INT32_MAX, nullptr);
     k_scan_apply<<<nch, 256, 0, c->stream>>>(nq, c->g_cnt, c->scan_tmp, c->g_start, nullptr,
                                              INT32_MAX, nullptr);
-    k_grown_lists<true><<<grid_for(nq), BLOCK, 0, c->stream>>>(
-        r.ncells, start, atoms, x, y, z, gg, nullptr, c->g_start, c->g_list, c->g_cum);
+    k_grown_lists<true><<<gb, BLOCK, 0, c->stream>>>(r.ncells, start, atoms, x, y, z, gg,
+                                                     nullptr, c->g_start, c->g_list, c->g_cum);
   }
   return hipGetLastError();
 }
