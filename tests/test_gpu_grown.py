@@ -123,6 +123,27 @@ def test_grown_many_cells(torch_cuda, oracle_mod):
     g.close()
 
 
+def test_grown_perfect_surrogate_equals_plain(torch_cuda, oracle_mod):
+    """Delayed acceptance with the exact dU as surrogate (one-stage and
+    batched pipelines) reproduces the plain grown-domain chain, which is the
+    oracle's."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = _thermal(seed=35)
+    args = (-0.3, 5.0, 0.1, 600.0)
+    st = O.SweepState(d["x"], d["y"], d["z"], d["box"], d["species"], pot)
+    so, _, _ = O.sweep(st, *args, 4, 515, grow_edge=1e-9)
+    for tiling in (("stage", 1), ("batch", 3)):
+        g = _ctx(d, pot, 1e-9)
+        g.set_surrogate("perfect")
+        g.set_tuning(*tiling)
+        print(f"[grown] perfect surrogate {tiling}", flush=True)
+        sg = g.sweep(*args, 4, 515)
+        _check(O, g, st, sg, so)
+        assert sg["stage1_pass"] == so["local_accepts"]
+        g.close()
+
+
 def test_grown_argument_checks(torch_cuda):
     from paper_1012_5082_amd.binding import VcsgcError
     pot = I.params("FS-P1")
