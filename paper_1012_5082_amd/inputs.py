@@ -84,8 +84,8 @@ def params(name: str = "FS-P1") -> EamFS:
 
 
 # --------------------------------------------------------------------------
-# Tabulated potentials (a general two-species EAM given by tables, the form
-# the paper's Fe-Cu potentials come in): f_A, f_B, phi_AA, phi_AB, phi_BB at
+# Tabulated potentials (a general two-species EAM given by tables, the form in
+# which published EAM potentials are distributed): f_A, f_B, phi_AA, phi_AB, phi_BB at
 # the radial knots r_k = k dr (k < nr), F_A, F_B at the density knots
 # rho_k = k drho (k < nrho).  Pair and density terms vanish for r >= rc.
 # The sets below tabulate closed forms on the knots; how the tables are
@@ -149,7 +149,33 @@ def table_x(dr: float = 0.01, drho: float = 0.05, rho_max: float = 80.0) -> EamT
                      lambda x, rho: -A[x] * np.sqrt(rho) + (0.002 + 0.001 * x) * rho)
 
 
-TABLE_SETS = {"TAB-FS1": lambda: table_fs(PARAM_SETS["FS-P1"]), "TAB-X": table_x}
+def _plateau(r, lo, hi, w):
+    """1 on [lo, hi], 0 farther than w outside it, a smooth cubic step between."""
+    def step(t):
+        t = np.clip(t, 0.0, 1.0)
+        return t * t * (3.0 - 2.0 * t)
+    return step((r - (lo - w)) / w) * step(((hi + w) - r) / w)
+
+
+def table_ising(U: float = 0.1, dr: float = 0.01) -> EamTable:
+    """The Ising-type bcc model of Sec. II.B as a tabulated pair model for
+    the rigid lattice (a = 2.87 A): phi_XY equals eps_XY(1) on a plateau
+    around the first-shell distance (2.49 A) and eps_XY(2) on one around the
+    second (2.87 A), zero beyond 3.05 A; f = F = 0, so U = 1/2 sum_ij phi.
+    eps_AA(1) = eps_BB(1) = -10 U, eps_AB(1) = -9.7 U, eps(2) = -2 U for
+    every pair (U in eV).  Every knot within two spacings of a shell
+    distance lies on its plateau, so the interpolant is exact there."""
+    e1 = (-10.0 * U, -9.7 * U, -10.0 * U)  # AA, AB, BB
+    e2 = -2.0 * U
+    return _tabulate(3.6, dr, 0.5, 1.0,
+                     lambda x, r: 0.0 * r,
+                     lambda k, r: e1[k] * _plateau(r, 2.35, 2.62, 0.05)
+                     + e2 * _plateau(r, 2.75, 3.0, 0.05),
+                     lambda x, rho: 0.0 * rho)
+
+
+TABLE_SETS = {"TAB-FS1": lambda: table_fs(PARAM_SETS["FS-P1"]), "TAB-X": table_x,
+              "ISING": table_ising}
 
 
 def table(name: str) -> EamTable:

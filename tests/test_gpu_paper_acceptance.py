@@ -1,0 +1,41 @@
+"""The paper's acceptance figures for its Ising-type model (Sec. III.C,
+Fig. 10 and the remarks that close the section) on the GPU: at c0 = 50%
+and the optimal dmu0 = 0 the serial VC-SGC-MC chain reaches about 47% and
+the parallel one, on the 40^3 lattice with the 64 domains of a 4 x 4 x 4
+decomposition active per stage, about 34%.  The model is the tabulated pair
+model inputs.table("ISING") on the rigid lattice, k_B T = 0.8617 U; 600
+sweeps from the 50% solid solution, the second half measured.
+"""
+import pytest
+
+from paper_1012_5082_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+U = 0.1
+T = 0.8617 * U / I.KB
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("n,kappa_u,want,cells", [(10, 1.0, 0.47, 8), (40, 0.1, 0.34, 512)])
+def test_paper_acceptance(torch_cuda, n, kappa_u, want, cells):
+    from paper_1012_5082_amd.binding import VCSGC
+    x, y, z, box = I.bcc(n, n, n)
+    g = VCSGC(x, y, z, box, I.initial_species(x.size, 0.5, 7), I.table("ISING"), r_dep=14.3)
+    assert g.info()["n_cells"] == [round(cells ** (1 / 3))] * 3
+    g.set_tuning("batch", 3)
+    args = (0.0, kappa_u * U, 0.5, T)
+    print(f"[paper] n={x.size} kappa={kappa_u} U", flush=True)
+    g.sweep(*args, 300, 11)
+    s = g.sweep(*args, 300, 11)
+    acc = s["flips"] / s["trials"]
+    assert abs(acc - want) <= 0.02, acc
+    assert abs(s["sum_n"] / 300 / x.size - 0.5) <= 0.01
+    g.close()
