@@ -39,3 +39,27 @@ def test_paper_acceptance(torch_cuda, n, kappa_u, want, cells):
     assert abs(acc - want) <= 0.02, acc
     assert abs(s["sum_n"] / 300 / x.size - 0.5) <= 0.01
     g.close()
+
+
+def test_weak_scaling_better_than_logarithmic(torch_cuda):
+    """Fig. 9: 2,000 sites per domain, dmu0 = 0, kappa = 10 U, c0 = 50%; the
+    acceptance falls more slowly than logarithmically with the number of
+    simultaneously active domains (1, 8, 64), and the composite moves are
+    rarely rejected as a whole."""
+    from paper_1012_5082_amd.binding import VCSGC
+    acc, stage = [], []
+    for q in (1, 2, 4):
+        n = 10 * q
+        x, y, z, box = I.bcc(n, n, n)
+        g = VCSGC(x, y, z, box, I.initial_species(x.size, 0.5, 7), I.table("ISING"), r_dep=14.3)
+        g.set_tuning("batch", 3)
+        args = (0.0, 10.0 * U, 0.5, T)
+        print(f"[paper] weak scaling, {q ** 3} domains", flush=True)
+        g.sweep(*args, 300, 11)
+        s = g.sweep(*args, 300, 11)
+        acc.append(s["flips"] / s["trials"])
+        stage.append(s["stage_accepts"] / s["stages"])
+        g.close()
+    assert acc[0] > acc[1] > acc[2] > 0.3
+    assert acc[0] - acc[1] > 1.5 * (acc[1] - acc[2])  # equal steps in ln p
+    assert min(stage[1:]) > 0.9
