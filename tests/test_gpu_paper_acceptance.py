@@ -63,3 +63,26 @@ def test_weak_scaling_better_than_logarithmic(torch_cuda):
     assert acc[0] > acc[1] > acc[2] > 0.3
     assert acc[0] - acc[1] > 1.5 * (acc[1] - acc[2])  # equal steps in ln p
     assert min(stage[1:]) > 0.9
+
+
+def test_dmu0_optimality(torch_cuda):
+    """Fig. 8 (c0 = 25%, inside the miscibility gap, 40^3 lattice, 64
+    domains): with a small kappa <c> follows dmu0, with a large one it stays
+    at c0 whatever dmu0; <c> = c0 and the acceptance is largest where dmu0
+    equals the driving force, 0 here by the model's A <-> B symmetry."""
+    from paper_1012_5082_amd.binding import VCSGC
+    x, y, z, box = I.bcc(40, 40, 40)
+    res = {}
+    for kt, dm in ((1.0, -0.3), (1.0, 0.3), (100.0, -0.3), (100.0, 0.0), (100.0, 0.3)):
+        g = VCSGC(x, y, z, box, I.initial_species(x.size, 0.25, 7), I.table("ISING"), r_dep=14.3)
+        g.set_tuning("batch", 3)
+        args = (dm * U, kt * U, 0.25, T)
+        print(f"[paper] kappa={kt} U dmu0={dm} U", flush=True)
+        g.sweep(*args, 150, 11)
+        s = g.sweep(*args, 150, 11)
+        res[(kt, dm)] = (s["flips"] / s["trials"], s["sum_n"] / 150 / x.size)
+        g.close()
+    assert res[(1.0, -0.3)][1] - res[(1.0, 0.3)][1] > 0.2
+    for dm in (-0.3, 0.0, 0.3):
+        assert abs(res[(100.0, dm)][1] - 0.25) < 0.005
+    assert res[(100.0, 0.0)][0] > max(res[(100.0, -0.3)][0], res[(100.0, 0.3)][0]) + 0.1
