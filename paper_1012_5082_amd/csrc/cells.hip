@@ -706,8 +706,10 @@ __global__ void __launch_bounds__(BLOCK)
   __shared__ int own_si[OWN_CAP];           // staged index of own atom q
   __shared__ unsigned char own_b[OWN_CAP];  // staged bin of own atom q
   __shared__ int own_off[NST];
-  // column t: staged indices of lane t's hits, its own atom among them
-  __shared__ unsigned short hit[KMAX + 1][BLOCK];
+  // column t: staged indices of lane t's hits, its own atom among them; the
+  // slot after the last hit takes every later candidate, so with KMAX
+  // neighbours (KMAX + 1 hits) that slot is row KMAX + 1, past the last hit
+  __shared__ unsigned short hit[KMAX + 2][BLOCK];
   __shared__ int2 wtot[BLOCK / 64];
   const int tid = threadIdx.x;
   const int xcd = (int)(blockIdx.x & 7u);
@@ -814,7 +816,7 @@ __global__ void __launch_bounds__(BLOCK)
             for (int v = 0; v < 4; ++v) {
               const float dx = cc[v].x - me.x, dyy = cc[v].y - me.y, dzz = cc[v].z - me.z;
               const float d2 = __builtin_fmaf(dzz, dzz, __builtin_fmaf(dyy, dyy, dx * dx));
-              hit[min(c, KMAX)][tid] = (unsigned short)(k0 + v);
+              hit[min(c, KMAX + 1)][tid] = (unsigned short)(k0 + v);
               c += (k0 + v < a1 && d2 < cut2f) ? 1 : 0;
             }
           }
@@ -823,7 +825,7 @@ __global__ void __launch_bounds__(BLOCK)
       // stored slot in its place (the own slot is the last one, or the last
       // one lies beyond the entries read)
       const int nb = c - 1, cc = nb < KMAX ? nb : KMAX;
-      const int last = hit[min(c - 1, KMAX)][tid];
+      const int last = hit[min(c - 1, KMAX + 1)][tid];
 #pragma unroll
       for (int u = 0; u < KMAX; u += 4) {
         int32_t w[4];

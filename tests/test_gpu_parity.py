@@ -192,6 +192,41 @@ def test_eam_parity_dense_bins(torch_cuda, oracle_mod, kind):
     g.close()
 
 
+def test_eam_parity_full_rows(torch_cuda, oracle_mod):
+    """Every row of the MD list full: a simple-cubic lattice of edge 1.7 A
+    gives each atom exactly 32 neighbours within rc + skin (skin 0.1 A),
+    all of them within rc (shells at 1.7, 2.40, 2.94 and 3.4 A; the next at
+    3.80 A).  The lists come from the region search (eleven search bins per
+    axis, grown to 32 slots).  A row holding the largest count must keep
+    every neighbour: energies and forces equal the oracle's bit for bit."""
+    cells = 24
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    a = 1.7
+    k = (np.arange(cells) + 0.5) * a
+    x, y, z = [v.ravel().copy() for v in np.meshgrid(k, k, k, indexing="ij")]
+    rng = np.random.default_rng(71 + cells)
+    for v in (x, y, z):
+        v += rng.uniform(-0.005, 0.005, v.size)
+    box = np.full(3, cells * a)
+    sp = I.initial_species(x.size, 0.2, 72)
+    wide = O.neighbors(x, y, z, box, pot.rc + 0.1 + 1e-3, vectors=False)
+    near = O.neighbors(x, y, z, box, pot.rc, vectors=False)
+    assert np.all(np.diff(wide.start) == 32) and np.all(np.diff(near.start) == 32)
+    g = gpu_context(dict(x=x, y=y, z=z, box=box, species=sp), pot, forces=True, skin=0.1)
+    U = g.energy(forces=True)
+    st = O.SweepState(x, y, z, box, sp, pot)
+    e_o = O.energy_atoms(st.nl, st.species, pot, st.rho)
+    assert np.array_equal(g.atom_energies().cpu().numpy(), e_o)
+    assert abs(U - math.fsum(e_o)) <= 1e-12 * abs(U)
+    fo = O.forces(O.neighbors(x, y, z, box, pot.rc), sp, pot, st.rho)
+    for got, want in zip((g.fx, g.fy, g.fz), fo):
+        assert np.array_equal(got.cpu().numpy(), want)
+    info = g.info()
+    assert info["md_pairs"] == 32 * x.size
+    g.close()
+
+
 def _sweep_parity(O, d, pot, n_sweeps, kappa=None, cbar=None, log=True, chunks=None,
                   strategy="graph", trials_per_group=1):
     kappa = d["kappa"] if kappa is None else kappa
