@@ -753,13 +753,14 @@ __global__ void __launch_bounds__(BLOCK)
     }
     if (tid == 0) off[NST] = tot.x;
     block_sync_lds();
-    // stage: staged atom c of bin u (off[u] <= c < off[u + 1]); four in flight
+    // stage: staged atom c of bin u (off[u] <= c < off[u + 1]); two in flight
+    // (four raised the kernel past 128 registers, to three waves per SIMD)
 #pragma unroll 1
-    for (int c0 = 0; c0 < tot.x; c0 += 4 * BLOCK) {
-      double4 p[4];
-      int uu[4];
+    for (int c0 = 0; c0 < tot.x; c0 += 2 * BLOCK) {
+      double4 p[2];
+      int uu[2];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 2; ++k) {
         const int c = c0 + k * BLOCK + tid;
         uu[k] = -1;
         if (c < tot.x) {
@@ -773,7 +774,7 @@ __global__ void __launch_bounds__(BLOCK)
         }
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 2; ++k) {
         const int u = uu[k];
         if (u >= 0) {
           const int c = c0 + k * BLOCK + tid;

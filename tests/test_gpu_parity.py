@@ -213,7 +213,9 @@ def test_eam_parity_full_rows(torch_cuda, oracle_mod):
     wide = O.neighbors(x, y, z, box, pot.rc + 0.1 + 1e-3, vectors=False)
     near = O.neighbors(x, y, z, box, pot.rc, vectors=False)
     assert np.all(np.diff(wide.start) == 32) and np.all(np.diff(near.start) == 32)
-    g = gpu_context(dict(x=x, y=y, z=z, box=box, species=sp), pot, forces=True, skin=0.1)
+    zero = np.zeros(x.size)
+    d = dict(x=x, y=y, z=z, vx=zero, vy=zero, vz=zero, box=box, species=sp)
+    g = gpu_context(d, pot, velocities=True, skin=0.1)
     U = g.energy(forces=True)
     st = O.SweepState(x, y, z, box, sp, pot)
     e_o = O.energy_atoms(st.nl, st.species, pot, st.rho)
@@ -224,6 +226,20 @@ def test_eam_parity_full_rows(torch_cuda, oracle_mod):
         assert np.array_equal(got.cpu().numpy(), want)
     info = g.info()
     assert info["md_pairs"] == 32 * x.size
+    # two MD steps of 0.1 fs (no rebuild), then a sweep on the r < rc rows
+    # filtered out of the full MD rows
+    g.md(0.1, 2)
+    out = O.md(x, y, z, zero, zero, zero, sp, box, pot, 0.1, 2)
+    for nm, want in zip(("x", "y", "z", "vx", "vy", "vz"), out[:6]):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), want), nm
+    s_g = g.sweep(0.0, 1000.0, 0.2, 600.0, 1, 73)
+    st2 = O.SweepState(out[0], out[1], out[2], box, sp, pot, vx=out[3], vy=out[4], vz=out[5])
+    s_o, _, _ = O.sweep(st2, 0.0, 1000.0, 0.2, 600.0, 1, 73)
+    assert g.info()["mc_pairs"] == 32 * x.size
+    for k in ("trials", "local_accepts", "stages", "stage_accepts", "flips", "n_final"):
+        assert s_g[k] == s_o[k], k
+    assert np.array_equal(g.species.cpu().numpy(), st2.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st2.rho)
     g.close()
 
 
