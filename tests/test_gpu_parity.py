@@ -192,16 +192,10 @@ def test_eam_parity_dense_bins(torch_cuda, oracle_mod, kind):
     g.close()
 
 
-def test_eam_parity_full_rows(torch_cuda, oracle_mod):
-    """Every row of the MD list full: a simple-cubic lattice of edge 1.7 A
-    gives each atom exactly 32 neighbours within rc + skin (skin 0.1 A),
-    all of them within rc (shells at 1.7, 2.40, 2.94 and 3.4 A; the next at
-    3.80 A).  The lists come from the region search (eleven search bins per
-    axis, grown to 32 slots).  A row holding the largest count must keep
-    every neighbour: energies and forces equal the oracle's bit for bit."""
-    cells = 24
-    O = oracle_mod
-    pot = I.params("FS-P1")
+def _full_rows_system(cells=24):
+    """A simple-cubic lattice of edge 1.7 A (0.005 A of noise): every atom
+    has exactly 32 neighbours within rc + 0.1 A, all of them within rc
+    (shells at 1.7, 2.40, 2.94 and 3.4 A; the next at 3.80 A)."""
     a = 1.7
     k = (np.arange(cells) + 0.5) * a
     x, y, z = [v.ravel().copy() for v in np.meshgrid(k, k, k, indexing="ij")]
@@ -210,6 +204,19 @@ def test_eam_parity_full_rows(torch_cuda, oracle_mod):
         v += rng.uniform(-0.005, 0.005, v.size)
     box = np.full(3, cells * a)
     sp = I.initial_species(x.size, 0.2, 72)
+    return dict(x=x, y=y, z=z, box=box, species=sp, dmu0=0.0, kappa=1000.0, cbar=0.2, T=600.0,
+                seed=73)
+
+
+def test_eam_parity_full_rows(torch_cuda, oracle_mod):
+    """Every row of the MD list full (the lattice above with an MD-list skin
+    of 0.1 A).  The lists come from the region search (eleven search bins
+    per axis, grown to 32 slots).  A row holding the largest count must keep
+    every neighbour: energies and forces equal the oracle's bit for bit."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    s = _full_rows_system()
+    x, y, z, box, sp = s["x"], s["y"], s["z"], s["box"], s["species"]
     wide = O.neighbors(x, y, z, box, pot.rc + 0.1 + 1e-3, vectors=False)
     near = O.neighbors(x, y, z, box, pot.rc, vectors=False)
     assert np.all(np.diff(wide.start) == 32) and np.all(np.diff(near.start) == 32)
@@ -241,6 +248,16 @@ def test_eam_parity_full_rows(torch_cuda, oracle_mod):
     assert np.array_equal(g.species.cpu().numpy(), st2.species)
     assert np.array_equal(g.rho().cpu().numpy(), st2.rho)
     g.close()
+
+
+@pytest.mark.parametrize("strategy,tpg", [("graph", 1), ("stage", 1), ("persistent", 1),
+                                          ("batch", 3)])
+def test_sweep_full_rows(torch_cuda, oracle_mod, strategy, tpg):
+    """Every MC row full (32 neighbours within rc for every atom): each sweep
+    strategy reproduces the oracle's chain over two sweeps."""
+    r = _sweep_parity(oracle_mod, _full_rows_system(), I.params("FS-P1"), 2,
+                      log=strategy != "batch", strategy=strategy, trials_per_group=tpg)
+    assert r["flips"] > 0
 
 
 def _sweep_parity(O, d, pot, n_sweeps, kappa=None, cbar=None, log=True, chunks=None,
