@@ -260,6 +260,26 @@ def test_sweep_full_rows(torch_cuda, oracle_mod, strategy, tpg):
     assert r["flips"] > 0
 
 
+def test_local_chain_full_rows(torch_cuda, oracle_mod):
+    """Local chains of 2 trials per cell and stage on full MC rows: the chain
+    (statistics, species and densities) equals the oracle's."""
+    O = oracle_mod
+    pot = I.params("FS-P1")
+    d = _full_rows_system()
+    args = (d["dmu0"], 5.0, d["cbar"], d["T"])
+    g = gpu_context(d, pot)
+    g.set_local_steps(2)
+    sg = g.sweep(*args, 2, d["seed"])
+    st = oracle_state(O, d, pot)
+    so, _, _ = O.sweep(st, *args, 2, d["seed"], local_steps=2)
+    for key in ("trials", "local_accepts", "stages", "stage_accepts", "flips", "n_final"):
+        assert sg[key] == so[key], key
+    assert sg["flips"] > 0
+    assert np.array_equal(g.species.cpu().numpy(), st.species)
+    assert np.array_equal(g.rho().cpu().numpy(), st.rho)
+    g.close()
+
+
 def _sweep_parity(O, d, pot, n_sweeps, kappa=None, cbar=None, log=True, chunks=None,
                   strategy="graph", trials_per_group=1):
     kappa = d["kappa"] if kappa is None else kappa
