@@ -57,3 +57,41 @@ def test_production_schedule_matches_oracle(torch_cuda, oracle_mod):
         assert np.array_equal(getattr(g, nm).cpu().numpy(), want), nm
     assert np.array_equal(g.barostat()[1], b)
     g.close()
+
+
+def test_production_resume_from_checkpoint(torch_cuda):
+    """A production run checkpointed after two cycles (positions,
+    velocities, species, box, the thermostat's xi and eta, the barostat's
+    momentum, the sweep counter and seed) and resumed in a fresh context
+    ends bit for bit where the uninterrupted run ends two cycles later."""
+    from paper_1012_5082_amd import production as PR
+    from paper_1012_5082_amd.binding import VCSGC
+    pot = I.params("FS-P1")
+    x, y, z, box, _ = I.voronoi_poly(12, 4, 23)
+    sp = I.initial_species(x.size, 0.04, 24)
+    vx, vy, vz = I.mb_velocities(sp, 700.0, 25)
+    s = PR.Schedule(dmu0=-0.25, cbar=0.04, relax_iter=30, equil_steps=40, tau_p=300.0, seed=99)
+    g = VCSGC(x, y, z, box, sp, pot, vx=vx, vy=vy, vz=vz, forces=True, skin=0.1)
+    g.set_tuning("batch", 3)
+    PR.relax_and_equilibrate(g, s)
+    PR.cycles(g, s, 2)
+    ck = {nm: getattr(g, nm).cpu().numpy().copy() for nm in ("x", "y", "z", "vx", "vy", "vz")}
+    ck["species"] = g.species.cpu().numpy().copy()
+    pe, bx, _ = g.barostat()
+    xi, eta = g.thermostat()
+    state = g.get_state()
+    a = PR.cycles(g, s, 2)
+    g2 = VCSGC(ck["x"], ck["y"], ck["z"], np.asarray(bx), ck["species"], pot, vx=ck["vx"],
+               vy=ck["vy"], vz=ck["vz"], forces=True, skin=0.1)
+    g2.set_tuning("batch", 3)
+    g2.set_thermostat(s.T, s.tau_t, xi, eta)
+    g2.set_barostat(s.p_ext, s.tau_p, pe)
+    g2.set_state(state["sweeps_done"], state["seed"])
+    b = PR.cycles(g2, s, 2)
+    assert (a["trials"], a["flips"]) == (b["trials"], b["flips"]) and a["flips"] > 0
+    for nm in ("x", "y", "z", "vx", "vy", "vz", "species"):
+        assert np.array_equal(getattr(g, nm).cpu().numpy(), getattr(g2, nm).cpu().numpy()), nm
+    assert np.array_equal(g.barostat()[1], g2.barostat()[1])
+    assert g.thermostat() == g2.thermostat()
+    g.close()
+    g2.close()
