@@ -18,7 +18,9 @@ def torch_cuda():
     return torch
 
 
-def test_production_schedule_matches_oracle(torch_cuda, oracle_mod):
+@pytest.mark.parametrize("colours,grow_edge", [(8, 0.0), (27, 0.0), (8, 15.0)])
+def test_production_schedule_matches_oracle(torch_cuda, oracle_mod, colours, grow_edge):
+    """With the octant scheme, 27 colours and grown domains (cells of 17.2 A)."""
     O = oracle_mod
     from paper_1012_5082_amd import production as PR
     from paper_1012_5082_amd.binding import VCSGC
@@ -28,10 +30,11 @@ def test_production_schedule_matches_oracle(torch_cuda, oracle_mod):
     vx, vy, vz = I.mb_velocities(sp, 700.0, 25)
     # skin 0.1 A: before relaxation some boundary sites have 33 neighbours
     # within rc + 0.3 A, more than a list row holds
-    g = VCSGC(x, y, z, box, sp, pot, vx=vx, vy=vy, vz=vz, forces=True, skin=0.1)
+    g = VCSGC(x, y, z, box, sp, pot, vx=vx, vy=vy, vz=vz, forces=True, skin=0.1,
+              colours=colours, grow_edge=grow_edge)
     g.set_tuning("batch", 3)
     s = PR.Schedule(dmu0=-0.25, cbar=0.04, relax_iter=30, equil_steps=40, tau_p=300.0, seed=99)
-    print(f"[production] n={x.size}", flush=True)
+    print(f"[production] n={x.size} colours={colours} grow_edge={grow_edge}", flush=True)
     pre = PR.relax_and_equilibrate(g, s)
     agg = PR.cycles(g, s, 3)
 
@@ -45,7 +48,8 @@ def test_production_schedule_matches_oracle(torch_cuda, oracle_mod):
     for cyc in range(3):
         ost = O.SweepState(*st[:3], b, spc, pot, vx=st[3], vy=st[4], vz=st[5])
         ost.w = cyc
-        so, _, _ = O.sweep(ost, s.dmu0, s.kappa, s.cbar, s.T, 1, s.seed)
+        so, _, _ = O.sweep(ost, s.dmu0, s.kappa, s.cbar, s.T, 1, s.seed,
+                           colour_period=3 if colours == 27 else 2, grow_edge=grow_edge)
         trials += so["trials"]
         flips += so["flips"]
         spc = ost.species
