@@ -18,13 +18,23 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("colours,grow_edge", [(8, 0.0), (27, 0.0), (8, 15.0)])
-def test_production_schedule_matches_oracle(torch_cuda, oracle_mod, colours, grow_edge):
-    """With the octant scheme, 27 colours and grown domains (cells of 17.2 A)."""
+@pytest.mark.parametrize("colours,grow_edge,potential", [(8, 0.0, "FS-P1"), (27, 0.0, "FS-P1"),
+                                                       (8, 15.0, "FS-P1"), (8, 0.0, "setfl")])
+def test_production_schedule_matches_oracle(torch_cuda, oracle_mod, tmp_path, colours, grow_edge,
+                                            potential):
+    """With the octant scheme, 27 colours and grown domains (cells of 17.2 A),
+    and with a tabulated potential read from a setfl file (TAB-X written as
+    setfl and read back)."""
     O = oracle_mod
     from paper_1012_5082_amd import production as PR
     from paper_1012_5082_amd.binding import VCSGC
-    pot = I.params("FS-P1")
+    if potential == "setfl":
+        from paper_1012_5082_amd import setfl
+        path = str(tmp_path / "tab_x.eam.alloy")
+        setfl.write(path, I.table("TAB-X"))
+        pot = setfl.read(path)[0]
+    else:
+        pot = I.params(potential)
     x, y, z, box, _ = I.voronoi_poly(12, 4, 23)
     sp = I.initial_species(x.size, 0.04, 24)
     vx, vy, vz = I.mb_velocities(sp, 700.0, 25)
