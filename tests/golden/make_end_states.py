@@ -8,11 +8,15 @@ tests/test_oracle_omp.py checks).
                  600 K, its calibrated dmu0) at cbar = 0.02, 0.05, 0.10
   c3_hybrid      the 1.96M-site polycrystal with Maxwell-Boltzmann velocities:
                  one sweep, 20 velocity-Verlet steps of 1 fs, one more sweep
+  c3_production  the same polycrystal on the production schedule's path: 3
+                 conjugate-gradient line searches, 4 Nose-Hoover NPT steps of
+                 2.5 fs (700 K, zero pressure, 100 and 1000 fs coupling
+                 times), one sweep
 
 Each entry holds the sweep statistics and SHA-256 digests of the species,
 density cache (and, for c3_hybrid, positions and velocities) as raw bytes.
 
-    python tests/golden/make_end_states.py [c2] [c3]
+    python tests/golden/make_end_states.py [c2] [c3] [c3p]
 """
 from __future__ import annotations
 
@@ -79,6 +83,22 @@ def c3_hybrid():
             "vx": digest(st2.vx), "vy": digest(st2.vy), "vz": digest(st2.vz)}
 
 
+def c3_production():
+    pot = I.params("FS-P1")
+    d = W.c3()
+    (x1, y1, z1, *_), relax, _ = O.cg(d["x"], d["y"], d["z"], d["species"], d["box"], pot,
+                                      max_iter=3, ftol=1e-3, dmax=0.1)
+    st, box, state, _ = O.md_npt(x1, y1, z1, d["vx"], d["vy"], d["vz"], d["species"], d["box"],
+                                 pot, 2.5, 4, 700.0, 100.0, 0.0, 1000.0)
+    ost = O.SweepState(*st[:3], box, d["species"], pot, vx=st[3], vy=st[4], vz=st[5])
+    s1, _ = O.sweep_omp(ost, d["dmu0"], d["kappa"], d["cbar"], d["T"], 1, d["seed"])
+    return {"dmu0": d["dmu0"], "n_sites": int(d["x"].size), "relax": relax,
+            "box": [float(v) for v in box], "stats": {k: s1[k] for k in STAT_KEYS},
+            "species": digest(ost.species), "rho": digest(ost.rho),
+            "x": digest(st[0]), "y": digest(st[1]), "z": digest(st[2]),
+            "vx": digest(ost.vx), "vy": digest(ost.vy), "vz": digest(ost.vz)}
+
+
 def main():
     what = sys.argv[1:] or ["c2", "c3"]
     res = json.load(open(OUT)) if os.path.exists(OUT) else {}
@@ -89,6 +109,9 @@ def main():
     if "c3" in what:
         res["c3_hybrid"] = c3_hybrid()
         print(f"c3 done ({time.time() - t0:.0f} s)", flush=True)
+    if "c3p" in what:
+        res["c3_production"] = c3_production()
+        print(f"c3p done ({time.time() - t0:.0f} s)", flush=True)
     with open(OUT, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)
     print("wrote", OUT)

@@ -79,7 +79,7 @@ def c3_data():
 
 
 def test_c3_bench_path_hybrid_cycle(torch_cuda, golden, c3_data):
-    """The benchmark's path at its shape: batched pipeline (16 stages per
+    """The benchmark's path at its shape: batched pipeline (3 stages per
     batch) with velocities, [sweep; 20 MD steps] then a sweep on the list
     and density taken from the MD pass."""
     want = golden["c3_hybrid"]
@@ -87,7 +87,7 @@ def test_c3_bench_path_hybrid_cycle(torch_cuda, golden, c3_data):
     assert d["dmu0"] == want["dmu0"] and d["x"].size == want["n_sites"]
     pot = I.params("FS-P1")
     g = gpu_context(d, pot, velocities=True)
-    g.set_tuning("batch", 16)
+    g.set_tuning("batch", 3)
     args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
     s1 = g.sweep(*args, 1, d["seed"])
     for k in STAT_KEYS:
@@ -97,6 +97,31 @@ def test_c3_bench_path_hybrid_cycle(torch_cuda, golden, c3_data):
     for k in STAT_KEYS:
         assert tot[k] == want["stats"][k], (k, tot[k], want["stats"][k], tot["near_ties"])
     assert tot["stage_accepts"] > 0 and tot["flips"] > 0
+    for nm in ("species", "x", "y", "z", "vx", "vy", "vz"):
+        assert digest(getattr(g, nm)) == want[nm], nm
+    assert digest(g.rho()) == want["rho"]
+    g.close()
+
+
+def test_c3_production_path(torch_cuda, golden, c3_data):
+    """The production schedule's path at full size: 3 conjugate-gradient line
+    searches, 4 Nose-Hoover NPT steps of 2.5 fs and a sweep on the batched
+    pipeline, against the oracle's end state (relaxation result, box,
+    statistics and digests of the state)."""
+    want = golden["c3_production"]
+    d = c3_data
+    assert d["dmu0"] == want["dmu0"] and d["x"].size == want["n_sites"]
+    pot = I.params("FS-P1")
+    g = gpu_context(d, pot, velocities=True)
+    assert g.minimize(max_iter=3, ftol=1e-3, dmax=0.1) == want["relax"]
+    g.set_thermostat(700.0, 100.0)
+    g.set_barostat(0.0, 1000.0)
+    g.md(2.5, 4)
+    assert [float(v) for v in g.barostat()[1]] == want["box"]
+    g.set_tuning("batch", 3)
+    s1 = g.sweep(d["dmu0"], d["kappa"], d["cbar"], d["T"], 1, d["seed"])
+    for k in STAT_KEYS:
+        assert s1[k] == want["stats"][k], (k, s1[k], want["stats"][k], s1["near_ties"])
     for nm in ("species", "x", "y", "z", "vx", "vy", "vz"):
         assert digest(getattr(g, nm)) == want[nm], nm
     assert digest(g.rho()) == want["rho"]
