@@ -128,6 +128,31 @@ def test_c3_production_path(torch_cuda, golden, c3_data):
     g.close()
 
 
+@pytest.mark.parametrize("colours,grow_edge", [(27, 0.0), (8, 15.1)])
+def test_c3_finer_schemes_sweep(torch_cuda, oracle_mod, c3_data, colours, grow_edge):
+    """27 colours and grown domains (cells of 15.9 A) at full size on the
+    batched pipeline with velocities: two sweeps against the serial oracle."""
+    from paper_1012_5082_amd.binding import VCSGC
+    O = oracle_mod
+    d = c3_data
+    pot = I.params("FS-P1")
+    g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
+              vz=d["vz"], colours=colours, grow_edge=grow_edge)
+    g.set_tuning("batch", 3)
+    args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
+    sg = g.sweep(*args, 2, d["seed"])
+    st = oracle_state(O, d, pot, velocities=True)
+    so, _, _ = O.sweep(st, *args, 2, d["seed"], colour_period=3 if colours == 27 else 2,
+                       grow_edge=grow_edge)
+    for k in STAT_KEYS:
+        assert sg[k] == so[k], (k, sg[k], so[k], sg["near_ties"])
+    assert sg["flips"] > 0
+    for nm in ("species", "vx", "vy", "vz"):
+        assert digest(getattr(g, nm)) == digest(getattr(st, nm)), nm
+    assert digest(g.rho()) == digest(st.rho)
+    g.close()
+
+
 def test_c4_replica_batch_matches_oracle(torch_cuda, oracle_mod):
     """All 64 replicas of the replica workload (sizes 2,000 to 250,000, one
     persistent launch per call, on two tilings): every replica equals its own
