@@ -153,6 +153,38 @@ def test_c3_finer_schemes_sweep(torch_cuda, oracle_mod, c3_data, colours, grow_e
     g.close()
 
 
+def test_c3_tabulated_hybrid(torch_cuda, oracle_mod, c3_data):
+    """The tabulated form of the potential (TAB-FS1) at full size: a sweep
+    on the batched pipeline, 2 MD steps and a sweep, against the oracle."""
+    from paper_1012_5082_amd.binding import VCSGC
+    O = oracle_mod
+    d = c3_data
+    pot = I.table("TAB-FS1")
+    g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
+              vz=d["vz"])
+    g.set_tuning("batch", 3)
+    args = (d["dmu0"], d["kappa"], d["cbar"], d["T"])
+    s1 = g.sweep(*args, 1, d["seed"])
+    g.md(1.0, 2)
+    tot = add(s1, g.sweep(*args, 1, d["seed"]))
+    st = oracle_state(O, d, pot, velocities=True)
+    o1, _, _ = O.sweep(st, *args, 1, d["seed"])
+    x, y, z, vx, vy, vz, *_ = O.md(d["x"], d["y"], d["z"], st.vx, st.vy, st.vz, st.species,
+                                   d["box"], pot, 1.0, 2)
+    st2 = O.SweepState(x, y, z, d["box"], st.species, pot, vx=vx, vy=vy, vz=vz)
+    st2.w = 1
+    o2, _, _ = O.sweep(st2, *args, 1, d["seed"])
+    want = add(o1, o2)
+    for k in STAT_KEYS:
+        assert tot[k] == want[k], (k, tot[k], want[k], tot["near_ties"])
+    assert tot["flips"] > 0
+    for nm, ref in (("species", st2.species), ("x", x), ("y", y), ("z", z), ("vx", st2.vx),
+                    ("vy", st2.vy), ("vz", st2.vz)):
+        assert digest(getattr(g, nm)) == digest(ref), nm
+    assert digest(g.rho()) == digest(st2.rho)
+    g.close()
+
+
 def test_c4_replica_batch_matches_oracle(torch_cuda, oracle_mod):
     """All 64 replicas of the replica workload (sizes 2,000 to 250,000, one
     persistent launch per call, on two tilings): every replica equals its own
