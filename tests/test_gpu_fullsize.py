@@ -185,6 +185,30 @@ def test_c3_tabulated_hybrid(torch_cuda, oracle_mod, c3_data):
     g.close()
 
 
+def test_c3_local_chains(torch_cuda, oracle_mod, c3_data):
+    """Local chains of 2 trials per cell and stage at full size (per-stage
+    kernels, velocities; kappa = 100 eV, where some stages are accepted):
+    two sweeps against the serial oracle."""
+    from paper_1012_5082_amd.binding import VCSGC
+    O = oracle_mod
+    d = c3_data
+    pot = I.params("FS-P1")
+    g = VCSGC(d["x"], d["y"], d["z"], d["box"], d["species"], pot, vx=d["vx"], vy=d["vy"],
+              vz=d["vz"])
+    g.set_local_steps(2)
+    args = (d["dmu0"], 100.0, d["cbar"], d["T"])
+    sg = g.sweep(*args, 2, d["seed"])
+    st = oracle_state(O, d, pot, velocities=True)
+    so, _, _ = O.sweep(st, *args, 2, d["seed"], local_steps=2)
+    for k in STAT_KEYS:
+        assert sg[k] == so[k], (k, sg[k], so[k], sg["near_ties"])
+    assert sg["stage_accepts"] > 0 and sg["local_accepts"] > sg["flips"] > 0
+    for nm in ("species", "vx", "vy", "vz"):
+        assert digest(getattr(g, nm)) == digest(getattr(st, nm)), nm
+    assert digest(g.rho()) == digest(st.rho)
+    g.close()
+
+
 def test_c4_replica_batch_matches_oracle(torch_cuda, oracle_mod):
     """All 64 replicas of the replica workload (sizes 2,000 to 250,000, one
     persistent launch per call, on two tilings): every replica equals its own
